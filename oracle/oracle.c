@@ -1,0 +1,959 @@
+/*
+ * Accessibility-field CPU ORACLE -- test infrastructure only (see oracle.h).
+ *
+ * Plain single-threaded C, fp64 where floating point is involved, built with
+ * -O2 -fno-fast-math -ffp-contract=off.  Every voxel lives in one hash map
+ * keyed by its packed index; nothing is blocked, tiled or reordered.
+ *
+ * Fixed point.  Positions are integers in units u = v/256 (P = rint(x*256/v),
+ * round-half-even on the fp64 product).  Voxel i spans [256 i, 256 i + 256)
+ * and its centre is C(i) = 256 i + 128.  Signed distances are integers in the
+ * same unit, and a voxel keeps the integer sums S = sum of clamped distances
+ * and W = number of contributions, so the TSDF value S/W of Section 3.2 is
+ * exact and independent of the order in which returns are applied.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define KEY_BIAS (1LL << 20)
+#define KEY_MASK ((1LL << 21) - 1)
+#define COORD_LIM ((1LL << 28) - 4096)
+#define MAX_TOOLS 16
+#define MAX_VP 8
+
+enum { CLS_BODY = 0, CLS_NEAR = 1, CLS_FAR = 2 };
+enum { LBL_UNSCORED = 0, LBL_ACCESSIBLE = 1, LBL_BLOCKED = 2, LBL_NOCAND = 3 };
+
+/* ---------------------------------------------------------------- helpers */
+int64_t orc_floor_div(int64_t a, int64_t b) {
+  int64_t q = a / b;
+  if ((a % b != 0) && ((a < 0) != (b < 0))) q -= 1;
+  return q;
+}
+
+/* Exact floor square root. */
+int64_t orc_isqrt(int64_t n) {
+  if (n <= 0) return 0;
+  int64_t r = (int64_t)sqrt((double)n);
+  while (r > 0 && (__int128)r * r > n) r -= 1;
+  while ((__int128)(r + 1) * (r + 1) <= n) r += 1;
+  return r;
+}
+
+int64_t orc_key(int64_t x, int64_t y, int64_t z) {
+  return ((x + KEY_BIAS) & KEY_MASK) | (((y + KEY_BIAS) & KEY_MASK) << 21) |
+         (((z + KEY_BIAS) & KEY_MASK) << 42);
+}
+
+void orc_unkey(int64_t key, int64_t out[3]) {
+  out[0] = (key & KEY_MASK) - KEY_BIAS;
+  out[1] = ((key >> 21) & KEY_MASK) - KEY_BIAS;
+  out[2] = ((key >> 42) & KEY_MASK) - KEY_BIAS;
+}
+
+/* ------------------------------------------------- int64 -> int64 hash map */
+typedef struct {
+  int64_t *keys, *vals;
+  int64_t cap, n;
+} hmap;
+
+static uint64_t mix64(uint64_t x) {
+  x ^= x >> 33;
+  x *= 0xff51afd7ed558ccdULL;
+  x ^= x >> 33;
+  x *= 0xc4ceb9fe1a85ec53ULL;
+  x ^= x >> 33;
+  return x;
+}
+
+static void hm_init(hmap *h, int64_t cap) {
+  h->cap = cap;
+  h->n = 0;
+  h->keys = (int64_t *)malloc(sizeof(int64_t) * cap);
+  h->vals = (int64_t *)malloc(sizeof(int64_t) * cap);
+  for (int64_t i = 0; i < cap; ++i) h->keys[i] = -1;
+}
+
+static void hm_free(hmap *h) {
+  free(h->keys);
+  free(h->vals);
+}
+
+static int64_t hm_get(const hmap *h, int64_t key) {
+  int64_t i = (int64_t)(mix64((uint64_t)key) & (uint64_t)(h->cap - 1));
+  for (;;) {
+    if (h->keys[i] == key) return h->vals[i];
+    if (h->keys[i] == -1) return -1;
+    i = (i + 1) & (h->cap - 1);
+  }
+}
+
+static void hm_put(hmap *h, int64_t key, int64_t val);
+
+static void hm_grow(hmap *h) {
+  hmap g;
+  hm_init(&g, h->cap * 2);
+  for (int64_t i = 0; i < h->cap; ++i)
+    if (h->keys[i] != -1) hm_put(&g, h->keys[i], h->vals[i]);
+  hm_free(h);
+  *h = g;
+}
+
+static void hm_put(hmap *h, int64_t key, int64_t val) {
+  if (2 * (h->n + 1) > h->cap) hm_grow(h);
+  int64_t i = (int64_t)(mix64((uint64_t)key) & (uint64_t)(h->cap - 1));
+  for (;;) {
+    if (h->keys[i] == key) {
+      h->vals[i] = val;
+      return;
+    }
+    if (h->keys[i] == -1) {
+      h->keys[i] = key;
+      h->vals[i] = val;
+      h->n += 1;
+      return;
+    }
+    i = (i + 1) & (h->cap - 1);
+  }
+}
+
+static void *grow_array(void *p, int64_t elem, int64_t *cap, int64_t need) {
+  if (need <= *cap) return p;
+  int64_t c = *cap ? *cap : 1024;
+  while (c < need) c *= 2;
+  p = realloc(p, (size_t)(elem * c));
+  memset((char *)p + elem * (*cap), 0, (size_t)(elem * (c - *cap)));
+  *cap = c;
+  return p;
+}
+
+/* ------------------------------------------------------------ the oracle */
+typedef struct {
+  int32_t K;
+  int64_t *begin;   /* K+1 prefix offsets into off/cls */
+  int32_t *off;     /* [m][3] */
+  uint8_t *cls;
+  double *rot;      /* K x 9 */
+} tool_tab;
+
+struct orc {
+  orc_config cfg;
+  double scale, tau;
+  int64_t tau_u, R, rc_u, dmin_u;
+  int roi;
+  int64_t roi_lo[3], roi_hi[3];
+  int64_t last_frame_id;
+  /* voxels */
+  hmap vmap;
+  int64_t nv, vcap;
+  int64_t *vkey, *S, *dS;
+  int32_t *W, *dW;
+  uint8_t *clr;
+  int64_t *dirty, ndirty, dcap;
+  /* surface points, canonical order */
+  hmap pmap;
+  int64_t np, pcap;
+  int64_t *pkey, *sumq;
+  int32_t *first_frame, *nvp, *vphead, *vp, *nq, *last_frame;
+  /* tools */
+  tool_tab tools[MAX_TOOLS];
+  /* last score results, by point index */
+  int64_t rcap;
+  uint8_t *label;
+  int32_t *first_free, *has_normal;
+  int64_t *normal;
+  uint64_t *mask;
+  int32_t mask_words;
+  orc_frame_stats fst;
+  orc_score_stats sst;
+};
+
+static int in_roi(const orc_t *o, int64_t x, int64_t y, int64_t z) {
+  if (!o->roi) return 1;
+  return x >= o->roi_lo[0] && x <= o->roi_hi[0] && y >= o->roi_lo[1] &&
+         y <= o->roi_hi[1] && z >= o->roi_lo[2] && z <= o->roi_hi[2];
+}
+
+orc_t *orc_create(const orc_config *cfg) {
+  orc_t *o = (orc_t *)calloc(1, sizeof(orc_t));
+  o->cfg = *cfg;
+  if (o->cfg.n_vp > MAX_VP || o->cfg.n_vp < 1 || cfg->voxel <= 0) {
+    free(o);
+    return NULL;
+  }
+  /* Section 3.2: tau = min(4v, 0.1 m) when not given (the text prints max;
+   * the voxel-size study of Section 4.1 needs tau to scale with v). */
+  o->tau = cfg->trunc > 0 ? cfg->trunc : fmin(4.0 * cfg->voxel, 0.1);
+  o->scale = 256.0 / cfg->voxel;
+  o->tau_u = llrint(o->tau * o->scale);
+  o->R = (o->tau_u + 255) / 256;          /* cube half-width ceil(tau/v) */
+  o->rc_u = llrint(cfg->r_c * o->scale);
+  o->dmin_u = llrint(cfg->vp_min_dist * o->scale);
+  if (o->R < 1 || o->R > 7) {
+    free(o);
+    return NULL;
+  }
+  o->last_frame_id = -1;
+  hm_init(&o->vmap, 1 << 16);
+  hm_init(&o->pmap, 1 << 12);
+  return o;
+}
+
+void orc_destroy(orc_t *o) {
+  if (!o) return;
+  hm_free(&o->vmap);
+  hm_free(&o->pmap);
+  free(o->vkey); free(o->S); free(o->dS); free(o->W); free(o->dW); free(o->clr);
+  free(o->dirty);
+  free(o->pkey); free(o->sumq); free(o->first_frame); free(o->nvp);
+  free(o->vphead); free(o->vp); free(o->nq); free(o->last_frame);
+  for (int t = 0; t < MAX_TOOLS; ++t) {
+    free(o->tools[t].begin); free(o->tools[t].off); free(o->tools[t].cls);
+    free(o->tools[t].rot);
+  }
+  free(o->label); free(o->first_free); free(o->has_normal); free(o->normal);
+  free(o->mask);
+  free(o);
+}
+
+void orc_set_roi(orc_t *o, const int64_t lo[3], const int64_t hi[3]) {
+  o->roi = 1;
+  for (int i = 0; i < 3; ++i) {
+    o->roi_lo[i] = lo[i];
+    o->roi_hi[i] = hi[i];
+  }
+}
+
+int orc_params(const orc_t *o, int64_t *tau_u, int64_t *R, int64_t *rc_u,
+               int64_t *dmin_u, double *scale) {
+  *tau_u = o->tau_u;
+  *R = o->R;
+  *rc_u = o->rc_u;
+  *dmin_u = o->dmin_u;
+  *scale = o->scale;
+  return 0;
+}
+
+/* Voxel record, created on first touch. */
+static int64_t voxel_slot(orc_t *o, int64_t key) {
+  int64_t i = hm_get(&o->vmap, key);
+  if (i >= 0) return i;
+  i = o->nv;
+  int64_t c = o->vcap;
+  o->vkey = (int64_t *)grow_array(o->vkey, sizeof(int64_t), &c, i + 1);
+  c = o->vcap;
+  o->S = (int64_t *)grow_array(o->S, sizeof(int64_t), &c, i + 1);
+  c = o->vcap;
+  o->dS = (int64_t *)grow_array(o->dS, sizeof(int64_t), &c, i + 1);
+  c = o->vcap;
+  o->W = (int32_t *)grow_array(o->W, sizeof(int32_t), &c, i + 1);
+  c = o->vcap;
+  o->dW = (int32_t *)grow_array(o->dW, sizeof(int32_t), &c, i + 1);
+  c = o->vcap;
+  o->clr = (uint8_t *)grow_array(o->clr, sizeof(uint8_t), &c, i + 1);
+  o->vcap = c;
+  o->vkey[i] = key;
+  o->nv += 1;
+  hm_put(&o->vmap, key, i);
+  return i;
+}
+
+static void point_arrays(orc_t *o, int64_t need) {
+  if (need <= o->pcap) return;
+  int64_t c0 = o->pcap, c;
+  c = c0; o->pkey = (int64_t *)grow_array(o->pkey, sizeof(int64_t), &c, need);
+  c = c0; o->sumq = (int64_t *)grow_array(o->sumq, 3 * sizeof(int64_t), &c, need);
+  c = c0; o->first_frame = (int32_t *)grow_array(o->first_frame, sizeof(int32_t), &c, need);
+  c = c0; o->nvp = (int32_t *)grow_array(o->nvp, sizeof(int32_t), &c, need);
+  c = c0; o->vphead = (int32_t *)grow_array(o->vphead, sizeof(int32_t), &c, need);
+  c = c0; o->vp = (int32_t *)grow_array(o->vp, MAX_VP * 3 * sizeof(int32_t), &c, need);
+  c = c0; o->nq = (int32_t *)grow_array(o->nq, sizeof(int32_t), &c, need);
+  c = c0; o->last_frame = (int32_t *)grow_array(o->last_frame, sizeof(int32_t), &c, need);
+  o->pcap = c;
+}
+
+static int cmp_i64(const void *a, const void *b) {
+  int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+  return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+/* Fixed-point quantisation: rint of the fp64 product (round half to even). */
+static int quantize(double x, double scale, int64_t *out) {
+  if (!isfinite(x)) return 0;
+  double p = x * scale;
+  if (!(fabs(p) <= (double)COORD_LIM)) return 0;
+  *out = llrint(p);
+  return 1;
+}
+
+/* Section 3.2 "Scan-centric integration": every voxel x of the index cube of
+ * half-width R = ceil(tau/v) around the return's voxel, except those inside
+ * the 18-degree cone behind the return (cos angle(x - p, p - q) > 0.95), gets
+ * d = |p - q| - |x - q| clamped to [0, tau], at the voxel centre. */
+static void accumulate_cube(orc_t *o, const int64_t P[3], const int64_t Q[3]) {
+  int64_t ip[3], b[3];
+  for (int i = 0; i < 3; ++i) {
+    ip[i] = orc_floor_div(P[i], 256);
+    b[i] = P[i] - Q[i];
+  }
+  int64_t bb = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+  int64_t range_p = orc_isqrt(bb);
+  for (int64_t dz = -o->R; dz <= o->R; ++dz)
+    for (int64_t dy = -o->R; dy <= o->R; ++dy)
+      for (int64_t dx = -o->R; dx <= o->R; ++dx) {
+        int64_t x[3] = {ip[0] + dx, ip[1] + dy, ip[2] + dz};
+        if (!in_roi(o, x[0], x[1], x[2])) continue;
+        int64_t c[3], a[3], cq[3];
+        for (int i = 0; i < 3; ++i) {
+          c[i] = 256 * x[i] + 128;
+          a[i] = c[i] - P[i];
+          cq[i] = c[i] - Q[i];
+        }
+        int64_t ab = a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+        int64_t aa = a[0] * a[0] + a[1] * a[1] + a[2] * a[2];
+        /* cos > 0.95  <=>  a.b > 0 and 400 (a.b)^2 > 361 |a|^2 |b|^2 */
+        if (ab > 0 && (__int128)400 * ab * ab > (__int128)361 * aa * bb) {
+          o->fst.pairs_excluded += 1;
+          continue;
+        }
+        int64_t d = range_p - orc_isqrt(cq[0] * cq[0] + cq[1] * cq[1] + cq[2] * cq[2]);
+        int64_t lo = o->cfg.clamp_negative ? -o->tau_u : 0;
+        if (d < lo) d = lo;
+        if (d > o->tau_u) d = o->tau_u;
+        int64_t s = voxel_slot(o, orc_key(x[0], x[1], x[2]));
+        if (o->dW[s] == 0) {
+          int64_t c2 = o->dcap;
+          o->dirty = (int64_t *)grow_array(o->dirty, sizeof(int64_t), &c2, o->ndirty + 1);
+          o->dcap = c2;
+          o->dirty[o->ndirty++] = s;
+        }
+        o->dS[s] += d;
+        o->dW[s] += 1;
+        o->fst.pairs_applied += 1;
+      }
+}
+
+/* a / b rounded to nearest, halves away from zero (b > 0); odd in a, so the
+ * band positions turn with the scene under axis flips and permutations. */
+static int64_t round_div(int64_t a, int64_t b) {
+  int64_t m = a < 0 ? -a : a;
+  int64_t q = (2 * m + b) / (2 * b);
+  return a < 0 ? -q : q;
+}
+
+/* Section 3.4 "Arm path checking": voxels in the band (tau, 2.25 tau] along
+ * the ray from the return back towards the sensor are marked ray-cleared.
+ * Samples every v/2 (at the nearest fixed-point position), never past the
+ * sensor. */
+static void mark_band(orc_t *o, const int64_t P[3], const int64_t Q[3]) {
+  int64_t g[3] = {Q[0] - P[0], Q[1] - P[1], Q[2] - P[2]};
+  int64_t L = orc_isqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+  for (int64_t j = 1;; ++j) {
+    int64_t lam = o->tau_u + 128 * j;
+    if (4 * lam > 9 * o->tau_u || lam >= L) break;
+    int64_t x[3];
+    for (int i = 0; i < 3; ++i)
+      x[i] = orc_floor_div(P[i] + round_div(lam * g[i], L), 256);
+    if (!in_roi(o, x[0], x[1], x[2])) continue;
+    int64_t s = voxel_slot(o, orc_key(x[0], x[1], x[2]));
+    o->clr[s] = 1;
+    o->fst.band_marks += 1;
+  }
+}
+
+int orc_integrate_frame(orc_t *o, const float *xyz, int64_t n,
+                        const float origin[3], int64_t frame_id) {
+  if (frame_id <= o->last_frame_id || n < 0) return -1;
+  int64_t Q[3];
+  for (int i = 0; i < 3; ++i)
+    if (!quantize((double)origin[i], o->scale, &Q[i])) return -1;
+  memset(&o->fst, 0, sizeof(o->fst));
+  o->fst.n_in = n;
+  int64_t *P = (int64_t *)malloc(sizeof(int64_t) * 3 * (n > 0 ? n : 1));
+  uint8_t *ok = (uint8_t *)malloc(n > 0 ? (size_t)n : 1);
+  int64_t *fresh = NULL, nfresh = 0, fcap = 0;
+  hmap seen;
+  hm_init(&seen, 1024);
+
+  for (int64_t r = 0; r < n; ++r) {
+    int v = 1;
+    for (int i = 0; i < 3; ++i) v &= quantize((double)xyz[3 * r + i], o->scale, &P[3 * r + i]);
+    if (v && P[3 * r] == Q[0] && P[3 * r + 1] == Q[1] && P[3 * r + 2] == Q[2]) v = 0;
+    ok[r] = (uint8_t)v;
+    if (!v) {
+      o->fst.n_dropped += 1;
+      continue;
+    }
+    o->fst.n_valid += 1;
+    accumulate_cube(o, &P[3 * r], Q);
+    mark_band(o, &P[3 * r], Q);
+    /* Section 3.1: the voxel holding a return becomes a surface point. */
+    int64_t ip[3];
+    for (int i = 0; i < 3; ++i) ip[i] = orc_floor_div(P[3 * r + i], 256);
+    if (!in_roi(o, ip[0], ip[1], ip[2])) continue;
+    int64_t k = orc_key(ip[0], ip[1], ip[2]);
+    if (hm_get(&o->pmap, k) < 0 && hm_get(&seen, k) < 0) {
+      hm_put(&seen, k, 1);
+      fresh = (int64_t *)grow_array(fresh, sizeof(int64_t), &fcap, nfresh + 1);
+      fresh[nfresh++] = k;
+    }
+  }
+
+  /* Fold the frame: S += dS, W += dW; weights saturate at the cap with
+   * proportional rescaling of S (Section 3.6, "TSDF integration"). */
+  for (int64_t j = 0; j < o->ndirty; ++j) {
+    int64_t s = o->dirty[j];
+    o->S[s] += o->dS[s];
+    o->W[s] += o->dW[s];
+    if (o->W[s] > o->cfg.weight_cap) {
+      o->S[s] = orc_floor_div(o->S[s] * o->cfg.weight_cap, o->W[s]);
+      o->W[s] = o->cfg.weight_cap;
+    }
+    o->dS[s] = 0;
+    o->dW[s] = 0;
+  }
+  o->fst.voxels_folded = o->ndirty;
+  o->ndirty = 0;
+
+  /* New points of the frame are appended in ascending key order. */
+  qsort(fresh, (size_t)nfresh, sizeof(int64_t), cmp_i64);
+  point_arrays(o, o->np + nfresh);
+  for (int64_t j = 0; j < nfresh; ++j) {
+    int64_t p = o->np++;
+    o->pkey[p] = fresh[j];
+    o->first_frame[p] = (int32_t)frame_id;
+    o->nvp[p] = 0;
+    o->vphead[p] = 0;
+    o->nq[p] = 0;
+    o->last_frame[p] = -1;
+    for (int i = 0; i < 3; ++i) o->sumq[3 * p + i] = 0;
+    hm_put(&o->pmap, fresh[j], p);
+  }
+  o->fst.new_points = nfresh;
+  o->fst.n_points = o->np;
+
+  /* Once per (point, frame): accumulate the sensor position for the normal
+   * orientation, and store it as a viewpoint if it moved more than the
+   * novelty distance from the last stored one (ring of n_vp). */
+  for (int64_t r = 0; r < n; ++r) {
+    if (!ok[r]) continue;
+    int64_t ip[3];
+    for (int i = 0; i < 3; ++i) ip[i] = orc_floor_div(P[3 * r + i], 256);
+    if (!in_roi(o, ip[0], ip[1], ip[2])) continue;
+    int64_t p = hm_get(&o->pmap, orc_key(ip[0], ip[1], ip[2]));
+    if (o->last_frame[p] == (int32_t)frame_id) continue;
+    o->last_frame[p] = (int32_t)frame_id;
+    for (int i = 0; i < 3; ++i) o->sumq[3 * p + i] += Q[i];
+    o->nq[p] += 1;
+    int store = 1;
+    if (o->nvp[p] > 0) {
+      int last = (o->vphead[p] + o->cfg.n_vp - 1) % o->cfg.n_vp;
+      int64_t d2 = 0;
+      for (int i = 0; i < 3; ++i) {
+        int64_t d = Q[i] - o->vp[(p * MAX_VP + last) * 3 + i];
+        d2 += d * d;
+      }
+      store = d2 > o->dmin_u * o->dmin_u;
+    }
+    if (store) {
+      for (int i = 0; i < 3; ++i) o->vp[(p * MAX_VP + o->vphead[p]) * 3 + i] = (int32_t)Q[i];
+      o->vphead[p] = (o->vphead[p] + 1) % o->cfg.n_vp;
+      if (o->nvp[p] < o->cfg.n_vp) o->nvp[p] += 1;
+    }
+  }
+  hm_free(&seen);
+  free(fresh);
+  free(P);
+  free(ok);
+  o->last_frame_id = frame_id;
+  return 0;
+}
+
+int orc_frame_stats_get(const orc_t *o, orc_frame_stats *st) {
+  *st = o->fst;
+  return 0;
+}
+
+int64_t orc_num_voxels(const orc_t *o) { return o->nv; }
+
+int64_t orc_read_tsdf(const orc_t *o, int64_t *key, int64_t *S, int32_t *W,
+                      uint8_t *cleared, int64_t cap) {
+  int64_t *k = (int64_t *)malloc(sizeof(int64_t) * (o->nv > 0 ? o->nv : 1));
+  for (int64_t i = 0; i < o->nv; ++i) k[i] = o->vkey[i];
+  qsort(k, (size_t)o->nv, sizeof(int64_t), cmp_i64);
+  int64_t m = o->nv < cap ? o->nv : cap;
+  for (int64_t i = 0; i < m; ++i) {
+    int64_t s = hm_get(&o->vmap, k[i]);
+    key[i] = k[i];
+    S[i] = o->S[s];
+    W[i] = o->W[s];
+    cleared[i] = o->clr[s];
+  }
+  free(k);
+  return o->nv;
+}
+
+int orc_voxel(const orc_t *o, int64_t key, int64_t *S, int32_t *W,
+              uint8_t *cleared) {
+  int64_t s = hm_get(&o->vmap, key);
+  if (s < 0) {
+    *S = 0;
+    *W = 0;
+    *cleared = 0;
+    return 0;
+  }
+  *S = o->S[s];
+  *W = o->W[s];
+  *cleared = o->clr[s];
+  return 1;
+}
+
+int64_t orc_num_points(const orc_t *o) { return o->np; }
+
+int64_t orc_read_points(const orc_t *o, int64_t *key, int32_t *first_frame,
+                        int32_t *n_vp, int32_t *vp, int64_t *sumq, int32_t *nq,
+                        int64_t cap) {
+  int64_t m = o->np < cap ? o->np : cap;
+  for (int64_t p = 0; p < m; ++p) {
+    key[p] = o->pkey[p];
+    first_frame[p] = o->first_frame[p];
+    n_vp[p] = o->nvp[p];
+    nq[p] = o->nq[p];
+    /* viewpoints oldest first */
+    int cnt = o->nvp[p];
+    int start = (o->vphead[p] - cnt + o->cfg.n_vp) % o->cfg.n_vp;
+    for (int j = 0; j < MAX_VP; ++j)
+      for (int i = 0; i < 3; ++i)
+        vp[(p * MAX_VP + j) * 3 + i] =
+            j < cnt ? o->vp[(p * MAX_VP + (start + j) % o->cfg.n_vp) * 3 + i] : 0;
+    for (int i = 0; i < 3; ++i) sumq[3 * p + i] = o->sumq[3 * p + i];
+  }
+  return o->np;
+}
+
+/* ------------------------------------------------------- tool kernel table */
+typedef struct {
+  int64_t n2;
+  int32_t o[3];
+} ent;
+
+static int cmp_ent(const void *a, const void *b) {
+  const ent *x = (const ent *)a, *y = (const ent *)b;
+  if (x->n2 != y->n2) return x->n2 < y->n2 ? -1 : 1;
+  for (int i = 2; i >= 0; --i)
+    if (x->o[i] != y->o[i]) return x->o[i] < y->o[i] ? -1 : 1;
+  return 0;
+}
+
+/* Section 3.4 "Tool kernel" / "Self-exclusion" / "Arm path checking": the
+ * rotated tool is a set of voxel offsets from the point's voxel.  BODY holds
+ * offsets whose centre lies in the rotated tool solid (0 <= x <= length),
+ * FAR those in its corridor (length < x <= length + corridor), both minus the
+ * self-exclusion ball of radius r_s around the tip; NEAR holds the three arm
+ * samples at {0.6, 1.25, 2.25} tau along the approach axis.  Membership is
+ * decided in fp64 in voxel units with a 1e-9 tolerance on the inclusive
+ * bounds. */
+static int build_orientation(const orc_tool *t, double v, double tau,
+                             const double *R, ent **body, int64_t *nb,
+                             ent **far_, int64_t *nf, int32_t near[3][3]) {
+  const double eps = 1e-9;
+  double Lv = t->length / v;
+  double Ev = (t->length + t->corridor) / v;
+  double a, b;
+  if (t->shape == 0) {
+    a = t->radius / v;
+    b = a;
+  } else {
+    a = (0.5 * t->width) / v;
+    b = (0.5 * t->height) / v;
+  }
+  double rv2 = a * a;
+  double rsv = t->r_s / v;
+  double rsv2 = rsv * rsv;
+  double fr[3] = {0.6, 1.25, 2.25};
+  for (int j = 0; j < 3; ++j) {
+    double lam = (fr[j] * tau) / v;
+    for (int i = 0; i < 3; ++i) near[j][i] = (int32_t)round(lam * R[3 * i]);
+  }
+  int64_t lo[3], hi[3];
+  for (int i = 0; i < 3; ++i) {
+    double mn = INFINITY, mx = -INFINITY;
+    for (int cx = 0; cx < 2; ++cx)
+      for (int cy = 0; cy < 2; ++cy)
+        for (int cz = 0; cz < 2; ++cz) {
+          double x = cx ? Ev : 0.0, y = cy ? a : -a, z = cz ? b : -b;
+          double w = R[3 * i] * x + R[3 * i + 1] * y + R[3 * i + 2] * z;
+          if (w < mn) mn = w;
+          if (w > mx) mx = w;
+        }
+    lo[i] = (int64_t)floor(mn) - 1;
+    hi[i] = (int64_t)ceil(mx) + 1;
+  }
+  int64_t cb = 0, cf = 0;
+  *nb = 0;
+  *nf = 0;
+  *body = NULL;
+  *far_ = NULL;
+  for (int64_t oz = lo[2]; oz <= hi[2]; ++oz)
+    for (int64_t oy = lo[1]; oy <= hi[1]; ++oy)
+      for (int64_t ox = lo[0]; ox <= hi[0]; ++ox) {
+        double fx = (double)ox, fy = (double)oy, fz = (double)oz;
+        double x = (R[0] * fx + R[3] * fy) + R[6] * fz;
+        double y = (R[1] * fx + R[4] * fy) + R[7] * fz;
+        double z = (R[2] * fx + R[5] * fy) + R[8] * fz;
+        int cross;
+        if (t->shape == 0)
+          cross = (y * y + z * z) <= rv2 + eps;
+        else
+          cross = fabs(y) <= a + eps && fabs(z) <= b + eps;
+        if (!cross) continue;
+        int64_t n2 = ox * ox + oy * oy + oz * oz;
+        if ((double)n2 < rsv2) continue;
+        if (x < -eps || x > Ev + eps) continue;
+        if (ox < -511 || ox > 511 || oy < -511 || oy > 511 || oz < -511 || oz > 511)
+          return -1;
+        ent e = {n2, {(int32_t)ox, (int32_t)oy, (int32_t)oz}};
+        if (x <= Lv + eps) {
+          *body = (ent *)grow_array(*body, sizeof(ent), &cb, *nb + 1);
+          (*body)[(*nb)++] = e;
+        } else {
+          *far_ = (ent *)grow_array(*far_, sizeof(ent), &cf, *nf + 1);
+          (*far_)[(*nf)++] = e;
+        }
+      }
+  qsort(*body, (size_t)*nb, sizeof(ent), cmp_ent);
+  qsort(*far_, (size_t)*nf, sizeof(ent), cmp_ent);
+  return 0;
+}
+
+int orc_set_tool(orc_t *o, int tool_id, const orc_tool *t, int32_t K,
+                 const double *rot) {
+  if (tool_id < 0 || tool_id >= MAX_TOOLS || K <= 0) return -1;
+  tool_tab *tt = &o->tools[tool_id];
+  free(tt->begin); free(tt->off); free(tt->cls); free(tt->rot);
+  memset(tt, 0, sizeof(*tt));
+  tt->K = K;
+  tt->rot = (double *)malloc(sizeof(double) * 9 * K);
+  memcpy(tt->rot, rot, sizeof(double) * 9 * K);
+  tt->begin = (int64_t *)malloc(sizeof(int64_t) * (K + 1));
+  int64_t cap = 0, m = 0;
+  int64_t ccap = 0;
+  tt->begin[0] = 0;
+  for (int32_t k = 0; k < K; ++k) {
+    ent *body, *far_;
+    int64_t nb, nf;
+    int32_t near[3][3];
+    if (build_orientation(t, o->cfg.voxel, o->tau, rot + 9 * k, &body, &nb, &far_, &nf,
+                          near) != 0)
+      return -1;
+    int64_t need = m + 3 + nb + nf;
+    int64_t c0 = cap;
+    tt->off = (int32_t *)grow_array(tt->off, 3 * sizeof(int32_t), &c0, need);
+    tt->cls = (uint8_t *)grow_array(tt->cls, 1, &ccap, need);
+    cap = c0;
+    for (int j = 0; j < 3; ++j) {
+      for (int i = 0; i < 3; ++i) tt->off[3 * m + i] = near[j][i];
+      tt->cls[m++] = CLS_NEAR;
+    }
+    for (int64_t j = 0; j < nb; ++j) {
+      for (int i = 0; i < 3; ++i) tt->off[3 * m + i] = body[j].o[i];
+      tt->cls[m++] = CLS_BODY;
+    }
+    for (int64_t j = 0; j < nf; ++j) {
+      for (int i = 0; i < 3; ++i) tt->off[3 * m + i] = far_[j].o[i];
+      tt->cls[m++] = CLS_FAR;
+    }
+    tt->begin[k + 1] = m;
+    free(body);
+    free(far_);
+  }
+  return 0;
+}
+
+int64_t orc_tool_table(const orc_t *o, int tool_id, int32_t k, int32_t *off,
+                       uint8_t *cls, int64_t cap) {
+  if (tool_id < 0 || tool_id >= MAX_TOOLS) return -1;
+  const tool_tab *tt = &o->tools[tool_id];
+  if (tt->K <= 0 || k < 0 || k >= tt->K) return -1;
+  int64_t b = tt->begin[k], m = tt->begin[k + 1] - b;
+  for (int64_t j = 0; j < m && j < cap; ++j) {
+    for (int i = 0; i < 3; ++i) off[3 * j + i] = tt->off[3 * (b + j) + i];
+    cls[j] = tt->cls[b + j];
+  }
+  return m;
+}
+
+/* ---------------------------------------------------------------- scoring */
+typedef struct {
+  int64_t S;
+  int32_t W;
+  uint8_t clr;
+} vrec;
+
+static vrec lookup(const orc_t *o, int64_t x, int64_t y, int64_t z) {
+  vrec r = {0, 0, 0};
+  int64_t s = hm_get(&o->vmap, orc_key(x, y, z));
+  if (s >= 0) {
+    r.S = o->S[s];
+    r.W = o->W[s];
+    r.clr = o->clr[s];
+  }
+  return r;
+}
+
+static int nb_cmp(const void *a, const void *b) {
+  const int32_t *x = (const int32_t *)a, *y = (const int32_t *)b;
+  int32_t nx = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+  int32_t ny = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
+  if (nx != ny) return nx < ny ? -1 : 1;
+  for (int i = 2; i >= 0; --i)
+    if (x[i] != y[i]) return x[i] < y[i] ? -1 : 1;
+  return 0;
+}
+
+static int bitlen64(uint64_t m) {
+  int n = 0;
+  while (m) {
+    n++;
+    m >>= 1;
+  }
+  return n;
+}
+
+/* Section 3.4 "Approach directions": the normal is the least principal axis
+ * (PCA) of the k nearest surface voxels, oriented towards the mean of the
+ * sensor positions recorded for the point.  Neighbours: surface voxels within
+ * +-3 voxels, the point itself included, taken nearest first; every voxel tied
+ * with the k-th at its distance is included too, so the set does not depend
+ * on the axis convention.  The scatter M = n sum(dd^T) - (sum d)(sum d)^T is exact in
+ * int64.  Its least eigenvector is the dominant one of B = trace(M) I - M,
+ * obtained by squaring B eight times (B^256) in integer arithmetic, keeping 28
+ * significant bits after each squaring (shifts round to nearest, halves away
+ * from zero, so the result turns exactly with the scene under axis flips and
+ * permutations), and taking the column of largest norm.  Returns 0 when
+ * fewer than 3 neighbours exist. */
+static int64_t round_shift(int64_t x, int sh) {
+  if (sh <= 0) return x;
+  int64_t m = x < 0 ? -x : x;
+  int64_t q = (m + (1LL << (sh - 1))) >> sh;
+  return x < 0 ? -q : q;
+}
+
+static int point_normal(const orc_t *o, int64_t p, const int32_t *nbo, int nnb,
+                        int64_t n_out[3]) {
+  int64_t s[3];
+  orc_unkey(o->pkey[p], s);
+  int64_t sx[3] = {0, 0, 0}, sxx[3][3] = {{0}};
+  int cnt = 0;
+  int32_t last_d2 = -1;
+  for (int j = 0; j < nnb; ++j) {
+    const int32_t *d = nbo + 3 * j;
+    int32_t d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    if (cnt >= o->cfg.knn_k && d2 != last_d2) break;
+    if (hm_get(&o->pmap, orc_key(s[0] + d[0], s[1] + d[1], s[2] + d[2])) < 0) continue;
+    cnt++;
+    last_d2 = d2;
+    for (int a = 0; a < 3; ++a) {
+      sx[a] += d[a];
+      for (int b = 0; b < 3; ++b) sxx[a][b] += (int64_t)d[a] * d[b];
+    }
+  }
+  if (cnt < 3) return 0;
+  int64_t M[3][3], B[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) M[a][b] = (int64_t)cnt * sxx[a][b] - sx[a] * sx[b];
+  int64_t tr = M[0][0] + M[1][1] + M[2][2];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) B[a][b] = (a == b ? tr : 0) - M[a][b];
+  for (int it = 0; it < 8; ++it) {
+    int64_t C[3][3];
+    uint64_t mx = 0;
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        C[a][b] = B[a][0] * B[0][b] + B[a][1] * B[1][b] + B[a][2] * B[2][b];
+        uint64_t m = (uint64_t)(C[a][b] < 0 ? -C[a][b] : C[a][b]);
+        if (m > mx) mx = m;
+      }
+    int sh = bitlen64(mx) - 28;
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) B[a][b] = round_shift(C[a][b], sh);
+  }
+  int best = 0;
+  int64_t bn = -1;
+  for (int c = 0; c < 3; ++c) {
+    int64_t nrm = B[0][c] * B[0][c] + B[1][c] * B[1][c] + B[2][c] * B[2][c];
+    if (nrm > bn) {
+      bn = nrm;
+      best = c;
+    }
+  }
+  if (bn <= 0) return 0;
+  for (int a = 0; a < 3; ++a) n_out[a] = B[a][best];
+  __int128 g = 0;
+  for (int a = 0; a < 3; ++a) {
+    int64_t ga = o->sumq[3 * p + a] - (int64_t)o->nq[p] * (256 * s[a] + 128);
+    g += (__int128)n_out[a] * ga;
+  }
+  if (g < 0)
+    for (int a = 0; a < 3; ++a) n_out[a] = -n_out[a];
+  return 1;
+}
+
+/* Candidate filters of Section 3.4 for approach direction d (column 0 of the
+ * orientation): within the half-cone of the outward normal (n.d >= cos70 |n|)
+ * and seen from that side by at least one stored viewpoint V
+ * ((V - s).d > 0.25 |V - s|).  Both tests are squared to avoid square roots. */
+static int candidate(const orc_t *o, int64_t p, const int64_t s[3],
+                     const int64_t n[3], int has_n, const double *R) {
+  double d[3] = {R[0], R[3], R[6]};
+  if (has_n) {
+    double dot = ((double)n[0] * d[0] + (double)n[1] * d[1]) + (double)n[2] * d[2];
+    double nn = (double)(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    double c2 = o->cfg.cos_normal * o->cfg.cos_normal;
+    if (!(dot >= 0.0 && dot * dot >= c2 * nn)) return 0;
+  }
+  int cnt = o->nvp[p];
+  double o2 = o->cfg.obs_dot * o->cfg.obs_dot;
+  for (int j = 0; j < cnt; ++j) {
+    int64_t w[3];
+    for (int i = 0; i < 3; ++i) w[i] = (int64_t)o->vp[(p * MAX_VP + j) * 3 + i] - (256 * s[i] + 128);
+    double wd = ((double)w[0] * d[0] + (double)w[1] * d[1]) + (double)w[2] * d[2];
+    double ww = (double)(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+    if (wd > 0.0 && wd * wd > o2 * ww) return 1;
+  }
+  return 0;
+}
+
+/* Section 3.4: one orientation is free when none of its arm samples hits
+ * (TSDF < r_c, or unknown and not ray-cleared), fewer than n_c body voxels
+ * have TSDF < r_c, and no corridor voxel has TSDF < r_c.  Unknown voxels read
+ * as free for the body and the corridor.  Entries are visited in table order
+ * (arm samples, body, corridor) and the visit stops at the deciding hit; the
+ * number of visited entries is the canonical lookup count. */
+static int orientation_free(const orc_t *o, const tool_tab *tt, int32_t k,
+                            const int64_t s[3], int64_t *lookups) {
+  int body = 0;
+  for (int64_t e = tt->begin[k]; e < tt->begin[k + 1]; ++e) {
+    *lookups += 1;
+    const int32_t *d = tt->off + 3 * e;
+    vrec r = lookup(o, s[0] + d[0], s[1] + d[1], s[2] + d[2]);
+    int occ = r.W > 0 && r.S < o->rc_u * (int64_t)r.W;
+    if (tt->cls[e] == CLS_NEAR) {
+      if (occ || (r.W == 0 && !r.clr)) return 0;
+    } else if (tt->cls[e] == CLS_BODY) {
+      if (occ && ++body >= o->cfg.n_c) return 0;
+    } else {
+      if (occ) return 0;
+    }
+  }
+  return 1;
+}
+
+int orc_score(orc_t *o, int tool_id, const int64_t *keys, int64_t n_keys) {
+  if (tool_id < 0 || tool_id >= MAX_TOOLS) return -1;
+  const tool_tab *tt = &o->tools[tool_id];
+  if (tt->K <= 0) return -4;
+  int32_t K = tt->K;
+  int32_t mw = (K + 63) / 64;
+  if (o->rcap < o->np || o->mask_words != mw) {
+    free(o->label); free(o->first_free); free(o->has_normal); free(o->normal);
+    free(o->mask);
+    o->rcap = o->np > 0 ? o->np : 1;
+    o->label = (uint8_t *)calloc(o->rcap, 1);
+    o->first_free = (int32_t *)calloc(o->rcap, sizeof(int32_t));
+    o->has_normal = (int32_t *)calloc(o->rcap, sizeof(int32_t));
+    o->normal = (int64_t *)calloc(o->rcap * 3, sizeof(int64_t));
+    o->mask = (uint64_t *)calloc(o->rcap * mw, sizeof(uint64_t));
+    o->mask_words = mw;
+  }
+  for (int64_t p = 0; p < o->np; ++p) {
+    o->label[p] = 255; /* not evaluated */
+    o->first_free[p] = -1;
+  }
+  memset(&o->sst, 0, sizeof(o->sst));
+  o->sst.n_points = o->np;
+  /* neighbour offsets, nearest first */
+  int32_t nbo[343 * 3];
+  int nnb = 0;
+  for (int z = -3; z <= 3; ++z)
+    for (int y = -3; y <= 3; ++y)
+      for (int x = -3; x <= 3; ++x) {
+        nbo[3 * nnb] = x;
+        nbo[3 * nnb + 1] = y;
+        nbo[3 * nnb + 2] = z;
+        nnb++;
+      }
+  qsort(nbo, (size_t)nnb, 3 * sizeof(int32_t), nb_cmp);
+
+  int64_t count = keys ? n_keys : o->np;
+  for (int64_t j = 0; j < count; ++j) {
+    int64_t p = keys ? hm_get(&o->pmap, keys[j]) : j;
+    if (p < 0) continue;
+    int64_t s[3];
+    orc_unkey(o->pkey[p], s);
+    vrec self = lookup(o, s[0], s[1], s[2]);
+    o->first_free[p] = -1;
+    o->has_normal[p] = 0;
+    for (int i = 0; i < 3; ++i) o->normal[3 * p + i] = 0;
+    for (int w = 0; w < mw; ++w) o->mask[p * mw + w] = 0;
+    /* Section 3.5: confidence c = w / (w + 5) < 0.2 (i.e. W < 2) is skipped */
+    if (self.W < o->cfg.conf_min_w) {
+      o->label[p] = LBL_UNSCORED;
+      continue;
+    }
+    o->sst.n_confident++;
+    int64_t n[3] = {0, 0, 0};
+    int hn = point_normal(o, p, nbo, nnb, n);
+    o->has_normal[p] = hn;
+    for (int i = 0; i < 3; ++i) o->normal[3 * p + i] = n[i];
+    int any = 0;
+    for (int32_t k = 0; k < K; ++k)
+      if (candidate(o, p, s, n, hn, tt->rot + 9 * k)) {
+        o->mask[p * mw + k / 64] |= 1ULL << (k % 64);
+        any = 1;
+        o->sst.candidate_tests++;
+      }
+    if (!any) {
+      o->label[p] = LBL_NOCAND;
+      o->sst.n_no_candidate++;
+      continue;
+    }
+    o->label[p] = LBL_BLOCKED;
+    for (int32_t k = 0; k < K; ++k) {
+      if (!((o->mask[p * mw + k / 64] >> (k % 64)) & 1)) continue;
+      o->sst.canonical_tests++;
+      if (orientation_free(o, tt, k, s, &o->sst.canonical_lookups)) {
+        o->label[p] = LBL_ACCESSIBLE;
+        o->first_free[p] = k;
+        break;
+      }
+    }
+    if (o->label[p] == LBL_ACCESSIBLE)
+      o->sst.n_accessible++;
+    else
+      o->sst.n_blocked++;
+  }
+  return 0;
+}
+
+int orc_score_stats_get(const orc_t *o, orc_score_stats *st) {
+  *st = o->sst;
+  return 0;
+}
+
+int orc_point_result(const orc_t *o, int64_t key, uint8_t *label,
+                     int32_t *first_free, int64_t normal[3], int32_t *has_normal,
+                     uint64_t *mask, int32_t mask_words) {
+  int64_t p = hm_get(&o->pmap, key);
+  if (p < 0 || p >= o->rcap) return -1;
+  *label = o->label[p];
+  *first_free = o->first_free[p];
+  *has_normal = o->has_normal[p];
+  for (int i = 0; i < 3; ++i) normal[i] = o->normal[3 * p + i];
+  for (int w = 0; w < mask_words && w < o->mask_words; ++w)
+    mask[w] = o->mask[p * o->mask_words + w];
+  return 0;
+}

@@ -1,0 +1,411 @@
+"""Pins of the oracle's scoring stage (CPU only).
+
+Tool kernels, self-exclusion and arm samples: Section 3.4 ("Tool kernel",
+"Self-exclusion", "Arm path checking").  Normal and observation filters:
+Section 3.4 ("Approach directions").  Collision count and confidence gate:
+Sections 3.4 and 3.5.
+"""
+import math
+
+import numpy as np
+import pytest
+
+V6 = 2.0 ** -6
+SC6 = 16384
+
+
+def f32(units):
+    return (np.asarray(units, dtype=np.float64) / SC6).astype(np.float32)
+
+
+def centre(i):
+    return 256 * np.asarray(i) + 128
+
+
+IDENT = np.eye(3).reshape(1, 9)
+
+
+# ----------------------------------------------------------------- tables
+def test_axis_aligned_counts_tiny_cylinder(oracle_mod, synth_mod):
+    """Cylinder r = 3 cm, L = 10 cm, corridor 50 cm, v = 2 cm, approach +x.
+    Cross-section: offsets with (dy^2 + dz^2) * 4 <= 9 -> 9 cells.  Body
+    x in [0, 5] voxels -> 54 offsets, minus the 14 with |o| < 1.5 (all 9 at
+    x = 0 and the 5 with |(1, dy, dz)| <= sqrt 2) = 40.  Corridor x in 6..30
+    -> 25 * 9 = 225.  Arm samples at 0.6, 1.25, 2.25 tau = 1.8, 3.75, 6.75
+    voxels -> 2, 4, 7."""
+    o = oracle_mod.Oracle(voxel=0.02, trunc=0.06)
+    o.set_tool(0, synth_mod.cylinder_tool(), IDENT)
+    off, cls = o.tool_table(0, 0)
+    assert np.bincount(cls, minlength=3).tolist() == [40, 3, 225]
+    assert off[cls == oracle_mod.CLS_NEAR].tolist() == [[2, 0, 0], [4, 0, 0], [7, 0, 0]]
+    body = off[cls == oracle_mod.CLS_BODY]
+    assert body[:, 0].min() == 1 and body[:, 0].max() == 5
+    far = off[cls == oracle_mod.CLS_FAR]
+    assert far[:, 0].min() == 6 and far[:, 0].max() == 30
+
+
+def test_axis_aligned_counts_saw_box(oracle_mod, synth_mod):
+    """Box 30 x 5 x 2 cm, corridor 1 m, v = 1 cm: cross-section 5 x 3 = 15
+    cells; body x in 0..30 -> 465 minus the 39 offsets with |o|^2 < 7.25
+    (r_s^2 = 2.5^2 + 1^2 voxels^2): 15 at x = 0, 15 at x = 1, 9 at x = 2 ->
+    426; corridor 31..130 -> 1500.  Arm samples 2.4, 5, 9 -> 2, 5, 9."""
+    o = oracle_mod.Oracle(voxel=0.01, trunc=0.04)
+    o.set_tool(0, synth_mod.box_tool(), IDENT)
+    off, cls = o.tool_table(0, 0)
+    assert np.bincount(cls, minlength=3).tolist() == [426, 3, 1500]
+    assert off[cls == oracle_mod.CLS_NEAR].tolist() == [[2, 0, 0], [5, 0, 0], [9, 0, 0]]
+    body = off[cls == oracle_mod.CLS_BODY]
+    assert set(np.abs(body[:, 1])) == {0, 1, 2} and set(np.abs(body[:, 2])) == {0, 1}
+
+
+def _membership(tool, rot, v, offs):
+    """Analytic tool-solid membership of voxel-centre offsets (metres), with
+    a 1e-7 m slack: returns (body, far, ambiguous) boolean arrays."""
+    R = rot.reshape(3, 3)
+    rel = offs.astype(np.float64) * v
+    loc = rel @ R              # local coordinates (x along the approach axis)
+    x, y, z = loc[:, 0], loc[:, 1], loc[:, 2]
+    e = 1e-7
+    if tool.shape == 0:
+        rr = np.sqrt(y * y + z * z)
+        cin, camb = rr <= tool.radius - e, np.abs(rr - tool.radius) <= e
+        cout = rr > tool.radius + e
+    else:
+        ay, az = np.abs(y), np.abs(z)
+        cin = (ay <= tool.width / 2 - e) & (az <= tool.height / 2 - e)
+        cout = (ay > tool.width / 2 + e) | (az > tool.height / 2 + e)
+        camb = ~cin & ~cout
+    nrm = np.linalg.norm(rel, axis=1)
+    self_ex = nrm < tool.r_s - e
+    samb = np.abs(nrm - tool.r_s) <= e
+    L, E = tool.length, tool.length + tool.corridor
+    body = cin & ~self_ex & (x >= e) & (x <= L - e)
+    far = cin & ~self_ex & (x > L + e) & (x <= E - e)
+    xamb = (np.abs(x) <= e) | (np.abs(x - L) <= e) | (np.abs(x - E) <= e)
+    clear_out = self_ex | cout | (x < -e) | (x > E + e)
+    amb = (camb | samb | xamb) & ~clear_out
+    return body, far, amb
+
+
+@pytest.mark.parametrize("which", ["tiny", "tree"])
+def test_table_membership_brute_force(oracle_mod, synth_mod, which):
+    """Every orientation's BODY / FAR sets equal the voxel centres inside the
+    rotated solid / corridor (minus the self-exclusion ball), computed
+    independently in metres; offsets within 1e-7 m of a boundary are skipped."""
+    if which == "tiny":
+        tool, rot, v, tau = synth_mod.cylinder_tool(), synth_mod.orientations(
+            synth_mod.fibonacci_directions(16), 1), 0.02, 0.06
+    else:
+        tool, rot, v, tau = synth_mod.box_tool(), synth_mod.orientations(
+            synth_mod.fibonacci_directions(6), 4), 0.01, 0.04
+    o = oracle_mod.Oracle(voxel=v, trunc=tau)
+    o.set_tool(0, tool, rot)
+    reach = int(math.ceil((tool.length + tool.corridor) / v)) + 2
+    g = np.arange(-reach, reach + 1)
+    for k in range(len(rot)):
+        off, cls = o.tool_table(0, k)
+        d = rot[k].reshape(3, 3)[:, 0]
+        # restrict the candidate grid to a slab around the axis
+        grid = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+        t = grid @ d * v
+        perp = np.linalg.norm(grid * v - np.outer(t, d), axis=1)
+        grid = grid[(t > -0.1) & (perp < 0.1)]
+        body, far, amb = _membership(tool, rot[k], v, grid)
+        got_b = {tuple(x) for x in off[cls == oracle_mod.CLS_BODY]}
+        got_f = {tuple(x) for x in off[cls == oracle_mod.CLS_FAR]}
+        exp_b = {tuple(x) for x in grid[body & ~amb]}
+        exp_f = {tuple(x) for x in grid[far & ~amb]}
+        ambs = {tuple(x) for x in grid[amb]}
+        assert exp_b <= got_b and got_b - exp_b <= ambs, k
+        assert exp_f <= got_f and got_f - exp_f <= ambs, k
+        # arm samples: voxel containing the point at lambda * d from the centre
+        near = off[cls == oracle_mod.CLS_NEAR]
+        for j, f in enumerate((0.6, 1.25, 2.25)):
+            q = f * tau * d / v
+            assert np.abs(near[j] - q).max() <= 0.5 + 1e-12
+
+
+def test_table_order_and_roll_symmetry(oracle_mod, synth_mod):
+    """Entries are arm samples, then body, then corridor, each sorted by
+    (|o|^2, z, y, x).  The box is symmetric under a half-turn roll, so roll pi
+    gives the same offset sets as roll 0."""
+    tool = synth_mod.box_tool()
+    dirs = synth_mod.fibonacci_directions(5)
+    rot0 = synth_mod.orientations(dirs, 1)
+    rot2 = synth_mod.orientations(dirs, 2)      # rolls 0, pi/2
+    o = oracle_mod.Oracle(voxel=0.01, trunc=0.04)
+    o.set_tool(0, tool, rot0)
+    # roll pi = negated cross-section axes
+    rpi = rot0.reshape(-1, 3, 3).copy()
+    rpi[:, :, 1:] *= -1
+    o.set_tool(1, tool, rpi.reshape(-1, 9))
+    o.set_tool(2, tool, rot2)
+    for k in range(len(dirs)):
+        a, ca = o.tool_table(0, k)
+        b, cb = o.tool_table(1, k)
+        assert np.array_equal(a, b) and np.array_equal(ca, cb)
+        assert list(ca[:3]) == [1, 1, 1]
+        body = a[ca == 0]
+        far = a[ca == 2]
+        assert np.all(np.where(ca[3:] == 0)[0] < np.where(ca[3:] == 2)[0].min())
+        for grp in (body, far):
+            key = [(int(x @ x), int(x[2]), int(x[1]), int(x[0])) for x in grp]
+            assert key == sorted(key)
+        # a quarter roll changes the footprint of a non-square box
+        c, _ = o.tool_table(2, 2 * k + 1)
+        assert {tuple(x) for x in c} != {tuple(x) for x in a}
+
+
+# ----------------------------------------------------------------- normals
+def _cluster_oracle(oracle_mod, clusters, sensor_dirs, n_frames=2):
+    """Surface points at the given voxels (one return at each voxel centre per
+    frame) seen from sensors far away along sensor_dirs."""
+    o = oracle_mod.Oracle(voxel=V6, trunc=3 * V6)
+    P = centre(np.concatenate(clusters))
+    cen = np.concatenate(clusters).mean(0)
+    for f in range(n_frames):
+        sd = np.asarray(sensor_dirs[f % len(sensor_dirs)], float)
+        Q = np.rint(centre(cen) + 60 * 256 * sd / np.linalg.norm(sd)).astype(np.int64)
+        o.integrate_frame(f32(P), f32(Q), f)
+    return o
+
+
+def test_normal_plane_is_exact_axis(oracle_mod, synth_mod):
+    """All neighbours in the plane z = 0: the scatter matrix has a zero third
+    row and column, so the least principal axis is exactly +-z; the sensor is
+    above, so +z.  An extra surface voxel 3 voxels above the centre is not
+    among the 10 nearest (self, 4 at distance 1, 4 at sqrt 2, and the 4 tied
+    at distance 2) and must not tilt the normal."""
+    plane = np.array([[i, j, 0] for i in range(-4, 5) for j in range(-4, 5)])
+    o = _cluster_oracle(oracle_mod, [plane, np.array([[0, 0, 3]])], [[0.1, 0.2, 1.0]])
+    o.set_tool(0, synth_mod.cylinder_tool(0.01, 0.02, 0.02), IDENT)
+    o.score(0, keys=[oracle_mod.key(0, 0, 0), oracle_mod.key(2, -1, 0)])
+    for k in (oracle_mod.key(0, 0, 0), oracle_mod.key(2, -1, 0)):
+        r = o.point_result(k, 1)
+        assert r["has_normal"] == 1
+        assert r["normal"][0] == 0 and r["normal"][1] == 0 and r["normal"][2] > 0
+
+
+def test_normal_matches_eigh(oracle_mod, synth_mod):
+    """Clusters of 10 surface voxels around a centre (all within the +-3
+    window, so all are the neighbours): the oracle's normal is parallel to the
+    eigenvector of the smallest eigenvalue of the covariance (numpy eigh) when
+    the spectrum is not degenerate, and faces the sensor."""
+    rng = np.random.default_rng(5)
+    clusters, centres, sens = [], [], []
+    for c in range(40):
+        base = np.array([20 * c, 0, 0])
+        nrm = rng.normal(size=3)
+        nrm /= np.linalg.norm(nrm)
+        pts = {(0, 0, 0)}
+        while len(pts) < 10:
+            q = rng.integers(-3, 4, 3)
+            if abs(q @ nrm) < 0.8:
+                pts.add(tuple(int(t) for t in q))
+        pts = np.array(sorted(pts))
+        clusters.append(base + pts)
+        centres.append((base, pts, nrm))
+    o = _cluster_oracle(oracle_mod, clusters, [[0.3, 0.5, 1.0]], n_frames=1)
+    o.set_tool(0, synth_mod.cylinder_tool(0.01, 0.02, 0.02), IDENT)
+    keys = [oracle_mod.key(*b) for b, _, _ in centres]
+    o.score(0, keys=keys)
+    checked = 0
+    for (b, pts, _), k in zip(centres, keys):
+        r = o.point_result(k, 1)
+        d = pts - pts.mean(0)
+        C = d.T @ d
+        w, U = np.linalg.eigh(C)
+        if w[1] < 1.5 * w[0] + 1e-9:
+            continue            # near-degenerate: the axis is ill-defined
+        u = U[:, 0]
+        n = r["normal"].astype(np.float64)
+        cosang = abs(n @ u) / np.linalg.norm(n)
+        assert cosang > 1 - 1e-9, (cosang, w)
+        # orientation: towards the sensor (placed as in _cluster_oracle)
+        cen = np.concatenate(clusters).mean(0)
+        sd = np.array([0.3, 0.5, 1.0])
+        Q = np.rint(centre(cen) + 60 * 256 * sd / np.linalg.norm(sd))
+        assert n @ (Q - centre(b)) >= 0
+        checked += 1
+    assert checked >= 25
+
+
+# ----------------------------------------------------------------- mask
+def test_candidate_mask_hand_cases(oracle_mod, synth_mod):
+    """Plane z = 0 (normal +z), one sensor 30 deg off the normal towards +x.
+    Directions in the x-z plane at angle t from +z (positive towards +x):
+      0, 60, 69 deg: inside the 70 deg cone, within 30/39 deg of the view
+                     direction -> candidates;
+      71 deg:        outside the cone;
+      -60 deg:       90 deg from the view direction (dot 0 < 0.25);
+      180 deg:       against the normal;
+      -40 deg:       70 deg from the view direction (cos 70 = 0.34 > 0.25);
+      -50 deg:       80 deg from the view direction (0.17 < 0.25)."""
+    plane = np.array([[i, j, 0] for i in range(-4, 5) for j in range(-4, 5)])
+    s30 = [math.sin(math.radians(30)), 0.0, math.cos(math.radians(30))]
+    o = _cluster_oracle(oracle_mod, [plane], [s30], n_frames=1)
+    angs = [0, 60, 69, 71, -60, 180, -40, -50]
+    rot = []
+    for a in angs:
+        t = math.radians(a)
+        d = np.array([math.sin(t), 0.0, math.cos(t)])
+        e2 = np.array([0.0, 1.0, 0.0])
+        rot.append(np.stack([d, e2, np.cross(d, e2)], 1).reshape(9))
+    o.set_tool(0, synth_mod.cylinder_tool(0.01, 0.02, 0.02), np.array(rot))
+    k = oracle_mod.key(0, 0, 0)
+    o.score(0, keys=[k])
+    m = int(o.point_result(k, len(angs))["mask"][0])
+    bits = [(m >> i) & 1 for i in range(len(angs))]
+    assert bits == [1, 1, 1, 0, 0, 0, 1, 0]
+
+
+# ----------------------------------------------------------------- scoring
+def _bf_first_free(o, oracle_mod, tool, rot, v, tau, rc_u, n_c, s, cand, vox):
+    """Table-free decision per candidate orientation: arm samples at the voxel
+    containing centre + lambda*d, body/corridor membership of every occupied
+    voxel in metres.  Returns first free index or -1, and a flag telling
+    whether an ambiguous (boundary) case decided it."""
+    occ_ijk, occ_set, known = vox
+    rel_all = occ_ijk - s
+    near_mask = np.abs(rel_all).max(1) <= int(math.ceil((tool.length + tool.corridor) / v)) + 2
+    rel = rel_all[near_mask]
+    for k in cand:
+        d = rot[k].reshape(3, 3)[:, 0]
+        hit = False
+        for f in (0.6, 1.25, 2.25):
+            q = f * tau * d / v + 0.5
+            frac = q - np.floor(q)
+            if np.any((frac < 1e-9) | (frac > 1 - 1e-9)):
+                return None, True
+            y = tuple(int(t) for t in (s + np.floor(q).astype(np.int64)))
+            if y in occ_set or y not in known:
+                hit = True
+        if not hit:
+            body, far, amb = _membership(tool, rot[k], v, rel)
+            if np.any(amb):
+                return None, True
+            hit = body.sum() >= n_c or far.any()
+        if not hit:
+            return k, False
+    return -1, False
+
+
+def test_scoring_brute_force_tiny(oracle_mod, synth_mod):
+    """Labels and first free orientation of 250 sampled points of the tiny
+    scene agree with a table-free brute force over every occupied voxel."""
+    w = synth_mod.tiny()
+    o = oracle_mod.Oracle(voxel=w.voxel, trunc=w.trunc, r_c=w.r_c)
+    for f in w.frames():
+        o.integrate_frame(f.xyz, f.origin, f.frame_id)
+    o.set_tool(0, w.tool, w.rot)
+    o.score(0)
+    p = o.params()
+    key, S, W, c = o.read_tsdf()
+    ijk = oracle_mod.unpack_keys(key)
+    occ = (W > 0) & (S < p["rc_u"] * W.astype(np.int64))
+    occ_ijk = ijk[occ]
+    occ_set = {tuple(map(int, t)) for t in occ_ijk}
+    known = {tuple(map(int, t)) for t in ijk[(W > 0) | (c > 0)]}
+    pts = o.read_points()["key"]
+    rng = np.random.default_rng(4)
+    sample = rng.choice(pts, size=250, replace=False)
+    K = len(w.rot)
+    agree = amb = 0
+    labels = []
+    for k in sample:
+        r = o.point_result(k, K)
+        labels.append(r["label"])
+        cand = [j for j in range(K) if (int(r["mask"][j // 64]) >> (j % 64)) & 1]
+        s = oracle_mod.unkey(k)
+        ff, ambiguous = _bf_first_free(o, oracle_mod, w.tool, w.rot, w.voxel, w.trunc,
+                                       p["rc_u"], 5, s, cand, (occ_ijk, occ_set, known))
+        if ambiguous:
+            amb += 1
+            continue
+        exp_label = 3 if not cand else (1 if ff >= 0 else 2)
+        assert (r["label"], r["first_free"]) == (exp_label, ff if ff >= 0 else -1), k
+        agree += 1
+    assert agree >= 200
+    assert 2 in labels and 1 in labels      # both outcomes exercised
+
+
+def test_sphere_invariant(oracle_mod, synth_mod):
+    """Convex sphere seen from outside (noise-free): every point is confident
+    and at least 97% are ACCESSIBLE.  The remainder is the method's own
+    conservatism, not an error: arm samples that no ray cleared read as
+    occupied (Section 3.4), and at 2 cm voxels the 3 cm tool clips voxels that
+    grazing returns pulled below r_c (the caveat of Section 3.2).  A sign error
+    in the distance, the normal or the approach direction blocks nearly
+    everything, and the share collapses."""
+    w = synth_mod.tiny(sigma=0.0, scene=synth_mod.sphere_scene())
+    o = oracle_mod.Oracle(voxel=w.voxel, trunc=w.trunc, r_c=w.r_c)
+    for f in w.frames():
+        o.integrate_frame(f.xyz, f.origin, f.frame_id)
+    o.set_tool(0, w.tool, w.rot)
+    o.score(0)
+    keys, lbl, ff = o.labels(len(w.rot))
+    assert np.all(lbl != 0)
+    assert (lbl == oracle_mod.LABEL_ACCESSIBLE).mean() > 0.97
+    # points facing the sensor circle's plane (the equator band) are all free
+    c = (oracle_mod.unpack_keys(keys) + 0.5) * w.voxel
+    band = np.abs(c[:, 2] - 0.5) < 0.15
+    assert band.sum() > 1000
+    assert (lbl[band] == oracle_mod.LABEL_ACCESSIBLE).mean() > 0.995
+
+
+def test_slot_invariant(oracle_mod, synth_mod):
+    """Points inside the 3 cm slot deeper than r_s + 2v below the rim cannot
+    take the 6 cm-wide tool: all BLOCKED (the set must be non-empty)."""
+    w = synth_mod.tiny(sigma=0.0)
+    o = oracle_mod.Oracle(voxel=w.voxel, trunc=w.trunc, r_c=w.r_c)
+    for f in w.frames():
+        o.integrate_frame(f.xyz, f.origin, f.frame_id)
+    o.set_tool(0, w.tool, w.rot)
+    o.score(0)
+    keys, lbl, _ = o.labels(len(w.rot))
+    c = (oracle_mod.unpack_keys(keys) + 0.5) * w.voxel
+    deep = 0.4 - (w.tool.r_s + 2 * w.voxel)
+    inside = (np.abs(c[:, 1]) < 0.015 + w.voxel) & (np.abs(c[:, 0] - 1.0) < 0.15 + w.voxel) \
+        & (c[:, 2] < deep) & (c[:, 2] > 0.2)
+    assert inside.sum() >= 2
+    assert np.all(lbl[inside] == oracle_mod.LABEL_BLOCKED)
+
+
+def test_rotation_invariance_yaw(oracle_mod, synth_mod):
+    """Yaw-only candidate set (the paper's D = 180) is closed under a quarter
+    turn about z; the scene, sensors and tool turned by 90 degrees give the
+    same labels at the mapped voxels.  TSDF sums are exactly equivariant;
+    only a ray-cleared band sample that lands exactly on a voxel boundary can
+    change voxel under negation, so at most 0.1% of labels may differ."""
+    w = synth_mod.tiny()
+    rot = synth_mod.orientations(synth_mod.yaw_directions(180), 1)
+    frames = w.frames()
+    # A return whose fixed-point x or y lies exactly on a voxel boundary
+    # changes voxel under negation (half-open voxels); leave those out.
+    scale = 256.0 / w.voxel
+    for f in frames:
+        P = np.rint(f.xyz.astype(np.float64) * scale).astype(np.int64)
+        f.xyz = f.xyz[(P[:, 0] % 256 != 0) & (P[:, 1] % 256 != 0)]
+
+    def run(turn):
+        o = oracle_mod.Oracle(voxel=w.voxel, trunc=w.trunc, r_c=w.r_c)
+        for f in frames:
+            xyz, q = f.xyz, f.origin
+            if turn:
+                xyz = np.stack([-xyz[:, 1], xyz[:, 0], xyz[:, 2]], 1)
+                q = np.array([-q[1], q[0], q[2]], np.float32)
+            o.integrate_frame(xyz, q, f.frame_id)
+        o.set_tool(0, w.tool, rot)
+        o.score(0)
+        return o
+
+    a, b = run(False), run(True)
+    ka, la, _ = a.labels(180)
+    kb, lb, _ = b.labels(180)
+    ia = oracle_mod.unpack_keys(ka)
+    mapped = oracle_mod.pack_keys(np.stack([-ia[:, 1] - 1, ia[:, 0], ia[:, 2]], 1))
+    db = dict(zip(kb.tolist(), lb.tolist()))
+    common = [(l, db[m]) for m, l in zip(mapped.tolist(), la.tolist()) if m in db]
+    assert len(common) > 0.99 * len(ka)
+    diff = sum(1 for x, y in common if x != y)
+    assert diff <= 0.001 * len(common), diff
