@@ -1,0 +1,209 @@
+/*
+ * af.h -- C ABI of the MI355X accessibility-field library (libaf.so).
+ *
+ * Implements the per-frame hot path of "Beyond Visibility: Real-Time Surface
+ * Accessibility Fields from Sparse LiDAR" (Scott, Schofield, Green):
+ *   integrate_frame  scan-centric TSDF integration of one LiDAR frame into a
+ *                    hashed 8^3 voxel-block map (Section 3.2), the ray-cleared
+ *                    band (Section 3.4, "Arm path checking") and the voxel-
+ *                    deduplicated surface point set (Section 3.1);
+ *   set_tool_kernels precomputed rotated tool kernels (Section 3.4, "Tool
+ *                    kernel", "Self-exclusion"; Section 3.6);
+ *   score_points     normal and observation filters, collision count and arm
+ *                    samples for every confident point (Sections 3.4, 3.5);
+ *   read_labels      the per-point accessibility field (Section 3.1).
+ *
+ * Conventions
+ *   - All functions return AF_OK (0) or a negative AF_E* code; no exception or
+ *     signal crosses the ABI.  af_last_error() gives a text for the last error.
+ *   - A context is not thread-safe; use one context per host thread.
+ *   - `stream` arguments are hipStream_t values passed as void* (NULL = the
+ *     default stream).  Work is enqueued asynchronously on that stream unless
+ *     the function says it synchronises.
+ *   - Device pointers must be device memory of the context's GPU; host
+ *     pointers are ordinary host memory.  The library never keeps a caller's
+ *     pointer after a call returns (device inputs must stay valid until the
+ *     stream reaches the call).
+ *   - Positions are world-frame metres (float32) and are quantised to
+ *     integers in units of voxel/256 (round half to even of the fp64
+ *     product); voxel i covers [i v, (i+1) v).  A voxel key packs the index
+ *     (i + 2^20) in 21 bits per axis, x lowest.
+ */
+#ifndef AF_H
+#define AF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  AF_OK = 0,
+  AF_EINVAL = -1,    /* bad argument */
+  AF_ENOMEM = -2,    /* device memory or HBM budget exhausted */
+  AF_EDEVICE = -3,   /* HIP runtime error */
+  AF_ENOTOOL = -4,   /* tool id never set */
+  AF_EOVERFLOW = -5  /* block / point capacity exceeded (state is then incomplete) */
+};
+
+/* point labels */
+enum {
+  AF_UNSCORED = 0,     /* TSDF confidence w/(w+5) < 0.2, i.e. W < 2 (Section 3.5) */
+  AF_ACCESSIBLE = 1,   /* some candidate orientation is free */
+  AF_BLOCKED = 2,      /* every candidate orientation collides */
+  AF_NO_CANDIDATE = 3  /* no orientation passes the normal/observation filters */
+};
+
+/* table entry classes */
+enum { AF_CLS_BODY = 0, AF_CLS_NEAR = 1, AF_CLS_FAR = 2 };
+
+/* tool shapes */
+enum { AF_TOOL_CYLINDER = 0, AF_TOOL_BOX = 1 };
+
+typedef struct af_ctx af_ctx;
+
+typedef struct af_config {
+  double voxel;           /* voxel edge v, metres (> 0) */
+  double trunc;           /* truncation tau, metres; <= 0 selects min(4v, 0.1 m)
+                             (Section 3.2; read as min, see the design notes) */
+  double r_c;             /* collision threshold on the TSDF, metres */
+  int32_t n_c;            /* body voxels below r_c that block an orientation (5) */
+  int32_t weight_cap;     /* weight saturation with proportional rescale (2000) */
+  int32_t conf_min_w;     /* minimum W of a scored point (2 <=> c >= 0.2) */
+  double cos_normal;      /* cosine of the normal half-cone (cos 70 deg) */
+  double obs_dot;         /* observation-side dot threshold (0.25) */
+  double vp_min_dist;     /* novelty distance of stored viewpoints, metres (0.1) */
+  int32_t n_vp;           /* stored viewpoints per point, 1..8 (8) */
+  int32_t knn_k;          /* neighbours of the PCA normal (10) */
+  int32_t clamp_negative; /* 0: clamp d to [0, tau] (paper); 1: [-tau, tau] */
+  int32_t max_tools;      /* tool slots */
+  int64_t max_blocks;     /* voxel-block capacity */
+  int64_t max_points;     /* surface-point capacity */
+  int32_t max_orientations; /* per tool */
+  int32_t pad;
+  int64_t hbm_budget;     /* bytes the context may allocate (0 = unlimited) */
+} af_config;
+
+typedef struct af_tool {
+  int32_t shape;          /* AF_TOOL_CYLINDER or AF_TOOL_BOX */
+  int32_t pad;
+  double length;          /* body length along the approach axis (+x), m */
+  double corridor;        /* approach corridor beyond the body, m */
+  double r_s;             /* self-exclusion radius around the tip, m */
+  double radius;          /* cylinder radius, m */
+  double width, height;   /* box cross-section (local y, z), m */
+} af_tool;
+
+typedef struct af_frame_stats {
+  int64_t n_in, n_valid, n_dropped;
+  int64_t pairs_applied, pairs_excluded, band_marks;
+  int64_t new_points, n_points, voxels_folded;
+  int64_t n_blocks, new_blocks;
+} af_frame_stats;
+
+typedef struct af_score_stats {
+  int64_t n_points, n_confident, n_accessible, n_blocked, n_no_candidate;
+  int64_t candidate_tests, canonical_tests, canonical_lookups;
+} af_score_stats;
+
+/* Fill *cfg with the paper's constants for voxel size `voxel` and truncation
+ * `trunc` (metres; <= 0 for the default) and capacities for a scene of about
+ * a million surface points.  Returns AF_EINVAL for voxel <= 0. */
+int af_config_default(af_config *cfg, double voxel, double trunc);
+
+/* Create a context on the current HIP device: allocates the block pool, the
+ * hash tables, the point arrays and the label arrays up front.  Returns
+ * AF_EINVAL for an inconsistent configuration (truncation above 7 voxels,
+ * n_vp outside 1..8, ...), AF_ENOMEM when the fixed allocations exceed
+ * cfg->hbm_budget or the device, AF_EDEVICE on a HIP error.  *out receives
+ * the context (NULL on error). */
+int af_create(const af_config *cfg, af_ctx **out);
+
+/* Release every device allocation of the context.  Synchronises the device. */
+int af_destroy(af_ctx *ctx);
+
+/* Text of the last error on this context (never NULL). */
+const char *af_last_error(const af_ctx *ctx);
+
+/* Section 3.4 "Tool kernel" / Section 3.6: precompute the rotated kernels of
+ * tool `tool_id` (0 <= id < max_tools) for K orientations.  `rot` is a host
+ * array of K row-major 3x3 rotation matrices (fp64) whose columns are the
+ * tool's local axes in world coordinates: column 0 is the approach direction
+ * (the tool extends along it from the tip at the surface point), columns 1-2
+ * span the cross-section.  The table of orientation k lists, as voxel offsets
+ * from the point's voxel: the three arm samples at {0.6, 1.25, 2.25} tau along
+ * the approach direction (NEAR), the voxel centres inside the tool body
+ * (BODY) and inside its corridor (FAR), minus the self-exclusion ball r_s;
+ * BODY and FAR are each sorted by (|o|^2, z, y, x).  Built on the device; the
+ * call synchronises `stream`.  Errors: AF_EINVAL (bad shape, K outside
+ * 1..max_orientations, rotation column norms off by > 1e-9, an offset beyond
+ * +-511 voxels or more than 16384 entries of one class), AF_ENOMEM. Replacing
+ * a tool invalidates its labels. */
+int af_set_tool_kernels(af_ctx *ctx, int32_t tool_id, const af_tool *tool,
+                        int32_t K, const double *rot, void *stream);
+
+/* Section 3.2: integrate one frame.  `xyz` is a DEVICE array of n float32
+ * triples (world frame), `origin` a HOST array of 3 floats (the sensor
+ * position of the frame).  For every valid return the voxels of the index
+ * cube of half-width ceil(tau/v) around it, except those inside the
+ * cos > 0.95 cone behind it, receive d = |p - q| - |x - q| (voxel centre x,
+ * clamped to [0, tau]) as integer sums S, W; the band (tau, 2.25 tau] back
+ * along the ray is marked ray-cleared; the return's voxel joins the surface
+ * point set.  The frame is folded at the end (weights capped with
+ * proportional rescaling of S).  Returns that are non-finite, out of range
+ * (|x| >= 2^28 units) or at the sensor position are dropped and counted.
+ * `frame_id` must increase strictly (AF_EINVAL otherwise).  The call
+ * synchronises `stream` once, after block allocation.  AF_EOVERFLOW when the
+ * block or point capacity is exceeded. */
+int af_integrate_frame(af_ctx *ctx, const float *xyz, int64_t n,
+                       const float origin[3], int64_t frame_id, void *stream);
+
+/* Sections 3.4-3.5: label every surface point for tool `tool_id`: W < W_min
+ * -> AF_UNSCORED; else candidates = orientations whose approach direction is
+ * within the normal half-cone and seen from that side by a stored viewpoint;
+ * the lowest-index candidate with no arm-sample hit (TSDF < r_c, or unknown
+ * and not ray-cleared), fewer than n_c body voxels with TSDF < r_c and no
+ * corridor voxel with TSDF < r_c is the point's first free orientation
+ * (AF_ACCESSIBLE); none -> AF_BLOCKED; no candidate -> AF_NO_CANDIDATE.
+ * Asynchronous on `stream`.  AF_ENOTOOL if the tool was never set. */
+int af_score_points(af_ctx *ctx, int32_t tool_id, void *stream);
+
+/* Copy labels of points [first, first + count) in canonical order (by first
+ * frame, then key) into HOST arrays (any may be NULL): voxel key, label,
+ * first free orientation (-1 if none) and the point voxel's weight W.
+ * Synchronises the context's last stream.  *n_written = number copied. */
+int af_read_labels(af_ctx *ctx, int32_t tool_id, int64_t first, int64_t count,
+                   int64_t *key, uint8_t *label, int16_t *first_free,
+                   uint16_t *w, int64_t *n_written);
+
+/* ---- inspection (tests and benchmarks); all synchronise ---- */
+int64_t af_num_points(af_ctx *ctx);
+int64_t af_num_blocks(af_ctx *ctx);
+/* Every voxel with W > 0 or ray-cleared, unordered, into HOST arrays of
+ * capacity cap; *n = number of such voxels (may exceed cap). */
+int af_read_tsdf(af_ctx *ctx, int64_t *key, int64_t *S, int32_t *W,
+                 uint8_t *cleared, int64_t cap, int64_t *n);
+/* Point records in canonical order: key, first frame, stored viewpoints
+ * (count and [8][3] fixed-point positions, oldest first), the running sum
+ * of sensor positions ([3]) and its count. */
+int af_read_points(af_ctx *ctx, int64_t first, int64_t count, int64_t *key,
+                   int32_t *first_frame, int32_t *n_vp, int32_t *vp,
+                   int64_t *sumq, int32_t *nq, int64_t *n_written);
+/* Table of orientation k: offsets [m][3] and classes; *m = entry count. */
+int af_read_tool_table(af_ctx *ctx, int32_t tool_id, int32_t k, int32_t *off,
+                       uint8_t *cls, int64_t cap, int64_t *m);
+/* Normals (int32 [3], has_normal) and candidate masks ([ceil(K/64)] words)
+ * from the last af_score_points of tool_id, for points [first, first+count). */
+int af_read_point_debug(af_ctx *ctx, int32_t tool_id, int64_t first,
+                        int64_t count, int32_t *normal, int32_t *has_normal,
+                        uint64_t *mask, int64_t *n_written);
+int af_frame_stats_get(af_ctx *ctx, af_frame_stats *st);
+int af_score_stats_get(af_ctx *ctx, int32_t tool_id, af_score_stats *st);
+/* Bytes of device memory the context holds. */
+int64_t af_device_bytes(af_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,289 @@
+"""Thin ctypes binding of libaf.so (include/af.h).
+
+Argument marshalling only: every step of the hot path runs in the library's
+HIP kernels.  PyTorch supplies device memory and streams: pass a CUDA float32
+tensor of shape [n, 3] to ``integrate_frame``; the current torch stream is
+used unless another is given.  There is no fallback: if libaf.so is missing
+or fails to load, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libaf.so")
+
+AF_OK, AF_EINVAL, AF_ENOMEM, AF_EDEVICE, AF_ENOTOOL, AF_EOVERFLOW = 0, -1, -2, -3, -4, -5
+UNSCORED, ACCESSIBLE, BLOCKED, NO_CANDIDATE = 0, 1, 2, 3
+CLS_BODY, CLS_NEAR, CLS_FAR = 0, 1, 2
+TOOL_CYLINDER, TOOL_BOX = 0, 1
+
+_ERRNAMES = {AF_EINVAL: "AF_EINVAL", AF_ENOMEM: "AF_ENOMEM", AF_EDEVICE: "AF_EDEVICE",
+             AF_ENOTOOL: "AF_ENOTOOL", AF_EOVERFLOW: "AF_EOVERFLOW"}
+
+
+class AFError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (_ERRNAMES.get(code, "error"), code, msg))
+        self.code = code
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("voxel", ctypes.c_double), ("trunc", ctypes.c_double),
+                ("r_c", ctypes.c_double), ("n_c", ctypes.c_int32),
+                ("weight_cap", ctypes.c_int32), ("conf_min_w", ctypes.c_int32),
+                ("cos_normal", ctypes.c_double), ("obs_dot", ctypes.c_double),
+                ("vp_min_dist", ctypes.c_double), ("n_vp", ctypes.c_int32),
+                ("knn_k", ctypes.c_int32), ("clamp_negative", ctypes.c_int32),
+                ("max_tools", ctypes.c_int32), ("max_blocks", ctypes.c_int64),
+                ("max_points", ctypes.c_int64), ("max_orientations", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("hbm_budget", ctypes.c_int64)]
+
+
+class Tool(ctypes.Structure):
+    _fields_ = [("shape", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("length", ctypes.c_double), ("corridor", ctypes.c_double),
+                ("r_s", ctypes.c_double), ("radius", ctypes.c_double),
+                ("width", ctypes.c_double), ("height", ctypes.c_double)]
+
+
+class FrameStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in
+                ("n_in", "n_valid", "n_dropped", "pairs_applied", "pairs_excluded",
+                 "band_marks", "new_points", "n_points", "voxels_folded", "n_blocks",
+                 "new_blocks")]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class ScoreStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in
+                ("n_points", "n_confident", "n_accessible", "n_blocked",
+                 "n_no_candidate", "candidate_tests", "canonical_tests",
+                 "canonical_lookups")]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+# name -> (restype, argtypes); also used by the export test
+_vp, _i32, _i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+SIGNATURES = {
+    "af_config_default": (ctypes.c_int, [ctypes.POINTER(Config), ctypes.c_double, ctypes.c_double]),
+    "af_create": (ctypes.c_int, [ctypes.POINTER(Config), ctypes.POINTER(_vp)]),
+    "af_destroy": (ctypes.c_int, [_vp]),
+    "af_last_error": (ctypes.c_char_p, [_vp]),
+    "af_set_tool_kernels": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(Tool), _i32, _vp, _vp]),
+    "af_integrate_frame": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _vp]),
+    "af_score_points": (ctypes.c_int, [_vp, _i32, _vp]),
+    "af_read_labels": (ctypes.c_int, [_vp, _i32, _i64, _i64, _vp, _vp, _vp, _vp, _vp]),
+    "af_num_points": (_i64, [_vp]),
+    "af_num_blocks": (_i64, [_vp]),
+    "af_read_tsdf": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _i64, _vp]),
+    "af_read_points": (ctypes.c_int, [_vp, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "af_read_tool_table": (ctypes.c_int, [_vp, _i32, _i32, _vp, _vp, _i64, _vp]),
+    "af_read_point_debug": (ctypes.c_int, [_vp, _i32, _i64, _i64, _vp, _vp, _vp, _vp]),
+    "af_frame_stats_get": (ctypes.c_int, [_vp, ctypes.POINTER(FrameStats)]),
+    "af_score_stats_get": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(ScoreStats)]),
+    "af_device_bytes": (_i64, [_vp]),
+}
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError("libaf.so is not built (%s); run __graft_entry__.build()" % path)
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        _lib = load_library()
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def default_config(voxel: float, trunc: float = 0.0, **overrides) -> Config:
+    cfg = Config()
+    rc = lib().af_config_default(ctypes.byref(cfg), float(voxel), float(trunc))
+    if rc != AF_OK:
+        raise AFError(rc, "bad voxel size")
+    for k, v in overrides.items():
+        if not hasattr(cfg, k):
+            raise KeyError(k)
+        setattr(cfg, k, v)
+    return cfg
+
+
+def tool_struct(tool) -> Tool:
+    g = (lambda k, d=0.0: tool[k] if isinstance(tool, dict) and k in tool
+         else getattr(tool, k, d))
+    return Tool(int(g("shape", 0)), 0, float(g("length")), float(g("corridor")),
+                float(g("r_s")), float(g("radius")), float(g("width")), float(g("height")))
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Context:
+    """One accessibility-field map on the current GPU (af_ctx)."""
+
+    def __init__(self, cfg: Config | None = None, voxel: float | None = None,
+                 trunc: float = 0.0, **overrides):
+        self._lib = lib()
+        if cfg is None:
+            cfg = default_config(voxel, trunc, **overrides)
+        self.cfg = cfg
+        h = ctypes.c_void_p()
+        rc = self._lib.af_create(ctypes.byref(cfg), ctypes.byref(h))
+        if rc != AF_OK:
+            raise AFError(rc, "af_create failed")
+        self.h = h
+        self.K = {}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._lib.af_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != AF_OK:
+            raise AFError(rc, self._lib.af_last_error(self.h).decode())
+
+    # ---- the four calls of the hot path ----
+    def set_tool_kernels(self, tool_id: int, tool, rot, stream=None):
+        rot = np.ascontiguousarray(rot, dtype=np.float64).reshape(-1, 9)
+        t = tool_struct(tool)
+        self._check(self._lib.af_set_tool_kernels(self.h, int(tool_id), ctypes.byref(t),
+                                                  len(rot), _p(rot), _stream_handle(stream)))
+        self.K[tool_id] = len(rot)
+
+    def integrate_frame(self, xyz, origin, frame_id: int, stream=None):
+        """xyz: CUDA float32 tensor [n, 3] (contiguous); origin: 3 floats."""
+        if not (getattr(xyz, "is_cuda", False) and str(xyz.dtype) == "torch.float32"
+                and xyz.is_contiguous() and xyz.dim() == 2 and xyz.shape[1] == 3):
+            raise TypeError("xyz must be a contiguous CUDA float32 tensor of shape [n, 3]")
+        o = np.ascontiguousarray(origin, dtype=np.float32).reshape(3)
+        self._check(self._lib.af_integrate_frame(self.h, ctypes.c_void_p(xyz.data_ptr()),
+                                                 int(xyz.shape[0]), _p(o), int(frame_id),
+                                                 _stream_handle(stream)))
+
+    def score_points(self, tool_id: int, stream=None):
+        self._check(self._lib.af_score_points(self.h, int(tool_id), _stream_handle(stream)))
+
+    def read_labels(self, tool_id: int, first: int = 0, count: int | None = None,
+                    with_w: bool = False):
+        n = self.num_points()
+        count = n - first if count is None else count
+        count = max(0, min(count, n - first))
+        key = np.zeros(count, np.int64)
+        lbl = np.zeros(count, np.uint8)
+        ff = np.zeros(count, np.int16)
+        w = np.zeros(count, np.uint16) if with_w else None
+        nw = ctypes.c_int64()
+        self._check(self._lib.af_read_labels(self.h, int(tool_id), int(first), int(count),
+                                             _p(key), _p(lbl), _p(ff),
+                                             _p(w) if with_w else None, ctypes.byref(nw)))
+        out = dict(key=key[:nw.value], label=lbl[:nw.value], first_free=ff[:nw.value])
+        if with_w:
+            out["w"] = w[:nw.value]
+        return out
+
+    # ---- inspection ----
+    def num_points(self) -> int:
+        n = self._lib.af_num_points(self.h)
+        if n < 0:
+            self._check(AF_EDEVICE)
+        return n
+
+    def num_blocks(self) -> int:
+        return self._lib.af_num_blocks(self.h)
+
+    def device_bytes(self) -> int:
+        return self._lib.af_device_bytes(self.h)
+
+    def read_tsdf(self):
+        n = ctypes.c_int64()
+        self._check(self._lib.af_read_tsdf(self.h, None, None, None, None, 0, ctypes.byref(n)))
+        m = n.value
+        key = np.zeros(m, np.int64)
+        S = np.zeros(m, np.int64)
+        W = np.zeros(m, np.int32)
+        c = np.zeros(m, np.uint8)
+        self._check(self._lib.af_read_tsdf(self.h, _p(key), _p(S), _p(W), _p(c), m,
+                                           ctypes.byref(n)))
+        o = np.argsort(key)
+        return key[o], S[o], W[o], c[o]
+
+    def read_points(self):
+        n = self.num_points()
+        key = np.zeros(n, np.int64)
+        ff = np.zeros(n, np.int32)
+        nvp = np.zeros(n, np.int32)
+        vp = np.zeros((n, 8, 3), np.int32)
+        sq = np.zeros((n, 3), np.int64)
+        nq = np.zeros(n, np.int32)
+        nw = ctypes.c_int64()
+        self._check(self._lib.af_read_points(self.h, 0, n, _p(key), _p(ff), _p(nvp), _p(vp),
+                                             _p(sq), _p(nq), ctypes.byref(nw)))
+        return dict(key=key, first_frame=ff, n_vp=nvp, vp=vp, sumq=sq, nq=nq)
+
+    def read_tool_table(self, tool_id: int, k: int):
+        m = ctypes.c_int64()
+        self._check(self._lib.af_read_tool_table(self.h, int(tool_id), int(k), None, None, 0,
+                                                 ctypes.byref(m)))
+        off = np.zeros((m.value, 3), np.int32)
+        cls = np.zeros(m.value, np.uint8)
+        self._check(self._lib.af_read_tool_table(self.h, int(tool_id), int(k), _p(off),
+                                                 _p(cls), m.value, ctypes.byref(m)))
+        return off, cls
+
+    def read_point_debug(self, tool_id: int, first: int = 0, count: int | None = None):
+        n = self.num_points()
+        count = n - first if count is None else count
+        count = max(0, min(count, n - first))
+        mw = (self.K[tool_id] + 63) // 64
+        nrm = np.zeros((count, 3), np.int32)
+        hn = np.zeros(count, np.int32)
+        mask = np.zeros((count, mw), np.uint64)
+        nw = ctypes.c_int64()
+        self._check(self._lib.af_read_point_debug(self.h, int(tool_id), int(first), int(count),
+                                                  _p(nrm), _p(hn), _p(mask), ctypes.byref(nw)))
+        return dict(normal=nrm, has_normal=hn, mask=mask)
+
+    def frame_stats(self):
+        st = FrameStats()
+        self._check(self._lib.af_frame_stats_get(self.h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def score_stats(self, tool_id: int):
+        st = ScoreStats()
+        self._check(self._lib.af_score_stats_get(self.h, int(tool_id), ctypes.byref(st)))
+        return st.as_dict()

@@ -1,0 +1,678 @@
+// libaf host side: context and device memory, the C ABI of include/af.h and
+// the stream-ordered sequence of kernels per call.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "af_internal.h"
+
+using namespace af;
+
+struct af_ctx {
+  af_config cfg;
+  Params p;
+  double tau;          // resolved truncation, metres
+  int device;
+  int64_t bytes;       // device bytes held
+  std::vector<void *> allocs;
+  MapDev map;
+  PointsDev pts;
+  FrameScratch fs;
+  GridDev grid;
+  int64_t grid_bricks;
+  FrameCounters *counters;      // device
+  FrameCounters *counters_host; // pinned
+  std::vector<ToolDev> tools;
+  std::vector<int64_t> tool_bytes;
+  uint64_t *mask;               // shared candidate-mask scratch
+  int64_t last_frame;
+  int64_t n_points, n_blocks;   // host mirrors after the last frame
+  int32_t bbox_lo[3], bbox_hi[3];
+  bool have_bbox;
+  hipStream_t last_stream;
+  af_frame_stats fstats;
+  std::string err;
+  int status;
+};
+
+namespace {
+
+const char *kNoError = "no error";
+
+int fail(af_ctx *c, int code, const char *fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return code;
+}
+
+#define HIP_TRY(ctx, expr)                                                             \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(ctx, AF_EDEVICE, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                  __LINE__);                                                           \
+  } while (0)
+
+int dev_alloc(af_ctx *c, void **p, int64_t bytes) {
+  if (bytes <= 0) bytes = 8;
+  if (c->cfg.hbm_budget > 0 && c->bytes + bytes > c->cfg.hbm_budget)
+    return fail(c, AF_ENOMEM, "HBM budget of %lld bytes exceeded (need %lld more)",
+                (long long)c->cfg.hbm_budget, (long long)bytes);
+  hipError_t e = hipMalloc(p, (size_t)bytes);
+  if (e != hipSuccess) return fail(c, AF_ENOMEM, "hipMalloc(%lld): %s", (long long)bytes, hipGetErrorString(e));
+  c->bytes += bytes;
+  c->allocs.push_back(*p);
+  return AF_OK;
+}
+
+void dev_free(af_ctx *c, void *p, int64_t bytes) {
+  if (!p) return;
+  hipFree(p);
+  c->bytes -= bytes;
+  c->allocs.erase(std::remove(c->allocs.begin(), c->allocs.end(), p), c->allocs.end());
+}
+
+uint32_t pow2_at_least(int64_t n) {
+  uint64_t c = 1;
+  while ((int64_t)c < n) c <<= 1;
+  return (uint32_t)c;
+}
+
+#define ALLOC(ctx, ptr, count)                                                            \
+  do {                                                                                    \
+    int rc_ = dev_alloc(ctx, (void **)&(ptr), (int64_t)sizeof(*(ptr)) * (int64_t)(count)); \
+    if (rc_ != AF_OK) return rc_;                                                         \
+  } while (0)
+
+int alloc_scratch(af_ctx *c, int64_t cap) {
+  FrameScratch &f = c->fs;
+  if (f.cap > 0) {
+    dev_free(c, f.P, sizeof(int4) * f.cap);
+    dev_free(c, f.span, sizeof(int32_t) * f.cap * kMaxSpan);
+    dev_free(c, f.band, sizeof(int32_t) * f.cap * kMaxBand * 2);
+    dev_free(c, f.pslot, sizeof(int32_t) * f.cap);
+    dev_free(c, f.new_blocks, sizeof(int32_t) * f.cap * (kMaxSpan + kMaxBand));
+    dev_free(c, f.new_keys, sizeof(int64_t) * f.cap);
+    dev_free(c, f.new_kslot, sizeof(int32_t) * f.cap);
+    dev_free(c, f.touched, sizeof(int32_t) * f.cap * (kMaxSpan + kMaxBand));
+    memset(&f, 0, sizeof(f));
+  }
+  ALLOC(c, f.P, cap);
+  ALLOC(c, f.span, cap * kMaxSpan);
+  ALLOC(c, f.band, cap * kMaxBand * 2);
+  ALLOC(c, f.pslot, cap);
+  ALLOC(c, f.new_blocks, cap * (kMaxSpan + kMaxBand));
+  ALLOC(c, f.new_keys, cap);
+  ALLOC(c, f.new_kslot, cap);
+  ALLOC(c, f.touched, cap * (kMaxSpan + kMaxBand));
+  f.cap = cap;
+  return AF_OK;
+}
+
+int hip_check(af_ctx *c, const char *where) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(c, AF_EDEVICE, "%s: %s", where, hipGetErrorString(e));
+  return AF_OK;
+}
+
+// Grow the brick grid so that it covers block box [lo, hi]; new grids are
+// filled with "unknown" and rebuilt from every block.
+int ensure_grid(af_ctx *c, hipStream_t s, bool &rebuilt) {
+  rebuilt = false;
+  if (!c->have_bbox) return AF_OK;
+  GridDev &g = c->grid;
+  bool inside = c->grid_bricks > 0;
+  for (int a = 0; a < 3 && inside; ++a)
+    inside = c->bbox_lo[a] >= g.g0[a] && c->bbox_hi[a] < g.g0[a] + g.gd[a];
+  if (inside) return AF_OK;
+  GridDev ng;
+  memset(&ng, 0, sizeof(ng));
+  int64_t nb = 1;
+  for (int a = 0; a < 3; ++a) {
+    int32_t ext = c->bbox_hi[a] - c->bbox_lo[a] + 1;
+    int32_t margin = std::max<int32_t>(4, ext / 4);
+    ng.g0[a] = c->bbox_lo[a] - margin;
+    ng.gd[a] = ext + 2 * margin;
+    nb *= ng.gd[a];
+  }
+  if (c->grid_bricks > 0) {
+    HIP_TRY(c, hipStreamSynchronize(s));
+    dev_free(c, g.pred, sizeof(uint32_t) * 32 * c->grid_bricks);
+    dev_free(c, g.surf, sizeof(uint32_t) * 16 * c->grid_bricks);
+    c->grid_bricks = 0;
+  }
+  ALLOC(c, ng.pred, nb * 32);
+  ALLOC(c, ng.surf, nb * 16);
+  c->grid = ng;
+  c->grid_bricks = nb;
+  launch_grid_fill(c->grid, s);
+  rebuilt = true;
+  return hip_check(c, "grid fill");
+}
+
+}  // namespace
+
+extern "C" {
+
+int af_config_default(af_config *cfg, double voxel, double trunc) {
+  if (!cfg || !(voxel > 0)) return AF_EINVAL;
+  memset(cfg, 0, sizeof(*cfg));
+  cfg->voxel = voxel;
+  cfg->trunc = trunc;
+  cfg->r_c = 0.01;
+  cfg->n_c = 5;
+  cfg->weight_cap = 2000;
+  cfg->conf_min_w = 2;
+  cfg->cos_normal = 0.3420201433256687;  // cos 70 deg
+  cfg->obs_dot = 0.25;
+  cfg->vp_min_dist = 0.1;
+  cfg->n_vp = 8;
+  cfg->knn_k = 10;
+  cfg->clamp_negative = 0;
+  cfg->max_tools = 8;
+  cfg->max_blocks = 1 << 18;
+  cfg->max_points = 1 << 22;
+  cfg->max_orientations = 1024;
+  cfg->hbm_budget = 0;
+  return AF_OK;
+}
+
+int af_create(const af_config *cfg, af_ctx **out) {
+  if (!out) return AF_EINVAL;
+  *out = nullptr;
+  if (!cfg || !(cfg->voxel > 0) || cfg->n_vp < 1 || cfg->n_vp > kMaxVp || cfg->knn_k < 1 ||
+      cfg->n_c < 1 || cfg->n_c > 64 || cfg->weight_cap < 1 || cfg->weight_cap > 60000 ||
+      cfg->max_tools < 1 || cfg->max_blocks < 1 || cfg->max_blocks >= (1LL << 22) ||
+      cfg->max_points < 1 || cfg->max_points >= (1LL << 30) || cfg->max_orientations < 1 ||
+      cfg->max_orientations > 65536)
+    return AF_EINVAL;
+  af_ctx *c = new af_ctx();
+  c->cfg = *cfg;
+  c->err = kNoError;
+  hipGetDevice(&c->device);
+  // Section 3.2: tau = min(4v, 0.1 m) unless given (the text prints max; the
+  // voxel-size study of Section 4.1 needs tau proportional to v).
+  c->tau = cfg->trunc > 0 ? cfg->trunc : std::min(4.0 * cfg->voxel, 0.1);
+  Params &p = c->p;
+  memset(&p, 0, sizeof(p));
+  p.scale = 256.0 / cfg->voxel;
+  int64_t tau_u = llrint(c->tau * p.scale);
+  int64_t R = (tau_u + 255) / 256;
+  if (R < 1 || R > 7) {
+    delete c;
+    return AF_EINVAL;
+  }
+  p.tau_u = (int32_t)tau_u;
+  p.R = (int32_t)R;
+  p.rc_u = (int32_t)llrint(cfg->r_c * p.scale);
+  p.n_c = cfg->n_c;
+  p.cap = cfg->weight_cap;
+  p.conf_min_w = cfg->conf_min_w;
+  p.n_vp = cfg->n_vp;
+  p.knn_k = cfg->knn_k;
+  p.clamp_neg = cfg->clamp_negative ? 1 : 0;
+  int64_t dmin = llrint(cfg->vp_min_dist * p.scale);
+  p.dmin2 = dmin * dmin;
+  p.cos2 = cfg->cos_normal * cfg->cos_normal;
+  p.obs2 = cfg->obs_dot * cfg->obs_dot;
+  c->last_frame = -1;
+  c->last_stream = nullptr;
+
+  auto bail = [&](int rc) {
+    for (void *q : c->allocs) hipFree(q);
+    if (c->counters_host) hipHostFree(c->counters_host);
+    delete c;
+    return rc;
+  };
+  int rc;
+#define CREATE_ALLOC(ptr, count)                                                   \
+  if ((rc = dev_alloc(c, (void **)&(ptr), (int64_t)sizeof(*(ptr)) * (int64_t)(count))) != AF_OK) \
+    return bail(rc);
+  const int64_t B = cfg->max_blocks, NP = cfg->max_points;
+  MapDev &m = c->map;
+  m.max_blocks = B;
+  m.h.mask = pow2_at_least(2 * B) - 1;
+  CREATE_ALLOC(m.h.keys, (int64_t)m.h.mask + 1);
+  CREATE_ALLOC(m.h.vals, (int64_t)m.h.mask + 1);
+  CREATE_ALLOC(m.bkey, B);
+  CREATE_ALLOC(m.S, B * kBlockVox);
+  CREATE_ALLOC(m.W, B * kBlockVox);
+  CREATE_ALLOC(m.clr, B * 16);
+  CREATE_ALLOC(m.surf, B * 16);
+  CREATE_ALLOC(m.delta, B * kBlockVox);
+  CREATE_ALLOC(m.touched, B);
+  CREATE_ALLOC(m.n_blocks, 1);
+  PointsDev &q = c->pts;
+  q.max_points = NP;
+  q.h.mask = pow2_at_least(2 * NP) - 1;
+  CREATE_ALLOC(q.h.keys, (int64_t)q.h.mask + 1);
+  CREATE_ALLOC(q.h.vals, (int64_t)q.h.mask + 1);
+  CREATE_ALLOC(q.key, NP);
+  CREATE_ALLOC(q.first, NP);
+  CREATE_ALLOC(q.addr, NP);
+  CREATE_ALLOC(q.last, NP);
+  CREATE_ALLOC(q.nvp, NP);
+  CREATE_ALLOC(q.head, NP);
+  CREATE_ALLOC(q.vp, NP * kMaxVp * 3);
+  CREATE_ALLOC(q.sumq, NP * 3);
+  CREATE_ALLOC(q.nq, NP);
+  CREATE_ALLOC(q.normal, NP * 3);
+  CREATE_ALLOC(q.has_normal, NP);
+  CREATE_ALLOC(q.n_points, 1);
+  CREATE_ALLOC(c->counters, 1);
+  CREATE_ALLOC(c->mask, NP * ((cfg->max_orientations + 63) / 64));
+  c->tools.assign(cfg->max_tools, ToolDev());
+  c->tool_bytes.assign(cfg->max_tools, 0);
+  for (auto &t : c->tools) memset(&t, 0, sizeof(t));
+  if (hipHostMalloc((void **)&c->counters_host, sizeof(FrameCounters)) != hipSuccess)
+    return bail(AF_ENOMEM);
+  memset(c->counters_host, 0, sizeof(FrameCounters));
+  if (hipMemset(m.h.keys, 0xff, sizeof(int64_t) * ((int64_t)m.h.mask + 1)) != hipSuccess ||
+      hipMemset(q.h.keys, 0xff, sizeof(int64_t) * ((int64_t)q.h.mask + 1)) != hipSuccess ||
+      hipMemset(m.n_blocks, 0, sizeof(int32_t)) != hipSuccess ||
+      hipMemset(q.n_points, 0, sizeof(int32_t)) != hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess)
+    return bail(AF_EDEVICE);
+  if ((rc = alloc_scratch(c, 1 << 15)) != AF_OK) return bail(rc);
+  *out = c;
+  return AF_OK;
+#undef CREATE_ALLOC
+}
+
+int af_destroy(af_ctx *c) {
+  if (!c) return AF_EINVAL;
+  hipDeviceSynchronize();
+  for (void *q : c->allocs) hipFree(q);
+  if (c->counters_host) hipHostFree(c->counters_host);
+  delete c;
+  return AF_OK;
+}
+
+const char *af_last_error(const af_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+int64_t af_device_bytes(af_ctx *c) { return c ? c->bytes : 0; }
+
+int af_set_tool_kernels(af_ctx *c, int32_t tool_id, const af_tool *tool, int32_t K,
+                        const double *rot, void *stream) {
+  if (!c) return AF_EINVAL;
+  if (tool_id < 0 || tool_id >= c->cfg.max_tools)
+    return fail(c, AF_EINVAL, "tool id %d outside [0, %d)", tool_id, c->cfg.max_tools);
+  if (!tool || !rot || K < 1 || K > c->cfg.max_orientations)
+    return fail(c, AF_EINVAL, "bad tool, rotations or K=%d", K);
+  if ((tool->shape != AF_TOOL_CYLINDER && tool->shape != AF_TOOL_BOX) || !(tool->length > 0) ||
+      !(tool->corridor >= 0) || !(tool->r_s >= 0) ||
+      (tool->shape == AF_TOOL_CYLINDER && !(tool->radius > 0)) ||
+      (tool->shape == AF_TOOL_BOX && !(tool->width > 0 && tool->height > 0)))
+    return fail(c, AF_EINVAL, "bad tool geometry");
+  for (int32_t k = 0; k < K; ++k)
+    for (int col = 0; col < 3; ++col) {
+      double n2 = 0;
+      for (int row = 0; row < 3; ++row) n2 += rot[9 * k + 3 * row + col] * rot[9 * k + 3 * row + col];
+      if (!(fabs(sqrt(n2) - 1.0) <= 1e-9))
+        return fail(c, AF_EINVAL, "orientation %d column %d is not a unit vector", k, col);
+    }
+  hipStream_t s = (hipStream_t)stream;
+  const double v = c->cfg.voxel;
+  ToolGeom tg;
+  memset(&tg, 0, sizeof(tg));
+  tg.shape = tool->shape;
+  tg.Lv = tool->length / v;
+  tg.Ev = (tool->length + tool->corridor) / v;
+  if (tool->shape == AF_TOOL_CYLINDER) {
+    tg.a = tool->radius / v;
+    tg.b = tg.a;
+  } else {
+    tg.a = (0.5 * tool->width) / v;
+    tg.b = (0.5 * tool->height) / v;
+  }
+  tg.rv2 = tg.a * tg.a;
+  double rsv = tool->r_s / v;
+  tg.rsv2 = rsv * rsv;
+  const double fr[3] = {0.6, 1.25, 2.25};
+  for (int j = 0; j < 3; ++j) tg.lam[j] = (fr[j] * c->tau) / v;
+
+  ToolDev &t = c->tools[tool_id];
+  if (t.entries) {
+    HIP_TRY(c, hipStreamSynchronize(s));
+    dev_free(c, t.entries, c->tool_bytes[tool_id]);
+    dev_free(c, t.begin, sizeof(uint32_t) * (t.K + 1));
+    dev_free(c, t.rot, sizeof(double) * 9 * t.K);
+    dev_free(c, t.label, c->cfg.max_points);
+    dev_free(c, t.first_free, sizeof(int16_t) * c->cfg.max_points);
+    dev_free(c, t.counters, sizeof(ScoreCounters));
+    memset(&t, 0, sizeof(t));
+  }
+  ToolDev nt;
+  memset(&nt, 0, sizeof(nt));
+  uint32_t *counts = nullptr;
+  int32_t *err = nullptr;
+  ALLOC(c, nt.rot, 9 * (int64_t)K);
+  ALLOC(c, nt.begin, K + 1);
+  ALLOC(c, counts, 2 * (int64_t)K);
+  ALLOC(c, err, 1);
+  HIP_TRY(c, hipMemcpyAsync(nt.rot, rot, sizeof(double) * 9 * K, hipMemcpyHostToDevice, s));
+  HIP_TRY(c, hipMemsetAsync(err, 0, sizeof(int32_t), s));
+  tg.pad = 0;
+  if (launch_table_build(tg, K, nt.rot, counts, nt.begin, err, nullptr, 0, s) != 0)
+    return hip_check(c, "table count");
+  uint32_t total = 0;
+  int32_t herr = 0;
+  HIP_TRY(c, hipMemcpyAsync(&total, nt.begin + K, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipMemcpyAsync(&herr, err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  if (herr) {
+    dev_free(c, counts, sizeof(uint32_t) * 2 * K);
+    dev_free(c, err, sizeof(int32_t));
+    dev_free(c, nt.rot, sizeof(double) * 9 * K);
+    dev_free(c, nt.begin, sizeof(uint32_t) * (K + 1));
+    return fail(c, AF_EINVAL, "tool too large for the voxel size (%s)",
+                herr & 2 ? "more than 16384 entries in one class" : "offset beyond 511 voxels");
+  }
+  ALLOC(c, nt.entries, total);
+  ALLOC(c, nt.label, c->cfg.max_points);
+  ALLOC(c, nt.first_free, c->cfg.max_points);
+  ALLOC(c, nt.counters, 1);
+  if (launch_table_build(tg, K, nt.rot, counts, nt.begin, err, nt.entries, 1, s) != 0)
+    return hip_check(c, "table fill");
+  HIP_TRY(c, hipMemsetAsync(nt.label, 0, c->cfg.max_points, s));
+  HIP_TRY(c, hipMemsetAsync(nt.counters, 0, sizeof(ScoreCounters), s));
+  HIP_TRY(c, hipMemcpyAsync(&herr, err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  dev_free(c, counts, sizeof(uint32_t) * 2 * K);
+  dev_free(c, err, sizeof(int32_t));
+  if (herr) return fail(c, AF_EINVAL, "tool table build failed (%d)", herr);
+  nt.K = K;
+  nt.mask = c->mask;
+  t = nt;
+  c->tool_bytes[tool_id] = sizeof(uint32_t) * (int64_t)total;
+  c->last_stream = s;
+  return AF_OK;
+}
+
+int af_integrate_frame(af_ctx *c, const float *xyz, int64_t n, const float origin[3],
+                       int64_t frame_id, void *stream) {
+  if (!c) return AF_EINVAL;
+  if (n < 0 || (n > 0 && !xyz) || !origin)
+    return fail(c, AF_EINVAL, "bad frame arguments");
+  if (frame_id <= c->last_frame || frame_id > 0x7ffffffe)
+    return fail(c, AF_EINVAL, "frame id %lld does not increase", (long long)frame_id);
+  int3 Q;
+  int *qq[3] = {&Q.x, &Q.y, &Q.z};
+  for (int a = 0; a < 3; ++a) {
+    double t = (double)origin[a] * c->p.scale;
+    if (!(fabs(t) <= (double)kCoordLim)) return fail(c, AF_EINVAL, "sensor origin out of range");
+    *qq[a] = (int)llrint(t);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  int rc;
+  if (n > c->fs.cap) {
+    HIP_TRY(c, hipStreamSynchronize(s));
+    if ((rc = alloc_scratch(c, std::max<int64_t>(n, 2 * c->fs.cap))) != AF_OK) return rc;
+  }
+  const int32_t frame = (int32_t)frame_id;
+  launch_frame_prep(xyz, n, Q, c->p, c->map, c->pts, c->fs, c->counters, s);
+  launch_assign_blocks(c->map, c->fs, c->counters, frame, s);
+  launch_commit_blocks(c->map, c->counters, s);
+  HIP_TRY(c, hipMemcpyAsync(c->counters_host, c->counters, sizeof(FrameCounters),
+                            hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  if ((rc = hip_check(c, "frame prep")) != AF_OK) return rc;
+  FrameCounters h = *c->counters_host;
+  if (h.n_new_blocks > 0) {
+    for (int a = 0; a < 3; ++a) {
+      if (!c->have_bbox || h.bmin[a] < c->bbox_lo[a]) c->bbox_lo[a] = h.bmin[a];
+      if (!c->have_bbox || h.bmax[a] > c->bbox_hi[a]) c->bbox_hi[a] = h.bmax[a];
+    }
+    c->have_bbox = true;
+  }
+  bool rebuilt = false;
+  if ((rc = ensure_grid(c, s, rebuilt)) != AF_OK) return rc;
+  launch_integrate(n, Q, c->p, c->map, c->fs, c->counters, s);
+  launch_touch_band(n, c->p, c->map, c->fs, c->counters, frame, s);
+  launch_points_append(h.n_new_points, c->map, c->pts, c->fs, c->counters, frame, s);
+  launch_commit_points(c->pts, c->counters, s);
+  launch_points_view(n, Q, c->p, c->pts, c->fs, frame, s);
+  int64_t nb_after = std::min<int64_t>((int64_t)h.blocks_before + h.n_new_blocks, c->cfg.max_blocks);
+  launch_fold(c->p, c->map, c->fs, c->counters, c->grid, std::max<int64_t>(1, std::min<int64_t>(nb_after, n * (kMaxSpan + kMaxBand))), s);
+  if (rebuilt) launch_grid_rebuild(c->p, c->map, c->grid, nb_after, s);
+  if ((rc = hip_check(c, "integrate")) != AF_OK) return rc;
+  c->last_frame = frame_id;
+  c->last_stream = s;
+  c->n_blocks = nb_after;
+  c->n_points = std::min<int64_t>((int64_t)h.points_before + h.n_new_points, c->cfg.max_points);
+  c->status = h.status;
+  if (h.status & kStatusHashFull) return fail(c, AF_EOVERFLOW, "hash table full");
+  if (h.status & kStatusBlockOverflow)
+    return fail(c, AF_EOVERFLOW, "block capacity %lld exceeded", (long long)c->cfg.max_blocks);
+  if (h.n_new_points + (int64_t)h.points_before > c->cfg.max_points)
+    return fail(c, AF_EOVERFLOW, "point capacity %lld exceeded", (long long)c->cfg.max_points);
+  return AF_OK;
+}
+
+int af_score_points(af_ctx *c, int32_t tool_id, void *stream) {
+  if (!c) return AF_EINVAL;
+  if (tool_id < 0 || tool_id >= c->cfg.max_tools) return fail(c, AF_EINVAL, "bad tool id");
+  ToolDev &t = c->tools[tool_id];
+  if (!t.entries) return fail(c, AF_ENOTOOL, "tool %d has no kernels", tool_id);
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(c, hipMemsetAsync(t.counters, 0, sizeof(ScoreCounters), s));
+  launch_normals(c->p, c->map, c->pts, c->grid, c->n_points, s);
+  launch_mask(c->p, c->pts, t, c->n_points, s);
+  launch_score(c->p, c->map, c->pts, t, c->grid, c->n_points, s);
+  c->last_stream = s;
+  return hip_check(c, "score");
+}
+
+static int sync_last(af_ctx *c) {
+  HIP_TRY(c, hipStreamSynchronize(c->last_stream));
+  return AF_OK;
+}
+
+int64_t af_num_points(af_ctx *c) {
+  if (!c || sync_last(c) != AF_OK) return -1;
+  return c->n_points;
+}
+
+int64_t af_num_blocks(af_ctx *c) {
+  if (!c || sync_last(c) != AF_OK) return -1;
+  return c->n_blocks;
+}
+
+int af_read_labels(af_ctx *c, int32_t tool_id, int64_t first, int64_t count, int64_t *key,
+                   uint8_t *label, int16_t *first_free, uint16_t *w, int64_t *n_written) {
+  if (!c) return AF_EINVAL;
+  if (tool_id < 0 || tool_id >= c->cfg.max_tools) return fail(c, AF_EINVAL, "bad tool id");
+  ToolDev &t = c->tools[tool_id];
+  if (!t.entries) return fail(c, AF_ENOTOOL, "tool %d has no kernels", tool_id);
+  int rc = sync_last(c);
+  if (rc != AF_OK) return rc;
+  if (first < 0 || count < 0) return fail(c, AF_EINVAL, "bad range");
+  int64_t m = std::max<int64_t>(0, std::min<int64_t>(count, c->n_points - first));
+  if (n_written) *n_written = m;
+  if (m == 0) return AF_OK;
+  if (key) HIP_TRY(c, hipMemcpy(key, c->pts.key + first, sizeof(int64_t) * m, hipMemcpyDeviceToHost));
+  if (label) HIP_TRY(c, hipMemcpy(label, t.label + first, m, hipMemcpyDeviceToHost));
+  if (first_free)
+    HIP_TRY(c, hipMemcpy(first_free, t.first_free + first, sizeof(int16_t) * m, hipMemcpyDeviceToHost));
+  if (w) {
+    std::vector<int32_t> addr(m);
+    HIP_TRY(c, hipMemcpy(addr.data(), c->pts.addr + first, sizeof(int32_t) * m, hipMemcpyDeviceToHost));
+    std::vector<uint16_t> Wall((size_t)c->n_blocks * kBlockVox);
+    if (!Wall.empty())
+      HIP_TRY(c, hipMemcpy(Wall.data(), c->map.W, sizeof(uint16_t) * Wall.size(), hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < m; ++i) w[i] = addr[i] >= 0 ? Wall[addr[i]] : 0;
+  }
+  return AF_OK;
+}
+
+int af_read_tsdf(af_ctx *c, int64_t *key, int64_t *S, int32_t *W, uint8_t *cleared, int64_t cap,
+                 int64_t *n) {
+  if (!c) return AF_EINVAL;
+  int rc = sync_last(c);
+  if (rc != AF_OK) return rc;
+  const int64_t nb = c->n_blocks;
+  std::vector<int64_t> bkey(nb);
+  std::vector<int32_t> hS(nb * kBlockVox);
+  std::vector<uint16_t> hW(nb * kBlockVox);
+  std::vector<uint32_t> hc(nb * 16);
+  if (nb > 0) {
+    HIP_TRY(c, hipMemcpy(bkey.data(), c->map.bkey, sizeof(int64_t) * nb, hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(hS.data(), c->map.S, sizeof(int32_t) * hS.size(), hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(hW.data(), c->map.W, sizeof(uint16_t) * hW.size(), hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(hc.data(), c->map.clr, sizeof(uint32_t) * hc.size(), hipMemcpyDeviceToHost));
+  }
+  int64_t cnt = 0;
+  for (int64_t b = 0; b < nb; ++b) {
+    int32_t bx, by, bz;
+    unpack_key(bkey[b], bx, by, bz);
+    for (int vi = 0; vi < kBlockVox; ++vi) {
+      int64_t v = b * kBlockVox + vi;
+      bool cl = (hc[b * 16 + (vi >> 5)] >> (vi & 31)) & 1u;
+      if (hW[v] == 0 && !cl) continue;
+      if (cnt < cap) {
+        if (key) key[cnt] = pack_key(8 * bx + (vi & 7), 8 * by + ((vi >> 3) & 7), 8 * bz + (vi >> 6));
+        if (S) S[cnt] = hS[v];
+        if (W) W[cnt] = hW[v];
+        if (cleared) cleared[cnt] = cl ? 1 : 0;
+      }
+      ++cnt;
+    }
+  }
+  if (n) *n = cnt;
+  return AF_OK;
+}
+
+int af_read_points(af_ctx *c, int64_t first, int64_t count, int64_t *key, int32_t *first_frame,
+                   int32_t *n_vp, int32_t *vp, int64_t *sumq, int32_t *nq, int64_t *n_written) {
+  if (!c) return AF_EINVAL;
+  int rc = sync_last(c);
+  if (rc != AF_OK) return rc;
+  if (first < 0 || count < 0) return fail(c, AF_EINVAL, "bad range");
+  int64_t m = std::max<int64_t>(0, std::min<int64_t>(count, c->n_points - first));
+  if (n_written) *n_written = m;
+  if (m == 0) return AF_OK;
+  const PointsDev &q = c->pts;
+  if (key) HIP_TRY(c, hipMemcpy(key, q.key + first, sizeof(int64_t) * m, hipMemcpyDeviceToHost));
+  if (first_frame)
+    HIP_TRY(c, hipMemcpy(first_frame, q.first + first, sizeof(int32_t) * m, hipMemcpyDeviceToHost));
+  if (nq) HIP_TRY(c, hipMemcpy(nq, q.nq + first, sizeof(int32_t) * m, hipMemcpyDeviceToHost));
+  if (sumq) HIP_TRY(c, hipMemcpy(sumq, q.sumq + 3 * first, sizeof(int64_t) * 3 * m, hipMemcpyDeviceToHost));
+  if (n_vp || vp) {
+    std::vector<int32_t> cnt(m), head(m), ring(m * kMaxVp * 3);
+    HIP_TRY(c, hipMemcpy(cnt.data(), q.nvp + first, sizeof(int32_t) * m, hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(head.data(), q.head + first, sizeof(int32_t) * m, hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(ring.data(), q.vp + first * kMaxVp * 3, sizeof(int32_t) * ring.size(),
+                         hipMemcpyDeviceToHost));
+    const int nv = c->cfg.n_vp;
+    for (int64_t i = 0; i < m; ++i) {
+      if (n_vp) n_vp[i] = cnt[i];
+      if (!vp) continue;
+      int start = (head[i] - cnt[i] + nv) % nv;  // oldest first
+      for (int j = 0; j < kMaxVp; ++j)
+        for (int a = 0; a < 3; ++a)
+          vp[(i * kMaxVp + j) * 3 + a] =
+              j < cnt[i] ? ring[(i * kMaxVp + (start + j) % nv) * 3 + a] : 0;
+    }
+  }
+  return AF_OK;
+}
+
+int af_read_tool_table(af_ctx *c, int32_t tool_id, int32_t k, int32_t *off, uint8_t *cls,
+                       int64_t cap, int64_t *m) {
+  if (!c) return AF_EINVAL;
+  if (tool_id < 0 || tool_id >= c->cfg.max_tools) return fail(c, AF_EINVAL, "bad tool id");
+  ToolDev &t = c->tools[tool_id];
+  if (!t.entries) return fail(c, AF_ENOTOOL, "tool %d has no kernels", tool_id);
+  if (k < 0 || k >= t.K) return fail(c, AF_EINVAL, "orientation %d outside [0, %d)", k, t.K);
+  int rc = sync_last(c);
+  if (rc != AF_OK) return rc;
+  uint32_t be[2];
+  HIP_TRY(c, hipMemcpy(be, t.begin + k, sizeof(be), hipMemcpyDeviceToHost));
+  int64_t cnt = be[1] - be[0];
+  if (m) *m = cnt;
+  std::vector<uint32_t> e(cnt);
+  if (cnt > 0) HIP_TRY(c, hipMemcpy(e.data(), t.entries + be[0], sizeof(uint32_t) * cnt, hipMemcpyDeviceToHost));
+  for (int64_t i = 0; i < cnt && i < cap; ++i) {
+    if (off) {
+      off[3 * i] = entry_x(e[i]);
+      off[3 * i + 1] = entry_y(e[i]);
+      off[3 * i + 2] = entry_z(e[i]);
+    }
+    if (cls) cls[i] = (uint8_t)entry_cls(e[i]);
+  }
+  return AF_OK;
+}
+
+int af_read_point_debug(af_ctx *c, int32_t tool_id, int64_t first, int64_t count, int32_t *normal,
+                        int32_t *has_normal, uint64_t *mask, int64_t *n_written) {
+  if (!c) return AF_EINVAL;
+  if (tool_id < 0 || tool_id >= c->cfg.max_tools) return fail(c, AF_EINVAL, "bad tool id");
+  ToolDev &t = c->tools[tool_id];
+  if (!t.entries) return fail(c, AF_ENOTOOL, "tool %d has no kernels", tool_id);
+  int rc = sync_last(c);
+  if (rc != AF_OK) return rc;
+  int64_t m = std::max<int64_t>(0, std::min<int64_t>(count, c->n_points - first));
+  if (n_written) *n_written = m;
+  if (m == 0) return AF_OK;
+  int32_t mw = (t.K + 63) / 64;
+  if (normal)
+    HIP_TRY(c, hipMemcpy(normal, c->pts.normal + 3 * first, sizeof(int32_t) * 3 * m, hipMemcpyDeviceToHost));
+  if (has_normal)
+    HIP_TRY(c, hipMemcpy(has_normal, c->pts.has_normal + first, sizeof(int32_t) * m, hipMemcpyDeviceToHost));
+  if (mask)
+    HIP_TRY(c, hipMemcpy(mask, t.mask + first * mw, sizeof(uint64_t) * mw * m, hipMemcpyDeviceToHost));
+  return AF_OK;
+}
+
+int af_frame_stats_get(af_ctx *c, af_frame_stats *st) {
+  if (!c || !st) return AF_EINVAL;
+  int rc = sync_last(c);
+  if (rc != AF_OK) return rc;
+  FrameCounters h;
+  HIP_TRY(c, hipMemcpy(&h, c->counters, sizeof(h), hipMemcpyDeviceToHost));
+  st->n_valid = (int64_t)h.n_valid;
+  st->n_dropped = (int64_t)h.n_dropped;
+  st->n_in = st->n_valid + st->n_dropped;
+  st->pairs_applied = (int64_t)h.pairs_applied;
+  st->pairs_excluded = (int64_t)h.pairs_excluded;
+  st->band_marks = (int64_t)h.band_marks;
+  st->new_points = h.n_new_points;
+  st->n_points = c->n_points;
+  st->voxels_folded = (int64_t)h.voxels_folded;
+  st->n_blocks = c->n_blocks;
+  st->new_blocks = h.n_new_blocks;
+  return AF_OK;
+}
+
+int af_score_stats_get(af_ctx *c, int32_t tool_id, af_score_stats *st) {
+  if (!c || !st) return AF_EINVAL;
+  if (tool_id < 0 || tool_id >= c->cfg.max_tools) return fail(c, AF_EINVAL, "bad tool id");
+  ToolDev &t = c->tools[tool_id];
+  if (!t.entries) return fail(c, AF_ENOTOOL, "tool %d has no kernels", tool_id);
+  int rc = sync_last(c);
+  if (rc != AF_OK) return rc;
+  ScoreCounters h;
+  HIP_TRY(c, hipMemcpy(&h, t.counters, sizeof(h), hipMemcpyDeviceToHost));
+  st->n_points = c->n_points;
+  st->n_confident = (int64_t)h.n_confident;
+  st->n_accessible = (int64_t)h.n_accessible;
+  st->n_blocked = (int64_t)h.n_blocked;
+  st->n_no_candidate = (int64_t)h.n_no_candidate;
+  st->candidate_tests = (int64_t)h.candidate_tests;
+  st->canonical_tests = (int64_t)h.canonical_tests;
+  st->canonical_lookups = (int64_t)h.canonical_lookups;
+  return AF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,561 @@
+// Per-frame integration kernels: quantisation, block allocation in the hash
+// map, scan-centric cube accumulation (Section 3.2), ray-cleared band
+// (Section 3.4, "Arm path checking"), surface points (Section 3.1), the fold
+// with the weight cap (Section 3.6) and the brick grid used by scoring.
+#include "af_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace af {
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ inline int lane_id() { return (int)(threadIdx.x & 63u); }
+
+__device__ inline uint32_t slot_of(int64_t key, uint32_t mask) {
+  uint64_t h = (uint64_t)key * 0x9E3779B97F4A7C15ull;
+  return (uint32_t)(h >> 29) & mask;
+}
+
+// Insert `key`; returns its slot (fresh = newly inserted) or -1 if full.
+__device__ int32_t hash_insert(HashTable t, int64_t key, bool &fresh) {
+  uint32_t s = slot_of(key, t.mask);
+  for (uint32_t i = 0; i <= t.mask; ++i) {
+    int64_t cur = __hip_atomic_load(&t.keys[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (cur == key) {
+      fresh = false;
+      return (int32_t)s;
+    }
+    if (cur == kEmpty) {
+      unsigned long long prev = atomicCAS((unsigned long long *)&t.keys[s],
+                                          (unsigned long long)kEmpty,
+                                          (unsigned long long)key);
+      if ((int64_t)prev == kEmpty) {
+        fresh = true;
+        return (int32_t)s;
+      }
+      if ((int64_t)prev == key) {
+        fresh = false;
+        return (int32_t)s;
+      }
+    }
+    s = (s + 1) & t.mask;
+  }
+  fresh = false;
+  return -1;
+}
+
+__device__ int32_t hash_find(HashTable t, int64_t key) {
+  uint32_t s = slot_of(key, t.mask);
+  for (uint32_t i = 0; i <= t.mask; ++i) {
+    int64_t cur = t.keys[s];
+    if (cur == key) return (int32_t)s;
+    if (cur == kEmpty) return -1;
+    s = (s + 1) & t.mask;
+  }
+  return -1;
+}
+
+// Exact floor(sqrt(n)) for 0 <= n < 2^62.
+__device__ inline int64_t isqrt64(int64_t n) {
+  if (n <= 0) return 0;
+  uint64_t u = (uint64_t)n;
+  uint64_t r = (uint64_t)__builtin_sqrt((double)n);
+  while (r * r > u) --r;
+  while ((r + 1) * (r + 1) <= u) ++r;
+  return (int64_t)r;
+}
+
+// a / b to nearest, halves away from zero (b > 0).
+__device__ inline int64_t div_round(int64_t a, int64_t b) {
+  int64_t m = a < 0 ? -a : a;
+  int64_t q = (2 * m + b) / (2 * b);
+  return a < 0 ? -q : q;
+}
+
+__device__ inline int64_t div_floor(int64_t a, int64_t b) {
+  int64_t q = a / b;
+  if ((a % b != 0) && ((a < 0) != (b < 0))) --q;
+  return q;
+}
+
+__device__ inline void wave_count(unsigned long long *ctr, bool flag) {
+  unsigned long long b = __ballot(flag);
+  if (lane_id() == 0 && b) atomicAdd(ctr, (unsigned long long)__popcll(b));
+}
+
+struct Span {
+  int lo[3], n[3];
+};
+
+__device__ inline Span cube_span(int4 P, int R) {
+  Span s;
+  int v[3] = {P.x >> 8, P.y >> 8, P.z >> 8};
+  for (int i = 0; i < 3; ++i) {
+    s.lo[i] = (v[i] - R) >> 3;
+    s.n[i] = ((v[i] + R) >> 3) - s.lo[i] + 1;
+  }
+  return s;
+}
+
+// --------------------------------------------------------------- prep
+// Quantise each return, insert the blocks of its cube and of its band
+// samples, and insert its voxel into the point set.
+__global__ void __launch_bounds__(kThreads)
+k_frame_prep(const float *__restrict__ xyz, int64_t n, int3 Q, Params p, MapDev m,
+             PointsDev pts, FrameScratch fs, FrameCounters *c) {
+  int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  bool in = r < n;
+  bool ok = in;
+  int P[3] = {0, 0, 0};
+  if (in) {
+    for (int i = 0; i < 3; ++i) {
+      double t = (double)xyz[3 * r + i] * p.scale;
+      if (!(fabs(t) <= (double)kCoordLim))
+        ok = false;
+      else
+        P[i] = (int)__builtin_rint(t);
+    }
+    if (ok && P[0] == Q.x && P[1] == Q.y && P[2] == Q.z) ok = false;
+  }
+  wave_count(&c->n_valid, ok);
+  wave_count(&c->n_dropped, in && !ok);
+  if (!in) return;
+  if (!ok) {
+    fs.P[r] = make_int4(0, 0, 0, 0);
+    return;
+  }
+  int64_t g[3] = {(int64_t)Q.x - P[0], (int64_t)Q.y - P[1], (int64_t)Q.z - P[2]};
+  int64_t L = isqrt64(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+  int4 P4 = make_int4(P[0], P[1], P[2], (int)L);
+  fs.P[r] = P4;
+
+  bool full = false;
+  // blocks of the cube
+  Span sp = cube_span(P4, p.R);
+  int idx = 0;
+  for (int bz = 0; bz < sp.n[2]; ++bz)
+    for (int by = 0; by < sp.n[1]; ++by)
+      for (int bx = 0; bx < sp.n[0]; ++bx) {
+        bool fresh;
+        int32_t s = hash_insert(m.h, pack_key(sp.lo[0] + bx, sp.lo[1] + by, sp.lo[2] + bz), fresh);
+        if (s < 0) full = true;
+        if (fresh) fs.new_blocks[atomicAdd(&c->n_new_blocks, 1)] = s;
+        fs.span[r * kMaxSpan + idx++] = s;
+      }
+  // band samples: (tau, 2.25 tau] back towards the sensor, every v/2
+  int j = 0;
+  for (; j < kMaxBand; ++j) {
+    int64_t lam = (int64_t)p.tau_u + 128 * (j + 1);
+    if (4 * lam > 9 * (int64_t)p.tau_u || lam >= L) break;
+    int64_t vx = (P[0] + div_round(lam * g[0], L)) >> 8;
+    int64_t vy = (P[1] + div_round(lam * g[1], L)) >> 8;
+    int64_t vz = (P[2] + div_round(lam * g[2], L)) >> 8;
+    bool fresh;
+    int32_t s = hash_insert(m.h, pack_key(vx >> 3, vy >> 3, vz >> 3), fresh);
+    if (s < 0) full = true;
+    if (fresh) fs.new_blocks[atomicAdd(&c->n_new_blocks, 1)] = s;
+    fs.band[2 * (r * kMaxBand + j)] = s;
+    fs.band[2 * (r * kMaxBand + j) + 1] = (int)((vx & 7) | ((vy & 7) << 3) | ((vz & 7) << 6));
+  }
+  if (j < kMaxBand) fs.band[2 * (r * kMaxBand + j)] = -2;  // end marker
+  // the return's voxel is a surface point
+  bool fresh;
+  int32_t ps = hash_insert(pts.h, pack_key(P[0] >> 8, P[1] >> 8, P[2] >> 8), fresh);
+  if (ps < 0) full = true;
+  if (fresh) {
+    int at = atomicAdd(&c->n_new_points, 1);
+    fs.new_keys[at] = pack_key(P[0] >> 8, P[1] >> 8, P[2] >> 8);
+    fs.new_kslot[at] = ps;
+  }
+  fs.pslot[r] = ps;
+  if (full) atomicOr(&c->status, kStatusHashFull);
+}
+
+__global__ void k_reset_counters(FrameCounters *c, MapDev m, PointsDev pts) {
+  c->n_valid = c->n_dropped = c->pairs_applied = c->pairs_excluded = 0;
+  c->band_marks = c->voxels_folded = 0;
+  c->n_new_blocks = c->n_touched = c->n_new_points = c->status = 0;
+  for (int i = 0; i < 3; ++i) {
+    c->bmin[i] = 0x7fffffff;
+    c->bmax[i] = -0x7fffffff - 1;
+  }
+  c->blocks_before = *m.n_blocks;
+  c->points_before = *pts.n_points;
+}
+
+// One workgroup per new block: assign its id and clear its voxels.
+__global__ void __launch_bounds__(kThreads)
+k_assign_blocks(MapDev m, FrameScratch fs, FrameCounters *c, int32_t frame) {
+  int n_new = c->n_new_blocks;
+  int64_t base = *m.n_blocks;
+  for (int i = blockIdx.x; i < n_new; i += gridDim.x) {
+    int32_t slot = fs.new_blocks[i];
+    int64_t id = base + i;
+    if (id >= m.max_blocks) {
+      if (threadIdx.x == 0) {
+        m.h.vals[slot] = -1;
+        atomicOr(&c->status, kStatusBlockOverflow);
+      }
+      continue;
+    }
+    if (threadIdx.x == 0) {
+      m.h.vals[slot] = (int32_t)id;
+      int64_t k = m.h.keys[slot];
+      m.bkey[id] = k;
+      m.touched[id] = -1;
+      int32_t b[3];
+      unpack_key(k, b[0], b[1], b[2]);
+      for (int a = 0; a < 3; ++a) {
+        atomicMin(&c->bmin[a], b[a]);
+        atomicMax(&c->bmax[a], b[a]);
+      }
+    }
+    for (int t = threadIdx.x; t < kBlockVox; t += kThreads) {
+      m.S[id * kBlockVox + t] = 0;
+      m.W[id * kBlockVox + t] = 0;
+      m.delta[id * kBlockVox + t] = 0;
+    }
+    if (threadIdx.x < 16) {
+      m.clr[id * 16 + threadIdx.x] = 0;
+      m.surf[id * 16 + threadIdx.x] = 0;
+    }
+  }
+}
+
+__global__ void k_commit_blocks(MapDev m, FrameCounters *c) {
+  int64_t base = *m.n_blocks;
+  int64_t add = c->n_new_blocks;
+  if (base + add > m.max_blocks) add = m.max_blocks - base;
+  *m.n_blocks = (int32_t)(base + add);
+}
+
+// ------------------------------------------------------------ integrate
+// One thread per (return, cube offset): cone test, clamped signed distance,
+// one 64-bit atomic add of (1 << 32) + d into the voxel's frame accumulator.
+__global__ void __launch_bounds__(kThreads)
+k_integrate(int64_t n, int3 Q, Params p, MapDev m, FrameScratch fs, FrameCounters *c) {
+  const int D = 2 * p.R + 1;
+  const int C = D * D * D;
+  int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  bool applied = false, excluded = false;
+  if (t < n * C) {
+    int64_t r = t / C;
+    int o = (int)(t - r * C);
+    int4 P = fs.P[r];
+    if (P.w > 0) {
+      int v[3] = {(P.x >> 8) + o % D - p.R, (P.y >> 8) + (o / D) % D - p.R,
+                  (P.z >> 8) + o / (D * D) - p.R};
+      int64_t a0 = 256 * (int64_t)v[0] + 128 - P.x;
+      int64_t a1 = 256 * (int64_t)v[1] + 128 - P.y;
+      int64_t a2 = 256 * (int64_t)v[2] + 128 - P.z;
+      int64_t b0 = (int64_t)P.x - Q.x, b1 = (int64_t)P.y - Q.y, b2 = (int64_t)P.z - Q.z;
+      int64_t ab = a0 * b0 + a1 * b1 + a2 * b2;
+      int64_t aa = a0 * a0 + a1 * a1 + a2 * a2;
+      int64_t bb = b0 * b0 + b1 * b1 + b2 * b2;
+      // behind the return within the cos > 0.95 cone: 400 (a.b)^2 > 361 |a|^2 |b|^2
+      if (ab > 0 && (__int128)400 * ab * ab > (__int128)361 * aa * bb) {
+        excluded = true;
+      } else {
+        applied = true;
+        int64_t c0 = a0 + b0, c1 = a1 + b1, c2 = a2 + b2;  // centre - Q
+        int64_t d = (int64_t)P.w - isqrt64(c0 * c0 + c1 * c1 + c2 * c2);
+        int64_t lo = p.clamp_neg ? -(int64_t)p.tau_u : 0;
+        d = d < lo ? lo : (d > p.tau_u ? p.tau_u : d);
+        Span sp = cube_span(P, p.R);
+        int idx = (((v[2] >> 3) - sp.lo[2]) * sp.n[1] + ((v[1] >> 3) - sp.lo[1])) * sp.n[0] +
+                  ((v[0] >> 3) - sp.lo[0]);
+        int32_t slot = fs.span[r * kMaxSpan + idx];
+        int32_t id = slot >= 0 ? m.h.vals[slot] : -1;
+        if (id >= 0) {
+          int vi = (v[0] & 7) | ((v[1] & 7) << 3) | ((v[2] & 7) << 6);
+          atomicAdd(&m.delta[(int64_t)id * kBlockVox + vi],
+                    (unsigned long long)((1LL << 32) + d));
+        }
+      }
+    }
+  }
+  wave_count(&c->pairs_applied, applied);
+  wave_count(&c->pairs_excluded, excluded);
+}
+
+// Mark every block of the frame touched (once) and set the band's cleared bits.
+__global__ void __launch_bounds__(kThreads)
+k_touch_band(int64_t n, Params p, MapDev m, FrameScratch fs, FrameCounters *c, int32_t frame) {
+  int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  int marks = 0;
+  if (r < n) {
+    int4 P = fs.P[r];
+    if (P.w > 0) {
+      Span sp = cube_span(P, p.R);
+      int ns = sp.n[0] * sp.n[1] * sp.n[2];
+      for (int i = 0; i < ns; ++i) {
+        int32_t s = fs.span[r * kMaxSpan + i];
+        int32_t id = s >= 0 ? m.h.vals[s] : -1;
+        if (id >= 0 && atomicExch(&m.touched[id], frame) != frame)
+          fs.touched[atomicAdd(&c->n_touched, 1)] = id;
+      }
+      for (int j = 0; j < kMaxBand; ++j) {
+        int32_t s = fs.band[2 * (r * kMaxBand + j)];
+        if (s == -2) break;
+        ++marks;
+        int32_t id = s >= 0 ? m.h.vals[s] : -1;
+        if (id < 0) continue;
+        int vi = fs.band[2 * (r * kMaxBand + j) + 1];
+        atomicOr(&m.clr[(int64_t)id * 16 + (vi >> 5)], 1u << (vi & 31));
+        if (atomicExch(&m.touched[id], frame) != frame)
+          fs.touched[atomicAdd(&c->n_touched, 1)] = id;
+      }
+    }
+  }
+  unsigned long long s = marks;
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor((unsigned)s, off);
+  if (lane_id() == 0 && s) atomicAdd(&c->band_marks, s);
+}
+
+// ---------------------------------------------------------------- points
+// New point keys of the frame get ids in ascending key order (rank by
+// counting smaller keys), are initialised and flagged in their block.
+__global__ void __launch_bounds__(kThreads)
+k_points_append(MapDev m, PointsDev pts, FrameScratch fs, FrameCounters *c, int32_t frame) {
+  __shared__ int64_t tile[kThreads];
+  int mcount = c->n_new_points;
+  int i = blockIdx.x * kThreads + threadIdx.x;
+  if ((int)(blockIdx.x * kThreads) >= mcount) return;
+  int64_t key = i < mcount ? fs.new_keys[i] : 0;
+  int rank = 0;
+  for (int base = 0; base < mcount; base += kThreads) {
+    __syncthreads();
+    tile[threadIdx.x] = base + (int)threadIdx.x < mcount ? fs.new_keys[base + threadIdx.x]
+                                                         : (int64_t)0x7fffffffffffffffLL;
+    __syncthreads();
+    int lim = mcount - base < kThreads ? mcount - base : kThreads;
+    for (int j = 0; j < lim; ++j) rank += tile[j] < key;
+  }
+  if (i >= mcount) return;
+  int64_t id = (int64_t)*pts.n_points + rank;
+  int32_t slot = fs.new_kslot[i];
+  if (id >= pts.max_points) {
+    pts.h.vals[slot] = -1;
+    atomicOr(&c->status, kStatusPointOverflow);
+    return;
+  }
+  pts.h.vals[slot] = (int32_t)id;
+  pts.key[id] = key;
+  pts.first[id] = frame;
+  pts.last[id] = -1;
+  pts.nvp[id] = 0;
+  pts.head[id] = 0;
+  pts.nq[id] = 0;
+  pts.sumq[3 * id] = pts.sumq[3 * id + 1] = pts.sumq[3 * id + 2] = 0;
+  pts.has_normal[id] = -1;
+  int32_t x, y, z;
+  unpack_key(key, x, y, z);
+  int32_t bs = hash_find(m.h, pack_key(x >> 3, y >> 3, z >> 3));
+  int32_t bid = bs >= 0 ? m.h.vals[bs] : -1;
+  int vi = (x & 7) | ((y & 7) << 3) | ((z & 7) << 6);
+  pts.addr[id] = bid >= 0 ? bid * kBlockVox + vi : -1;
+  if (bid >= 0) atomicOr(&m.surf[(int64_t)bid * 16 + (vi >> 5)], 1u << (vi & 31));
+}
+
+__global__ void k_commit_points(PointsDev pts, FrameCounters *c) {
+  int64_t base = *pts.n_points;
+  int64_t add = c->n_new_points;
+  if (base + add > pts.max_points) add = pts.max_points - base;
+  *pts.n_points = (int32_t)(base + add);
+}
+
+// Once per (point, frame): running sensor sum and the viewpoint ring.
+__global__ void __launch_bounds__(kThreads)
+k_points_view(int64_t n, int3 Q, Params p, PointsDev pts, FrameScratch fs, int32_t frame) {
+  int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (r >= n || fs.P[r].w == 0) return;
+  int32_t s = fs.pslot[r];
+  int32_t id = s >= 0 ? pts.h.vals[s] : -1;
+  if (id < 0 || atomicExch(&pts.last[id], frame) == frame) return;
+  pts.sumq[3 * (int64_t)id] += Q.x;
+  pts.sumq[3 * (int64_t)id + 1] += Q.y;
+  pts.sumq[3 * (int64_t)id + 2] += Q.z;
+  pts.nq[id] += 1;
+  int cnt = pts.nvp[id], head = pts.head[id];
+  bool store = true;
+  if (cnt > 0) {
+    int last = (head + p.n_vp - 1) % p.n_vp;
+    const int32_t *v = pts.vp + ((int64_t)id * kMaxVp + last) * 3;
+    int64_t d0 = (int64_t)Q.x - v[0], d1 = (int64_t)Q.y - v[1], d2 = (int64_t)Q.z - v[2];
+    store = d0 * d0 + d1 * d1 + d2 * d2 > p.dmin2;
+  }
+  if (store) {
+    int32_t *v = pts.vp + ((int64_t)id * kMaxVp + head) * 3;
+    v[0] = Q.x;
+    v[1] = Q.y;
+    v[2] = Q.z;
+    pts.head[id] = (head + 1) % p.n_vp;
+    pts.nvp[id] = cnt < p.n_vp ? cnt + 1 : cnt;
+  }
+}
+
+// ------------------------------------------------------------ fold/bricks
+// Two-bit code of one voxel: bit 0 TSDF < r_c, bit 1 unknown and not cleared.
+__device__ inline uint32_t voxel_code(const Params &p, int32_t S, int32_t W, bool cleared) {
+  bool occ = W > 0 && (int64_t)S < (int64_t)p.rc_u * W;
+  bool unk = W == 0 && !cleared;
+  return (occ ? 1u : 0u) | (unk ? 2u : 0u);
+}
+
+// Block `id` (512 threads, one voxel each; `code` is workgroup scratch)
+// written to its brick of the grid.
+__device__ void write_brick(const Params &p, MapDev m, GridDev g, int64_t id, int32_t S,
+                            int32_t W, uint8_t *code) {
+  int t = threadIdx.x;
+  bool cl = (m.clr[id * 16 + (t >> 5)] >> (t & 31)) & 1u;
+  code[t] = (uint8_t)voxel_code(p, S, W, cl);
+  __syncthreads();
+  int32_t b[3];
+  unpack_key(m.bkey[id], b[0], b[1], b[2]);
+  int x = b[0] - g.g0[0], y = b[1] - g.g0[1], z = b[2] - g.g0[2];
+  bool inside = (unsigned)x < (unsigned)g.gd[0] && (unsigned)y < (unsigned)g.gd[1] &&
+                (unsigned)z < (unsigned)g.gd[2];
+  if (inside) {
+    int64_t brick = ((int64_t)z * g.gd[1] + y) * g.gd[0] + x;
+    if (t < 32) {
+      uint32_t w = 0;
+      for (int j = 0; j < 16; ++j) w |= (uint32_t)code[t * 16 + j] << (2 * j);
+      g.pred[brick * 32 + t] = w;
+    } else if (t < 48) {
+      g.surf[brick * 16 + (t - 32)] = m.surf[id * 16 + (t - 32)];
+    }
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(kBlockVox)
+k_fold(Params p, MapDev m, FrameScratch fs, FrameCounters *c, GridDev g) {
+  __shared__ uint8_t code[kBlockVox];
+  int nt = c->n_touched;
+  int folded = 0;
+  for (int i = blockIdx.x; i < nt; i += gridDim.x) {
+    int64_t id = fs.touched[i];
+    int64_t v = id * kBlockVox + threadIdx.x;
+    unsigned long long d = m.delta[v];
+    int32_t S = m.S[v];
+    int32_t W = m.W[v];
+    if (d != 0) {
+      int32_t dS = (int32_t)(uint32_t)d;
+      int64_t dW = ((int64_t)d - dS) >> 32;
+      int64_t S2 = (int64_t)S + dS, W2 = (int64_t)W + dW;
+      if (W2 > p.cap) {
+        S2 = div_floor(S2 * p.cap, W2);
+        W2 = p.cap;
+      }
+      S = (int32_t)S2;
+      W = (int32_t)W2;
+      m.S[v] = S;
+      m.W[v] = (uint16_t)W;
+      m.delta[v] = 0;
+      ++folded;
+    }
+    write_brick(p, m, g, id, S, W, code);
+  }
+  unsigned long long s = folded;
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor((unsigned)s, off);
+  if (lane_id() == 0 && s) atomicAdd(&c->voxels_folded, s);
+}
+
+__global__ void __launch_bounds__(kBlockVox)
+k_grid_rebuild(Params p, MapDev m, GridDev g, int64_t n_blocks) {
+  __shared__ uint8_t code[kBlockVox];
+  for (int64_t id = blockIdx.x; id < n_blocks; id += gridDim.x) {
+    int64_t v = id * kBlockVox + threadIdx.x;
+    write_brick(p, m, g, id, m.S[v], m.W[v], code);
+  }
+}
+
+__global__ void k_grid_fill(GridDev g, int64_t nbricks) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t j = i; j < nbricks * 32; j += stride) g.pred[j] = kUnknownWord;
+  for (int64_t j = i; j < nbricks * 16; j += stride) g.surf[j] = 0u;
+}
+
+inline unsigned grid_for(int64_t threads) {
+  int64_t b = (threads + kThreads - 1) / kThreads;
+  return (unsigned)(b > 0 ? b : 1);
+}
+
+}  // namespace
+
+void launch_frame_prep(const float *xyz, int64_t n, int3 Q, const Params &p, MapDev m,
+                       PointsDev pts, FrameScratch fs, FrameCounters *c, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(1), 0, s, c, m, pts);
+  if (n > 0)
+    hipLaunchKernelGGL(k_frame_prep, dim3(grid_for(n)), dim3(kThreads), 0, s, xyz, n, Q, p, m,
+                       pts, fs, c);
+}
+
+void launch_assign_blocks(MapDev m, FrameScratch fs, FrameCounters *c, int32_t frame,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_assign_blocks, dim3(4096), dim3(kThreads), 0, s, m, fs, c, frame);
+}
+
+void launch_commit_blocks(MapDev m, FrameCounters *c, hipStream_t s) {
+  hipLaunchKernelGGL(k_commit_blocks, dim3(1), dim3(1), 0, s, m, c);
+}
+
+void launch_integrate(int64_t n, int3 Q, const Params &p, MapDev m, FrameScratch fs,
+                      FrameCounters *c, hipStream_t s) {
+  int64_t D = 2 * p.R + 1;
+  if (n > 0)
+    hipLaunchKernelGGL(k_integrate, dim3(grid_for(n * D * D * D)), dim3(kThreads), 0, s, n, Q,
+                       p, m, fs, c);
+}
+
+void launch_touch_band(int64_t n, const Params &p, MapDev m, FrameScratch fs,
+                       FrameCounters *c, int32_t frame, hipStream_t s) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_touch_band, dim3(grid_for(n)), dim3(kThreads), 0, s, n, p, m, fs, c,
+                       frame);
+}
+
+void launch_points_append(int64_t n_new, MapDev m, PointsDev pts, FrameScratch fs,
+                          FrameCounters *c, int32_t frame, hipStream_t s) {
+  if (n_new > 0)
+    hipLaunchKernelGGL(k_points_append, dim3(grid_for(n_new)), dim3(kThreads), 0, s, m, pts,
+                       fs, c, frame);
+}
+
+void launch_commit_points(PointsDev pts, FrameCounters *c, hipStream_t s) {
+  hipLaunchKernelGGL(k_commit_points, dim3(1), dim3(1), 0, s, pts, c);
+}
+
+void launch_points_view(int64_t n, int3 Q, const Params &p, PointsDev pts, FrameScratch fs,
+                        int32_t frame, hipStream_t s) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_points_view, dim3(grid_for(n)), dim3(kThreads), 0, s, n, Q, p, pts,
+                       fs, frame);
+}
+
+void launch_fold(const Params &p, MapDev m, FrameScratch fs, FrameCounters *c, GridDev g,
+                 int64_t max_touched, hipStream_t s) {
+  int64_t wg = max_touched < 8192 ? max_touched : 8192;
+  if (wg > 0)
+    hipLaunchKernelGGL(k_fold, dim3((unsigned)wg), dim3(kBlockVox), 0, s, p, m, fs, c, g);
+}
+
+void launch_grid_fill(GridDev g, hipStream_t s) {
+  int64_t nb = (int64_t)g.gd[0] * g.gd[1] * g.gd[2];
+  int64_t blocks = (nb * 32 + kThreads - 1) / kThreads;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_grid_fill, dim3((unsigned)blocks), dim3(kThreads), 0, s, g, nb);
+}
+
+void launch_grid_rebuild(const Params &p, MapDev m, GridDev g, int64_t n_blocks,
+                         hipStream_t s) {
+  int64_t wg = n_blocks < 8192 ? n_blocks : 8192;
+  if (wg > 0)
+    hipLaunchKernelGGL(k_grid_rebuild, dim3((unsigned)wg), dim3(kBlockVox), 0, s, p, m, g,
+                       n_blocks);
+}
+
+}  // namespace af

@@ -1,0 +1,201 @@
+// Device-side data layout and kernel launchers of libaf (internal).
+//
+// Map: open-addressing hash of 8^3 voxel blocks (block key -> block id) over a
+// block pool stored structure-of-arrays: S (int32) and W (uint16) per voxel,
+// ray-cleared and surface bits (16 x uint32 per block), and a per-frame
+// accumulator of 64-bit packed (W << 32) + S sums.  Integer sums make the
+// result independent of the order in which returns are applied.
+//
+// Scoring reads a dense brick grid derived from the map after every fold: per
+// 8^3 block position inside the bounding box of all blocks, 512 two-bit codes
+// (bit 0: TSDF < r_c, bit 1: unknown and not ray-cleared) in 32 words, plus
+// the 512 surface bits in 16 words.  Positions outside the grid were never
+// touched and read as unknown, not cleared.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "af.h"
+
+namespace af {
+
+constexpr int kBlockEdge = 8;
+constexpr int kBlockVox = 512;
+constexpr int64_t kKeyBias = 1LL << 20;
+constexpr int64_t kKeyMask = (1LL << 21) - 1;
+constexpr int64_t kCoordLim = (1LL << 28) - 4096;  // |P| bound, fixed-point units
+constexpr int64_t kEmpty = -1;
+constexpr int kMaxSpan = 27;      // blocks touched by one return's cube (R <= 7)
+constexpr int kMaxBand = 18;      // band samples per return (1.25 tau / (v/2) for R <= 7)
+constexpr int kMaxVp = 8;
+constexpr int kTableMaxClass = 16384;
+constexpr uint32_t kUnknownWord = 0xAAAAAAAAu;  // 16 voxels coded "unknown, not cleared"
+
+// Status bits latched on the device.
+constexpr int kStatusBlockOverflow = 1;
+constexpr int kStatusPointOverflow = 2;
+constexpr int kStatusHashFull = 4;
+
+// Constants derived once from af_config (see af_context.hip).
+struct Params {
+  double scale;      // 256 / voxel: metres -> fixed-point units
+  int32_t tau_u;     // truncation, units
+  int32_t R;         // cube half-width, voxels
+  int32_t rc_u;      // collision threshold, units
+  int32_t n_c;
+  int32_t cap;       // weight cap
+  int32_t conf_min_w;
+  int32_t n_vp;
+  int32_t knn_k;
+  int32_t clamp_neg;
+  int32_t pad;
+  int64_t dmin2;     // squared viewpoint novelty distance, units^2
+  double cos2;       // cos_normal^2
+  double obs2;       // obs_dot^2
+};
+
+// Per-frame device counters (zeroed at the start of each frame).
+struct FrameCounters {
+  unsigned long long n_valid, n_dropped, pairs_applied, pairs_excluded;
+  unsigned long long band_marks, voxels_folded;
+  int32_t n_new_blocks, n_touched, n_new_points, status;
+  int32_t bmin[3], bmax[3];
+  int32_t blocks_before, points_before;
+};
+
+struct ScoreCounters {
+  unsigned long long n_confident, n_accessible, n_blocked, n_no_candidate;
+  unsigned long long candidate_tests, canonical_tests, canonical_lookups;
+};
+
+struct HashTable {
+  int64_t *keys;   // kEmpty when free
+  int32_t *vals;   // id, or -1 when the id could not be assigned
+  uint32_t mask;   // capacity - 1 (power of two)
+};
+
+struct MapDev {
+  HashTable h;
+  int64_t *bkey;                 // [max_blocks]
+  int32_t *S;                    // [max_blocks * 512]
+  uint16_t *W;                   // [max_blocks * 512]
+  uint32_t *clr;                 // [max_blocks * 16]
+  uint32_t *surf;                // [max_blocks * 16]
+  unsigned long long *delta;     // [max_blocks * 512]
+  int32_t *touched;              // [max_blocks] last frame that touched the block
+  int32_t *n_blocks;             // device counter
+  int64_t max_blocks;
+};
+
+struct PointsDev {
+  HashTable h;
+  int64_t *key;       // [max_points]
+  int32_t *first;     // first frame
+  int32_t *addr;      // block id * 512 + voxel index of the point's voxel
+  int32_t *last;      // last frame that updated the viewpoints
+  int32_t *nvp;       // stored viewpoints
+  int32_t *head;      // ring head
+  int32_t *vp;        // [max_points * 8 * 3]
+  int64_t *sumq;      // [max_points * 3]
+  int32_t *nq;
+  int32_t *normal;    // [max_points * 3]
+  int32_t *has_normal;// 1 normal, 0 none, -1 not confident
+  int32_t *n_points;  // device counter
+  int64_t max_points;
+};
+
+// Per-frame scratch, sized for `cap` returns.
+struct FrameScratch {
+  int4 *P;            // fixed-point return + isqrt |P-Q| (0 when dropped)
+  int32_t *span;      // [cap * kMaxSpan] block hash slots of the cube span
+  int32_t *band;      // [cap * kMaxBand * 2] (hash slot, voxel index) pairs
+  int32_t *pslot;     // [cap] point hash slot
+  int32_t *new_blocks;// [cap * (kMaxSpan + kMaxBand)] hash slots of new blocks
+  int64_t *new_keys;  // [cap] new point keys
+  int32_t *new_kslot; // [cap] their hash slots
+  int32_t *touched;   // [cap * (kMaxSpan + kMaxBand)] touched block ids
+  int64_t cap;
+};
+
+struct GridDev {
+  uint32_t *pred;     // [nbricks * 32]
+  uint32_t *surf;     // [nbricks * 16]
+  int32_t g0[3];      // block coordinate of brick (0,0,0)
+  int32_t gd[3];      // bricks per axis
+};
+
+struct ToolDev {
+  int32_t K;
+  uint32_t *entries;  // packed offsets + class
+  uint32_t *begin;    // [K + 1]
+  double *rot;        // [K * 9]
+  uint8_t *label;     // [max_points]
+  int16_t *first_free;// [max_points]
+  uint64_t *mask;     // [max_points * ceil(K/64)]
+  ScoreCounters *counters;
+};
+
+// Table entry packing: 10-bit two's complement offsets, class in bits 30-31.
+__host__ __device__ inline uint32_t pack_entry(int ox, int oy, int oz, int cls) {
+  return (uint32_t)(ox & 1023) | ((uint32_t)(oy & 1023) << 10) |
+         ((uint32_t)(oz & 1023) << 20) | ((uint32_t)cls << 30);
+}
+__host__ __device__ inline int entry_x(uint32_t e) { return (int)(e << 22) >> 22; }
+__host__ __device__ inline int entry_y(uint32_t e) { return (int)(e << 12) >> 22; }
+__host__ __device__ inline int entry_z(uint32_t e) { return (int)(e << 2) >> 22; }
+__host__ __device__ inline int entry_cls(uint32_t e) { return (int)(e >> 30); }
+
+__host__ __device__ inline int64_t pack_key(int64_t x, int64_t y, int64_t z) {
+  return ((x + kKeyBias) & kKeyMask) | (((y + kKeyBias) & kKeyMask) << 21) |
+         (((z + kKeyBias) & kKeyMask) << 42);
+}
+__host__ __device__ inline void unpack_key(int64_t k, int32_t &x, int32_t &y, int32_t &z) {
+  x = (int32_t)((k & kKeyMask) - kKeyBias);
+  y = (int32_t)(((k >> 21) & kKeyMask) - kKeyBias);
+  z = (int32_t)(((k >> 42) & kKeyMask) - kKeyBias);
+}
+
+struct ToolGeom {     // tool constants in voxel units (host-derived, fp64)
+  int32_t shape;
+  int32_t pad;
+  double Lv, Ev;      // body end, corridor end
+  double a, b;        // half cross-section (cylinder: a = b = radius)
+  double rv2;         // cylinder radius^2
+  double rsv2;        // self-exclusion radius^2
+  double lam[3];      // arm samples
+};
+
+// ---- launchers (stream-ordered) ----
+void launch_frame_prep(const float *xyz, int64_t n, int3 Q, const Params &p,
+                       MapDev m, PointsDev pts, FrameScratch fs,
+                       FrameCounters *c, hipStream_t s);
+void launch_assign_blocks(MapDev m, FrameScratch fs, FrameCounters *c, int32_t frame,
+                          hipStream_t s);
+void launch_commit_blocks(MapDev m, FrameCounters *c, hipStream_t s);
+void launch_integrate(int64_t n, int3 Q, const Params &p, MapDev m, FrameScratch fs,
+                      FrameCounters *c, hipStream_t s);
+void launch_touch_band(int64_t n, const Params &p, MapDev m, FrameScratch fs,
+                       FrameCounters *c, int32_t frame, hipStream_t s);
+void launch_points_append(int64_t n, MapDev m, PointsDev pts, FrameScratch fs,
+                          FrameCounters *c, int32_t frame, hipStream_t s);
+void launch_commit_points(PointsDev pts, FrameCounters *c, hipStream_t s);
+void launch_points_view(int64_t n, int3 Q, const Params &p, PointsDev pts,
+                        FrameScratch fs, int32_t frame, hipStream_t s);
+void launch_fold(const Params &p, MapDev m, FrameScratch fs, FrameCounters *c,
+                 GridDev g, int64_t max_touched, hipStream_t s);
+void launch_grid_fill(GridDev g, hipStream_t s);
+void launch_grid_rebuild(const Params &p, MapDev m, GridDev g, int64_t n_blocks,
+                         hipStream_t s);
+
+int launch_table_build(const ToolGeom &tg, int32_t K, const double *rot_dev,
+                       uint32_t *counts_dev, uint32_t *begin_dev, int32_t *err_dev,
+                       uint32_t *entries_dev, int pass, hipStream_t s);
+
+void launch_normals(const Params &p, MapDev m, PointsDev pts, GridDev g,
+                    int64_t n_points, hipStream_t s);
+void launch_mask(const Params &p, PointsDev pts, ToolDev t, int64_t n_points,
+                 hipStream_t s);
+void launch_score(const Params &p, MapDev m, PointsDev pts, ToolDev t, GridDev g,
+                  int64_t n_points, hipStream_t s);
+
+}  // namespace af

@@ -1,0 +1,156 @@
+// Rotated tool kernels (Section 3.4, "Tool kernel", "Self-exclusion", "Arm
+// path checking"; precomputed once, Section 3.6).  One workgroup per
+// orientation enumerates the voxel offsets of the rotated tool's bounding
+// box, keeps those whose centre lies in the body or in the corridor (minus the
+// self-exclusion ball), sorts each class by (|o|^2, z, y, x) in LDS and
+// writes packed entries: 3 arm samples, then body, then corridor.
+#include "af_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace af {
+namespace {
+
+constexpr int kTableThreads = 1024;
+
+// 0 body, 2 corridor, -1 outside.  fp64 in voxel units with a 1e-9 slack on
+// the inclusive bounds.
+__device__ inline int classify(const ToolGeom &tg, const double *R, int ox, int oy, int oz) {
+  const double eps = 1e-9;
+  double fx = (double)ox, fy = (double)oy, fz = (double)oz;
+  double x = (R[0] * fx + R[3] * fy) + R[6] * fz;
+  double y = (R[1] * fx + R[4] * fy) + R[7] * fz;
+  double z = (R[2] * fx + R[5] * fy) + R[8] * fz;
+  bool cross = tg.shape == AF_TOOL_CYLINDER ? (y * y + z * z) <= tg.rv2 + eps
+                                            : (fabs(y) <= tg.a + eps && fabs(z) <= tg.b + eps);
+  if (!cross) return -1;
+  int64_t n2 = (int64_t)ox * ox + (int64_t)oy * oy + (int64_t)oz * oz;
+  if ((double)n2 < tg.rsv2) return -1;
+  if (x < -eps || x > tg.Ev + eps) return -1;
+  return x <= tg.Lv + eps ? AF_CLS_BODY : AF_CLS_FAR;
+}
+
+__device__ inline void bounds(const ToolGeom &tg, const double *R, int lo[3], int hi[3]) {
+  for (int i = 0; i < 3; ++i) {
+    double mn = 1e300, mx = -1e300;
+    for (int c = 0; c < 8; ++c) {
+      double x = (c & 1) ? tg.Ev : 0.0;
+      double y = (c & 2) ? tg.a : -tg.a;
+      double z = (c & 4) ? tg.b : -tg.b;
+      double w = R[3 * i] * x + R[3 * i + 1] * y + R[3 * i + 2] * z;
+      mn = w < mn ? w : mn;
+      mx = w > mx ? w : mx;
+    }
+    lo[i] = (int)floor(mn) - 1;
+    hi[i] = (int)ceil(mx) + 1;
+  }
+}
+
+__global__ void __launch_bounds__(kTableThreads)
+k_table(ToolGeom tg, int32_t K, const double *__restrict__ rot, uint32_t *counts,
+        const uint32_t *begin, int32_t *err, uint32_t *entries, int pass) {
+  __shared__ unsigned long long keys[kTableMaxClass];
+  __shared__ int nkeys;
+  __shared__ int lo[3], hi[3];
+  const int k = blockIdx.x;
+  if (k >= K) return;
+  const double *R = rot + 9 * (int64_t)k;
+  if (threadIdx.x == 0) bounds(tg, R, lo, hi);
+  __syncthreads();
+  const int64_t e0 = hi[0] - lo[0] + 1, e1 = hi[1] - lo[1] + 1, e2 = hi[2] - lo[2] + 1;
+  const int64_t vol = e0 * e1 * e2;
+  uint32_t out = pass ? begin[k] + 3 : 0;
+  for (int cls = 0; cls <= 2; cls += 2) {
+    if (threadIdx.x == 0) nkeys = 0;
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < vol; i += kTableThreads) {
+      int ox = lo[0] + (int)(i % e0);
+      int oy = lo[1] + (int)((i / e0) % e1);
+      int oz = lo[2] + (int)(i / (e0 * e1));
+      if (classify(tg, R, ox, oy, oz) != cls) continue;
+      if (ox < -511 || ox > 511 || oy < -511 || oy > 511 || oz < -511 || oz > 511) {
+        atomicOr(err, 1);
+        continue;
+      }
+      int at = atomicAdd(&nkeys, 1);
+      if (at >= kTableMaxClass) {
+        atomicOr(err, 2);
+        continue;
+      }
+      uint64_t n2 = (uint64_t)((int64_t)ox * ox + (int64_t)oy * oy + (int64_t)oz * oz);
+      keys[at] = (n2 << 32) | ((uint64_t)(oz + 512) << 20) | ((uint64_t)(oy + 512) << 10) |
+                 (uint64_t)(ox + 512);
+    }
+    __syncthreads();
+    int n = nkeys < kTableMaxClass ? nkeys : kTableMaxClass;
+    if (pass == 0) {
+      if (threadIdx.x == 0) counts[2 * k + (cls == AF_CLS_FAR)] = (uint32_t)n;
+      __syncthreads();
+      continue;
+    }
+    // bitonic sort of keys[0, npow) with +inf padding
+    int npow = 1;
+    while (npow < n) npow <<= 1;
+    for (int i = n + (int)threadIdx.x; i < npow; i += kTableThreads) keys[i] = ~0ull;
+    __syncthreads();
+    for (int size = 2; size <= npow; size <<= 1) {
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        for (int i = threadIdx.x; i < npow; i += kTableThreads) {
+          int j = i ^ stride;
+          if (j > i) {
+            bool up = (i & size) == 0;
+            unsigned long long a = keys[i], b = keys[j];
+            if ((a > b) == up) {
+              keys[i] = b;
+              keys[j] = a;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    for (int i = threadIdx.x; i < n; i += kTableThreads) {
+      unsigned long long key = keys[i];
+      int ox = (int)(key & 1023) - 512;
+      int oy = (int)((key >> 10) & 1023) - 512;
+      int oz = (int)((key >> 20) & 1023) - 512;
+      entries[out + i] = pack_entry(ox, oy, oz, cls);
+    }
+    out += (uint32_t)n;
+    __syncthreads();
+  }
+  if (pass == 1 && threadIdx.x < 3) {
+    double lam = tg.lam[threadIdx.x];
+    int o[3];
+    for (int i = 0; i < 3; ++i) {
+      double t = round(lam * R[3 * i]);
+      o[i] = (int)t;
+    }
+    if (o[0] < -511 || o[0] > 511 || o[1] < -511 || o[1] > 511 || o[2] < -511 || o[2] > 511)
+      atomicOr(err, 1);
+    entries[begin[k] + threadIdx.x] = pack_entry(o[0], o[1], o[2], AF_CLS_NEAR);
+  }
+}
+
+// Prefix of 3 + body + corridor entries over orientations (one thread).
+__global__ void k_table_scan(int32_t K, const uint32_t *counts, uint32_t *begin) {
+  uint32_t acc = 0;
+  for (int k = 0; k < K; ++k) {
+    begin[k] = acc;
+    acc += 3 + counts[2 * k] + counts[2 * k + 1];
+  }
+  begin[K] = acc;
+}
+
+}  // namespace
+
+int launch_table_build(const ToolGeom &tg, int32_t K, const double *rot_dev,
+                       uint32_t *counts_dev, uint32_t *begin_dev, int32_t *err_dev,
+                       uint32_t *entries_dev, int pass, hipStream_t s) {
+  hipLaunchKernelGGL(k_table, dim3((unsigned)K), dim3(kTableThreads), 0, s, tg, K, rot_dev,
+                     counts_dev, begin_dev, err_dev, entries_dev, pass);
+  if (pass == 0) hipLaunchKernelGGL(k_table_scan, dim3(1), dim3(1), 0, s, K, counts_dev, begin_dev);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace af

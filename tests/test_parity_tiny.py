@@ -1,0 +1,205 @@
+"""GPU parity against the CPU oracle on the tiny workload (sphere + slotted
+box, 20 frames x 2,000 returns, v = 2 cm, tau = 6 cm, cylinder tool, 64
+Fibonacci directions) and on edge cases.  Integer work (TSDF sums, weights,
+cleared flags, points, viewpoints, tables, normals, masks, labels, counts)
+must match bit for bit."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU test on a machine without a GPU"
+    return torch
+
+
+def _ctx(w, **kw):
+    from paper_2608_06412_amd import Context, default_config
+    cfg = default_config(w.voxel, w.trunc, r_c=w.r_c, max_blocks=kw.pop("max_blocks", 1 << 15),
+                         max_points=kw.pop("max_points", 1 << 17),
+                         max_orientations=kw.pop("max_orientations", 256), max_tools=2, **kw)
+    return Context(cfg)
+
+
+def _oracle(w, **kw):
+    import oracle
+    return oracle.Oracle(voxel=w.voxel, trunc=w.trunc, r_c=w.r_c, **kw)
+
+
+def _cmp_tsdf(ctx, orc):
+    g = ctx.read_tsdf()
+    o = orc.read_tsdf()
+    assert len(g[0]) == len(o[0])
+    for a, b, name in zip(g, o, ("key", "S", "W", "cleared")):
+        assert np.array_equal(np.asarray(a, np.int64), np.asarray(b, np.int64)), name
+
+
+def _cmp_points(ctx, orc):
+    g = ctx.read_points()
+    o = orc.read_points()
+    for name in ("key", "first_frame", "n_vp", "vp", "sumq", "nq"):
+        assert np.array_equal(g[name], o[name]), name
+
+
+FRAME_KEYS = ("n_in", "n_valid", "n_dropped", "pairs_applied", "pairs_excluded",
+              "band_marks", "new_points", "n_points", "voxels_folded")
+SCORE_KEYS = ("n_points", "n_confident", "n_accessible", "n_blocked", "n_no_candidate",
+              "candidate_tests", "canonical_tests", "canonical_lookups")
+
+
+@pytest.fixture(scope="module")
+def tiny_run(synth_mod, oracle_mod):
+    torch = _torch()
+    w = synth_mod.tiny()
+    frames = w.frames()
+    ctx = _ctx(w)
+    orc = _oracle(w)
+    per_frame = []
+    for f in frames:
+        print("tiny frame", f.frame_id, flush=True)
+        ctx.integrate_frame(torch.from_numpy(f.xyz).cuda(), f.origin, f.frame_id)
+        orc.integrate_frame(f.xyz, f.origin, f.frame_id)
+        gs, os_ = ctx.frame_stats(), orc.frame_stats()
+        per_frame.append(({k: gs[k] for k in FRAME_KEYS}, {k: os_[k] for k in FRAME_KEYS}))
+        if f.frame_id in (0, 7):
+            _cmp_tsdf(ctx, orc)
+    ctx.set_tool_kernels(0, w.tool, w.rot)
+    orc.set_tool(0, w.tool, w.rot)
+    ctx.score_points(0)
+    orc.score(0)
+    return w, ctx, orc, per_frame
+
+
+def test_frame_stats(tiny_run):
+    _, _, _, per_frame = tiny_run
+    for g, o in per_frame:
+        assert g == o
+
+
+def test_tsdf_bit_exact(tiny_run):
+    _, ctx, orc, _ = tiny_run
+    _cmp_tsdf(ctx, orc)
+
+
+def test_points_and_viewpoints(tiny_run):
+    _, ctx, orc, _ = tiny_run
+    _cmp_points(ctx, orc)
+
+
+def test_tool_tables(tiny_run):
+    w, ctx, orc, _ = tiny_run
+    for k in range(len(w.rot)):
+        go, gc = ctx.read_tool_table(0, k)
+        oo, oc = orc.tool_table(0, k)
+        assert np.array_equal(go, oo) and np.array_equal(gc, oc), k
+
+
+def test_normals_and_masks(tiny_run):
+    w, ctx, orc, _ = tiny_run
+    K = len(w.rot)
+    dbg = ctx.read_point_debug(0)
+    keys = ctx.read_points()["key"]
+    for i, k in enumerate(keys):
+        r = orc.point_result(k, K)
+        if r["label"] == 0:
+            assert dbg["has_normal"][i] == -1
+            continue
+        assert dbg["has_normal"][i] == r["has_normal"], k
+        assert np.array_equal(dbg["normal"][i].astype(np.int64), r["normal"]), k
+        assert np.array_equal(dbg["mask"][i], r["mask"]), k
+
+
+def test_labels_bit_exact(tiny_run):
+    w, ctx, orc, _ = tiny_run
+    lab = ctx.read_labels(0)
+    keys, lbl, ff = orc.labels(len(w.rot), lab["key"])
+    assert np.array_equal(lab["label"], lbl)
+    assert np.array_equal(lab["first_free"].astype(np.int32), ff)
+    assert set(np.unique(lbl)) >= {1, 2}
+
+
+def test_score_stats(tiny_run):
+    _, ctx, orc, _ = tiny_run
+    g, o = ctx.score_stats(0), orc.score_stats()
+    assert {k: g[k] for k in SCORE_KEYS} == {k: o[k] for k in SCORE_KEYS}
+
+
+def test_rescore_is_stateless(tiny_run):
+    """Scoring twice gives the same labels (no state carried between calls)."""
+    w, ctx, orc, _ = tiny_run
+    a = ctx.read_labels(0)
+    ctx.score_points(0)
+    b = ctx.read_labels(0)
+    assert np.array_equal(a["label"], b["label"]) and np.array_equal(a["first_free"], b["first_free"])
+
+
+def test_edge_frames(synth_mod, oracle_mod):
+    """Empty frame, ragged frame sizes (1, 63, 257, 1000), dropped returns
+    (NaN, inf, at the sensor, out of range), and a frame id that does not
+    increase."""
+    torch = _torch()
+    from paper_2608_06412_amd import AFError
+    w = synth_mod.tiny(n_frames=6, n_hits=1000)
+    frames = w.frames()
+    ctx = _ctx(w)
+    orc = _oracle(w)
+    sizes = [0, 1, 63, 257, 1000, 1000]
+    for f, n in zip(frames, sizes):
+        xyz = f.xyz[:n].copy()
+        if n == 1000 and f.frame_id == 5:
+            xyz[3] = [np.nan, 0, 0]
+            xyz[10] = [np.inf, 1, 1]
+            xyz[20] = f.origin
+            xyz[30] = [1e7, 0, 0]
+        print("edge frame", f.frame_id, n, flush=True)
+        ctx.integrate_frame(torch.from_numpy(np.ascontiguousarray(xyz)).cuda(), f.origin,
+                            f.frame_id)
+        orc.integrate_frame(xyz, f.origin, f.frame_id)
+        gs, os_ = ctx.frame_stats(), orc.frame_stats()
+        assert {k: gs[k] for k in FRAME_KEYS} == {k: os_[k] for k in FRAME_KEYS}
+    _cmp_tsdf(ctx, orc)
+    _cmp_points(ctx, orc)
+    with pytest.raises(AFError):
+        ctx.integrate_frame(torch.from_numpy(frames[0].xyz).cuda(), frames[0].origin, 5)
+    # K = 70 (two mask words, ragged), yaw-only directions
+    rot = synth_mod.orientations(synth_mod.yaw_directions(70), 1)
+    ctx.set_tool_kernels(1, w.tool, rot)
+    orc.set_tool(1, w.tool, rot)
+    ctx.score_points(1)
+    orc.score(1)
+    lab = ctx.read_labels(1)
+    _, lbl, ff = orc.labels(70, lab["key"])
+    assert np.array_equal(lab["label"], lbl)
+    assert np.array_equal(lab["first_free"].astype(np.int32), ff)
+
+
+def test_clamp_ablation_and_cap(synth_mod, oracle_mod):
+    """[-tau, tau] clamp ablation, and a frame where thousands of returns hit
+    the same voxels so the weight cap rescales S."""
+    torch = _torch()
+    w = synth_mod.tiny(n_frames=3, n_hits=1500)
+    frames = w.frames()
+    ctx = _ctx(w, clamp_negative=1)
+    orc = _oracle(w, clamp_negative=1)
+    for f in frames:
+        xyz = np.concatenate([f.xyz, np.repeat(f.xyz[:1], 2100, axis=0)])
+        ctx.integrate_frame(torch.from_numpy(xyz).cuda(), f.origin, f.frame_id)
+        orc.integrate_frame(xyz, f.origin, f.frame_id)
+    _cmp_tsdf(ctx, orc)
+    W = ctx.read_tsdf()[2]
+    assert W.max() == 2000
+    assert (ctx.read_tsdf()[1] < 0).any()
+
+
+def test_capacity_overflow_reported(synth_mod):
+    """A block capacity far below the frame's needs is reported, not hidden."""
+    torch = _torch()
+    from paper_2608_06412_amd import AFError, af
+    w = synth_mod.tiny(n_frames=1, n_hits=500)
+    f = w.frames()[0]
+    ctx = _ctx(w, max_blocks=8)
+    with pytest.raises(AFError) as e:
+        ctx.integrate_frame(torch.from_numpy(f.xyz).cuda(), f.origin, 0)
+    assert e.value.code == af.AF_EOVERFLOW
