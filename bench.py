@@ -1,0 +1,242 @@
+#!/usr/bin/env python3
+"""Benchmark of the accessibility-field hot path on one MI355X.
+
+Workload (tree): a procedural 8 m tree (40 cm trunk, 5 branching levels,
+branch radii 1-15 cm) scanned by a Mid-360-shaped sensor on a seeded orbiting,
+climbing trajectory: 20,000 returns per frame at 10 Hz, range noise 2 cm;
+1 cm voxels, 4 cm truncation; a 30 x 5 x 2 cm saw-box tool with a 1 m
+corridor at 256 orientations (64 Fibonacci directions x 4 rolls).
+
+One step = one frame through the whole hot path: integrate_frame (scan-centric
+TSDF integration, ray-cleared band, surface points, fold) then score_points
+(normals, candidate masks, collision-count search for every confident point).
+Frames 0..W-1 are untimed warm-up, frames W..W+K-1 are timed back to back with
+their returns already in HBM, and the remaining frames (default 100) are
+replayed under 10 Hz pacing from pinned host memory to measure frame latency
+(release -> labels on the host).  The defaults cover the workload's 600 frames.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("point×orientation tests/s + returns integrated/s; p99 frame latency @10 Hz")
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_score_tree.json")
+SCORE_SRC = os.path.join(ROOT, "paper_2608_06412_amd", "csrc", "af_score.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def src_sha(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def score_bytes(lookups, confident, K):
+    """Algorithmic bytes of the scoring kernel: an 8-byte voxel record per
+    canonical lookup plus, per confident point, its key (8), candidate mask
+    (K/8), weight (4) and outputs (3)."""
+    return 8.0 * lookups + confident * (8 + K / 8 + 4 + 3)
+
+
+def cpu_baseline(w, frames, n_frames, n_points, seed=17):
+    import oracle
+    oracle.build(force=False)
+    orc = oracle.Oracle(voxel=w.voxel, trunc=w.trunc, r_c=w.r_c)
+    t = time.perf_counter()
+    nret = 0
+    for f in frames[:n_frames]:
+        orc.integrate_frame(f.xyz, f.origin, f.frame_id)
+        nret += len(f.xyz)
+    t_int = time.perf_counter() - t
+    orc.set_tool(0, w.tool, w.rot)
+    keys = orc.read_points()["key"]
+    rng = np.random.default_rng(seed)
+    sample = rng.choice(keys, size=min(n_points, len(keys)), replace=False)
+    t = time.perf_counter()
+    orc.score(0, keys=sample)
+    t_score = time.perf_counter() - t
+    st = orc.score_stats()
+    return {
+        "value": st["canonical_tests"] / t_score,
+        "unit": "point-orientation tests/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": ("single-threaded C oracle: frames 0-%d of the tree workload integrated "
+                   "(%d returns, %.1f s -> %.0f returns/s), then %d seeded-random points of "
+                   "that map scored against all %d orientations (%d canonical tests in %.1f s)"
+                   % (n_frames - 1, nret, t_int, nret / t_int, len(sample), len(w.rot),
+                      st["canonical_tests"], t_score)),
+        "returns_per_s": nret / t_int,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--latency-frames", type=int, default=100)
+    ap.add_argument("--cpu-frames", type=int, default=12)
+    ap.add_argument("--cpu-points", type=int, default=1500)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU; this build has no multi-GPU path "
+              "(see DESIGN.md for how the map would shard). Run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_2608_06412_amd import Context, default_config
+
+    synth.build(force=False)
+    W, K, L = args.warmup, args.steps, args.latency_frames
+    total = W + K + L
+    w = synth.tree(n_frames=total)
+    t = time.perf_counter()
+    frames = w.frames(total)
+    log("generated %d frames in %.1f s" % (total, time.perf_counter() - t))
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    resident = [torch.from_numpy(f.xyz).to(dev) for f in frames[:W + K]]
+    pinned = [torch.from_numpy(f.xyz).pin_memory() for f in frames[W + K:]]
+    nmax = max(len(f.xyz) for f in frames)
+    staging = torch.empty((nmax, 3), dtype=torch.float32, device=dev)
+
+    cfg = default_config(w.voxel, w.trunc, r_c=w.r_c, max_blocks=1 << 17,
+                         max_points=1 << 22, max_orientations=len(w.rot), max_tools=1)
+    ctx = Context(cfg)
+    ctx.set_tool_kernels(0, w.tool, w.rot)
+    Krot = len(w.rot)
+
+    t = time.perf_counter()
+    for i in range(W):
+        ctx.integrate_frame(resident[i], frames[i].origin, frames[i].frame_id)
+        ctx.score_points(0)
+        if i % 20 == 0:
+            log("warm-up frame %d, %d points" % (i, ctx.num_points()))
+    torch.cuda.synchronize()
+    log("warm-up %d frames in %.1f s" % (W, time.perf_counter() - t))
+
+    ctx.timing_enable(True)
+    ctx.timing_read(reset=True)
+    tests = lookups = conf = nominal = returns = 0
+    byts = 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(W, W + K):
+        ctx.integrate_frame(resident[i], frames[i].origin, frames[i].frame_id)
+        ctx.score_points(0)
+        st = ctx.score_stats(0)
+        tests += st["canonical_tests"]
+        lookups += st["canonical_lookups"]
+        conf += st["n_confident"]
+        nominal += st["n_confident"] * Krot
+        byts += score_bytes(st["canonical_lookups"], st["n_confident"], Krot)
+        returns += len(frames[i].xyz)
+        if (i - W) % 50 == 0:
+            log("timed frame %d: %d points, %d confident, %d canonical tests" %
+                (i, st["n_points"], st["n_confident"], st["canonical_tests"]))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tm = ctx.timing_read(reset=True)
+    wall = t1 - t0
+    log("timed %d frames in %.2f s" % (K, wall))
+    map_points = ctx.num_points()
+    map_blocks = ctx.num_blocks()
+
+    # 10 Hz paced latency: release -> labels on the host
+    lat = []
+    tstart = time.perf_counter() + 0.05
+    for j, f in enumerate(frames[W + K:]):
+        release = tstart + 0.1 * j
+        while time.perf_counter() < release:
+            time.sleep(0.0005)
+        n = len(f.xyz)
+        staging[:n].copy_(pinned[j], non_blocking=True)
+        ctx.integrate_frame(staging[:n], f.origin, f.frame_id)
+        ctx.score_points(0)
+        ctx.read_labels(0)
+        lat.append((time.perf_counter() - release) * 1e3)
+    lat = np.array(lat) if lat else np.zeros(1)
+    log("latency over %d paced frames: p50 %.1f ms, p99 %.1f ms" %
+        (len(lat), np.percentile(lat, 50), np.percentile(lat, 99)))
+
+    kernels = {"k_score": tm["k_score_ms"], "k_integrate": tm["k_integrate_ms"],
+               "k_normals": tm["k_normals_ms"], "k_mask": tm["k_mask_ms"],
+               "k_fold": tm["k_fold_ms"]}
+    dominant = max(kernels, key=kernels.get)
+    score_s = tm["k_score_ms"] / 1e3
+    achieved = byts / score_s / 1e9 if score_s > 0 else 0.0
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        tr = json.load(open(TRAFFIC_FILE))
+        if tr.get("src_sha") == src_sha(SCORE_SRC):
+            traffic = tr.get("bytes_per_launch")
+    roofline = {"kernel": "k_score", "bound": "hbm", "achieved": achieved,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                "traffic": traffic,
+                "algorithmic_bytes_per_launch": byts / max(K, 1),
+                "avg_launch_ms": tm["k_score_ms"] / max(tm["score_calls"], 1),
+                "dominant_kernel": dominant}
+
+    out = {
+        "metric": METRIC,
+        "value": tests / wall,
+        "unit": "point-orientation tests/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": wall / K * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {
+            "workload": "tree: procedural 8 m tree, 20,000 returns/frame from an orbiting "
+                        "Mid-360-shaped sensor, v=1 cm, tau=4 cm, saw box 30x5x2 cm + 1 m "
+                        "corridor, K=256 (64 directions x 4 rolls)",
+            "frames_timed": [W, W + K - 1], "returns_per_frame": int(np.mean([len(f.xyz) for f in frames])),
+            "orientations": Krot, "voxel_m": w.voxel, "trunc_m": w.trunc,
+            "map_points_end": int(map_points), "map_blocks_end": int(map_blocks),
+        },
+        "returns_integrated_per_s": returns / (tm["integrate_ms"] / 1e3),
+        "nominal_tests_per_s": nominal / wall,
+        "canonical_lookups_per_s": lookups / wall,
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "max": float(lat.max()), "frames": int(len(lat)), "rate_hz": 10,
+                       "includes": "H2D of the frame, integrate, score, D2H of all labels"},
+        "stage_ms_per_step": {k: v / max(K, 1) for k, v in
+                              {"integrate": tm["integrate_ms"], "score": tm["score_ms"],
+                               **kernels}.items()},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        t = time.perf_counter()
+        out["cpu_baseline"] = cpu_baseline(w, frames, args.cpu_frames, args.cpu_points)
+        log("cpu baseline in %.1f s" % (time.perf_counter() - t))
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -203,6 +203,20 @@ int af_score_stats_get(af_ctx *ctx, int32_t tool_id, af_score_stats *st);
 /* Bytes of device memory the context holds. */
 int64_t af_device_bytes(af_ctx *ctx);
 
+/* Per-stage device time, measured with hipEvents recorded on the call's own
+ * stream around each stage (enabled by af_timing_enable; off by default).
+ * Stages: whole integrate_frame work, its cube-accumulation kernel and its
+ * fold/brick kernel; whole score_points work, its normal, mask and score
+ * kernels.  Times in milliseconds, summed over calls since the last reset. */
+typedef struct af_timing {
+  double integrate_ms, k_integrate_ms, k_fold_ms;
+  double score_ms, k_normals_ms, k_mask_ms, k_score_ms;
+  int64_t integrate_calls, score_calls;
+} af_timing;
+int af_timing_enable(af_ctx *ctx, int on);
+/* Synchronises the pending events, fills *out, and zeroes the sums if reset. */
+int af_timing_read(af_ctx *ctx, af_timing *out, int reset);
+
 #ifdef __cplusplus
 }
 #endif

@@ -70,6 +70,16 @@ class ScoreStats(ctypes.Structure):
         return {n: getattr(self, n) for n, _ in self._fields_}
 
 
+class Timing(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in
+                ("integrate_ms", "k_integrate_ms", "k_fold_ms", "score_ms", "k_normals_ms",
+                 "k_mask_ms", "k_score_ms")] + \
+               [("integrate_calls", ctypes.c_int64), ("score_calls", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
 # name -> (restype, argtypes); also used by the export test
 _vp, _i32, _i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
 SIGNATURES = {
@@ -90,6 +100,8 @@ SIGNATURES = {
     "af_frame_stats_get": (ctypes.c_int, [_vp, ctypes.POINTER(FrameStats)]),
     "af_score_stats_get": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(ScoreStats)]),
     "af_device_bytes": (_i64, [_vp]),
+    "af_timing_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "af_timing_read": (ctypes.c_int, [_vp, ctypes.POINTER(Timing), ctypes.c_int]),
 }
 
 
@@ -282,6 +294,14 @@ class Context:
         st = FrameStats()
         self._check(self._lib.af_frame_stats_get(self.h, ctypes.byref(st)))
         return st.as_dict()
+
+    def timing_enable(self, on: bool = True):
+        self._check(self._lib.af_timing_enable(self.h, 1 if on else 0))
+
+    def timing_read(self, reset: bool = False):
+        t = Timing()
+        self._check(self._lib.af_timing_read(self.h, ctypes.byref(t), 1 if reset else 0))
+        return t.as_dict()
 
     def score_stats(self, tool_id: int):
         st = ScoreStats()

@@ -38,6 +38,13 @@ struct af_ctx {
   af_frame_stats fstats;
   std::string err;
   int status;
+  // stage timing (hipEvents on the call's stream)
+  bool timing;
+  std::vector<hipEvent_t> ev_free, ev_inflight;
+  struct Pending { int stage; hipEvent_t a, b; };
+  std::vector<Pending> pending;
+  double stage_ms[7];
+  int64_t integrate_calls, score_calls;
 };
 
 namespace {
@@ -161,9 +168,74 @@ int ensure_grid(af_ctx *c, hipStream_t s, bool &rebuilt) {
   return hip_check(c, "grid fill");
 }
 
+enum { ST_INTEGRATE, ST_K_INTEGRATE, ST_K_FOLD, ST_SCORE, ST_K_NORMALS, ST_K_MASK, ST_K_SCORE };
+
+hipEvent_t timing_mark(af_ctx *c, hipStream_t s) {
+  if (!c->timing) return nullptr;
+  hipEvent_t e;
+  if (!c->ev_free.empty()) {
+    e = c->ev_free.back();
+    c->ev_free.pop_back();
+  } else if (hipEventCreate(&e) != hipSuccess) {
+    return nullptr;
+  }
+  hipEventRecord(e, s);
+  c->ev_inflight.push_back(e);
+  return e;
+}
+
+int timing_flush(af_ctx *c) {
+  for (auto &p : c->pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(p.b) != hipSuccess || hipEventElapsedTime(&ms, p.a, p.b) != hipSuccess)
+      return fail(c, AF_EDEVICE, "timing event failed");
+    c->stage_ms[p.stage] += ms;
+  }
+  if (!c->ev_inflight.empty() && hipEventSynchronize(c->ev_inflight.back()) != hipSuccess)
+    return fail(c, AF_EDEVICE, "timing event failed");
+  c->ev_free.insert(c->ev_free.end(), c->ev_inflight.begin(), c->ev_inflight.end());
+  c->ev_inflight.clear();
+  c->pending.clear();
+  return AF_OK;
+}
+
+void timing_pair(af_ctx *c, int stage, hipEvent_t a, hipEvent_t b) {
+  if (!a || !b) return;
+  c->pending.push_back({stage, a, b});
+  if (c->ev_inflight.size() > 8192) timing_flush(c);
+}
+
 }  // namespace
 
 extern "C" {
+
+int af_timing_enable(af_ctx *c, int on) {
+  if (!c) return AF_EINVAL;
+  c->timing = on != 0;
+  return AF_OK;
+}
+
+int af_timing_read(af_ctx *c, af_timing *out, int reset) {
+  if (!c) return AF_EINVAL;
+  int rc = timing_flush(c);
+  if (rc != AF_OK) return rc;
+  if (out) {
+    out->integrate_ms = c->stage_ms[ST_INTEGRATE];
+    out->k_integrate_ms = c->stage_ms[ST_K_INTEGRATE];
+    out->k_fold_ms = c->stage_ms[ST_K_FOLD];
+    out->score_ms = c->stage_ms[ST_SCORE];
+    out->k_normals_ms = c->stage_ms[ST_K_NORMALS];
+    out->k_mask_ms = c->stage_ms[ST_K_MASK];
+    out->k_score_ms = c->stage_ms[ST_K_SCORE];
+    out->integrate_calls = c->integrate_calls;
+    out->score_calls = c->score_calls;
+  }
+  if (reset) {
+    for (double &x : c->stage_ms) x = 0;
+    c->integrate_calls = c->score_calls = 0;
+  }
+  return AF_OK;
+}
 
 int af_config_default(af_config *cfg, double voxel, double trunc) {
   if (!cfg || !(voxel > 0)) return AF_EINVAL;
@@ -293,6 +365,8 @@ int af_create(const af_config *cfg, af_ctx **out) {
 int af_destroy(af_ctx *c) {
   if (!c) return AF_EINVAL;
   hipDeviceSynchronize();
+  timing_flush(c);
+  for (hipEvent_t e : c->ev_free) hipEventDestroy(e);
   for (void *q : c->allocs) hipFree(q);
   if (c->counters_host) hipHostFree(c->counters_host);
   delete c;
@@ -421,6 +495,7 @@ int af_integrate_frame(af_ctx *c, const float *xyz, int64_t n, const float origi
     if ((rc = alloc_scratch(c, std::max<int64_t>(n, 2 * c->fs.cap))) != AF_OK) return rc;
   }
   const int32_t frame = (int32_t)frame_id;
+  hipEvent_t t0 = timing_mark(c, s);
   launch_frame_prep(xyz, n, Q, c->p, c->map, c->pts, c->fs, c->counters, s);
   launch_assign_blocks(c->map, c->fs, c->counters, frame, s);
   launch_commit_blocks(c->map, c->counters, s);
@@ -438,14 +513,25 @@ int af_integrate_frame(af_ctx *c, const float *xyz, int64_t n, const float origi
   }
   bool rebuilt = false;
   if ((rc = ensure_grid(c, s, rebuilt)) != AF_OK) return rc;
+  hipEvent_t t1 = timing_mark(c, s);
   launch_integrate(n, Q, c->p, c->map, c->fs, c->counters, s);
+  hipEvent_t t2 = timing_mark(c, s);
   launch_touch_band(n, c->p, c->map, c->fs, c->counters, frame, s);
   launch_points_append(h.n_new_points, c->map, c->pts, c->fs, c->counters, frame, s);
   launch_commit_points(c->pts, c->counters, s);
   launch_points_view(n, Q, c->p, c->pts, c->fs, frame, s);
   int64_t nb_after = std::min<int64_t>((int64_t)h.blocks_before + h.n_new_blocks, c->cfg.max_blocks);
+  hipEvent_t t3 = timing_mark(c, s);
   launch_fold(c->p, c->map, c->fs, c->counters, c->grid, std::max<int64_t>(1, std::min<int64_t>(nb_after, n * (kMaxSpan + kMaxBand))), s);
+  hipEvent_t t4 = timing_mark(c, s);
   if (rebuilt) launch_grid_rebuild(c->p, c->map, c->grid, nb_after, s);
+  hipEvent_t t5 = timing_mark(c, s);
+  if (c->timing) {
+    timing_pair(c, ST_INTEGRATE, t0, t5);
+    timing_pair(c, ST_K_INTEGRATE, t1, t2);
+    timing_pair(c, ST_K_FOLD, t3, t4);
+    c->integrate_calls += 1;
+  }
   if ((rc = hip_check(c, "integrate")) != AF_OK) return rc;
   c->last_frame = frame_id;
   c->last_stream = s;
@@ -466,10 +552,22 @@ int af_score_points(af_ctx *c, int32_t tool_id, void *stream) {
   ToolDev &t = c->tools[tool_id];
   if (!t.entries) return fail(c, AF_ENOTOOL, "tool %d has no kernels", tool_id);
   hipStream_t s = (hipStream_t)stream;
+  hipEvent_t t0 = timing_mark(c, s);
   HIP_TRY(c, hipMemsetAsync(t.counters, 0, sizeof(ScoreCounters), s));
+  hipEvent_t t1 = timing_mark(c, s);
   launch_normals(c->p, c->map, c->pts, c->grid, c->n_points, s);
+  hipEvent_t t2 = timing_mark(c, s);
   launch_mask(c->p, c->pts, t, c->n_points, s);
+  hipEvent_t t3 = timing_mark(c, s);
   launch_score(c->p, c->map, c->pts, t, c->grid, c->n_points, s);
+  hipEvent_t t4 = timing_mark(c, s);
+  if (c->timing) {
+    timing_pair(c, ST_SCORE, t0, t4);
+    timing_pair(c, ST_K_NORMALS, t1, t2);
+    timing_pair(c, ST_K_MASK, t2, t3);
+    timing_pair(c, ST_K_SCORE, t3, t4);
+    c->score_calls += 1;
+  }
   c->last_stream = s;
   return hip_check(c, "score");
 }

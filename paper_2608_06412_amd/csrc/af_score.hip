@@ -130,55 +130,79 @@ k_normals(Params p, MapDev m, PointsDev pts, GridDev g, int64_t n) {
   pts.has_normal[i] = 1;
 }
 
-// One wave per (point, 64 orientations): lane l decides orientation 64w + l.
+// One lane per point: the point's normal and viewpoint vectors stay in
+// registers (fp64, exact conversions of integers) while every lane walks the
+// same orientation list, so each direction is a wave-uniform load.
 __global__ void __launch_bounds__(kThreads)
 k_mask(Params p, PointsDev pts, ToolDev t, int64_t n, int32_t mw) {
-  int64_t item = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
-  if (item >= n * mw) return;
-  int64_t i = item / mw;
-  int w = (int)(item - i * mw);
-  int lane = lane_id();
-  int hn = pts.has_normal[i];
-  if (hn < 0) {
-    if (lane == 0) t.mask[i * mw + w] = 0;
-    return;
-  }
-  int k = 64 * w + lane;
-  bool bit = false;
-  if (k < t.K) {
-    const double *R = t.rot + 9 * (int64_t)k;
-    double d0 = R[0], d1 = R[3], d2 = R[6];
-    bool nok = true;
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const bool act = i < n;
+  const int hn = act ? pts.has_normal[i] : -1;
+  double n0 = 0, n1 = 0, n2 = 0, nn = 0;
+  double wx[kMaxVp], wy[kMaxVp], wz[kMaxVp], ww[kMaxVp];
+  int nv = 0;
+  if (hn >= 0) {
     if (hn > 0) {
-      const int32_t *nv = pts.normal + 3 * i;
-      double dot = ((double)nv[0] * d0 + (double)nv[1] * d1) + (double)nv[2] * d2;
-      double nn = (double)((int64_t)nv[0] * nv[0] + (int64_t)nv[1] * nv[1] +
-                           (int64_t)nv[2] * nv[2]);
-      nok = dot >= 0.0 && dot * dot >= p.cos2 * nn;
+      const int32_t *nvp = pts.normal + 3 * i;
+      n0 = (double)nvp[0];
+      n1 = (double)nvp[1];
+      n2 = (double)nvp[2];
+      nn = (double)((int64_t)nvp[0] * nvp[0] + (int64_t)nvp[1] * nvp[1] +
+                    (int64_t)nvp[2] * nvp[2]);
     }
-    if (nok) {
-      int32_t s[3];
-      unpack_key(pts.key[i], s[0], s[1], s[2]);
-      int nv = pts.nvp[i];
-      for (int j = 0; j < nv; ++j) {
+    int32_t s[3];
+    unpack_key(pts.key[i], s[0], s[1], s[2]);
+    nv = pts.nvp[i];
+#pragma unroll
+    for (int j = 0; j < kMaxVp; ++j) {
+      if (j < nv) {
         const int32_t *V = pts.vp + (i * kMaxVp + j) * 3;
-        int64_t w0 = (int64_t)V[0] - (256 * (int64_t)s[0] + 128);
-        int64_t w1 = (int64_t)V[1] - (256 * (int64_t)s[1] + 128);
-        int64_t w2 = (int64_t)V[2] - (256 * (int64_t)s[2] + 128);
-        double wd = ((double)w0 * d0 + (double)w1 * d1) + (double)w2 * d2;
-        double ww = (double)(w0 * w0 + w1 * w1 + w2 * w2);
-        if (wd > 0.0 && wd * wd > p.obs2 * ww) {
-          bit = true;
-          break;
-        }
+        int64_t a0 = (int64_t)V[0] - (256 * (int64_t)s[0] + 128);
+        int64_t a1 = (int64_t)V[1] - (256 * (int64_t)s[1] + 128);
+        int64_t a2 = (int64_t)V[2] - (256 * (int64_t)s[2] + 128);
+        wx[j] = (double)a0;
+        wy[j] = (double)a1;
+        wz[j] = (double)a2;
+        ww[j] = (double)(a0 * a0 + a1 * a1 + a2 * a2);
+      } else {
+        wx[j] = wy[j] = wz[j] = ww[j] = 0.0;
       }
     }
   }
-  unsigned long long b = __ballot(bit);
-  if (lane == 0) {
-    t.mask[i * mw + w] = b;
-    if (b) atomicAdd(&t.counters->candidate_tests, (unsigned long long)__popcll(b));
+  unsigned long long cand = 0;
+  for (int w = 0; w < mw; ++w) {
+    uint64_t word = 0;
+    const int kend = t.K - 64 * w < 64 ? t.K - 64 * w : 64;
+    for (int j = 0; j < kend; ++j) {
+      const double *R = t.rot + 9 * (int64_t)(64 * w + j);
+      const double d0 = R[0], d1 = R[3], d2 = R[6];
+      bool ok = hn >= 0;
+      if (hn > 0) {
+        double dot = (n0 * d0 + n1 * d1) + n2 * d2;
+        ok = dot >= 0.0 && dot * dot >= p.cos2 * nn;
+      }
+      if (ok) {
+        bool seen = false;
+#pragma unroll
+        for (int v = 0; v < kMaxVp; ++v) {
+          if (v < nv && !seen) {
+            double wd = (wx[v] * d0 + wy[v] * d1) + wz[v] * d2;
+            seen = wd > 0.0 && wd * wd > p.obs2 * ww[v];
+          }
+        }
+        ok = seen;
+      }
+      word |= (uint64_t)ok << j;
+    }
+    if (act) t.mask[i * mw + w] = word;
+    cand += (unsigned long long)__popcll(word);
   }
+  for (int off = 32; off >= 1; off >>= 1) {
+    unsigned lo = __shfl_xor((unsigned)(cand & 0xffffffffu), off);
+    unsigned hi = __shfl_xor((unsigned)(cand >> 32), off);
+    cand += ((unsigned long long)hi << 32) | lo;
+  }
+  if (lane_id() == 0 && cand) atomicAdd(&t.counters->candidate_tests, cand);
 }
 
 // Position of the r-th (1-based) set bit of m, or 64.
@@ -188,11 +212,18 @@ __device__ inline int nth_bit(uint64_t m, int r) {
   return __ffsll((long long)m) - 1;
 }
 
+constexpr int kScoreThreads = 1024;
+constexpr int kScoreWaves = kScoreThreads / 64;
+constexpr int kLdsK = 256;   // orientations whose first table chunk lives in LDS
+
 // One orientation of one point, lanes over table entries in order; returns
-// true when free.  `lookups` counts entries up to the deciding one.
+// true when free.  `lookups` counts entries up to the deciding one.  The first
+// 64 entries of orientations below kLdsK come from LDS.
 __device__ inline bool orientation_free(const Params &p, const ToolDev &t, const GridDev &g,
-                                        const int32_t s[3], int k, uint64_t &lookups) {
-  const uint32_t b = t.begin[k], e = t.begin[k + 1];
+                                        const int32_t s[3], int k, const uint32_t *s_begin,
+                                        const uint32_t *s_first, int kc, uint64_t &lookups) {
+  const uint32_t b = k < kc ? s_begin[k] : t.begin[k];
+  const uint32_t e = k < kc ? s_begin[k + 1] : t.begin[k + 1];
   const int lane = lane_id();
   int body = 0;
   for (uint32_t base = b; base < e; base += 64) {
@@ -200,7 +231,7 @@ __device__ inline bool orientation_free(const Params &p, const ToolDev &t, const
     bool hit = false;
     int cls = AF_CLS_BODY;
     if (idx < e) {
-      uint32_t ent = t.entries[idx];
+      uint32_t ent = (base == b && k < kc) ? s_first[64 * k + lane] : t.entries[idx];
       cls = entry_cls(ent);
       uint32_t code = code_at(g, s[0] + entry_x(ent), s[1] + entry_y(ent), s[2] + entry_z(ent));
       hit = cls == AF_CLS_NEAR ? code != 0u : (code & 1u) != 0u;
@@ -220,13 +251,25 @@ __device__ inline bool orientation_free(const Params &p, const ToolDev &t, const
   return true;
 }
 
-// One wave per point (grid-stride): the lowest-index candidate orientation
-// that is free labels the point accessible.
-__global__ void __launch_bounds__(kThreads)
+// Persistent workgroups of 16 waves, one wave per point (grid-stride): the
+// lowest-index candidate orientation that is free labels the point
+// accessible.
+__global__ void __launch_bounds__(kScoreThreads)
 k_score(Params p, MapDev m, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t mw) {
+  __shared__ uint32_t s_begin[kLdsK + 1];
+  __shared__ uint32_t s_first[kLdsK * 64];
+  const int kc = t.K < kLdsK ? t.K : kLdsK;
+  for (int j = threadIdx.x; j <= kc; j += kScoreThreads) s_begin[j] = t.begin[j];
+  __syncthreads();
+  for (int j = threadIdx.x; j < kc * 64; j += kScoreThreads) {
+    uint32_t pos = s_begin[j >> 6] + (uint32_t)(j & 63);
+    s_first[j] = pos < s_begin[(j >> 6) + 1] ? t.entries[pos] : 0u;
+  }
+  __syncthreads();
   const int lane = lane_id();
-  const int64_t wave0 = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
-  const int64_t nwaves = (int64_t)gridDim.x * kWaves;
+  const int64_t wave0 =
+      (int64_t)blockIdx.x * kScoreWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t nwaves = (int64_t)gridDim.x * kScoreWaves;
   uint64_t conf = 0, acc = 0, blk = 0, nocand = 0, tests = 0, lookups = 0;
   for (int64_t i = wave0; i < n; i += nwaves) {
     int hn = __builtin_amdgcn_readfirstlane(pts.has_normal[i]);
@@ -246,7 +289,7 @@ k_score(Params p, MapDev m, PointsDev pts, ToolDev t, GridDev g, int64_t n, int3
           word &= word - 1;
           label = AF_BLOCKED;
           ++tests;
-          if (orientation_free(p, t, g, s, k, lookups)) {
+          if (orientation_free(p, t, g, s, k, s_begin, s_first, kc, lookups)) {
             label = AF_ACCESSIBLE;
             ff = (int16_t)k;
             break;
@@ -308,9 +351,8 @@ void launch_normals(const Params &p, MapDev m, PointsDev pts, GridDev g, int64_t
 
 void launch_mask(const Params &p, PointsDev pts, ToolDev t, int64_t n, hipStream_t s) {
   int32_t mw = (t.K + 63) / 64;
-  int64_t items = n * mw;
-  if (items <= 0) return;
-  hipLaunchKernelGGL(k_mask, dim3((unsigned)((items + kWaves - 1) / kWaves)), dim3(kThreads), 0,
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_mask, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0,
                      s, p, pts, t, n, mw);
 }
 
@@ -318,9 +360,10 @@ void launch_score(const Params &p, MapDev m, PointsDev pts, ToolDev t, GridDev g
                   hipStream_t s) {
   int32_t mw = (t.K + 63) / 64;
   if (n <= 0) return;
-  int64_t wg = (n + kWaves - 1) / kWaves;
-  if (wg > 4096) wg = 4096;
-  hipLaunchKernelGGL(k_score, dim3((unsigned)wg), dim3(kThreads), 0, s, p, m, pts, t, g, n, mw);
+  int64_t wg = (n + kScoreWaves - 1) / kScoreWaves;
+  if (wg > 512) wg = 512;   // two resident workgroups per CU
+  hipLaunchKernelGGL(k_score, dim3((unsigned)wg), dim3(kScoreThreads), 0, s, p, m, pts, t, g, n,
+                     mw);
 }
 
 }  // namespace af

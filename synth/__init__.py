@@ -222,15 +222,15 @@ def circle_poses(n: int, radius: float = 3.0, centre=(0.5, 0.0), z: float = 1.5)
 
 
 def orbit_poses(n: int, seed: int = 3, r_lo: float = 4.0, r_hi: float = 6.0,
-                z_lo: float = 0.5, z_hi: float = 8.0, period: int = 150):
+                z_lo: float = 0.5, z_hi: float = 8.0, period: int = 150, span: int = 600):
     """Seeded orbit around the z axis: radius wanders in [r_lo, r_hi], altitude
-    climbs from z_lo to z_hi and back over the run, small jitter."""
+    climbs from z_lo to z_hi and back once every `span` frames, small jitter."""
     rng = np.random.default_rng(seed)
     t = np.arange(n, dtype=np.float64)
     ph = rng.uniform(0, 2 * math.pi, size=3)
     ang = 2 * math.pi * t / period + ph[0]
     rad = 0.5 * (r_lo + r_hi) + 0.5 * (r_hi - r_lo) * np.sin(2 * math.pi * t / (2.3 * period) + ph[1])
-    frac = 0.5 - 0.5 * np.cos(2 * math.pi * t / max(n, 1))
+    frac = 0.5 - 0.5 * np.cos(2 * math.pi * t / span)
     z = z_lo + (z_hi - z_lo) * frac
     jit = rng.normal(0.0, 0.03, size=(n, 3))
     return np.stack([rad * np.cos(ang), rad * np.sin(ang), z], axis=1) + jit
@@ -368,7 +368,7 @@ def tree(n_frames: int = 600, n_hits=20000, sigma: float = 0.02, seed: int = 5,
          tree_seed: int = 7, traj_seed: int = 3) -> Workload:
     """Procedural 8 m tree, 600 x 20,000 returns, v = 1 cm, tau = 4 cm, saw box
     30x5x2 cm with 1 m corridor at 64 directions x 4 rolls."""
-    poses = orbit_poses(600, seed=traj_seed)
+    poses = orbit_poses(max(600, n_frames), seed=traj_seed)
     return Workload("tree", 0.01, 0.04, 0.01, tree_scene(tree_seed), poses, n_hits,
                     sigma, seed, -7.0, 52.0, box_tool(),
                     orientations(fibonacci_directions(64), 4), n_frames)
