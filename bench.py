@@ -94,6 +94,8 @@ def main():
     ap.add_argument("--cpu-frames", type=int, default=12)
     ap.add_argument("--cpu-points", type=int, default=1500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--score-variant", type=int, default=None)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU; this build has no multi-GPU path "
@@ -134,6 +136,15 @@ def main():
             log("warm-up frame %d, %d points" % (i, ctx.num_points()))
     torch.cuda.synchronize()
     log("warm-up %d frames in %.1f s" % (W, time.perf_counter() - t))
+    tuning = None
+    if not args.no_tune:
+        best, ms = ctx.tune_score(0, reps=3)
+        names = ctx.score_variants()
+        tuning = {"chosen": names[best], "ms": {n: round(m, 3) for n, m in zip(names, ms)},
+                  "at_frame": W}
+        log("score tuning at frame %d: %s" % (W, json.dumps(tuning)))
+    elif args.score_variant is not None:
+        ctx.set_score_variant(args.score_variant)
 
     ctx.timing_enable(True)
     ctx.timing_read(reset=True)
@@ -179,9 +190,8 @@ def main():
     log("latency over %d paced frames: p50 %.1f ms, p99 %.1f ms" %
         (len(lat), np.percentile(lat, 50), np.percentile(lat, 99)))
 
-    kernels = {"k_score": tm["k_score_ms"], "k_integrate": tm["k_integrate_ms"],
-               "k_normals": tm["k_normals_ms"], "k_mask": tm["k_mask_ms"],
-               "k_fold": tm["k_fold_ms"]}
+    kernels = {"k_score": tm["k_score_ms"], "k_integrate_fold": tm["k_integrate_ms"],
+               "k_normals": tm["k_normals_ms"], "k_mask": tm["k_mask_ms"]}
     dominant = max(kernels, key=kernels.get)
     score_s = tm["k_score_ms"] / 1e3
     achieved = byts / score_s / 1e9 if score_s > 0 else 0.0
@@ -228,6 +238,7 @@ def main():
                               {"integrate": tm["integrate_ms"], "score": tm["score_ms"],
                                **kernels}.items()},
         "roofline": roofline,
+        "score_tuning": tuning,
     }
     if not args.no_cpu_baseline:
         t = time.perf_counter()

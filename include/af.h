@@ -205,17 +205,33 @@ int64_t af_device_bytes(af_ctx *ctx);
 
 /* Per-stage device time, measured with hipEvents recorded on the call's own
  * stream around each stage (enabled by af_timing_enable; off by default).
- * Stages: whole integrate_frame work, its cube-accumulation kernel and its
- * fold/brick kernel; whole score_points work, its normal, mask and score
- * kernels.  Times in milliseconds, summed over calls since the last reset. */
+ * Stages: whole integrate_frame work and its accumulation step (binning of
+ * returns by block plus the per-block gather, fold and brick update); whole
+ * score_points work and its normal, mask and score kernels.  Times in
+ * milliseconds, summed over calls since the last reset. */
 typedef struct af_timing {
-  double integrate_ms, k_integrate_ms, k_fold_ms;
+  double integrate_ms, k_integrate_ms;
   double score_ms, k_normals_ms, k_mask_ms, k_score_ms;
   int64_t integrate_calls, score_calls;
 } af_timing;
 int af_timing_enable(af_ctx *ctx, int on);
 /* Synchronises the pending events, fills *out, and zeroes the sums if reset. */
 int af_timing_read(af_ctx *ctx, af_timing *out, int reset);
+
+/* Scoring kernel configurations (workgroup size, LDS staging of the tables,
+ * look-ahead over candidate orientations, unrolling, per-brick occupancy
+ * skip, dynamic point fetch).  All give identical labels; they differ in
+ * speed only.  af_tune_score times every configuration `reps` times on the
+ * context's current map and tool (HIP events on `stream`), keeps the fastest
+ * for later af_score_points calls, writes its index to *best and, if
+ * ms_per_variant is not NULL, each configuration's mean time (host array of
+ * af_score_variant_count() floats).  Synchronises `stream`. */
+int af_score_variant_count(void);
+const char *af_score_variant_name(int32_t v);
+int af_set_score_variant(af_ctx *ctx, int32_t v);
+int32_t af_get_score_variant(af_ctx *ctx);
+int af_tune_score(af_ctx *ctx, int32_t tool_id, int32_t reps, void *stream, int32_t *best,
+                  float *ms_per_variant);
 
 #ifdef __cplusplus
 }

@@ -72,7 +72,7 @@ class ScoreStats(ctypes.Structure):
 
 class Timing(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in
-                ("integrate_ms", "k_integrate_ms", "k_fold_ms", "score_ms", "k_normals_ms",
+                ("integrate_ms", "k_integrate_ms", "score_ms", "k_normals_ms",
                  "k_mask_ms", "k_score_ms")] + \
                [("integrate_calls", ctypes.c_int64), ("score_calls", ctypes.c_int64)]
 
@@ -102,6 +102,11 @@ SIGNATURES = {
     "af_device_bytes": (_i64, [_vp]),
     "af_timing_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "af_timing_read": (ctypes.c_int, [_vp, ctypes.POINTER(Timing), ctypes.c_int]),
+    "af_score_variant_count": (ctypes.c_int, []),
+    "af_score_variant_name": (ctypes.c_char_p, [_i32]),
+    "af_set_score_variant": (ctypes.c_int, [_vp, _i32]),
+    "af_get_score_variant": (_i32, [_vp]),
+    "af_tune_score": (ctypes.c_int, [_vp, _i32, _i32, _vp, _vp, _vp]),
 }
 
 
@@ -302,6 +307,26 @@ class Context:
         t = Timing()
         self._check(self._lib.af_timing_read(self.h, ctypes.byref(t), 1 if reset else 0))
         return t.as_dict()
+
+    def score_variants(self):
+        n = self._lib.af_score_variant_count()
+        return [self._lib.af_score_variant_name(i).decode() for i in range(n)]
+
+    def set_score_variant(self, v: int):
+        self._check(self._lib.af_set_score_variant(self.h, int(v)))
+
+    def score_variant(self) -> int:
+        return self._lib.af_get_score_variant(self.h)
+
+    def tune_score(self, tool_id: int, reps: int = 3, stream=None):
+        """Time every scoring configuration on the current map; keep the
+        fastest.  Returns (best index, per-configuration ms)."""
+        n = self._lib.af_score_variant_count()
+        ms = (ctypes.c_float * n)()
+        best = ctypes.c_int32()
+        self._check(self._lib.af_tune_score(self.h, int(tool_id), int(reps),
+                                            _stream_handle(stream), ctypes.byref(best), ms))
+        return best.value, list(ms)
 
     def score_stats(self, tool_id: int):
         st = ScoreStats()

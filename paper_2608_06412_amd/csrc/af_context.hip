@@ -30,6 +30,8 @@ struct af_ctx {
   std::vector<ToolDev> tools;
   std::vector<int64_t> tool_bytes;
   uint64_t *mask;               // shared candidate-mask scratch
+  unsigned *work;               // point counter of the dynamic score variants
+  int score_variant;
   int64_t last_frame;
   int64_t n_points, n_blocks;   // host mirrors after the last frame
   int32_t bbox_lo[3], bbox_hi[3];
@@ -43,7 +45,7 @@ struct af_ctx {
   std::vector<hipEvent_t> ev_free, ev_inflight;
   struct Pending { int stage; hipEvent_t a, b; };
   std::vector<Pending> pending;
-  double stage_ms[7];
+  double stage_ms[6];
   int64_t integrate_calls, score_calls;
 };
 
@@ -113,6 +115,10 @@ int alloc_scratch(af_ctx *c, int64_t cap) {
     dev_free(c, f.new_keys, sizeof(int64_t) * f.cap);
     dev_free(c, f.new_kslot, sizeof(int32_t) * f.cap);
     dev_free(c, f.touched, sizeof(int32_t) * f.cap * (kMaxSpan + kMaxBand));
+    dev_free(c, f.bin_cnt, sizeof(int32_t) * f.cap * (kMaxSpan + kMaxBand));
+    dev_free(c, f.bin_off, sizeof(int32_t) * (f.cap * (kMaxSpan + kMaxBand) + 1));
+    dev_free(c, f.bin_fill, sizeof(int32_t) * f.cap * (kMaxSpan + kMaxBand));
+    dev_free(c, f.bin_list, sizeof(int32_t) * f.cap * kMaxSpan);
     memset(&f, 0, sizeof(f));
   }
   ALLOC(c, f.P, cap);
@@ -123,6 +129,10 @@ int alloc_scratch(af_ctx *c, int64_t cap) {
   ALLOC(c, f.new_keys, cap);
   ALLOC(c, f.new_kslot, cap);
   ALLOC(c, f.touched, cap * (kMaxSpan + kMaxBand));
+  ALLOC(c, f.bin_cnt, cap * (kMaxSpan + kMaxBand));
+  ALLOC(c, f.bin_off, cap * (kMaxSpan + kMaxBand) + 1);
+  ALLOC(c, f.bin_fill, cap * (kMaxSpan + kMaxBand));
+  ALLOC(c, f.bin_list, cap * kMaxSpan);
   f.cap = cap;
   return AF_OK;
 }
@@ -157,10 +167,12 @@ int ensure_grid(af_ctx *c, hipStream_t s, bool &rebuilt) {
     HIP_TRY(c, hipStreamSynchronize(s));
     dev_free(c, g.pred, sizeof(uint32_t) * 32 * c->grid_bricks);
     dev_free(c, g.surf, sizeof(uint32_t) * 16 * c->grid_bricks);
+    dev_free(c, g.occ_any, sizeof(uint32_t) * ((c->grid_bricks + 31) / 32));
     c->grid_bricks = 0;
   }
   ALLOC(c, ng.pred, nb * 32);
   ALLOC(c, ng.surf, nb * 16);
+  ALLOC(c, ng.occ_any, (nb + 31) / 32);
   c->grid = ng;
   c->grid_bricks = nb;
   launch_grid_fill(c->grid, s);
@@ -168,7 +180,7 @@ int ensure_grid(af_ctx *c, hipStream_t s, bool &rebuilt) {
   return hip_check(c, "grid fill");
 }
 
-enum { ST_INTEGRATE, ST_K_INTEGRATE, ST_K_FOLD, ST_SCORE, ST_K_NORMALS, ST_K_MASK, ST_K_SCORE };
+enum { ST_INTEGRATE, ST_K_INTEGRATE, ST_SCORE, ST_K_NORMALS, ST_K_MASK, ST_K_SCORE, ST_COUNT };
 
 hipEvent_t timing_mark(af_ctx *c, hipStream_t s) {
   if (!c->timing) return nullptr;
@@ -222,7 +234,6 @@ int af_timing_read(af_ctx *c, af_timing *out, int reset) {
   if (out) {
     out->integrate_ms = c->stage_ms[ST_INTEGRATE];
     out->k_integrate_ms = c->stage_ms[ST_K_INTEGRATE];
-    out->k_fold_ms = c->stage_ms[ST_K_FOLD];
     out->score_ms = c->stage_ms[ST_SCORE];
     out->k_normals_ms = c->stage_ms[ST_K_NORMALS];
     out->k_mask_ms = c->stage_ms[ST_K_MASK];
@@ -322,8 +333,8 @@ int af_create(const af_config *cfg, af_ctx **out) {
   CREATE_ALLOC(m.W, B * kBlockVox);
   CREATE_ALLOC(m.clr, B * 16);
   CREATE_ALLOC(m.surf, B * 16);
-  CREATE_ALLOC(m.delta, B * kBlockVox);
   CREATE_ALLOC(m.touched, B);
+  CREATE_ALLOC(m.tpos, B);
   CREATE_ALLOC(m.n_blocks, 1);
   PointsDev &q = c->pts;
   q.max_points = NP;
@@ -343,6 +354,7 @@ int af_create(const af_config *cfg, af_ctx **out) {
   CREATE_ALLOC(q.has_normal, NP);
   CREATE_ALLOC(q.n_points, 1);
   CREATE_ALLOC(c->counters, 1);
+  CREATE_ALLOC(c->work, 1);
   CREATE_ALLOC(c->mask, NP * ((cfg->max_orientations + 63) / 64));
   c->tools.assign(cfg->max_tools, ToolDev());
   c->tool_bytes.assign(cfg->max_tools, 0);
@@ -513,23 +525,20 @@ int af_integrate_frame(af_ctx *c, const float *xyz, int64_t n, const float origi
   }
   bool rebuilt = false;
   if ((rc = ensure_grid(c, s, rebuilt)) != AF_OK) return rc;
-  hipEvent_t t1 = timing_mark(c, s);
-  launch_integrate(n, Q, c->p, c->map, c->fs, c->counters, s);
-  hipEvent_t t2 = timing_mark(c, s);
   launch_touch_band(n, c->p, c->map, c->fs, c->counters, frame, s);
   launch_points_append(h.n_new_points, c->map, c->pts, c->fs, c->counters, frame, s);
   launch_commit_points(c->pts, c->counters, s);
   launch_points_view(n, Q, c->p, c->pts, c->fs, frame, s);
   int64_t nb_after = std::min<int64_t>((int64_t)h.blocks_before + h.n_new_blocks, c->cfg.max_blocks);
-  hipEvent_t t3 = timing_mark(c, s);
-  launch_fold(c->p, c->map, c->fs, c->counters, c->grid, std::max<int64_t>(1, std::min<int64_t>(nb_after, n * (kMaxSpan + kMaxBand))), s);
-  hipEvent_t t4 = timing_mark(c, s);
+  hipEvent_t t1 = timing_mark(c, s);
+  launch_integrate(n, Q, c->p, c->map, c->fs, c->counters, c->grid,
+                   std::max<int64_t>(1, std::min<int64_t>(nb_after, n * (kMaxSpan + kMaxBand))), s);
+  hipEvent_t t2 = timing_mark(c, s);
   if (rebuilt) launch_grid_rebuild(c->p, c->map, c->grid, nb_after, s);
   hipEvent_t t5 = timing_mark(c, s);
   if (c->timing) {
     timing_pair(c, ST_INTEGRATE, t0, t5);
     timing_pair(c, ST_K_INTEGRATE, t1, t2);
-    timing_pair(c, ST_K_FOLD, t3, t4);
     c->integrate_calls += 1;
   }
   if ((rc = hip_check(c, "integrate")) != AF_OK) return rc;
@@ -559,7 +568,7 @@ int af_score_points(af_ctx *c, int32_t tool_id, void *stream) {
   hipEvent_t t2 = timing_mark(c, s);
   launch_mask(c->p, c->pts, t, c->n_points, s);
   hipEvent_t t3 = timing_mark(c, s);
-  launch_score(c->p, c->map, c->pts, t, c->grid, c->n_points, s);
+  launch_score(c->p, c->pts, t, c->grid, c->n_points, c->score_variant, c->work, s);
   hipEvent_t t4 = timing_mark(c, s);
   if (c->timing) {
     timing_pair(c, ST_SCORE, t0, t4);
@@ -570,6 +579,60 @@ int af_score_points(af_ctx *c, int32_t tool_id, void *stream) {
   }
   c->last_stream = s;
   return hip_check(c, "score");
+}
+
+int af_score_variant_count(void) { return score_variants(); }
+
+const char *af_score_variant_name(int32_t v) { return score_variant_name(v); }
+
+int af_set_score_variant(af_ctx *c, int32_t v) {
+  if (!c) return AF_EINVAL;
+  if (v < 0 || v >= score_variants()) return fail(c, AF_EINVAL, "score variant %d out of range", v);
+  c->score_variant = v;
+  return AF_OK;
+}
+
+int32_t af_get_score_variant(af_ctx *c) { return c ? c->score_variant : -1; }
+
+int af_tune_score(af_ctx *c, int32_t tool_id, int32_t reps, void *stream, int32_t *best,
+                  float *ms_per_variant) {
+  if (!c) return AF_EINVAL;
+  if (tool_id < 0 || tool_id >= c->cfg.max_tools) return fail(c, AF_EINVAL, "bad tool id");
+  ToolDev &t = c->tools[tool_id];
+  if (!t.entries) return fail(c, AF_ENOTOOL, "tool %d has no kernels", tool_id);
+  if (reps < 1) reps = 1;
+  hipStream_t s = (hipStream_t)stream;
+  launch_normals(c->p, c->map, c->pts, c->grid, c->n_points, s);
+  launch_mask(c->p, c->pts, t, c->n_points, s);
+  hipEvent_t a, b;
+  HIP_TRY(c, hipEventCreate(&a));
+  HIP_TRY(c, hipEventCreate(&b));
+  int nv = score_variants();
+  float best_ms = 3.4e38f;
+  int best_v = c->score_variant;
+  for (int v = 0; v < nv; ++v) {
+    launch_score(c->p, c->pts, t, c->grid, c->n_points, v, c->work, s);  // warm
+    HIP_TRY(c, hipEventRecord(a, s));
+    for (int r = 0; r < reps; ++r)
+      launch_score(c->p, c->pts, t, c->grid, c->n_points, v, c->work, s);
+    HIP_TRY(c, hipEventRecord(b, s));
+    HIP_TRY(c, hipEventSynchronize(b));
+    float ms = 0.f;
+    HIP_TRY(c, hipEventElapsedTime(&ms, a, b));
+    ms /= (float)reps;
+    if (ms_per_variant) ms_per_variant[v] = ms;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best_v = v;
+    }
+  }
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  c->score_variant = best_v;
+  if (best) *best = best_v;
+  HIP_TRY(c, hipMemsetAsync(t.counters, 0, sizeof(ScoreCounters), s));
+  c->last_stream = s;
+  return hip_check(c, "tune");
 }
 
 static int sync_last(af_ctx *c) {

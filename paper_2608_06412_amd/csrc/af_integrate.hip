@@ -215,7 +215,6 @@ k_assign_blocks(MapDev m, FrameScratch fs, FrameCounters *c, int32_t frame) {
     for (int t = threadIdx.x; t < kBlockVox; t += kThreads) {
       m.S[id * kBlockVox + t] = 0;
       m.W[id * kBlockVox + t] = 0;
-      m.delta[id * kBlockVox + t] = 0;
     }
     if (threadIdx.x < 16) {
       m.clr[id * 16 + threadIdx.x] = 0;
@@ -231,55 +230,6 @@ __global__ void k_commit_blocks(MapDev m, FrameCounters *c) {
   *m.n_blocks = (int32_t)(base + add);
 }
 
-// ------------------------------------------------------------ integrate
-// One thread per (return, cube offset): cone test, clamped signed distance,
-// one 64-bit atomic add of (1 << 32) + d into the voxel's frame accumulator.
-__global__ void __launch_bounds__(kThreads)
-k_integrate(int64_t n, int3 Q, Params p, MapDev m, FrameScratch fs, FrameCounters *c) {
-  const int D = 2 * p.R + 1;
-  const int C = D * D * D;
-  int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  bool applied = false, excluded = false;
-  if (t < n * C) {
-    int64_t r = t / C;
-    int o = (int)(t - r * C);
-    int4 P = fs.P[r];
-    if (P.w > 0) {
-      int v[3] = {(P.x >> 8) + o % D - p.R, (P.y >> 8) + (o / D) % D - p.R,
-                  (P.z >> 8) + o / (D * D) - p.R};
-      int64_t a0 = 256 * (int64_t)v[0] + 128 - P.x;
-      int64_t a1 = 256 * (int64_t)v[1] + 128 - P.y;
-      int64_t a2 = 256 * (int64_t)v[2] + 128 - P.z;
-      int64_t b0 = (int64_t)P.x - Q.x, b1 = (int64_t)P.y - Q.y, b2 = (int64_t)P.z - Q.z;
-      int64_t ab = a0 * b0 + a1 * b1 + a2 * b2;
-      int64_t aa = a0 * a0 + a1 * a1 + a2 * a2;
-      int64_t bb = b0 * b0 + b1 * b1 + b2 * b2;
-      // behind the return within the cos > 0.95 cone: 400 (a.b)^2 > 361 |a|^2 |b|^2
-      if (ab > 0 && (__int128)400 * ab * ab > (__int128)361 * aa * bb) {
-        excluded = true;
-      } else {
-        applied = true;
-        int64_t c0 = a0 + b0, c1 = a1 + b1, c2 = a2 + b2;  // centre - Q
-        int64_t d = (int64_t)P.w - isqrt64(c0 * c0 + c1 * c1 + c2 * c2);
-        int64_t lo = p.clamp_neg ? -(int64_t)p.tau_u : 0;
-        d = d < lo ? lo : (d > p.tau_u ? p.tau_u : d);
-        Span sp = cube_span(P, p.R);
-        int idx = (((v[2] >> 3) - sp.lo[2]) * sp.n[1] + ((v[1] >> 3) - sp.lo[1])) * sp.n[0] +
-                  ((v[0] >> 3) - sp.lo[0]);
-        int32_t slot = fs.span[r * kMaxSpan + idx];
-        int32_t id = slot >= 0 ? m.h.vals[slot] : -1;
-        if (id >= 0) {
-          int vi = (v[0] & 7) | ((v[1] & 7) << 3) | ((v[2] & 7) << 6);
-          atomicAdd(&m.delta[(int64_t)id * kBlockVox + vi],
-                    (unsigned long long)((1LL << 32) + d));
-        }
-      }
-    }
-  }
-  wave_count(&c->pairs_applied, applied);
-  wave_count(&c->pairs_excluded, excluded);
-}
-
 // Mark every block of the frame touched (once) and set the band's cleared bits.
 __global__ void __launch_bounds__(kThreads)
 k_touch_band(int64_t n, Params p, MapDev m, FrameScratch fs, FrameCounters *c, int32_t frame) {
@@ -293,8 +243,12 @@ k_touch_band(int64_t n, Params p, MapDev m, FrameScratch fs, FrameCounters *c, i
       for (int i = 0; i < ns; ++i) {
         int32_t s = fs.span[r * kMaxSpan + i];
         int32_t id = s >= 0 ? m.h.vals[s] : -1;
-        if (id >= 0 && atomicExch(&m.touched[id], frame) != frame)
-          fs.touched[atomicAdd(&c->n_touched, 1)] = id;
+        if (id >= 0 && atomicExch(&m.touched[id], frame) != frame) {
+          int pos = atomicAdd(&c->n_touched, 1);
+          fs.touched[pos] = id;
+          m.tpos[id] = pos;
+          fs.bin_cnt[pos] = 0;
+        }
       }
       for (int j = 0; j < kMaxBand; ++j) {
         int32_t s = fs.band[2 * (r * kMaxBand + j)];
@@ -304,8 +258,12 @@ k_touch_band(int64_t n, Params p, MapDev m, FrameScratch fs, FrameCounters *c, i
         if (id < 0) continue;
         int vi = fs.band[2 * (r * kMaxBand + j) + 1];
         atomicOr(&m.clr[(int64_t)id * 16 + (vi >> 5)], 1u << (vi & 31));
-        if (atomicExch(&m.touched[id], frame) != frame)
-          fs.touched[atomicAdd(&c->n_touched, 1)] = id;
+        if (atomicExch(&m.touched[id], frame) != frame) {
+          int pos = atomicAdd(&c->n_touched, 1);
+          fs.touched[pos] = id;
+          m.tpos[id] = pos;
+          fs.bin_cnt[pos] = 0;
+        }
       }
     }
   }
@@ -410,8 +368,9 @@ __device__ void write_brick(const Params &p, MapDev m, GridDev g, int64_t id, in
                             int32_t W, uint8_t *code) {
   int t = threadIdx.x;
   bool cl = (m.clr[id * 16 + (t >> 5)] >> (t & 31)) & 1u;
-  code[t] = (uint8_t)voxel_code(p, S, W, cl);
-  __syncthreads();
+  uint32_t cd = voxel_code(p, S, W, cl);
+  code[t] = (uint8_t)cd;
+  int any_occ = __syncthreads_or((int)(cd & 1u));
   int32_t b[3];
   unpack_key(m.bkey[id], b[0], b[1], b[2]);
   int x = b[0] - g.g0[0], y = b[1] - g.g0[1], z = b[2] - g.g0[2];
@@ -425,25 +384,136 @@ __device__ void write_brick(const Params &p, MapDev m, GridDev g, int64_t id, in
       g.pred[brick * 32 + t] = w;
     } else if (t < 48) {
       g.surf[brick * 16 + (t - 32)] = m.surf[id * 16 + (t - 32)];
+    } else if (t == 48) {
+      uint32_t bit = 1u << (brick & 31);
+      if (any_occ)
+        atomicOr(&g.occ_any[brick >> 5], bit);
+      else
+        atomicAnd(&g.occ_any[brick >> 5], ~bit);
     }
   }
   __syncthreads();
 }
 
+// ---------------------------------------------------- binned integration
+// Section 3.2 as a gather: every (return, block of its cube) pair is binned
+// by block; one workgroup per touched block then gives each thread one voxel,
+// which sums the clamped distances of the block's returns whose cube contains
+// it (cone test, isqrt) in registers.  The fold with the weight cap
+// (Section 3.6) and the block's brick follow in the same workgroup, so the
+// map sees one plain store per voxel and no atomics.
+__global__ void __launch_bounds__(kThreads)
+k_bin_count(int64_t n, Params p, MapDev m, FrameScratch fs) {
+  int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (r >= n) return;
+  int4 P = fs.P[r];
+  if (P.w == 0) return;
+  Span sp = cube_span(P, p.R);
+  int ns = sp.n[0] * sp.n[1] * sp.n[2];
+  for (int i = 0; i < ns; ++i) {
+    int32_t s = fs.span[r * kMaxSpan + i];
+    int32_t id = s >= 0 ? m.h.vals[s] : -1;
+    if (id >= 0) atomicAdd(&fs.bin_cnt[m.tpos[id]], 1);
+  }
+}
+
+// Exclusive prefix of the bin counts (one workgroup).
+__global__ void __launch_bounds__(1024) k_bin_scan(FrameScratch fs, FrameCounters *c) {
+  __shared__ int part[1024];
+  const int nt = c->n_touched;
+  const int t = threadIdx.x;
+  const int seg = (nt + 1023) / 1024;
+  const int lo = t * seg < nt ? t * seg : nt;
+  const int hi = lo + seg < nt ? lo + seg : nt;
+  int sum = 0;
+  for (int j = lo; j < hi; ++j) sum += fs.bin_cnt[j];
+  part[t] = sum;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    int v = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int run = part[t] - sum;
+  for (int j = lo; j < hi; ++j) {
+    fs.bin_off[j] = run;
+    fs.bin_fill[j] = run;
+    run += fs.bin_cnt[j];
+  }
+  if (t == 1023) fs.bin_off[nt] = part[1023];
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_bin_fill(int64_t n, Params p, MapDev m, FrameScratch fs) {
+  int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (r >= n) return;
+  int4 P = fs.P[r];
+  if (P.w == 0) return;
+  Span sp = cube_span(P, p.R);
+  int ns = sp.n[0] * sp.n[1] * sp.n[2];
+  for (int i = 0; i < ns; ++i) {
+    int32_t s = fs.span[r * kMaxSpan + i];
+    int32_t id = s >= 0 ? m.h.vals[s] : -1;
+    if (id >= 0) fs.bin_list[atomicAdd(&fs.bin_fill[m.tpos[id]], 1)] = (int32_t)r;
+  }
+}
+
 __global__ void __launch_bounds__(kBlockVox)
-k_fold(Params p, MapDev m, FrameScratch fs, FrameCounters *c, GridDev g) {
+k_integrate_fold(int3 Q, Params p, MapDev m, FrameScratch fs, FrameCounters *c, GridDev g) {
+  __shared__ int4 tile[kBlockVox];
   __shared__ uint8_t code[kBlockVox];
-  int nt = c->n_touched;
-  int folded = 0;
+  const int nt = c->n_touched;
+  const int t = threadIdx.x;
+  const int64_t lo_clamp = p.clamp_neg ? -(int64_t)p.tau_u : 0;
+  unsigned applied = 0, excluded = 0, folded = 0;
   for (int i = blockIdx.x; i < nt; i += gridDim.x) {
-    int64_t id = fs.touched[i];
-    int64_t v = id * kBlockVox + threadIdx.x;
-    unsigned long long d = m.delta[v];
+    const int64_t id = fs.touched[i];
+    int32_t b[3];
+    unpack_key(m.bkey[id], b[0], b[1], b[2]);
+    const int vx = 8 * b[0] + (t & 7), vy = 8 * b[1] + ((t >> 3) & 7), vz = 8 * b[2] + (t >> 6);
+    const int64_t cq0 = 256 * (int64_t)vx + 128 - Q.x;  // voxel centre - sensor
+    const int64_t cq1 = 256 * (int64_t)vy + 128 - Q.y;
+    const int64_t cq2 = 256 * (int64_t)vz + 128 - Q.z;
+    const int64_t dist_c = isqrt64(cq0 * cq0 + cq1 * cq1 + cq2 * cq2);
+    const int beg = fs.bin_off[i], end = fs.bin_off[i + 1];
+    int64_t dS = 0;
+    int dW = 0;
+    for (int tb = beg; tb < end; tb += kBlockVox) {
+      __syncthreads();
+      if (tb + t < end) tile[t] = fs.P[fs.bin_list[tb + t]];
+      __syncthreads();
+      const int cnt = end - tb < kBlockVox ? end - tb : kBlockVox;
+      for (int j = 0; j < cnt; ++j) {
+        const int4 P = tile[j];
+        int ex = vx - (P.x >> 8), ey = vy - (P.y >> 8), ez = vz - (P.z >> 8);
+        ex = ex < 0 ? -ex : ex;
+        ey = ey < 0 ? -ey : ey;
+        ez = ez < 0 ? -ez : ez;
+        if (ex > p.R || ey > p.R || ez > p.R) continue;
+        const int64_t a0 = 256 * (int64_t)vx + 128 - P.x;
+        const int64_t a1 = 256 * (int64_t)vy + 128 - P.y;
+        const int64_t a2 = 256 * (int64_t)vz + 128 - P.z;
+        const int64_t b0 = (int64_t)P.x - Q.x, b1 = (int64_t)P.y - Q.y, b2 = (int64_t)P.z - Q.z;
+        const int64_t ab = a0 * b0 + a1 * b1 + a2 * b2;
+        const int64_t aa = a0 * a0 + a1 * a1 + a2 * a2;
+        const int64_t bb = b0 * b0 + b1 * b1 + b2 * b2;
+        // behind the return within the cos > 0.95 cone: 400 (a.b)^2 > 361 |a|^2 |b|^2
+        if (ab > 0 && (__int128)400 * ab * ab > (__int128)361 * aa * bb) {
+          ++excluded;
+          continue;
+        }
+        ++applied;
+        int64_t d = (int64_t)P.w - dist_c;
+        d = d < lo_clamp ? lo_clamp : (d > p.tau_u ? p.tau_u : d);
+        dS += d;
+        ++dW;
+      }
+    }
+    const int64_t v = id * kBlockVox + t;
     int32_t S = m.S[v];
     int32_t W = m.W[v];
-    if (d != 0) {
-      int32_t dS = (int32_t)(uint32_t)d;
-      int64_t dW = ((int64_t)d - dS) >> 32;
+    if (dW > 0) {
       int64_t S2 = (int64_t)S + dS, W2 = (int64_t)W + dW;
       if (W2 > p.cap) {
         S2 = div_floor(S2 * p.cap, W2);
@@ -453,14 +523,21 @@ k_fold(Params p, MapDev m, FrameScratch fs, FrameCounters *c, GridDev g) {
       W = (int32_t)W2;
       m.S[v] = S;
       m.W[v] = (uint16_t)W;
-      m.delta[v] = 0;
       ++folded;
     }
     write_brick(p, m, g, id, S, W, code);
   }
-  unsigned long long s = folded;
-  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor((unsigned)s, off);
-  if (lane_id() == 0 && s) atomicAdd(&c->voxels_folded, s);
+  unsigned long long sa = applied, se = excluded, sf = folded;
+  for (int off = 32; off >= 1; off >>= 1) {
+    sa += __shfl_xor((unsigned)sa, off);
+    se += __shfl_xor((unsigned)se, off);
+    sf += __shfl_xor((unsigned)sf, off);
+  }
+  if (lane_id() == 0) {
+    if (sa) atomicAdd(&c->pairs_applied, sa);
+    if (se) atomicAdd(&c->pairs_excluded, se);
+    if (sf) atomicAdd(&c->voxels_folded, sf);
+  }
 }
 
 __global__ void __launch_bounds__(kBlockVox)
@@ -477,6 +554,7 @@ __global__ void k_grid_fill(GridDev g, int64_t nbricks) {
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t j = i; j < nbricks * 32; j += stride) g.pred[j] = kUnknownWord;
   for (int64_t j = i; j < nbricks * 16; j += stride) g.surf[j] = 0u;
+  for (int64_t j = i; j < (nbricks + 31) / 32; j += stride) g.occ_any[j] = 0u;
 }
 
 inline unsigned grid_for(int64_t threads) {
@@ -504,11 +582,18 @@ void launch_commit_blocks(MapDev m, FrameCounters *c, hipStream_t s) {
 }
 
 void launch_integrate(int64_t n, int3 Q, const Params &p, MapDev m, FrameScratch fs,
-                      FrameCounters *c, hipStream_t s) {
-  int64_t D = 2 * p.R + 1;
-  if (n > 0)
-    hipLaunchKernelGGL(k_integrate, dim3(grid_for(n * D * D * D)), dim3(kThreads), 0, s, n, Q,
-                       p, m, fs, c);
+                      FrameCounters *c, GridDev g, int64_t max_touched, hipStream_t s) {
+  if (n > 0) {
+    hipLaunchKernelGGL(k_bin_count, dim3(grid_for(n)), dim3(kThreads), 0, s, n, p, m, fs);
+    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, s, fs, c);
+    hipLaunchKernelGGL(k_bin_fill, dim3(grid_for(n)), dim3(kThreads), 0, s, n, p, m, fs);
+  } else {
+    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, s, fs, c);
+  }
+  int64_t wg = max_touched < 8192 ? max_touched : 8192;
+  if (wg > 0)
+    hipLaunchKernelGGL(k_integrate_fold, dim3((unsigned)wg), dim3(kBlockVox), 0, s, Q, p, m, fs,
+                       c, g);
 }
 
 void launch_touch_band(int64_t n, const Params &p, MapDev m, FrameScratch fs,
@@ -534,13 +619,6 @@ void launch_points_view(int64_t n, int3 Q, const Params &p, PointsDev pts, Frame
   if (n > 0)
     hipLaunchKernelGGL(k_points_view, dim3(grid_for(n)), dim3(kThreads), 0, s, n, Q, p, pts,
                        fs, frame);
-}
-
-void launch_fold(const Params &p, MapDev m, FrameScratch fs, FrameCounters *c, GridDev g,
-                 int64_t max_touched, hipStream_t s) {
-  int64_t wg = max_touched < 8192 ? max_touched : 8192;
-  if (wg > 0)
-    hipLaunchKernelGGL(k_fold, dim3((unsigned)wg), dim3(kBlockVox), 0, s, p, m, fs, c, g);
 }
 
 void launch_grid_fill(GridDev g, hipStream_t s) {

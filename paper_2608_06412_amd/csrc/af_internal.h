@@ -2,15 +2,16 @@
 //
 // Map: open-addressing hash of 8^3 voxel blocks (block key -> block id) over a
 // block pool stored structure-of-arrays: S (int32) and W (uint16) per voxel,
-// ray-cleared and surface bits (16 x uint32 per block), and a per-frame
-// accumulator of 64-bit packed (W << 32) + S sums.  Integer sums make the
-// result independent of the order in which returns are applied.
+// ray-cleared and surface bits (16 x uint32 per block).  A frame's
+// contributions are summed per voxel in integers, so the result does not
+// depend on the order in which returns are applied.
 //
 // Scoring reads a dense brick grid derived from the map after every fold: per
 // 8^3 block position inside the bounding box of all blocks, 512 two-bit codes
 // (bit 0: TSDF < r_c, bit 1: unknown and not ray-cleared) in 32 words, plus
-// the 512 surface bits in 16 words.  Positions outside the grid were never
-// touched and read as unknown, not cleared.
+// the 512 surface bits in 16 words, and one bit per brick telling whether any
+// of its voxels has TSDF < r_c.  Positions outside the grid were never touched
+// and read as unknown, not cleared.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -81,8 +82,8 @@ struct MapDev {
   uint16_t *W;                   // [max_blocks * 512]
   uint32_t *clr;                 // [max_blocks * 16]
   uint32_t *surf;                // [max_blocks * 16]
-  unsigned long long *delta;     // [max_blocks * 512]
   int32_t *touched;              // [max_blocks] last frame that touched the block
+  int32_t *tpos;                 // [max_blocks] position in that frame's touched list
   int32_t *n_blocks;             // device counter
   int64_t max_blocks;
 };
@@ -114,12 +115,17 @@ struct FrameScratch {
   int64_t *new_keys;  // [cap] new point keys
   int32_t *new_kslot; // [cap] their hash slots
   int32_t *touched;   // [cap * (kMaxSpan + kMaxBand)] touched block ids
+  int32_t *bin_cnt;   // [cap * (kMaxSpan + kMaxBand)] returns per touched block
+  int32_t *bin_off;   // [cap * (kMaxSpan + kMaxBand) + 1] their prefix
+  int32_t *bin_fill;  // [cap * (kMaxSpan + kMaxBand)] insertion cursors
+  int32_t *bin_list;  // [cap * kMaxSpan] return ids grouped by block
   int64_t cap;
 };
 
 struct GridDev {
   uint32_t *pred;     // [nbricks * 32]
   uint32_t *surf;     // [nbricks * 16]
+  uint32_t *occ_any;  // [ceil(nbricks / 32)] brick holds a voxel with TSDF < r_c
   int32_t g0[3];      // block coordinate of brick (0,0,0)
   int32_t gd[3];      // bricks per axis
 };
@@ -173,7 +179,7 @@ void launch_assign_blocks(MapDev m, FrameScratch fs, FrameCounters *c, int32_t f
                           hipStream_t s);
 void launch_commit_blocks(MapDev m, FrameCounters *c, hipStream_t s);
 void launch_integrate(int64_t n, int3 Q, const Params &p, MapDev m, FrameScratch fs,
-                      FrameCounters *c, hipStream_t s);
+                      FrameCounters *c, GridDev g, int64_t max_touched, hipStream_t s);
 void launch_touch_band(int64_t n, const Params &p, MapDev m, FrameScratch fs,
                        FrameCounters *c, int32_t frame, hipStream_t s);
 void launch_points_append(int64_t n, MapDev m, PointsDev pts, FrameScratch fs,
@@ -181,8 +187,6 @@ void launch_points_append(int64_t n, MapDev m, PointsDev pts, FrameScratch fs,
 void launch_commit_points(PointsDev pts, FrameCounters *c, hipStream_t s);
 void launch_points_view(int64_t n, int3 Q, const Params &p, PointsDev pts,
                         FrameScratch fs, int32_t frame, hipStream_t s);
-void launch_fold(const Params &p, MapDev m, FrameScratch fs, FrameCounters *c,
-                 GridDev g, int64_t max_touched, hipStream_t s);
 void launch_grid_fill(GridDev g, hipStream_t s);
 void launch_grid_rebuild(const Params &p, MapDev m, GridDev g, int64_t n_blocks,
                          hipStream_t s);
@@ -195,7 +199,9 @@ void launch_normals(const Params &p, MapDev m, PointsDev pts, GridDev g,
                     int64_t n_points, hipStream_t s);
 void launch_mask(const Params &p, PointsDev pts, ToolDev t, int64_t n_points,
                  hipStream_t s);
-void launch_score(const Params &p, MapDev m, PointsDev pts, ToolDev t, GridDev g,
-                  int64_t n_points, hipStream_t s);
+void launch_score(const Params &p, PointsDev pts, ToolDev t, GridDev g, int64_t n_points,
+                  int variant, unsigned *work, hipStream_t s);
+int score_variants();
+const char *score_variant_name(int v);
 
 }  // namespace af

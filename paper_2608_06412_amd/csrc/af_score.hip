@@ -212,66 +212,107 @@ __device__ inline int nth_bit(uint64_t m, int r) {
   return __ffsll((long long)m) - 1;
 }
 
-constexpr int kScoreThreads = 1024;
-constexpr int kScoreWaves = kScoreThreads / 64;
-constexpr int kLdsK = 256;   // orientations whose first table chunk lives in LDS
+// Hit test of one table entry at point s: arm samples (NEAR) hit on TSDF < r_c
+// or unknown-and-not-cleared; body and corridor entries hit on TSDF < r_c
+// only.  With OCC, a brick without any voxel below r_c answers body and
+// corridor entries from its occupancy bit.
+template <int OCC>
+__device__ inline bool entry_hits(const GridDev &g, const int32_t s[3], uint32_t ent) {
+  const int cls = entry_cls(ent);
+  const int x = s[0] + entry_x(ent), y = s[1] + entry_y(ent), z = s[2] + entry_z(ent);
+  const int64_t b = brick_index(g, x, y, z);
+  if (b < 0) return cls == AF_CLS_NEAR;
+  const int lin = (x & 7) | ((y & 7) << 3) | ((z & 7) << 6);
+  if (OCC && cls != AF_CLS_NEAR && !((g.occ_any[b >> 5] >> (b & 31)) & 1u)) return false;
+  const uint32_t code = (g.pred[b * 32 + (lin >> 4)] >> (2 * (lin & 15))) & 3u;
+  return cls == AF_CLS_NEAR ? code != 0u : (code & 1u) != 0u;
+}
 
-// One orientation of one point, lanes over table entries in order; returns
-// true when free.  `lookups` counts entries up to the deciding one.  The first
-// 64 entries of orientations below kLdsK come from LDS.
-__device__ inline bool orientation_free(const Params &p, const ToolDev &t, const GridDev &g,
-                                        const int32_t s[3], int k, const uint32_t *s_begin,
-                                        const uint32_t *s_first, int kc, uint64_t &lookups) {
-  const uint32_t b = k < kc ? s_begin[k] : t.begin[k];
-  const uint32_t e = k < kc ? s_begin[k + 1] : t.begin[k + 1];
+// Position of the deciding hit in a chunk (an arm/corridor hit, or the
+// need-th body hit), or 64 if the chunk does not decide.
+__device__ inline int chunk_stop(uint64_t nf, uint64_t bm, int need) {
+  int stop = nf ? __ffsll((long long)nf) - 1 : 64;
+  int sb = nth_bit(bm, need);
+  return sb < stop ? sb : stop;
+}
+
+// Entries [b, e) of one orientation after its first chunk, UN chunks per
+// step (several gathers per lane in flight); decisions are taken chunk by
+// chunk in table order, so `lookups` stays the canonical count.
+template <int UN, int OCC>
+__device__ inline bool scan_rest(const Params &p, const ToolDev &t, const GridDev &g,
+                                 const int32_t s[3], uint32_t b, uint32_t e, int body,
+                                 uint64_t &lookups) {
   const int lane = lane_id();
-  int body = 0;
-  for (uint32_t base = b; base < e; base += 64) {
-    uint32_t idx = base + lane;
-    bool hit = false;
-    int cls = AF_CLS_BODY;
-    if (idx < e) {
-      uint32_t ent = (base == b && k < kc) ? s_first[64 * k + lane] : t.entries[idx];
-      cls = entry_cls(ent);
-      uint32_t code = code_at(g, s[0] + entry_x(ent), s[1] + entry_y(ent), s[2] + entry_z(ent));
-      hit = cls == AF_CLS_NEAR ? code != 0u : (code & 1u) != 0u;
+  for (uint32_t base = b; base < e; base += 64 * UN) {
+    bool hit[UN];
+    uint32_t ent[UN];
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+      uint32_t idx = base + 64 * u + lane;
+      ent[u] = idx < e ? t.entries[idx] : 0u;
     }
-    uint64_t nf = __ballot(hit && cls != AF_CLS_BODY);
-    uint64_t bm = __ballot(hit && cls == AF_CLS_BODY);
-    int stop = nf ? __ffsll((long long)nf) - 1 : 64;
-    int sb = nth_bit(bm, p.n_c - body);
-    stop = sb < stop ? sb : stop;
-    if (stop < 64) {
-      lookups += (uint64_t)stop + 1;
-      return false;
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+      uint32_t idx = base + 64 * u + lane;
+      hit[u] = idx < e && entry_hits<OCC>(g, s, ent[u]);
     }
-    body += __popcll(bm);
-    lookups += (e - base) < 64u ? (e - base) : 64u;
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+      const uint32_t cb = base + 64 * u;
+      uint64_t nf = __ballot(hit[u] && entry_cls(ent[u]) != AF_CLS_BODY);
+      uint64_t bm = __ballot(hit[u] && entry_cls(ent[u]) == AF_CLS_BODY);
+      if (cb >= e) break;
+      int stop = chunk_stop(nf, bm, p.n_c - body);
+      if (stop < 64) {
+        lookups += (uint64_t)stop + 1;
+        return false;
+      }
+      body += __popcll(bm);
+      lookups += (e - cb) < 64u ? (e - cb) : 64u;
+    }
   }
   return true;
 }
 
-// Persistent workgroups of 16 waves, one wave per point (grid-stride): the
-// lowest-index candidate orientation that is free labels the point
-// accessible.
-__global__ void __launch_bounds__(kScoreThreads)
-k_score(Params p, MapDev m, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t mw) {
-  __shared__ uint32_t s_begin[kLdsK + 1];
-  __shared__ uint32_t s_first[kLdsK * 64];
-  const int kc = t.K < kLdsK ? t.K : kLdsK;
-  for (int j = threadIdx.x; j <= kc; j += kScoreThreads) s_begin[j] = t.begin[j];
-  __syncthreads();
-  for (int j = threadIdx.x; j < kc * 64; j += kScoreThreads) {
-    uint32_t pos = s_begin[j >> 6] + (uint32_t)(j & 63);
-    s_first[j] = pos < s_begin[(j >> 6) + 1] ? t.entries[pos] : 0u;
+// One wave per point: the lowest-index candidate orientation that is free
+// labels the point accessible.  Persistent workgroups of NT threads take
+// points by grid stride (DYN = 0) or in batches of 16 from a counter
+// (DYN = 1).  The first chunks of the next AH candidates are read together
+// (they decide most blocked orientations); a candidate they leave undecided
+// is finished before the next one is looked at.  With LK > 0 the table
+// begin offsets and the first 64 entries of the first LK orientations are
+// staged in LDS.
+template <int NT, int LK, int AH, int UN, int OCC, int DYN>
+__global__ void __launch_bounds__(NT)
+k_score(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t mw,
+        unsigned *work) {
+  constexpr int NW = NT / 64;
+  __shared__ uint32_t s_begin[LK > 0 ? LK + 1 : 1];
+  __shared__ uint32_t s_first[LK > 0 ? LK * 64 : 1];
+  const int kc = LK > 0 ? (t.K < LK ? t.K : LK) : 0;
+  if (LK > 0) {
+    for (int j = threadIdx.x; j <= kc; j += NT) s_begin[j] = t.begin[j];
+    __syncthreads();
+    for (int j = threadIdx.x; j < kc * 64; j += NT) {
+      uint32_t pos = s_begin[j >> 6] + (uint32_t)(j & 63);
+      s_first[j] = pos < s_begin[(j >> 6) + 1] ? t.entries[pos] : 0u;
+    }
+    __syncthreads();
   }
-  __syncthreads();
   const int lane = lane_id();
   const int64_t wave0 =
-      (int64_t)blockIdx.x * kScoreWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t nwaves = (int64_t)gridDim.x * kScoreWaves;
+      (int64_t)blockIdx.x * NW + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t nwaves = (int64_t)gridDim.x * NW;
   uint64_t conf = 0, acc = 0, blk = 0, nocand = 0, tests = 0, lookups = 0;
-  for (int64_t i = wave0; i < n; i += nwaves) {
+  int64_t i = wave0, batch_end = wave0 + 1;
+  if (DYN) {
+    unsigned got = 0;
+    if (lane == 0) got = atomicAdd(work, 16u);
+    i = (int64_t)__builtin_amdgcn_readfirstlane(__shfl(got, 0));
+    batch_end = i + 16;
+  }
+  while (i < n) {
     int hn = __builtin_amdgcn_readfirstlane(pts.has_normal[i]);
     uint8_t label;
     int16_t ff = -1;
@@ -282,20 +323,51 @@ k_score(Params p, MapDev m, PointsDev pts, ToolDev t, GridDev g, int64_t n, int3
       int32_t s[3];
       unpack_key(pts.key[i], s[0], s[1], s[2]);
       label = AF_NO_CANDIDATE;
-      for (int w = 0; w < mw && ff < 0; ++w) {
-        uint64_t word = t.mask[i * mw + w];
-        while (word) {
-          int k = 64 * w + (__ffsll((long long)word) - 1);
+      int w = 0;
+      uint64_t word = mw > 0 ? t.mask[i * mw] : 0;
+      while (ff < 0) {
+        int ks[AH];
+        int nk = 0;
+        while (nk < AH) {
+          while (!word && ++w < mw) word = t.mask[i * mw + w];
+          if (!word) break;
+          ks[nk++] = 64 * w + (__ffsll((long long)word) - 1);
           word &= word - 1;
-          label = AF_BLOCKED;
+        }
+        if (nk == 0) break;
+        label = AF_BLOCKED;
+        uint32_t bs[AH], es[AH], ent[AH];
+        bool hit[AH];
+#pragma unroll
+        for (int a = 0; a < AH; ++a) {
+          const int k = a < nk ? ks[a] : ks[0];
+          const bool cached = LK > 0 && k < kc;
+          bs[a] = cached ? s_begin[k] : t.begin[k];
+          es[a] = cached ? s_begin[k + 1] : t.begin[k + 1];
+          const uint32_t idx = bs[a] + lane;
+          ent[a] = idx < es[a] ? (cached ? s_first[64 * k + lane] : t.entries[idx]) : 0u;
+        }
+#pragma unroll
+        for (int a = 0; a < AH; ++a)
+          hit[a] = a < nk && bs[a] + lane < es[a] && entry_hits<OCC>(g, s, ent[a]);
+#pragma unroll
+        for (int a = 0; a < AH; ++a) {
+          uint64_t nf = __ballot(hit[a] && entry_cls(ent[a]) != AF_CLS_BODY);
+          uint64_t bm = __ballot(hit[a] && entry_cls(ent[a]) == AF_CLS_BODY);
+          if (a >= nk || ff >= 0) continue;
           ++tests;
-          if (orientation_free(p, t, g, s, k, s_begin, s_first, kc, lookups)) {
-            label = AF_ACCESSIBLE;
-            ff = (int16_t)k;
-            break;
+          int stop = chunk_stop(nf, bm, p.n_c);
+          if (stop < 64) {
+            lookups += (uint64_t)stop + 1;
+            continue;
           }
+          const uint32_t n0 = es[a] - bs[a] < 64u ? es[a] - bs[a] : 64u;
+          lookups += n0;
+          if (scan_rest<UN, OCC>(p, t, g, s, bs[a] + n0, es[a], __popcll(bm), lookups))
+            ff = (int16_t)ks[a];
         }
       }
+      if (ff >= 0) label = AF_ACCESSIBLE;
       acc += label == AF_ACCESSIBLE;
       blk += label == AF_BLOCKED;
       nocand += label == AF_NO_CANDIDATE;
@@ -303,6 +375,16 @@ k_score(Params p, MapDev m, PointsDev pts, ToolDev t, GridDev g, int64_t n, int3
     if (lane == 0) {
       t.label[i] = label;
       t.first_free[i] = ff;
+    }
+    if (DYN) {
+      if (++i >= batch_end) {
+        unsigned got = 0;
+        if (lane == 0) got = atomicAdd(work, 16u);
+        i = (int64_t)__builtin_amdgcn_readfirstlane(__shfl(got, 0));
+        batch_end = i + 16;
+      }
+    } else {
+      i += nwaves;
     }
   }
   if (lane == 0) {
@@ -314,6 +396,35 @@ k_score(Params p, MapDev m, PointsDev pts, ToolDev t, GridDev g, int64_t n, int3
     if (lookups) atomicAdd(&t.counters->canonical_lookups, (unsigned long long)lookups);
   }
 }
+
+using ScoreKernel = void (*)(Params, PointsDev, ToolDev, GridDev, int64_t, int32_t, unsigned *);
+
+struct ScoreVariant {
+  ScoreKernel fn;
+  int threads;
+  const char *name;
+};
+
+// The tunable score configurations (identical results; speed only).
+const ScoreVariant kVariants[] = {
+    {k_score<256, 0, 1, 1, 0, 0>, 256, "wg256 ahead1 unroll1"},
+    {k_score<256, 0, 1, 1, 1, 0>, 256, "wg256 ahead1 unroll1 occ"},
+    {k_score<256, 0, 2, 2, 1, 0>, 256, "wg256 ahead2 unroll2 occ"},
+    {k_score<256, 0, 4, 4, 1, 0>, 256, "wg256 ahead4 unroll4 occ"},
+    {k_score<256, 0, 2, 2, 1, 1>, 256, "wg256 ahead2 unroll2 occ dyn"},
+    {k_score<512, 128, 2, 2, 1, 0>, 512, "wg512 lds128 ahead2 unroll2 occ"},
+    {k_score<1024, 256, 4, 4, 1, 0>, 1024, "wg1024 lds256 ahead4 unroll4 occ"},
+    {k_score<1024, 256, 1, 1, 0, 0>, 1024, "wg1024 lds256 ahead1 unroll1"},
+    {k_score<256, 0, 1, 4, 1, 0>, 256, "wg256 ahead1 unroll4 occ"},
+    {k_score<256, 0, 4, 1, 0, 0>, 256, "wg256 ahead4 unroll1"},
+    {k_score<256, 0, 2, 1, 0, 1>, 256, "wg256 ahead2 unroll1 dyn"},
+    {k_score<512, 0, 2, 2, 0, 0>, 512, "wg512 ahead2 unroll2"},
+};
+constexpr int kNumVariants = (int)(sizeof(kVariants) / sizeof(kVariants[0]));
+int g_resident[kNumVariants];   // workgroups per CU, from the occupancy query
+int g_num_cu = 0;
+
+__global__ void k_zero(unsigned *w) { *w = 0u; }
 
 bool g_tables_ready = false;
 
@@ -356,14 +467,37 @@ void launch_mask(const Params &p, PointsDev pts, ToolDev t, int64_t n, hipStream
                      s, p, pts, t, n, mw);
 }
 
-void launch_score(const Params &p, MapDev m, PointsDev pts, ToolDev t, GridDev g, int64_t n,
-                  hipStream_t s) {
+int score_variants() { return kNumVariants; }
+
+const char *score_variant_name(int v) {
+  return v >= 0 && v < kNumVariants ? kVariants[v].name : "";
+}
+
+void launch_score(const Params &p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int variant,
+                  unsigned *work, hipStream_t s) {
   int32_t mw = (t.K + 63) / 64;
   if (n <= 0) return;
-  int64_t wg = (n + kScoreWaves - 1) / kScoreWaves;
-  if (wg > 512) wg = 512;   // two resident workgroups per CU
-  hipLaunchKernelGGL(k_score, dim3((unsigned)wg), dim3(kScoreThreads), 0, s, p, m, pts, t, g, n,
-                     mw);
+  if (variant < 0 || variant >= kNumVariants) variant = 0;
+  const ScoreVariant &v = kVariants[variant];
+  if (g_num_cu == 0) {
+    int dev = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&g_num_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (g_num_cu <= 0) g_num_cu = 256;
+  }
+  if (g_resident[variant] == 0) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, v.fn, v.threads, 0) != hipSuccess ||
+        per_cu <= 0)
+      per_cu = 1;
+    g_resident[variant] = per_cu;
+  }
+  const int64_t nw = v.threads / 64;
+  int64_t wg = (int64_t)g_resident[variant] * g_num_cu;
+  int64_t need = (n + nw - 1) / nw;
+  if (wg > need) wg = need;
+  hipLaunchKernelGGL(k_zero, dim3(1), dim3(1), 0, s, work);
+  hipLaunchKernelGGL(v.fn, dim3((unsigned)wg), dim3(v.threads), 0, s, p, pts, t, g, n, mw, work);
 }
 
 }  // namespace af

@@ -126,6 +126,30 @@ def test_score_stats(tiny_run):
     assert {k: g[k] for k in SCORE_KEYS} == {k: o[k] for k in SCORE_KEYS}
 
 
+def test_all_score_variants(tiny_run):
+    """Every scoring configuration (workgroup size, LDS staging, look-ahead,
+    unrolling, occupancy skip, dynamic fetch) gives the oracle's labels and
+    canonical counts; the autotuner keeps one of them."""
+    w, ctx, orc, _ = tiny_run
+    keys, lbl, ff = orc.labels(len(w.rot), ctx.read_labels(0)["key"])
+    o = orc.score_stats()
+    names = ctx.score_variants()
+    assert len(names) >= 8
+    for v in range(len(names)):
+        ctx.set_score_variant(v)
+        ctx.score_points(0)
+        lab = ctx.read_labels(0)
+        assert np.array_equal(lab["label"], lbl), names[v]
+        assert np.array_equal(lab["first_free"].astype(np.int32), ff), names[v]
+        g = ctx.score_stats(0)
+        assert {k: g[k] for k in SCORE_KEYS} == {k: o[k] for k in SCORE_KEYS}, names[v]
+    best, ms = ctx.tune_score(0, reps=2)
+    assert 0 <= best < len(names) and ctx.score_variant() == best
+    assert all(m > 0 for m in ms)
+    ctx.score_points(0)
+    assert np.array_equal(ctx.read_labels(0)["label"], lbl)
+
+
 def test_rescore_is_stateless(tiny_run):
     """Scoring twice gives the same labels (no state carried between calls)."""
     w, ctx, orc, _ = tiny_run

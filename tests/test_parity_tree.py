@@ -1,0 +1,127 @@
+"""GPU parity at the real shape of the tree workload (20,000 returns per frame,
+1 cm voxels, 4 cm truncation, saw box with a 1 m corridor, K = 256), in the
+launch configuration the benchmark uses (the autotuned scoring kernel).
+
+The oracle integrates the same frames restricted to a region of interest
+(ROI) around a cluster of sampled points; every voxel's state depends only on
+the returns near it, so inside the ROI the oracle's TSDF is exact.  The ROI
+reaches further than any tool lookup or normal neighbourhood of the sampled
+points.  Checked bit for bit: every voxel of the ROI (S, W, cleared), and the
+sampled points' viewpoints, normals, candidate masks, labels and first free
+orientations.  Sampled points are voxels of seeded-random input returns."""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+N_FRAMES = 40
+N_SAMPLE = 250
+
+
+@pytest.fixture(scope="module")
+def tree_run(synth_mod, oracle_mod):
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2608_06412_amd import Context, default_config
+    w = synth_mod.tree(n_frames=N_FRAMES)
+    frames = w.frames(N_FRAMES)
+    cfg = default_config(w.voxel, w.trunc, r_c=w.r_c, max_blocks=1 << 16, max_points=1 << 21,
+                         max_orientations=256, max_tools=1)
+    ctx = Context(cfg)
+    ctx.set_tool_kernels(0, w.tool, w.rot)
+    for f in frames:
+        ctx.integrate_frame(torch.from_numpy(f.xyz).cuda(), f.origin, f.frame_id)
+    print("gpu integrated %d frames, %d points" % (N_FRAMES, ctx.num_points()), flush=True)
+    best, ms = ctx.tune_score(0, reps=1)
+    ctx.score_points(0)
+    print("tuned variant", ctx.score_variants()[best], flush=True)
+
+    # sampled points: voxels of returns near a seeded centre return
+    rng = np.random.default_rng(2024)
+    allxyz = np.concatenate([f.xyz for f in frames[N_FRAMES // 2:]]).astype(np.float64)
+    c = allxyz[rng.integers(len(allxyz))]
+    near = allxyz[np.linalg.norm(allxyz - c, axis=1) < 0.35]
+    pick = near[rng.choice(len(near), size=min(4 * N_SAMPLE, len(near)), replace=False)]
+    ijk = np.floor(pick / w.voxel).astype(np.int64)
+    keys = np.unique(oracle_mod.pack_keys(ijk))[:N_SAMPLE]
+    vox = oracle_mod.unpack_keys(keys)
+    reach = int(math.ceil((w.tool.length + w.tool.corridor) / w.voxel)) + 8
+    lo = vox.min(0) - reach
+    hi = vox.max(0) + reach
+    orc = oracle_mod.Oracle(voxel=w.voxel, trunc=w.trunc, r_c=w.r_c)
+    orc.set_roi(lo, hi)
+    for f in frames:
+        orc.integrate_frame(f.xyz, f.origin, f.frame_id)
+    # keep the sampled voxels that are surface points (a return's float
+    # coordinate divided by v can fall in the neighbour of its fixed-point voxel)
+    keys = keys[np.isin(keys, orc.read_points()["key"])]
+    assert len(keys) > N_SAMPLE // 2
+    orc.set_tool(0, w.tool, w.rot)
+    orc.score(0, keys=keys)
+    print("oracle ROI", lo.tolist(), hi.tolist(), flush=True)
+    return w, ctx, orc, keys, lo, hi
+
+
+def test_tsdf_in_roi(tree_run, oracle_mod):
+    w, ctx, orc, keys, lo, hi = tree_run
+    gk, gS, gW, gc = ctx.read_tsdf()
+    ijk = oracle_mod.unpack_keys(gk)
+    inside = np.all((ijk >= lo) & (ijk <= hi), axis=1)
+    ok, oS, oW, oc = orc.read_tsdf()
+    assert len(ok) > 100000
+    assert np.array_equal(gk[inside], ok)
+    assert np.array_equal(gS[inside], oS)
+    assert np.array_equal(gW[inside].astype(np.int64), oW.astype(np.int64))
+    assert np.array_equal(gc[inside], oc)
+
+
+def test_sampled_points(tree_run):
+    w, ctx, orc, keys, lo, hi = tree_run
+    pts = ctx.read_points()
+    pos = {k: i for i, k in enumerate(pts["key"].tolist())}
+    opts = orc.read_points()
+    opos = {k: i for i, k in enumerate(opts["key"].tolist())}
+    for k in keys.tolist():
+        i, j = pos[k], opos[k]
+        for name in ("first_frame", "n_vp", "vp", "sumq", "nq"):
+            assert np.array_equal(pts[name][i], opts[name][j]), (k, name)
+
+
+def test_sampled_labels_normals_masks(tree_run):
+    w, ctx, orc, keys, lo, hi = tree_run
+    K = len(w.rot)
+    lab = ctx.read_labels(0)
+    dbg = ctx.read_point_debug(0)
+    pos = {k: i for i, k in enumerate(lab["key"].tolist())}
+    seen = set()
+    for k in keys.tolist():
+        i = pos[k]
+        r = orc.point_result(k, K)
+        assert lab["label"][i] == r["label"], k
+        assert int(lab["first_free"][i]) == r["first_free"], k
+        if r["label"] != 0:
+            assert dbg["has_normal"][i] == r["has_normal"], k
+            assert np.array_equal(dbg["normal"][i].astype(np.int64), r["normal"]), k
+            assert np.array_equal(dbg["mask"][i], r["mask"]), k
+        seen.add(r["label"])
+    assert 2 in seen
+
+
+def test_whole_map_properties(tree_run):
+    """Properties that hold at any size: weights never exceed the cap,
+    every point's voxel is stored, labels are in range, first_free is set
+    exactly for accessible points and its mask bit is set."""
+    w, ctx, orc, keys, lo, hi = tree_run
+    gk, gS, gW, gc = ctx.read_tsdf()
+    assert gW.max() <= 2000 and gS.min() >= 0
+    lab = ctx.read_labels(0, with_w=True)
+    assert set(np.unique(lab["label"])) <= {0, 1, 2, 3}
+    acc = lab["label"] == 1
+    assert np.all(lab["first_free"][acc] >= 0) and np.all(lab["first_free"][~acc] == -1)
+    assert np.all((lab["w"] >= 2) == (lab["label"] != 0))
+    dbg = ctx.read_point_debug(0)
+    ff = lab["first_free"][acc].astype(np.int64)
+    words = dbg["mask"][acc][np.arange(acc.sum()), ff // 64]
+    assert np.all((words >> (ff % 64).astype(np.uint64)) & np.uint64(1) == 1)
