@@ -23,6 +23,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -35,6 +36,11 @@ METRIC = ("point×orientation tests/s + returns integrated/s; p99 frame latency 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_score_tree.json")
 SCORE_SRC = os.path.join(ROOT, "paper_2608_06412_amd", "csrc", "af_score.hip")
+# scoring configuration timed by default (the one the autotuner picks on this
+# workload); --tune re-runs the tuner after the warm-up instead
+DEFAULT_VARIANT = "fast wg256 head4 unroll2 dyn16 coarse"
+# kernels whose per-launch device time the bench reports (symbol prefixes)
+TRACE_KERNELS = ("k_score", "k_integrate_fold", "k_normals", "k_mask")
 
 
 def log(*a):
@@ -85,6 +91,34 @@ def cpu_baseline(w, frames, n_frames, n_points, seed=17):
     }
 
 
+def trace_summary(csv_path, warmup, steps):
+    """Per-launch device time of the hot kernels from a rocprofv3 kernel-trace
+    CSV of a default bench run: mean over all launches and over the timed
+    frames' launches only (one launch per frame, frames warmup..warmup+steps-1)."""
+    import csv
+    per = {}
+    with open(csv_path) as f:
+        for row in csv.DictReader(f):
+            name = row["Kernel_Name"]
+            m = re.search(r"\b(k_[A-Za-z0-9_]+)\s*[<(]", name)
+            if not m:
+                continue
+            base = "k_score" if m.group(1).startswith("k_score") else m.group(1)
+            if base not in TRACE_KERNELS:
+                continue
+            per.setdefault(base, []).append(
+                (int(row["Start_Timestamp"]), int(row["End_Timestamp"]), name))
+    out = {}
+    for base, rows in per.items():
+        rows.sort()
+        d = np.array([(e - b) / 1e6 for b, e, _ in rows])
+        timed = d[warmup:warmup + steps]
+        out[base] = {"launches": int(len(d)), "avg_ms_all": float(d.mean()),
+                     "avg_ms_timed": float(timed.mean()) if len(timed) else None,
+                     "timed_launches": int(len(timed)), "symbol": rows[0][2][:120]}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,9 +128,30 @@ def main():
     ap.add_argument("--cpu-frames", type=int, default=12)
     ap.add_argument("--cpu-points", type=int, default=1500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-tune", action="store_true")
-    ap.add_argument("--score-variant", type=int, default=None)
+    ap.add_argument("--tune", action="store_true",
+                    help="autotune the scoring kernel after the warm-up")
+    ap.add_argument("--score-variant", default=DEFAULT_VARIANT,
+                    help="scoring configuration (index or name) when not tuning")
+    ap.add_argument("--trace-summary", default=None,
+                    help="only summarise a rocprofv3 kernel_trace.csv of a bench run "
+                         "with the same --warmup/--steps")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only run a device-to-device copy of this many bytes (3 times); "
+                         "used to calibrate rocprofv3 FETCH_SIZE/WRITE_SIZE")
     args = ap.parse_args()
+    if args.trace_summary:
+        print(json.dumps(trace_summary(args.trace_summary, args.warmup, args.steps), indent=1))
+        return
+    if args.copy_probe:
+        import torch
+        n = args.copy_probe // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n * 4}))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU; this build has no multi-GPU path "
               "(see DESIGN.md for how the map would shard). Run with --gpus 1.",
@@ -128,6 +183,11 @@ def main():
     ctx.set_tool_kernels(0, w.tool, w.rot)
     Krot = len(w.rot)
 
+    names = ctx.score_variants()
+    if not args.tune:
+        v = args.score_variant
+        idx = int(v) if str(v).isdigit() else names.index(v)
+        ctx.set_score_variant(idx)
     t = time.perf_counter()
     for i in range(W):
         ctx.integrate_frame(resident[i], frames[i].origin, frames[i].frame_id)
@@ -136,19 +196,18 @@ def main():
             log("warm-up frame %d, %d points" % (i, ctx.num_points()))
     torch.cuda.synchronize()
     log("warm-up %d frames in %.1f s" % (W, time.perf_counter() - t))
-    tuning = None
-    if not args.no_tune:
+    if args.tune:
         best, ms = ctx.tune_score(0, reps=3)
-        names = ctx.score_variants()
         tuning = {"chosen": names[best], "ms": {n: round(m, 3) for n, m in zip(names, ms)},
                   "at_frame": W}
         log("score tuning at frame %d: %s" % (W, json.dumps(tuning)))
-    elif args.score_variant is not None:
-        ctx.set_score_variant(args.score_variant)
+    else:
+        tuning = {"chosen": names[ctx.score_variant()], "tuned": False}
 
     ctx.timing_enable(True)
     ctx.timing_read(reset=True)
-    tests = lookups = conf = nominal = returns = 0
+    tests = lookups = conf = nominal = returns = accessible = deep = deep_chunks = cand = 0
+    cchecks = cclear = 0
     byts = 0.0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -160,6 +219,12 @@ def main():
         lookups += st["canonical_lookups"]
         conf += st["n_confident"]
         nominal += st["n_confident"] * Krot
+        accessible += st["n_accessible"]
+        deep += st["deep_tests"]
+        deep_chunks += st["deep_chunks_max"]
+        cchecks += st["coarse_checks"]
+        cclear += st["coarse_clear"]
+        cand += st["candidate_tests"]
         byts += score_bytes(st["canonical_lookups"], st["n_confident"], Krot)
         returns += len(frames[i].xyz)
         if (i - W) % 50 == 0:
@@ -239,6 +304,11 @@ def main():
                                **kernels}.items()},
         "roofline": roofline,
         "score_tuning": tuning,
+        "score_work_per_step": {"confident_points": conf / K, "accessible_points": accessible / K,
+                                "candidate_tests": cand / K, "canonical_tests": tests / K,
+                                "canonical_lookups": lookups / K, "deep_tests": deep / K,
+                                "deep_tests_full_chunks": deep_chunks / K,
+                                "coarse_checks": cchecks / K, "coarse_clear": cclear / K},
     }
     if not args.no_cpu_baseline:
         t = time.perf_counter()

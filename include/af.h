@@ -105,6 +105,12 @@ typedef struct af_frame_stats {
 typedef struct af_score_stats {
   int64_t n_points, n_confident, n_accessible, n_blocked, n_no_candidate;
   int64_t candidate_tests, canonical_tests, canonical_lookups;
+  /* diagnostics of the two-phase scoring configurations (0 for the others):
+   * canonical tests not decided by the first table entries read per lane,
+   * and the 64-entry chunks a full scan of those tests would take; coarse
+   * corridor checks made and those that found every corridor brick clear */
+  int64_t deep_tests, deep_chunks_max;
+  int64_t coarse_checks, coarse_clear;
 } af_score_stats;
 
 /* Fill *cfg with the paper's constants for voxel size `voxel` and truncation

@@ -64,7 +64,8 @@ class ScoreStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
                 ("n_points", "n_confident", "n_accessible", "n_blocked",
                  "n_no_candidate", "candidate_tests", "canonical_tests",
-                 "canonical_lookups")]
+                 "canonical_lookups", "deep_tests", "deep_chunks_max",
+                                   "coarse_checks", "coarse_clear")]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

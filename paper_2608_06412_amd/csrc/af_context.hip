@@ -28,7 +28,7 @@ struct af_ctx {
   FrameCounters *counters;      // device
   FrameCounters *counters_host; // pinned
   std::vector<ToolDev> tools;
-  std::vector<int64_t> tool_bytes;
+  std::vector<int64_t> tool_bytes, tool_cbytes;
   uint64_t *mask;               // shared candidate-mask scratch
   unsigned *work;               // point counter of the dynamic score variants
   int score_variant;
@@ -358,6 +358,7 @@ int af_create(const af_config *cfg, af_ctx **out) {
   CREATE_ALLOC(c->mask, NP * ((cfg->max_orientations + 63) / 64));
   c->tools.assign(cfg->max_tools, ToolDev());
   c->tool_bytes.assign(cfg->max_tools, 0);
+  c->tool_cbytes.assign(cfg->max_tools, 0);
   for (auto &t : c->tools) memset(&t, 0, sizeof(t));
   if (hipHostMalloc((void **)&c->counters_host, sizeof(FrameCounters)) != hipSuccess)
     return bail(AF_ENOMEM);
@@ -437,6 +438,10 @@ int af_set_tool_kernels(af_ctx *c, int32_t tool_id, const af_tool *tool, int32_t
     dev_free(c, t.label, c->cfg.max_points);
     dev_free(c, t.first_free, sizeof(int16_t) * c->cfg.max_points);
     dev_free(c, t.counters, sizeof(ScoreCounters));
+    dev_free(c, t.far_begin, sizeof(uint32_t) * t.K);
+    dev_free(c, t.cbegin, sizeof(uint32_t) * (t.K + 1));
+    dev_free(c, t.cflag, t.K);
+    dev_free(c, t.centries, c->tool_cbytes[tool_id]);
     memset(&t, 0, sizeof(t));
   }
   ToolDev nt;
@@ -474,10 +479,28 @@ int af_set_tool_kernels(af_ctx *c, int32_t tool_id, const af_tool *tool, int32_t
   HIP_TRY(c, hipMemsetAsync(nt.label, 0, c->cfg.max_points, s));
   HIP_TRY(c, hipMemsetAsync(nt.counters, 0, sizeof(ScoreCounters), s));
   HIP_TRY(c, hipMemcpyAsync(&herr, err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  // coarse corridor lists
+  uint32_t *ccounts = nullptr;
+  ALLOC(c, nt.far_begin, K);
+  ALLOC(c, nt.cbegin, K + 1);
+  ALLOC(c, nt.cflag, K);
+  ALLOC(c, ccounts, K);
+  if (launch_table_coarse(K, nt.begin, counts, nt.entries, nt.far_begin, ccounts, nt.cbegin,
+                          nullptr, nt.cflag, 0, s) != 0)
+    return hip_check(c, "coarse count");
+  uint32_t ctotal = 0;
+  HIP_TRY(c, hipMemcpyAsync(&ctotal, nt.cbegin + K, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   HIP_TRY(c, hipStreamSynchronize(s));
+  ALLOC(c, nt.centries, ctotal);
+  if (launch_table_coarse(K, nt.begin, counts, nt.entries, nt.far_begin, ccounts, nt.cbegin,
+                          nt.centries, nt.cflag, 1, s) != 0)
+    return hip_check(c, "coarse fill");
+  HIP_TRY(c, hipStreamSynchronize(s));
+  dev_free(c, ccounts, sizeof(uint32_t) * K);
   dev_free(c, counts, sizeof(uint32_t) * 2 * K);
   dev_free(c, err, sizeof(int32_t));
   if (herr) return fail(c, AF_EINVAL, "tool table build failed (%d)", herr);
+  c->tool_cbytes[tool_id] = sizeof(uint32_t) * (int64_t)ctotal;
   nt.K = K;
   nt.mask = c->mask;
   t = nt;
@@ -833,6 +856,10 @@ int af_score_stats_get(af_ctx *c, int32_t tool_id, af_score_stats *st) {
   st->candidate_tests = (int64_t)h.candidate_tests;
   st->canonical_tests = (int64_t)h.canonical_tests;
   st->canonical_lookups = (int64_t)h.canonical_lookups;
+  st->deep_tests = (int64_t)h.deep_tests;
+  st->deep_chunks_max = (int64_t)h.deep_chunks_max;
+  st->coarse_checks = (int64_t)h.coarse_checks;
+  st->coarse_clear = (int64_t)h.coarse_clear;
   return AF_OK;
 }
 

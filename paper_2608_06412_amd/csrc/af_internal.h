@@ -67,6 +67,8 @@ struct FrameCounters {
 struct ScoreCounters {
   unsigned long long n_confident, n_accessible, n_blocked, n_no_candidate;
   unsigned long long candidate_tests, canonical_tests, canonical_lookups;
+  unsigned long long deep_tests, deep_chunks_max;  // diagnostics of the two-phase kernels
+  unsigned long long coarse_checks, coarse_clear;   // corridor brick checks, and those clear
 };
 
 struct HashTable {
@@ -139,6 +141,13 @@ struct ToolDev {
   int16_t *first_free;// [max_points]
   uint64_t *mask;     // [max_points * ceil(K/64)]
   ScoreCounters *counters;
+  // coarse corridor lists: for orientation k, the brick offsets (relative to
+  // the point's brick) that its corridor entries can fall in, for any
+  // position of the point inside its brick
+  uint32_t *far_begin;  // [K] index of the first corridor entry
+  uint32_t *cbegin;     // [K + 1]
+  uint32_t *centries;   // packed brick offsets
+  uint8_t *cflag;       // [K] 1: list valid
 };
 
 // Table entry packing: 10-bit two's complement offsets, class in bits 30-31.
@@ -194,6 +203,11 @@ void launch_grid_rebuild(const Params &p, MapDev m, GridDev g, int64_t n_blocks,
 int launch_table_build(const ToolGeom &tg, int32_t K, const double *rot_dev,
                        uint32_t *counts_dev, uint32_t *begin_dev, int32_t *err_dev,
                        uint32_t *entries_dev, int pass, hipStream_t s);
+
+int launch_table_coarse(int32_t K, const uint32_t *begin, const uint32_t *counts,
+                        const uint32_t *entries, uint32_t *far_begin, uint32_t *ccounts,
+                        uint32_t *cbegin, uint32_t *centries, uint8_t *cflag, int pass,
+                        hipStream_t s);
 
 void launch_normals(const Params &p, MapDev m, PointsDev pts, GridDev g,
                     int64_t n_points, hipStream_t s);

@@ -142,7 +142,112 @@ __global__ void k_table_scan(int32_t K, const uint32_t *counts, uint32_t *begin)
   begin[K] = acc;
 }
 
+// Coarse corridor list of orientation k: every brick offset floor((r + o)/8)
+// (r in [0, 8)^3, o a corridor entry), as a bitmap over the bounding box of
+// those offsets, compacted in linear order.  A bounding box above kCoarseBits
+// cells leaves the orientation without a list (cflag = 0).
+constexpr int kCoarseBits = 1 << 18;
+
+__global__ void __launch_bounds__(256)
+k_table_coarse(int32_t K, const uint32_t *begin, const uint32_t *counts, const uint32_t *entries,
+               uint32_t *far_begin, uint32_t *ccounts, const uint32_t *cbegin,
+               uint32_t *centries, uint8_t *cflag, int pass) {
+  __shared__ uint32_t bits[kCoarseBits / 32];
+  __shared__ int lo[3], hi[3];
+  __shared__ uint32_t part[256];
+  const int k = blockIdx.x;
+  if (k >= K) return;
+  const uint32_t fb = begin[k] + 3 + counts[2 * k], e = begin[k + 1];
+  if (threadIdx.x < 3) {
+    lo[threadIdx.x] = 1 << 20;
+    hi[threadIdx.x] = -(1 << 20);
+  }
+  __syncthreads();
+  for (uint32_t j = fb + threadIdx.x; j < e; j += 256) {
+    const uint32_t en = entries[j];
+    const int o[3] = {entry_x(en), entry_y(en), entry_z(en)};
+    for (int a = 0; a < 3; ++a) {
+      atomicMin(&lo[a], o[a] >> 3);
+      atomicMax(&hi[a], (o[a] + 7) >> 3);
+    }
+  }
+  __syncthreads();
+  const int dx = hi[0] - lo[0] + 1, dy = hi[1] - lo[1] + 1, dz = hi[2] - lo[2] + 1;
+  const bool ok = fb >= e || (int64_t)dx * dy * dz <= kCoarseBits;
+  if (pass == 0 && threadIdx.x == 0) {
+    far_begin[k] = fb;
+    cflag[k] = ok ? 1 : 0;
+  }
+  if (!ok || fb >= e) {
+    if (pass == 0 && threadIdx.x == 0) ccounts[k] = 0;
+    return;
+  }
+  const int nbits = dx * dy * dz, nwords = (nbits + 31) / 32;
+  for (int w = threadIdx.x; w < nwords; w += 256) bits[w] = 0u;
+  __syncthreads();
+  for (uint32_t j = fb + threadIdx.x; j < e; j += 256) {
+    const uint32_t en = entries[j];
+    const int o[3] = {entry_x(en), entry_y(en), entry_z(en)};
+    for (int c = 0; c < 8; ++c) {
+      const int bx = ((o[0] + ((c & 1) ? 7 : 0)) >> 3) - lo[0];
+      const int by = ((o[1] + ((c & 2) ? 7 : 0)) >> 3) - lo[1];
+      const int bz = ((o[2] + ((c & 4) ? 7 : 0)) >> 3) - lo[2];
+      const int idx = (bz * dy + by) * dx + bx;
+      atomicOr(&bits[idx >> 5], 1u << (idx & 31));
+    }
+  }
+  __syncthreads();
+  // per-thread contiguous word ranges, block prefix of their bit counts
+  const int seg = (nwords + 255) / 256;
+  const int w0 = threadIdx.x * seg < nwords ? threadIdx.x * seg : nwords;
+  const int w1 = w0 + seg < nwords ? w0 + seg : nwords;
+  uint32_t cnt = 0;
+  for (int w = w0; w < w1; ++w) cnt += __popc(bits[w]);
+  part[threadIdx.x] = cnt;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    uint32_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  if (pass == 0) {
+    if (threadIdx.x == 255) ccounts[k] = part[255];
+    return;
+  }
+  uint32_t at = cbegin[k] + part[threadIdx.x] - cnt;
+  for (int w = w0; w < w1; ++w) {
+    uint32_t m = bits[w];
+    while (m) {
+      const int b = __ffs(m) - 1;
+      m &= m - 1;
+      const int idx = 32 * w + b;
+      const int bx = idx % dx, by = (idx / dx) % dy, bz = idx / (dx * dy);
+      centries[at++] = pack_entry(bx + lo[0], by + lo[1], bz + lo[2], 0);
+    }
+  }
+}
+
+__global__ void k_coarse_scan(int32_t K, const uint32_t *ccounts, uint32_t *cbegin) {
+  uint32_t acc = 0;
+  for (int k = 0; k < K; ++k) {
+    cbegin[k] = acc;
+    acc += ccounts[k];
+  }
+  cbegin[K] = acc;
+}
+
 }  // namespace
+
+int launch_table_coarse(int32_t K, const uint32_t *begin, const uint32_t *counts,
+                        const uint32_t *entries, uint32_t *far_begin, uint32_t *ccounts,
+                        uint32_t *cbegin, uint32_t *centries, uint8_t *cflag, int pass,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_table_coarse, dim3((unsigned)K), dim3(256), 0, s, K, begin, counts, entries,
+                     far_begin, ccounts, cbegin, centries, cflag, pass);
+  if (pass == 0) hipLaunchKernelGGL(k_coarse_scan, dim3(1), dim3(1), 0, s, K, ccounts, cbegin);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
 
 int launch_table_build(const ToolGeom &tg, int32_t K, const double *rot_dev,
                        uint32_t *counts_dev, uint32_t *begin_dev, int32_t *err_dev,
