@@ -38,7 +38,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_score_tree.json")
 SCORE_SRC = os.path.join(ROOT, "paper_2608_06412_amd", "csrc", "af_score.hip")
 # scoring configuration timed by default (the one the autotuner picks on this
 # workload); --tune re-runs the tuner after the warm-up instead
-DEFAULT_VARIANT = "fast wg256 head4 unroll2 dyn16 coarse"
+DEFAULT_VARIANT = "near wg256 unroll1 dyn16 coarse4 bit"
 # kernels whose per-launch device time the bench reports (symbol prefixes)
 TRACE_KERNELS = ("k_score", "k_integrate_fold", "k_normals", "k_mask")
 
@@ -207,7 +207,7 @@ def main():
     ctx.timing_enable(True)
     ctx.timing_read(reset=True)
     tests = lookups = conf = nominal = returns = accessible = deep = deep_chunks = cand = 0
-    cchecks = cclear = 0
+    cchecks = cclear = cbody = cfar = 0
     byts = 0.0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -224,6 +224,8 @@ def main():
         deep_chunks += st["deep_chunks_max"]
         cchecks += st["coarse_checks"]
         cclear += st["coarse_clear"]
+        cbody += st["chunks_body"]
+        cfar += st["chunks_far"]
         cand += st["candidate_tests"]
         byts += score_bytes(st["canonical_lookups"], st["n_confident"], Krot)
         returns += len(frames[i].xyz)
@@ -308,7 +310,8 @@ def main():
                                 "candidate_tests": cand / K, "canonical_tests": tests / K,
                                 "canonical_lookups": lookups / K, "deep_tests": deep / K,
                                 "deep_tests_full_chunks": deep_chunks / K,
-                                "coarse_checks": cchecks / K, "coarse_clear": cclear / K},
+                                "coarse_checks": cchecks / K, "coarse_clear": cclear / K,
+                                "deep_steps_body": cbody / K, "deep_steps_corridor": cfar / K},
     }
     if not args.no_cpu_baseline:
         t = time.perf_counter()

@@ -108,9 +108,11 @@ typedef struct af_score_stats {
   /* diagnostics of the two-phase scoring configurations (0 for the others):
    * canonical tests not decided by the first table entries read per lane,
    * and the 64-entry chunks a full scan of those tests would take; coarse
-   * corridor checks made and those that found every corridor brick clear */
+   * corridor checks made and those that found every corridor brick clear;
+   * 64-entry steps the deep scans took over body and over corridor entries */
   int64_t deep_tests, deep_chunks_max;
   int64_t coarse_checks, coarse_clear;
+  int64_t chunks_body, chunks_far;
 } af_score_stats;
 
 /* Fill *cfg with the paper's constants for voxel size `voxel` and truncation

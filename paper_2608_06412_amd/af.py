@@ -65,7 +65,8 @@ class ScoreStats(ctypes.Structure):
                 ("n_points", "n_confident", "n_accessible", "n_blocked",
                  "n_no_candidate", "candidate_tests", "canonical_tests",
                  "canonical_lookups", "deep_tests", "deep_chunks_max",
-                                   "coarse_checks", "coarse_clear")]
+                                   "coarse_checks", "coarse_clear", "chunks_body",
+                                   "chunks_far")]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

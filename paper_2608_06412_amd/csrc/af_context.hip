@@ -30,6 +30,7 @@ struct af_ctx {
   std::vector<ToolDev> tools;
   std::vector<int64_t> tool_bytes, tool_cbytes;
   uint64_t *mask;               // shared candidate-mask scratch
+  uint64_t *nearp;              // shared arm-sample planes
   unsigned *work;               // point counter of the dynamic score variants
   int score_variant;
   int64_t last_frame;
@@ -143,41 +144,126 @@ int hip_check(af_ctx *c, const char *where) {
   return AF_OK;
 }
 
-// Grow the brick grid so that it covers block box [lo, hi]; new grids are
-// filled with "unknown" and rebuilt from every block.
+// Exact 4^3-cell masks of every orientation's body and corridor entries, for
+// each position r of the point's voxel modulo 4: entry o lands in cell
+// floor((r + o) / 4) (relative to the point's cell) at bit position
+// ((r + o) mod 4) per axis.  Cells are listed in order of first appearance
+// in the table.  Layout as described for ToolDev::mbegin.
+void build_cell_masks(const std::vector<uint32_t> &ent, const std::vector<uint32_t> &begin,
+                      int32_t K, std::vector<uint32_t> &mbeg, std::vector<uint32_t> &mcell,
+                      std::vector<uint64_t> &mmask) {
+  mbeg.assign(128 * (size_t)K + 1, 0u);
+  std::vector<int32_t> slot;   // cell -> list index, over a bounding box
+  for (int32_t k = 0; k < K; ++k) {
+    const uint32_t b = begin[k] + 3, e = begin[k + 1];
+    int lo[3] = {1 << 20, 1 << 20, 1 << 20}, hi[3] = {-(1 << 20), -(1 << 20), -(1 << 20)};
+    for (uint32_t j = b; j < e; ++j) {
+      const int o[3] = {entry_x(ent[j]), entry_y(ent[j]), entry_z(ent[j])};
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = std::min(lo[a], o[a] >> 2);
+        hi[a] = std::max(hi[a], (o[a] + 3) >> 2);
+      }
+    }
+    const int dx = std::max(0, hi[0] - lo[0] + 1), dy = std::max(0, hi[1] - lo[1] + 1),
+              dz = std::max(0, hi[2] - lo[2] + 1);
+    slot.assign((size_t)dx * dy * dz, -1);
+    for (int r = 0; r < 64; ++r) {
+      const int rr[3] = {r & 3, (r >> 2) & 3, (r >> 4) & 3};
+      for (int part = 0; part < 2; ++part) {
+        mbeg[2 * (64 * (size_t)k + r) + part] = (uint32_t)mcell.size();
+        const size_t first = mcell.size();
+        std::vector<size_t> used;
+        for (uint32_t j = b; j < e; ++j) {
+          const uint32_t en = ent[j];
+          if ((entry_cls(en) == AF_CLS_BODY) != (part == 0)) continue;
+          const int v[3] = {rr[0] + entry_x(en), rr[1] + entry_y(en), rr[2] + entry_z(en)};
+          const int cx = v[0] >> 2, cy = v[1] >> 2, cz = v[2] >> 2;
+          const size_t si = ((size_t)(cz - lo[2]) * dy + (cy - lo[1])) * dx + (cx - lo[0]);
+          if (slot[si] < 0) {
+            slot[si] = (int32_t)(mcell.size() - first);
+            used.push_back(si);
+            mcell.push_back(pack_entry(cx, cy, cz, 0));
+            mmask.push_back(0ull);
+          }
+          const int bit = (v[0] & 3) | ((v[1] & 3) << 2) | ((v[2] & 3) << 4);
+          mmask[first + (size_t)slot[si]] |= 1ull << bit;
+        }
+        for (size_t si : used) slot[si] = -1;
+      }
+    }
+  }
+  mbeg[128 * (size_t)K] = (uint32_t)mcell.size();
+}
+
+// Bricks of margin the grid keeps around every allocated block: every table
+// lookup of a point (its brick plus any offset of any tool) stays inside the
+// grid, so lookups need no bounds test.
+int32_t grid_margin_need(const af_ctx *c) {
+  int32_t need = 4;
+  for (const ToolDev &t : c->tools)
+    if (t.entries) need = std::max<int32_t>(need, (t.reach + 7) / 8 + 1);
+  return need;
+}
+
+// Grow the brick grid so that it covers block box [lo, hi] with the margin
+// above; new grids are filled with "unknown" (the caller rebuilds them from
+// every block) and every tool's grid-relative table is recomputed.
 int ensure_grid(af_ctx *c, hipStream_t s, bool &rebuilt) {
   rebuilt = false;
   if (!c->have_bbox) return AF_OK;
   GridDev &g = c->grid;
+  const int32_t need = grid_margin_need(c);
   bool inside = c->grid_bricks > 0;
   for (int a = 0; a < 3 && inside; ++a)
-    inside = c->bbox_lo[a] >= g.g0[a] && c->bbox_hi[a] < g.g0[a] + g.gd[a];
+    inside = c->bbox_lo[a] - g.g0[a] >= need && g.g0[a] + g.gd[a] - 1 - c->bbox_hi[a] >= need;
   if (inside) return AF_OK;
   GridDev ng;
   memset(&ng, 0, sizeof(ng));
   int64_t nb = 1;
   for (int a = 0; a < 3; ++a) {
     int32_t ext = c->bbox_hi[a] - c->bbox_lo[a] + 1;
-    int32_t margin = std::max<int32_t>(4, ext / 4);
+    int32_t margin = std::max<int32_t>(need, ext / 4);
     ng.g0[a] = c->bbox_lo[a] - margin;
     ng.gd[a] = ext + 2 * margin;
     nb *= ng.gd[a];
   }
+  if (nb * 128 >= (int64_t(1) << 32))
+    return fail(c, AF_ENOMEM, "brick grid of %lld bricks exceeds 4 GiB", (long long)nb);
   if (c->grid_bricks > 0) {
     HIP_TRY(c, hipStreamSynchronize(s));
     dev_free(c, g.pred, sizeof(uint32_t) * 32 * c->grid_bricks);
     dev_free(c, g.surf, sizeof(uint32_t) * 16 * c->grid_bricks);
     dev_free(c, g.occ_any, sizeof(uint32_t) * ((c->grid_bricks + 31) / 32));
+    dev_free(c, g.occ4, c->grid_bricks);
+    dev_free(c, g.occ1, sizeof(uint32_t) * 16 * c->grid_bricks);
+    dev_free(c, g.occ64, sizeof(uint64_t) * 8 * c->grid_bricks);
     c->grid_bricks = 0;
   }
   ALLOC(c, ng.pred, nb * 32);
   ALLOC(c, ng.surf, nb * 16);
   ALLOC(c, ng.occ_any, (nb + 31) / 32);
+  ALLOC(c, ng.occ4, nb);
+  ALLOC(c, ng.occ1, nb * 16);
+  ALLOC(c, ng.occ64, nb * 8);
   c->grid = ng;
   c->grid_bricks = nb;
   launch_grid_fill(c->grid, s);
+  for (const ToolDev &t : c->tools)
+    if (t.entries && launch_table_grid(t, c->grid, s) != 0) return hip_check(c, "table grid");
   rebuilt = true;
   return hip_check(c, "grid fill");
+}
+
+// ensure_grid outside a frame: a reallocated grid is refilled at once.
+int regrid(af_ctx *c, hipStream_t s) {
+  bool rebuilt = false;
+  int rc = ensure_grid(c, s, rebuilt);
+  if (rc != AF_OK) return rc;
+  if (rebuilt) {
+    launch_grid_rebuild(c->p, c->map, c->grid, c->n_blocks, s);
+    return hip_check(c, "grid rebuild");
+  }
+  return AF_OK;
 }
 
 enum { ST_INTEGRATE, ST_K_INTEGRATE, ST_SCORE, ST_K_NORMALS, ST_K_MASK, ST_K_SCORE, ST_COUNT };
@@ -356,6 +442,7 @@ int af_create(const af_config *cfg, af_ctx **out) {
   CREATE_ALLOC(c->counters, 1);
   CREATE_ALLOC(c->work, 1);
   CREATE_ALLOC(c->mask, NP * ((cfg->max_orientations + 63) / 64));
+  CREATE_ALLOC(c->nearp, NP * 2 * ((cfg->max_orientations + 63) / 64));
   c->tools.assign(cfg->max_tools, ToolDev());
   c->tool_bytes.assign(cfg->max_tools, 0);
   c->tool_cbytes.assign(cfg->max_tools, 0);
@@ -442,6 +529,15 @@ int af_set_tool_kernels(af_ctx *c, int32_t tool_id, const af_tool *tool, int32_t
     dev_free(c, t.cbegin, sizeof(uint32_t) * (t.K + 1));
     dev_free(c, t.cflag, t.K);
     dev_free(c, t.centries, c->tool_cbytes[tool_id]);
+    dev_free(c, t.same, sizeof(uint64_t) * ((t.K + 63) / 64));
+    dev_free(c, t.xent, sizeof(uint2) * std::max<int64_t>(1, t.n_entries));
+    dev_free(c, t.cdelta, sizeof(int32_t) * std::max<int64_t>(1, t.n_centries));
+    dev_free(c, t.c4begin, sizeof(uint32_t) * (t.K + 1));
+    dev_free(c, t.c4flag, t.K);
+    dev_free(c, t.c4entries, sizeof(uint32_t) * std::max<int64_t>(1, t.n_c4entries));
+    dev_free(c, t.mbegin, sizeof(uint32_t) * (128 * (int64_t)t.K + 1));
+    dev_free(c, t.mcell, sizeof(uint32_t) * std::max<int64_t>(1, t.n_masks));
+    dev_free(c, t.mmask, sizeof(uint64_t) * std::max<int64_t>(1, t.n_masks));
     memset(&t, 0, sizeof(t));
   }
   ToolDev nt;
@@ -450,6 +546,16 @@ int af_set_tool_kernels(af_ctx *c, int32_t tool_id, const af_tool *tool, int32_t
   int32_t *err = nullptr;
   ALLOC(c, nt.rot, 9 * (int64_t)K);
   ALLOC(c, nt.begin, K + 1);
+  {
+    std::vector<uint64_t> same((K + 63) / 64, 0ull);
+    for (int32_t k = 1; k < K; ++k)
+      if (rot[9 * k] == rot[9 * (k - 1)] && rot[9 * k + 3] == rot[9 * (k - 1) + 3] &&
+          rot[9 * k + 6] == rot[9 * (k - 1) + 6])
+        same[k >> 6] |= 1ull << (k & 63);
+    ALLOC(c, nt.same, (K + 63) / 64);
+    HIP_TRY(c, hipMemcpy(nt.same, same.data(), sizeof(uint64_t) * same.size(),
+                         hipMemcpyHostToDevice));
+  }
   ALLOC(c, counts, 2 * (int64_t)K);
   ALLOC(c, err, 1);
   HIP_TRY(c, hipMemcpyAsync(nt.rot, rot, sizeof(double) * 9 * K, hipMemcpyHostToDevice, s));
@@ -486,27 +592,72 @@ int af_set_tool_kernels(af_ctx *c, int32_t tool_id, const af_tool *tool, int32_t
   ALLOC(c, nt.cflag, K);
   ALLOC(c, ccounts, K);
   if (launch_table_coarse(K, nt.begin, counts, nt.entries, nt.far_begin, ccounts, nt.cbegin,
-                          nullptr, nt.cflag, 0, s) != 0)
+                          nullptr, nt.cflag, 0, 3, s) != 0)
     return hip_check(c, "coarse count");
   uint32_t ctotal = 0;
   HIP_TRY(c, hipMemcpyAsync(&ctotal, nt.cbegin + K, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   HIP_TRY(c, hipStreamSynchronize(s));
   ALLOC(c, nt.centries, ctotal);
   if (launch_table_coarse(K, nt.begin, counts, nt.entries, nt.far_begin, ccounts, nt.cbegin,
-                          nt.centries, nt.cflag, 1, s) != 0)
+                          nt.centries, nt.cflag, 1, 3, s) != 0)
     return hip_check(c, "coarse fill");
+  // 4^3-cell lists
+  ALLOC(c, nt.c4begin, K + 1);
+  ALLOC(c, nt.c4flag, K);
+  if (launch_table_coarse(K, nt.begin, counts, nt.entries, nt.far_begin, ccounts, nt.c4begin,
+                          nullptr, nt.c4flag, 0, 2, s) != 0)
+    return hip_check(c, "coarse4 count");
+  uint32_t c4total = 0;
+  HIP_TRY(c, hipMemcpyAsync(&c4total, nt.c4begin + K, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  ALLOC(c, nt.c4entries, std::max<uint32_t>(1u, c4total));
+  if (launch_table_coarse(K, nt.begin, counts, nt.entries, nt.far_begin, ccounts, nt.c4begin,
+                          nt.c4entries, nt.c4flag, 1, 2, s) != 0)
+    return hip_check(c, "coarse4 fill");
+  nt.n_c4entries = c4total;
   HIP_TRY(c, hipStreamSynchronize(s));
   dev_free(c, ccounts, sizeof(uint32_t) * K);
   dev_free(c, counts, sizeof(uint32_t) * 2 * K);
   dev_free(c, err, sizeof(int32_t));
   if (herr) return fail(c, AF_EINVAL, "tool table build failed (%d)", herr);
   c->tool_cbytes[tool_id] = sizeof(uint32_t) * (int64_t)ctotal;
+  {
+    std::vector<uint32_t> he(total);
+    HIP_TRY(c, hipMemcpy(he.data(), nt.entries, sizeof(uint32_t) * total, hipMemcpyDeviceToHost));
+    int32_t reach = 0;
+    for (uint32_t e : he)
+      reach = std::max({reach, std::abs(entry_x(e)), std::abs(entry_y(e)), std::abs(entry_z(e))});
+    nt.reach = reach;
+    std::vector<uint32_t> hb(K + 1);
+    HIP_TRY(c, hipMemcpy(hb.data(), nt.begin, sizeof(uint32_t) * (K + 1), hipMemcpyDeviceToHost));
+    std::vector<uint32_t> mbeg, mcell;
+    std::vector<uint64_t> mmask;
+    build_cell_masks(he, hb, K, mbeg, mcell, mmask);
+    nt.n_masks = (int64_t)mcell.size();
+    ALLOC(c, nt.mbegin, 128 * (int64_t)K + 1);
+    ALLOC(c, nt.mcell, std::max<int64_t>(1, nt.n_masks));
+    ALLOC(c, nt.mmask, std::max<int64_t>(1, nt.n_masks));
+    HIP_TRY(c, hipMemcpy(nt.mbegin, mbeg.data(), sizeof(uint32_t) * mbeg.size(),
+                         hipMemcpyHostToDevice));
+    if (nt.n_masks) {
+      HIP_TRY(c, hipMemcpy(nt.mcell, mcell.data(), sizeof(uint32_t) * mcell.size(),
+                           hipMemcpyHostToDevice));
+      HIP_TRY(c, hipMemcpy(nt.mmask, mmask.data(), sizeof(uint64_t) * mmask.size(),
+                           hipMemcpyHostToDevice));
+    }
+  }
+  nt.n_entries = total;
+  nt.n_centries = ctotal;
+  ALLOC(c, nt.xent, std::max<int64_t>(1, total));
+  ALLOC(c, nt.cdelta, std::max<int64_t>(1, ctotal));
   nt.K = K;
   nt.mask = c->mask;
+  nt.nearp = c->nearp;
   t = nt;
   c->tool_bytes[tool_id] = sizeof(uint32_t) * (int64_t)total;
   c->last_stream = s;
-  return AF_OK;
+  if (c->grid_bricks > 0 && launch_table_grid(t, c->grid, s) != 0) return hip_check(c, "table grid");
+  return regrid(c, s);
 }
 
 int af_integrate_frame(af_ctx *c, const float *xyz, int64_t n, const float origin[3],
@@ -584,12 +735,14 @@ int af_score_points(af_ctx *c, int32_t tool_id, void *stream) {
   ToolDev &t = c->tools[tool_id];
   if (!t.entries) return fail(c, AF_ENOTOOL, "tool %d has no kernels", tool_id);
   hipStream_t s = (hipStream_t)stream;
+  int rc = regrid(c, s);
+  if (rc != AF_OK) return rc;
   hipEvent_t t0 = timing_mark(c, s);
   HIP_TRY(c, hipMemsetAsync(t.counters, 0, sizeof(ScoreCounters), s));
   hipEvent_t t1 = timing_mark(c, s);
   launch_normals(c->p, c->map, c->pts, c->grid, c->n_points, s);
   hipEvent_t t2 = timing_mark(c, s);
-  launch_mask(c->p, c->pts, t, c->n_points, s);
+  launch_mask(c->p, c->pts, t, c->grid, c->n_points, s);
   hipEvent_t t3 = timing_mark(c, s);
   launch_score(c->p, c->pts, t, c->grid, c->n_points, c->score_variant, c->work, s);
   hipEvent_t t4 = timing_mark(c, s);
@@ -626,7 +779,7 @@ int af_tune_score(af_ctx *c, int32_t tool_id, int32_t reps, void *stream, int32_
   if (reps < 1) reps = 1;
   hipStream_t s = (hipStream_t)stream;
   launch_normals(c->p, c->map, c->pts, c->grid, c->n_points, s);
-  launch_mask(c->p, c->pts, t, c->n_points, s);
+  launch_mask(c->p, c->pts, t, c->grid, c->n_points, s);
   hipEvent_t a, b;
   HIP_TRY(c, hipEventCreate(&a));
   HIP_TRY(c, hipEventCreate(&b));
@@ -860,6 +1013,8 @@ int af_score_stats_get(af_ctx *c, int32_t tool_id, af_score_stats *st) {
   st->deep_chunks_max = (int64_t)h.deep_chunks_max;
   st->coarse_checks = (int64_t)h.coarse_checks;
   st->coarse_clear = (int64_t)h.coarse_clear;
+  st->chunks_body = (int64_t)h.chunks_body;
+  st->chunks_far = (int64_t)h.chunks_far;
   return AF_OK;
 }
 

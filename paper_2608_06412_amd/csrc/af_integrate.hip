@@ -371,6 +371,21 @@ __device__ void write_brick(const Params &p, MapDev m, GridDev g, int64_t id, in
   uint32_t cd = voxel_code(p, S, W, cl);
   code[t] = (uint8_t)cd;
   int any_occ = __syncthreads_or((int)(cd & 1u));
+  // occupancy of the brick's eight 4^3 octants: each wave holds one z slice
+  // (64 voxels, lane = x | y << 3), so four masks of its ballot give the
+  // slice's four (x, y) quadrants
+  __shared__ uint32_t s_occ4;
+  const uint64_t bal = __ballot(cd & 1u);
+  {
+    uint32_t nib = (uint32_t)((bal & 0x000000000F0F0F0Full) != 0) |
+                   ((uint32_t)((bal & 0x00000000F0F0F0F0ull) != 0) << 1) |
+                   ((uint32_t)((bal & 0x0F0F0F0F00000000ull) != 0) << 2) |
+                   ((uint32_t)((bal & 0xF0F0F0F000000000ull) != 0) << 3);
+    if (t == 0) s_occ4 = 0u;
+    __syncthreads();
+    if ((t & 63) == 0 && nib) atomicOr(&s_occ4, nib << (4 * ((t >> 8) & 1)));
+    __syncthreads();
+  }
   int32_t b[3];
   unpack_key(m.bkey[id], b[0], b[1], b[2]);
   int x = b[0] - g.g0[0], y = b[1] - g.g0[1], z = b[2] - g.g0[2];
@@ -390,6 +405,20 @@ __device__ void write_brick(const Params &p, MapDev m, GridDev g, int64_t id, in
         atomicOr(&g.occ_any[brick >> 5], bit);
       else
         atomicAnd(&g.occ_any[brick >> 5], ~bit);
+    } else if (t == 49) {
+      g.occ4[brick] = (uint8_t)s_occ4;
+    }
+    if ((t & 63) == 0) {   // this wave's z slice: two words of the bit plane
+      g.occ1[brick * 16 + 2 * (t >> 6)] = (uint32_t)bal;
+      g.occ1[brick * 16 + 2 * (t >> 6) + 1] = (uint32_t)(bal >> 32);
+    }
+    if ((t & 63) < 4) {    // the slice's 16 bits of each (x, y) octant, lane = x | y << 3
+      const int ox = t & 1, oy = (t >> 1) & 1, lz = t >> 6;
+      uint32_t piece = 0;
+      for (int yy = 0; yy < 4; ++yy)
+        piece |= (uint32_t)((bal >> (4 * ox + 8 * (4 * oy + yy))) & 0xfull) << (4 * yy);
+      const int oct = ox | (oy << 1) | ((lz >> 2) << 2);
+      reinterpret_cast<uint16_t *>(g.occ64)[brick * 32 + oct * 4 + (lz & 3)] = (uint16_t)piece;
     }
   }
   __syncthreads();
@@ -555,6 +584,9 @@ __global__ void k_grid_fill(GridDev g, int64_t nbricks) {
   for (int64_t j = i; j < nbricks * 32; j += stride) g.pred[j] = kUnknownWord;
   for (int64_t j = i; j < nbricks * 16; j += stride) g.surf[j] = 0u;
   for (int64_t j = i; j < (nbricks + 31) / 32; j += stride) g.occ_any[j] = 0u;
+  for (int64_t j = i; j < nbricks; j += stride) g.occ4[j] = 0u;
+  for (int64_t j = i; j < nbricks * 16; j += stride) g.occ1[j] = 0u;
+  for (int64_t j = i; j < nbricks * 8; j += stride) g.occ64[j] = 0ull;
 }
 
 inline unsigned grid_for(int64_t threads) {

@@ -130,11 +130,90 @@ k_normals(Params p, MapDev m, PointsDev pts, GridDev g, int64_t n) {
   pts.has_normal[i] = 1;
 }
 
+// ---------------------------------------------------------------------------
+// Grid-relative lookups.  The grid keeps a margin of bricks around every
+// allocated block that is wider than any table offset, so a lookup needs no
+// bounds test.  A point is its linear brick index Bp plus its in-brick
+// position rp = rx | ry << 4 | rz << 8; an entry is its brick delta plus its
+// in-brick offset o7 in the same 4-bit fields.  One add gives rp + o7, whose
+// bits 3, 7 and 11 are the per-axis brick carries and whose other bits are
+// the target voxel's in-brick coordinates.  The word is read through a buffer
+// resource over the grid (a stray offset reads 0 instead of faulting).
+struct SwFrame {
+  uint32_t Bp, rp;
+};
+
+struct SwGrid {
+  __amdgpu_buffer_rsrc_t pred, occ1;
+  uint32_t gx, gxy, nbricks;
+  const uint32_t *occ_any;
+};
+
+__device__ inline SwGrid sw_grid(const GridDev &g) {
+  SwGrid q;
+  q.gx = (uint32_t)g.gd[0];
+  q.gxy = (uint32_t)g.gd[0] * (uint32_t)g.gd[1];
+  q.nbricks = q.gxy * (uint32_t)g.gd[2];
+  q.pred = __builtin_amdgcn_make_buffer_rsrc((void *)g.pred, (short)0, (int)(q.nbricks << 7),
+                                             0x00020000);
+  q.occ1 = __builtin_amdgcn_make_buffer_rsrc((void *)g.occ1, (short)0, (int)(q.nbricks << 6),
+                                             0x00020000);
+  q.occ_any = g.occ_any;
+  return q;
+}
+
+__device__ inline SwFrame sw_frame(const GridDev &g, const SwGrid &q, const int32_t s[3]) {
+  const uint32_t bx = (uint32_t)((s[0] >> 3) - g.g0[0]);
+  const uint32_t by = (uint32_t)((s[1] >> 3) - g.g0[1]);
+  const uint32_t bz = (uint32_t)((s[2] >> 3) - g.g0[2]);
+  SwFrame f;
+  f.Bp = bx + q.gx * by + q.gxy * bz;
+  f.rp = (uint32_t)(s[0] & 7) | ((uint32_t)(s[1] & 7) << 4) | ((uint32_t)(s[2] & 7) << 8);
+  return f;
+}
+
+__device__ inline uint32_t code_sw(const SwGrid &q, const SwFrame &f, uint2 xe) {
+  const uint32_t tt = f.rp + xe.y;
+  uint32_t brick = f.Bp + xe.x + ((tt >> 3) & 1u);
+  brick += ((tt >> 7) & 1u) * q.gx;
+  brick += ((tt >> 11) & 1u) * q.gxy;
+  const uint32_t wib = ((tt >> 5) & 3u) | ((tt >> 6) & 0x1cu);   // (ly >> 1) | lz << 2
+  const uint32_t bit = ((tt & 7u) << 1) | (tt & 0x10u);          // 2 (lx + 8 (ly & 1))
+  const uint32_t w =
+      __builtin_amdgcn_raw_buffer_load_b32(q.pred, ((brick << 5) | wib) << 2, 0, 0);
+  return (w >> bit) & 3u;
+}
+
+// Body and corridor entries only need "TSDF < r_c": one bit per voxel, so a
+// whole brick is 64 bytes.
+__device__ inline uint32_t occ_bit_sw(const SwGrid &q, const SwFrame &f, uint2 xe) {
+  const uint32_t tt = f.rp + xe.y;
+  uint32_t brick = f.Bp + xe.x + ((tt >> 3) & 1u);
+  brick += ((tt >> 7) & 1u) * q.gx;
+  brick += ((tt >> 11) & 1u) * q.gxy;
+  const uint32_t wib = ((tt >> 6) & 1u) | ((tt >> 7) & 0xeu);   // (ly >> 2) | lz << 1
+  const uint32_t bit = (tt & 7u) | ((tt >> 1) & 0x18u);          // lx | (ly & 3) << 3
+  const uint32_t w =
+      __builtin_amdgcn_raw_buffer_load_b32(q.occ1, ((brick << 4) | wib) << 2, 0, 0);
+  return (w >> bit) & 1u;
+}
+
+__device__ inline uint32_t sw_cls(uint2 xe) { return xe.y >> 30; }
+
+__device__ inline bool sw_hits(uint2 xe, uint32_t code) {
+  return sw_cls(xe) == AF_CLS_NEAR ? code != 0u : (code & 1u) != 0u;
+}
+
 // One lane per point: the point's normal and viewpoint vectors stay in
 // registers (fp64, exact conversions of integers) while every lane walks the
 // same orientation list, so each direction is a wave-uniform load.
+//
+// For every candidate direction the lane also reads the direction's three
+// arm samples (Section 3.4 "Arm path checking"; they depend on the approach
+// direction only, so orientations that share it share the result) and
+// records which one hits first, as two bit planes per mask word.
 __global__ void __launch_bounds__(kThreads)
-k_mask(Params p, PointsDev pts, ToolDev t, int64_t n, int32_t mw) {
+k_mask(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t mw) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const bool act = i < n;
   const int hn = act ? pts.has_normal[i] : -1;
@@ -169,14 +248,31 @@ k_mask(Params p, PointsDev pts, ToolDev t, int64_t n, int32_t mw) {
       }
     }
   }
+  const SwGrid q = sw_grid(g);
+  SwFrame f;
+  f.Bp = f.rp = 0u;
+  if (hn >= 0) {
+    int32_t s[3];
+    unpack_key(pts.key[i], s[0], s[1], s[2]);
+    f = sw_frame(g, q, s);
+  }
   unsigned long long cand = 0;
+  bool ok = false;     // candidate bit of the previous orientation
+  uint32_t nb = 0u;    // its arm-sample result
   for (int w = 0; w < mw; ++w) {
-    uint64_t word = 0;
+    uint64_t word = 0, pl0 = 0, pl1 = 0;
     const int kend = t.K - 64 * w < 64 ? t.K - 64 * w : 64;
+    const uint64_t same = t.same[w];
     for (int j = 0; j < kend; ++j) {
+      if ((same >> j) & 1ull) {   // same direction as orientation k - 1
+        word |= (uint64_t)ok << j;
+        pl0 |= (uint64_t)(nb & 1u) << j;
+        pl1 |= (uint64_t)(nb >> 1) << j;
+        continue;
+      }
       const double *R = t.rot + 9 * (int64_t)(64 * w + j);
       const double d0 = R[0], d1 = R[3], d2 = R[6];
-      bool ok = hn >= 0;
+      ok = hn >= 0;
       if (hn > 0) {
         double dot = (n0 * d0 + n1 * d1) + n2 * d2;
         ok = dot >= 0.0 && dot * dot >= p.cos2 * nn;
@@ -192,9 +288,23 @@ k_mask(Params p, PointsDev pts, ToolDev t, int64_t n, int32_t mw) {
         }
         ok = seen;
       }
+      nb = 0u;
+      if (ok) {
+        const uint32_t b = t.begin[64 * w + j];
+        const uint32_t h0 = code_sw(q, f, t.xent[b]) != 0u;
+        const uint32_t h1 = code_sw(q, f, t.xent[b + 1]) != 0u;
+        const uint32_t h2 = code_sw(q, f, t.xent[b + 2]) != 0u;
+        nb = h0 ? 1u : (h1 ? 2u : (h2 ? 3u : 0u));
+      }
       word |= (uint64_t)ok << j;
+      pl0 |= (uint64_t)(nb & 1u) << j;
+      pl1 |= (uint64_t)(nb >> 1) << j;
     }
-    if (act) t.mask[i * mw + w] = word;
+    if (act) {
+      t.mask[i * mw + w] = word;
+      t.nearp[i * 2 * mw + w] = pl0;
+      t.nearp[i * 2 * mw + mw + w] = pl1;
+    }
     cand += (unsigned long long)__popcll(word);
   }
   for (int off = 32; off >= 1; off >>= 1) {
@@ -784,6 +894,714 @@ k_score_fast(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t m
   }
 }
 
+// scan_fine with the next step's table entries loaded while the current
+// step's voxel words are gathered, so only one memory latency per step.
+template <int UN>
+__device__ inline bool scan_fine_pf(const Params &p, const ToolDev &t, const GridDev &g,
+                                    const PointFrame &f, uint32_t b, uint32_t e, int &body,
+                                    uint64_t &lookups) {
+  if (b >= e) return true;
+  const uint32_t lane = (uint32_t)lane_id();
+  uint32_t ent[UN];
+#pragma unroll
+  for (int u = 0; u < UN; ++u) {
+    const uint32_t idx = b + 64 * u + lane;
+    ent[u] = t.entries[idx < e ? idx : e - 1];
+  }
+  for (uint32_t base = b; base < e; base += 64 * UN) {
+    uint32_t code[UN], nxt[UN];
+#pragma unroll
+    for (int u = 0; u < UN; ++u) code[u] = code_fast(g, f, ent[u]);
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+      const uint32_t idx = base + 64 * (UN + u) + lane;
+      nxt[u] = t.entries[idx < e ? idx : e - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+      const uint32_t cb = base + 64 * u;
+      const bool hit = cb + lane < e && code_hits(ent[u], code[u]);
+      const uint64_t nf = __ballot(hit && entry_cls(ent[u]) != AF_CLS_BODY);
+      const uint64_t bm = __ballot(hit && entry_cls(ent[u]) == AF_CLS_BODY);
+      if (cb >= e) break;
+      const int stop = chunk_stop(nf, bm, p.n_c - body);
+      if (stop < 64) {
+        lookups += (uint64_t)stop + 1;
+        return false;
+      }
+      body += __popcll(bm);
+      lookups += (e - cb) < 64u ? (e - cb) : 64u;
+    }
+#pragma unroll
+    for (int u = 0; u < UN; ++u) ent[u] = nxt[u];
+  }
+  return true;
+}
+
+template <int UN, int CO>
+__device__ inline bool scan_rest_pf(const Params &p, const ToolDev &t, const GridDev &g,
+                                    const PointFrame &f, int k, uint32_t b, uint32_t e, int body,
+                                    uint64_t &lookups, uint64_t &cchecks, uint64_t &cclear) {
+  if (!CO) return scan_fine_pf<UN>(p, t, g, f, b, e, body, lookups);
+  const uint32_t fb = t.far_begin[k];
+  const uint32_t mid = fb > b ? fb : b;
+  if (!scan_fine_pf<UN>(p, t, g, f, b, mid, body, lookups)) return false;
+  if (mid >= e) return true;
+  if (t.cflag[k]) {
+    ++cchecks;
+    if (corridor_clear(t, g, f, k)) {
+      ++cclear;
+      lookups += e - mid;
+      return true;
+    }
+  }
+  return scan_fine_pf<UN>(p, t, g, f, mid, e, body, lookups);
+}
+
+// Sum over the lanes in m of a per-lane value below 16 held as four ballots
+// of its bits.
+__device__ inline uint32_t plane_sum(const uint64_t pl[4], uint64_t m) {
+  return (uint32_t)__popcll(pl[0] & m) + 2u * (uint32_t)__popcll(pl[1] & m) +
+         4u * (uint32_t)__popcll(pl[2] & m) + 8u * (uint32_t)__popcll(pl[3] & m);
+}
+
+// As k_score_fast, with the bookkeeping of phase 2 done for the whole wave
+// at once: candidates decided by their first E entries (blocked ones, at
+// entry pos) are summed from ballots -- tests by popcount, canonical lookups
+// (pos + 1) from four bit-plane ballots -- so only candidates that need a
+// deeper scan, or are free, are visited one by one.  Same labels, first
+// free orientations and canonical counts.
+template <int NT, int E, int UN, int FB, int CO>
+__global__ void __launch_bounds__(NT)
+k_score_wave(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t mw,
+             unsigned *work) {
+  static_assert(E >= 1 && E <= 15, "head length must fit the 4-bit planes");
+  constexpr int NW = NT / 64;
+  constexpr int ST = E + 1;
+  __shared__ uint32_t s_begin[kLdsK + 1];
+  __shared__ uint32_t s_head[kLdsK * ST];
+  const int K = t.K;
+  for (int j = threadIdx.x; j <= K; j += NT) s_begin[j] = t.begin[j];
+  __syncthreads();
+  for (int j = threadIdx.x; j < K * E; j += NT) {
+    const int k = j / E, q = j - k * E;
+    const uint32_t pos = s_begin[k] + (uint32_t)q;
+    s_head[k * ST + q] = pos < s_begin[k + 1] ? t.entries[pos] : 0u;
+  }
+  __syncthreads();
+  const int lane = lane_id();
+  const int64_t wave0 =
+      (int64_t)blockIdx.x * NW + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t nwaves = (int64_t)gridDim.x * NW;
+  uint64_t conf = 0, acc = 0, blk = 0, nocand = 0, tests = 0, lookups = 0, deep = 0, chunks = 0;
+  uint64_t cchecks = 0, cclear = 0;
+  int64_t i = wave0, batch_end = wave0 + 1;
+  if (FB > 0) {
+    unsigned got = 0;
+    if (lane == 0) got = atomicAdd(work, (unsigned)FB);
+    i = (int64_t)__builtin_amdgcn_readfirstlane(__shfl(got, 0));
+    batch_end = i + FB;
+  }
+  for (; i < n;) {
+    const int hn = __builtin_amdgcn_readfirstlane(pts.has_normal[i]);
+    uint8_t label;
+    int16_t ff = -1;
+    if (hn < 0) {
+      label = AF_UNSCORED;
+    } else {
+      ++conf;
+      int32_t s[3];
+      unpack_key(pts.key[i], s[0], s[1], s[2]);
+      const PointFrame f = point_frame(g, s);
+      label = AF_NO_CANDIDATE;
+      const uint64_t mine = lane < mw ? t.mask[i * mw + lane] : 0ull;
+      for (int w = 0; w < mw && ff < 0; ++w) {
+        const uint64_t word =
+            ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(mine >> 32), w) << 32) |
+            (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)mine, w);
+        if (!word) continue;
+        label = AF_BLOCKED;
+        const int k = 64 * w + lane;
+        const int kk = k < K ? k : K - 1;
+        const bool cand = (word >> lane) & 1ull;
+        const uint32_t len = s_begin[kk + 1] - s_begin[kk];
+        uint32_t ent[E], code[E];
+#pragma unroll
+        for (int q = 0; q < E; ++q) ent[q] = s_head[kk * ST + q];
+#pragma unroll
+        for (int q = 0; q < E; ++q) code[q] = code_fast(g, f, ent[q]);
+        int state = 0, pos = 0, body = 0;   // 0 undecided, 1 blocked, 2 free
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+          const bool hit = (uint32_t)q < len && code_hits(ent[q], code[q]);
+          if (state == 0 && hit) {
+            if (entry_cls(ent[q]) != AF_CLS_BODY || ++body >= p.n_c) {
+              state = 1;
+              pos = q;
+            }
+          }
+        }
+        if (state == 0 && len <= (uint32_t)E) state = 2;
+        const uint64_t fm = __ballot(cand && state == 2);
+        uint64_t open = fm | __ballot(cand && state == 0);
+        const uint32_t v = (cand && state == 1) ? (uint32_t)pos + 1u : 0u;
+        const uint64_t pl[4] = {__ballot(v & 1u), __ballot(v & 2u), __ballot(v & 4u),
+                                __ballot(v & 8u)};
+        uint64_t left = word;   // candidates not yet accounted
+        for (;;) {
+          if (!open) {          // the rest are blocked within their first E entries
+            tests += (uint64_t)__popcll(left);
+            lookups += plane_sum(pl, left);
+            break;
+          }
+          const int j = __ffsll((long long)open) - 1;
+          open &= open - 1;
+          const uint64_t below = left & ((1ull << j) - 1ull);
+          tests += (uint64_t)__popcll(below) + 1;
+          lookups += plane_sum(pl, below);
+          left &= ~((2ull << j) - 1ull);
+          const int kj = 64 * w + j;
+          const uint32_t b = s_begin[kj], e = s_begin[kj + 1];
+          if ((fm >> j) & 1ull) {
+            lookups += e - b;
+            ff = (int16_t)kj;
+            break;
+          }
+          lookups += E;
+          ++deep;
+          chunks += (e - b - E + 63) / 64;
+          if (scan_rest_pf<UN, CO>(p, t, g, f, kj, b + E, e,
+                                   __builtin_amdgcn_readlane(body, j), lookups, cchecks,
+                                   cclear)) {
+            ff = (int16_t)kj;
+            break;
+          }
+        }
+      }
+      if (ff >= 0) label = AF_ACCESSIBLE;
+      acc += label == AF_ACCESSIBLE;
+      blk += label == AF_BLOCKED;
+      nocand += label == AF_NO_CANDIDATE;
+    }
+    if (lane == 0) {
+      t.label[i] = label;
+      t.first_free[i] = ff;
+    }
+    if (FB > 0) {
+      if (++i >= batch_end) {
+        unsigned got = 0;
+        if (lane == 0) got = atomicAdd(work, (unsigned)FB);
+        i = (int64_t)__builtin_amdgcn_readfirstlane(__shfl(got, 0));
+        batch_end = i + FB;
+      }
+    } else {
+      i += nwaves;
+    }
+  }
+  if (lane == 0) {
+    if (conf) atomicAdd(&t.counters->n_confident, (unsigned long long)conf);
+    if (acc) atomicAdd(&t.counters->n_accessible, (unsigned long long)acc);
+    if (blk) atomicAdd(&t.counters->n_blocked, (unsigned long long)blk);
+    if (nocand) atomicAdd(&t.counters->n_no_candidate, (unsigned long long)nocand);
+    if (tests) atomicAdd(&t.counters->canonical_tests, (unsigned long long)tests);
+    if (lookups) atomicAdd(&t.counters->canonical_lookups, (unsigned long long)lookups);
+    if (deep) atomicAdd(&t.counters->deep_tests, (unsigned long long)deep);
+    if (chunks) atomicAdd(&t.counters->deep_chunks_max, (unsigned long long)chunks);
+    if (cchecks) atomicAdd(&t.counters->coarse_checks, (unsigned long long)cchecks);
+    if (cclear) atomicAdd(&t.counters->coarse_clear, (unsigned long long)cclear);
+  }
+}
+
+
+// B1: the entries are body or corridor entries only (no arm samples), read
+// from the one-bit plane.
+template <int UN, int B1>
+__device__ inline bool scan_fine_sw(const Params &p, const ToolDev &t, const SwGrid &q,
+                                    const SwFrame &f, uint32_t b, uint32_t e, int &body,
+                                    uint32_t &lookups, uint32_t &steps) {
+  if (b >= e) return true;
+  const uint32_t lane = (uint32_t)lane_id();
+  uint2 ent[UN];
+#pragma unroll
+  for (int u = 0; u < UN; ++u) {
+    const uint32_t idx = b + 64 * u + lane;
+    ent[u] = t.xent[idx < e ? idx : e - 1];
+  }
+  for (uint32_t base = b; base < e; base += 64 * UN) {
+    ++steps;
+    uint32_t code[UN];
+    uint2 nxt[UN];
+#pragma unroll
+    for (int u = 0; u < UN; ++u) code[u] = B1 ? occ_bit_sw(q, f, ent[u]) : code_sw(q, f, ent[u]);
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+      const uint32_t idx = base + 64 * (UN + u) + lane;
+      nxt[u] = t.xent[idx < e ? idx : e - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+      const uint32_t cb = base + 64 * u;
+      const bool hit = cb + lane < e && (B1 ? code[u] != 0u : sw_hits(ent[u], code[u]));
+      const uint64_t nf = __ballot(hit && sw_cls(ent[u]) != AF_CLS_BODY);
+      const uint64_t bm = __ballot(hit && sw_cls(ent[u]) == AF_CLS_BODY);
+      if (cb >= e) break;
+      const int stop = chunk_stop(nf, bm, p.n_c - body);
+      if (stop < 64) {
+        lookups += (uint32_t)stop + 1u;
+        return false;
+      }
+      body += __popcll(bm);
+      lookups += (e - cb) < 64u ? (e - cb) : 64u;
+    }
+#pragma unroll
+    for (int u = 0; u < UN; ++u) ent[u] = nxt[u];
+  }
+  return true;
+}
+
+__device__ inline bool corridor_clear_sw(const ToolDev &t, const SwGrid &q, const SwFrame &f,
+                                         int k) {
+  const uint32_t cb = t.cbegin[k], ce = t.cbegin[k + 1];
+  const uint32_t lane = (uint32_t)lane_id();
+  for (uint32_t base = cb; base < ce; base += 64) {
+    const uint32_t idx = base + lane;
+    const uint32_t brick = f.Bp + (uint32_t)t.cdelta[idx < ce ? idx : ce - 1];
+    const uint32_t bs = brick < q.nbricks ? brick : 0u;
+    const bool occ = (q.occ_any[bs >> 5] >> (bs & 31)) & 1u;
+    if (__ballot(idx < ce && occ)) return false;
+  }
+  return true;
+}
+
+// As corridor_clear_sw over 4^3 cells: c4 is the point's cell (voxel >> 2)
+// relative to the grid; a cell's bit lives in its brick's octant byte.
+__device__ inline bool corridor_clear4_sw(const ToolDev &t, const SwGrid &q, const uint32_t c4[3],
+                                          const uint8_t *occ4, int k) {
+  const uint32_t cb = t.c4begin[k], ce = t.c4begin[k + 1];
+  const uint32_t lane = (uint32_t)lane_id();
+  for (uint32_t base = cb; base < ce; base += 64) {
+    const uint32_t idx = base + lane;
+    const uint32_t d = t.c4entries[idx < ce ? idx : ce - 1];
+    const uint32_t X = c4[0] + (uint32_t)entry_x(d), Y = c4[1] + (uint32_t)entry_y(d),
+                   Z = c4[2] + (uint32_t)entry_z(d);
+    const uint32_t brick = (X >> 1) + q.gx * (Y >> 1) + q.gxy * (Z >> 1);
+    const uint32_t bs = brick < q.nbricks ? brick : 0u;
+    const uint32_t bit = (X & 1u) | ((Y & 1u) << 1) | ((Z & 1u) << 2);
+    const bool occ = (occ4[bs] >> bit) & 1u;
+    if (__ballot(idx < ce && occ)) return false;
+  }
+  return true;
+}
+
+// Exact cell-mask tests over a segment [mb, me) of a point's mask list:
+// occupied entries per cell are popcount(occ64 word & mask).  mask_count
+// returns min(total, 15); mask_any whether any entry is occupied.
+__device__ inline uint64_t cell_word(const SwGrid &q, const uint32_t c4[3], const uint64_t *occ64,
+                                     uint32_t d) {
+  const uint32_t X = c4[0] + (uint32_t)entry_x(d), Y = c4[1] + (uint32_t)entry_y(d),
+                 Z = c4[2] + (uint32_t)entry_z(d);
+  const uint32_t brick = (X >> 1) + q.gx * (Y >> 1) + q.gxy * (Z >> 1);
+  const uint32_t bs = brick < q.nbricks ? brick : 0u;
+  return occ64[(bs << 3) | (X & 1u) | ((Y & 1u) << 1) | ((Z & 1u) << 2)];
+}
+
+__device__ inline uint32_t mask_count(const ToolDev &t, const SwGrid &q, const uint32_t c4[3],
+                                      const uint64_t *occ64, uint32_t mb, uint32_t me) {
+  const uint32_t lane = (uint32_t)lane_id();
+  uint32_t total = 0;
+  for (uint32_t base = mb; base < me && total < 15u; base += 64) {
+    const uint32_t idx = base + lane;
+    const uint32_t j = idx < me ? idx : me - 1;
+    const uint64_t w = cell_word(q, c4, occ64, t.mcell[j]) & t.mmask[j];
+    uint32_t c = idx < me ? (uint32_t)__popcll(w) : 0u;
+    c = c < 15u ? c : 15u;
+    const uint64_t pl[4] = {__ballot(c & 1u), __ballot(c & 2u), __ballot(c & 4u),
+                            __ballot(c & 8u)};
+    total += plane_sum(pl, ~0ull);
+  }
+  return total < 15u ? total : 15u;
+}
+
+__device__ inline bool mask_any(const ToolDev &t, const SwGrid &q, const uint32_t c4[3],
+                                const uint64_t *occ64, uint32_t mb, uint32_t me) {
+  const uint32_t lane = (uint32_t)lane_id();
+  for (uint32_t base = mb; base < me; base += 64) {
+    const uint32_t idx = base + lane;
+    const uint32_t j = idx < me ? idx : me - 1;
+    const uint64_t w = cell_word(q, c4, occ64, t.mcell[j]) & t.mmask[j];
+    if (__ballot(idx < me && w != 0ull)) return true;
+  }
+  return false;
+}
+
+// Deep scan with exact cell masks: one fine step of body entries (most
+// blocked candidates stop there); if undecided, the exact body count decides
+// whether the body blocks (then the fine scan finds where) or passes (its
+// remaining entries are counted as examined); then the exact corridor test
+// decides free, or the fine scan finds the corridor's first hit.  Labels and
+// canonical counts are those of the plain scan.
+template <int UN, int B1>
+__device__ inline bool scan_rest_mk(const Params &p, const ToolDev &t, const SwGrid &q,
+                                    const SwFrame &f, int k, uint32_t b, uint32_t e, int body,
+                                    uint32_t &lookups, uint32_t &cchecks, uint32_t &cclear,
+                                    uint32_t &sbody, uint32_t &sfar, const uint32_t c4[3],
+                                    const uint64_t *occ64, uint32_t rmod) {
+  const uint32_t fb = t.far_begin[k];
+  const uint32_t mid = fb > b ? fb : b;
+  const uint32_t seg = 2u * (64u * (uint32_t)k + rmod);
+  if (b < mid) {
+    const uint32_t first_end = mid - b > 64u ? b + 64u : mid;
+    if (!scan_fine_sw<1, B1>(p, t, q, f, b, first_end, body, lookups, sbody)) return false;
+    if (first_end < mid) {
+      const uint32_t cnt = mask_count(t, q, c4, occ64, t.mbegin[seg], t.mbegin[seg + 1]);
+      if ((int)cnt >= p.n_c) {
+        if (!scan_fine_sw<UN, B1>(p, t, q, f, first_end, mid, body, lookups, sbody)) return false;
+      } else {
+        lookups += mid - first_end;
+      }
+    }
+  }
+  if (mid >= e) return true;
+  ++cchecks;
+  if (!mask_any(t, q, c4, occ64, t.mbegin[seg + 1], t.mbegin[seg + 2])) {
+    ++cclear;
+    lookups += e - mid;
+    return true;
+  }
+  return scan_fine_sw<UN, B1>(p, t, q, f, mid, e, body, lookups, sfar);
+}
+
+template <int UN, int CO, int B1>
+__device__ inline bool scan_rest_sw(const Params &p, const ToolDev &t, const SwGrid &q,
+                                    const SwFrame &f, int k, uint32_t b, uint32_t e, int body,
+                                    uint32_t &lookups, uint32_t &cchecks, uint32_t &cclear,
+                                    uint32_t &sbody, uint32_t &sfar, const uint32_t c4[3],
+                                    const uint8_t *occ4) {
+  if (!CO) return scan_fine_sw<UN, B1>(p, t, q, f, b, e, body, lookups, sbody);
+  const uint32_t fb = t.far_begin[k];
+  const uint32_t mid = fb > b ? fb : b;
+  if (!scan_fine_sw<UN, B1>(p, t, q, f, b, mid, body, lookups, sbody)) return false;
+  if (mid >= e) return true;
+  if (CO == 1 ? t.cflag[k] != 0 : t.c4flag[k] != 0) {
+    ++cchecks;
+    if (CO == 1 ? corridor_clear_sw(t, q, f, k) : corridor_clear4_sw(t, q, c4, occ4, k)) {
+      ++cclear;
+      lookups += e - mid;
+      return true;
+    }
+  }
+  return scan_fine_sw<UN, B1>(p, t, q, f, mid, e, body, lookups, sfar);
+}
+
+// k_score_wave with grid-relative lookups (the configurations named "swar").
+// WPE > 0 asks the compiler to fit WPE waves per SIMD (scalar registers are
+// the occupancy limit of this kernel).
+template <int NT, int E, int UN, int FB, int CO, int WPE = 0, int B1 = 0, int MK = 0>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))
+k_score_swar(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t mw,
+             unsigned *work) {
+  static_assert(E >= 1 && E <= 15, "head length must fit the 4-bit planes");
+  static_assert(!B1 || E >= 3, "the one-bit plane serves only entries after the arm samples");
+  static_assert(!MK || E >= 3, "cell masks cover only entries after the arm samples");
+  constexpr int NW = NT / 64;
+  constexpr int ST = E | 1;   // odd row stride of 8-byte entries: no bank conflicts
+  __shared__ uint32_t s_begin[kLdsK + 1];
+  __shared__ uint2 s_head[kLdsK * ST];
+  const int K = t.K;
+  for (int j = threadIdx.x; j <= K; j += NT) s_begin[j] = t.begin[j];
+  __syncthreads();
+  for (int j = threadIdx.x; j < K * E; j += NT) {
+    const int k = j / E, qq = j - k * E;
+    const uint32_t pos = s_begin[k] + (uint32_t)qq;
+    s_head[k * ST + qq] = pos < s_begin[k + 1] ? t.xent[pos] : make_uint2(0u, 0u);
+  }
+  __syncthreads();
+  const SwGrid q = sw_grid(g);
+  const int lane = lane_id();
+  const int64_t wave0 =
+      (int64_t)blockIdx.x * NW + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t nwaves = (int64_t)gridDim.x * NW;
+  // per-wave counters in 32 bits (fewer scalar registers), flushed to the
+  // 64-bit totals whenever the largest of them passes 2^30
+  uint32_t conf = 0, acc = 0, blk = 0, nocand = 0, tests = 0, lookups = 0, deep = 0, chunks = 0;
+  uint32_t cchecks = 0, cclear = 0, sbody = 0, sfar = 0;
+  auto flush = [&]() {
+    if (lane == 0) {
+      if (conf) atomicAdd(&t.counters->n_confident, (unsigned long long)conf);
+      if (acc) atomicAdd(&t.counters->n_accessible, (unsigned long long)acc);
+      if (blk) atomicAdd(&t.counters->n_blocked, (unsigned long long)blk);
+      if (nocand) atomicAdd(&t.counters->n_no_candidate, (unsigned long long)nocand);
+      if (tests) atomicAdd(&t.counters->canonical_tests, (unsigned long long)tests);
+      if (lookups) atomicAdd(&t.counters->canonical_lookups, (unsigned long long)lookups);
+      if (deep) atomicAdd(&t.counters->deep_tests, (unsigned long long)deep);
+      if (chunks) atomicAdd(&t.counters->deep_chunks_max, (unsigned long long)chunks);
+      if (cchecks) atomicAdd(&t.counters->coarse_checks, (unsigned long long)cchecks);
+      if (cclear) atomicAdd(&t.counters->coarse_clear, (unsigned long long)cclear);
+      if (sbody) atomicAdd(&t.counters->chunks_body, (unsigned long long)sbody);
+      if (sfar) atomicAdd(&t.counters->chunks_far, (unsigned long long)sfar);
+    }
+    conf = acc = blk = nocand = tests = lookups = deep = chunks = 0;
+    cchecks = cclear = sbody = sfar = 0;
+  };
+  int64_t i = wave0, batch_end = wave0 + 1;
+  if (FB > 0) {
+    unsigned got = 0;
+    if (lane == 0) got = atomicAdd(work, (unsigned)FB);
+    i = (int64_t)__builtin_amdgcn_readfirstlane(__shfl(got, 0));
+    batch_end = i + FB;
+  }
+  for (; i < n;) {
+    const int hn = __builtin_amdgcn_readfirstlane(pts.has_normal[i]);
+    uint8_t label;
+    int16_t ff = -1;
+    if (hn < 0) {
+      label = AF_UNSCORED;
+    } else {
+      ++conf;
+      int32_t s[3];
+      unpack_key(pts.key[i], s[0], s[1], s[2]);
+      const SwFrame f = sw_frame(g, q, s);
+      uint32_t c4[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) c4[a] = (uint32_t)((s[a] >> 2) - 2 * g.g0[a]);
+      const uint32_t rmod = (uint32_t)(s[0] & 3) | ((uint32_t)(s[1] & 3) << 2) |
+                            ((uint32_t)(s[2] & 3) << 4);
+      label = AF_NO_CANDIDATE;
+      const uint64_t mine = lane < mw ? t.mask[i * mw + lane] : 0ull;
+      for (int w = 0; w < mw && ff < 0; ++w) {
+        const uint64_t word =
+            ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(mine >> 32), w) << 32) |
+            (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)mine, w);
+        if (!word) continue;
+        label = AF_BLOCKED;
+        const int k = 64 * w + lane;
+        const int kk = k < K ? k : K - 1;
+        const bool cand = (word >> lane) & 1ull;
+        const uint32_t len = s_begin[kk + 1] - s_begin[kk];
+        uint2 ent[E];
+        uint32_t code[E];
+#pragma unroll
+        for (int qq = 0; qq < E; ++qq) ent[qq] = s_head[kk * ST + qq];
+#pragma unroll
+        for (int qq = 0; qq < E; ++qq) code[qq] = code_sw(q, f, ent[qq]);
+        // branch-free head decision: hit bits of non-body and body entries,
+        // then the first non-body hit and the n_c-th body hit
+        uint32_t nbm = 0u, bhm = 0u;
+#pragma unroll
+        for (int qq = 0; qq < E; ++qq) {
+          const uint32_t cls = sw_cls(ent[qq]);
+          const uint32_t c = code[qq];
+          const uint32_t hit =
+              (cls == AF_CLS_NEAR ? (uint32_t)(c != 0u) : (c & 1u)) & (uint32_t)(qq < (int)len);
+          nbm |= (hit & (uint32_t)(cls != AF_CLS_BODY)) << qq;
+          bhm |= (hit & (uint32_t)(cls == AF_CLS_BODY)) << qq;
+        }
+        int pos = nbm ? __builtin_ctz(nbm) : 32;
+        {
+          int cnt = 0, p5 = 32;
+#pragma unroll
+          for (int qq = 0; qq < E; ++qq) {
+            cnt += (int)((bhm >> qq) & 1u);
+            p5 = (p5 == 32 && cnt >= p.n_c) ? qq : p5;
+          }
+          pos = p5 < pos ? p5 : pos;
+        }
+        const int body = __popc(bhm);
+        const int state = pos < 32 ? 1 : (len <= (uint32_t)E ? 2 : 0);   // 1 blocked, 2 free
+        const uint64_t fm = __ballot(cand && state == 2);
+        uint64_t open = fm | __ballot(cand && state == 0);
+        const uint32_t v = (cand && state == 1) ? (uint32_t)pos + 1u : 0u;
+        const uint64_t pl[4] = {__ballot(v & 1u), __ballot(v & 2u), __ballot(v & 4u),
+                                __ballot(v & 8u)};
+        uint64_t left = word;
+        for (;;) {
+          if (!open) {
+            tests += (uint32_t)__popcll(left);
+            lookups += plane_sum(pl, left);
+            break;
+          }
+          const int j = __ffsll((long long)open) - 1;
+          open &= open - 1;
+          const uint64_t below = left & ((1ull << j) - 1ull);
+          tests += (uint32_t)__popcll(below) + 1u;
+          lookups += plane_sum(pl, below);
+          left &= ~((2ull << j) - 1ull);
+          const int kj = 64 * w + j;
+          const uint32_t b = s_begin[kj], e = s_begin[kj + 1];
+          if ((fm >> j) & 1ull) {
+            lookups += e - b;
+            ff = (int16_t)kj;
+            break;
+          }
+          lookups += E;
+          ++deep;
+          chunks += (e - b - E + 63) / 64;
+          const bool fr =
+              MK && p.n_c <= 15
+                  ? scan_rest_mk<UN, B1>(p, t, q, f, kj, b + E, e,
+                                         __builtin_amdgcn_readlane(body, j), lookups, cchecks,
+                                         cclear, sbody, sfar, c4, g.occ64, rmod)
+                  : scan_rest_sw<UN, CO, B1>(p, t, q, f, kj, b + E, e,
+                                             __builtin_amdgcn_readlane(body, j), lookups, cchecks,
+                                             cclear, sbody, sfar, c4, g.occ4);
+          if (fr) {
+            ff = (int16_t)kj;
+            break;
+          }
+        }
+      }
+      if (ff >= 0) label = AF_ACCESSIBLE;
+      acc += label == AF_ACCESSIBLE;
+      blk += label == AF_BLOCKED;
+      nocand += label == AF_NO_CANDIDATE;
+    }
+    if (lane == 0) {
+      t.label[i] = label;
+      t.first_free[i] = ff;
+    }
+    if (lookups > (1u << 30) || chunks > (1u << 30)) flush();
+    if (FB > 0) {
+      if (++i >= batch_end) {
+        unsigned got = 0;
+        if (lane == 0) got = atomicAdd(work, (unsigned)FB);
+        i = (int64_t)__builtin_amdgcn_readfirstlane(__shfl(got, 0));
+        batch_end = i + FB;
+      }
+    } else {
+      i += nwaves;
+    }
+  }
+  flush();
+}
+
+__device__ inline uint64_t readlane64(uint64_t v, int l) {
+  return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(v >> 32), l) << 32) |
+         (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+}
+
+// Scoring with the arm samples already evaluated by k_mask (the
+// configurations named "near"): a candidate whose arm sample q hits first is
+// blocked after q + 1 lookups, summed for the whole wave from the two planes;
+// only the others are visited, scanning body and corridor from their fourth
+// entry.  Requires K <= kLdsK.  Same labels, first free orientations and
+// canonical counts as the plain scan.
+template <int NT, int UN, int FB, int CO, int B1>
+__global__ void __launch_bounds__(NT)
+k_score_near(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t mw,
+             unsigned *work) {
+  constexpr int NW = NT / 64;
+  constexpr uint32_t E = 3;   // the arm samples
+  __shared__ uint32_t s_begin[kLdsK + 1];
+  const int K = t.K;
+  for (int j = threadIdx.x; j <= K; j += NT) s_begin[j] = t.begin[j];
+  __syncthreads();
+  const SwGrid q = sw_grid(g);
+  const int lane = lane_id();
+  const int64_t wave0 =
+      (int64_t)blockIdx.x * NW + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t nwaves = (int64_t)gridDim.x * NW;
+  uint32_t conf = 0, acc = 0, blk = 0, nocand = 0, tests = 0, lookups = 0, deep = 0, chunks = 0;
+  uint32_t cchecks = 0, cclear = 0, sbody = 0, sfar = 0;
+  auto flush = [&]() {
+    if (lane == 0) {
+      if (conf) atomicAdd(&t.counters->n_confident, (unsigned long long)conf);
+      if (acc) atomicAdd(&t.counters->n_accessible, (unsigned long long)acc);
+      if (blk) atomicAdd(&t.counters->n_blocked, (unsigned long long)blk);
+      if (nocand) atomicAdd(&t.counters->n_no_candidate, (unsigned long long)nocand);
+      if (tests) atomicAdd(&t.counters->canonical_tests, (unsigned long long)tests);
+      if (lookups) atomicAdd(&t.counters->canonical_lookups, (unsigned long long)lookups);
+      if (deep) atomicAdd(&t.counters->deep_tests, (unsigned long long)deep);
+      if (chunks) atomicAdd(&t.counters->deep_chunks_max, (unsigned long long)chunks);
+      if (cchecks) atomicAdd(&t.counters->coarse_checks, (unsigned long long)cchecks);
+      if (cclear) atomicAdd(&t.counters->coarse_clear, (unsigned long long)cclear);
+      if (sbody) atomicAdd(&t.counters->chunks_body, (unsigned long long)sbody);
+      if (sfar) atomicAdd(&t.counters->chunks_far, (unsigned long long)sfar);
+    }
+    conf = acc = blk = nocand = tests = lookups = deep = chunks = 0;
+    cchecks = cclear = sbody = sfar = 0;
+  };
+  int64_t i = wave0, batch_end = wave0 + 1;
+  if (FB > 0) {
+    unsigned got = 0;
+    if (lane == 0) got = atomicAdd(work, (unsigned)FB);
+    i = (int64_t)__builtin_amdgcn_readfirstlane(__shfl(got, 0));
+    batch_end = i + FB;
+  }
+  for (; i < n;) {
+    const int hn = __builtin_amdgcn_readfirstlane(pts.has_normal[i]);
+    uint8_t label;
+    int16_t ff = -1;
+    if (hn < 0) {
+      label = AF_UNSCORED;
+    } else {
+      ++conf;
+      int32_t s[3];
+      unpack_key(pts.key[i], s[0], s[1], s[2]);
+      const SwFrame f = sw_frame(g, q, s);
+      uint32_t c4[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) c4[a] = (uint32_t)((s[a] >> 2) - 2 * g.g0[a]);
+      label = AF_NO_CANDIDATE;
+      // lanes [0, mw): mask words; [mw, 3 mw): the two arm-sample planes
+      const uint64_t mine = lane < mw       ? t.mask[i * mw + lane]
+                            : lane < 3 * mw ? t.nearp[i * 2 * mw + (lane - mw)]
+                                            : 0ull;
+      for (int w = 0; w < mw && ff < 0; ++w) {
+        const uint64_t word = readlane64(mine, w);
+        if (!word) continue;
+        label = AF_BLOCKED;
+        const uint64_t pl[4] = {readlane64(mine, mw + w) & word,
+                                readlane64(mine, 2 * mw + w) & word, 0ull, 0ull};
+        uint64_t open = word & ~(pl[0] | pl[1]);
+        uint64_t left = word;
+        for (;;) {
+          if (!open) {   // the rest are blocked by an arm sample
+            tests += (uint32_t)__popcll(left);
+            lookups += plane_sum(pl, left);
+            break;
+          }
+          const int j = __ffsll((long long)open) - 1;
+          open &= open - 1;
+          const uint64_t below = left & ((1ull << j) - 1ull);
+          tests += (uint32_t)__popcll(below) + 1u;
+          lookups += plane_sum(pl, below);
+          left &= ~((2ull << j) - 1ull);
+          const int kj = 64 * w + j;
+          const uint32_t b = s_begin[kj], e = s_begin[kj + 1];
+          lookups += E;
+          ++deep;
+          chunks += (e - b - E + 63) / 64;
+          if (scan_rest_sw<UN, CO, B1>(p, t, q, f, kj, b + E, e, 0, lookups, cchecks, cclear,
+                                       sbody, sfar, c4, g.occ4)) {
+            ff = (int16_t)kj;
+            break;
+          }
+        }
+      }
+      if (ff >= 0) label = AF_ACCESSIBLE;
+      acc += label == AF_ACCESSIBLE;
+      blk += label == AF_BLOCKED;
+      nocand += label == AF_NO_CANDIDATE;
+    }
+    if (lane == 0) {
+      t.label[i] = label;
+      t.first_free[i] = ff;
+    }
+    if (lookups > (1u << 30) || chunks > (1u << 30)) flush();
+    if (FB > 0) {
+      if (++i >= batch_end) {
+        unsigned got = 0;
+        if (lane == 0) got = atomicAdd(work, (unsigned)FB);
+        i = (int64_t)__builtin_amdgcn_readfirstlane(__shfl(got, 0));
+        batch_end = i + FB;
+      }
+    } else {
+      i += nwaves;
+    }
+  }
+  flush();
+}
+
 using ScoreKernel = void (*)(Params, PointsDev, ToolDev, GridDev, int64_t, int32_t, unsigned *);
 
 struct ScoreVariant {
@@ -830,6 +1648,42 @@ const ScoreVariant kVariants[] = {
     {k_score_fast<256, 8, 2, 16, 1>, 256, "fast wg256 head8 unroll2 dyn16 coarse", 1},
     {k_score_fast<256, 6, 2, 16, 1>, 256, "fast wg256 head6 unroll2 dyn16 coarse", 1},
     {k_score_fast<512, 4, 2, 16, 1>, 512, "fast wg512 head4 unroll2 dyn16 coarse", 1},
+    {k_score_wave<256, 4, 2, 16, 1>, 256, "wave wg256 head4 unroll2 dyn16 coarse", 1},
+    {k_score_wave<256, 4, 1, 16, 1>, 256, "wave wg256 head4 unroll1 dyn16 coarse", 1},
+    {k_score_wave<256, 4, 2, 16, 0>, 256, "wave wg256 head4 unroll2 dyn16", 1},
+    {k_score_wave<256, 8, 2, 16, 1>, 256, "wave wg256 head8 unroll2 dyn16 coarse", 1},
+    {k_score_wave<256, 6, 2, 16, 1>, 256, "wave wg256 head6 unroll2 dyn16 coarse", 1},
+    {k_score_wave<256, 2, 2, 16, 1>, 256, "wave wg256 head2 unroll2 dyn16 coarse", 1},
+    {k_score_wave<256, 4, 4, 16, 1>, 256, "wave wg256 head4 unroll4 dyn16 coarse", 1},
+    {k_score_wave<256, 4, 2, 4, 1>, 256, "wave wg256 head4 unroll2 dyn4 coarse", 1},
+    {k_score_swar<256, 4, 1, 16, 1>, 256, "swar wg256 head4 unroll1 dyn16 coarse", 1},
+    {k_score_swar<256, 4, 2, 16, 1>, 256, "swar wg256 head4 unroll2 dyn16 coarse", 1},
+    {k_score_swar<256, 4, 1, 16, 0>, 256, "swar wg256 head4 unroll1 dyn16", 1},
+    {k_score_swar<256, 6, 1, 16, 1>, 256, "swar wg256 head6 unroll1 dyn16 coarse", 1},
+    {k_score_swar<256, 3, 1, 16, 1>, 256, "swar wg256 head3 unroll1 dyn16 coarse", 1},
+    {k_score_swar<256, 4, 1, 4, 1>, 256, "swar wg256 head4 unroll1 dyn4 coarse", 1},
+    {k_score_swar<512, 4, 1, 16, 1>, 512, "swar wg512 head4 unroll1 dyn16 coarse", 1},
+    {k_score_swar<256, 4, 1, 16, 2>, 256, "swar wg256 head4 unroll1 dyn16 coarse4", 1},
+    {k_score_swar<256, 3, 1, 16, 2>, 256, "swar wg256 head3 unroll1 dyn16 coarse4", 1},
+    {k_score_swar<256, 4, 2, 16, 2>, 256, "swar wg256 head4 unroll2 dyn16 coarse4", 1},
+    {k_score_swar<256, 3, 1, 16, 2, 0, 1>, 256, "swar wg256 head3 unroll1 dyn16 coarse4 bit", 1},
+    {k_score_near<256, 1, 16, 2, 1>, 256, "near wg256 unroll1 dyn16 coarse4 bit", 1},
+    {k_score_near<256, 1, 16, 2, 0>, 256, "near wg256 unroll1 dyn16 coarse4", 1},
+    {k_score_near<256, 2, 16, 2, 1>, 256, "near wg256 unroll2 dyn16 coarse4 bit", 1},
+    {k_score_near<256, 1, 8, 2, 1>, 256, "near wg256 unroll1 dyn8 coarse4 bit", 1},
+    {k_score_near<256, 1, 32, 2, 1>, 256, "near wg256 unroll1 dyn32 coarse4 bit", 1},
+    {k_score_near<512, 1, 16, 2, 1>, 512, "near wg512 unroll1 dyn16 coarse4 bit", 1},
+    {k_score_swar<256, 3, 1, 16, 2, 0, 1, 1>, 256, "swar wg256 head3 unroll1 dyn16 bit masks", 1},
+    {k_score_swar<256, 3, 2, 16, 2, 0, 1, 1>, 256, "swar wg256 head3 unroll2 dyn16 bit masks", 1},
+    {k_score_swar<256, 4, 1, 16, 2, 0, 1, 1>, 256, "swar wg256 head4 unroll1 dyn16 bit masks", 1},
+    {k_score_swar<256, 3, 1, 16, 2, 0, 0, 1>, 256, "swar wg256 head3 unroll1 dyn16 masks", 1},
+    {k_score_swar<256, 4, 1, 16, 2, 0, 1>, 256, "swar wg256 head4 unroll1 dyn16 coarse4 bit", 1},
+    {k_score_swar<256, 3, 2, 16, 2, 0, 1>, 256, "swar wg256 head3 unroll2 dyn16 coarse4 bit", 1},
+    {k_score_swar<256, 3, 1, 16, 1, 0, 1>, 256, "swar wg256 head3 unroll1 dyn16 coarse bit", 1},
+    {k_score_swar<256, 4, 1, 16, 1, 8>, 256, "swar wg256 head4 unroll1 dyn16 coarse wpe8", 1},
+    {k_score_swar<256, 3, 1, 16, 1, 8>, 256, "swar wg256 head3 unroll1 dyn16 coarse wpe8", 1},
+    {k_score_swar<256, 4, 1, 16, 0, 8>, 256, "swar wg256 head4 unroll1 dyn16 wpe8", 1},
+    {k_score_swar<256, 4, 2, 16, 1, 8>, 256, "swar wg256 head4 unroll2 dyn16 coarse wpe8", 1},
 };
 constexpr int kNumVariants = (int)(sizeof(kVariants) / sizeof(kVariants[0]));
 int g_resident[kNumVariants];   // workgroups per CU, from the occupancy query
@@ -871,11 +1725,12 @@ void launch_normals(const Params &p, MapDev m, PointsDev pts, GridDev g, int64_t
                      0, s, p, m, pts, g, n);
 }
 
-void launch_mask(const Params &p, PointsDev pts, ToolDev t, int64_t n, hipStream_t s) {
+void launch_mask(const Params &p, PointsDev pts, ToolDev t, GridDev g, int64_t n,
+                 hipStream_t s) {
   int32_t mw = (t.K + 63) / 64;
   if (n <= 0) return;
   hipLaunchKernelGGL(k_mask, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0,
-                     s, p, pts, t, n, mw);
+                     s, p, pts, t, g, n, mw);
 }
 
 int score_variants() { return kNumVariants; }

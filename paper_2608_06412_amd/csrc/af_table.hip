@@ -6,6 +6,8 @@
 // writes packed entries: 3 arm samples, then body, then corridor.
 #include "af_internal.h"
 
+#include <algorithm>
+
 #pragma clang fp contract(off)
 
 namespace af {
@@ -142,16 +144,19 @@ __global__ void k_table_scan(int32_t K, const uint32_t *counts, uint32_t *begin)
   begin[K] = acc;
 }
 
-// Coarse corridor list of orientation k: every brick offset floor((r + o)/8)
-// (r in [0, 8)^3, o a corridor entry), as a bitmap over the bounding box of
-// those offsets, compacted in linear order.  A bounding box above kCoarseBits
-// cells leaves the orientation without a list (cflag = 0).
+// Coarse corridor list of orientation k for cells of C = 2^SH voxels per
+// axis: every cell offset floor((r + o)/C) (r in [0, C)^3 the point's
+// position inside its cell, o a corridor entry), as a bitmap over the
+// bounding box of those offsets, compacted in linear order.  A bounding box
+// above kCoarseBits cells leaves the orientation without a list (cflag = 0).
 constexpr int kCoarseBits = 1 << 18;
 
+template <int SH>
 __global__ void __launch_bounds__(256)
 k_table_coarse(int32_t K, const uint32_t *begin, const uint32_t *counts, const uint32_t *entries,
                uint32_t *far_begin, uint32_t *ccounts, const uint32_t *cbegin,
                uint32_t *centries, uint8_t *cflag, int pass) {
+  constexpr int CM = (1 << SH) - 1;
   __shared__ uint32_t bits[kCoarseBits / 32];
   __shared__ int lo[3], hi[3];
   __shared__ uint32_t part[256];
@@ -167,8 +172,8 @@ k_table_coarse(int32_t K, const uint32_t *begin, const uint32_t *counts, const u
     const uint32_t en = entries[j];
     const int o[3] = {entry_x(en), entry_y(en), entry_z(en)};
     for (int a = 0; a < 3; ++a) {
-      atomicMin(&lo[a], o[a] >> 3);
-      atomicMax(&hi[a], (o[a] + 7) >> 3);
+      atomicMin(&lo[a], o[a] >> SH);
+      atomicMax(&hi[a], (o[a] + CM) >> SH);
     }
   }
   __syncthreads();
@@ -189,9 +194,9 @@ k_table_coarse(int32_t K, const uint32_t *begin, const uint32_t *counts, const u
     const uint32_t en = entries[j];
     const int o[3] = {entry_x(en), entry_y(en), entry_z(en)};
     for (int c = 0; c < 8; ++c) {
-      const int bx = ((o[0] + ((c & 1) ? 7 : 0)) >> 3) - lo[0];
-      const int by = ((o[1] + ((c & 2) ? 7 : 0)) >> 3) - lo[1];
-      const int bz = ((o[2] + ((c & 4) ? 7 : 0)) >> 3) - lo[2];
+      const int bx = ((o[0] + ((c & 1) ? CM : 0)) >> SH) - lo[0];
+      const int by = ((o[1] + ((c & 2) ? CM : 0)) >> SH) - lo[1];
+      const int bz = ((o[2] + ((c & 4) ? CM : 0)) >> SH) - lo[2];
       const int idx = (bz * dy + by) * dx + bx;
       atomicOr(&bits[idx >> 5], 1u << (idx & 31));
     }
@@ -237,14 +242,44 @@ __global__ void k_coarse_scan(int32_t K, const uint32_t *ccounts, uint32_t *cbeg
   cbegin[K] = acc;
 }
 
+__global__ void k_table_grid(const uint32_t *entries, int64_t n, const uint32_t *centries,
+                             int64_t nc, int32_t gx, int32_t gxy, uint2 *xent, int32_t *cdelta) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const uint32_t e = entries[i];
+    const int ox = entry_x(e), oy = entry_y(e), oz = entry_z(e);
+    const int32_t d = (ox >> 3) + gx * (oy >> 3) + gxy * (oz >> 3);
+    const uint32_t o7 = (uint32_t)(ox & 7) | ((uint32_t)(oy & 7) << 4) |
+                        ((uint32_t)(oz & 7) << 8) | ((uint32_t)entry_cls(e) << 30);
+    xent[i] = make_uint2((uint32_t)d, o7);
+  }
+  if (i < nc) {
+    const uint32_t e = centries[i];
+    cdelta[i] = entry_x(e) + gx * entry_y(e) + gxy * entry_z(e);
+  }
+}
+
 }  // namespace
+
+int launch_table_grid(const ToolDev &t, const GridDev &g, hipStream_t s) {
+  const int64_t n = std::max(t.n_entries, t.n_centries);
+  if (n <= 0) return 0;
+  hipLaunchKernelGGL(k_table_grid, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, t.entries,
+                     t.n_entries, t.centries, t.n_centries, g.gd[0], g.gd[0] * g.gd[1], t.xent,
+                     t.cdelta);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
 
 int launch_table_coarse(int32_t K, const uint32_t *begin, const uint32_t *counts,
                         const uint32_t *entries, uint32_t *far_begin, uint32_t *ccounts,
-                        uint32_t *cbegin, uint32_t *centries, uint8_t *cflag, int pass,
+                        uint32_t *cbegin, uint32_t *centries, uint8_t *cflag, int pass, int sh,
                         hipStream_t s) {
-  hipLaunchKernelGGL(k_table_coarse, dim3((unsigned)K), dim3(256), 0, s, K, begin, counts, entries,
-                     far_begin, ccounts, cbegin, centries, cflag, pass);
+  if (sh == 3)
+    hipLaunchKernelGGL(k_table_coarse<3>, dim3((unsigned)K), dim3(256), 0, s, K, begin, counts,
+                       entries, far_begin, ccounts, cbegin, centries, cflag, pass);
+  else
+    hipLaunchKernelGGL(k_table_coarse<2>, dim3((unsigned)K), dim3(256), 0, s, K, begin, counts,
+                       entries, far_begin, ccounts, cbegin, centries, cflag, pass);
   if (pass == 0) hipLaunchKernelGGL(k_coarse_scan, dim3(1), dim3(1), 0, s, K, ccounts, cbegin);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
