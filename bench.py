@@ -36,9 +36,6 @@ METRIC = ("point×orientation tests/s + returns integrated/s; p99 frame latency 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_score_tree.json")
 SCORE_SRC = os.path.join(ROOT, "paper_2608_06412_amd", "csrc", "af_score.hip")
-# scoring configuration timed by default (the one the autotuner picks on this
-# workload); --tune re-runs the tuner after the warm-up instead
-DEFAULT_VARIANT = "near wg256 unroll1 dyn16 coarse4 bit"
 # kernels whose per-launch device time the bench reports (symbol prefixes)
 TRACE_KERNELS = ("k_score", "k_integrate_fold", "k_normals", "k_mask")
 
@@ -53,10 +50,17 @@ def src_sha(path):
 
 
 def score_bytes(lookups, confident, K):
-    """Algorithmic bytes of the scoring kernel: an 8-byte voxel record per
+    """Algorithmic bytes of the scoring step: an 8-byte voxel record per
     canonical lookup plus, per confident point, its key (8), candidate mask
     (K/8), weight (4) and outputs (3)."""
     return 8.0 * lookups + confident * (8 + K / 8 + 4 + 3)
+
+
+def kscore_bytes(lookups, arm_lookups, confident, K):
+    """The scoring kernel's own share: canonical lookups less the arm samples
+    whose result the mask kernel precomputed, plus per confident point its
+    key, mask and the two arm-sample planes (3 K/8), weight and outputs."""
+    return 8.0 * (lookups - arm_lookups) + confident * (8 + 3 * K / 8 + 4 + 3)
 
 
 def cpu_baseline(w, frames, n_frames, n_points, seed=17):
@@ -126,12 +130,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--latency-frames", type=int, default=100)
     ap.add_argument("--cpu-frames", type=int, default=12)
-    ap.add_argument("--cpu-points", type=int, default=1500)
+    ap.add_argument("--cpu-points", type=int, default=100000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tune", action="store_true",
                     help="autotune the scoring kernel after the warm-up")
-    ap.add_argument("--score-variant", default=DEFAULT_VARIANT,
-                    help="scoring configuration (index or name) when not tuning")
+    ap.add_argument("--score-variant", default=None,
+                    help="scoring configuration (index or name) when not tuning; default: "
+                         "the library's default configuration")
     ap.add_argument("--trace-summary", default=None,
                     help="only summarise a rocprofv3 kernel_trace.csv of a bench run "
                          "with the same --warmup/--steps")
@@ -184,7 +189,7 @@ def main():
     Krot = len(w.rot)
 
     names = ctx.score_variants()
-    if not args.tune:
+    if not args.tune and args.score_variant is not None:
         v = args.score_variant
         idx = int(v) if str(v).isdigit() else names.index(v)
         ctx.set_score_variant(idx)
@@ -208,7 +213,7 @@ def main():
     ctx.timing_read(reset=True)
     tests = lookups = conf = nominal = returns = accessible = deep = deep_chunks = cand = 0
     cchecks = cclear = cbody = cfar = 0
-    byts = 0.0
+    byts = kbyts = 0.0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(W, W + K):
@@ -228,6 +233,7 @@ def main():
         cfar += st["chunks_far"]
         cand += st["candidate_tests"]
         byts += score_bytes(st["canonical_lookups"], st["n_confident"], Krot)
+        kbyts += kscore_bytes(st["canonical_lookups"], st["arm_lookups"], st["n_confident"], Krot)
         returns += len(frames[i].xyz)
         if (i - W) % 50 == 0:
             log("timed frame %d: %d points, %d confident, %d canonical tests" %
@@ -261,7 +267,9 @@ def main():
                "k_normals": tm["k_normals_ms"], "k_mask": tm["k_mask_ms"]}
     dominant = max(kernels, key=kernels.get)
     score_s = tm["k_score_ms"] / 1e3
-    achieved = byts / score_s / 1e9 if score_s > 0 else 0.0
+    achieved = kbyts / score_s / 1e9 if score_s > 0 else 0.0
+    path_s = (tm["k_score_ms"] + tm["k_mask_ms"]) / 1e3
+    path_achieved = byts / path_s / 1e9 if path_s > 0 else 0.0
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         tr = json.load(open(TRAFFIC_FILE))
@@ -270,7 +278,13 @@ def main():
     roofline = {"kernel": "k_score", "bound": "hbm", "achieved": achieved,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                 "traffic": traffic,
-                "algorithmic_bytes_per_launch": byts / max(K, 1),
+                "algorithmic_bytes_per_launch": kbyts / max(K, 1),
+                "bytes_model": "8 B per canonical lookup not answered by the mask kernel + "
+                               "per confident point 8 B key + 3K/8 B mask and arm planes + "
+                               "4 B weight + 3 B outputs",
+                "score_path": {"kernels": "k_mask + k_score",
+                               "algorithmic_bytes_per_step": byts / max(K, 1),
+                               "achieved": path_achieved, "frac": path_achieved / HBM_PEAK_GBS},
                 "avg_launch_ms": tm["k_score_ms"] / max(tm["score_calls"], 1),
                 "dominant_kernel": dominant}
 

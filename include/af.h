@@ -109,10 +109,13 @@ typedef struct af_score_stats {
    * canonical tests not decided by the first table entries read per lane,
    * and the 64-entry chunks a full scan of those tests would take; coarse
    * corridor checks made and those that found every corridor brick clear;
-   * 64-entry steps the deep scans took over body and over corridor entries */
+   * 64-entry steps the deep scans took over body and over corridor entries;
+   * the canonical lookups of arm samples whose result the mask pass
+   * precomputed (configurations "near"; included in canonical_lookups) */
   int64_t deep_tests, deep_chunks_max;
   int64_t coarse_checks, coarse_clear;
   int64_t chunks_body, chunks_far;
+  int64_t arm_lookups;
 } af_score_stats;
 
 /* Fill *cfg with the paper's constants for voxel size `voxel` and truncation
@@ -226,15 +229,21 @@ int af_timing_enable(af_ctx *ctx, int on);
 /* Synchronises the pending events, fills *out, and zeroes the sums if reset. */
 int af_timing_read(af_ctx *ctx, af_timing *out, int reset);
 
-/* Scoring kernel configurations (workgroup size, LDS staging of the tables,
- * look-ahead over candidate orientations, unrolling, per-brick occupancy
- * skip, dynamic point fetch).  All give identical labels; they differ in
- * speed only.  af_tune_score times every configuration `reps` times on the
+/* Scoring kernel configurations: "plain" (one orientation at a time, any K),
+ * "swar" (candidate-parallel first entries, grid-relative lookups) and "near"
+ * (arm samples taken from the mask pass), with unrolling, dynamic point
+ * fetch, the 4^3-cell corridor skip ("coarse4") and the one-bit occupancy
+ * plane ("bit") as options.  All give identical labels, first free
+ * orientations and canonical counts; they differ in speed only.  A new
+ * context uses af_score_variant_default(); configurations that need K <= 256
+ * fall back to configuration 0 for larger K.  af_tune_score times every
+ * configuration `reps` times on the
  * context's current map and tool (HIP events on `stream`), keeps the fastest
  * for later af_score_points calls, writes its index to *best and, if
  * ms_per_variant is not NULL, each configuration's mean time (host array of
  * af_score_variant_count() floats).  Synchronises `stream`. */
 int af_score_variant_count(void);
+int af_score_variant_default(void);
 const char *af_score_variant_name(int32_t v);
 int af_set_score_variant(af_ctx *ctx, int32_t v);
 int32_t af_get_score_variant(af_ctx *ctx);

@@ -66,7 +66,7 @@ class ScoreStats(ctypes.Structure):
                  "n_no_candidate", "candidate_tests", "canonical_tests",
                  "canonical_lookups", "deep_tests", "deep_chunks_max",
                                    "coarse_checks", "coarse_clear", "chunks_body",
-                                   "chunks_far")]
+                                   "chunks_far", "arm_lookups")]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -105,6 +105,7 @@ SIGNATURES = {
     "af_timing_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "af_timing_read": (ctypes.c_int, [_vp, ctypes.POINTER(Timing), ctypes.c_int]),
     "af_score_variant_count": (ctypes.c_int, []),
+    "af_score_variant_default": (ctypes.c_int, []),
     "af_score_variant_name": (ctypes.c_char_p, [_i32]),
     "af_set_score_variant": (ctypes.c_int, [_vp, _i32]),
     "af_get_score_variant": (_i32, [_vp]),
@@ -319,6 +320,9 @@ class Context:
 
     def score_variant(self) -> int:
         return self._lib.af_get_score_variant(self.h)
+
+    def score_variant_default(self) -> int:
+        return self._lib.af_score_variant_default()
 
     def tune_score(self, tool_id: int, reps: int = 3, stream=None):
         """Time every scoring configuration on the current map; keep the

@@ -28,7 +28,7 @@ struct af_ctx {
   FrameCounters *counters;      // device
   FrameCounters *counters_host; // pinned
   std::vector<ToolDev> tools;
-  std::vector<int64_t> tool_bytes, tool_cbytes;
+  std::vector<int64_t> tool_bytes;
   uint64_t *mask;               // shared candidate-mask scratch
   uint64_t *nearp;              // shared arm-sample planes
   unsigned *work;               // point counter of the dynamic score variants
@@ -144,57 +144,6 @@ int hip_check(af_ctx *c, const char *where) {
   return AF_OK;
 }
 
-// Exact 4^3-cell masks of every orientation's body and corridor entries, for
-// each position r of the point's voxel modulo 4: entry o lands in cell
-// floor((r + o) / 4) (relative to the point's cell) at bit position
-// ((r + o) mod 4) per axis.  Cells are listed in order of first appearance
-// in the table.  Layout as described for ToolDev::mbegin.
-void build_cell_masks(const std::vector<uint32_t> &ent, const std::vector<uint32_t> &begin,
-                      int32_t K, std::vector<uint32_t> &mbeg, std::vector<uint32_t> &mcell,
-                      std::vector<uint64_t> &mmask) {
-  mbeg.assign(128 * (size_t)K + 1, 0u);
-  std::vector<int32_t> slot;   // cell -> list index, over a bounding box
-  for (int32_t k = 0; k < K; ++k) {
-    const uint32_t b = begin[k] + 3, e = begin[k + 1];
-    int lo[3] = {1 << 20, 1 << 20, 1 << 20}, hi[3] = {-(1 << 20), -(1 << 20), -(1 << 20)};
-    for (uint32_t j = b; j < e; ++j) {
-      const int o[3] = {entry_x(ent[j]), entry_y(ent[j]), entry_z(ent[j])};
-      for (int a = 0; a < 3; ++a) {
-        lo[a] = std::min(lo[a], o[a] >> 2);
-        hi[a] = std::max(hi[a], (o[a] + 3) >> 2);
-      }
-    }
-    const int dx = std::max(0, hi[0] - lo[0] + 1), dy = std::max(0, hi[1] - lo[1] + 1),
-              dz = std::max(0, hi[2] - lo[2] + 1);
-    slot.assign((size_t)dx * dy * dz, -1);
-    for (int r = 0; r < 64; ++r) {
-      const int rr[3] = {r & 3, (r >> 2) & 3, (r >> 4) & 3};
-      for (int part = 0; part < 2; ++part) {
-        mbeg[2 * (64 * (size_t)k + r) + part] = (uint32_t)mcell.size();
-        const size_t first = mcell.size();
-        std::vector<size_t> used;
-        for (uint32_t j = b; j < e; ++j) {
-          const uint32_t en = ent[j];
-          if ((entry_cls(en) == AF_CLS_BODY) != (part == 0)) continue;
-          const int v[3] = {rr[0] + entry_x(en), rr[1] + entry_y(en), rr[2] + entry_z(en)};
-          const int cx = v[0] >> 2, cy = v[1] >> 2, cz = v[2] >> 2;
-          const size_t si = ((size_t)(cz - lo[2]) * dy + (cy - lo[1])) * dx + (cx - lo[0]);
-          if (slot[si] < 0) {
-            slot[si] = (int32_t)(mcell.size() - first);
-            used.push_back(si);
-            mcell.push_back(pack_entry(cx, cy, cz, 0));
-            mmask.push_back(0ull);
-          }
-          const int bit = (v[0] & 3) | ((v[1] & 3) << 2) | ((v[2] & 3) << 4);
-          mmask[first + (size_t)slot[si]] |= 1ull << bit;
-        }
-        for (size_t si : used) slot[si] = -1;
-      }
-    }
-  }
-  mbeg[128 * (size_t)K] = (uint32_t)mcell.size();
-}
-
 // Bricks of margin the grid keeps around every allocated block: every table
 // lookup of a point (its brick plus any offset of any tool) stays inside the
 // grid, so lookups need no bounds test.
@@ -236,7 +185,6 @@ int ensure_grid(af_ctx *c, hipStream_t s, bool &rebuilt) {
     dev_free(c, g.occ_any, sizeof(uint32_t) * ((c->grid_bricks + 31) / 32));
     dev_free(c, g.occ4, c->grid_bricks);
     dev_free(c, g.occ1, sizeof(uint32_t) * 16 * c->grid_bricks);
-    dev_free(c, g.occ64, sizeof(uint64_t) * 8 * c->grid_bricks);
     c->grid_bricks = 0;
   }
   ALLOC(c, ng.pred, nb * 32);
@@ -244,7 +192,6 @@ int ensure_grid(af_ctx *c, hipStream_t s, bool &rebuilt) {
   ALLOC(c, ng.occ_any, (nb + 31) / 32);
   ALLOC(c, ng.occ4, nb);
   ALLOC(c, ng.occ1, nb * 16);
-  ALLOC(c, ng.occ64, nb * 8);
   c->grid = ng;
   c->grid_bricks = nb;
   launch_grid_fill(c->grid, s);
@@ -441,11 +388,11 @@ int af_create(const af_config *cfg, af_ctx **out) {
   CREATE_ALLOC(q.n_points, 1);
   CREATE_ALLOC(c->counters, 1);
   CREATE_ALLOC(c->work, 1);
+  c->score_variant = score_variant_default();
   CREATE_ALLOC(c->mask, NP * ((cfg->max_orientations + 63) / 64));
   CREATE_ALLOC(c->nearp, NP * 2 * ((cfg->max_orientations + 63) / 64));
   c->tools.assign(cfg->max_tools, ToolDev());
   c->tool_bytes.assign(cfg->max_tools, 0);
-  c->tool_cbytes.assign(cfg->max_tools, 0);
   for (auto &t : c->tools) memset(&t, 0, sizeof(t));
   if (hipHostMalloc((void **)&c->counters_host, sizeof(FrameCounters)) != hipSuccess)
     return bail(AF_ENOMEM);
@@ -526,18 +473,11 @@ int af_set_tool_kernels(af_ctx *c, int32_t tool_id, const af_tool *tool, int32_t
     dev_free(c, t.first_free, sizeof(int16_t) * c->cfg.max_points);
     dev_free(c, t.counters, sizeof(ScoreCounters));
     dev_free(c, t.far_begin, sizeof(uint32_t) * t.K);
-    dev_free(c, t.cbegin, sizeof(uint32_t) * (t.K + 1));
-    dev_free(c, t.cflag, t.K);
-    dev_free(c, t.centries, c->tool_cbytes[tool_id]);
     dev_free(c, t.same, sizeof(uint64_t) * ((t.K + 63) / 64));
     dev_free(c, t.xent, sizeof(uint2) * std::max<int64_t>(1, t.n_entries));
-    dev_free(c, t.cdelta, sizeof(int32_t) * std::max<int64_t>(1, t.n_centries));
     dev_free(c, t.c4begin, sizeof(uint32_t) * (t.K + 1));
     dev_free(c, t.c4flag, t.K);
     dev_free(c, t.c4entries, sizeof(uint32_t) * std::max<int64_t>(1, t.n_c4entries));
-    dev_free(c, t.mbegin, sizeof(uint32_t) * (128 * (int64_t)t.K + 1));
-    dev_free(c, t.mcell, sizeof(uint32_t) * std::max<int64_t>(1, t.n_masks));
-    dev_free(c, t.mmask, sizeof(uint64_t) * std::max<int64_t>(1, t.n_masks));
     memset(&t, 0, sizeof(t));
   }
   ToolDev nt;
@@ -585,23 +525,10 @@ int af_set_tool_kernels(af_ctx *c, int32_t tool_id, const af_tool *tool, int32_t
   HIP_TRY(c, hipMemsetAsync(nt.label, 0, c->cfg.max_points, s));
   HIP_TRY(c, hipMemsetAsync(nt.counters, 0, sizeof(ScoreCounters), s));
   HIP_TRY(c, hipMemcpyAsync(&herr, err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  // coarse corridor lists
   uint32_t *ccounts = nullptr;
   ALLOC(c, nt.far_begin, K);
-  ALLOC(c, nt.cbegin, K + 1);
-  ALLOC(c, nt.cflag, K);
   ALLOC(c, ccounts, K);
-  if (launch_table_coarse(K, nt.begin, counts, nt.entries, nt.far_begin, ccounts, nt.cbegin,
-                          nullptr, nt.cflag, 0, 3, s) != 0)
-    return hip_check(c, "coarse count");
-  uint32_t ctotal = 0;
-  HIP_TRY(c, hipMemcpyAsync(&ctotal, nt.cbegin + K, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-  HIP_TRY(c, hipStreamSynchronize(s));
-  ALLOC(c, nt.centries, ctotal);
-  if (launch_table_coarse(K, nt.begin, counts, nt.entries, nt.far_begin, ccounts, nt.cbegin,
-                          nt.centries, nt.cflag, 1, 3, s) != 0)
-    return hip_check(c, "coarse fill");
-  // 4^3-cell lists
+  // coarse corridor lists over 4^3 cells
   ALLOC(c, nt.c4begin, K + 1);
   ALLOC(c, nt.c4flag, K);
   if (launch_table_coarse(K, nt.begin, counts, nt.entries, nt.far_begin, ccounts, nt.c4begin,
@@ -620,7 +547,6 @@ int af_set_tool_kernels(af_ctx *c, int32_t tool_id, const af_tool *tool, int32_t
   dev_free(c, counts, sizeof(uint32_t) * 2 * K);
   dev_free(c, err, sizeof(int32_t));
   if (herr) return fail(c, AF_EINVAL, "tool table build failed (%d)", herr);
-  c->tool_cbytes[tool_id] = sizeof(uint32_t) * (int64_t)ctotal;
   {
     std::vector<uint32_t> he(total);
     HIP_TRY(c, hipMemcpy(he.data(), nt.entries, sizeof(uint32_t) * total, hipMemcpyDeviceToHost));
@@ -628,28 +554,9 @@ int af_set_tool_kernels(af_ctx *c, int32_t tool_id, const af_tool *tool, int32_t
     for (uint32_t e : he)
       reach = std::max({reach, std::abs(entry_x(e)), std::abs(entry_y(e)), std::abs(entry_z(e))});
     nt.reach = reach;
-    std::vector<uint32_t> hb(K + 1);
-    HIP_TRY(c, hipMemcpy(hb.data(), nt.begin, sizeof(uint32_t) * (K + 1), hipMemcpyDeviceToHost));
-    std::vector<uint32_t> mbeg, mcell;
-    std::vector<uint64_t> mmask;
-    build_cell_masks(he, hb, K, mbeg, mcell, mmask);
-    nt.n_masks = (int64_t)mcell.size();
-    ALLOC(c, nt.mbegin, 128 * (int64_t)K + 1);
-    ALLOC(c, nt.mcell, std::max<int64_t>(1, nt.n_masks));
-    ALLOC(c, nt.mmask, std::max<int64_t>(1, nt.n_masks));
-    HIP_TRY(c, hipMemcpy(nt.mbegin, mbeg.data(), sizeof(uint32_t) * mbeg.size(),
-                         hipMemcpyHostToDevice));
-    if (nt.n_masks) {
-      HIP_TRY(c, hipMemcpy(nt.mcell, mcell.data(), sizeof(uint32_t) * mcell.size(),
-                           hipMemcpyHostToDevice));
-      HIP_TRY(c, hipMemcpy(nt.mmask, mmask.data(), sizeof(uint64_t) * mmask.size(),
-                           hipMemcpyHostToDevice));
-    }
   }
   nt.n_entries = total;
-  nt.n_centries = ctotal;
   ALLOC(c, nt.xent, std::max<int64_t>(1, total));
-  ALLOC(c, nt.cdelta, std::max<int64_t>(1, ctotal));
   nt.K = K;
   nt.mask = c->mask;
   nt.nearp = c->nearp;
@@ -767,6 +674,8 @@ int af_set_score_variant(af_ctx *c, int32_t v) {
   c->score_variant = v;
   return AF_OK;
 }
+
+int af_score_variant_default(void) { return af::score_variant_default(); }
 
 int32_t af_get_score_variant(af_ctx *c) { return c ? c->score_variant : -1; }
 
@@ -1015,6 +924,7 @@ int af_score_stats_get(af_ctx *c, int32_t tool_id, af_score_stats *st) {
   st->coarse_clear = (int64_t)h.coarse_clear;
   st->chunks_body = (int64_t)h.chunks_body;
   st->chunks_far = (int64_t)h.chunks_far;
+  st->arm_lookups = (int64_t)h.arm_lookups;
   return AF_OK;
 }
 

@@ -412,14 +412,6 @@ __device__ void write_brick(const Params &p, MapDev m, GridDev g, int64_t id, in
       g.occ1[brick * 16 + 2 * (t >> 6)] = (uint32_t)bal;
       g.occ1[brick * 16 + 2 * (t >> 6) + 1] = (uint32_t)(bal >> 32);
     }
-    if ((t & 63) < 4) {    // the slice's 16 bits of each (x, y) octant, lane = x | y << 3
-      const int ox = t & 1, oy = (t >> 1) & 1, lz = t >> 6;
-      uint32_t piece = 0;
-      for (int yy = 0; yy < 4; ++yy)
-        piece |= (uint32_t)((bal >> (4 * ox + 8 * (4 * oy + yy))) & 0xfull) << (4 * yy);
-      const int oct = ox | (oy << 1) | ((lz >> 2) << 2);
-      reinterpret_cast<uint16_t *>(g.occ64)[brick * 32 + oct * 4 + (lz & 3)] = (uint16_t)piece;
-    }
   }
   __syncthreads();
 }
@@ -586,7 +578,6 @@ __global__ void k_grid_fill(GridDev g, int64_t nbricks) {
   for (int64_t j = i; j < (nbricks + 31) / 32; j += stride) g.occ_any[j] = 0u;
   for (int64_t j = i; j < nbricks; j += stride) g.occ4[j] = 0u;
   for (int64_t j = i; j < nbricks * 16; j += stride) g.occ1[j] = 0u;
-  for (int64_t j = i; j < nbricks * 8; j += stride) g.occ64[j] = 0ull;
 }
 
 inline unsigned grid_for(int64_t threads) {

@@ -70,6 +70,7 @@ struct ScoreCounters {
   unsigned long long deep_tests, deep_chunks_max;  // diagnostics of the two-phase kernels
   unsigned long long coarse_checks, coarse_clear;   // corridor brick checks, and those clear
   unsigned long long chunks_body, chunks_far;       // 64-entry steps taken by deep scans
+  unsigned long long arm_lookups;   // canonical arm-sample lookups answered by the mask kernel
 };
 
 struct HashTable {
@@ -131,8 +132,6 @@ struct GridDev {
   uint32_t *occ_any;  // [ceil(nbricks / 32)] brick holds a voxel with TSDF < r_c
   uint8_t *occ4;      // [nbricks] bit (x>>2) | (y>>2) << 1 | (z>>2) << 2: that 4^3 octant does
   uint32_t *occ1;     // [nbricks * 16] one bit per voxel (linear x | y << 3 | z << 6): TSDF < r_c
-  uint64_t *occ64;    // [nbricks * 8] the same bits by 4^3 octant: word (x>>2) | (y>>2) << 1 |
-                      // (z>>2) << 2, bit (x&3) | (y&3) << 2 | (z&3) << 4
   int32_t g0[3];      // block coordinate of brick (0,0,0)
   int32_t gd[3];      // bricks per axis
 };
@@ -149,37 +148,23 @@ struct ToolDev {
   // word: 0 no arm sample hits, 1..3 the first hit is arm sample 0..2
   uint64_t *nearp;    // [max_points * 2 * ceil(K/64)]
   ScoreCounters *counters;
-  // coarse corridor lists: for orientation k, the brick offsets (relative to
-  // the point's brick) that its corridor entries can fall in, for any
-  // position of the point inside its brick
   uint32_t *far_begin;  // [K] index of the first corridor entry
-  uint32_t *cbegin;     // [K + 1]
-  uint32_t *centries;   // packed brick offsets
-  uint8_t *cflag;       // [K] 1: list valid
   // bit k set: orientation k has the same approach direction (first column
   // of its rotation) as orientation k - 1, so its candidate bit is the same
   uint64_t *same;       // [ceil(K / 64)]
-  // grid-relative form of the table for the current brick grid: per entry
-  // {brick delta (ox>>3) + gx (oy>>3) + gx gy (oz>>3), in-brick offsets
-  // (ox&7) | (oy&7) << 4 | (oz&7) << 8 | class << 30}; per coarse entry its
-  // brick delta.  Rebuilt whenever the grid is reallocated.
-  // the same lists for cells of 4^3 voxels, offsets relative to the point's
-  // cell (any position of the point inside it)
+  // coarse corridor lists over 4^3-voxel cells: for orientation k, the cell
+  // offsets (relative to the point's cell) that its corridor entries can fall
+  // in, for any position of the point inside its cell
   uint32_t *c4begin;    // [K + 1]
   uint32_t *c4entries;
-  uint8_t *c4flag;      // [K]
+  uint8_t *c4flag;      // [K] 1: list valid
   int64_t n_c4entries;
-  // exact cell masks: for orientation k and the point's voxel position
-  // modulo 4 (r = rx | ry << 2 | rz << 4), segment 2 (64 k + r) lists the 4^3
-  // cells its body entries fall in, segment 2 (64 k + r) + 1 those of its
-  // corridor entries; each with the 64-bit mask of the entries in that cell
-  uint32_t *mbegin;     // [128 K + 1]
-  uint32_t *mcell;      // packed cell offsets relative to the point's cell
-  uint64_t *mmask;
-  int64_t n_masks;
+  // grid-relative form of the table for the current brick grid: per entry
+  // {brick delta (ox>>3) + gx (oy>>3) + gx gy (oz>>3), in-brick offsets
+  // (ox&7) | (oy&7) << 4 | (oz&7) << 8 | class << 30}.  Rebuilt whenever the
+  // grid is reallocated.
   uint2 *xent;          // [entries]
-  int32_t *cdelta;      // [coarse entries]
-  int64_t n_entries, n_centries;
+  int64_t n_entries;
   int32_t reach;        // largest |offset| component over the table, voxels
 };
 
@@ -250,6 +235,7 @@ void launch_mask(const Params &p, PointsDev pts, ToolDev t, GridDev g, int64_t n
 void launch_score(const Params &p, PointsDev pts, ToolDev t, GridDev g, int64_t n_points,
                   int variant, unsigned *work, hipStream_t s);
 int score_variants();
+int score_variant_default();
 const char *score_variant_name(int v);
 
 }  // namespace af

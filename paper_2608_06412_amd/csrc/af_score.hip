@@ -508,610 +508,12 @@ k_score(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t mw,
   }
 }
 
-// Candidate-parallel variant.  The mask is taken one 64-orientation word at
-// a time.  Phase 1: lane j examines the first E entries of orientation 64w+j
-// (if it is a candidate), all gathers issued together; near the tip these
-// decide most blocked orientations.  Phase 2: the word's candidates are taken
-// in index order; decided ones only add their canonical counts, undecided
-// ones are finished with lanes over entries.  The first E entries of the
-// first kLdsK orientations are staged in LDS with an odd row stride.
-template <int NT, int E, int UN, int OCC, int FB>
-__global__ void __launch_bounds__(NT)
-k_score_batch(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t mw,
-              unsigned *work) {
-  constexpr int NW = NT / 64;
-  constexpr int ST = E + 1;
-  __shared__ uint32_t s_begin[kLdsK + 1];
-  __shared__ uint32_t s_head[kLdsK * ST];
-  const int kc = t.K < kLdsK ? t.K : kLdsK;
-  for (int j = threadIdx.x; j <= kc; j += NT) s_begin[j] = t.begin[j];
-  __syncthreads();
-  for (int j = threadIdx.x; j < kc * E; j += NT) {
-    const int k = j / E, q = j - k * E;
-    const uint32_t pos = s_begin[k] + (uint32_t)q;
-    s_head[k * ST + q] = pos < s_begin[k + 1] ? t.entries[pos] : 0u;
-  }
-  __syncthreads();
-  const int lane = lane_id();
-  const int64_t wave0 =
-      (int64_t)blockIdx.x * NW + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t nwaves = (int64_t)gridDim.x * NW;
-  uint64_t conf = 0, acc = 0, blk = 0, nocand = 0, tests = 0, lookups = 0;
-  // points by grid stride (FB = 0) or in batches of FB from a shared counter
-  int64_t i = wave0, batch_end = wave0 + 1;
-  if (FB > 0) {
-    unsigned got = 0;
-    if (lane == 0) got = atomicAdd(work, (unsigned)FB);
-    i = (int64_t)__builtin_amdgcn_readfirstlane(__shfl(got, 0));
-    batch_end = i + FB;
-  }
-  for (; i < n;) {
-    const int hn = __builtin_amdgcn_readfirstlane(pts.has_normal[i]);
-    uint8_t label;
-    int16_t ff = -1;
-    if (hn < 0) {
-      label = AF_UNSCORED;
-    } else {
-      ++conf;
-      int32_t s[3];
-      unpack_key(pts.key[i], s[0], s[1], s[2]);
-      label = AF_NO_CANDIDATE;
-      for (int w = 0; w < mw && ff < 0; ++w) {
-        const uint64_t word = t.mask[i * mw + w];
-        if (!word) continue;
-        label = AF_BLOCKED;
-        // phase 1: lane j <-> orientation 64w + j
-        const int k = 64 * w + lane;
-        const bool cand = (word >> lane) & 1ull;
-        int state = 0, pos = 0, body = 0;   // state 0 undecided, 1 blocked, 2 free
-        if (cand) {
-          const bool cached = k < kc;
-          const uint32_t b = cached ? s_begin[k] : t.begin[k];
-          const uint32_t e = cached ? s_begin[k + 1] : t.begin[k + 1];
-          const uint32_t len = e - b;
-          uint32_t ent[E];
-#pragma unroll
-          for (int q = 0; q < E; ++q)
-            ent[q] = (uint32_t)q < len ? (cached ? s_head[k * ST + q] : t.entries[b + q]) : 0u;
-          bool hit[E];
-#pragma unroll
-          for (int q = 0; q < E; ++q) hit[q] = (uint32_t)q < len && entry_hits<OCC>(g, s, ent[q]);
-#pragma unroll
-          for (int q = 0; q < E; ++q) {
-            if (state == 0 && hit[q]) {
-              if (entry_cls(ent[q]) != AF_CLS_BODY || ++body >= p.n_c) {
-                state = 1;
-                pos = q;
-              }
-            }
-          }
-          if (state == 0 && len <= (uint32_t)E) state = 2;
-        }
-        const int packed = state | (pos << 2) | (body << 10);
-        // phase 2: candidates of this word in index order
-        uint64_t rest = word;
-        while (rest) {
-          const int j = __ffsll((long long)rest) - 1;
-          rest &= rest - 1;
-          const int pk = __builtin_amdgcn_readfirstlane(__shfl(packed, j));
-          const int kj = 64 * w + j;
-          ++tests;
-          const int st = pk & 3;
-          if (st == 1) {
-            lookups += (uint64_t)((pk >> 2) & 255) + 1;
-            continue;
-          }
-          const bool cj = kj < kc;
-          const uint32_t b = cj ? s_begin[kj] : t.begin[kj];
-          const uint32_t e = cj ? s_begin[kj + 1] : t.begin[kj + 1];
-          if (st == 2) {
-            lookups += e - b;
-            ff = (int16_t)kj;
-            break;
-          }
-          lookups += E;
-          if (scan_rest<UN, OCC>(p, t, g, s, b + E, e, pk >> 10, lookups)) {
-            ff = (int16_t)kj;
-            break;
-          }
-        }
-      }
-      if (ff >= 0) label = AF_ACCESSIBLE;
-      acc += label == AF_ACCESSIBLE;
-      blk += label == AF_BLOCKED;
-      nocand += label == AF_NO_CANDIDATE;
-    }
-    if (lane == 0) {
-      t.label[i] = label;
-      t.first_free[i] = ff;
-    }
-    if (FB > 0) {
-      if (++i >= batch_end) {
-        unsigned got = 0;
-        if (lane == 0) got = atomicAdd(work, (unsigned)FB);
-        i = (int64_t)__builtin_amdgcn_readfirstlane(__shfl(got, 0));
-        batch_end = i + FB;
-      }
-    } else {
-      i += nwaves;
-    }
-  }
-  if (lane == 0) {
-    if (conf) atomicAdd(&t.counters->n_confident, (unsigned long long)conf);
-    if (acc) atomicAdd(&t.counters->n_accessible, (unsigned long long)acc);
-    if (blk) atomicAdd(&t.counters->n_blocked, (unsigned long long)blk);
-    if (nocand) atomicAdd(&t.counters->n_no_candidate, (unsigned long long)nocand);
-    if (tests) atomicAdd(&t.counters->canonical_tests, (unsigned long long)tests);
-    if (lookups) atomicAdd(&t.counters->canonical_lookups, (unsigned long long)lookups);
-  }
-}
-
-// Branch-free lookup: the point's brick (relative to the grid) and in-brick
-// offset are hoisted; offsets outside the grid read "unknown, not cleared"
-// from a clamped (valid) address, so every lane issues its load.
-struct PointFrame {
-  int rx, ry, rz;   // point voxel & 7
-  int bx, by, bz;   // point brick - grid origin
-};
-
-__device__ inline PointFrame point_frame(const GridDev &g, const int32_t s[3]) {
-  PointFrame f;
-  f.rx = s[0] & 7;
-  f.ry = s[1] & 7;
-  f.rz = s[2] & 7;
-  f.bx = (s[0] >> 3) - g.g0[0];
-  f.by = (s[1] >> 3) - g.g0[1];
-  f.bz = (s[2] >> 3) - g.g0[2];
-  return f;
-}
-
-__device__ inline uint32_t code_fast(const GridDev &g, const PointFrame &f, uint32_t ent) {
-  const int tx = f.rx + entry_x(ent), ty = f.ry + entry_y(ent), tz = f.rz + entry_z(ent);
-  const int bx = f.bx + (tx >> 3), by = f.by + (ty >> 3), bz = f.bz + (tz >> 3);
-  const bool in = (unsigned)bx < (unsigned)g.gd[0] && (unsigned)by < (unsigned)g.gd[1] &&
-                  (unsigned)bz < (unsigned)g.gd[2];
-  const unsigned brick = in ? (unsigned)((bz * g.gd[1] + by) * g.gd[0] + bx) : 0u;
-  const unsigned lin = (unsigned)((tx & 7) | ((ty & 7) << 3) | ((tz & 7) << 6));
-  const unsigned w = g.pred[(brick << 5) | (lin >> 4)];
-  const unsigned code = (w >> ((lin & 15u) << 1)) & 3u;
-  return in ? code : 2u;
-}
-
-__device__ inline bool code_hits(uint32_t ent, uint32_t code) {
-  return entry_cls(ent) == AF_CLS_NEAR ? code != 0u : (code & 1u) != 0u;
-}
-
-template <int UN>
-__device__ inline bool scan_fine(const Params &p, const ToolDev &t, const GridDev &g,
-                                 const PointFrame &f, uint32_t b, uint32_t e, int &body,
-                                 uint64_t &lookups) {
-  const uint32_t lane = (uint32_t)lane_id();
-  for (uint32_t base = b; base < e; base += 64 * UN) {
-    uint32_t ent[UN], code[UN];
-#pragma unroll
-    for (int u = 0; u < UN; ++u) {
-      const uint32_t idx = base + 64 * u + lane;
-      ent[u] = t.entries[idx < e ? idx : e - 1];
-    }
-#pragma unroll
-    for (int u = 0; u < UN; ++u) code[u] = code_fast(g, f, ent[u]);
-#pragma unroll
-    for (int u = 0; u < UN; ++u) {
-      const uint32_t cb = base + 64 * u;
-      const bool hit = cb + lane < e && code_hits(ent[u], code[u]);
-      uint64_t nf = __ballot(hit && entry_cls(ent[u]) != AF_CLS_BODY);
-      uint64_t bm = __ballot(hit && entry_cls(ent[u]) == AF_CLS_BODY);
-      if (cb >= e) break;
-      int stop = chunk_stop(nf, bm, p.n_c - body);
-      if (stop < 64) {
-        lookups += (uint64_t)stop + 1;
-        return false;
-      }
-      body += __popcll(bm);
-      lookups += (e - cb) < 64u ? (e - cb) : 64u;
-    }
-  }
-  return true;
-}
-
-// True if no brick of the coarse corridor list of orientation k (relative to
-// the point's brick) holds a voxel with TSDF < r_c; then no corridor entry
-// can hit (corridor hits need TSDF < r_c) and the fine scan can be skipped.
-__device__ inline bool corridor_clear(const ToolDev &t, const GridDev &g, const PointFrame &f,
-                                      int k) {
-  const uint32_t cb = t.cbegin[k], ce = t.cbegin[k + 1];
-  const uint32_t lane = (uint32_t)lane_id();
-  for (uint32_t base = cb; base < ce; base += 64) {
-    const uint32_t idx = base + lane;
-    const uint32_t d = t.centries[idx < ce ? idx : ce - 1];
-    const int bx = f.bx + entry_x(d), by = f.by + entry_y(d), bz = f.bz + entry_z(d);
-    const bool in = (unsigned)bx < (unsigned)g.gd[0] && (unsigned)by < (unsigned)g.gd[1] &&
-                    (unsigned)bz < (unsigned)g.gd[2];
-    const unsigned brick = in ? (unsigned)((bz * g.gd[1] + by) * g.gd[0] + bx) : 0u;
-    const bool occ = in && ((g.occ_any[brick >> 5] >> (brick & 31)) & 1u);
-    if (__ballot(idx < ce && occ)) return false;
-  }
-  return true;
-}
-
-// Entries [b, e) of orientation k after its head: body entries finely, then
-// the corridor -- skipped when its coarse bricks are clear (CO), finely
-// otherwise.  Canonical lookups stay the table-order count.
-template <int UN, int CO>
-__device__ inline bool scan_rest_fast(const Params &p, const ToolDev &t, const GridDev &g,
-                                      const PointFrame &f, int k, uint32_t b, uint32_t fb,
-                                      uint32_t e, int body, uint64_t &lookups,
-                                      uint64_t &cchecks, uint64_t &cclear) {
-  if (!CO) return scan_fine<UN>(p, t, g, f, b, e, body, lookups);
-  const uint32_t mid = fb > b ? fb : b;
-  if (!scan_fine<UN>(p, t, g, f, b, mid, body, lookups)) return false;
-  if (mid >= e) return true;
-  if (t.cflag[k]) {
-    ++cchecks;
-    if (corridor_clear(t, g, f, k)) {
-      ++cclear;
-      lookups += e - mid;
-      return true;
-    }
-  }
-  return scan_fine<UN>(p, t, g, f, mid, e, body, lookups);
-}
-
-// Candidate-parallel scoring, branch-free.  Requires K <= kLdsK: every
-// orientation's begin offset and first E entries are staged in LDS (rows
-// padded to an odd stride); see k_score_batch for the two phases.
-template <int NT, int E, int UN, int FB, int CO>
-__global__ void __launch_bounds__(NT)
-k_score_fast(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t mw,
-             unsigned *work) {
-  constexpr int NW = NT / 64;
-  constexpr int ST = E + 1;
-  __shared__ uint32_t s_begin[kLdsK + 1];
-  __shared__ uint32_t s_head[kLdsK * ST];
-  const int K = t.K;
-  for (int j = threadIdx.x; j <= K; j += NT) s_begin[j] = t.begin[j];
-  __syncthreads();
-  for (int j = threadIdx.x; j < K * E; j += NT) {
-    const int k = j / E, q = j - k * E;
-    const uint32_t pos = s_begin[k] + (uint32_t)q;
-    s_head[k * ST + q] = pos < s_begin[k + 1] ? t.entries[pos] : 0u;
-  }
-  __syncthreads();
-  const int lane = lane_id();
-  const int64_t wave0 =
-      (int64_t)blockIdx.x * NW + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t nwaves = (int64_t)gridDim.x * NW;
-  uint64_t conf = 0, acc = 0, blk = 0, nocand = 0, tests = 0, lookups = 0, deep = 0, chunks = 0;
-  uint64_t cchecks = 0, cclear = 0;
-  int64_t i = wave0, batch_end = wave0 + 1;
-  if (FB > 0) {
-    unsigned got = 0;
-    if (lane == 0) got = atomicAdd(work, (unsigned)FB);
-    i = (int64_t)__builtin_amdgcn_readfirstlane(__shfl(got, 0));
-    batch_end = i + FB;
-  }
-  for (; i < n;) {
-    const int hn = __builtin_amdgcn_readfirstlane(pts.has_normal[i]);
-    uint8_t label;
-    int16_t ff = -1;
-    if (hn < 0) {
-      label = AF_UNSCORED;
-    } else {
-      ++conf;
-      int32_t s[3];
-      unpack_key(pts.key[i], s[0], s[1], s[2]);
-      const PointFrame f = point_frame(g, s);
-      label = AF_NO_CANDIDATE;
-      // all mask words of the point in one load (lane w holds word w)
-      const uint64_t mine = lane < mw ? t.mask[i * mw + lane] : 0ull;
-      for (int w = 0; w < mw && ff < 0; ++w) {
-        const uint64_t word =
-            ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(mine >> 32), w) << 32) |
-            (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)mine, w);
-        if (!word) continue;
-        label = AF_BLOCKED;
-        const int k = 64 * w + lane;
-        const int kk = k < K ? k : K - 1;
-        const bool cand = (word >> lane) & 1ull;
-        const uint32_t len = s_begin[kk + 1] - s_begin[kk];
-        uint32_t ent[E], code[E];
-#pragma unroll
-        for (int q = 0; q < E; ++q) ent[q] = s_head[kk * ST + q];
-#pragma unroll
-        for (int q = 0; q < E; ++q) code[q] = code_fast(g, f, ent[q]);
-        int state = 0, pos = 0, body = 0;   // 0 undecided, 1 blocked, 2 free
-#pragma unroll
-        for (int q = 0; q < E; ++q) {
-          const bool hit = (uint32_t)q < len && code_hits(ent[q], code[q]);
-          if (state == 0 && hit) {
-            if (entry_cls(ent[q]) != AF_CLS_BODY || ++body >= p.n_c) {
-              state = 1;
-              pos = q;
-            }
-          }
-        }
-        if (state == 0 && len <= (uint32_t)E) state = 2;
-        const int packed = cand ? (state | (pos << 2) | (body << 10)) : 0;
-        uint64_t rest = word;
-        while (rest) {
-          const int j = __ffsll((long long)rest) - 1;
-          rest &= rest - 1;
-          const int pk = __builtin_amdgcn_readlane(packed, j);
-          const int kj = 64 * w + j;
-          ++tests;
-          const int st = pk & 3;
-          if (st == 1) {
-            lookups += (uint64_t)((pk >> 2) & 255) + 1;
-            continue;
-          }
-          const uint32_t b = s_begin[kj], e = s_begin[kj + 1];
-          if (st == 2) {
-            lookups += e - b;
-            ff = (int16_t)kj;
-            break;
-          }
-          lookups += E;
-          ++deep;
-          chunks += (e - b - E + 63) / 64;
-          if (scan_rest_fast<UN, CO>(p, t, g, f, kj, b + E, CO ? t.far_begin[kj] : e, e, pk >> 10,
-                                     lookups, cchecks, cclear)) {
-            ff = (int16_t)kj;
-            break;
-          }
-        }
-      }
-      if (ff >= 0) label = AF_ACCESSIBLE;
-      acc += label == AF_ACCESSIBLE;
-      blk += label == AF_BLOCKED;
-      nocand += label == AF_NO_CANDIDATE;
-    }
-    if (lane == 0) {
-      t.label[i] = label;
-      t.first_free[i] = ff;
-    }
-    if (FB > 0) {
-      if (++i >= batch_end) {
-        unsigned got = 0;
-        if (lane == 0) got = atomicAdd(work, (unsigned)FB);
-        i = (int64_t)__builtin_amdgcn_readfirstlane(__shfl(got, 0));
-        batch_end = i + FB;
-      }
-    } else {
-      i += nwaves;
-    }
-  }
-  if (lane == 0) {
-    if (conf) atomicAdd(&t.counters->n_confident, (unsigned long long)conf);
-    if (acc) atomicAdd(&t.counters->n_accessible, (unsigned long long)acc);
-    if (blk) atomicAdd(&t.counters->n_blocked, (unsigned long long)blk);
-    if (nocand) atomicAdd(&t.counters->n_no_candidate, (unsigned long long)nocand);
-    if (tests) atomicAdd(&t.counters->canonical_tests, (unsigned long long)tests);
-    if (lookups) atomicAdd(&t.counters->canonical_lookups, (unsigned long long)lookups);
-    if (deep) atomicAdd(&t.counters->deep_tests, (unsigned long long)deep);
-    if (chunks) atomicAdd(&t.counters->deep_chunks_max, (unsigned long long)chunks);
-    if (cchecks) atomicAdd(&t.counters->coarse_checks, (unsigned long long)cchecks);
-    if (cclear) atomicAdd(&t.counters->coarse_clear, (unsigned long long)cclear);
-  }
-}
-
-// scan_fine with the next step's table entries loaded while the current
-// step's voxel words are gathered, so only one memory latency per step.
-template <int UN>
-__device__ inline bool scan_fine_pf(const Params &p, const ToolDev &t, const GridDev &g,
-                                    const PointFrame &f, uint32_t b, uint32_t e, int &body,
-                                    uint64_t &lookups) {
-  if (b >= e) return true;
-  const uint32_t lane = (uint32_t)lane_id();
-  uint32_t ent[UN];
-#pragma unroll
-  for (int u = 0; u < UN; ++u) {
-    const uint32_t idx = b + 64 * u + lane;
-    ent[u] = t.entries[idx < e ? idx : e - 1];
-  }
-  for (uint32_t base = b; base < e; base += 64 * UN) {
-    uint32_t code[UN], nxt[UN];
-#pragma unroll
-    for (int u = 0; u < UN; ++u) code[u] = code_fast(g, f, ent[u]);
-#pragma unroll
-    for (int u = 0; u < UN; ++u) {
-      const uint32_t idx = base + 64 * (UN + u) + lane;
-      nxt[u] = t.entries[idx < e ? idx : e - 1];
-    }
-#pragma unroll
-    for (int u = 0; u < UN; ++u) {
-      const uint32_t cb = base + 64 * u;
-      const bool hit = cb + lane < e && code_hits(ent[u], code[u]);
-      const uint64_t nf = __ballot(hit && entry_cls(ent[u]) != AF_CLS_BODY);
-      const uint64_t bm = __ballot(hit && entry_cls(ent[u]) == AF_CLS_BODY);
-      if (cb >= e) break;
-      const int stop = chunk_stop(nf, bm, p.n_c - body);
-      if (stop < 64) {
-        lookups += (uint64_t)stop + 1;
-        return false;
-      }
-      body += __popcll(bm);
-      lookups += (e - cb) < 64u ? (e - cb) : 64u;
-    }
-#pragma unroll
-    for (int u = 0; u < UN; ++u) ent[u] = nxt[u];
-  }
-  return true;
-}
-
-template <int UN, int CO>
-__device__ inline bool scan_rest_pf(const Params &p, const ToolDev &t, const GridDev &g,
-                                    const PointFrame &f, int k, uint32_t b, uint32_t e, int body,
-                                    uint64_t &lookups, uint64_t &cchecks, uint64_t &cclear) {
-  if (!CO) return scan_fine_pf<UN>(p, t, g, f, b, e, body, lookups);
-  const uint32_t fb = t.far_begin[k];
-  const uint32_t mid = fb > b ? fb : b;
-  if (!scan_fine_pf<UN>(p, t, g, f, b, mid, body, lookups)) return false;
-  if (mid >= e) return true;
-  if (t.cflag[k]) {
-    ++cchecks;
-    if (corridor_clear(t, g, f, k)) {
-      ++cclear;
-      lookups += e - mid;
-      return true;
-    }
-  }
-  return scan_fine_pf<UN>(p, t, g, f, mid, e, body, lookups);
-}
-
 // Sum over the lanes in m of a per-lane value below 16 held as four ballots
 // of its bits.
 __device__ inline uint32_t plane_sum(const uint64_t pl[4], uint64_t m) {
   return (uint32_t)__popcll(pl[0] & m) + 2u * (uint32_t)__popcll(pl[1] & m) +
          4u * (uint32_t)__popcll(pl[2] & m) + 8u * (uint32_t)__popcll(pl[3] & m);
 }
-
-// As k_score_fast, with the bookkeeping of phase 2 done for the whole wave
-// at once: candidates decided by their first E entries (blocked ones, at
-// entry pos) are summed from ballots -- tests by popcount, canonical lookups
-// (pos + 1) from four bit-plane ballots -- so only candidates that need a
-// deeper scan, or are free, are visited one by one.  Same labels, first
-// free orientations and canonical counts.
-template <int NT, int E, int UN, int FB, int CO>
-__global__ void __launch_bounds__(NT)
-k_score_wave(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t mw,
-             unsigned *work) {
-  static_assert(E >= 1 && E <= 15, "head length must fit the 4-bit planes");
-  constexpr int NW = NT / 64;
-  constexpr int ST = E + 1;
-  __shared__ uint32_t s_begin[kLdsK + 1];
-  __shared__ uint32_t s_head[kLdsK * ST];
-  const int K = t.K;
-  for (int j = threadIdx.x; j <= K; j += NT) s_begin[j] = t.begin[j];
-  __syncthreads();
-  for (int j = threadIdx.x; j < K * E; j += NT) {
-    const int k = j / E, q = j - k * E;
-    const uint32_t pos = s_begin[k] + (uint32_t)q;
-    s_head[k * ST + q] = pos < s_begin[k + 1] ? t.entries[pos] : 0u;
-  }
-  __syncthreads();
-  const int lane = lane_id();
-  const int64_t wave0 =
-      (int64_t)blockIdx.x * NW + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t nwaves = (int64_t)gridDim.x * NW;
-  uint64_t conf = 0, acc = 0, blk = 0, nocand = 0, tests = 0, lookups = 0, deep = 0, chunks = 0;
-  uint64_t cchecks = 0, cclear = 0;
-  int64_t i = wave0, batch_end = wave0 + 1;
-  if (FB > 0) {
-    unsigned got = 0;
-    if (lane == 0) got = atomicAdd(work, (unsigned)FB);
-    i = (int64_t)__builtin_amdgcn_readfirstlane(__shfl(got, 0));
-    batch_end = i + FB;
-  }
-  for (; i < n;) {
-    const int hn = __builtin_amdgcn_readfirstlane(pts.has_normal[i]);
-    uint8_t label;
-    int16_t ff = -1;
-    if (hn < 0) {
-      label = AF_UNSCORED;
-    } else {
-      ++conf;
-      int32_t s[3];
-      unpack_key(pts.key[i], s[0], s[1], s[2]);
-      const PointFrame f = point_frame(g, s);
-      label = AF_NO_CANDIDATE;
-      const uint64_t mine = lane < mw ? t.mask[i * mw + lane] : 0ull;
-      for (int w = 0; w < mw && ff < 0; ++w) {
-        const uint64_t word =
-            ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(mine >> 32), w) << 32) |
-            (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)mine, w);
-        if (!word) continue;
-        label = AF_BLOCKED;
-        const int k = 64 * w + lane;
-        const int kk = k < K ? k : K - 1;
-        const bool cand = (word >> lane) & 1ull;
-        const uint32_t len = s_begin[kk + 1] - s_begin[kk];
-        uint32_t ent[E], code[E];
-#pragma unroll
-        for (int q = 0; q < E; ++q) ent[q] = s_head[kk * ST + q];
-#pragma unroll
-        for (int q = 0; q < E; ++q) code[q] = code_fast(g, f, ent[q]);
-        int state = 0, pos = 0, body = 0;   // 0 undecided, 1 blocked, 2 free
-#pragma unroll
-        for (int q = 0; q < E; ++q) {
-          const bool hit = (uint32_t)q < len && code_hits(ent[q], code[q]);
-          if (state == 0 && hit) {
-            if (entry_cls(ent[q]) != AF_CLS_BODY || ++body >= p.n_c) {
-              state = 1;
-              pos = q;
-            }
-          }
-        }
-        if (state == 0 && len <= (uint32_t)E) state = 2;
-        const uint64_t fm = __ballot(cand && state == 2);
-        uint64_t open = fm | __ballot(cand && state == 0);
-        const uint32_t v = (cand && state == 1) ? (uint32_t)pos + 1u : 0u;
-        const uint64_t pl[4] = {__ballot(v & 1u), __ballot(v & 2u), __ballot(v & 4u),
-                                __ballot(v & 8u)};
-        uint64_t left = word;   // candidates not yet accounted
-        for (;;) {
-          if (!open) {          // the rest are blocked within their first E entries
-            tests += (uint64_t)__popcll(left);
-            lookups += plane_sum(pl, left);
-            break;
-          }
-          const int j = __ffsll((long long)open) - 1;
-          open &= open - 1;
-          const uint64_t below = left & ((1ull << j) - 1ull);
-          tests += (uint64_t)__popcll(below) + 1;
-          lookups += plane_sum(pl, below);
-          left &= ~((2ull << j) - 1ull);
-          const int kj = 64 * w + j;
-          const uint32_t b = s_begin[kj], e = s_begin[kj + 1];
-          if ((fm >> j) & 1ull) {
-            lookups += e - b;
-            ff = (int16_t)kj;
-            break;
-          }
-          lookups += E;
-          ++deep;
-          chunks += (e - b - E + 63) / 64;
-          if (scan_rest_pf<UN, CO>(p, t, g, f, kj, b + E, e,
-                                   __builtin_amdgcn_readlane(body, j), lookups, cchecks,
-                                   cclear)) {
-            ff = (int16_t)kj;
-            break;
-          }
-        }
-      }
-      if (ff >= 0) label = AF_ACCESSIBLE;
-      acc += label == AF_ACCESSIBLE;
-      blk += label == AF_BLOCKED;
-      nocand += label == AF_NO_CANDIDATE;
-    }
-    if (lane == 0) {
-      t.label[i] = label;
-      t.first_free[i] = ff;
-    }
-    if (FB > 0) {
-      if (++i >= batch_end) {
-        unsigned got = 0;
-        if (lane == 0) got = atomicAdd(work, (unsigned)FB);
-        i = (int64_t)__builtin_amdgcn_readfirstlane(__shfl(got, 0));
-        batch_end = i + FB;
-      }
-    } else {
-      i += nwaves;
-    }
-  }
-  if (lane == 0) {
-    if (conf) atomicAdd(&t.counters->n_confident, (unsigned long long)conf);
-    if (acc) atomicAdd(&t.counters->n_accessible, (unsigned long long)acc);
-    if (blk) atomicAdd(&t.counters->n_blocked, (unsigned long long)blk);
-    if (nocand) atomicAdd(&t.counters->n_no_candidate, (unsigned long long)nocand);
-    if (tests) atomicAdd(&t.counters->canonical_tests, (unsigned long long)tests);
-    if (lookups) atomicAdd(&t.counters->canonical_lookups, (unsigned long long)lookups);
-    if (deep) atomicAdd(&t.counters->deep_tests, (unsigned long long)deep);
-    if (chunks) atomicAdd(&t.counters->deep_chunks_max, (unsigned long long)chunks);
-    if (cchecks) atomicAdd(&t.counters->coarse_checks, (unsigned long long)cchecks);
-    if (cclear) atomicAdd(&t.counters->coarse_clear, (unsigned long long)cclear);
-  }
-}
-
 
 // B1: the entries are body or corridor entries only (no arm samples), read
 // from the one-bit plane.
@@ -1159,22 +561,12 @@ __device__ inline bool scan_fine_sw(const Params &p, const ToolDev &t, const SwG
   return true;
 }
 
-__device__ inline bool corridor_clear_sw(const ToolDev &t, const SwGrid &q, const SwFrame &f,
-                                         int k) {
-  const uint32_t cb = t.cbegin[k], ce = t.cbegin[k + 1];
-  const uint32_t lane = (uint32_t)lane_id();
-  for (uint32_t base = cb; base < ce; base += 64) {
-    const uint32_t idx = base + lane;
-    const uint32_t brick = f.Bp + (uint32_t)t.cdelta[idx < ce ? idx : ce - 1];
-    const uint32_t bs = brick < q.nbricks ? brick : 0u;
-    const bool occ = (q.occ_any[bs >> 5] >> (bs & 31)) & 1u;
-    if (__ballot(idx < ce && occ)) return false;
-  }
-  return true;
-}
-
-// As corridor_clear_sw over 4^3 cells: c4 is the point's cell (voxel >> 2)
-// relative to the grid; a cell's bit lives in its brick's octant byte.
+// True if no 4^3 cell of the corridor list of orientation k holds a voxel
+// with TSDF < r_c; corridor entries hit only such voxels, so the fine scan
+// of the corridor can then be skipped.  c4 is the point's cell (voxel >> 2)
+// relative to the grid; a cell's bit lives in its brick's octant byte.  The
+// list holds every cell offset floor((r + o) / 4) over corridor entries o and
+// positions r in [0, 4)^3 of the point inside its cell.
 __device__ inline bool corridor_clear4_sw(const ToolDev &t, const SwGrid &q, const uint32_t c4[3],
                                           const uint8_t *occ4, int k) {
   const uint32_t cb = t.c4begin[k], ce = t.c4begin[k + 1];
@@ -1193,84 +585,9 @@ __device__ inline bool corridor_clear4_sw(const ToolDev &t, const SwGrid &q, con
   return true;
 }
 
-// Exact cell-mask tests over a segment [mb, me) of a point's mask list:
-// occupied entries per cell are popcount(occ64 word & mask).  mask_count
-// returns min(total, 15); mask_any whether any entry is occupied.
-__device__ inline uint64_t cell_word(const SwGrid &q, const uint32_t c4[3], const uint64_t *occ64,
-                                     uint32_t d) {
-  const uint32_t X = c4[0] + (uint32_t)entry_x(d), Y = c4[1] + (uint32_t)entry_y(d),
-                 Z = c4[2] + (uint32_t)entry_z(d);
-  const uint32_t brick = (X >> 1) + q.gx * (Y >> 1) + q.gxy * (Z >> 1);
-  const uint32_t bs = brick < q.nbricks ? brick : 0u;
-  return occ64[(bs << 3) | (X & 1u) | ((Y & 1u) << 1) | ((Z & 1u) << 2)];
-}
-
-__device__ inline uint32_t mask_count(const ToolDev &t, const SwGrid &q, const uint32_t c4[3],
-                                      const uint64_t *occ64, uint32_t mb, uint32_t me) {
-  const uint32_t lane = (uint32_t)lane_id();
-  uint32_t total = 0;
-  for (uint32_t base = mb; base < me && total < 15u; base += 64) {
-    const uint32_t idx = base + lane;
-    const uint32_t j = idx < me ? idx : me - 1;
-    const uint64_t w = cell_word(q, c4, occ64, t.mcell[j]) & t.mmask[j];
-    uint32_t c = idx < me ? (uint32_t)__popcll(w) : 0u;
-    c = c < 15u ? c : 15u;
-    const uint64_t pl[4] = {__ballot(c & 1u), __ballot(c & 2u), __ballot(c & 4u),
-                            __ballot(c & 8u)};
-    total += plane_sum(pl, ~0ull);
-  }
-  return total < 15u ? total : 15u;
-}
-
-__device__ inline bool mask_any(const ToolDev &t, const SwGrid &q, const uint32_t c4[3],
-                                const uint64_t *occ64, uint32_t mb, uint32_t me) {
-  const uint32_t lane = (uint32_t)lane_id();
-  for (uint32_t base = mb; base < me; base += 64) {
-    const uint32_t idx = base + lane;
-    const uint32_t j = idx < me ? idx : me - 1;
-    const uint64_t w = cell_word(q, c4, occ64, t.mcell[j]) & t.mmask[j];
-    if (__ballot(idx < me && w != 0ull)) return true;
-  }
-  return false;
-}
-
-// Deep scan with exact cell masks: one fine step of body entries (most
-// blocked candidates stop there); if undecided, the exact body count decides
-// whether the body blocks (then the fine scan finds where) or passes (its
-// remaining entries are counted as examined); then the exact corridor test
-// decides free, or the fine scan finds the corridor's first hit.  Labels and
-// canonical counts are those of the plain scan.
-template <int UN, int B1>
-__device__ inline bool scan_rest_mk(const Params &p, const ToolDev &t, const SwGrid &q,
-                                    const SwFrame &f, int k, uint32_t b, uint32_t e, int body,
-                                    uint32_t &lookups, uint32_t &cchecks, uint32_t &cclear,
-                                    uint32_t &sbody, uint32_t &sfar, const uint32_t c4[3],
-                                    const uint64_t *occ64, uint32_t rmod) {
-  const uint32_t fb = t.far_begin[k];
-  const uint32_t mid = fb > b ? fb : b;
-  const uint32_t seg = 2u * (64u * (uint32_t)k + rmod);
-  if (b < mid) {
-    const uint32_t first_end = mid - b > 64u ? b + 64u : mid;
-    if (!scan_fine_sw<1, B1>(p, t, q, f, b, first_end, body, lookups, sbody)) return false;
-    if (first_end < mid) {
-      const uint32_t cnt = mask_count(t, q, c4, occ64, t.mbegin[seg], t.mbegin[seg + 1]);
-      if ((int)cnt >= p.n_c) {
-        if (!scan_fine_sw<UN, B1>(p, t, q, f, first_end, mid, body, lookups, sbody)) return false;
-      } else {
-        lookups += mid - first_end;
-      }
-    }
-  }
-  if (mid >= e) return true;
-  ++cchecks;
-  if (!mask_any(t, q, c4, occ64, t.mbegin[seg + 1], t.mbegin[seg + 2])) {
-    ++cclear;
-    lookups += e - mid;
-    return true;
-  }
-  return scan_fine_sw<UN, B1>(p, t, q, f, mid, e, body, lookups, sfar);
-}
-
+// Entries [b, e) of orientation k after its first E: body entries finely,
+// then the corridor -- skipped when its 4^3 cells are clear (CO), finely
+// otherwise.  Canonical lookups stay the table-order count.
 template <int UN, int CO, int B1>
 __device__ inline bool scan_rest_sw(const Params &p, const ToolDev &t, const SwGrid &q,
                                     const SwFrame &f, int k, uint32_t b, uint32_t e, int body,
@@ -1282,9 +599,9 @@ __device__ inline bool scan_rest_sw(const Params &p, const ToolDev &t, const SwG
   const uint32_t mid = fb > b ? fb : b;
   if (!scan_fine_sw<UN, B1>(p, t, q, f, b, mid, body, lookups, sbody)) return false;
   if (mid >= e) return true;
-  if (CO == 1 ? t.cflag[k] != 0 : t.c4flag[k] != 0) {
+  if (t.c4flag[k] != 0) {
     ++cchecks;
-    if (CO == 1 ? corridor_clear_sw(t, q, f, k) : corridor_clear4_sw(t, q, c4, occ4, k)) {
+    if (corridor_clear4_sw(t, q, c4, occ4, k)) {
       ++cclear;
       lookups += e - mid;
       return true;
@@ -1293,16 +610,21 @@ __device__ inline bool scan_rest_sw(const Params &p, const ToolDev &t, const SwG
   return scan_fine_sw<UN, B1>(p, t, q, f, mid, e, body, lookups, sfar);
 }
 
-// k_score_wave with grid-relative lookups (the configurations named "swar").
-// WPE > 0 asks the compiler to fit WPE waves per SIMD (scalar registers are
-// the occupancy limit of this kernel).
-template <int NT, int E, int UN, int FB, int CO, int WPE = 0, int B1 = 0, int MK = 0>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))
+// Candidate-parallel scoring with grid-relative lookups (the configurations
+// named "swar").  The mask is taken one 64-orientation word at a time.
+// Phase 1: lane j reads the first E entries of orientation 64w + j (staged in
+// LDS) and decides it if they block it, all gathers issued together.
+// Phase 2, for the whole wave at once: candidates blocked within their first
+// E entries (at entry pos) are summed from ballots -- tests by popcount,
+// canonical lookups (pos + 1) from four bit-plane ballots -- so only the
+// others are visited in index order, with lanes over their remaining
+// entries.  Requires K <= kLdsK.
+template <int NT, int E, int UN, int FB, int CO, int B1>
+__global__ void __launch_bounds__(NT)
 k_score_swar(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t mw,
              unsigned *work) {
   static_assert(E >= 1 && E <= 15, "head length must fit the 4-bit planes");
   static_assert(!B1 || E >= 3, "the one-bit plane serves only entries after the arm samples");
-  static_assert(!MK || E >= 3, "cell masks cover only entries after the arm samples");
   constexpr int NW = NT / 64;
   constexpr int ST = E | 1;   // odd row stride of 8-byte entries: no bank conflicts
   __shared__ uint32_t s_begin[kLdsK + 1];
@@ -1364,8 +686,6 @@ k_score_swar(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t m
       uint32_t c4[3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) c4[a] = (uint32_t)((s[a] >> 2) - 2 * g.g0[a]);
-      const uint32_t rmod = (uint32_t)(s[0] & 3) | ((uint32_t)(s[1] & 3) << 2) |
-                            ((uint32_t)(s[2] & 3) << 4);
       label = AF_NO_CANDIDATE;
       const uint64_t mine = lane < mw ? t.mask[i * mw + lane] : 0ull;
       for (int w = 0; w < mw && ff < 0; ++w) {
@@ -1436,15 +756,9 @@ k_score_swar(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t m
           lookups += E;
           ++deep;
           chunks += (e - b - E + 63) / 64;
-          const bool fr =
-              MK && p.n_c <= 15
-                  ? scan_rest_mk<UN, B1>(p, t, q, f, kj, b + E, e,
-                                         __builtin_amdgcn_readlane(body, j), lookups, cchecks,
-                                         cclear, sbody, sfar, c4, g.occ64, rmod)
-                  : scan_rest_sw<UN, CO, B1>(p, t, q, f, kj, b + E, e,
-                                             __builtin_amdgcn_readlane(body, j), lookups, cchecks,
-                                             cclear, sbody, sfar, c4, g.occ4);
-          if (fr) {
+          if (scan_rest_sw<UN, CO, B1>(p, t, q, f, kj, b + E, e,
+                                       __builtin_amdgcn_readlane(body, j), lookups, cchecks,
+                                       cclear, sbody, sfar, c4, g.occ4)) {
             ff = (int16_t)kj;
             break;
           }
@@ -1501,7 +815,7 @@ k_score_near(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t m
       (int64_t)blockIdx.x * NW + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t nwaves = (int64_t)gridDim.x * NW;
   uint32_t conf = 0, acc = 0, blk = 0, nocand = 0, tests = 0, lookups = 0, deep = 0, chunks = 0;
-  uint32_t cchecks = 0, cclear = 0, sbody = 0, sfar = 0;
+  uint32_t cchecks = 0, cclear = 0, sbody = 0, sfar = 0, arm = 0;
   auto flush = [&]() {
     if (lane == 0) {
       if (conf) atomicAdd(&t.counters->n_confident, (unsigned long long)conf);
@@ -1516,9 +830,10 @@ k_score_near(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t m
       if (cclear) atomicAdd(&t.counters->coarse_clear, (unsigned long long)cclear);
       if (sbody) atomicAdd(&t.counters->chunks_body, (unsigned long long)sbody);
       if (sfar) atomicAdd(&t.counters->chunks_far, (unsigned long long)sfar);
+      if (arm) atomicAdd(&t.counters->arm_lookups, (unsigned long long)arm);
     }
     conf = acc = blk = nocand = tests = lookups = deep = chunks = 0;
-    cchecks = cclear = sbody = sfar = 0;
+    cchecks = cclear = sbody = sfar = arm = 0;
   };
   int64_t i = wave0, batch_end = wave0 + 1;
   if (FB > 0) {
@@ -1557,14 +872,18 @@ k_score_near(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t m
         for (;;) {
           if (!open) {   // the rest are blocked by an arm sample
             tests += (uint32_t)__popcll(left);
-            lookups += plane_sum(pl, left);
+            const uint32_t a = plane_sum(pl, left);
+            lookups += a;
+            arm += a;
             break;
           }
           const int j = __ffsll((long long)open) - 1;
           open &= open - 1;
           const uint64_t below = left & ((1ull << j) - 1ull);
           tests += (uint32_t)__popcll(below) + 1u;
-          lookups += plane_sum(pl, below);
+          const uint32_t a = plane_sum(pl, below);
+          lookups += a;
+          arm += a + E;
           left &= ~((2ull << j) - 1ull);
           const int kj = 64 * w + j;
           const uint32_t b = s_begin[kj], e = s_begin[kj + 1];
@@ -1613,77 +932,17 @@ struct ScoreVariant {
 
 // The tunable score configurations (identical results; speed only).
 const ScoreVariant kVariants[] = {
-    {k_score<256, 0, 1, 1, 0, 0>, 256, "wg256 ahead1 unroll1"},
-    {k_score<256, 0, 1, 1, 1, 0>, 256, "wg256 ahead1 unroll1 occ"},
-    {k_score<256, 0, 2, 2, 1, 0>, 256, "wg256 ahead2 unroll2 occ"},
-    {k_score<256, 0, 4, 4, 1, 0>, 256, "wg256 ahead4 unroll4 occ"},
-    {k_score<256, 0, 2, 2, 1, 16>, 256, "wg256 ahead2 unroll2 occ dyn16"},
-    {k_score<512, 128, 2, 2, 1, 0>, 512, "wg512 lds128 ahead2 unroll2 occ"},
-    {k_score<1024, 256, 4, 4, 1, 0>, 1024, "wg1024 lds256 ahead4 unroll4 occ"},
-    {k_score<1024, 256, 1, 1, 0, 0>, 1024, "wg1024 lds256 ahead1 unroll1"},
-    {k_score<256, 0, 1, 4, 1, 0>, 256, "wg256 ahead1 unroll4 occ"},
-    {k_score<256, 0, 4, 1, 0, 0>, 256, "wg256 ahead4 unroll1"},
-    {k_score<256, 0, 2, 1, 0, 16>, 256, "wg256 ahead2 unroll1 dyn16"},
-    {k_score<512, 0, 2, 2, 0, 0>, 512, "wg512 ahead2 unroll2"},
-    {k_score<256, 0, 2, 1, 0, 4>, 256, "wg256 ahead2 unroll1 dyn4"},
-    {k_score<256, 0, 1, 1, 0, 16>, 256, "wg256 ahead1 unroll1 dyn16"},
-    {k_score<256, 0, 4, 1, 0, 16>, 256, "wg256 ahead4 unroll1 dyn16"},
-    {k_score_batch<256, 16, 2, 1, 0>, 256, "batch wg256 head16 unroll2 occ"},
-    {k_score_batch<256, 16, 1, 0, 16>, 256, "batch wg256 head16 unroll1 dyn16"},
-    {k_score_batch<256, 16, 1, 0, 4>, 256, "batch wg256 head16 unroll1 dyn4"},
-    {k_score_batch<256, 24, 1, 0, 16>, 256, "batch wg256 head24 unroll1 dyn16"},
-    {k_score_batch<256, 32, 1, 0, 16>, 256, "batch wg256 head32 unroll1 dyn16"},
-    {k_score_batch<256, 8, 1, 0, 16>, 256, "batch wg256 head8 unroll1 dyn16"},
-    {k_score_batch<256, 16, 2, 0, 16>, 256, "batch wg256 head16 unroll2 dyn16"},
-    {k_score_batch<512, 16, 1, 0, 16>, 512, "batch wg512 head16 unroll1 dyn16"},
-    {k_score_fast<256, 8, 1, 16, 0>, 256, "fast wg256 head8 unroll1 dyn16", 1},
-    {k_score_fast<256, 8, 2, 16, 0>, 256, "fast wg256 head8 unroll2 dyn16", 1},
-    {k_score_fast<256, 4, 1, 16, 0>, 256, "fast wg256 head4 unroll1 dyn16", 1},
-    {k_score_fast<256, 4, 2, 16, 0>, 256, "fast wg256 head4 unroll2 dyn16", 1},
-    {k_score_fast<256, 8, 1, 4, 0>, 256, "fast wg256 head8 unroll1 dyn4", 1},
-    {k_score_fast<512, 8, 2, 16, 0>, 512, "fast wg512 head8 unroll2 dyn16", 1},
-    {k_score_fast<256, 4, 1, 16, 1>, 256, "fast wg256 head4 unroll1 dyn16 coarse", 1},
-    {k_score_fast<256, 4, 2, 16, 1>, 256, "fast wg256 head4 unroll2 dyn16 coarse", 1},
-    {k_score_fast<256, 8, 1, 16, 1>, 256, "fast wg256 head8 unroll1 dyn16 coarse", 1},
-    {k_score_fast<256, 8, 2, 16, 1>, 256, "fast wg256 head8 unroll2 dyn16 coarse", 1},
-    {k_score_fast<256, 6, 2, 16, 1>, 256, "fast wg256 head6 unroll2 dyn16 coarse", 1},
-    {k_score_fast<512, 4, 2, 16, 1>, 512, "fast wg512 head4 unroll2 dyn16 coarse", 1},
-    {k_score_wave<256, 4, 2, 16, 1>, 256, "wave wg256 head4 unroll2 dyn16 coarse", 1},
-    {k_score_wave<256, 4, 1, 16, 1>, 256, "wave wg256 head4 unroll1 dyn16 coarse", 1},
-    {k_score_wave<256, 4, 2, 16, 0>, 256, "wave wg256 head4 unroll2 dyn16", 1},
-    {k_score_wave<256, 8, 2, 16, 1>, 256, "wave wg256 head8 unroll2 dyn16 coarse", 1},
-    {k_score_wave<256, 6, 2, 16, 1>, 256, "wave wg256 head6 unroll2 dyn16 coarse", 1},
-    {k_score_wave<256, 2, 2, 16, 1>, 256, "wave wg256 head2 unroll2 dyn16 coarse", 1},
-    {k_score_wave<256, 4, 4, 16, 1>, 256, "wave wg256 head4 unroll4 dyn16 coarse", 1},
-    {k_score_wave<256, 4, 2, 4, 1>, 256, "wave wg256 head4 unroll2 dyn4 coarse", 1},
-    {k_score_swar<256, 4, 1, 16, 1>, 256, "swar wg256 head4 unroll1 dyn16 coarse", 1},
-    {k_score_swar<256, 4, 2, 16, 1>, 256, "swar wg256 head4 unroll2 dyn16 coarse", 1},
-    {k_score_swar<256, 4, 1, 16, 0>, 256, "swar wg256 head4 unroll1 dyn16", 1},
-    {k_score_swar<256, 6, 1, 16, 1>, 256, "swar wg256 head6 unroll1 dyn16 coarse", 1},
-    {k_score_swar<256, 3, 1, 16, 1>, 256, "swar wg256 head3 unroll1 dyn16 coarse", 1},
-    {k_score_swar<256, 4, 1, 4, 1>, 256, "swar wg256 head4 unroll1 dyn4 coarse", 1},
-    {k_score_swar<512, 4, 1, 16, 1>, 512, "swar wg512 head4 unroll1 dyn16 coarse", 1},
-    {k_score_swar<256, 4, 1, 16, 2>, 256, "swar wg256 head4 unroll1 dyn16 coarse4", 1},
-    {k_score_swar<256, 3, 1, 16, 2>, 256, "swar wg256 head3 unroll1 dyn16 coarse4", 1},
-    {k_score_swar<256, 4, 2, 16, 2>, 256, "swar wg256 head4 unroll2 dyn16 coarse4", 1},
-    {k_score_swar<256, 3, 1, 16, 2, 0, 1>, 256, "swar wg256 head3 unroll1 dyn16 coarse4 bit", 1},
+    {k_score<256, 0, 1, 1, 0, 0>, 256, "plain wg256", 0},
+    {k_score<256, 0, 2, 2, 1, 16>, 256, "plain wg256 ahead2 unroll2 occ dyn16", 0},
+    {k_score_swar<256, 3, 1, 16, 2, 1>, 256, "swar wg256 head3 unroll1 dyn16 coarse4 bit", 1},
+    {k_score_swar<256, 4, 1, 16, 2, 1>, 256, "swar wg256 head4 unroll1 dyn16 coarse4 bit", 1},
+    {k_score_swar<256, 4, 1, 16, 0, 0>, 256, "swar wg256 head4 unroll1 dyn16", 1},
     {k_score_near<256, 1, 16, 2, 1>, 256, "near wg256 unroll1 dyn16 coarse4 bit", 1},
     {k_score_near<256, 1, 16, 2, 0>, 256, "near wg256 unroll1 dyn16 coarse4", 1},
+    {k_score_near<256, 1, 16, 0, 1>, 256, "near wg256 unroll1 dyn16 bit", 1},
     {k_score_near<256, 2, 16, 2, 1>, 256, "near wg256 unroll2 dyn16 coarse4 bit", 1},
     {k_score_near<256, 1, 8, 2, 1>, 256, "near wg256 unroll1 dyn8 coarse4 bit", 1},
-    {k_score_near<256, 1, 32, 2, 1>, 256, "near wg256 unroll1 dyn32 coarse4 bit", 1},
     {k_score_near<512, 1, 16, 2, 1>, 512, "near wg512 unroll1 dyn16 coarse4 bit", 1},
-    {k_score_swar<256, 3, 1, 16, 2, 0, 1, 1>, 256, "swar wg256 head3 unroll1 dyn16 bit masks", 1},
-    {k_score_swar<256, 3, 2, 16, 2, 0, 1, 1>, 256, "swar wg256 head3 unroll2 dyn16 bit masks", 1},
-    {k_score_swar<256, 4, 1, 16, 2, 0, 1, 1>, 256, "swar wg256 head4 unroll1 dyn16 bit masks", 1},
-    {k_score_swar<256, 3, 1, 16, 2, 0, 0, 1>, 256, "swar wg256 head3 unroll1 dyn16 masks", 1},
-    {k_score_swar<256, 4, 1, 16, 2, 0, 1>, 256, "swar wg256 head4 unroll1 dyn16 coarse4 bit", 1},
-    {k_score_swar<256, 3, 2, 16, 2, 0, 1>, 256, "swar wg256 head3 unroll2 dyn16 coarse4 bit", 1},
-    {k_score_swar<256, 3, 1, 16, 1, 0, 1>, 256, "swar wg256 head3 unroll1 dyn16 coarse bit", 1},
-    {k_score_swar<256, 4, 1, 16, 1, 8>, 256, "swar wg256 head4 unroll1 dyn16 coarse wpe8", 1},
-    {k_score_swar<256, 3, 1, 16, 1, 8>, 256, "swar wg256 head3 unroll1 dyn16 coarse wpe8", 1},
-    {k_score_swar<256, 4, 1, 16, 0, 8>, 256, "swar wg256 head4 unroll1 dyn16 wpe8", 1},
-    {k_score_swar<256, 4, 2, 16, 1, 8>, 256, "swar wg256 head4 unroll2 dyn16 coarse wpe8", 1},
 };
 constexpr int kNumVariants = (int)(sizeof(kVariants) / sizeof(kVariants[0]));
 int g_resident[kNumVariants];   // workgroups per CU, from the occupancy query
@@ -1734,6 +993,8 @@ void launch_mask(const Params &p, PointsDev pts, ToolDev t, GridDev g, int64_t n
 }
 
 int score_variants() { return kNumVariants; }
+
+int score_variant_default() { return 5; }   // "near wg256 unroll1 dyn16 coarse4 bit"
 
 const char *score_variant_name(int v) {
   return v >= 0 && v < kNumVariants ? kVariants[v].name : "";

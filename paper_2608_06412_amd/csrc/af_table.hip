@@ -242,8 +242,8 @@ __global__ void k_coarse_scan(int32_t K, const uint32_t *ccounts, uint32_t *cbeg
   cbegin[K] = acc;
 }
 
-__global__ void k_table_grid(const uint32_t *entries, int64_t n, const uint32_t *centries,
-                             int64_t nc, int32_t gx, int32_t gxy, uint2 *xent, int32_t *cdelta) {
+__global__ void k_table_grid(const uint32_t *entries, int64_t n, int32_t gx, int32_t gxy,
+                             uint2 *xent) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
     const uint32_t e = entries[i];
@@ -253,20 +253,15 @@ __global__ void k_table_grid(const uint32_t *entries, int64_t n, const uint32_t 
                         ((uint32_t)(oz & 7) << 8) | ((uint32_t)entry_cls(e) << 30);
     xent[i] = make_uint2((uint32_t)d, o7);
   }
-  if (i < nc) {
-    const uint32_t e = centries[i];
-    cdelta[i] = entry_x(e) + gx * entry_y(e) + gxy * entry_z(e);
-  }
 }
 
 }  // namespace
 
 int launch_table_grid(const ToolDev &t, const GridDev &g, hipStream_t s) {
-  const int64_t n = std::max(t.n_entries, t.n_centries);
+  const int64_t n = t.n_entries;
   if (n <= 0) return 0;
   hipLaunchKernelGGL(k_table_grid, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, t.entries,
-                     t.n_entries, t.centries, t.n_centries, g.gd[0], g.gd[0] * g.gd[1], t.xent,
-                     t.cdelta);
+                     n, g.gd[0], g.gd[0] * g.gd[1], t.xent);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -274,12 +269,9 @@ int launch_table_coarse(int32_t K, const uint32_t *begin, const uint32_t *counts
                         const uint32_t *entries, uint32_t *far_begin, uint32_t *ccounts,
                         uint32_t *cbegin, uint32_t *centries, uint8_t *cflag, int pass, int sh,
                         hipStream_t s) {
-  if (sh == 3)
-    hipLaunchKernelGGL(k_table_coarse<3>, dim3((unsigned)K), dim3(256), 0, s, K, begin, counts,
-                       entries, far_begin, ccounts, cbegin, centries, cflag, pass);
-  else
-    hipLaunchKernelGGL(k_table_coarse<2>, dim3((unsigned)K), dim3(256), 0, s, K, begin, counts,
-                       entries, far_begin, ccounts, cbegin, centries, cflag, pass);
+  if (sh != 2) return -1;
+  hipLaunchKernelGGL(k_table_coarse<2>, dim3((unsigned)K), dim3(256), 0, s, K, begin, counts,
+                     entries, far_begin, ccounts, cbegin, centries, cflag, pass);
   if (pass == 0) hipLaunchKernelGGL(k_coarse_scan, dim3(1), dim3(1), 0, s, K, ccounts, cbegin);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
