@@ -1,6 +1,7 @@
 // libaf host side: context and device memory, the C ABI of include/af.h and
 // the stream-ordered sequence of kernels per call.
 #include <math.h>
+#include <stddef.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
@@ -475,6 +476,7 @@ int af_set_tool_kernels(af_ctx *c, int32_t tool_id, const af_tool *tool, int32_t
     dev_free(c, t.far_begin, sizeof(uint32_t) * t.K);
     dev_free(c, t.same, sizeof(uint64_t) * ((t.K + 63) / 64));
     dev_free(c, t.xent, sizeof(uint2) * std::max<int64_t>(1, t.n_entries));
+    if (t.rent) dev_free(c, t.rent, sizeof(uint32_t) * std::max<int64_t>(1, t.n_entries));
     dev_free(c, t.c4begin, sizeof(uint32_t) * (t.K + 1));
     dev_free(c, t.c4flag, t.K);
     dev_free(c, t.c4entries, sizeof(uint32_t) * std::max<int64_t>(1, t.n_c4entries));
@@ -554,6 +556,16 @@ int af_set_tool_kernels(af_ctx *c, int32_t tool_id, const af_tool *tool, int32_t
     for (uint32_t e : he)
       reach = std::max({reach, std::abs(entry_x(e)), std::abs(entry_y(e)), std::abs(entry_z(e))});
     nt.reach = reach;
+    if (reach <= 255) {
+      std::vector<uint32_t> rel(total);
+      for (uint32_t j = 0; j < total; ++j) {
+        const uint32_t e = he[j];
+        rel[j] = (uint32_t)(entry_x(e) + 256) | ((uint32_t)(entry_y(e) + 256) << 10) |
+                 ((uint32_t)(entry_z(e) + 256) << 20) | ((uint32_t)entry_cls(e) << 30);
+      }
+      ALLOC(c, nt.rent, std::max<int64_t>(1, total));
+      HIP_TRY(c, hipMemcpy(nt.rent, rel.data(), sizeof(uint32_t) * total, hipMemcpyHostToDevice));
+    }
   }
   nt.n_entries = total;
   ALLOC(c, nt.xent, std::max<int64_t>(1, total));
@@ -592,7 +604,7 @@ int af_integrate_frame(af_ctx *c, const float *xyz, int64_t n, const float origi
   launch_frame_prep(xyz, n, Q, c->p, c->map, c->pts, c->fs, c->counters, s);
   launch_assign_blocks(c->map, c->fs, c->counters, frame, s);
   launch_commit_blocks(c->map, c->counters, s);
-  HIP_TRY(c, hipMemcpyAsync(c->counters_host, c->counters, sizeof(FrameCounters),
+  HIP_TRY(c, hipMemcpyAsync(c->counters_host, c->counters, offsetof(FrameCounters, fold),
                             hipMemcpyDeviceToHost, s));
   HIP_TRY(c, hipStreamSynchronize(s));
   if ((rc = hip_check(c, "frame prep")) != AF_OK) return rc;
@@ -890,6 +902,11 @@ int af_frame_stats_get(af_ctx *c, af_frame_stats *st) {
   st->n_valid = (int64_t)h.n_valid;
   st->n_dropped = (int64_t)h.n_dropped;
   st->n_in = st->n_valid + st->n_dropped;
+  for (int i = 0; i < kStatSlots; ++i) {
+    h.pairs_applied += h.fold[i][0];
+    h.pairs_excluded += h.fold[i][1];
+    h.voxels_folded += h.fold[i][2];
+  }
   st->pairs_applied = (int64_t)h.pairs_applied;
   st->pairs_excluded = (int64_t)h.pairs_excluded;
   st->band_marks = (int64_t)h.band_marks;
@@ -908,8 +925,26 @@ int af_score_stats_get(af_ctx *c, int32_t tool_id, af_score_stats *st) {
   if (!t.entries) return fail(c, AF_ENOTOOL, "tool %d has no kernels", tool_id);
   int rc = sync_last(c);
   if (rc != AF_OK) return rc;
-  ScoreCounters h;
-  HIP_TRY(c, hipMemcpy(&h, t.counters, sizeof(h), hipMemcpyDeviceToHost));
+  std::vector<ScoreCounterBlock> blk(kStatSlots);
+  HIP_TRY(c, hipMemcpy(blk.data(), t.counters, sizeof(ScoreCounters), hipMemcpyDeviceToHost));
+  ScoreCounterBlock h;
+  memset(&h, 0, sizeof(h));
+  for (const ScoreCounterBlock &b : blk) {
+    h.n_confident += b.n_confident;
+    h.n_accessible += b.n_accessible;
+    h.n_blocked += b.n_blocked;
+    h.n_no_candidate += b.n_no_candidate;
+    h.candidate_tests += b.candidate_tests;
+    h.canonical_tests += b.canonical_tests;
+    h.canonical_lookups += b.canonical_lookups;
+    h.deep_tests += b.deep_tests;
+    h.deep_chunks_max += b.deep_chunks_max;
+    h.coarse_checks += b.coarse_checks;
+    h.coarse_clear += b.coarse_clear;
+    h.chunks_body += b.chunks_body;
+    h.chunks_far += b.chunks_far;
+    h.arm_lookups += b.arm_lookups;
+  }
   st->n_points = c->n_points;
   st->n_confident = (int64_t)h.n_confident;
   st->n_accessible = (int64_t)h.n_accessible;

@@ -177,6 +177,7 @@ __global__ void k_reset_counters(FrameCounters *c, MapDev m, PointsDev pts) {
   c->n_valid = c->n_dropped = c->pairs_applied = c->pairs_excluded = 0;
   c->band_marks = c->voxels_folded = 0;
   c->n_new_blocks = c->n_touched = c->n_new_points = c->status = 0;
+  for (int i = 0; i < kStatSlots; ++i) c->fold[i][0] = c->fold[i][1] = c->fold[i][2] = 0ull;
   for (int i = 0; i < 3; ++i) {
     c->bmin[i] = 0x7fffffff;
     c->bmax[i] = -0x7fffffff - 1;
@@ -363,11 +364,14 @@ __device__ inline uint32_t voxel_code(const Params &p, int32_t S, int32_t W, boo
 }
 
 // Block `id` (512 threads, one voxel each; `code` is workgroup scratch)
-// written to its brick of the grid.
+// written to its brick of the grid.  clrw is the block's cleared-bit word of
+// this thread's voxel, surfw its surface word t - 32 (threads 32..47), both
+// loaded by the caller (early, so the loads overlap other work); bkey its key.
 __device__ void write_brick(const Params &p, MapDev m, GridDev g, int64_t id, int32_t S,
-                            int32_t W, uint8_t *code) {
+                            int32_t W, uint8_t *code, uint32_t clrw, uint32_t surfw,
+                            int64_t bkey) {
   int t = threadIdx.x;
-  bool cl = (m.clr[id * 16 + (t >> 5)] >> (t & 31)) & 1u;
+  bool cl = (clrw >> (t & 31)) & 1u;
   uint32_t cd = voxel_code(p, S, W, cl);
   code[t] = (uint8_t)cd;
   int any_occ = __syncthreads_or((int)(cd & 1u));
@@ -387,7 +391,7 @@ __device__ void write_brick(const Params &p, MapDev m, GridDev g, int64_t id, in
     __syncthreads();
   }
   int32_t b[3];
-  unpack_key(m.bkey[id], b[0], b[1], b[2]);
+  unpack_key(bkey, b[0], b[1], b[2]);
   int x = b[0] - g.g0[0], y = b[1] - g.g0[1], z = b[2] - g.g0[2];
   bool inside = (unsigned)x < (unsigned)g.gd[0] && (unsigned)y < (unsigned)g.gd[1] &&
                 (unsigned)z < (unsigned)g.gd[2];
@@ -398,7 +402,7 @@ __device__ void write_brick(const Params &p, MapDev m, GridDev g, int64_t id, in
       for (int j = 0; j < 16; ++j) w |= (uint32_t)code[t * 16 + j] << (2 * j);
       g.pred[brick * 32 + t] = w;
     } else if (t < 48) {
-      g.surf[brick * 16 + (t - 32)] = m.surf[id * 16 + (t - 32)];
+      g.surf[brick * 16 + (t - 32)] = surfw;
     } else if (t == 48) {
       uint32_t bit = 1u << (brick & 31);
       if (any_occ)
@@ -484,14 +488,23 @@ __global__ void __launch_bounds__(kBlockVox)
 k_integrate_fold(int3 Q, Params p, MapDev m, FrameScratch fs, FrameCounters *c, GridDev g) {
   __shared__ int4 tile[kBlockVox];
   __shared__ uint8_t code[kBlockVox];
+  __shared__ unsigned long long s_stat[3];
+  if (threadIdx.x < 3) s_stat[threadIdx.x] = 0ull;
   const int nt = c->n_touched;
   const int t = threadIdx.x;
   const int64_t lo_clamp = p.clamp_neg ? -(int64_t)p.tau_u : 0;
   unsigned applied = 0, excluded = 0, folded = 0;
   for (int i = blockIdx.x; i < nt; i += gridDim.x) {
     const int64_t id = fs.touched[i];
+    // the block's own words first: their latency overlaps the gather below
+    const int64_t v = id * kBlockVox + t;
+    const int32_t S0 = m.S[v];
+    const int32_t W0 = m.W[v];
+    const uint32_t clrw = m.clr[id * 16 + (t >> 5)];
+    const uint32_t surfw = (t >= 32 && t < 48) ? m.surf[id * 16 + (t - 32)] : 0u;
+    const int64_t bkey = m.bkey[id];
     int32_t b[3];
-    unpack_key(m.bkey[id], b[0], b[1], b[2]);
+    unpack_key(bkey, b[0], b[1], b[2]);
     const int vx = 8 * b[0] + (t & 7), vy = 8 * b[1] + ((t >> 3) & 7), vz = 8 * b[2] + (t >> 6);
     const int64_t cq0 = 256 * (int64_t)vx + 128 - Q.x;  // voxel centre - sensor
     const int64_t cq1 = 256 * (int64_t)vy + 128 - Q.y;
@@ -531,9 +544,8 @@ k_integrate_fold(int3 Q, Params p, MapDev m, FrameScratch fs, FrameCounters *c, 
         ++dW;
       }
     }
-    const int64_t v = id * kBlockVox + t;
-    int32_t S = m.S[v];
-    int32_t W = m.W[v];
+    int32_t S = S0;
+    int32_t W = W0;
     if (dW > 0) {
       int64_t S2 = (int64_t)S + dS, W2 = (int64_t)W + dW;
       if (W2 > p.cap) {
@@ -546,7 +558,7 @@ k_integrate_fold(int3 Q, Params p, MapDev m, FrameScratch fs, FrameCounters *c, 
       m.W[v] = (uint16_t)W;
       ++folded;
     }
-    write_brick(p, m, g, id, S, W, code);
+    write_brick(p, m, g, id, S, W, code, clrw, surfw, bkey);
   }
   unsigned long long sa = applied, se = excluded, sf = folded;
   for (int off = 32; off >= 1; off >>= 1) {
@@ -554,19 +566,25 @@ k_integrate_fold(int3 Q, Params p, MapDev m, FrameScratch fs, FrameCounters *c, 
     se += __shfl_xor((unsigned)se, off);
     sf += __shfl_xor((unsigned)sf, off);
   }
+  __syncthreads();
   if (lane_id() == 0) {
-    if (sa) atomicAdd(&c->pairs_applied, sa);
-    if (se) atomicAdd(&c->pairs_excluded, se);
-    if (sf) atomicAdd(&c->voxels_folded, sf);
+    if (sa) atomicAdd(&s_stat[0], sa);
+    if (se) atomicAdd(&s_stat[1], se);
+    if (sf) atomicAdd(&s_stat[2], sf);
   }
+  __syncthreads();
+  if (threadIdx.x < 3 && s_stat[threadIdx.x])
+    atomicAdd(&c->fold[blockIdx.x % kStatSlots][threadIdx.x], s_stat[threadIdx.x]);
 }
 
 __global__ void __launch_bounds__(kBlockVox)
 k_grid_rebuild(Params p, MapDev m, GridDev g, int64_t n_blocks) {
   __shared__ uint8_t code[kBlockVox];
   for (int64_t id = blockIdx.x; id < n_blocks; id += gridDim.x) {
-    int64_t v = id * kBlockVox + threadIdx.x;
-    write_brick(p, m, g, id, m.S[v], m.W[v], code);
+    const int t = threadIdx.x;
+    const int64_t v = id * kBlockVox + t;
+    write_brick(p, m, g, id, m.S[v], m.W[v], code, m.clr[id * 16 + (t >> 5)],
+                (t >= 32 && t < 48) ? m.surf[id * 16 + (t - 32)] : 0u, m.bkey[id]);
   }
 }
 

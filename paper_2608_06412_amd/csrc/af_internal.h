@@ -56,21 +56,37 @@ struct Params {
 };
 
 // Per-frame device counters (zeroed at the start of each frame).
+// Counters that many workgroups add to are spread over kStatSlots cache
+// lines (slot = workgroup index mod kStatSlots): atomics on one address are
+// serialised by the cache, so a single address would stall every workgroup.
+constexpr int kStatSlots = 32;
+
 struct FrameCounters {
   unsigned long long n_valid, n_dropped, pairs_applied, pairs_excluded;
   unsigned long long band_marks, voxels_folded;
   int32_t n_new_blocks, n_touched, n_new_points, status;
   int32_t bmin[3], bmax[3];
   int32_t blocks_before, points_before;
+  // per-slot fold statistics: [slot][0] applied pairs, [1] cone-excluded
+  // pairs, [2] folded voxels (summed on the host; not part of the mid-frame
+  // read of the fields above)
+  unsigned long long fold[kStatSlots][16];
 };
 
-struct ScoreCounters {
+// One block of scoring counters; the device holds kStatSlots of them, one
+// 128-byte line each (see kStatSlots), and the host sums them.
+struct ScoreCounterBlock {
   unsigned long long n_confident, n_accessible, n_blocked, n_no_candidate;
   unsigned long long candidate_tests, canonical_tests, canonical_lookups;
   unsigned long long deep_tests, deep_chunks_max;  // diagnostics of the two-phase kernels
-  unsigned long long coarse_checks, coarse_clear;   // corridor brick checks, and those clear
+  unsigned long long coarse_checks, coarse_clear;   // corridor cell checks, and those clear
   unsigned long long chunks_body, chunks_far;       // 64-entry steps taken by deep scans
   unsigned long long arm_lookups;   // canonical arm-sample lookups answered by the mask kernel
+  unsigned long long pad[2];
+};
+
+struct ScoreCounters {
+  ScoreCounterBlock s[kStatSlots];
 };
 
 struct HashTable {
@@ -164,6 +180,9 @@ struct ToolDev {
   // (ox&7) | (oy&7) << 4 | (oz&7) << 8 | class << 30}.  Rebuilt whenever the
   // grid is reallocated.
   uint2 *xent;          // [entries]
+  // grid-independent 4-byte form, when every offset component is within
+  // +-255: (ox + 256) | (oy + 256) << 10 | (oz + 256) << 20 | class << 30
+  uint32_t *rent;       // [entries] or null
   int64_t n_entries;
   int32_t reach;        // largest |offset| component over the table, voxels
 };

@@ -3,6 +3,7 @@
 #include "af_internal.h"
 
 #include <algorithm>
+#include <cstring>
 #include <vector>
 
 #pragma clang fp contract(off)
@@ -204,6 +205,64 @@ __device__ inline bool sw_hits(uint2 xe, uint32_t code) {
   return sw_cls(xe) == AF_CLS_NEAR ? code != 0u : (code & 1u) != 0u;
 }
 
+// The 4-byte grid-independent entry form: per axis a 10-bit field
+// r + o + 256 (r the point's in-brick coordinate, |o| <= 255), so one add of
+// the point's fields to the entry gives, per axis, the brick offset + 32 in
+// bits 3-9 and the target's in-brick coordinate in bits 0-2 of each field.
+// Bp carries the -32 bias of all three axes.
+__device__ inline SwFrame rel_frame(const GridDev &g, const SwGrid &q, const int32_t s[3]) {
+  const uint32_t bx = (uint32_t)((s[0] >> 3) - g.g0[0]);
+  const uint32_t by = (uint32_t)((s[1] >> 3) - g.g0[1]);
+  const uint32_t bz = (uint32_t)((s[2] >> 3) - g.g0[2]);
+  SwFrame f;
+  f.Bp = bx + q.gx * by + q.gxy * bz - 32u * (1u + q.gx + q.gxy);
+  f.rp = (uint32_t)(s[0] & 7) | ((uint32_t)(s[1] & 7) << 10) | ((uint32_t)(s[2] & 7) << 20);
+  return f;
+}
+
+__device__ inline uint32_t rel_brick(const SwGrid &q, const SwFrame &f, uint32_t tt) {
+  return f.Bp + ((tt >> 3) & 127u) + q.gx * ((tt >> 13) & 127u) + q.gxy * ((tt >> 23) & 127u);
+}
+
+__device__ inline uint32_t code_rel(const SwGrid &q, const SwFrame &f, uint32_t e) {
+  const uint32_t tt = f.rp + e;
+  const uint32_t brick = rel_brick(q, f, tt);
+  const uint32_t wib = ((tt >> 11) & 3u) | ((tt >> 18) & 0x1cu);   // (ly >> 1) | lz << 2
+  const uint32_t bit = ((tt & 7u) << 1) | ((tt >> 6) & 0x10u);     // 2 (lx + 8 (ly & 1))
+  const uint32_t w =
+      __builtin_amdgcn_raw_buffer_load_b32(q.pred, ((brick << 5) | wib) << 2, 0, 0);
+  return (w >> bit) & 3u;
+}
+
+__device__ inline uint32_t occ_rel(const SwGrid &q, const SwFrame &f, uint32_t e) {
+  const uint32_t tt = f.rp + e;
+  const uint32_t brick = rel_brick(q, f, tt);
+  const uint32_t wib = ((tt >> 12) & 1u) | ((tt >> 19) & 0xeu);    // (ly >> 2) | lz << 1
+  const uint32_t bit = (tt & 7u) | ((tt >> 7) & 0x18u);            // lx | (ly & 3) << 3
+  const uint32_t w =
+      __builtin_amdgcn_raw_buffer_load_b32(q.occ1, ((brick << 4) | wib) << 2, 0, 0);
+  return (w >> bit) & 1u;
+}
+
+// Uniform access to the two entry forms (RE: the 4-byte form).
+template <int RE> struct EntryOf { using T = uint2; };
+template <> struct EntryOf<1> { using T = uint32_t; };
+
+template <int RE>
+__device__ inline typename EntryOf<RE>::T load_entry(const ToolDev &t, uint32_t idx) {
+  if constexpr (RE) return t.rent[idx]; else return t.xent[idx];
+}
+__device__ inline uint32_t ent_cls(uint2 xe) { return xe.y >> 30; }
+__device__ inline uint32_t ent_cls(uint32_t e) { return e >> 30; }
+template <int B1>
+__device__ inline uint32_t ent_code(const SwGrid &q, const SwFrame &f, uint2 xe) {
+  return B1 ? occ_bit_sw(q, f, xe) : code_sw(q, f, xe);
+}
+template <int B1>
+__device__ inline uint32_t ent_code(const SwGrid &q, const SwFrame &f, uint32_t e) {
+  return B1 ? occ_rel(q, f, e) : code_rel(q, f, e);
+}
+
 // One lane per point: the point's normal and viewpoint vectors stay in
 // registers (fp64, exact conversions of integers) while every lane walks the
 // same orientation list, so each direction is a wave-uniform load.
@@ -312,7 +371,10 @@ k_mask(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t mw) {
     unsigned hi = __shfl_xor((unsigned)(cand >> 32), off);
     cand += ((unsigned long long)hi << 32) | lo;
   }
-  if (lane_id() == 0 && cand) atomicAdd(&t.counters->candidate_tests, cand);
+  if (lane_id() == 0 && cand)
+    atomicAdd(&t.counters->s[(blockIdx.x * kWaves + (threadIdx.x >> 6)) % kStatSlots]
+                   .candidate_tests,
+              cand);
 }
 
 // Position of the r-th (1-based) set bit of m, or 64.
@@ -415,6 +477,7 @@ k_score(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t mw,
   const int64_t wave0 =
       (int64_t)blockIdx.x * NW + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t nwaves = (int64_t)gridDim.x * NW;
+  ScoreCounterBlock &sc = t.counters->s[(blockIdx.x * NW + (threadIdx.x >> 6)) % kStatSlots];
   uint64_t conf = 0, acc = 0, blk = 0, nocand = 0, tests = 0, lookups = 0;
   int64_t i = wave0, batch_end = wave0 + 1;
   if (FB > 0) {
@@ -499,12 +562,12 @@ k_score(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t mw,
     }
   }
   if (lane == 0) {
-    if (conf) atomicAdd(&t.counters->n_confident, (unsigned long long)conf);
-    if (acc) atomicAdd(&t.counters->n_accessible, (unsigned long long)acc);
-    if (blk) atomicAdd(&t.counters->n_blocked, (unsigned long long)blk);
-    if (nocand) atomicAdd(&t.counters->n_no_candidate, (unsigned long long)nocand);
-    if (tests) atomicAdd(&t.counters->canonical_tests, (unsigned long long)tests);
-    if (lookups) atomicAdd(&t.counters->canonical_lookups, (unsigned long long)lookups);
+    if (conf) atomicAdd(&sc.n_confident, (unsigned long long)conf);
+    if (acc) atomicAdd(&sc.n_accessible, (unsigned long long)acc);
+    if (blk) atomicAdd(&sc.n_blocked, (unsigned long long)blk);
+    if (nocand) atomicAdd(&sc.n_no_candidate, (unsigned long long)nocand);
+    if (tests) atomicAdd(&sc.canonical_tests, (unsigned long long)tests);
+    if (lookups) atomicAdd(&sc.canonical_lookups, (unsigned long long)lookups);
   }
 }
 
@@ -515,37 +578,42 @@ __device__ inline uint32_t plane_sum(const uint64_t pl[4], uint64_t m) {
          4u * (uint32_t)__popcll(pl[2] & m) + 8u * (uint32_t)__popcll(pl[3] & m);
 }
 
-// B1: the entries are body or corridor entries only (no arm samples), read
-// from the one-bit plane.
-template <int UN, int B1>
+// Lanes over entries [b, e) of one orientation, 64 per step, the next step's
+// entries loaded while this step's voxel words are gathered.  B1: the
+// entries are body or corridor entries only (no arm samples), read from the
+// one-bit plane.  RE: the 4-byte entry form.
+template <int UN, int B1, int RE>
 __device__ inline bool scan_fine_sw(const Params &p, const ToolDev &t, const SwGrid &q,
                                     const SwFrame &f, uint32_t b, uint32_t e, int &body,
                                     uint32_t &lookups, uint32_t &steps) {
+  using Ent = typename EntryOf<RE>::T;
   if (b >= e) return true;
   const uint32_t lane = (uint32_t)lane_id();
-  uint2 ent[UN];
+  Ent ent[UN];
 #pragma unroll
   for (int u = 0; u < UN; ++u) {
     const uint32_t idx = b + 64 * u + lane;
-    ent[u] = t.xent[idx < e ? idx : e - 1];
+    ent[u] = load_entry<RE>(t, idx < e ? idx : e - 1);
   }
   for (uint32_t base = b; base < e; base += 64 * UN) {
     ++steps;
     uint32_t code[UN];
-    uint2 nxt[UN];
+    Ent nxt[UN];
 #pragma unroll
-    for (int u = 0; u < UN; ++u) code[u] = B1 ? occ_bit_sw(q, f, ent[u]) : code_sw(q, f, ent[u]);
+    for (int u = 0; u < UN; ++u) code[u] = ent_code<B1>(q, f, ent[u]);
 #pragma unroll
     for (int u = 0; u < UN; ++u) {
       const uint32_t idx = base + 64 * (UN + u) + lane;
-      nxt[u] = t.xent[idx < e ? idx : e - 1];
+      nxt[u] = load_entry<RE>(t, idx < e ? idx : e - 1);
     }
 #pragma unroll
     for (int u = 0; u < UN; ++u) {
       const uint32_t cb = base + 64 * u;
-      const bool hit = cb + lane < e && (B1 ? code[u] != 0u : sw_hits(ent[u], code[u]));
-      const uint64_t nf = __ballot(hit && sw_cls(ent[u]) != AF_CLS_BODY);
-      const uint64_t bm = __ballot(hit && sw_cls(ent[u]) == AF_CLS_BODY);
+      const uint32_t cls = ent_cls(ent[u]);
+      const bool hit = cb + lane < e &&
+                       (B1 || cls != AF_CLS_NEAR ? (code[u] & 1u) != 0u : code[u] != 0u);
+      const uint64_t nf = __ballot(hit && cls != AF_CLS_BODY);
+      const uint64_t bm = __ballot(hit && cls == AF_CLS_BODY);
       if (cb >= e) break;
       const int stop = chunk_stop(nf, bm, p.n_c - body);
       if (stop < 64) {
@@ -588,16 +656,16 @@ __device__ inline bool corridor_clear4_sw(const ToolDev &t, const SwGrid &q, con
 // Entries [b, e) of orientation k after its first E: body entries finely,
 // then the corridor -- skipped when its 4^3 cells are clear (CO), finely
 // otherwise.  Canonical lookups stay the table-order count.
-template <int UN, int CO, int B1>
+template <int UN, int CO, int B1, int RE = 0>
 __device__ inline bool scan_rest_sw(const Params &p, const ToolDev &t, const SwGrid &q,
                                     const SwFrame &f, int k, uint32_t b, uint32_t e, int body,
                                     uint32_t &lookups, uint32_t &cchecks, uint32_t &cclear,
                                     uint32_t &sbody, uint32_t &sfar, const uint32_t c4[3],
                                     const uint8_t *occ4) {
-  if (!CO) return scan_fine_sw<UN, B1>(p, t, q, f, b, e, body, lookups, sbody);
+  if (!CO) return scan_fine_sw<UN, B1, RE>(p, t, q, f, b, e, body, lookups, sbody);
   const uint32_t fb = t.far_begin[k];
   const uint32_t mid = fb > b ? fb : b;
-  if (!scan_fine_sw<UN, B1>(p, t, q, f, b, mid, body, lookups, sbody)) return false;
+  if (!scan_fine_sw<UN, B1, RE>(p, t, q, f, b, mid, body, lookups, sbody)) return false;
   if (mid >= e) return true;
   if (t.c4flag[k] != 0) {
     ++cchecks;
@@ -607,7 +675,7 @@ __device__ inline bool scan_rest_sw(const Params &p, const ToolDev &t, const SwG
       return true;
     }
   }
-  return scan_fine_sw<UN, B1>(p, t, q, f, mid, e, body, lookups, sfar);
+  return scan_fine_sw<UN, B1, RE>(p, t, q, f, mid, e, body, lookups, sfar);
 }
 
 // Candidate-parallel scoring with grid-relative lookups (the configurations
@@ -643,24 +711,25 @@ k_score_swar(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t m
   const int64_t wave0 =
       (int64_t)blockIdx.x * NW + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t nwaves = (int64_t)gridDim.x * NW;
+  ScoreCounterBlock &sc = t.counters->s[(blockIdx.x * NW + (threadIdx.x >> 6)) % kStatSlots];
   // per-wave counters in 32 bits (fewer scalar registers), flushed to the
   // 64-bit totals whenever the largest of them passes 2^30
   uint32_t conf = 0, acc = 0, blk = 0, nocand = 0, tests = 0, lookups = 0, deep = 0, chunks = 0;
   uint32_t cchecks = 0, cclear = 0, sbody = 0, sfar = 0;
   auto flush = [&]() {
     if (lane == 0) {
-      if (conf) atomicAdd(&t.counters->n_confident, (unsigned long long)conf);
-      if (acc) atomicAdd(&t.counters->n_accessible, (unsigned long long)acc);
-      if (blk) atomicAdd(&t.counters->n_blocked, (unsigned long long)blk);
-      if (nocand) atomicAdd(&t.counters->n_no_candidate, (unsigned long long)nocand);
-      if (tests) atomicAdd(&t.counters->canonical_tests, (unsigned long long)tests);
-      if (lookups) atomicAdd(&t.counters->canonical_lookups, (unsigned long long)lookups);
-      if (deep) atomicAdd(&t.counters->deep_tests, (unsigned long long)deep);
-      if (chunks) atomicAdd(&t.counters->deep_chunks_max, (unsigned long long)chunks);
-      if (cchecks) atomicAdd(&t.counters->coarse_checks, (unsigned long long)cchecks);
-      if (cclear) atomicAdd(&t.counters->coarse_clear, (unsigned long long)cclear);
-      if (sbody) atomicAdd(&t.counters->chunks_body, (unsigned long long)sbody);
-      if (sfar) atomicAdd(&t.counters->chunks_far, (unsigned long long)sfar);
+      if (conf) atomicAdd(&sc.n_confident, (unsigned long long)conf);
+      if (acc) atomicAdd(&sc.n_accessible, (unsigned long long)acc);
+      if (blk) atomicAdd(&sc.n_blocked, (unsigned long long)blk);
+      if (nocand) atomicAdd(&sc.n_no_candidate, (unsigned long long)nocand);
+      if (tests) atomicAdd(&sc.canonical_tests, (unsigned long long)tests);
+      if (lookups) atomicAdd(&sc.canonical_lookups, (unsigned long long)lookups);
+      if (deep) atomicAdd(&sc.deep_tests, (unsigned long long)deep);
+      if (chunks) atomicAdd(&sc.deep_chunks_max, (unsigned long long)chunks);
+      if (cchecks) atomicAdd(&sc.coarse_checks, (unsigned long long)cchecks);
+      if (cclear) atomicAdd(&sc.coarse_clear, (unsigned long long)cclear);
+      if (sbody) atomicAdd(&sc.chunks_body, (unsigned long long)sbody);
+      if (sfar) atomicAdd(&sc.chunks_far, (unsigned long long)sfar);
     }
     conf = acc = blk = nocand = tests = lookups = deep = chunks = 0;
     cchecks = cclear = sbody = sfar = 0;
@@ -797,43 +866,61 @@ __device__ inline uint64_t readlane64(uint64_t v, int l) {
 // configurations named "near"): a candidate whose arm sample q hits first is
 // blocked after q + 1 lookups, summed for the whole wave from the two planes;
 // only the others are visited, scanning body and corridor from their fourth
-// entry.  Requires K <= kLdsK.  Same labels, first free orientations and
+// entry.  With PF > 1 the next PF such candidates first get their first
+// 64/PF entries in one step (64/PF lanes each): most are blocked there, and
+// only the undecided ones continue lane-parallel.  Requires K <= kLdsK.  Same labels, first free orientations and
 // canonical counts as the plain scan.
-template <int NT, int UN, int FB, int CO, int B1>
+template <int NT, int UN, int FB, int CO, int B1, int DIAG, int PF = 1, int RE = 0>
 __global__ void __launch_bounds__(NT)
 k_score_near(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t mw,
              unsigned *work) {
   constexpr int NW = NT / 64;
   constexpr uint32_t E = 3;   // the arm samples
+  constexpr int F = 64 / PF;  // prefix entries per candidate when PF > 1
+  static_assert(PF == 1 || PF == 2 || PF == 4 || PF == 8, "PF divides the wave");
   __shared__ uint32_t s_begin[kLdsK + 1];
   const int K = t.K;
   for (int j = threadIdx.x; j <= K; j += NT) s_begin[j] = t.begin[j];
   __syncthreads();
-  const SwGrid q = sw_grid(g);
+  SwGrid q = sw_grid(g);
+  // values every lane combines with its own entry: kept in vector registers
+  // (scalar registers limit this kernel's occupancy)
+  asm volatile("" : "+v"(q.gx), "+v"(q.gxy), "+v"(q.nbricks));
   const int lane = lane_id();
   const int64_t wave0 =
       (int64_t)blockIdx.x * NW + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t nwaves = (int64_t)gridDim.x * NW;
-  uint32_t conf = 0, acc = 0, blk = 0, nocand = 0, tests = 0, lookups = 0, deep = 0, chunks = 0;
-  uint32_t cchecks = 0, cclear = 0, sbody = 0, sfar = 0, arm = 0;
+  ScoreCounterBlock &sc = t.counters->s[(blockIdx.x * NW + (threadIdx.x >> 6)) % kStatSlots];
+  // Scalar registers limit this kernel's occupancy, so the per-point label
+  // counts live in a vector register (lane 0 confident, 1 accessible,
+  // 2 blocked, 3 no candidate) and the diagnostics exist only with DIAG.
+  uint32_t labv = 0;
+  uint32_t tests = 0, lookups = 0, arm = 0, deep = 0, chunks = 0;
+  uint32_t cchecks = 0, cclear = 0, sbody = 0, sfar = 0;
   auto flush = [&]() {
-    if (lane == 0) {
-      if (conf) atomicAdd(&t.counters->n_confident, (unsigned long long)conf);
-      if (acc) atomicAdd(&t.counters->n_accessible, (unsigned long long)acc);
-      if (blk) atomicAdd(&t.counters->n_blocked, (unsigned long long)blk);
-      if (nocand) atomicAdd(&t.counters->n_no_candidate, (unsigned long long)nocand);
-      if (tests) atomicAdd(&t.counters->canonical_tests, (unsigned long long)tests);
-      if (lookups) atomicAdd(&t.counters->canonical_lookups, (unsigned long long)lookups);
-      if (deep) atomicAdd(&t.counters->deep_tests, (unsigned long long)deep);
-      if (chunks) atomicAdd(&t.counters->deep_chunks_max, (unsigned long long)chunks);
-      if (cchecks) atomicAdd(&t.counters->coarse_checks, (unsigned long long)cchecks);
-      if (cclear) atomicAdd(&t.counters->coarse_clear, (unsigned long long)cclear);
-      if (sbody) atomicAdd(&t.counters->chunks_body, (unsigned long long)sbody);
-      if (sfar) atomicAdd(&t.counters->chunks_far, (unsigned long long)sfar);
-      if (arm) atomicAdd(&t.counters->arm_lookups, (unsigned long long)arm);
+    if (lane < 4 && labv) {
+      unsigned long long *dst = lane == 0   ? &sc.n_confident
+                                : lane == 1 ? &sc.n_accessible
+                                : lane == 2 ? &sc.n_blocked
+                                            : &sc.n_no_candidate;
+      atomicAdd(dst, (unsigned long long)labv);
     }
-    conf = acc = blk = nocand = tests = lookups = deep = chunks = 0;
-    cchecks = cclear = sbody = sfar = arm = 0;
+    if (lane == 0) {
+      if (tests) atomicAdd(&sc.canonical_tests, (unsigned long long)tests);
+      if (lookups) atomicAdd(&sc.canonical_lookups, (unsigned long long)lookups);
+      if (arm) atomicAdd(&sc.arm_lookups, (unsigned long long)arm);
+      if (DIAG) {
+        if (deep) atomicAdd(&sc.deep_tests, (unsigned long long)deep);
+        if (chunks) atomicAdd(&sc.deep_chunks_max, (unsigned long long)chunks);
+        if (cchecks) atomicAdd(&sc.coarse_checks, (unsigned long long)cchecks);
+        if (cclear) atomicAdd(&sc.coarse_clear, (unsigned long long)cclear);
+        if (sbody) atomicAdd(&sc.chunks_body, (unsigned long long)sbody);
+        if (sfar) atomicAdd(&sc.chunks_far, (unsigned long long)sfar);
+      }
+    }
+    labv = 0;
+    tests = lookups = arm = deep = chunks = 0;
+    cchecks = cclear = sbody = sfar = 0;
   };
   int64_t i = wave0, batch_end = wave0 + 1;
   if (FB > 0) {
@@ -849,13 +936,13 @@ k_score_near(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t m
     if (hn < 0) {
       label = AF_UNSCORED;
     } else {
-      ++conf;
       int32_t s[3];
       unpack_key(pts.key[i], s[0], s[1], s[2]);
-      const SwFrame f = sw_frame(g, q, s);
+      SwFrame f = RE ? rel_frame(g, q, s) : sw_frame(g, q, s);
       uint32_t c4[3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) c4[a] = (uint32_t)((s[a] >> 2) - 2 * g.g0[a]);
+      asm volatile("" : "+v"(f.Bp), "+v"(f.rp), "+v"(c4[0]), "+v"(c4[1]), "+v"(c4[2]));
       label = AF_NO_CANDIDATE;
       // lanes [0, mw): mask words; [mw, 3 mw): the two arm-sample planes
       const uint64_t mine = lane < mw       ? t.mask[i * mw + lane]
@@ -869,44 +956,88 @@ k_score_near(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t m
                                 readlane64(mine, 2 * mw + w) & word, 0ull, 0ull};
         uint64_t open = word & ~(pl[0] | pl[1]);
         uint64_t left = word;
-        for (;;) {
-          if (!open) {   // the rest are blocked by an arm sample
-            tests += (uint32_t)__popcll(left);
-            const uint32_t a = plane_sum(pl, left);
-            lookups += a;
-            arm += a;
-            break;
+        while (open && ff < 0) {
+          // the next PF candidates that need their body and corridor
+          int js[PF];
+          int nb = 0;
+#pragma unroll
+          for (int c = 0; c < PF; ++c) {
+            js[c] = open ? __ffsll((long long)open) - 1 : 0;
+            nb += open != 0ull;
+            open &= open - 1;
           }
-          const int j = __ffsll((long long)open) - 1;
-          open &= open - 1;
-          const uint64_t below = left & ((1ull << j) - 1ull);
-          tests += (uint32_t)__popcll(below) + 1u;
-          const uint32_t a = plane_sum(pl, below);
+          // their first F entries after the arm samples, F lanes each
+          uint64_t nf = 0, bm = 0;
+          if (PF > 1) {
+            const int c = lane / F, off = lane % F;
+            int jc = js[0];
+#pragma unroll
+            for (int cc = 1; cc < PF; ++cc) jc = c == cc ? js[cc] : jc;
+            const int kc = 64 * w + jc;
+            const uint32_t b = s_begin[kc] + E, e = s_begin[kc + 1];
+            const uint32_t idx = b + (uint32_t)off;
+            const bool valid = c < nb && idx < e;
+            const auto ent = load_entry<RE>(t, valid ? idx : (e > 0 ? e - 1 : 0));
+            const uint32_t code = ent_code<B1>(q, f, ent);
+            const uint32_t cls = ent_cls(ent);
+            const bool hit =
+                valid && (B1 || cls != AF_CLS_NEAR ? (code & 1u) != 0u : code != 0u);
+            nf = __ballot(hit && cls != AF_CLS_BODY);
+            bm = __ballot(hit && cls == AF_CLS_BODY);
+          }
+#pragma unroll
+          for (int c = 0; c < PF; ++c) {
+            if (c >= nb) break;
+            const int jj = js[c];
+            const uint64_t below = left & ((1ull << jj) - 1ull);
+            tests += (uint32_t)__popcll(below) + 1u;
+            const uint32_t a = plane_sum(pl, below);
+            lookups += a + E;
+            arm += a + E;
+            left &= ~((2ull << jj) - 1ull);
+            const int kj = 64 * w + jj;
+            const uint32_t b = s_begin[kj] + E, e = s_begin[kj + 1];
+            ++deep;
+            chunks += (e - b + 63) / 64;
+            uint32_t start = b;
+            int body = 0;
+            if (PF > 1) {
+              const uint64_t fm = F >= 64 ? ~0ull : ((1ull << F) - 1ull);
+              const uint64_t nf1 = (nf >> (F * c)) & fm, bm1 = (bm >> (F * c)) & fm;
+              const int stop = chunk_stop(nf1, bm1, p.n_c);
+              if (stop < F) {   // blocked within the prefix
+                lookups += (uint32_t)stop + 1u;
+                continue;
+              }
+              const uint32_t nin = e - b < (uint32_t)F ? e - b : (uint32_t)F;
+              lookups += nin;
+              body = __popcll(bm1);
+              start = b + nin;
+            }
+            if (scan_rest_sw<UN, CO, B1, RE>(p, t, q, f, kj, start, e, body, lookups, cchecks,
+                                             cclear, sbody, sfar, c4, g.occ4)) {
+              ff = (int16_t)kj;
+              break;
+            }
+          }
+        }
+        if (ff < 0) {   // the rest are blocked by an arm sample
+          tests += (uint32_t)__popcll(left);
+          const uint32_t a = plane_sum(pl, left);
           lookups += a;
-          arm += a + E;
-          left &= ~((2ull << j) - 1ull);
-          const int kj = 64 * w + j;
-          const uint32_t b = s_begin[kj], e = s_begin[kj + 1];
-          lookups += E;
-          ++deep;
-          chunks += (e - b - E + 63) / 64;
-          if (scan_rest_sw<UN, CO, B1>(p, t, q, f, kj, b + E, e, 0, lookups, cchecks, cclear,
-                                       sbody, sfar, c4, g.occ4)) {
-            ff = (int16_t)kj;
-            break;
-          }
+          arm += a;
         }
       }
       if (ff >= 0) label = AF_ACCESSIBLE;
-      acc += label == AF_ACCESSIBLE;
-      blk += label == AF_BLOCKED;
-      nocand += label == AF_NO_CANDIDATE;
+      labv += (uint32_t)(lane == 0) | (uint32_t)(lane == 1 && label == AF_ACCESSIBLE) |
+              (uint32_t)(lane == 2 && label == AF_BLOCKED) |
+              (uint32_t)(lane == 3 && label == AF_NO_CANDIDATE);
     }
     if (lane == 0) {
       t.label[i] = label;
       t.first_free[i] = ff;
     }
-    if (lookups > (1u << 30) || chunks > (1u << 30)) flush();
+    if (lookups > (1u << 30)) flush();
     if (FB > 0) {
       if (++i >= batch_end) {
         unsigned got = 0;
@@ -928,6 +1059,7 @@ struct ScoreVariant {
   int threads;
   const char *name;
   int needs_lds_k;   // 1: only for K <= kLdsK
+  int needs_rel;     // 1: only with the 4-byte entry form (offsets within +-255)
 };
 
 // The tunable score configurations (identical results; speed only).
@@ -935,14 +1067,15 @@ const ScoreVariant kVariants[] = {
     {k_score<256, 0, 1, 1, 0, 0>, 256, "plain wg256", 0},
     {k_score<256, 0, 2, 2, 1, 16>, 256, "plain wg256 ahead2 unroll2 occ dyn16", 0},
     {k_score_swar<256, 3, 1, 16, 2, 1>, 256, "swar wg256 head3 unroll1 dyn16 coarse4 bit", 1},
-    {k_score_swar<256, 4, 1, 16, 2, 1>, 256, "swar wg256 head4 unroll1 dyn16 coarse4 bit", 1},
     {k_score_swar<256, 4, 1, 16, 0, 0>, 256, "swar wg256 head4 unroll1 dyn16", 1},
-    {k_score_near<256, 1, 16, 2, 1>, 256, "near wg256 unroll1 dyn16 coarse4 bit", 1},
-    {k_score_near<256, 1, 16, 2, 0>, 256, "near wg256 unroll1 dyn16 coarse4", 1},
-    {k_score_near<256, 1, 16, 0, 1>, 256, "near wg256 unroll1 dyn16 bit", 1},
-    {k_score_near<256, 2, 16, 2, 1>, 256, "near wg256 unroll2 dyn16 coarse4 bit", 1},
-    {k_score_near<256, 1, 8, 2, 1>, 256, "near wg256 unroll1 dyn8 coarse4 bit", 1},
-    {k_score_near<512, 1, 16, 2, 1>, 512, "near wg512 unroll1 dyn16 coarse4 bit", 1},
+    {k_score_near<256, 1, 16, 2, 1, 0>, 256, "near wg256 unroll1 dyn16 coarse4 bit", 1},
+    {k_score_near<256, 1, 16, 0, 1, 0>, 256, "near wg256 unroll1 dyn16 bit", 1},
+    {k_score_near<256, 1, 8, 2, 1, 0, 1, 1>, 256, "near wg256 unroll1 dyn8 coarse4 bit rel", 1, 1},
+    {k_score_near<256, 1, 8, 2, 1, 1, 1, 1>, 256, "near wg256 unroll1 dyn8 coarse4 bit rel diag", 1, 1},
+    {k_score_near<256, 1, 16, 2, 1, 0, 1, 1>, 256, "near wg256 unroll1 dyn16 coarse4 bit rel", 1, 1},
+    {k_score_near<256, 2, 8, 2, 1, 0, 1, 1>, 256, "near wg256 unroll2 dyn8 coarse4 bit rel", 1, 1},
+    {k_score_near<512, 1, 8, 2, 1, 0, 1, 1>, 512, "near wg512 unroll1 dyn8 coarse4 bit rel", 1, 1},
+    {k_score_near<256, 1, 8, 2, 1, 0, 2, 1>, 256, "near wg256 unroll1 dyn8 coarse4 bit prefix2 rel", 1, 1},
 };
 constexpr int kNumVariants = (int)(sizeof(kVariants) / sizeof(kVariants[0]));
 int g_resident[kNumVariants];   // workgroups per CU, from the occupancy query
@@ -994,7 +1127,14 @@ void launch_mask(const Params &p, PointsDev pts, ToolDev t, GridDev g, int64_t n
 
 int score_variants() { return kNumVariants; }
 
-int score_variant_default() { return 5; }   // "near wg256 unroll1 dyn16 coarse4 bit"
+
+// The configuration a new context uses (the fastest on the tree workload).
+int score_variant_default() {
+  static const char kDefault[] = "near wg256 unroll1 dyn8 coarse4 bit rel";
+  for (int v = 0; v < kNumVariants; ++v)
+    if (strcmp(kVariants[v].name, kDefault) == 0) return v;
+  return 0;
+}
 
 const char *score_variant_name(int v) {
   return v >= 0 && v < kNumVariants ? kVariants[v].name : "";
@@ -1006,6 +1146,7 @@ void launch_score(const Params &p, PointsDev pts, ToolDev t, GridDev g, int64_t 
   if (n <= 0) return;
   if (variant < 0 || variant >= kNumVariants) variant = 0;
   if (kVariants[variant].needs_lds_k && t.K > kLdsK) variant = 0;
+  if (kVariants[variant].needs_rel && !t.rent) variant = 0;
   const ScoreVariant &v = kVariants[variant];
   if (g_num_cu == 0) {
     int dev = 0;
