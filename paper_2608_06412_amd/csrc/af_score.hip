@@ -882,10 +882,7 @@ k_score_near(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t m
   const int K = t.K;
   for (int j = threadIdx.x; j <= K; j += NT) s_begin[j] = t.begin[j];
   __syncthreads();
-  SwGrid q = sw_grid(g);
-  // values every lane combines with its own entry: kept in vector registers
-  // (scalar registers limit this kernel's occupancy)
-  asm volatile("" : "+v"(q.gx), "+v"(q.gxy), "+v"(q.nbricks));
+  const SwGrid q = sw_grid(g);
   const int lane = lane_id();
   const int64_t wave0 =
       (int64_t)blockIdx.x * NW + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -942,6 +939,8 @@ k_score_near(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t m
       uint32_t c4[3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) c4[a] = (uint32_t)((s[a] >> 2) - 2 * g.g0[a]);
+      // values every lane combines with its own entry: kept in vector
+      // registers (scalar registers limit this kernel's occupancy)
       asm volatile("" : "+v"(f.Bp), "+v"(f.rp), "+v"(c4[0]), "+v"(c4[1]), "+v"(c4[2]));
       label = AF_NO_CANDIDATE;
       // lanes [0, mw): mask words; [mw, 3 mw): the two arm-sample planes
