@@ -270,9 +270,15 @@ __device__ inline uint32_t ent_code(const SwGrid &q, const SwFrame &f, uint32_t 
 // For every candidate direction the lane also reads the direction's three
 // arm samples (Section 3.4 "Arm path checking"; they depend on the approach
 // direction only, so orientations that share it share the result) and
-// records which one hits first, as two bit planes per mask word.
+// records which one hits first, as two bit planes per mask word.  With
+// dynamic LDS (mw <= kMaskStageMw) the workgroup's words are staged there and
+// written out contiguously (a lane's own words are 8 bytes at a 96-byte
+// stride, which the memory system would write back as partial lines).
+constexpr int kMaskStageMw = 8;
+
 __global__ void __launch_bounds__(kThreads)
-k_mask(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t mw) {
+k_mask(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t mw, int stage) {
+  extern __shared__ uint64_t s_out[];   // [kThreads * mw] mask, then [kThreads * 2 mw] planes
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const bool act = i < n;
   const int hn = act ? pts.has_normal[i] : -1;
@@ -359,12 +365,24 @@ k_mask(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t mw) {
       pl0 |= (uint64_t)(nb & 1u) << j;
       pl1 |= (uint64_t)(nb >> 1) << j;
     }
-    if (act) {
+    if (stage) {
+      s_out[threadIdx.x * mw + w] = word;
+      s_out[kThreads * mw + threadIdx.x * 2 * mw + w] = pl0;
+      s_out[kThreads * mw + threadIdx.x * 2 * mw + mw + w] = pl1;
+    } else if (act) {
       t.mask[i * mw + w] = word;
       t.nearp[i * 2 * mw + w] = pl0;
       t.nearp[i * 2 * mw + mw + w] = pl1;
     }
     cand += (unsigned long long)__popcll(word);
+  }
+  if (stage) {
+    __syncthreads();
+    const int64_t i0 = (int64_t)blockIdx.x * kThreads;
+    const int64_t np = n - i0 < kThreads ? n - i0 : kThreads;
+    for (int64_t k = threadIdx.x; k < np * mw; k += kThreads) t.mask[i0 * mw + k] = s_out[k];
+    for (int64_t k = threadIdx.x; k < np * 2 * mw; k += kThreads)
+      t.nearp[i0 * 2 * mw + k] = s_out[kThreads * mw + k];
   }
   for (int off = 32; off >= 1; off >>= 1) {
     unsigned lo = __shfl_xor((unsigned)(cand & 0xffffffffu), off);
@@ -1120,8 +1138,10 @@ void launch_mask(const Params &p, PointsDev pts, ToolDev t, GridDev g, int64_t n
                  hipStream_t s) {
   int32_t mw = (t.K + 63) / 64;
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_mask, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0,
-                     s, p, pts, t, g, n, mw);
+  const int stage = mw <= kMaskStageMw ? 1 : 0;
+  const size_t lds = stage ? sizeof(uint64_t) * kThreads * 3 * mw : 0;
+  hipLaunchKernelGGL(k_mask, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads),
+                     lds, s, p, pts, t, g, n, mw, stage);
 }
 
 int score_variants() { return kNumVariants; }
