@@ -229,6 +229,17 @@ int af_timing_enable(af_ctx *ctx, int on);
 /* Synchronises the pending events, fills *out, and zeroes the sums if reset. */
 int af_timing_read(af_ctx *ctx, af_timing *out, int reset);
 
+/* Score every point against several tools (1..8, each with K <= 1024 and at
+ * most 8200 orientations in total) in one persistent scoring launch: the
+ * batching form of af_score_points (Section 3.4's tool kernels, one set per
+ * tool).  Labels, first free orientations and statistics of each tool are
+ * those af_score_points gives for it.  The first call for a tool gives it
+ * its own candidate-mask buffers (3 K/8 bytes per point capacity), so the
+ * tools' masks coexist.  Asynchronous on `stream`.  AF_EINVAL for a bad or
+ * repeated id or too many orientations, AF_ENOTOOL for a tool without
+ * kernels. */
+int af_score_tools(af_ctx *ctx, const int32_t *tool_ids, int32_t n_tools, void *stream);
+
 /* Scoring kernel configurations: "plain" (one orientation at a time, any K),
  * "swar" (candidate-parallel first entries, grid-relative lookups) and "near"
  * (arm samples taken from the mask pass), with unrolling, dynamic point

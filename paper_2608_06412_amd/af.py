@@ -105,6 +105,7 @@ SIGNATURES = {
     "af_timing_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "af_timing_read": (ctypes.c_int, [_vp, ctypes.POINTER(Timing), ctypes.c_int]),
     "af_score_variant_count": (ctypes.c_int, []),
+    "af_score_tools": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "af_score_variant_default": (ctypes.c_int, []),
     "af_score_variant_name": (ctypes.c_char_p, [_i32]),
     "af_set_score_variant": (ctypes.c_int, [_vp, _i32]),
@@ -320,6 +321,11 @@ class Context:
 
     def score_variant(self) -> int:
         return self._lib.af_get_score_variant(self.h)
+
+    def score_tools(self, tool_ids, stream=None):
+        """Score every point against several tools in one launch."""
+        ids = (ctypes.c_int32 * len(tool_ids))(*[int(x) for x in tool_ids])
+        self._check(self._lib.af_score_tools(self.h, ids, len(tool_ids), _stream_handle(stream)))
 
     def score_variant_default(self) -> int:
         return self._lib.af_score_variant_default()

@@ -32,6 +32,8 @@ struct af_ctx {
   std::vector<int64_t> tool_bytes;
   uint64_t *mask;               // shared candidate-mask scratch
   uint64_t *nearp;              // shared arm-sample planes
+  ToolDev *tools_dev;           // device mirror of `tools` (for the multi-tool launch)
+  std::vector<char> own_mask;   // tool has its own mask and plane buffers
   unsigned *work;               // point counter of the dynamic score variants
   int score_variant;
   int64_t last_frame;
@@ -392,6 +394,8 @@ int af_create(const af_config *cfg, af_ctx **out) {
   c->score_variant = score_variant_default();
   CREATE_ALLOC(c->mask, NP * ((cfg->max_orientations + 63) / 64));
   CREATE_ALLOC(c->nearp, NP * 2 * ((cfg->max_orientations + 63) / 64));
+  CREATE_ALLOC(c->tools_dev, cfg->max_tools);
+  c->own_mask.assign(cfg->max_tools, 0);
   c->tools.assign(cfg->max_tools, ToolDev());
   c->tool_bytes.assign(cfg->max_tools, 0);
   for (auto &t : c->tools) memset(&t, 0, sizeof(t));
@@ -477,6 +481,12 @@ int af_set_tool_kernels(af_ctx *c, int32_t tool_id, const af_tool *tool, int32_t
     dev_free(c, t.same, sizeof(uint64_t) * ((t.K + 63) / 64));
     dev_free(c, t.xent, sizeof(uint2) * std::max<int64_t>(1, t.n_entries));
     if (t.rent) dev_free(c, t.rent, sizeof(uint32_t) * std::max<int64_t>(1, t.n_entries));
+    if (c->own_mask[tool_id]) {
+      const int64_t mw = (t.K + 63) / 64;
+      dev_free(c, t.mask, sizeof(uint64_t) * c->cfg.max_points * mw);
+      dev_free(c, t.nearp, sizeof(uint64_t) * c->cfg.max_points * 2 * mw);
+      c->own_mask[tool_id] = 0;
+    }
     dev_free(c, t.c4begin, sizeof(uint32_t) * (t.K + 1));
     dev_free(c, t.c4flag, t.K);
     dev_free(c, t.c4entries, sizeof(uint32_t) * std::max<int64_t>(1, t.n_c4entries));
@@ -576,6 +586,7 @@ int af_set_tool_kernels(af_ctx *c, int32_t tool_id, const af_tool *tool, int32_t
   c->tool_bytes[tool_id] = sizeof(uint32_t) * (int64_t)total;
   c->last_stream = s;
   if (c->grid_bricks > 0 && launch_table_grid(t, c->grid, s) != 0) return hip_check(c, "table grid");
+  HIP_TRY(c, hipMemcpy(&c->tools_dev[tool_id], &t, sizeof(ToolDev), hipMemcpyHostToDevice));
   return regrid(c, s);
 }
 
@@ -674,6 +685,68 @@ int af_score_points(af_ctx *c, int32_t tool_id, void *stream) {
   }
   c->last_stream = s;
   return hip_check(c, "score");
+}
+
+int af_score_tools(af_ctx *c, const int32_t *tool_ids, int32_t n_tools, void *stream) {
+  if (!c) return AF_EINVAL;
+  if (!tool_ids || n_tools < 1 || n_tools > kMultiTools)
+    return fail(c, AF_EINVAL, "n_tools must be 1..%d", kMultiTools);
+  ToolSet set;
+  memset(&set, 0, sizeof(set));
+  set.n = n_tools;
+  int32_t words = 0;
+  for (int32_t i = 0; i < n_tools; ++i) {
+    const int32_t id = tool_ids[i];
+    if (id < 0 || id >= c->cfg.max_tools) return fail(c, AF_EINVAL, "bad tool id %d", id);
+    if (!c->tools[id].entries) return fail(c, AF_ENOTOOL, "tool %d has no kernels", id);
+    for (int32_t j = 0; j < i; ++j)
+      if (tool_ids[j] == id) return fail(c, AF_EINVAL, "tool %d listed twice", id);
+    if (c->tools[id].K > 1024) return fail(c, AF_EINVAL, "tool %d: K above 1024", id);
+    set.id[i] = id;
+    set.base[i] = words;
+    words += c->tools[id].K + 1;
+  }
+  if (words > multi_begin_capacity())
+    return fail(c, AF_EINVAL, "%d orientations exceed one launch", words - n_tools);
+  hipStream_t s = (hipStream_t)stream;
+  int rc = regrid(c, s);
+  if (rc != AF_OK) return rc;
+  ToolDev host[kMultiTools];
+  for (int32_t i = 0; i < n_tools; ++i) {
+    const int32_t id = set.id[i];
+    ToolDev &t = c->tools[id];
+    if (!c->own_mask[id]) {   // masks of every tool must coexist
+      const int64_t mw = (t.K + 63) / 64;
+      uint64_t *mk = nullptr, *np = nullptr;
+      ALLOC(c, mk, c->cfg.max_points * mw);
+      ALLOC(c, np, c->cfg.max_points * 2 * mw);
+      t.mask = mk;
+      t.nearp = np;
+      c->own_mask[id] = 1;
+      HIP_TRY(c, hipMemcpy(&c->tools_dev[id], &t, sizeof(ToolDev), hipMemcpyHostToDevice));
+    }
+    host[i] = t;
+  }
+  hipEvent_t t0 = timing_mark(c, s);
+  for (int32_t i = 0; i < n_tools; ++i)
+    HIP_TRY(c, hipMemsetAsync(host[i].counters, 0, sizeof(ScoreCounters), s));
+  hipEvent_t t1 = timing_mark(c, s);
+  launch_normals(c->p, c->map, c->pts, c->grid, c->n_points, s);
+  hipEvent_t t2 = timing_mark(c, s);
+  for (int32_t i = 0; i < n_tools; ++i)
+    launch_mask(c->p, c->pts, host[i], c->grid, c->n_points, s);
+  hipEvent_t t3 = timing_mark(c, s);
+  launch_score_multi(c->p, c->pts, c->tools_dev, host, set, c->grid, c->n_points, c->work, s);
+  hipEvent_t t4 = timing_mark(c, s);
+  if (c->timing) {
+    timing_pair(c, ST_SCORE, t0, t4);
+    timing_pair(c, ST_K_NORMALS, t1, t2);
+    timing_pair(c, ST_K_MASK, t2, t3);
+    timing_pair(c, ST_K_SCORE, t3, t4);
+    c->score_calls += 1;
+  }
+  c->last_stream = s;
+  return hip_check(c, "score tools");
 }
 
 int af_score_variant_count(void) { return score_variants(); }

@@ -251,6 +251,19 @@ void launch_normals(const Params &p, MapDev m, PointsDev pts, GridDev g,
                     int64_t n_points, hipStream_t s);
 void launch_mask(const Params &p, PointsDev pts, ToolDev t, GridDev g, int64_t n_points,
                  hipStream_t s);
+// Up to kMultiTools tools scored in one launch: their ids in the context's
+// device mirror of the tool table and the offsets of their begin arrays in
+// the launch's LDS copy (passed by value).
+constexpr int kMultiTools = 8;
+struct ToolSet {
+  int32_t n;
+  int32_t id[kMultiTools];
+  int32_t base[kMultiTools];
+};
+int multi_begin_capacity();
+void launch_score_multi(const Params &p, PointsDev pts, const ToolDev *tools_dev,
+                        const ToolDev *host_tools, const ToolSet &set, GridDev g, int64_t n,
+                        unsigned *work, hipStream_t s);
 void launch_score(const Params &p, PointsDev pts, ToolDev t, GridDev g, int64_t n_points,
                   int variant, unsigned *work, hipStream_t s);
 int score_variants();

@@ -402,7 +402,8 @@ __device__ inline int nth_bit(uint64_t m, int r) {
   return __ffsll((long long)m) - 1;
 }
 
-constexpr int kLdsK = 256;   // orientations whose table heads are staged in LDS
+constexpr int kLdsK = 256;    // orientations whose table heads the "swar" kernels stage in LDS
+constexpr int kNearK = 1024;  // orientations whose table offsets the "near" kernels stage in LDS
 
 // Hit test of one table entry at point s: arm samples (NEAR) hit on TSDF < r_c
 // or unknown-and-not-cleared; body and corridor entries hit on TSDF < r_c
@@ -880,23 +881,173 @@ __device__ inline uint64_t readlane64(uint64_t v, int l) {
          (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
 }
 
+// Accumulated per-wave counts of the "near" kernels (flushed to a counter
+// block; see near_flush).
+struct NearAcc {
+  uint32_t labv;   // per lane: lane 0 confident, 1 accessible, 2 blocked, 3 no candidate
+  uint32_t tests, lookups, arm, deep, chunks, cchecks, cclear, sbody, sfar;
+};
+
+template <int DIAG>
+__device__ inline void near_flush(ScoreCounterBlock &sc, NearAcc &a, int lane) {
+  if (lane < 4 && a.labv) {
+    unsigned long long *dst = lane == 0   ? &sc.n_confident
+                              : lane == 1 ? &sc.n_accessible
+                              : lane == 2 ? &sc.n_blocked
+                                          : &sc.n_no_candidate;
+    atomicAdd(dst, (unsigned long long)a.labv);
+  }
+  if (lane == 0) {
+    if (a.tests) atomicAdd(&sc.canonical_tests, (unsigned long long)a.tests);
+    if (a.lookups) atomicAdd(&sc.canonical_lookups, (unsigned long long)a.lookups);
+    if (a.arm) atomicAdd(&sc.arm_lookups, (unsigned long long)a.arm);
+    if (DIAG) {
+      if (a.deep) atomicAdd(&sc.deep_tests, (unsigned long long)a.deep);
+      if (a.chunks) atomicAdd(&sc.deep_chunks_max, (unsigned long long)a.chunks);
+      if (a.cchecks) atomicAdd(&sc.coarse_checks, (unsigned long long)a.cchecks);
+      if (a.cclear) atomicAdd(&sc.coarse_clear, (unsigned long long)a.cclear);
+      if (a.sbody) atomicAdd(&sc.chunks_body, (unsigned long long)a.sbody);
+      if (a.sfar) atomicAdd(&sc.chunks_far, (unsigned long long)a.sfar);
+    }
+  }
+  a = NearAcc{0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+}
+
+// One point of the "near" scoring (see k_score_near): label and first free
+// orientation of point i for tool t, whose begin offsets are s_begin.
+template <int UN, int CO, int B1, int PF, int RE>
+__device__ inline void near_point(const Params &p, const PointsDev &pts, const ToolDev &t,
+                                  const GridDev &g, const SwGrid &q, const uint32_t *s_begin,
+                                  int32_t mw, int64_t i, int lane, NearAcc &acc) {
+  constexpr uint32_t E = 3;   // the arm samples
+  constexpr int F = 64 / PF;  // prefix entries per candidate when PF > 1
+  static_assert(PF == 1 || PF == 2 || PF == 4 || PF == 8, "PF divides the wave");
+  const int hn = __builtin_amdgcn_readfirstlane(pts.has_normal[i]);
+  uint8_t label;
+  int16_t ff = -1;
+  if (hn < 0) {
+    label = AF_UNSCORED;
+  } else {
+    int32_t s[3];
+    unpack_key(pts.key[i], s[0], s[1], s[2]);
+    SwFrame f = RE ? rel_frame(g, q, s) : sw_frame(g, q, s);
+    uint32_t c4[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) c4[a] = (uint32_t)((s[a] >> 2) - 2 * g.g0[a]);
+    // values every lane combines with its own entry: kept in vector
+    // registers (scalar registers limit this kernel's occupancy)
+    asm volatile("" : "+v"(f.Bp), "+v"(f.rp), "+v"(c4[0]), "+v"(c4[1]), "+v"(c4[2]));
+    label = AF_NO_CANDIDATE;
+    // lanes [0, mw): mask words; [mw, 3 mw): the two arm-sample planes
+    const uint64_t mine = lane < mw       ? t.mask[i * mw + lane]
+                          : lane < 3 * mw ? t.nearp[i * 2 * mw + (lane - mw)]
+                                          : 0ull;
+    for (int w = 0; w < mw && ff < 0; ++w) {
+      const uint64_t word = readlane64(mine, w);
+      if (!word) continue;
+      label = AF_BLOCKED;
+      const uint64_t pl[4] = {readlane64(mine, mw + w) & word,
+                              readlane64(mine, 2 * mw + w) & word, 0ull, 0ull};
+      uint64_t open = word & ~(pl[0] | pl[1]);
+      uint64_t left = word;
+      while (open && ff < 0) {
+        // the next PF candidates that need their body and corridor
+        int js[PF];
+        int nb = 0;
+#pragma unroll
+        for (int c = 0; c < PF; ++c) {
+          js[c] = open ? __ffsll((long long)open) - 1 : 0;
+          nb += open != 0ull;
+          open &= open - 1;
+        }
+        // their first F entries after the arm samples, F lanes each
+        uint64_t nf = 0, bm = 0;
+        if (PF > 1) {
+          const int c = lane / F, off = lane % F;
+          int jc = js[0];
+#pragma unroll
+          for (int cc = 1; cc < PF; ++cc) jc = c == cc ? js[cc] : jc;
+          const int kc = 64 * w + jc;
+          const uint32_t b = s_begin[kc] + E, e = s_begin[kc + 1];
+          const uint32_t idx = b + (uint32_t)off;
+          const bool valid = c < nb && idx < e;
+          const auto ent = load_entry<RE>(t, valid ? idx : (e > 0 ? e - 1 : 0));
+          const uint32_t code = ent_code<B1>(q, f, ent);
+          const uint32_t cls = ent_cls(ent);
+          const bool hit =
+              valid && (B1 || cls != AF_CLS_NEAR ? (code & 1u) != 0u : code != 0u);
+          nf = __ballot(hit && cls != AF_CLS_BODY);
+          bm = __ballot(hit && cls == AF_CLS_BODY);
+        }
+#pragma unroll
+        for (int c = 0; c < PF; ++c) {
+          if (c >= nb) break;
+          const int jj = js[c];
+          const uint64_t below = left & ((1ull << jj) - 1ull);
+          acc.tests += (uint32_t)__popcll(below) + 1u;
+          const uint32_t a = plane_sum(pl, below);
+          acc.lookups += a + E;
+          acc.arm += a + E;
+          left &= ~((2ull << jj) - 1ull);
+          const int kj = 64 * w + jj;
+          const uint32_t b = s_begin[kj] + E, e = s_begin[kj + 1];
+          ++acc.deep;
+          acc.chunks += (e - b + 63) / 64;
+          uint32_t start = b;
+          int body = 0;
+          if (PF > 1) {
+            const uint64_t fm = F >= 64 ? ~0ull : ((1ull << F) - 1ull);
+            const uint64_t nf1 = (nf >> (F * c)) & fm, bm1 = (bm >> (F * c)) & fm;
+            const int stop = chunk_stop(nf1, bm1, p.n_c);
+            if (stop < F) {   // blocked within the prefix
+              acc.lookups += (uint32_t)stop + 1u;
+              continue;
+            }
+            const uint32_t nin = e - b < (uint32_t)F ? e - b : (uint32_t)F;
+            acc.lookups += nin;
+            body = __popcll(bm1);
+            start = b + nin;
+          }
+          if (scan_rest_sw<UN, CO, B1, RE>(p, t, q, f, kj, start, e, body, acc.lookups, acc.cchecks,
+                                           acc.cclear, acc.sbody, acc.sfar, c4, g.occ4)) {
+            ff = (int16_t)kj;
+            break;
+          }
+        }
+      }
+      if (ff < 0) {   // the rest are blocked by an arm sample
+        acc.tests += (uint32_t)__popcll(left);
+        const uint32_t a = plane_sum(pl, left);
+        acc.lookups += a;
+        acc.arm += a;
+      }
+    }
+    if (ff >= 0) label = AF_ACCESSIBLE;
+    acc.labv += (uint32_t)(lane == 0) | (uint32_t)(lane == 1 && label == AF_ACCESSIBLE) |
+            (uint32_t)(lane == 2 && label == AF_BLOCKED) |
+            (uint32_t)(lane == 3 && label == AF_NO_CANDIDATE);
+  }
+  if (lane == 0) {
+    t.label[i] = label;
+    t.first_free[i] = ff;
+  }
+}
+
 // Scoring with the arm samples already evaluated by k_mask (the
 // configurations named "near"): a candidate whose arm sample q hits first is
 // blocked after q + 1 lookups, summed for the whole wave from the two planes;
 // only the others are visited, scanning body and corridor from their fourth
 // entry.  With PF > 1 the next PF such candidates first get their first
 // 64/PF entries in one step (64/PF lanes each): most are blocked there, and
-// only the undecided ones continue lane-parallel.  Requires K <= kLdsK.  Same labels, first free orientations and
-// canonical counts as the plain scan.
+// only the undecided ones continue lane-parallel.  Requires K <= kNearK.
+// Same labels, first free orientations and canonical counts as the plain
+// scan.
 template <int NT, int UN, int FB, int CO, int B1, int DIAG, int PF = 1, int RE = 0>
 __global__ void __launch_bounds__(NT)
 k_score_near(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t mw,
              unsigned *work) {
   constexpr int NW = NT / 64;
-  constexpr uint32_t E = 3;   // the arm samples
-  constexpr int F = 64 / PF;  // prefix entries per candidate when PF > 1
-  static_assert(PF == 1 || PF == 2 || PF == 4 || PF == 8, "PF divides the wave");
-  __shared__ uint32_t s_begin[kLdsK + 1];
+  __shared__ uint32_t s_begin[kNearK + 1];
   const int K = t.K;
   for (int j = threadIdx.x; j <= K; j += NT) s_begin[j] = t.begin[j];
   __syncthreads();
@@ -906,37 +1057,7 @@ k_score_near(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t m
       (int64_t)blockIdx.x * NW + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t nwaves = (int64_t)gridDim.x * NW;
   ScoreCounterBlock &sc = t.counters->s[(blockIdx.x * NW + (threadIdx.x >> 6)) % kStatSlots];
-  // Scalar registers limit this kernel's occupancy, so the per-point label
-  // counts live in a vector register (lane 0 confident, 1 accessible,
-  // 2 blocked, 3 no candidate) and the diagnostics exist only with DIAG.
-  uint32_t labv = 0;
-  uint32_t tests = 0, lookups = 0, arm = 0, deep = 0, chunks = 0;
-  uint32_t cchecks = 0, cclear = 0, sbody = 0, sfar = 0;
-  auto flush = [&]() {
-    if (lane < 4 && labv) {
-      unsigned long long *dst = lane == 0   ? &sc.n_confident
-                                : lane == 1 ? &sc.n_accessible
-                                : lane == 2 ? &sc.n_blocked
-                                            : &sc.n_no_candidate;
-      atomicAdd(dst, (unsigned long long)labv);
-    }
-    if (lane == 0) {
-      if (tests) atomicAdd(&sc.canonical_tests, (unsigned long long)tests);
-      if (lookups) atomicAdd(&sc.canonical_lookups, (unsigned long long)lookups);
-      if (arm) atomicAdd(&sc.arm_lookups, (unsigned long long)arm);
-      if (DIAG) {
-        if (deep) atomicAdd(&sc.deep_tests, (unsigned long long)deep);
-        if (chunks) atomicAdd(&sc.deep_chunks_max, (unsigned long long)chunks);
-        if (cchecks) atomicAdd(&sc.coarse_checks, (unsigned long long)cchecks);
-        if (cclear) atomicAdd(&sc.coarse_clear, (unsigned long long)cclear);
-        if (sbody) atomicAdd(&sc.chunks_body, (unsigned long long)sbody);
-        if (sfar) atomicAdd(&sc.chunks_far, (unsigned long long)sfar);
-      }
-    }
-    labv = 0;
-    tests = lookups = arm = deep = chunks = 0;
-    cchecks = cclear = sbody = sfar = 0;
-  };
+  NearAcc a{0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
   int64_t i = wave0, batch_end = wave0 + 1;
   if (FB > 0) {
     unsigned got = 0;
@@ -945,116 +1066,8 @@ k_score_near(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t m
     batch_end = i + FB;
   }
   for (; i < n;) {
-    const int hn = __builtin_amdgcn_readfirstlane(pts.has_normal[i]);
-    uint8_t label;
-    int16_t ff = -1;
-    if (hn < 0) {
-      label = AF_UNSCORED;
-    } else {
-      int32_t s[3];
-      unpack_key(pts.key[i], s[0], s[1], s[2]);
-      SwFrame f = RE ? rel_frame(g, q, s) : sw_frame(g, q, s);
-      uint32_t c4[3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) c4[a] = (uint32_t)((s[a] >> 2) - 2 * g.g0[a]);
-      // values every lane combines with its own entry: kept in vector
-      // registers (scalar registers limit this kernel's occupancy)
-      asm volatile("" : "+v"(f.Bp), "+v"(f.rp), "+v"(c4[0]), "+v"(c4[1]), "+v"(c4[2]));
-      label = AF_NO_CANDIDATE;
-      // lanes [0, mw): mask words; [mw, 3 mw): the two arm-sample planes
-      const uint64_t mine = lane < mw       ? t.mask[i * mw + lane]
-                            : lane < 3 * mw ? t.nearp[i * 2 * mw + (lane - mw)]
-                                            : 0ull;
-      for (int w = 0; w < mw && ff < 0; ++w) {
-        const uint64_t word = readlane64(mine, w);
-        if (!word) continue;
-        label = AF_BLOCKED;
-        const uint64_t pl[4] = {readlane64(mine, mw + w) & word,
-                                readlane64(mine, 2 * mw + w) & word, 0ull, 0ull};
-        uint64_t open = word & ~(pl[0] | pl[1]);
-        uint64_t left = word;
-        while (open && ff < 0) {
-          // the next PF candidates that need their body and corridor
-          int js[PF];
-          int nb = 0;
-#pragma unroll
-          for (int c = 0; c < PF; ++c) {
-            js[c] = open ? __ffsll((long long)open) - 1 : 0;
-            nb += open != 0ull;
-            open &= open - 1;
-          }
-          // their first F entries after the arm samples, F lanes each
-          uint64_t nf = 0, bm = 0;
-          if (PF > 1) {
-            const int c = lane / F, off = lane % F;
-            int jc = js[0];
-#pragma unroll
-            for (int cc = 1; cc < PF; ++cc) jc = c == cc ? js[cc] : jc;
-            const int kc = 64 * w + jc;
-            const uint32_t b = s_begin[kc] + E, e = s_begin[kc + 1];
-            const uint32_t idx = b + (uint32_t)off;
-            const bool valid = c < nb && idx < e;
-            const auto ent = load_entry<RE>(t, valid ? idx : (e > 0 ? e - 1 : 0));
-            const uint32_t code = ent_code<B1>(q, f, ent);
-            const uint32_t cls = ent_cls(ent);
-            const bool hit =
-                valid && (B1 || cls != AF_CLS_NEAR ? (code & 1u) != 0u : code != 0u);
-            nf = __ballot(hit && cls != AF_CLS_BODY);
-            bm = __ballot(hit && cls == AF_CLS_BODY);
-          }
-#pragma unroll
-          for (int c = 0; c < PF; ++c) {
-            if (c >= nb) break;
-            const int jj = js[c];
-            const uint64_t below = left & ((1ull << jj) - 1ull);
-            tests += (uint32_t)__popcll(below) + 1u;
-            const uint32_t a = plane_sum(pl, below);
-            lookups += a + E;
-            arm += a + E;
-            left &= ~((2ull << jj) - 1ull);
-            const int kj = 64 * w + jj;
-            const uint32_t b = s_begin[kj] + E, e = s_begin[kj + 1];
-            ++deep;
-            chunks += (e - b + 63) / 64;
-            uint32_t start = b;
-            int body = 0;
-            if (PF > 1) {
-              const uint64_t fm = F >= 64 ? ~0ull : ((1ull << F) - 1ull);
-              const uint64_t nf1 = (nf >> (F * c)) & fm, bm1 = (bm >> (F * c)) & fm;
-              const int stop = chunk_stop(nf1, bm1, p.n_c);
-              if (stop < F) {   // blocked within the prefix
-                lookups += (uint32_t)stop + 1u;
-                continue;
-              }
-              const uint32_t nin = e - b < (uint32_t)F ? e - b : (uint32_t)F;
-              lookups += nin;
-              body = __popcll(bm1);
-              start = b + nin;
-            }
-            if (scan_rest_sw<UN, CO, B1, RE>(p, t, q, f, kj, start, e, body, lookups, cchecks,
-                                             cclear, sbody, sfar, c4, g.occ4)) {
-              ff = (int16_t)kj;
-              break;
-            }
-          }
-        }
-        if (ff < 0) {   // the rest are blocked by an arm sample
-          tests += (uint32_t)__popcll(left);
-          const uint32_t a = plane_sum(pl, left);
-          lookups += a;
-          arm += a;
-        }
-      }
-      if (ff >= 0) label = AF_ACCESSIBLE;
-      labv += (uint32_t)(lane == 0) | (uint32_t)(lane == 1 && label == AF_ACCESSIBLE) |
-              (uint32_t)(lane == 2 && label == AF_BLOCKED) |
-              (uint32_t)(lane == 3 && label == AF_NO_CANDIDATE);
-    }
-    if (lane == 0) {
-      t.label[i] = label;
-      t.first_free[i] = ff;
-    }
-    if (lookups > (1u << 30)) flush();
+    near_point<UN, CO, B1, PF, RE>(p, pts, t, g, q, s_begin, mw, i, lane, a);
+    if (a.lookups > (1u << 30)) near_flush<DIAG>(sc, a, lane);
     if (FB > 0) {
       if (++i >= batch_end) {
         unsigned got = 0;
@@ -1066,7 +1079,57 @@ k_score_near(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t m
       i += nwaves;
     }
   }
-  flush();
+  near_flush<DIAG>(sc, a, lane);
+}
+
+// Several tools in one persistent launch: work item j is point j mod n of
+// tool set.id[j / n] (tool-major, so a tool's table stays cached while the
+// waves go through its points).  Every tool's begin offsets are staged in
+// LDS (at set.base[ti]); each tool keeps its own masks, labels and counters.
+// Same results as one k_score_near launch per tool.
+constexpr int kMultiBegin = 8 * (kNearK + 1);
+
+template <int NT, int UN, int FB, int CO, int B1, int PF, int RE>
+__global__ void __launch_bounds__(NT)
+k_score_near_multi(Params p, PointsDev pts, const ToolDev *tools, ToolSet set, GridDev g,
+                   int64_t n, unsigned *work) {
+  constexpr int NW = NT / 64;
+  extern __shared__ uint32_t s_begin[];   // sized for the set at launch
+  for (int ti = 0; ti < set.n; ++ti) {
+    const uint32_t *bg = tools[set.id[ti]].begin;
+    const int K = tools[set.id[ti]].K, o = set.base[ti];
+    for (int j = threadIdx.x; j <= K; j += NT) s_begin[o + j] = bg[j];
+  }
+  __syncthreads();
+  const SwGrid q = sw_grid(g);
+  const int lane = lane_id();
+  const int slot = (blockIdx.x * NW + (threadIdx.x >> 6)) % kStatSlots;
+  NearAcc a{0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+  const int64_t total = n * set.n;
+  int64_t j = 0, batch_end = 0;
+  int cur = -1;
+  ToolDev t;
+  int32_t mw = 0;
+  for (;;) {
+    if (j >= batch_end) {
+      unsigned got = 0;
+      if (lane == 0) got = atomicAdd(work, (unsigned)FB);
+      j = (int64_t)__builtin_amdgcn_readfirstlane(__shfl(got, 0));
+      batch_end = j + FB;
+    }
+    if (j >= total) break;
+    const int ti = (int)(j / n);
+    if (ti != cur) {
+      if (cur >= 0) near_flush<0>(t.counters->s[slot], a, lane);
+      cur = ti;
+      t = tools[set.id[ti]];
+      mw = (t.K + 63) / 64;
+    }
+    near_point<UN, CO, B1, PF, RE>(p, pts, t, g, q, s_begin + set.base[ti], mw,
+                                   j - (int64_t)ti * n, lane, a);
+    ++j;
+  }
+  if (cur >= 0) near_flush<0>(t.counters->s[slot], a, lane);
 }
 
 using ScoreKernel = void (*)(Params, PointsDev, ToolDev, GridDev, int64_t, int32_t, unsigned *);
@@ -1075,7 +1138,7 @@ struct ScoreVariant {
   ScoreKernel fn;
   int threads;
   const char *name;
-  int needs_lds_k;   // 1: only for K <= kLdsK
+  int max_k;         // largest K the configuration handles (0: any)
   int needs_rel;     // 1: only with the 4-byte entry form (offsets within +-255)
 };
 
@@ -1083,16 +1146,16 @@ struct ScoreVariant {
 const ScoreVariant kVariants[] = {
     {k_score<256, 0, 1, 1, 0, 0>, 256, "plain wg256", 0},
     {k_score<256, 0, 2, 2, 1, 16>, 256, "plain wg256 ahead2 unroll2 occ dyn16", 0},
-    {k_score_swar<256, 3, 1, 16, 2, 1>, 256, "swar wg256 head3 unroll1 dyn16 coarse4 bit", 1},
-    {k_score_swar<256, 4, 1, 16, 0, 0>, 256, "swar wg256 head4 unroll1 dyn16", 1},
-    {k_score_near<256, 1, 16, 2, 1, 0>, 256, "near wg256 unroll1 dyn16 coarse4 bit", 1},
-    {k_score_near<256, 1, 16, 0, 1, 0>, 256, "near wg256 unroll1 dyn16 bit", 1},
-    {k_score_near<256, 1, 8, 2, 1, 0, 1, 1>, 256, "near wg256 unroll1 dyn8 coarse4 bit rel", 1, 1},
-    {k_score_near<256, 1, 8, 2, 1, 1, 1, 1>, 256, "near wg256 unroll1 dyn8 coarse4 bit rel diag", 1, 1},
-    {k_score_near<256, 1, 16, 2, 1, 0, 1, 1>, 256, "near wg256 unroll1 dyn16 coarse4 bit rel", 1, 1},
-    {k_score_near<256, 2, 8, 2, 1, 0, 1, 1>, 256, "near wg256 unroll2 dyn8 coarse4 bit rel", 1, 1},
-    {k_score_near<512, 1, 8, 2, 1, 0, 1, 1>, 512, "near wg512 unroll1 dyn8 coarse4 bit rel", 1, 1},
-    {k_score_near<256, 1, 8, 2, 1, 0, 2, 1>, 256, "near wg256 unroll1 dyn8 coarse4 bit prefix2 rel", 1, 1},
+    {k_score_swar<256, 3, 1, 16, 2, 1>, 256, "swar wg256 head3 unroll1 dyn16 coarse4 bit", kLdsK},
+    {k_score_swar<256, 4, 1, 16, 0, 0>, 256, "swar wg256 head4 unroll1 dyn16", kLdsK},
+    {k_score_near<256, 1, 16, 2, 1, 0>, 256, "near wg256 unroll1 dyn16 coarse4 bit", kNearK},
+    {k_score_near<256, 1, 16, 0, 1, 0>, 256, "near wg256 unroll1 dyn16 bit", kNearK},
+    {k_score_near<256, 1, 8, 2, 1, 0, 1, 1>, 256, "near wg256 unroll1 dyn8 coarse4 bit rel", kNearK, 1},
+    {k_score_near<256, 1, 8, 2, 1, 1, 1, 1>, 256, "near wg256 unroll1 dyn8 coarse4 bit rel diag", kNearK, 1},
+    {k_score_near<256, 1, 16, 2, 1, 0, 1, 1>, 256, "near wg256 unroll1 dyn16 coarse4 bit rel", kNearK, 1},
+    {k_score_near<256, 2, 8, 2, 1, 0, 1, 1>, 256, "near wg256 unroll2 dyn8 coarse4 bit rel", kNearK, 1},
+    {k_score_near<512, 1, 8, 2, 1, 0, 1, 1>, 512, "near wg512 unroll1 dyn8 coarse4 bit rel", kNearK, 1},
+    {k_score_near<256, 1, 8, 2, 1, 0, 2, 1>, 256, "near wg256 unroll1 dyn8 coarse4 bit prefix2 rel", kNearK, 1},
 };
 constexpr int kNumVariants = (int)(sizeof(kVariants) / sizeof(kVariants[0]));
 int g_resident[kNumVariants];   // workgroups per CU, from the occupancy query
@@ -1159,12 +1222,49 @@ const char *score_variant_name(int v) {
   return v >= 0 && v < kNumVariants ? kVariants[v].name : "";
 }
 
+int multi_begin_capacity() { return kMultiBegin; }
+
+// The tools of `set` (host copies of their tables in host_tools, indexed
+// like set.id) in one persistent launch.
+void launch_score_multi(const Params &p, PointsDev pts, const ToolDev *tools_dev,
+                        const ToolDev *host_tools, const ToolSet &set, GridDev g, int64_t n,
+                        unsigned *work, hipStream_t s) {
+  if (n <= 0 || set.n <= 0) return;
+  bool rel = true;
+  for (int i = 0; i < set.n; ++i) rel = rel && host_tools[i].rent != nullptr;
+  using MultiKernel = void (*)(Params, PointsDev, const ToolDev *, ToolSet, GridDev, int64_t,
+                               unsigned *);
+  const MultiKernel fn = rel ? k_score_near_multi<256, 1, 8, 2, 1, 1, 1>
+                             : k_score_near_multi<256, 1, 8, 2, 1, 1, 0>;
+  if (g_num_cu == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    if (hipDeviceGetAttribute(&g_num_cu, hipDeviceAttributeMultiprocessorCount, dev) !=
+            hipSuccess ||
+        g_num_cu <= 0)
+      g_num_cu = 256;
+  }
+  int32_t words = 0;
+  for (int i = 0; i < set.n; ++i) words += host_tools[i].K + 1;
+  const size_t lds = sizeof(uint32_t) * (size_t)words;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, lds) != hipSuccess ||
+      per_cu <= 0)
+    per_cu = 1;
+  int64_t wg = (int64_t)per_cu * g_num_cu;
+  const int64_t need = (n * set.n + 3) / 4;
+  if (wg > need) wg = need;
+  hipLaunchKernelGGL(k_zero, dim3(1), dim3(1), 0, s, work);
+  hipLaunchKernelGGL(fn, dim3((unsigned)wg), dim3(256), lds, s, p, pts, tools_dev, set, g, n,
+                     work);
+}
+
 void launch_score(const Params &p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int variant,
                   unsigned *work, hipStream_t s) {
   int32_t mw = (t.K + 63) / 64;
   if (n <= 0) return;
   if (variant < 0 || variant >= kNumVariants) variant = 0;
-  if (kVariants[variant].needs_lds_k && t.K > kLdsK) variant = 0;
+  if (kVariants[variant].max_k && t.K > kVariants[variant].max_k) variant = 0;
   if (kVariants[variant].needs_rel && !t.rent) variant = 0;
   const ScoreVariant &v = kVariants[variant];
   if (g_num_cu == 0) {

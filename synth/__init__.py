@@ -376,3 +376,32 @@ def tree(n_frames: int = 600, n_hits=20000, sigma: float = 0.02, seed: int = 5,
 
 def uneven_counts(n: int, lo: int = 5000, hi: int = 40000, seed: int = 9):
     return np.random.default_rng(seed).integers(lo, hi + 1, size=n)
+
+
+def batch_tools(seed: int = 13):
+    """Eight seeded tools for the batching workload: cylinders (even index)
+    and boxes (odd) with 2-8 cm cross-sections, 10-30 cm bodies and
+    0.3-1.5 m corridors."""
+    rng = np.random.default_rng(seed)
+    tools = []
+    for i in range(8):
+        size = float(rng.uniform(0.02, 0.08))
+        length = float(rng.uniform(0.10, 0.30))
+        corridor = float(rng.uniform(0.3, 1.5))
+        if i % 2 == 0:
+            tools.append(cylinder_tool(radius=size / 2, length=length, corridor=corridor))
+        else:
+            height = float(rng.uniform(0.02, size))
+            tools.append(box_tool(length=length, width=size, height=height, corridor=corridor))
+    return tools
+
+
+def batch(n_frames: int = 600, seed: int = 5, counts_seed: int = 9) -> Workload:
+    """The tree scene with frames of 5,000-40,000 returns (uniform, seeded);
+    the tools and their 512 orientations (128 directions x 4 rolls) come from
+    batch_tools() and orientations(fibonacci_directions(128), 4)."""
+    w = tree(n_frames=n_frames, seed=seed)
+    w.name = "batch"
+    w.n_hits = uneven_counts(max(600, n_frames), seed=counts_seed)
+    w.rot = orientations(fibonacci_directions(128), 4)
+    return w
