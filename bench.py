@@ -190,6 +190,29 @@ def run_batch(args):
     same = all(np.array_equal(multi[j]["label"], ctx.read_labels(j)["label"]) and
                np.array_equal(multi[j]["first_free"], ctx.read_labels(j)["first_free"])
                for j in ids)
+    # the same frames through the recorded per-frame graph on a second context
+    rec = Context(cfg)
+    for i, tl in enumerate(tools):
+        rec.set_tool_kernels(i, tl, w.rot)
+    allx = np.concatenate([f.xyz for f in frames])
+    rec.graph_prepare(allx.min(0) - 1.0, allx.max(0) + 1.0, max(len(f.xyz) for f in frames), ids)
+    for i in range(W):
+        rec.graph_frame(resident[i], frames[i].origin, frames[i].frame_id)
+    rec.graph_sync()
+    gtests = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(W, W + K):
+        rec.graph_frame(resident[i], frames[i].origin, frames[i].frame_id)
+        rec.graph_sync()
+        for j in ids:
+            gtests += rec.score_stats(j)["canonical_tests"]
+    torch.cuda.synchronize()
+    gwall = time.perf_counter() - t0
+    gsame = all(np.array_equal(ctx.read_labels(j)["label"], rec.read_labels(j)["label"]) and
+                np.array_equal(ctx.read_labels(j)["first_free"], rec.read_labels(j)["first_free"])
+                for j in ids)
+    log("recorded frames: %.2f ms/frame (eager %.2f)" % (gwall / K * 1e3, wall / K * 1e3))
     out = {
         "metric": "point\u00d7orientation tests/s, 8 tools x 512 orientations",
         "value": tests / wall,
@@ -213,6 +236,10 @@ def run_batch(args):
         "one_launch_vs_per_tool": {"ms_one_launch": ms_multi, "ms_per_tool_launches": ms_single,
                                    "speedup": ms_single / ms_multi,
                                    "labels_identical": bool(same)},
+        "recorded_graph": {"ms_per_step": gwall / K * 1e3, "tests_per_s": gtests / gwall,
+                           "eager_ms_per_step": wall / K * 1e3,
+                           "same_tests": bool(gtests == tests),
+                           "labels_identical": bool(gsame)},
     }
     print(json.dumps(out), flush=True)
 

@@ -261,6 +261,39 @@ int32_t af_get_score_variant(af_ctx *ctx);
 int af_tune_score(af_ctx *ctx, int32_t tool_id, int32_t reps, void *stream, int32_t *best,
                   float *ms_per_variant);
 
+/* Recorded frame pipeline (the scan-centric update of Section 3.3 followed by
+ * the per-point test of Section 3.5 for a set of tools, as one HIP graph).
+ *
+ * af_graph_prepare records, once, everything one frame does: integration of
+ * up to `max_returns` returns, then normals, masks and the one-launch scoring
+ * of tools `tool_ids[0..n_tools)` (as af_score_tools) over every point the
+ * map then holds.  The brick grid is sized for the scene box [lo, hi]
+ * (metres, merged with every block already mapped) and is not regrown while
+ * the graph is in use, so no frame needs a host round trip.  Synchronises
+ * `stream`.  AF_EINVAL for bad arguments or tools (as af_score_tools),
+ * AF_ENOMEM, AF_EDEVICE if the capture fails.
+ *
+ * af_graph_frame replays the graph for one frame: `xyz` (device, n x 3 float,
+ * n <= max_returns; may be af_graph_slot(), which skips a copy), sensor origin
+ * and an increasing frame id as for af_integrate_frame.  Asynchronous on
+ * `stream`; host-side counts and errors of replayed frames are settled by
+ * af_graph_sync, which waits for them and reports AF_EOVERFLOW if any frame
+ * since the last settlement overflowed the hash table, block or point
+ * capacity, or mapped a block outside the recorded scene box (those frames'
+ * results are then incomplete).  Every other call of this interface settles
+ * first, so eager calls and replays may be mixed on one stream.  A call that
+ * reallocates a buffer the graph holds (a frame larger than the scratch
+ * capacity, grid growth, af_set_tool_kernels) makes af_graph_frame return
+ * AF_EINVAL until af_graph_prepare is called again.  Labels, first free
+ * orientations, statistics and the map after each replay equal those of
+ * af_integrate_frame followed by af_score_tools. */
+int af_graph_prepare(af_ctx *ctx, const float lo[3], const float hi[3], int64_t max_returns,
+                     const int32_t *tool_ids, int32_t n_tools, void *stream);
+int af_graph_frame(af_ctx *ctx, const float *xyz, int64_t n, const float origin[3],
+                   int64_t frame_id, void *stream);
+float *af_graph_slot(af_ctx *ctx);
+int af_graph_sync(af_ctx *ctx);
+
 #ifdef __cplusplus
 }
 #endif

@@ -107,6 +107,13 @@ SIGNATURES = {
     "af_score_variant_count": (ctypes.c_int, []),
     "af_score_tools": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "af_score_variant_default": (ctypes.c_int, []),
+    "af_graph_prepare": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_int64, ctypes.c_void_p, ctypes.c_int32,
+                                        ctypes.c_void_p]),
+    "af_graph_frame": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                      ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
+    "af_graph_slot": (ctypes.c_void_p, [ctypes.c_void_p]),
+    "af_graph_sync": (ctypes.c_int, [ctypes.c_void_p]),
     "af_score_variant_name": (ctypes.c_char_p, [_i32]),
     "af_set_score_variant": (ctypes.c_int, [_vp, _i32]),
     "af_get_score_variant": (_i32, [_vp]),
@@ -326,6 +333,34 @@ class Context:
         """Score every point against several tools in one launch."""
         ids = (ctypes.c_int32 * len(tool_ids))(*[int(x) for x in tool_ids])
         self._check(self._lib.af_score_tools(self.h, ids, len(tool_ids), _stream_handle(stream)))
+
+    def graph_prepare(self, lo, hi, max_returns: int, tool_ids, stream=None):
+        """Record one frame (integration of up to max_returns returns, then
+        scoring of tool_ids in one launch) as a HIP graph; the brick grid
+        covers the scene box [lo, hi] (metres)."""
+        lo = np.ascontiguousarray(lo, dtype=np.float32).reshape(3)
+        hi = np.ascontiguousarray(hi, dtype=np.float32).reshape(3)
+        ids = (ctypes.c_int32 * len(tool_ids))(*[int(x) for x in tool_ids])
+        self._check(self._lib.af_graph_prepare(self.h, _p(lo), _p(hi), int(max_returns), ids,
+                                               len(tool_ids), _stream_handle(stream)))
+
+    def graph_frame(self, xyz, origin, frame_id: int, stream=None):
+        """Replay the recorded frame on xyz (contiguous CUDA float32 [n, 3])."""
+        if not (getattr(xyz, "is_cuda", False) and str(xyz.dtype) == "torch.float32"
+                and xyz.is_contiguous() and xyz.dim() == 2 and xyz.shape[1] == 3):
+            raise TypeError("xyz must be a contiguous CUDA float32 tensor of shape [n, 3]")
+        o = np.ascontiguousarray(origin, dtype=np.float32).reshape(3)
+        self._check(self._lib.af_graph_frame(self.h, ctypes.c_void_p(xyz.data_ptr()),
+                                             int(xyz.shape[0]), _p(o), int(frame_id),
+                                             _stream_handle(stream)))
+
+    def graph_slot(self) -> int:
+        """Device address of the recorded frame's input slot (0 if none)."""
+        return int(self._lib.af_graph_slot(self.h) or 0)
+
+    def graph_sync(self):
+        """Wait for replayed frames and raise on any overflow they reported."""
+        self._check(self._lib.af_graph_sync(self.h))
 
     def score_variant_default(self) -> int:
         return self._lib.af_score_variant_default()

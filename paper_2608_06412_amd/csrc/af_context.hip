@@ -33,6 +33,15 @@ struct af_ctx {
   uint64_t *mask;               // shared candidate-mask scratch
   uint64_t *nearp;              // shared arm-sample planes
   ToolDev *tools_dev;           // device mirror of `tools` (for the multi-tool launch)
+  FrameArgs *fargs;             // device: the current frame's n, origin, id
+  // recorded frame pipeline (af_graph_prepare)
+  hipGraph_t graph;
+  hipGraphExec_t gexec;
+  hipStream_t cap_stream;
+  float *slot_xyz;              // device frame slot
+  int64_t slot_cap;
+  bool graph_dirty;             // recorded frames ran since the host mirrors were refreshed
+  bool graph_stale;             // a buffer the graph holds was reallocated
   std::vector<char> own_mask;   // tool has its own mask and plane buffers
   unsigned *work;               // point counter of the dynamic score variants
   int score_variant;
@@ -109,6 +118,7 @@ uint32_t pow2_at_least(int64_t n) {
   } while (0)
 
 int alloc_scratch(af_ctx *c, int64_t cap) {
+  c->graph_stale = true;
   FrameScratch &f = c->fs;
   if (f.cap > 0) {
     dev_free(c, f.P, sizeof(int4) * f.cap);
@@ -179,8 +189,10 @@ int ensure_grid(af_ctx *c, hipStream_t s, bool &rebuilt) {
     ng.gd[a] = ext + 2 * margin;
     nb *= ng.gd[a];
   }
+  ng.margin = need;
   if (nb * 128 >= (int64_t(1) << 32))
     return fail(c, AF_ENOMEM, "brick grid of %lld bricks exceeds 4 GiB", (long long)nb);
+  c->graph_stale = true;
   if (c->grid_bricks > 0) {
     HIP_TRY(c, hipStreamSynchronize(s));
     dev_free(c, g.pred, sizeof(uint32_t) * 32 * c->grid_bricks);
@@ -395,6 +407,7 @@ int af_create(const af_config *cfg, af_ctx **out) {
   CREATE_ALLOC(c->mask, NP * ((cfg->max_orientations + 63) / 64));
   CREATE_ALLOC(c->nearp, NP * 2 * ((cfg->max_orientations + 63) / 64));
   CREATE_ALLOC(c->tools_dev, cfg->max_tools);
+  CREATE_ALLOC(c->fargs, 1);
   c->own_mask.assign(cfg->max_tools, 0);
   c->tools.assign(cfg->max_tools, ToolDev());
   c->tool_bytes.assign(cfg->max_tools, 0);
@@ -417,6 +430,9 @@ int af_create(const af_config *cfg, af_ctx **out) {
 int af_destroy(af_ctx *c) {
   if (!c) return AF_EINVAL;
   hipDeviceSynchronize();
+  if (c->gexec) hipGraphExecDestroy(c->gexec);
+  if (c->graph) hipGraphDestroy(c->graph);
+  if (c->cap_stream) hipStreamDestroy(c->cap_stream);
   timing_flush(c);
   for (hipEvent_t e : c->ev_free) hipEventDestroy(e);
   for (void *q : c->allocs) hipFree(q);
@@ -429,9 +445,15 @@ const char *af_last_error(const af_ctx *c) { return c ? c->err.c_str() : "null c
 
 int64_t af_device_bytes(af_ctx *c) { return c ? c->bytes : 0; }
 
+static int graph_settle(af_ctx *c);
+
 int af_set_tool_kernels(af_ctx *c, int32_t tool_id, const af_tool *tool, int32_t K,
                         const double *rot, void *stream) {
   if (!c) return AF_EINVAL;
+  if (c->graph_dirty) {
+    const int rc = graph_settle(c);
+    if (rc != AF_OK) return rc;
+  }
   if (tool_id < 0 || tool_id >= c->cfg.max_tools)
     return fail(c, AF_EINVAL, "tool id %d outside [0, %d)", tool_id, c->cfg.max_tools);
   if (!tool || !rot || K < 1 || K > c->cfg.max_orientations)
@@ -587,12 +609,17 @@ int af_set_tool_kernels(af_ctx *c, int32_t tool_id, const af_tool *tool, int32_t
   c->last_stream = s;
   if (c->grid_bricks > 0 && launch_table_grid(t, c->grid, s) != 0) return hip_check(c, "table grid");
   HIP_TRY(c, hipMemcpy(&c->tools_dev[tool_id], &t, sizeof(ToolDev), hipMemcpyHostToDevice));
+  c->graph_stale = true;
   return regrid(c, s);
 }
 
 int af_integrate_frame(af_ctx *c, const float *xyz, int64_t n, const float origin[3],
                        int64_t frame_id, void *stream) {
   if (!c) return AF_EINVAL;
+  if (c->graph_dirty) {
+    const int rc = graph_settle(c);
+    if (rc != AF_OK) return rc;
+  }
   if (n < 0 || (n > 0 && !xyz) || !origin)
     return fail(c, AF_EINVAL, "bad frame arguments");
   if (frame_id <= c->last_frame || frame_id > 0x7ffffffe)
@@ -612,8 +639,9 @@ int af_integrate_frame(af_ctx *c, const float *xyz, int64_t n, const float origi
   }
   const int32_t frame = (int32_t)frame_id;
   hipEvent_t t0 = timing_mark(c, s);
-  launch_frame_prep(xyz, n, Q, c->p, c->map, c->pts, c->fs, c->counters, s);
-  launch_assign_blocks(c->map, c->fs, c->counters, frame, s);
+  launch_set_frame_args(c->fargs, n, Q, frame, s);
+  launch_frame_prep(xyz, c->fargs, n, c->p, c->map, c->pts, c->fs, c->counters, s);
+  launch_assign_blocks(c->map, c->fs, c->counters, c->fargs, s);
   launch_commit_blocks(c->map, c->counters, s);
   HIP_TRY(c, hipMemcpyAsync(c->counters_host, c->counters, offsetof(FrameCounters, fold),
                             hipMemcpyDeviceToHost, s));
@@ -629,13 +657,13 @@ int af_integrate_frame(af_ctx *c, const float *xyz, int64_t n, const float origi
   }
   bool rebuilt = false;
   if ((rc = ensure_grid(c, s, rebuilt)) != AF_OK) return rc;
-  launch_touch_band(n, c->p, c->map, c->fs, c->counters, frame, s);
-  launch_points_append(h.n_new_points, c->map, c->pts, c->fs, c->counters, frame, s);
+  launch_touch_band(c->fargs, n, c->p, c->map, c->fs, c->counters, s);
+  launch_points_append(h.n_new_points, c->map, c->pts, c->fs, c->counters, c->fargs, s);
   launch_commit_points(c->pts, c->counters, s);
-  launch_points_view(n, Q, c->p, c->pts, c->fs, frame, s);
+  launch_points_view(c->fargs, n, c->p, c->pts, c->fs, s);
   int64_t nb_after = std::min<int64_t>((int64_t)h.blocks_before + h.n_new_blocks, c->cfg.max_blocks);
   hipEvent_t t1 = timing_mark(c, s);
-  launch_integrate(n, Q, c->p, c->map, c->fs, c->counters, c->grid,
+  launch_integrate(c->fargs, n, c->p, c->map, c->fs, c->counters, c->grid,
                    std::max<int64_t>(1, std::min<int64_t>(nb_after, n * (kMaxSpan + kMaxBand))), s);
   hipEvent_t t2 = timing_mark(c, s);
   if (rebuilt) launch_grid_rebuild(c->p, c->map, c->grid, nb_after, s);
@@ -661,6 +689,10 @@ int af_integrate_frame(af_ctx *c, const float *xyz, int64_t n, const float origi
 
 int af_score_points(af_ctx *c, int32_t tool_id, void *stream) {
   if (!c) return AF_EINVAL;
+  if (c->graph_dirty) {
+    const int rc = graph_settle(c);
+    if (rc != AF_OK) return rc;
+  }
   if (tool_id < 0 || tool_id >= c->cfg.max_tools) return fail(c, AF_EINVAL, "bad tool id");
   ToolDev &t = c->tools[tool_id];
   if (!t.entries) return fail(c, AF_ENOTOOL, "tool %d has no kernels", tool_id);
@@ -687,11 +719,12 @@ int af_score_points(af_ctx *c, int32_t tool_id, void *stream) {
   return hip_check(c, "score");
 }
 
-int af_score_tools(af_ctx *c, const int32_t *tool_ids, int32_t n_tools, void *stream) {
-  if (!c) return AF_EINVAL;
+// The tool set of one multi-tool launch: ids checked, LDS offsets, and each
+// tool given its own mask buffers (masks of every tool must coexist).
+static int make_toolset(af_ctx *c, const int32_t *tool_ids, int32_t n_tools, ToolSet &set,
+                        ToolDev *host) {
   if (!tool_ids || n_tools < 1 || n_tools > kMultiTools)
     return fail(c, AF_EINVAL, "n_tools must be 1..%d", kMultiTools);
-  ToolSet set;
   memset(&set, 0, sizeof(set));
   set.n = n_tools;
   int32_t words = 0;
@@ -708,14 +741,10 @@ int af_score_tools(af_ctx *c, const int32_t *tool_ids, int32_t n_tools, void *st
   }
   if (words > multi_begin_capacity())
     return fail(c, AF_EINVAL, "%d orientations exceed one launch", words - n_tools);
-  hipStream_t s = (hipStream_t)stream;
-  int rc = regrid(c, s);
-  if (rc != AF_OK) return rc;
-  ToolDev host[kMultiTools];
   for (int32_t i = 0; i < n_tools; ++i) {
     const int32_t id = set.id[i];
     ToolDev &t = c->tools[id];
-    if (!c->own_mask[id]) {   // masks of every tool must coexist
+    if (!c->own_mask[id]) {
       const int64_t mw = (t.K + 63) / 64;
       uint64_t *mk = nullptr, *np = nullptr;
       ALLOC(c, mk, c->cfg.max_points * mw);
@@ -727,6 +756,20 @@ int af_score_tools(af_ctx *c, const int32_t *tool_ids, int32_t n_tools, void *st
     }
     host[i] = t;
   }
+  return AF_OK;
+}
+
+static int sync_last(af_ctx *c);
+
+int af_score_tools(af_ctx *c, const int32_t *tool_ids, int32_t n_tools, void *stream) {
+  if (!c) return AF_EINVAL;
+  int rc;
+  if (c->graph_dirty && (rc = graph_settle(c)) != AF_OK) return rc;
+  ToolSet set;
+  ToolDev host[kMultiTools];
+  if ((rc = make_toolset(c, tool_ids, n_tools, set, host)) != AF_OK) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = regrid(c, s)) != AF_OK) return rc;
   hipEvent_t t0 = timing_mark(c, s);
   for (int32_t i = 0; i < n_tools; ++i)
     HIP_TRY(c, hipMemsetAsync(host[i].counters, 0, sizeof(ScoreCounters), s));
@@ -749,6 +792,150 @@ int af_score_tools(af_ctx *c, const int32_t *tool_ids, int32_t n_tools, void *st
   return hip_check(c, "score tools");
 }
 
+static_assert(offsetof(FrameCounters, sbmin) == offsetof(FrameCounters, sticky) + 4 &&
+                  offsetof(FrameCounters, sbmax) == offsetof(FrameCounters, sticky) + 16,
+              "sticky fields are cleared as one block");
+static hipError_t clear_sticky(af_ctx *c) {
+  int32_t v[7] = {0, 0x7fffffff, 0x7fffffff, 0x7fffffff, -0x7fffffff - 1, -0x7fffffff - 1,
+                  -0x7fffffff - 1};
+  return hipMemcpy(&c->counters->sticky, v, sizeof(v), hipMemcpyHostToDevice);
+}
+
+// Wait for recorded frames, refresh the host's point and block counts and
+// report any status they raised (sticky across frames).
+static int graph_settle(af_ctx *c) {
+  c->graph_dirty = false;
+  HIP_TRY(c, hipStreamSynchronize(c->last_stream));
+  FrameCounters h;
+  HIP_TRY(c, hipMemcpy(&h, c->counters, offsetof(FrameCounters, fold), hipMemcpyDeviceToHost));
+  int32_t nb = 0, np = 0;
+  HIP_TRY(c, hipMemcpy(&nb, c->map.n_blocks, sizeof(int32_t), hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipMemcpy(&np, c->pts.n_points, sizeof(int32_t), hipMemcpyDeviceToHost));
+  c->n_blocks = std::min<int64_t>(nb, c->cfg.max_blocks);
+  c->n_points = std::min<int64_t>(np, c->cfg.max_points);
+  if (h.sbmin[0] <= h.sbmax[0]) {
+    for (int a = 0; a < 3; ++a) {
+      c->bbox_lo[a] = c->have_bbox ? std::min(c->bbox_lo[a], h.sbmin[a]) : h.sbmin[a];
+      c->bbox_hi[a] = c->have_bbox ? std::max(c->bbox_hi[a], h.sbmax[a]) : h.sbmax[a];
+    }
+    c->have_bbox = true;
+  }
+  HIP_TRY(c, clear_sticky(c));
+  c->status = h.sticky;
+  // a block beyond the recorded box: the grid must grow, so the graph is done
+  if (h.sticky & kStatusOutsideGrid) c->graph_stale = true;
+  if (h.sticky & kStatusHashFull) return fail(c, AF_EOVERFLOW, "hash table full");
+  if (h.sticky & kStatusBlockOverflow)
+    return fail(c, AF_EOVERFLOW, "block capacity %lld exceeded", (long long)c->cfg.max_blocks);
+  if (h.sticky & kStatusPointOverflow)
+    return fail(c, AF_EOVERFLOW, "point capacity %lld exceeded", (long long)c->cfg.max_points);
+  if (h.sticky & kStatusOutsideGrid)
+    return fail(c, AF_EOVERFLOW, "a block left the recorded scene box");
+  return AF_OK;
+}
+
+int af_graph_prepare(af_ctx *c, const float lo[3], const float hi[3], int64_t max_returns,
+                     const int32_t *tool_ids, int32_t n_tools, void *stream) {
+  if (!c) return AF_EINVAL;
+  if (!lo || !hi || max_returns < 1) return fail(c, AF_EINVAL, "bad graph arguments");
+  int rc;
+  if (c->graph_dirty && (rc = graph_settle(c)) != AF_OK) return rc;
+  ToolSet set;
+  ToolDev host[kMultiTools];
+  if ((rc = make_toolset(c, tool_ids, n_tools, set, host)) != AF_OK) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(c, hipStreamSynchronize(s));
+  // the grid covers the scene box (and every block so far) and never grows
+  const double bs = 8.0 * c->cfg.voxel;
+  for (int a = 0; a < 3; ++a) {
+    if (!(lo[a] < hi[a]) || !(fabs((double)lo[a]) < 1e4) || !(fabs((double)hi[a]) < 1e4))
+      return fail(c, AF_EINVAL, "bad scene box");
+    const int32_t l = (int32_t)floor((double)lo[a] / bs), h = (int32_t)floor((double)hi[a] / bs);
+    c->bbox_lo[a] = c->have_bbox ? std::min(c->bbox_lo[a], l) : l;
+    c->bbox_hi[a] = c->have_bbox ? std::max(c->bbox_hi[a], h) : h;
+  }
+  c->have_bbox = true;
+  if ((rc = regrid(c, s)) != AF_OK) return rc;
+  if (max_returns > c->fs.cap && (rc = alloc_scratch(c, max_returns)) != AF_OK) return rc;
+  if (c->slot_xyz) dev_free(c, c->slot_xyz, sizeof(float) * 3 * c->slot_cap);
+  c->slot_xyz = nullptr;
+  ALLOC(c, c->slot_xyz, 3 * max_returns);
+  c->slot_cap = max_returns;
+  launch_normals(c->p, c->map, c->pts, c->grid, 0, s);   // uploads its constant table
+  HIP_TRY(c, hipStreamSynchronize(s));
+  HIP_TRY(c, clear_sticky(c));
+  if (c->gexec) hipGraphExecDestroy(c->gexec);
+  if (c->graph) hipGraphDestroy(c->graph);
+  c->gexec = nullptr;
+  c->graph = nullptr;
+  if (!c->cap_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  hipStream_t cs = c->cap_stream;
+  const int64_t cap = max_returns, NP = c->cfg.max_points;
+  HIP_TRY(c, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  launch_frame_prep(c->slot_xyz, c->fargs, cap, c->p, c->map, c->pts, c->fs, c->counters, cs);
+  launch_assign_blocks(c->map, c->fs, c->counters, c->fargs, cs);
+  launch_commit_blocks(c->map, c->counters, cs);
+  launch_touch_band(c->fargs, cap, c->p, c->map, c->fs, c->counters, cs);
+  launch_points_append(cap, c->map, c->pts, c->fs, c->counters, c->fargs, cs);
+  launch_commit_points(c->pts, c->counters, cs);
+  launch_points_view(c->fargs, cap, c->p, c->pts, c->fs, cs);
+  launch_integrate(c->fargs, cap, c->p, c->map, c->fs, c->counters, c->grid,
+                   std::min<int64_t>(c->cfg.max_blocks, cap * (kMaxSpan + kMaxBand)), cs);
+  launch_stick_status(c->counters, cs);
+  for (int32_t i = 0; i < n_tools; ++i)
+    launch_zero_words(host[i].counters, sizeof(ScoreCounters), cs);
+  launch_normals(c->p, c->map, c->pts, c->grid, NP, cs, true);
+  for (int32_t i = 0; i < n_tools; ++i) launch_mask(c->p, c->pts, host[i], c->grid, NP, cs, true);
+  launch_score_multi(c->p, c->pts, c->tools_dev, host, set, c->grid, NP, c->work, cs, true);
+  hipGraph_t g = nullptr;
+  const hipError_t e1 = hipStreamEndCapture(cs, &g);
+  if (e1 != hipSuccess || !g)
+    return fail(c, AF_EDEVICE, "frame graph capture: %s", hipGetErrorString(e1));
+  c->graph = g;
+  HIP_TRY(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+  c->graph_stale = false;
+  c->last_stream = s;
+  return hip_check(c, "graph prepare");
+}
+
+int af_graph_frame(af_ctx *c, const float *xyz, int64_t n, const float origin[3],
+                   int64_t frame_id, void *stream) {
+  if (!c) return AF_EINVAL;
+  if (!c->gexec) return fail(c, AF_EINVAL, "no recorded frame graph");
+  if (c->graph_stale)
+    return fail(c, AF_EINVAL, "buffers of the recorded frame graph were reallocated: prepare again");
+  if (n < 0 || n > c->slot_cap || (n > 0 && !xyz) || !origin)
+    return fail(c, AF_EINVAL, "bad frame arguments (n = %lld, slot %lld)", (long long)n,
+                (long long)c->slot_cap);
+  if (frame_id <= c->last_frame || frame_id > 0x7ffffffe)
+    return fail(c, AF_EINVAL, "frame id %lld does not increase", (long long)frame_id);
+  int3 Q;
+  int *qq[3] = {&Q.x, &Q.y, &Q.z};
+  for (int a = 0; a < 3; ++a) {
+    double t = (double)origin[a] * c->p.scale;
+    if (!(fabs(t) <= (double)kCoordLim)) return fail(c, AF_EINVAL, "sensor origin out of range");
+    *qq[a] = (int)llrint(t);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  if (n > 0 && xyz != c->slot_xyz)
+    HIP_TRY(c, hipMemcpyAsync(c->slot_xyz, xyz, sizeof(float) * 3 * n, hipMemcpyDeviceToDevice,
+                              s));
+  launch_set_frame_args(c->fargs, n, Q, (int32_t)frame_id, s);
+  HIP_TRY(c, hipGraphLaunch(c->gexec, s));
+  c->last_frame = frame_id;
+  c->last_stream = s;
+  c->graph_dirty = true;
+  return hip_check(c, "graph frame");
+}
+
+float *af_graph_slot(af_ctx *c) { return c ? c->slot_xyz : nullptr; }
+
+int af_graph_sync(af_ctx *c) {
+  if (!c) return AF_EINVAL;
+  if (!c->graph_dirty) return sync_last(c);
+  return graph_settle(c);
+}
+
 int af_score_variant_count(void) { return score_variants(); }
 
 const char *af_score_variant_name(int32_t v) { return score_variant_name(v); }
@@ -767,6 +954,10 @@ int32_t af_get_score_variant(af_ctx *c) { return c ? c->score_variant : -1; }
 int af_tune_score(af_ctx *c, int32_t tool_id, int32_t reps, void *stream, int32_t *best,
                   float *ms_per_variant) {
   if (!c) return AF_EINVAL;
+  if (c->graph_dirty) {
+    const int rc = graph_settle(c);
+    if (rc != AF_OK) return rc;
+  }
   if (tool_id < 0 || tool_id >= c->cfg.max_tools) return fail(c, AF_EINVAL, "bad tool id");
   ToolDev &t = c->tools[tool_id];
   if (!t.entries) return fail(c, AF_ENOTOOL, "tool %d has no kernels", tool_id);
@@ -806,6 +997,7 @@ int af_tune_score(af_ctx *c, int32_t tool_id, int32_t reps, void *stream, int32_
 }
 
 static int sync_last(af_ctx *c) {
+  if (c->graph_dirty) return graph_settle(c);
   HIP_TRY(c, hipStreamSynchronize(c->last_stream));
   return AF_OK;
 }

@@ -4,6 +4,8 @@
 // with the weight cap (Section 3.6) and the brick grid used by scoring.
 #include "af_internal.h"
 
+#include <algorithm>
+
 #pragma clang fp contract(off)
 
 namespace af {
@@ -103,8 +105,10 @@ __device__ inline Span cube_span(int4 P, int R) {
 // Quantise each return, insert the blocks of its cube and of its band
 // samples, and insert its voxel into the point set.
 __global__ void __launch_bounds__(kThreads)
-k_frame_prep(const float *__restrict__ xyz, int64_t n, int3 Q, Params p, MapDev m,
+k_frame_prep(const float *__restrict__ xyz, const FrameArgs *fa, Params p, MapDev m,
              PointsDev pts, FrameScratch fs, FrameCounters *c) {
+  const int64_t n = fa->n;
+  const int3 Q = fa->Q;
   int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   bool in = r < n;
   bool ok = in;
@@ -188,7 +192,8 @@ __global__ void k_reset_counters(FrameCounters *c, MapDev m, PointsDev pts) {
 
 // One workgroup per new block: assign its id and clear its voxels.
 __global__ void __launch_bounds__(kThreads)
-k_assign_blocks(MapDev m, FrameScratch fs, FrameCounters *c, int32_t frame) {
+k_assign_blocks(MapDev m, FrameScratch fs, FrameCounters *c, const FrameArgs *fa) {
+  const int32_t frame = fa->frame;
   int n_new = c->n_new_blocks;
   int64_t base = *m.n_blocks;
   for (int i = blockIdx.x; i < n_new; i += gridDim.x) {
@@ -233,7 +238,9 @@ __global__ void k_commit_blocks(MapDev m, FrameCounters *c) {
 
 // Mark every block of the frame touched (once) and set the band's cleared bits.
 __global__ void __launch_bounds__(kThreads)
-k_touch_band(int64_t n, Params p, MapDev m, FrameScratch fs, FrameCounters *c, int32_t frame) {
+k_touch_band(const FrameArgs *fa, Params p, MapDev m, FrameScratch fs, FrameCounters *c) {
+  const int64_t n = fa->n;
+  const int32_t frame = fa->frame;
   int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   int marks = 0;
   if (r < n) {
@@ -277,7 +284,8 @@ k_touch_band(int64_t n, Params p, MapDev m, FrameScratch fs, FrameCounters *c, i
 // New point keys of the frame get ids in ascending key order (rank by
 // counting smaller keys), are initialised and flagged in their block.
 __global__ void __launch_bounds__(kThreads)
-k_points_append(MapDev m, PointsDev pts, FrameScratch fs, FrameCounters *c, int32_t frame) {
+k_points_append(MapDev m, PointsDev pts, FrameScratch fs, FrameCounters *c, const FrameArgs *fa) {
+  const int32_t frame = fa->frame;
   __shared__ int64_t tile[kThreads];
   int mcount = c->n_new_points;
   int i = blockIdx.x * kThreads + threadIdx.x;
@@ -327,7 +335,10 @@ __global__ void k_commit_points(PointsDev pts, FrameCounters *c) {
 
 // Once per (point, frame): running sensor sum and the viewpoint ring.
 __global__ void __launch_bounds__(kThreads)
-k_points_view(int64_t n, int3 Q, Params p, PointsDev pts, FrameScratch fs, int32_t frame) {
+k_points_view(const FrameArgs *fa, Params p, PointsDev pts, FrameScratch fs) {
+  const int64_t n = fa->n;
+  const int3 Q = fa->Q;
+  const int32_t frame = fa->frame;
   int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (r >= n || fs.P[r].w == 0) return;
   int32_t s = fs.pslot[r];
@@ -428,7 +439,8 @@ __device__ void write_brick(const Params &p, MapDev m, GridDev g, int64_t id, in
 // (Section 3.6) and the block's brick follow in the same workgroup, so the
 // map sees one plain store per voxel and no atomics.
 __global__ void __launch_bounds__(kThreads)
-k_bin_count(int64_t n, Params p, MapDev m, FrameScratch fs) {
+k_bin_count(const FrameArgs *fa, Params p, MapDev m, FrameScratch fs) {
+  const int64_t n = fa->n;
   int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (r >= n) return;
   int4 P = fs.P[r];
@@ -470,7 +482,8 @@ __global__ void __launch_bounds__(1024) k_bin_scan(FrameScratch fs, FrameCounter
 }
 
 __global__ void __launch_bounds__(kThreads)
-k_bin_fill(int64_t n, Params p, MapDev m, FrameScratch fs) {
+k_bin_fill(const FrameArgs *fa, Params p, MapDev m, FrameScratch fs) {
+  const int64_t n = fa->n;
   int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (r >= n) return;
   int4 P = fs.P[r];
@@ -485,7 +498,9 @@ k_bin_fill(int64_t n, Params p, MapDev m, FrameScratch fs) {
 }
 
 __global__ void __launch_bounds__(kBlockVox)
-k_integrate_fold(int3 Q, Params p, MapDev m, FrameScratch fs, FrameCounters *c, GridDev g) {
+k_integrate_fold(const FrameArgs *fa, Params p, MapDev m, FrameScratch fs, FrameCounters *c,
+                 GridDev g) {
+  const int3 Q = fa->Q;
   __shared__ int4 tile[kBlockVox];
   __shared__ uint8_t code[kBlockVox];
   __shared__ unsigned long long s_stat[3];
@@ -505,6 +520,12 @@ k_integrate_fold(int3 Q, Params p, MapDev m, FrameScratch fs, FrameCounters *c, 
     const int64_t bkey = m.bkey[id];
     int32_t b[3];
     unpack_key(bkey, b[0], b[1], b[2]);
+    if (t == 0) {
+      bool in = true;
+      for (int a = 0; a < 3; ++a)
+        in = in && b[a] - g.g0[a] >= g.margin && b[a] - g.g0[a] < g.gd[a] - g.margin;
+      if (!in) atomicOr(&c->status, kStatusOutsideGrid);
+    }
     const int vx = 8 * b[0] + (t & 7), vy = 8 * b[1] + ((t >> 3) & 7), vz = 8 * b[2] + (t >> 6);
     const int64_t cq0 = 256 * (int64_t)vx + 128 - Q.x;  // voxel centre - sensor
     const int64_t cq1 = 256 * (int64_t)vy + 128 - Q.y;
@@ -598,6 +619,27 @@ __global__ void k_grid_fill(GridDev g, int64_t nbricks) {
   for (int64_t j = i; j < nbricks * 16; j += stride) g.occ1[j] = 0u;
 }
 
+__global__ void k_stick_status(FrameCounters *c) {
+  c->sticky |= c->status;
+  if (c->n_new_blocks > 0)
+    for (int a = 0; a < 3; ++a) {
+      c->sbmin[a] = c->bmin[a] < c->sbmin[a] ? c->bmin[a] : c->sbmin[a];
+      c->sbmax[a] = c->bmax[a] > c->sbmax[a] ? c->bmax[a] : c->sbmax[a];
+    }
+}
+
+__global__ void k_zero_words(uint32_t *p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+__global__ void k_set_frame_args(FrameArgs *fa, int64_t n, int3 Q, int32_t frame) {
+  fa->n = n;
+  fa->Q = Q;
+  fa->frame = frame;
+}
+
 inline unsigned grid_for(int64_t threads) {
   int64_t b = (threads + kThreads - 1) / kThreads;
   return (unsigned)(b > 0 ? b : 1);
@@ -605,61 +647,77 @@ inline unsigned grid_for(int64_t threads) {
 
 }  // namespace
 
-void launch_frame_prep(const float *xyz, int64_t n, int3 Q, const Params &p, MapDev m,
-                       PointsDev pts, FrameScratch fs, FrameCounters *c, hipStream_t s) {
+void launch_zero_words(void *p, int64_t bytes, hipStream_t s) {
+  const int64_t n = bytes / 4;
+  hipLaunchKernelGGL(k_zero_words, dim3((unsigned)std::min<int64_t>(1024, (n + 255) / 256)),
+                     dim3(256), 0, s, (uint32_t *)p, n);
+}
+
+void launch_stick_status(FrameCounters *c, hipStream_t s) {
+  hipLaunchKernelGGL(k_stick_status, dim3(1), dim3(1), 0, s, c);
+}
+
+void launch_set_frame_args(FrameArgs *fa, int64_t n, int3 Q, int32_t frame, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_frame_args, dim3(1), dim3(1), 0, s, fa, n, Q, frame);
+}
+
+void launch_frame_prep(const float *xyz, const FrameArgs *fa, int64_t nb, const Params &p,
+                       MapDev m, PointsDev pts, FrameScratch fs, FrameCounters *c,
+                       hipStream_t s) {
   hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(1), 0, s, c, m, pts);
-  if (n > 0)
-    hipLaunchKernelGGL(k_frame_prep, dim3(grid_for(n)), dim3(kThreads), 0, s, xyz, n, Q, p, m,
+  if (nb > 0)
+    hipLaunchKernelGGL(k_frame_prep, dim3(grid_for(nb)), dim3(kThreads), 0, s, xyz, fa, p, m,
                        pts, fs, c);
 }
 
-void launch_assign_blocks(MapDev m, FrameScratch fs, FrameCounters *c, int32_t frame,
+void launch_assign_blocks(MapDev m, FrameScratch fs, FrameCounters *c, const FrameArgs *fa,
                           hipStream_t s) {
-  hipLaunchKernelGGL(k_assign_blocks, dim3(4096), dim3(kThreads), 0, s, m, fs, c, frame);
+  hipLaunchKernelGGL(k_assign_blocks, dim3(4096), dim3(kThreads), 0, s, m, fs, c, fa);
 }
 
 void launch_commit_blocks(MapDev m, FrameCounters *c, hipStream_t s) {
   hipLaunchKernelGGL(k_commit_blocks, dim3(1), dim3(1), 0, s, m, c);
 }
 
-void launch_integrate(int64_t n, int3 Q, const Params &p, MapDev m, FrameScratch fs,
-                      FrameCounters *c, GridDev g, int64_t max_touched, hipStream_t s) {
-  if (n > 0) {
-    hipLaunchKernelGGL(k_bin_count, dim3(grid_for(n)), dim3(kThreads), 0, s, n, p, m, fs);
+void launch_integrate(const FrameArgs *fa, int64_t nb, const Params &p, MapDev m,
+                      FrameScratch fs, FrameCounters *c, GridDev g, int64_t max_touched,
+                      hipStream_t s) {
+  if (nb > 0) {
+    hipLaunchKernelGGL(k_bin_count, dim3(grid_for(nb)), dim3(kThreads), 0, s, fa, p, m, fs);
     hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, s, fs, c);
-    hipLaunchKernelGGL(k_bin_fill, dim3(grid_for(n)), dim3(kThreads), 0, s, n, p, m, fs);
+    hipLaunchKernelGGL(k_bin_fill, dim3(grid_for(nb)), dim3(kThreads), 0, s, fa, p, m, fs);
   } else {
     hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, s, fs, c);
   }
   int64_t wg = max_touched < 8192 ? max_touched : 8192;
   if (wg > 0)
-    hipLaunchKernelGGL(k_integrate_fold, dim3((unsigned)wg), dim3(kBlockVox), 0, s, Q, p, m, fs,
-                       c, g);
+    hipLaunchKernelGGL(k_integrate_fold, dim3((unsigned)wg), dim3(kBlockVox), 0, s, fa, p, m,
+                       fs, c, g);
 }
 
-void launch_touch_band(int64_t n, const Params &p, MapDev m, FrameScratch fs,
-                       FrameCounters *c, int32_t frame, hipStream_t s) {
-  if (n > 0)
-    hipLaunchKernelGGL(k_touch_band, dim3(grid_for(n)), dim3(kThreads), 0, s, n, p, m, fs, c,
-                       frame);
+void launch_touch_band(const FrameArgs *fa, int64_t nb, const Params &p, MapDev m,
+                       FrameScratch fs, FrameCounters *c, hipStream_t s) {
+  if (nb > 0)
+    hipLaunchKernelGGL(k_touch_band, dim3(grid_for(nb)), dim3(kThreads), 0, s, fa, p, m, fs,
+                       c);
 }
 
 void launch_points_append(int64_t n_new, MapDev m, PointsDev pts, FrameScratch fs,
-                          FrameCounters *c, int32_t frame, hipStream_t s) {
+                          FrameCounters *c, const FrameArgs *fa, hipStream_t s) {
   if (n_new > 0)
     hipLaunchKernelGGL(k_points_append, dim3(grid_for(n_new)), dim3(kThreads), 0, s, m, pts,
-                       fs, c, frame);
+                       fs, c, fa);
 }
 
 void launch_commit_points(PointsDev pts, FrameCounters *c, hipStream_t s) {
   hipLaunchKernelGGL(k_commit_points, dim3(1), dim3(1), 0, s, pts, c);
 }
 
-void launch_points_view(int64_t n, int3 Q, const Params &p, PointsDev pts, FrameScratch fs,
-                        int32_t frame, hipStream_t s) {
-  if (n > 0)
-    hipLaunchKernelGGL(k_points_view, dim3(grid_for(n)), dim3(kThreads), 0, s, n, Q, p, pts,
-                       fs, frame);
+void launch_points_view(const FrameArgs *fa, int64_t nb, const Params &p, PointsDev pts,
+                        FrameScratch fs, hipStream_t s) {
+  if (nb > 0)
+    hipLaunchKernelGGL(k_points_view, dim3(grid_for(nb)), dim3(kThreads), 0, s, fa, p, pts,
+                       fs);
 }
 
 void launch_grid_fill(GridDev g, hipStream_t s) {

@@ -36,6 +36,7 @@ constexpr uint32_t kUnknownWord = 0xAAAAAAAAu;  // 16 voxels coded "unknown, not
 constexpr int kStatusBlockOverflow = 1;
 constexpr int kStatusPointOverflow = 2;
 constexpr int kStatusHashFull = 4;
+constexpr int kStatusOutsideGrid = 8;   // a block left the fixed grid's margin (recorded frames)
 
 // Constants derived once from af_config (see af_context.hip).
 struct Params {
@@ -67,6 +68,8 @@ struct FrameCounters {
   int32_t n_new_blocks, n_touched, n_new_points, status;
   int32_t bmin[3], bmax[3];
   int32_t blocks_before, points_before;
+  int32_t sticky;   // status bits of recorded frames since the host last looked (not reset per frame)
+  int32_t sbmin[3], sbmax[3];   // block box of those frames (empty when sbmin > sbmax)
   // per-slot fold statistics: [slot][0] applied pairs, [1] cone-excluded
   // pairs, [2] folded voxels (summed on the host; not part of the mid-frame
   // read of the fields above)
@@ -150,6 +153,7 @@ struct GridDev {
   uint32_t *occ1;     // [nbricks * 16] one bit per voxel (linear x | y << 3 | z << 6): TSDF < r_c
   int32_t g0[3];      // block coordinate of brick (0,0,0)
   int32_t gd[3];      // bricks per axis
+  int32_t margin;     // bricks every block keeps from the grid's faces
 };
 
 struct ToolDev {
@@ -218,21 +222,33 @@ struct ToolGeom {     // tool constants in voxel units (host-derived, fp64)
 };
 
 // ---- launchers (stream-ordered) ----
-void launch_frame_prep(const float *xyz, int64_t n, int3 Q, const Params &p,
-                       MapDev m, PointsDev pts, FrameScratch fs,
-                       FrameCounters *c, hipStream_t s);
-void launch_assign_blocks(MapDev m, FrameScratch fs, FrameCounters *c, int32_t frame,
+// Per-frame parameters read by the integration kernels from device memory
+// (so that a recorded frame graph can be replayed with new values).
+struct FrameArgs {
+  int64_t n;      // returns in the frame
+  int3 Q;         // quantised sensor origin
+  int32_t frame;  // frame id
+};
+void launch_set_frame_args(FrameArgs *fa, int64_t n, int3 Q, int32_t frame, hipStream_t s);
+void launch_stick_status(FrameCounters *c, hipStream_t s);
+void launch_zero_words(void *p, int64_t bytes, hipStream_t s);   // a fill kernel (graph-safe)
+// nb: an upper bound of the frame's returns (sizes the launches)
+void launch_frame_prep(const float *xyz, const FrameArgs *fa, int64_t nb, const Params &p,
+                       MapDev m, PointsDev pts, FrameScratch fs, FrameCounters *c,
+                       hipStream_t s);
+void launch_assign_blocks(MapDev m, FrameScratch fs, FrameCounters *c, const FrameArgs *fa,
                           hipStream_t s);
 void launch_commit_blocks(MapDev m, FrameCounters *c, hipStream_t s);
-void launch_integrate(int64_t n, int3 Q, const Params &p, MapDev m, FrameScratch fs,
-                      FrameCounters *c, GridDev g, int64_t max_touched, hipStream_t s);
-void launch_touch_band(int64_t n, const Params &p, MapDev m, FrameScratch fs,
-                       FrameCounters *c, int32_t frame, hipStream_t s);
-void launch_points_append(int64_t n, MapDev m, PointsDev pts, FrameScratch fs,
-                          FrameCounters *c, int32_t frame, hipStream_t s);
+void launch_integrate(const FrameArgs *fa, int64_t nb, const Params &p, MapDev m,
+                      FrameScratch fs, FrameCounters *c, GridDev g, int64_t max_touched,
+                      hipStream_t s);
+void launch_touch_band(const FrameArgs *fa, int64_t nb, const Params &p, MapDev m,
+                       FrameScratch fs, FrameCounters *c, hipStream_t s);
+void launch_points_append(int64_t n_new, MapDev m, PointsDev pts, FrameScratch fs,
+                          FrameCounters *c, const FrameArgs *fa, hipStream_t s);
 void launch_commit_points(PointsDev pts, FrameCounters *c, hipStream_t s);
-void launch_points_view(int64_t n, int3 Q, const Params &p, PointsDev pts,
-                        FrameScratch fs, int32_t frame, hipStream_t s);
+void launch_points_view(const FrameArgs *fa, int64_t nb, const Params &p, PointsDev pts,
+                        FrameScratch fs, hipStream_t s);
 void launch_grid_fill(GridDev g, hipStream_t s);
 void launch_grid_rebuild(const Params &p, MapDev m, GridDev g, int64_t n_blocks,
                          hipStream_t s);
@@ -247,10 +263,12 @@ int launch_table_coarse(int32_t K, const uint32_t *begin, const uint32_t *counts
                         uint32_t *cbegin, uint32_t *centries, uint8_t *cflag, int pass, int sh,
                         hipStream_t s);
 
+// dev_n: the kernels take the point count from the device counter; n_points
+// is then only an upper bound that sizes the launch
 void launch_normals(const Params &p, MapDev m, PointsDev pts, GridDev g,
-                    int64_t n_points, hipStream_t s);
+                    int64_t n_points, hipStream_t s, bool dev_n = false);
 void launch_mask(const Params &p, PointsDev pts, ToolDev t, GridDev g, int64_t n_points,
-                 hipStream_t s);
+                 hipStream_t s, bool dev_n = false);
 // Up to kMultiTools tools scored in one launch: their ids in the context's
 // device mirror of the tool table and the offsets of their begin arrays in
 // the launch's LDS copy (passed by value).
@@ -263,9 +281,9 @@ struct ToolSet {
 int multi_begin_capacity();
 void launch_score_multi(const Params &p, PointsDev pts, const ToolDev *tools_dev,
                         const ToolDev *host_tools, const ToolSet &set, GridDev g, int64_t n,
-                        unsigned *work, hipStream_t s);
+                        unsigned *work, hipStream_t s, bool dev_n = false);
 void launch_score(const Params &p, PointsDev pts, ToolDev t, GridDev g, int64_t n_points,
-                  int variant, unsigned *work, hipStream_t s);
+                  int variant, unsigned *work, hipStream_t s, bool dev_n = false);
 int score_variants();
 int score_variant_default();
 const char *score_variant_name(int v);

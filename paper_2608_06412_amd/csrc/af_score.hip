@@ -58,6 +58,7 @@ __device__ inline int bit_length(uint64_t m) { return m ? 64 - __clzll((long lon
 // 28-bit renormalisation by rounded shifts) as its largest-norm column.
 __global__ void __launch_bounds__(kThreads)
 k_normals(Params p, MapDev m, PointsDev pts, GridDev g, int64_t n) {
+  if (n < 0) n = *pts.n_points;   // the point count on the device (recorded graphs)
   int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= n) return;
   int32_t addr = pts.addr[i];
@@ -278,6 +279,7 @@ constexpr int kMaskStageMw = 8;
 
 __global__ void __launch_bounds__(kThreads)
 k_mask(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t mw, int stage) {
+  if (n < 0) n = *pts.n_points;   // the point count on the device (recorded graphs)
   extern __shared__ uint64_t s_out[];   // [kThreads * mw] mask, then [kThreads * 2 mw] planes
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const bool act = i < n;
@@ -479,6 +481,7 @@ template <int NT, int LK, int AH, int UN, int OCC, int FB>
 __global__ void __launch_bounds__(NT)
 k_score(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t mw,
         unsigned *work) {
+  if (n < 0) n = *pts.n_points;   // the point count on the device (recorded graphs)
   constexpr int NW = NT / 64;
   __shared__ uint32_t s_begin[LK > 0 ? LK + 1 : 1];
   __shared__ uint32_t s_first[LK > 0 ? LK * 64 : 1];
@@ -710,6 +713,7 @@ template <int NT, int E, int UN, int FB, int CO, int B1>
 __global__ void __launch_bounds__(NT)
 k_score_swar(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t mw,
              unsigned *work) {
+  if (n < 0) n = *pts.n_points;   // the point count on the device (recorded graphs)
   static_assert(E >= 1 && E <= 15, "head length must fit the 4-bit planes");
   static_assert(!B1 || E >= 3, "the one-bit plane serves only entries after the arm samples");
   constexpr int NW = NT / 64;
@@ -1046,6 +1050,7 @@ template <int NT, int UN, int FB, int CO, int B1, int DIAG, int PF = 1, int RE =
 __global__ void __launch_bounds__(NT)
 k_score_near(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t mw,
              unsigned *work) {
+  if (n < 0) n = *pts.n_points;   // the point count on the device (recorded graphs)
   constexpr int NW = NT / 64;
   __shared__ uint32_t s_begin[kNearK + 1];
   const int K = t.K;
@@ -1093,6 +1098,7 @@ template <int NT, int UN, int FB, int CO, int B1, int PF, int RE>
 __global__ void __launch_bounds__(NT)
 k_score_near_multi(Params p, PointsDev pts, const ToolDev *tools, ToolSet set, GridDev g,
                    int64_t n, unsigned *work) {
+  if (n < 0) n = *pts.n_points;   // the point count on the device (recorded graphs)
   constexpr int NW = NT / 64;
   extern __shared__ uint32_t s_begin[];   // sized for the set at launch
   for (int ti = 0; ti < set.n; ++ti) {
@@ -1190,21 +1196,21 @@ void init_tables() {
 }  // namespace
 
 void launch_normals(const Params &p, MapDev m, PointsDev pts, GridDev g, int64_t n,
-                    hipStream_t s) {
+                    hipStream_t s, bool dev_n) {
   init_tables();
   if (n <= 0) return;
   hipLaunchKernelGGL(k_normals, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads),
-                     0, s, p, m, pts, g, n);
+                     0, s, p, m, pts, g, dev_n ? (int64_t)-1 : n);
 }
 
 void launch_mask(const Params &p, PointsDev pts, ToolDev t, GridDev g, int64_t n,
-                 hipStream_t s) {
+                 hipStream_t s, bool dev_n) {
   int32_t mw = (t.K + 63) / 64;
   if (n <= 0) return;
   const int stage = mw <= kMaskStageMw ? 1 : 0;
   const size_t lds = stage ? sizeof(uint64_t) * kThreads * 3 * mw : 0;
   hipLaunchKernelGGL(k_mask, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads),
-                     lds, s, p, pts, t, g, n, mw, stage);
+                     lds, s, p, pts, t, g, dev_n ? (int64_t)-1 : n, mw, stage);
 }
 
 int score_variants() { return kNumVariants; }
@@ -1228,7 +1234,7 @@ int multi_begin_capacity() { return kMultiBegin; }
 // like set.id) in one persistent launch.
 void launch_score_multi(const Params &p, PointsDev pts, const ToolDev *tools_dev,
                         const ToolDev *host_tools, const ToolSet &set, GridDev g, int64_t n,
-                        unsigned *work, hipStream_t s) {
+                        unsigned *work, hipStream_t s, bool dev_n) {
   if (n <= 0 || set.n <= 0) return;
   bool rel = true;
   for (int i = 0; i < set.n; ++i) rel = rel && host_tools[i].rent != nullptr;
@@ -1255,12 +1261,12 @@ void launch_score_multi(const Params &p, PointsDev pts, const ToolDev *tools_dev
   const int64_t need = (n * set.n + 3) / 4;
   if (wg > need) wg = need;
   hipLaunchKernelGGL(k_zero, dim3(1), dim3(1), 0, s, work);
-  hipLaunchKernelGGL(fn, dim3((unsigned)wg), dim3(256), lds, s, p, pts, tools_dev, set, g, n,
-                     work);
+  hipLaunchKernelGGL(fn, dim3((unsigned)wg), dim3(256), lds, s, p, pts, tools_dev, set, g,
+                     dev_n ? (int64_t)-1 : n, work);
 }
 
 void launch_score(const Params &p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int variant,
-                  unsigned *work, hipStream_t s) {
+                  unsigned *work, hipStream_t s, bool dev_n) {
   int32_t mw = (t.K + 63) / 64;
   if (n <= 0) return;
   if (variant < 0 || variant >= kNumVariants) variant = 0;
@@ -1287,7 +1293,8 @@ void launch_score(const Params &p, PointsDev pts, ToolDev t, GridDev g, int64_t 
   int64_t need = (n + nw - 1) / nw;
   if (wg > need) wg = need;
   hipLaunchKernelGGL(k_zero, dim3(1), dim3(1), 0, s, work);
-  hipLaunchKernelGGL(v.fn, dim3((unsigned)wg), dim3(v.threads), 0, s, p, pts, t, g, n, mw, work);
+  hipLaunchKernelGGL(v.fn, dim3((unsigned)wg), dim3(v.threads), 0, s, p, pts, t, g,
+                     dev_n ? (int64_t)-1 : n, mw, work);
 }
 
 }  // namespace af

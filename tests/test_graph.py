@@ -1,0 +1,144 @@
+"""Recorded frame pipeline (af_graph_prepare / af_graph_frame): every replay
+of the per-frame graph -- integration of the frame, then normals, masks and
+one-launch scoring of four tools -- leaves the map, the points, the labels,
+first free orientations and statistics exactly as af_integrate_frame followed
+by af_score_tools does, frame by frame.  Replays take frames of varying size,
+with eager work, host reads and synchronisations between them, and one frame
+in the middle goes through the eager calls on the same context.  A frame that
+maps a block beyond the recorded scene box is reported, and the context then
+continues eagerly to the same result.  Tiny scene (v = 2 cm), four tools of
+the batching workload."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+STAT_KEYS = ("n_points", "n_confident", "n_accessible", "n_blocked", "n_no_candidate",
+             "candidate_tests", "canonical_tests", "canonical_lookups", "arm_lookups")
+FRAME_KEYS = ("n_in", "n_valid", "n_dropped", "pairs_applied", "pairs_excluded",
+              "band_marks", "new_points", "n_points", "voxels_folded", "n_blocks",
+              "new_blocks")
+IDS = [0, 1, 2, 3]
+
+
+def _setup(synth_mod):
+    from paper_2608_06412_amd import Context, default_config
+    w = synth_mod.tiny()
+    frames = w.frames()
+    tools = synth_mod.batch_tools()[:4]
+    rots = [synth_mod.orientations(synth_mod.fibonacci_directions(128), 4),
+            synth_mod.orientations(synth_mod.fibonacci_directions(64), 1),
+            synth_mod.orientations(synth_mod.yaw_directions(70), 1),
+            synth_mod.orientations(synth_mod.fibonacci_directions(32), 8)]
+    cfg = default_config(w.voxel, w.trunc, r_c=w.r_c, max_blocks=1 << 15, max_points=1 << 17,
+                         max_orientations=512, max_tools=4)
+
+    def make():
+        ctx = Context(cfg)
+        for i, (tl, r) in enumerate(zip(tools, rots)):
+            ctx.set_tool_kernels(i, tl, r)
+        return ctx
+    # frames of uneven size: a seeded prefix of each frame's returns
+    rng = np.random.default_rng(5)
+    sizes = [int(rng.integers(len(f.xyz) // 4, len(f.xyz) + 1)) for f in frames]
+    return w, frames, sizes, make
+
+
+def _same_scores(a, b, where):
+    assert a.num_points() == b.num_points(), where
+    assert a.num_blocks() == b.num_blocks(), where
+    for i in IDS:
+        la, lb = a.read_labels(i), b.read_labels(i)
+        assert np.array_equal(la["key"], lb["key"]), (where, i)
+        assert np.array_equal(la["label"], lb["label"]), (where, i)
+        assert np.array_equal(la["first_free"], lb["first_free"]), (where, i)
+        sa, sb = a.score_stats(i), b.score_stats(i)
+        for k in STAT_KEYS:
+            assert sa[k] == sb[k], (where, i, k)
+
+
+def _same_map(a, b):
+    for x, y in zip(a.read_tsdf(), b.read_tsdf()):
+        assert np.array_equal(x, y)
+    pa, pb = a.read_points(), b.read_points()
+    for k in pa:
+        assert np.array_equal(pa[k], pb[k]), k
+
+
+def test_replays_equal_eager(synth_mod):
+    import torch
+    assert torch.cuda.is_available()
+    w, frames, sizes, make = _setup(synth_mod)
+    eager, rec = make(), make()
+    allx = np.concatenate([f.xyz for f in frames])
+    lo, hi = allx.min(0) - 0.5, allx.max(0) + 0.5
+    rec.graph_prepare(lo, hi, max(sizes), IDS)
+    assert rec.graph_slot() != 0
+    scratch = torch.zeros(1 << 20, device="cuda")
+    for j, (f, n) in enumerate(zip(frames, sizes)):
+        print("frame", j, "n", n, flush=True)
+        x = torch.from_numpy(np.ascontiguousarray(f.xyz[:n])).cuda()
+        eager.integrate_frame(x, f.origin, f.frame_id)
+        eager.score_tools(IDS)
+        if j == len(frames) // 2:
+            rec.integrate_frame(x, f.origin, f.frame_id)   # an eager frame between replays
+            rec.score_tools(IDS)
+        else:
+            rec.graph_frame(x, f.origin, f.frame_id)
+            scratch.mul_(0.5).add_(1.0)                     # unrelated eager work on the stream
+            if j % 3 == 0:
+                torch.cuda.synchronize()
+            rec.graph_sync()
+            fe, fr = eager.frame_stats(), rec.frame_stats()
+            for k in FRAME_KEYS:
+                assert fe[k] == fr[k], (j, k)
+        _same_scores(eager, rec, j)
+    _same_map(eager, rec)
+
+
+def test_block_outside_box_reported(synth_mod):
+    import torch
+    from paper_2608_06412_amd import AFError
+    w, frames, sizes, make = _setup(synth_mod)
+    eager, rec = make(), make()
+    o = np.asarray(frames[0].origin, np.float64)
+    rec.graph_prepare(o - 0.05, o + 0.05, len(frames[0].xyz), IDS)
+    f = frames[0]
+    x = torch.from_numpy(f.xyz).cuda()
+    rec.graph_frame(x, f.origin, f.frame_id)
+    with pytest.raises(AFError):
+        rec.graph_sync()
+    with pytest.raises(AFError):
+        rec.graph_frame(torch.from_numpy(frames[1].xyz).cuda(), frames[1].origin,
+                        frames[1].frame_id)
+    eager.integrate_frame(x, f.origin, f.frame_id)
+    for f in frames[1:4]:
+        x = torch.from_numpy(f.xyz).cuda()
+        eager.integrate_frame(x, f.origin, f.frame_id)
+        rec.integrate_frame(x, f.origin, f.frame_id)
+    eager.score_tools(IDS)
+    rec.score_tools(IDS)
+    _same_scores(eager, rec, "after")
+    _same_map(eager, rec)
+
+
+def test_graph_argument_errors(synth_mod):
+    import torch
+    from paper_2608_06412_amd import AFError
+    w, frames, sizes, make = _setup(synth_mod)
+    ctx = make()
+    f = frames[0]
+    x = torch.from_numpy(f.xyz).cuda()
+    with pytest.raises(AFError):
+        ctx.graph_frame(x, f.origin, f.frame_id)          # nothing recorded
+    with pytest.raises(AFError):
+        ctx.graph_prepare([0, 0, 0], [1, 1, 1], 100, [0, 0])
+    with pytest.raises(AFError):
+        ctx.graph_prepare([1, 0, 0], [0, 1, 1], 100, IDS)
+    ctx.graph_prepare([-3, -3, -1], [3, 3, 3], 100, IDS)
+    with pytest.raises(AFError):
+        ctx.graph_frame(x, f.origin, f.frame_id)          # larger than recorded
+    ctx.graph_frame(x[:100].contiguous(), f.origin, f.frame_id)
+    with pytest.raises(AFError):
+        ctx.graph_frame(x[:100].contiguous(), f.origin, f.frame_id)   # id not increasing
+    ctx.graph_sync()
