@@ -127,6 +127,7 @@ int alloc_scratch(af_ctx *c, int64_t cap) {
     dev_free(c, f.pslot, sizeof(int32_t) * f.cap);
     dev_free(c, f.new_blocks, sizeof(int32_t) * f.cap * (kMaxSpan + kMaxBand));
     dev_free(c, f.new_keys, sizeof(int64_t) * f.cap);
+    dev_free(c, f.new_sorted, sizeof(int64_t) * ((f.cap + 255) / 256 * 256));
     dev_free(c, f.new_kslot, sizeof(int32_t) * f.cap);
     dev_free(c, f.touched, sizeof(int32_t) * f.cap * (kMaxSpan + kMaxBand));
     dev_free(c, f.bin_cnt, sizeof(int32_t) * f.cap * (kMaxSpan + kMaxBand));
@@ -141,6 +142,7 @@ int alloc_scratch(af_ctx *c, int64_t cap) {
   ALLOC(c, f.pslot, cap);
   ALLOC(c, f.new_blocks, cap * (kMaxSpan + kMaxBand));
   ALLOC(c, f.new_keys, cap);
+  ALLOC(c, f.new_sorted, (cap + 255) / 256 * 256);
   ALLOC(c, f.new_kslot, cap);
   ALLOC(c, f.touched, cap * (kMaxSpan + kMaxBand));
   ALLOC(c, f.bin_cnt, cap * (kMaxSpan + kMaxBand));

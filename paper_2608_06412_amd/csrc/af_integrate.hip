@@ -283,6 +283,34 @@ k_touch_band(const FrameArgs *fa, Params p, MapDev m, FrameScratch fs, FrameCoun
 // ---------------------------------------------------------------- points
 // New point keys of the frame get ids in ascending key order (rank by
 // counting smaller keys), are initialised and flagged in their block.
+// New points are appended in key order.  Each workgroup first sorts its
+// tile of (distinct) new keys in LDS with Batcher's bitonic network; a key's
+// rank among all new keys is then the sum of its lower bounds in the tiles.
+__global__ void __launch_bounds__(kThreads)
+k_sort_new_tiles(FrameScratch fs, const FrameCounters *c) {
+  static_assert((kThreads & (kThreads - 1)) == 0, "bitonic tile needs a power of two");
+  __shared__ int64_t v[kThreads];
+  const int m = c->n_new_points;
+  const int base = blockIdx.x * kThreads;
+  if (base >= m) return;
+  const int t = threadIdx.x;
+  v[t] = base + t < m ? fs.new_keys[base + t] : (int64_t)0x7fffffffffffffffLL;
+  __syncthreads();
+  for (int k = 2; k <= kThreads; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const int q = t ^ j;
+      if (q > t) {
+        const int64_t a = v[t], b = v[q];
+        if ((a > b) == ((t & k) == 0)) {
+          v[t] = b;
+          v[q] = a;
+        }
+      }
+      __syncthreads();
+    }
+  fs.new_sorted[base + t] = v[t];
+}
+
 __global__ void __launch_bounds__(kThreads)
 k_points_append(MapDev m, PointsDev pts, FrameScratch fs, FrameCounters *c, const FrameArgs *fa) {
   const int32_t frame = fa->frame;
@@ -294,11 +322,15 @@ k_points_append(MapDev m, PointsDev pts, FrameScratch fs, FrameCounters *c, cons
   int rank = 0;
   for (int base = 0; base < mcount; base += kThreads) {
     __syncthreads();
-    tile[threadIdx.x] = base + (int)threadIdx.x < mcount ? fs.new_keys[base + threadIdx.x]
-                                                         : (int64_t)0x7fffffffffffffffLL;
+    tile[threadIdx.x] = fs.new_sorted[base + threadIdx.x];
     __syncthreads();
-    int lim = mcount - base < kThreads ? mcount - base : kThreads;
-    for (int j = 0; j < lim; ++j) rank += tile[j] < key;
+    int lo = 0, hi = mcount - base < kThreads ? mcount - base : kThreads;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (tile[mid] < key) lo = mid + 1;
+      else hi = mid;
+    }
+    rank += lo;
   }
   if (i >= mcount) return;
   int64_t id = (int64_t)*pts.n_points + rank;
@@ -704,9 +736,11 @@ void launch_touch_band(const FrameArgs *fa, int64_t nb, const Params &p, MapDev 
 
 void launch_points_append(int64_t n_new, MapDev m, PointsDev pts, FrameScratch fs,
                           FrameCounters *c, const FrameArgs *fa, hipStream_t s) {
-  if (n_new > 0)
+  if (n_new > 0) {
+    hipLaunchKernelGGL(k_sort_new_tiles, dim3(grid_for(n_new)), dim3(kThreads), 0, s, fs, c);
     hipLaunchKernelGGL(k_points_append, dim3(grid_for(n_new)), dim3(kThreads), 0, s, m, pts,
                        fs, c, fa);
+  }
 }
 
 void launch_commit_points(PointsDev pts, FrameCounters *c, hipStream_t s) {

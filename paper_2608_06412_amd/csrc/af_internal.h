@@ -136,6 +136,7 @@ struct FrameScratch {
   int32_t *pslot;     // [cap] point hash slot
   int32_t *new_blocks;// [cap * (kMaxSpan + kMaxBand)] hash slots of new blocks
   int64_t *new_keys;  // [cap] new point keys
+  int64_t *new_sorted;  // [cap rounded up to 256] the new keys, sorted within each 256-key tile
   int32_t *new_kslot; // [cap] their hash slots
   int32_t *touched;   // [cap * (kMaxSpan + kMaxBand)] touched block ids
   int32_t *bin_cnt;   // [cap * (kMaxSpan + kMaxBand)] returns per touched block

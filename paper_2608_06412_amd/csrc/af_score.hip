@@ -280,6 +280,7 @@ constexpr int kMaskStageMw = 8;
 __global__ void __launch_bounds__(kThreads)
 k_mask(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t mw, int stage) {
   if (n < 0) n = *pts.n_points;   // the point count on the device (recorded graphs)
+  if ((int64_t)blockIdx.x * kThreads >= n) return;   // whole workgroup past the end
   extern __shared__ uint64_t s_out[];   // [kThreads * mw] mask, then [kThreads * 2 mw] planes
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const bool act = i < n;
