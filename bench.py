@@ -244,6 +244,190 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def run_serve(args):
+    """Serving workload: four concurrent streams (trees and box clusters, own
+    tools at 256 orientations, frames of 5,000-40,000 returns at 10 Hz, TSDF
+    capacity 2e8 voxels each) admitted by a 24 GiB device budget (6 GiB per
+    stream; a fifth stream is refused).  Frames 0..W-1 warm up; W..W+K-1 are
+    run back to back, one frame of every stream per server step, against the
+    plain sequential path (per frame: integrate, score, wait) on four other
+    contexts; W+K..W+K+L-1 arrive at 10 Hz from each stream's phase, and the
+    latency of each frame runs from its arrival to its labels on the host."""
+    import torch
+    import synth
+    from paper_2608_06412_amd import AFError, Context, Server, default_config
+
+    W = args.warmup if args.warmup != 100 else 20
+    K = args.steps if args.steps != 400 else 40
+    L = args.latency_frames if args.latency_frames != 100 else 60
+    n = W + K + L
+    specs = synth.serving(n_streams=4, n_frames=n)
+    t = time.perf_counter()
+    frames = [sp.workload.frames(n) for sp in specs]
+    log("generated 4 x %d frames in %.1f s" % (n, time.perf_counter() - t))
+    torch.cuda.set_device(0)
+    GiB = 1 << 30
+
+    def cfg(budget):
+        w = specs[0].workload
+        c = default_config(w.voxel, w.trunc, r_c=w.r_c, max_blocks=390625, max_points=1 << 22,
+                           max_orientations=256, max_tools=1)
+        c.hbm_budget = int(budget)
+        return c
+    srv = Server(24 * GiB, max_streams=5)
+    sids = [srv.admit(cfg(6 * GiB)) for _ in specs]
+    try:
+        srv.admit(cfg(6 * GiB))
+        refused = False
+    except AFError:
+        refused = True
+    seq = []
+    for s, sp in enumerate(specs):
+        w = sp.workload
+        allx = np.concatenate([f.xyz for f in frames[s]])
+        srv.context(sids[s]).set_tool_kernels(0, w.tool, w.rot)
+        srv.prepare(sids[s], allx.min(0) - 1.0, allx.max(0) + 1.0,
+                    max(len(f.xyz) for f in frames[s]), [0])
+        c = Context(cfg(0))
+        c.set_tool_kernels(0, w.tool, w.rot)
+        seq.append(c)
+    resident = [[torch.from_numpy(f.xyz).cuda() for f in fr[:W + K]] for fr in frames]
+
+    def serve_frames(lo, hi):
+        tests = 0
+        for k in range(lo, hi):
+            for s, sid in enumerate(sids):
+                f = frames[s][k]
+                srv.submit(sid, f.xyz, f.origin, f.frame_id)
+            for sid, fid, st in srv.step():
+                if st != 0:
+                    raise RuntimeError("stream %d frame %d: %s" % (sid, fid, srv.last_error()))
+                tests += srv.context(sid).score_stats(0)["canonical_tests"]
+        return tests
+
+    def seq_frames(lo, hi):
+        tests = 0
+        for k in range(lo, hi):
+            for s, c in enumerate(seq):
+                f = frames[s][k]
+                c.integrate_frame(resident[s][k], f.origin, f.frame_id)
+                c.score_points(0)
+                tests += c.score_stats(0)["canonical_tests"]
+        return tests
+    serve_frames(0, W)
+    seq_frames(0, W)
+    log("warm-up done; points per stream %s" % [srv.context(i).num_points() for i in sids])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tests_srv = serve_frames(W, W + K)
+    wall_srv = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    tests_seq = seq_frames(W, W + K)
+    torch.cuda.synchronize()
+    wall_seq = time.perf_counter() - t0
+    same = all(np.array_equal(srv.context(sid).read_labels(0)["label"], seq[s].read_labels(0)["label"])
+               and np.array_equal(srv.context(sid).read_labels(0)["first_free"],
+                                  seq[s].read_labels(0)["first_free"])
+               for s, sid in enumerate(sids))
+    returns = sum(len(frames[s][k].xyz) for s in range(4) for k in range(W, W + K))
+    log("throughput: server %.1f ms per 4 frames, sequential %.1f" %
+        (wall_srv / K * 1e3, wall_seq / K * 1e3))
+
+    # paced: every stream at 10 Hz from its phase
+    def paced(run_one_step):
+        arr = sorted((specs[s].phase + 0.1 * j, s, W + K + j) for s in range(4) for j in range(L))
+        lat = []
+        i = 0
+        t0 = time.perf_counter() + 0.05
+        while i < len(arr) or run_one_step(None, peek=True):
+            now = time.perf_counter() - t0
+            while i < len(arr) and arr[i][0] <= now:
+                run_one_step(arr[i])
+                i += 1
+            done = run_one_step(None)
+            if done:
+                end = time.perf_counter() - t0
+                lat += [end - a for a in done]
+            elif i < len(arr):
+                time.sleep(max(0.0, min(0.002, arr[i][0] - (time.perf_counter() - t0))))
+        return np.array(lat) * 1e3
+
+    queue = []
+
+    def srv_step(item, peek=False):
+        if peek:
+            return any(srv.pending(sid) for sid in sids)
+        if item is not None:
+            a, s, k = item
+            f = frames[s][k]
+            srv.submit(sids[s], f.xyz, f.origin, f.frame_id)
+            queue.append((s, f.frame_id, a))
+            return None
+        if not any(srv.pending(sid) for sid in sids):
+            return []
+        done = []
+        for sid, fid, st in srv.step():
+            if st != 0:
+                raise RuntimeError("stream %d frame %d: %s" % (sid, fid, srv.last_error()))
+            s = sids.index(sid)
+            srv.context(sid).read_labels(0)
+            j = next(j for j, q in enumerate(queue) if q[0] == s and q[1] == fid)
+            done.append(queue.pop(j)[2])
+        return done
+    lat_srv = paced(srv_step)
+    waiting = []
+    pinned = {(s, k): torch.from_numpy(frames[s][k].xyz).pin_memory()
+              for s in range(4) for k in range(W + K, n)}
+
+    def seq_step(item, peek=False):
+        if peek:
+            return bool(waiting)
+        if item is not None:
+            waiting.append(item)
+            return None
+        if not waiting:
+            return []
+        a, s, k = waiting.pop(0)
+        f = frames[s][k]
+        x = pinned[(s, k)].cuda(non_blocking=True)
+        seq[s].integrate_frame(x, f.origin, f.frame_id)
+        seq[s].score_points(0)
+        seq[s].read_labels(0)
+        return [a]
+    lat_seq = paced(seq_step)
+    same_end = all(np.array_equal(srv.context(sid).read_labels(0)["label"],
+                                  seq[s].read_labels(0)["label"]) for s, sid in enumerate(sids))
+    pct = lambda v, q: float(np.percentile(v, q))
+    out = {
+        "metric": "frame latency p50/p99 and throughput, 4 concurrent streams at 10 Hz",
+        "value": pct(lat_srv, 99),
+        "unit": "ms (p99 frame latency, arrival to labels on the host)",
+        "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": wall_srv / K * 1e3,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int64", "data": "synthetic",
+        "config": {"workload": "serve: 4 streams (2 procedural trees, 2 box clusters), own tool "
+                               "each at 256 orientations, frames of 5,000-40,000 returns at 10 Hz, "
+                               "TSDF capacity 2e8 voxels per stream",
+                   "frames_per_stream": {"warmup": W, "throughput": K, "paced": L},
+                   "map_points_end": [int(srv.context(i).num_points()) for i in sids]},
+        "admission": {"budget_bytes": 24 * GiB, "per_stream_bytes": 6 * GiB, "admitted": len(sids),
+                      "fifth_refused": refused,
+                      "device_bytes": [int(srv.context(i).device_bytes()) for i in sids]},
+        "latency_ms": {"p50": pct(lat_srv, 50), "p99": pct(lat_srv, 99), "max": float(lat_srv.max()),
+                       "frames": int(len(lat_srv))},
+        "sequential_latency_ms": {"p50": pct(lat_seq, 50), "p99": pct(lat_seq, 99),
+                                  "max": float(lat_seq.max())},
+        "throughput": {"frames_per_s": 4 * K / wall_srv, "returns_per_s": returns / wall_srv,
+                       "tests_per_s": tests_srv / wall_srv,
+                       "sequential_frames_per_s": 4 * K / wall_seq,
+                       "sequential_tests_per_s": tests_seq / wall_seq,
+                       "speedup": wall_seq / wall_srv, "same_tests": bool(tests_srv == tests_seq),
+                       "labels_identical": bool(same), "labels_identical_after_paced": bool(same_end)},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -258,7 +442,7 @@ def main():
     ap.add_argument("--score-variant", default=None,
                     help="scoring configuration (index or name) when not tuning; default: "
                          "the library's default configuration")
-    ap.add_argument("--workload", default="tree", choices=["tree", "batch"],
+    ap.add_argument("--workload", default="tree", choices=["tree", "batch", "serve"],
                     help="tree: the default single-tool workload; batch: 8 tools x 512 "
                          "orientations scored in one launch, frames of 5k-40k returns")
     ap.add_argument("--trace-summary", default=None,
@@ -292,6 +476,8 @@ def main():
     from paper_2608_06412_amd import Context, default_config
 
     synth.build(force=False)
+    if args.workload == "serve":
+        return run_serve(args)
     if args.workload == "batch":
         run_batch(args)
         return

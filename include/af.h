@@ -44,7 +44,8 @@ enum {
   AF_ENOMEM = -2,    /* device memory or HBM budget exhausted */
   AF_EDEVICE = -3,   /* HIP runtime error */
   AF_ENOTOOL = -4,   /* tool id never set */
-  AF_EOVERFLOW = -5  /* block / point capacity exceeded (state is then incomplete) */
+  AF_EOVERFLOW = -5, /* block / point capacity exceeded (state is then incomplete) */
+  AF_EBUSY = -6      /* a server's stream slots or a stream's frame queue are full */
 };
 
 /* point labels */
@@ -293,6 +294,54 @@ int af_graph_frame(af_ctx *ctx, const float *xyz, int64_t n, const float origin[
                    int64_t frame_id, void *stream);
 float *af_graph_slot(af_ctx *ctx);
 int af_graph_sync(af_ctx *ctx);
+
+/* Serving several concurrent sensor streams (the real-time frame budget of
+ * Section 3.6, for several sensors on one GPU).
+ *
+ * A server admits streams against a device budget: af_server_admit creates a
+ * context from `cfg`, whose hbm_budget (> 0, bytes) is reserved against the
+ * server's `hbm_budget`; AF_ENOMEM when it does not fit (nothing is
+ * allocated then), AF_EBUSY when all `max_streams` (1..64) slots are taken.
+ * Each stream keeps its map on the device until af_server_release, which also
+ * returns its reservation.  af_server_context gives the stream's context (for
+ * af_set_tool_kernels, af_read_labels and the other calls; the server owns
+ * it) and af_server_hip_stream its HIP stream (non-blocking, default
+ * priority), on which all of its frames run.
+ *
+ * af_server_prepare records the stream's frame graph (af_graph_prepare: scene
+ * box lo/hi in metres, up to max_returns returns per frame, tools tool_ids)
+ * and allocates four pinned host slots of max_returns returns; frames still
+ * queued are dropped.  af_server_submit copies a frame (host xyz, n x 3
+ * float) into a free slot and queues it: AF_EBUSY when four frames already
+ * wait, AF_EINVAL for a stream without a recorded graph, n above max_returns
+ * or a frame id that does not increase.  af_server_pending gives the queue
+ * length (-1 for a bad id).
+ *
+ * af_server_step takes the oldest queued frame of every stream (streams
+ * visited round robin), launches each (host-to-device copy, then the recorded
+ * frame) on its own HIP stream so that the GPU overlaps them, then waits for
+ * all of them and writes, for each frame processed, its stream id, frame id
+ * and status (AF_OK, or the code af_graph_sync / af_graph_frame gave; a failed
+ * frame is consumed) into the caller's arrays of `cap` >= max_streams
+ * entries, and their number into *n_done.  Returns AF_EINVAL if the arrays
+ * are too small, else AF_OK.  Not thread-safe: one host thread drives a
+ * server. */
+typedef struct af_server af_server;
+int af_server_create(int64_t hbm_budget, int32_t max_streams, af_server **out);
+int af_server_destroy(af_server *srv);
+const char *af_server_last_error(af_server *srv);
+int64_t af_server_reserved(af_server *srv);
+int af_server_admit(af_server *srv, const af_config *cfg, int32_t *stream_id);
+int af_server_release(af_server *srv, int32_t stream_id);
+af_ctx *af_server_context(af_server *srv, int32_t stream_id);
+void *af_server_hip_stream(af_server *srv, int32_t stream_id);
+int af_server_prepare(af_server *srv, int32_t stream_id, const float lo[3], const float hi[3],
+                      int64_t max_returns, const int32_t *tool_ids, int32_t n_tools);
+int af_server_submit(af_server *srv, int32_t stream_id, const float *xyz, int64_t n,
+                     const float origin[3], int64_t frame_id);
+int32_t af_server_pending(af_server *srv, int32_t stream_id);
+int af_server_step(af_server *srv, int32_t *stream_ids, int64_t *frame_ids, int32_t *status,
+                   int32_t cap, int32_t *n_done);
 
 #ifdef __cplusplus
 }

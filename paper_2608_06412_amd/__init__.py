@@ -7,4 +7,4 @@ kernels), ``score_points`` (label every confident surface point) and
 arguments.
 """
 from .af import (ACCESSIBLE, BLOCKED, NO_CANDIDATE, UNSCORED, AFError, Context,  # noqa: F401
-                 default_config, lib, load_library)
+                 Server, default_config, lib, load_library)

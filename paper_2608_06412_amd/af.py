@@ -16,13 +16,13 @@ import numpy as np
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libaf.so")
 
-AF_OK, AF_EINVAL, AF_ENOMEM, AF_EDEVICE, AF_ENOTOOL, AF_EOVERFLOW = 0, -1, -2, -3, -4, -5
+AF_OK, AF_EINVAL, AF_ENOMEM, AF_EDEVICE, AF_ENOTOOL, AF_EOVERFLOW, AF_EBUSY = 0, -1, -2, -3, -4, -5, -6
 UNSCORED, ACCESSIBLE, BLOCKED, NO_CANDIDATE = 0, 1, 2, 3
 CLS_BODY, CLS_NEAR, CLS_FAR = 0, 1, 2
 TOOL_CYLINDER, TOOL_BOX = 0, 1
 
 _ERRNAMES = {AF_EINVAL: "AF_EINVAL", AF_ENOMEM: "AF_ENOMEM", AF_EDEVICE: "AF_EDEVICE",
-             AF_ENOTOOL: "AF_ENOTOOL", AF_EOVERFLOW: "AF_EOVERFLOW"}
+             AF_ENOTOOL: "AF_ENOTOOL", AF_EOVERFLOW: "AF_EOVERFLOW", AF_EBUSY: "AF_EBUSY"}
 
 
 class AFError(RuntimeError):
@@ -114,6 +114,22 @@ SIGNATURES = {
                                       ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     "af_graph_slot": (ctypes.c_void_p, [ctypes.c_void_p]),
     "af_graph_sync": (ctypes.c_int, [ctypes.c_void_p]),
+    "af_server_create": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p]),
+    "af_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "af_server_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "af_server_reserved": (ctypes.c_int64, [ctypes.c_void_p]),
+    "af_server_admit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "af_server_release": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "af_server_context": (ctypes.c_void_p, [ctypes.c_void_p, ctypes.c_int32]),
+    "af_server_hip_stream": (ctypes.c_void_p, [ctypes.c_void_p, ctypes.c_int32]),
+    "af_server_prepare": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                         ctypes.c_int32]),
+    "af_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                        ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64]),
+    "af_server_pending": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
+    "af_server_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "af_score_variant_name": (ctypes.c_char_p, [_i32]),
     "af_set_score_variant": (ctypes.c_int, [_vp, _i32]),
     "af_get_score_variant": (_i32, [_vp]),
@@ -190,7 +206,17 @@ class Context:
         self.h = h
         self.K = {}
 
+    @classmethod
+    def _borrow(cls, lib_, handle, cfg, owner):
+        """A context owned by a Server (not destroyed by this object)."""
+        self = cls.__new__(cls)
+        self._lib, self.cfg, self.h, self.K, self._owner = lib_, cfg, handle, {}, owner
+        return self
+
     def close(self):
+        if getattr(self, "_owner", None) is not None:
+            self.h = None
+            return
         if getattr(self, "h", None):
             self._lib.af_destroy(self.h)
             self.h = None
@@ -379,3 +405,89 @@ class Context:
         st = ScoreStats()
         self._check(self._lib.af_score_stats_get(self.h, int(tool_id), ctypes.byref(st)))
         return st.as_dict()
+
+
+class Server:
+    """Several sensor streams on one GPU (af_server): admission by device
+    budget, one context, HIP stream, recorded frame graph and frame queue per
+    stream, and a step that runs the oldest queued frame of every stream."""
+
+    def __init__(self, hbm_budget: int, max_streams: int = 4):
+        self._lib = lib()
+        h = ctypes.c_void_p()
+        rc = self._lib.af_server_create(int(hbm_budget), int(max_streams), ctypes.byref(h))
+        if rc != AF_OK:
+            raise AFError(rc, "af_server_create failed")
+        self.h = h
+        self.max_streams = int(max_streams)
+        self._ctx = {}
+
+    def close(self):
+        if getattr(self, "h", None):
+            for c in self._ctx.values():
+                c.h = None
+            self._ctx.clear()
+            self._lib.af_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != AF_OK:
+            raise AFError(rc, self._lib.af_server_last_error(self.h).decode())
+
+    def reserved(self) -> int:
+        return int(self._lib.af_server_reserved(self.h))
+
+    def admit(self, cfg: Config) -> int:
+        sid = ctypes.c_int32()
+        self._check(self._lib.af_server_admit(self.h, ctypes.byref(cfg), ctypes.byref(sid)))
+        handle = ctypes.c_void_p(self._lib.af_server_context(self.h, sid.value))
+        self._ctx[sid.value] = Context._borrow(self._lib, handle, cfg, self)
+        return sid.value
+
+    def release(self, sid: int):
+        self._check(self._lib.af_server_release(self.h, int(sid)))
+        c = self._ctx.pop(int(sid), None)
+        if c is not None:
+            c.h = None
+
+    def context(self, sid: int) -> Context:
+        return self._ctx[int(sid)]
+
+    def hip_stream(self, sid: int) -> int:
+        return int(self._lib.af_server_hip_stream(self.h, int(sid)) or 0)
+
+    def prepare(self, sid: int, lo, hi, max_returns: int, tool_ids):
+        lo = np.ascontiguousarray(lo, dtype=np.float32).reshape(3)
+        hi = np.ascontiguousarray(hi, dtype=np.float32).reshape(3)
+        ids = (ctypes.c_int32 * len(tool_ids))(*[int(x) for x in tool_ids])
+        self._check(self._lib.af_server_prepare(self.h, int(sid), _p(lo), _p(hi),
+                                                int(max_returns), ids, len(tool_ids)))
+
+    def submit(self, sid: int, xyz, origin, frame_id: int):
+        """xyz: host float32 array [n, 3]; it is copied before the call returns."""
+        x = np.ascontiguousarray(xyz, dtype=np.float32).reshape(-1, 3)
+        o = np.ascontiguousarray(origin, dtype=np.float32).reshape(3)
+        self._check(self._lib.af_server_submit(self.h, int(sid), _p(x), len(x), _p(o),
+                                               int(frame_id)))
+
+    def pending(self, sid: int) -> int:
+        return int(self._lib.af_server_pending(self.h, int(sid)))
+
+    def step(self):
+        """Run the oldest queued frame of every stream; [(stream, frame id, status)]."""
+        n = self.max_streams
+        sids = (ctypes.c_int32 * n)()
+        fids = (ctypes.c_int64 * n)()
+        st = (ctypes.c_int32 * n)()
+        nd = ctypes.c_int32()
+        self._check(self._lib.af_server_step(self.h, sids, fids, st, n, ctypes.byref(nd)))
+        return [(sids[i], fids[i], st[i]) for i in range(nd.value)]
+
+    def last_error(self) -> str:
+        return self._lib.af_server_last_error(self.h).decode()

@@ -405,3 +405,34 @@ def batch(n_frames: int = 600, seed: int = 5, counts_seed: int = 9) -> Workload:
     w.n_hits = uneven_counts(max(600, n_frames), seed=counts_seed)
     w.rot = orientations(fibonacci_directions(128), 4)
     return w
+
+
+@dataclass
+class ServeStream:
+    workload: Workload
+    phase: float   # seconds after the start at which the stream's first frame arrives
+
+
+def serving(n_streams: int = 4, n_frames: int = 600, seed: int = 21):
+    """Concurrent sensor streams: even streams see a seeded tree, odd streams a
+    seeded box cluster; each has its own trajectory, its own tool (from
+    batch_tools()) at 256 orientations (64 directions x 4 rolls), frames of
+    5,000-40,000 returns (uniform, seeded) at 10 Hz from a seeded phase;
+    v = 1 cm, tau = 4 cm."""
+    rng = np.random.default_rng(seed)
+    tools = batch_tools()
+    rot = orientations(fibonacci_directions(64), 4)
+    out = []
+    for s in range(n_streams):
+        if s % 2 == 0:
+            scene = tree_scene(seed=7 + s)
+            poses = orbit_poses(max(600, n_frames), seed=3 + s)
+        else:
+            scene = box_cluster_scene(seed=11 + s)
+            poses = orbit_poses(max(600, n_frames), seed=3 + s, r_lo=3.5, r_hi=5.0,
+                                z_lo=0.5, z_hi=3.0)
+        w = Workload("serve%d" % s, 0.01, 0.04, 0.01, scene, poses,
+                     uneven_counts(max(600, n_frames), seed=9 + s), 0.02, 5 + s, -7.0, 52.0,
+                     tools[s % len(tools)], rot, n_frames)
+        out.append(ServeStream(w, float(rng.uniform(0.0, 0.1))))
+    return out
