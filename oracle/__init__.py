@@ -25,10 +25,11 @@ CLS_BODY, CLS_NEAR, CLS_FAR = 0, 1, 2
 
 
 def build(force: bool = True) -> str:
-    src = os.path.join(_HERE, "oracle.c")
-    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(src):
+    srcs = [os.path.join(_HERE, f) for f in ("oracle.c", "smooth.c")]
+    dep = max(os.path.getmtime(f) for f in srcs + [os.path.join(_HERE, "oracle.h")])
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < dep:
         tmp = _SO + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", *CFLAGS, src, "-o", tmp, "-lm"])
+        subprocess.check_call(["gcc", *CFLAGS, *srcs, "-o", tmp, "-lm"])
         os.replace(tmp, _SO)
     return _SO
 
@@ -111,6 +112,14 @@ def _load():
     L.orc_key.argtypes = [i64, i64, i64]
     L.orc_unkey.argtypes = [i64, vp]
     L.orc_params.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.orc_smooth.restype = ctypes.c_int
+    L.orc_smooth.argtypes = [vp, vp, vp, i64, vp, i32, dbl, dbl, vp, vp, vp, vp]
+    L.orc_smooth_dense.restype = ctypes.c_int
+    L.orc_smooth_dense.argtypes = [vp, vp, vp, dbl, dbl, vp, vp, i64, vp, i32, dbl, dbl,
+                                   vp, vp, vp, vp]
+    L.orc_smooth_refine.restype = ctypes.c_int
+    L.orc_smooth_refine.argtypes = [vp, vp, i64, vp, i32, vp, i32, dbl, dbl, i32, dbl, dbl,
+                                    vp, vp, vp]
     _lib = L
     return L
 
@@ -281,6 +290,34 @@ class Oracle:
         return dict(label=lbl.value, first_free=ff.value, normal=n, has_normal=hn.value,
                     mask=m)
 
+    def smooth(self, p, q, samples, c=0.01, tau_s=0.005):
+        """The smoothed score on this oracle's map (see smooth_dense)."""
+        p, q, smp = _f32(p, 3), _f32(q, 4), _f32(samples, 3)
+        assert len(p) == len(q)
+        s, dq, dp, face = _smooth_out(len(p))
+        rc = self.L.orc_smooth(self.h, _p(p), _p(q), len(p), _p(smp), len(smp), float(c),
+                               float(tau_s), _p(s), _p(dq), _p(dp), _p(face))
+        if rc != 0:
+            raise ValueError("orc_smooth rejected its arguments")
+        return s, dq, dp, face
+
+
+    def smooth_refine(self, p, q0, samples, steps, eta, max_step, c=0.01, tau_s=0.005):
+        """Gradient ascent of the orientation from len(q0) / len(p) starts per
+        point; returns (q, s, face) per (point, start)."""
+        p, q0, smp = _f32(p, 3), _f32(q0, 4), _f32(samples, 3)
+        S = len(q0) // max(1, len(p))
+        assert S * len(p) == len(q0)
+        q = np.zeros((len(q0), 4))
+        s = np.zeros(len(q0))
+        face = np.zeros(len(q0))
+        rc = self.L.orc_smooth_refine(self.h, _p(p), len(p), _p(q0), S, _p(smp), len(smp),
+                                      float(c), float(tau_s), int(steps), float(eta),
+                                      float(max_step), _p(q), _p(s), _p(face))
+        if rc != 0:
+            raise ValueError("orc_smooth_refine rejected its arguments")
+        return q, s, face
+
     def labels(self, K, keys=None):
         """(keys, label, first_free) for all points (canonical order) or the
         listed keys."""
@@ -293,3 +330,30 @@ class Oracle:
             lbl[i] = r["label"]
             ff[i] = r["first_free"]
         return np.asarray(keys), lbl, ff
+
+
+# ---- smoothed clearance score (smooth.c) ----
+def _f32(a, cols):
+    return np.ascontiguousarray(a, dtype=np.float32).reshape(-1, cols)
+
+
+def _smooth_out(n):
+    return (np.zeros(n), np.zeros((n, 4)), np.zeros((n, 3)), np.zeros(n))
+
+
+def smooth_dense(val, origin, v, tau, p, q, samples, c=0.01, tau_s=0.005):
+    """s, ds/dq, ds/dp and the smallest sample-to-face distance (voxels) of
+    each (p, q) pair on a dense voxel block val[k, j, i] whose voxel
+    (0, 0, 0) is `origin`; voxels outside read tau."""
+    val = np.ascontiguousarray(val, dtype=np.float64)
+    dims = np.array(val.shape[::-1], np.int64)
+    org = np.ascontiguousarray(origin, dtype=np.int64)
+    p, q, smp = _f32(p, 3), _f32(q, 4), _f32(samples, 3)
+    assert len(p) == len(q)
+    s, dq, dp, face = _smooth_out(len(p))
+    rc = _load().orc_smooth_dense(_p(val), _p(dims), _p(org), float(v), float(tau), _p(p),
+                                  _p(q), len(p), _p(smp), len(smp), float(c), float(tau_s),
+                                  _p(s), _p(dq), _p(dp), _p(face))
+    if rc != 0:
+        raise ValueError("orc_smooth_dense rejected its arguments")
+    return s, dq, dp, face

@@ -97,6 +97,20 @@ int orc_point_result(const orc_t *o, int64_t key, uint8_t *label,
                      int32_t *first_free, int64_t normal[3], int32_t *has_normal,
                      uint64_t *mask, int32_t mask_words);
 
+/* Smoothed clearance score (smooth.c): sum over tool samples o of
+ * log sigma((T(p + R(q) o) - c) / tau_s) with trilinear T, and its gradients
+ * with respect to the quaternion q (w, x, y, z) and the point p. */
+int orc_smooth(const orc_t *o, const float *p, const float *q, int64_t n, const float *samples,
+               int32_t M, double c, double tau_s, double *s, double *dq, double *dp,
+               double *face);
+int orc_smooth_dense(const double *val, const int64_t dims[3], const int64_t origin[3],
+                     double v, double tau, const float *p, const float *q, int64_t n,
+                     const float *samples, int32_t M, double c, double tau_s, double *s,
+                     double *dq, double *dp, double *face);
+int orc_smooth_refine(const orc_t *o, const float *p, int64_t n, const float *q0, int32_t S,
+                      const float *samples, int32_t M, double c, double tau_s, int32_t steps,
+                      double eta, double max_step, double *q_out, double *s_out, double *face);
+
 /* Exposed for unit tests. */
 int64_t orc_isqrt(int64_t n);
 int64_t orc_floor_div(int64_t a, int64_t b);

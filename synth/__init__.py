@@ -291,6 +291,36 @@ def box_tool(length=0.30, width=0.05, height=0.02, corridor=1.0) -> Tool:
                 width=width, height=height)
 
 
+def tool_samples(tool: Tool, n_stations: int = 16) -> np.ndarray:
+    """Points of the tool solid in its local frame (approach axis +x, tip at
+    the origin) for the smoothed score: `n_stations` stations evenly spaced
+    from r_s to length + corridor, and at each the four rim points of the
+    cross-section (cylinder: radius at 0, 90, 180, 270 degrees; box: the
+    corners).  float32, (4 n_stations) x 3."""
+    xs = np.linspace(tool.r_s, tool.length + tool.corridor, n_stations)
+    if tool.shape == CYLINDER:
+        rim = [(tool.radius, 0.0), (0.0, tool.radius), (-tool.radius, 0.0), (0.0, -tool.radius)]
+    else:
+        hw, hh = tool.width / 2, tool.height / 2
+        rim = [(hw, hh), (-hw, hh), (-hw, -hh), (hw, -hh)]
+    return np.array([[x, y, z] for x in xs for y, z in rim], np.float32)
+
+
+def quaternion_towards(dirs: np.ndarray) -> np.ndarray:
+    """Unit quaternions (w, x, y, z) of the shortest rotations taking the
+    tool axis +x to each direction (the antipode turns about +z)."""
+    out = []
+    for d in np.asarray(dirs, dtype=np.float64):
+        d = d / np.linalg.norm(d)
+        w = 1.0 + d[0]
+        if w < 1e-9:
+            out.append([0.0, 0.0, 0.0, 1.0])
+            continue
+        q = np.array([w, 0.0, -d[2], d[1]])   # (1 + e_x.d, e_x x d)
+        out.append(q / np.linalg.norm(q))
+    return np.array(out, np.float32)
+
+
 def fibonacci_directions(n: int) -> np.ndarray:
     k = np.arange(n, dtype=np.float64)
     z = 1.0 - (2 * k + 1) / n
