@@ -225,6 +225,7 @@ typedef struct af_timing {
   double integrate_ms, k_integrate_ms;
   double score_ms, k_normals_ms, k_mask_ms, k_score_ms;
   int64_t integrate_calls, score_calls;
+  double k_smooth_ms;   /* af_smooth_refine kernels */
 } af_timing;
 int af_timing_enable(af_ctx *ctx, int on);
 /* Synchronises the pending events, fills *out, and zeroes the sums if reset. */
@@ -294,6 +295,40 @@ int af_graph_frame(af_ctx *ctx, const float *xyz, int64_t n, const float origin[
                    int64_t frame_id, void *stream);
 float *af_graph_slot(af_ctx *ctx);
 int af_graph_sync(af_ctx *ctx);
+
+/* Smoothed clearance score (a differentiable form of the collision count of
+ * Section 3.5, for refining approach directions between the K orientations):
+ *
+ *   s(p, q) = sum over samples o of log sigma((T(p + R(q/|q|) o) - c) / tau_s)
+ *
+ * T: the TSDF in metres, S/W of the map's voxels, read by trilinear
+ * interpolation between voxel centres ((i, j, k) + 1/2) v; voxels without
+ * weight, unallocated blocks and voxels outside the brick grid read the
+ * truncation distance.  q = (w, x, y, z), any non-zero length; R(q/|q|) maps
+ * the tool's local axes to world axes (its first column is the approach
+ * direction).  samples: M x 3 points of the tool solid in its local frame
+ * (metres, 1 <= M <= 1024).  Arithmetic is fp32 per sample; each pair's
+ * position is split into voxel and fraction in double precision.
+ *
+ * af_smooth_eval: n pairs p[n x 3] (metres), q[n x 4]; writes s_out[n] (may
+ * be NULL when gradients are asked for) and, if dq and dp are both given,
+ * grad_s[i] * ds/dq (n x 4, through the normalisation) and grad_s[i] * ds/dp
+ * (n x 3); grad_s NULL means 1.  All pointers are device memory; the map is
+ * read as it stands after the calls before.  Asynchronous on `stream`.
+ * AF_EINVAL for bad sizes or pointers.
+ *
+ * af_smooth_refine: for point i (p[n_points x 3]) and start j, the pair
+ * i * n_starts + j starts from q0 (row-major, (n_points n_starts) x 4) and
+ * takes `steps` ascent steps q <- (q + D) / |q + D| with D = eta ds/dq,
+ * scaled down to length max_step if longer; q_out receives the final unit
+ * quaternion and s_out its score.  Asynchronous on `stream`. */
+int af_smooth_eval(af_ctx *ctx, const float *p, const float *q, int64_t n, const float *samples,
+                   int32_t M, float c, float tau_s, const float *grad_s, float *s_out,
+                   float *dq, float *dp, void *stream);
+int af_smooth_refine(af_ctx *ctx, const float *p, int64_t n_points, const float *q0,
+                     int32_t n_starts, const float *samples, int32_t M, float c, float tau_s,
+                     int32_t steps, float eta, float max_step, float *q_out, float *s_out,
+                     void *stream);
 
 /* Serving several concurrent sensor streams (the real-time frame budget of
  * Section 3.6, for several sensors on one GPU).

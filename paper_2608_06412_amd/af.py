@@ -76,7 +76,8 @@ class Timing(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in
                 ("integrate_ms", "k_integrate_ms", "score_ms", "k_normals_ms",
                  "k_mask_ms", "k_score_ms")] + \
-               [("integrate_calls", ctypes.c_int64), ("score_calls", ctypes.c_int64)]
+               [("integrate_calls", ctypes.c_int64), ("score_calls", ctypes.c_int64),
+                ("k_smooth_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -114,6 +115,16 @@ SIGNATURES = {
                                       ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     "af_graph_slot": (ctypes.c_void_p, [ctypes.c_void_p]),
     "af_graph_sync": (ctypes.c_int, [ctypes.c_void_p]),
+    "af_smooth_eval": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_int64, ctypes.c_void_p, ctypes.c_int32,
+                                      ctypes.c_float, ctypes.c_float, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_void_p]),
+    "af_smooth_refine": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                        ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                        ctypes.c_int32, ctypes.c_float, ctypes.c_float,
+                                        ctypes.c_int32, ctypes.c_float, ctypes.c_float,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "af_server_create": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p]),
     "af_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "af_server_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
@@ -188,6 +199,12 @@ def _stream_handle(stream):
     if isinstance(stream, int):
         return ctypes.c_void_p(stream)
     return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _check_f32(t, shape, name):
+    if not (getattr(t, "is_cuda", False) and str(t.dtype) == "torch.float32"
+            and t.is_contiguous() and tuple(t.shape) == tuple(shape)):
+        raise TypeError("%s must be a contiguous CUDA float32 tensor of shape %s" % (name, shape))
 
 
 class Context:
@@ -387,6 +404,45 @@ class Context:
     def graph_sync(self):
         """Wait for replayed frames and raise on any overflow they reported."""
         self._check(self._lib.af_graph_sync(self.h))
+
+    def smooth_eval(self, p, q, samples, c=0.01, tau_s=0.005, grad_s=None, s=None, dq=None,
+                    dp=None, stream=None):
+        """Smoothed clearance score of the pairs (p[n, 3], q[n, 4]) into the
+        given CUDA float32 outputs (s[n]; dq[n, 4] and dp[n, 3] together)."""
+        n = int(p.shape[0])
+        _check_f32(p, (n, 3), "p")
+        _check_f32(q, (n, 4), "q")
+        _check_f32(samples, (samples.shape[0], 3), "samples")
+        for t, shp, name in ((grad_s, (n,), "grad_s"), (s, (n,), "s"), (dq, (n, 4), "dq"),
+                             (dp, (n, 3), "dp")):
+            if t is not None:
+                _check_f32(t, shp, name)
+        ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+        self._check(self._lib.af_smooth_eval(self.h, ptr(p), ptr(q), n, ptr(samples),
+                                             int(samples.shape[0]), float(c), float(tau_s),
+                                             ptr(grad_s), ptr(s), ptr(dq), ptr(dp),
+                                             _stream_handle(stream)))
+
+    def smooth_refine(self, p, q0, samples, steps=20, eta=1e-3, max_step=0.05, c=0.01,
+                      tau_s=0.005, stream=None):
+        """Orientation ascent from q0[n_points * n_starts, 4]; returns (q, s)
+        as new CUDA tensors."""
+        import torch
+        n = int(p.shape[0])
+        _check_f32(p, (n, 3), "p")
+        if n == 0 or q0.shape[0] % n:
+            raise ValueError("q0 must hold n_starts quaternions per point")
+        _check_f32(q0, (q0.shape[0], 4), "q0")
+        _check_f32(samples, (samples.shape[0], 3), "samples")
+        q = torch.empty_like(q0)
+        s = torch.empty(q0.shape[0], device=q0.device, dtype=torch.float32)
+        self._check(self._lib.af_smooth_refine(
+            self.h, ctypes.c_void_p(p.data_ptr()), n, ctypes.c_void_p(q0.data_ptr()),
+            q0.shape[0] // n, ctypes.c_void_p(samples.data_ptr()), int(samples.shape[0]),
+            float(c), float(tau_s), int(steps), float(eta), float(max_step),
+            ctypes.c_void_p(q.data_ptr()), ctypes.c_void_p(s.data_ptr()),
+            _stream_handle(stream)))
+        return q, s
 
     def score_variant_default(self) -> int:
         return self._lib.af_score_variant_default()

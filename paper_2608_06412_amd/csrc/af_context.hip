@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <string>
 #include <vector>
 
@@ -42,6 +43,11 @@ struct af_ctx {
   int64_t slot_cap;
   bool graph_dirty;             // recorded frames ran since the host mirrors were refreshed
   bool graph_stale;             // a buffer the graph holds was reallocated
+  // smoothed score: per-voxel TSDF values and the brick-to-block table
+  float *sm_T;
+  int64_t sm_T_cap;             // voxels
+  int32_t *sm_bid;
+  int64_t sm_bid_cap;           // bricks
   std::vector<char> own_mask;   // tool has its own mask and plane buffers
   unsigned *work;               // point counter of the dynamic score variants
   int score_variant;
@@ -230,7 +236,8 @@ int regrid(af_ctx *c, hipStream_t s) {
   return AF_OK;
 }
 
-enum { ST_INTEGRATE, ST_K_INTEGRATE, ST_SCORE, ST_K_NORMALS, ST_K_MASK, ST_K_SCORE, ST_COUNT };
+enum { ST_INTEGRATE, ST_K_INTEGRATE, ST_SCORE, ST_K_NORMALS, ST_K_MASK, ST_K_SCORE, ST_K_SMOOTH,
+       ST_COUNT };
 
 hipEvent_t timing_mark(af_ctx *c, hipStream_t s) {
   if (!c->timing) return nullptr;
@@ -290,6 +297,7 @@ int af_timing_read(af_ctx *c, af_timing *out, int reset) {
     out->k_score_ms = c->stage_ms[ST_K_SCORE];
     out->integrate_calls = c->integrate_calls;
     out->score_calls = c->score_calls;
+    out->k_smooth_ms = c->stage_ms[ST_K_SMOOTH];
   }
   if (reset) {
     for (double &x : c->stage_ms) x = 0;
@@ -936,6 +944,88 @@ int af_graph_sync(af_ctx *c) {
   if (!c) return AF_EINVAL;
   if (!c->graph_dirty) return sync_last(c);
   return graph_settle(c);
+}
+
+// TSDF values and the brick table for the smoothed score, rebuilt from the
+// current map (a few tens of microseconds; the map may change between calls).
+static int smooth_prepare(af_ctx *c, hipStream_t s, SmoothField &f) {
+  int rc;
+  if (c->graph_dirty && (rc = graph_settle(c)) != AF_OK) return rc;
+  if ((rc = regrid(c, s)) != AF_OK) return rc;
+  const int64_t nv = std::max<int64_t>(1, c->n_blocks * kBlockVox);
+  if (nv > c->sm_T_cap) {
+    HIP_TRY(c, hipStreamSynchronize(s));
+    if (c->sm_T) dev_free(c, c->sm_T, sizeof(float) * c->sm_T_cap);
+    c->sm_T = nullptr;
+    c->sm_T_cap = 0;
+    const int64_t cap = std::min<int64_t>(c->cfg.max_blocks * kBlockVox, nv + nv / 2 + kBlockVox);
+    ALLOC(c, c->sm_T, cap);
+    c->sm_T_cap = cap;
+  }
+  const int64_t nb = std::max<int64_t>(1, c->grid_bricks);
+  if (nb > c->sm_bid_cap) {
+    HIP_TRY(c, hipStreamSynchronize(s));
+    if (c->sm_bid) dev_free(c, c->sm_bid, sizeof(int32_t) * c->sm_bid_cap);
+    c->sm_bid = nullptr;
+    c->sm_bid_cap = 0;
+    ALLOC(c, c->sm_bid, nb);
+    c->sm_bid_cap = nb;
+  }
+  const float tau = (float)((double)c->p.tau_u / c->p.scale);
+  launch_smooth_prepare(c->p, c->map, c->n_blocks, c->grid, c->sm_T, c->sm_bid, c->grid_bricks,
+                        tau, s);
+  f.T = c->sm_T;
+  f.bid = c->sm_bid;
+  for (int a = 0; a < 3; ++a) {
+    f.g0[a] = c->grid.g0[a];
+    f.gd[a] = c->grid_bricks > 0 ? c->grid.gd[a] : 0;
+  }
+  f.tau = tau;
+  return hip_check(c, "smooth prepare");
+}
+
+static bool smooth_args_ok(int32_t M, float c_thr, float tau_s) {
+  return M >= 1 && M <= 1024 && std::isfinite(c_thr) && tau_s > 0.f && std::isfinite(tau_s);
+}
+
+int af_smooth_eval(af_ctx *c, const float *p, const float *q, int64_t n, const float *samples,
+                   int32_t M, float c_thr, float tau_s, const float *grad_s, float *s_out,
+                   float *dq, float *dp, void *stream) {
+  if (!c) return AF_EINVAL;
+  if (n < 0 || (n > 0 && (!p || !q || !samples)) || !smooth_args_ok(M, c_thr, tau_s) ||
+      (!dq) != (!dp) || (n > 0 && !s_out && !dq))
+    return fail(c, AF_EINVAL, "bad smoothed-score arguments");
+  hipStream_t s = (hipStream_t)stream;
+  SmoothField f;
+  int rc = smooth_prepare(c, s, f);
+  if (rc != AF_OK) return rc;
+  launch_smooth_eval(f, 256.0 / c->p.scale, p, q, n, samples, M, c_thr, tau_s, grad_s, s_out, dq,
+                     dp, s);
+  c->last_stream = s;
+  return hip_check(c, "smooth eval");
+}
+
+int af_smooth_refine(af_ctx *c, const float *p, int64_t n_points, const float *q0,
+                     int32_t n_starts, const float *samples, int32_t M, float c_thr, float tau_s,
+                     int32_t steps, float eta, float max_step, float *q_out, float *s_out,
+                     void *stream) {
+  if (!c) return AF_EINVAL;
+  if (n_points < 0 || n_starts < 1 || steps < 0 || steps > 100000 ||
+      (n_points > 0 && (!p || !q0 || !samples || !q_out || !s_out)) ||
+      !smooth_args_ok(M, c_thr, tau_s) || !std::isfinite(eta) || !(max_step > 0.f) ||
+      n_points > ((int64_t)1 << 40) / n_starts)
+    return fail(c, AF_EINVAL, "bad refinement arguments");
+  hipStream_t s = (hipStream_t)stream;
+  SmoothField f;
+  int rc = smooth_prepare(c, s, f);
+  if (rc != AF_OK) return rc;
+  hipEvent_t t0 = timing_mark(c, s);
+  launch_smooth_refine(f, 256.0 / c->p.scale, p, n_points, q0, n_starts, samples, M, c_thr, tau_s,
+                       steps, eta, max_step, q_out, s_out, s);
+  hipEvent_t t1 = timing_mark(c, s);
+  if (c->timing) timing_pair(c, ST_K_SMOOTH, t0, t1);
+  c->last_stream = s;
+  return hip_check(c, "smooth refine");
 }
 
 int af_score_variant_count(void) { return score_variants(); }

@@ -231,6 +231,24 @@ struct FrameArgs {
   int32_t frame;  // frame id
 };
 void launch_set_frame_args(FrameArgs *fa, int64_t n, int3 Q, int32_t frame, hipStream_t s);
+
+// Smoothed clearance score: the TSDF as one float per voxel of every block
+// (tau where W = 0) and the block id of every brick of the dense grid.
+struct SmoothField {
+  const float *T;       // [n_blocks * 512], metres
+  const int32_t *bid;   // [grid bricks], -1 for no block
+  int32_t g0[3], gd[3];
+  float tau;            // metres
+};
+void launch_smooth_prepare(const Params &p, MapDev m, int64_t n_blocks, GridDev g, float *T,
+                           int32_t *bid, int64_t grid_bricks, float tau, hipStream_t s);
+void launch_smooth_eval(const SmoothField &f, double v, const float *p, const float *q, int64_t n,
+                        const float *samples, int32_t M, float c, float tau_s,
+                        const float *grad_s, float *s_out, float *dq, float *dp, hipStream_t s);
+void launch_smooth_refine(const SmoothField &f, double v, const float *p, int64_t n_points,
+                          const float *q0, int32_t n_starts, const float *samples, int32_t M,
+                          float c, float tau_s, int32_t steps, float eta, float max_step,
+                          float *q_out, float *s_out, hipStream_t s);
 void launch_stick_status(FrameCounters *c, hipStream_t s);
 void launch_zero_words(void *p, int64_t bytes, hipStream_t s);   // a fill kernel (graph-safe)
 // nb: an upper bound of the frame's returns (sizes the launches)

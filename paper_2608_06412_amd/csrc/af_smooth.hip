@@ -1,0 +1,340 @@
+// Smoothed clearance score and its adjoint.
+//
+// A differentiable companion of the collision-count score of Section 3.5:
+// each sample o of the tool solid (local frame, approach axis +x, tip at the
+// origin) placed at p + R(q) o contributes log sigma((T - c) / tau_s), where
+// T is the TSDF (Section 3.2) interpolated trilinearly between voxel centres
+// and a voxel without weight reads the truncation distance.  Gradients with
+// respect to the quaternion q (through q / |q|) and the point p come from the
+// same pass: d log sigma(z) / dz = sigma(-z).
+//
+// Layout: one wave per (point, orientation) pair, one tool sample per lane,
+// so the 64 lanes read neighbouring voxels along the tool and the sums are a
+// wave reduction.  The TSDF is first expanded to one float per voxel of every
+// allocated block and a brick-to-block table over the dense brick grid, so a
+// tap is two loads with no hashing.
+//
+// Precision: the placement of a sample in its voxel cell (p + R o, divided by
+// v) is computed in double precision, because an fp32 position is only good
+// to ~1e-5 voxel at metre scale and the gradient's relative error follows the
+// cell fractions; interpolation, score and adjoint are fp32.  The quaternion
+// derivative uses the degree-0 homogeneous form of the rotation,
+// R(q) = P(q) / |q|^2, whose gradient has no radial part, so no projection
+// (and no cancellation) is needed to pass through the normalisation.
+
+#include "af_internal.h"
+
+namespace af {
+namespace {
+
+constexpr int kSmoothThreads = 256;
+
+__global__ void __launch_bounds__(kSmoothThreads)
+k_smooth_values(MapDev m, int64_t n_vox, double scale, float tau, float *T) {
+  const int64_t i = (int64_t)blockIdx.x * kSmoothThreads + threadIdx.x;
+  if (i >= n_vox) return;
+  const int32_t W = m.W[i];
+  T[i] = W > 0 ? (float)(((double)m.S[i] / (double)W) / scale) : tau;
+}
+
+__global__ void __launch_bounds__(kSmoothThreads) k_smooth_bid_clear(int32_t *bid, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kSmoothThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kSmoothThreads)
+    bid[i] = -1;
+}
+
+__global__ void __launch_bounds__(kSmoothThreads)
+k_smooth_bid(MapDev m, int64_t n_blocks, GridDev g, int32_t *bid) {
+  const int64_t id = (int64_t)blockIdx.x * kSmoothThreads + threadIdx.x;
+  if (id >= n_blocks) return;
+  int32_t b[3];
+  unpack_key(m.bkey[id], b[0], b[1], b[2]);
+  const int x = b[0] - g.g0[0], y = b[1] - g.g0[1], z = b[2] - g.g0[2];
+  if ((unsigned)x < (unsigned)g.gd[0] && (unsigned)y < (unsigned)g.gd[1] &&
+      (unsigned)z < (unsigned)g.gd[2])
+    bid[((int64_t)z * g.gd[1] + y) * g.gd[0] + x] = (int32_t)id;
+}
+
+__device__ inline float wave_sum(float x) {
+  for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off);
+  return x;
+}
+
+// T of voxel (X, Y, Z): tau outside the grid or in an unallocated brick.
+__device__ inline float smooth_tap(const SmoothField &f, int X, int Y, int Z) {
+  const int bx = (X >> 3) - f.g0[0], by = (Y >> 3) - f.g0[1], bz = (Z >> 3) - f.g0[2];
+  if ((unsigned)bx >= (unsigned)f.gd[0] || (unsigned)by >= (unsigned)f.gd[1] ||
+      (unsigned)bz >= (unsigned)f.gd[2])
+    return f.tau;
+  const int32_t id = f.bid[((int64_t)bz * f.gd[1] + by) * f.gd[0] + bx];
+  if (id < 0) return f.tau;
+  return f.T[(int64_t)id * 512 + ((X & 7) | ((Y & 7) << 3) | ((Z & 7) << 6))];
+}
+
+// A pair's point as integer voxel coordinate + fraction of p / v - 1/2.
+struct PairBase {
+  int ip[3];
+  double rp[3];
+};
+
+__device__ inline PairBase pair_base(const float *p, double v) {
+  PairBase b;
+  for (int a = 0; a < 3; ++a) {
+    const double g = (double)p[a] / v - 0.5;
+    const double fl = floor(g);
+    b.ip[a] = (int)fl;
+    b.rp[a] = g - fl;
+  }
+  return b;
+}
+
+// Normalised quaternion, its norm, and the rotation (row-major, double for
+// the placement of samples).
+struct Rot {
+  float qn[4];
+  float nq;
+  double R[9];
+};
+
+__device__ inline Rot make_rot(const float q[4]) {
+  Rot r;
+  const double q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3];
+  const double n = sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+  const double w = q0 / n, x = q1 / n, y = q2 / n, z = q3 / n;
+  r.nq = (float)n;
+  r.qn[0] = (float)w;
+  r.qn[1] = (float)x;
+  r.qn[2] = (float)y;
+  r.qn[3] = (float)z;
+  r.R[0] = 1.0 - 2.0 * (y * y + z * z);
+  r.R[1] = 2.0 * (x * y - w * z);
+  r.R[2] = 2.0 * (x * z + w * y);
+  r.R[3] = 2.0 * (x * y + w * z);
+  r.R[4] = 1.0 - 2.0 * (x * x + z * z);
+  r.R[5] = 2.0 * (y * z - w * x);
+  r.R[6] = 2.0 * (x * z - w * y);
+  r.R[7] = 2.0 * (y * z + w * x);
+  r.R[8] = 1.0 - 2.0 * (x * x + y * y);
+  return r;
+}
+
+__device__ inline float log_sigmoid(float z) {
+  return z >= 0.f ? -log1pf(expf(-z)) : z - log1pf(expf(z));
+}
+
+__device__ inline float sigmoid_neg(float z) {
+  if (z >= 0.f) {
+    const float e = expf(-z);
+    return e / (1.f + e);
+  }
+  return 1.f / (1.f + expf(z));
+}
+
+// One sample: returns its log sigma term; with G > 0 adds gs |q| ds/dq (4)
+// and, with G == 1, gs ds/dp (3).
+template <int G>
+__device__ inline float smooth_sample(const SmoothField &f, const PairBase &pb, const Rot &r,
+                                      double inv_v, const float o[3], float c, float inv_ts,
+                                      float gs, float dp[3], float dqn[4]) {
+  int cell[3];
+  float fr[3], u[3];
+  for (int a = 0; a < 3; ++a) {
+    const double ud = r.R[3 * a] * (double)o[0] + r.R[3 * a + 1] * (double)o[1] +
+                      r.R[3 * a + 2] * (double)o[2];
+    const double gl = pb.rp[a] + ud * inv_v;
+    const double fl = floor(gl);
+    cell[a] = pb.ip[a] + (int)fl;
+    fr[a] = (float)(gl - fl);
+    u[a] = (float)ud;
+  }
+  float val = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int a = k & 1, b = (k >> 1) & 1, cc = k >> 2;
+    const float t = smooth_tap(f, cell[0] + a, cell[1] + b, cell[2] + cc);
+    const float wx = a ? fr[0] : 1.f - fr[0], wy = b ? fr[1] : 1.f - fr[1],
+                wz = cc ? fr[2] : 1.f - fr[2];
+    val += wx * wy * wz * t;
+    if (G > 0) {
+      gx += (a ? 1.f : -1.f) * wy * wz * t;
+      gy += wx * (b ? 1.f : -1.f) * wz * t;
+      gz += wx * wy * (cc ? 1.f : -1.f) * t;
+    }
+  }
+  const float z = (val - c) * inv_ts;
+  if (G > 0) {
+    const float wgt = sigmoid_neg(z) * inv_ts * gs;
+    const float iv = (float)inv_v;
+    const float g0 = wgt * gx * iv, g1 = wgt * gy * iv, g2 = wgt * gz * iv;
+    if (G == 1) {
+      dp[0] += g0;
+      dp[1] += g1;
+      dp[2] += g2;
+    }
+    // R o = P(q) o / |q|^2 with P quadratic: at |q| = 1,
+    // d(R o)/dq_a = dP/dq_a o - 2 q_a (R o), which is orthogonal to q.
+    const float w = r.qn[0], x = r.qn[1], y = r.qn[2], zz = r.qn[3];
+    const float ox = o[0], oy = o[1], oz = o[2];
+    const float gu = g0 * u[0] + g1 * u[1] + g2 * u[2];
+    dqn[0] += 2.f * (g0 * (w * ox - zz * oy + y * oz) + g1 * (zz * ox + w * oy - x * oz) +
+                     g2 * (-y * ox + x * oy + w * oz)) - 2.f * w * gu;
+    dqn[1] += 2.f * (g0 * (x * ox + y * oy + zz * oz) + g1 * (y * ox - x * oy - w * oz) +
+                     g2 * (zz * ox + w * oy - x * oz)) - 2.f * x * gu;
+    dqn[2] += 2.f * (g0 * (-y * ox + x * oy + w * oz) + g1 * (x * ox + y * oy + zz * oz) +
+                     g2 * (-w * ox + zz * oy - y * oz)) - 2.f * y * gu;
+    dqn[3] += 2.f * (g0 * (-zz * ox - w * oy + x * oz) + g1 * (w * ox - zz * oy + y * oz) +
+                     g2 * (x * ox + y * oy + zz * oz)) - 2.f * zz * gu;
+  }
+  return log_sigmoid(z);
+}
+
+// s of one pair (wave-uniform result), gradients reduced over the wave.
+template <int G>
+__device__ inline float smooth_pair(const SmoothField &f, const PairBase &pb, const Rot &r,
+                                    double inv_v, const float *samples, int M, float c,
+                                    float inv_ts, float gs, float dp[3], float dqn[4]) {
+  const int lane = threadIdx.x & 63;
+  float s = 0.f;
+  for (int a = 0; a < 3; ++a) dp[a] = 0.f;
+  for (int a = 0; a < 4; ++a) dqn[a] = 0.f;
+  for (int m0 = 0; m0 < M; m0 += 64) {
+    const int m = m0 + lane;
+    if (m < M) {
+      const float o[3] = {samples[3 * m], samples[3 * m + 1], samples[3 * m + 2]};
+      s += smooth_sample<G>(f, pb, r, inv_v, o, c, inv_ts, gs, dp, dqn);
+    }
+  }
+  s = wave_sum(s);
+  if (G == 1)
+    for (int a = 0; a < 3; ++a) dp[a] = wave_sum(dp[a]);
+  if (G > 0)
+    for (int a = 0; a < 4; ++a) dqn[a] = wave_sum(dqn[a]);
+  return s;
+}
+
+// The homogeneous form's gradient at q / |q| scales by 1 / |q| at q.
+__device__ inline void unnormalise(const Rot &r, const float dqn[4], float dq[4]) {
+  for (int a = 0; a < 4; ++a) dq[a] = dqn[a] / r.nq;
+}
+
+template <int G>
+__global__ void __launch_bounds__(kSmoothThreads)
+k_smooth_eval(SmoothField f, double v, const float *p, const float *q, int64_t n,
+              const float *samples, int M, float c, float tau_s, const float *grad_s,
+              float *s_out, float *dq_out, float *dp_out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nwaves = ((int64_t)gridDim.x * kSmoothThreads) >> 6;
+  const double inv_v = 1.0 / v;
+  const float inv_ts = 1.f / tau_s;
+  for (int64_t i = ((int64_t)blockIdx.x * kSmoothThreads + threadIdx.x) >> 6; i < n;
+       i += nwaves) {
+    const PairBase pb = pair_base(p + 3 * i, v);
+    const float q4[4] = {q[4 * i], q[4 * i + 1], q[4 * i + 2], q[4 * i + 3]};
+    const Rot r = make_rot(q4);
+    const float gs = grad_s ? grad_s[i] : 1.f;
+    float dp[3], dqn[4];
+    const float s = smooth_pair<G>(f, pb, r, inv_v, samples, M, c, inv_ts, gs, dp, dqn);
+    if (lane == 0) {
+      if (s_out) s_out[i] = s;
+      if (G == 1) {
+        float dq[4];
+        unnormalise(r, dqn, dq);
+        for (int a = 0; a < 4; ++a) dq_out[4 * i + a] = dq[a];
+        for (int a = 0; a < 3; ++a) dp_out[3 * i + a] = dp[a];
+      }
+    }
+  }
+}
+
+// Orientation ascent: per (point, start) pair, `steps` updates
+// q <- (q + D) / |q + D|, D = eta ds/dq clipped to length max_step, with q
+// kept in registers; then s at the final q.
+__global__ void __launch_bounds__(kSmoothThreads)
+k_smooth_refine(SmoothField f, double v, const float *p, int64_t n_points, const float *q0,
+                int n_starts, const float *samples, int M, float c, float tau_s, int steps,
+                float eta, float max_step, float *q_out, float *s_out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t n = n_points * n_starts;
+  const int64_t nwaves = ((int64_t)gridDim.x * kSmoothThreads) >> 6;
+  const double inv_v = 1.0 / v;
+  const float inv_ts = 1.f / tau_s;
+  for (int64_t i = ((int64_t)blockIdx.x * kSmoothThreads + threadIdx.x) >> 6; i < n;
+       i += nwaves) {
+    const PairBase pb = pair_base(p + 3 * (i / n_starts), v);
+    float q[4] = {q0[4 * i], q0[4 * i + 1], q0[4 * i + 2], q0[4 * i + 3]};
+    float dp[3], dqn[4], dq[4];
+    for (int t = 0; t < steps; ++t) {
+      const Rot r = make_rot(q);
+      smooth_pair<2>(f, pb, r, inv_v, samples, M, c, inv_ts, 1.f, dp, dqn);
+      unnormalise(r, dqn, dq);
+      float D[4], len = 0.f;
+      for (int a = 0; a < 4; ++a) {
+        D[a] = eta * dq[a];
+        len += D[a] * D[a];
+      }
+      len = sqrtf(len);
+      const float sc = len > max_step ? max_step / len : 1.f;
+      float nn = 0.f;
+      for (int a = 0; a < 4; ++a) {
+        q[a] += D[a] * sc;
+        nn += q[a] * q[a];
+      }
+      nn = sqrtf(nn);
+      for (int a = 0; a < 4; ++a) q[a] /= nn;
+    }
+    const Rot r = make_rot(q);
+    const float s = smooth_pair<0>(f, pb, r, inv_v, samples, M, c, inv_ts, 1.f, dp, dqn);
+    if (lane == 0) {
+      s_out[i] = s;
+      for (int a = 0; a < 4; ++a) q_out[4 * i + a] = r.qn[a];
+    }
+  }
+}
+
+unsigned smooth_grid(int64_t pairs) {
+  const int64_t wg = (pairs + 3) / 4;   // four waves per workgroup
+  return (unsigned)(wg < 2048 ? (wg > 0 ? wg : 1) : 2048);
+}
+
+}  // namespace
+
+void launch_smooth_prepare(const Params &p, MapDev m, int64_t n_blocks, GridDev g, float *T,
+                           int32_t *bid, int64_t grid_bricks, float tau, hipStream_t s) {
+  const int64_t nv = n_blocks * 512;
+  if (nv > 0)
+    hipLaunchKernelGGL(k_smooth_values, dim3((unsigned)((nv + kSmoothThreads - 1) / kSmoothThreads)),
+                       dim3(kSmoothThreads), 0, s, m, nv, p.scale, tau, T);
+  if (grid_bricks > 0) {
+    const int64_t wg = std::min<int64_t>(4096, (grid_bricks + kSmoothThreads - 1) / kSmoothThreads);
+    hipLaunchKernelGGL(k_smooth_bid_clear, dim3((unsigned)wg), dim3(kSmoothThreads), 0, s, bid,
+                       grid_bricks);
+  }
+  if (n_blocks > 0 && grid_bricks > 0)
+    hipLaunchKernelGGL(k_smooth_bid, dim3((unsigned)((n_blocks + kSmoothThreads - 1) / kSmoothThreads)),
+                       dim3(kSmoothThreads), 0, s, m, n_blocks, g, bid);
+}
+
+void launch_smooth_eval(const SmoothField &f, double v, const float *p, const float *q, int64_t n,
+                        const float *samples, int32_t M, float c, float tau_s,
+                        const float *grad_s, float *s_out, float *dq, float *dp, hipStream_t s) {
+  if (n <= 0) return;
+  if (dq)
+    hipLaunchKernelGGL(k_smooth_eval<1>, dim3(smooth_grid(n)), dim3(kSmoothThreads), 0, s, f, v,
+                       p, q, n, samples, M, c, tau_s, grad_s, s_out, dq, dp);
+  else
+    hipLaunchKernelGGL(k_smooth_eval<0>, dim3(smooth_grid(n)), dim3(kSmoothThreads), 0, s, f, v,
+                       p, q, n, samples, M, c, tau_s, grad_s, s_out, dq, dp);
+}
+
+void launch_smooth_refine(const SmoothField &f, double v, const float *p, int64_t n_points,
+                          const float *q0, int32_t n_starts, const float *samples, int32_t M,
+                          float c, float tau_s, int32_t steps, float eta, float max_step,
+                          float *q_out, float *s_out, hipStream_t s) {
+  const int64_t n = n_points * n_starts;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_smooth_refine, dim3(smooth_grid(n)), dim3(kSmoothThreads), 0, s, f, v, p,
+                     n_points, q0, n_starts, samples, M, c, tau_s, steps, eta, max_step, q_out,
+                     s_out);
+}
+
+}  // namespace af

@@ -1,0 +1,188 @@
+"""Smoothed clearance score on the GPU (af_smooth_eval / af_smooth_refine, fp32)
+against the oracle's fp64 definition (oracle/smooth.c) on the tiny scene:
+
+* s and the gradients in q and p, relative error below 1e-4 of the fp64
+  values, pairs whose samples lie within 1e-6 voxel of a cell face excluded
+  (there the trilinear gradient jumps, and the two sides may pick different
+  cells);
+* central differences (h = 1e-3) of the GPU's own s, stencils that cross a
+  cell face excluded;
+* the torch.autograd.Function gives the adjoint kernel's gradients, scaled by
+  the upstream gradient;
+* orientation ascent (20 steps) ends where the fp64 ascent ends;
+* edge cases: no pairs, one sample, a sample count that is not a multiple of
+  the wave, pairs far outside the map, argument errors."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+C, TS = 0.01, 0.005
+
+
+@pytest.fixture(scope="module")
+def smooth_setup(synth_mod, oracle_mod):
+    import torch
+    from paper_2608_06412_amd import Context, default_config
+    w = synth_mod.tiny()
+    frames = w.frames()
+    ctx = Context(default_config(w.voxel, w.trunc, r_c=w.r_c, max_blocks=1 << 15,
+                                 max_points=1 << 17))
+    orc = oracle_mod.Oracle(voxel=w.voxel, trunc=w.trunc, r_c=w.r_c)
+    for f in frames:
+        ctx.integrate_frame(torch.from_numpy(f.xyz).cuda(), f.origin, f.frame_id)
+        orc.integrate_frame(f.xyz, f.origin, f.frame_id)
+    rng = np.random.default_rng(7)
+    key = orc.read_points()["key"]
+    pts = ((oracle_mod.unpack_keys(key[rng.choice(len(key), 300, replace=False)]) + 0.5)
+           * w.voxel).astype(np.float32)
+    # jitter the points off the voxel centres, random orientations
+    p = (np.repeat(pts, 4, axis=0) + rng.uniform(-0.3, 0.3, (1200, 3)) * w.voxel).astype(np.float32)
+    q = rng.normal(size=(1200, 4)).astype(np.float32)
+    return w, ctx, orc, p, q
+
+
+def _cuda(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _gpu_eval(ctx, p, q, smp, grads=True):
+    import torch
+    n = len(p)
+    s = torch.empty(n, device="cuda")
+    dq = torch.empty(n, 4, device="cuda") if grads else None
+    dp = torch.empty(n, 3, device="cuda") if grads else None
+    ctx.smooth_eval(_cuda(p), _cuda(q), _cuda(smp), C, TS, s=s, dq=dq, dp=dp)
+    torch.cuda.synchronize()
+    return s.cpu().numpy(), (dq.cpu().numpy() if grads else None), \
+        (dp.cpu().numpy() if grads else None)
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b, axis=1) / np.maximum(np.linalg.norm(b, axis=1), 1e-30)
+
+
+@pytest.mark.parametrize("n_stations", [16, 18])
+def test_against_fp64_oracle(smooth_setup, synth_mod, n_stations):
+    w, ctx, orc, p, q = smooth_setup
+    smp = synth_mod.tool_samples(synth_mod.cylinder_tool(), n_stations)   # M = 64, 72
+    s, dq, dp = _gpu_eval(ctx, p, q, smp)
+    so, dqo, dpo, face = orc.smooth(p, q, smp, C, TS)
+    assert np.all(np.abs(s - so) <= 1e-5 * np.abs(so) + 1e-4), np.abs(s - so).max()
+    ok = face > 1e-6
+    big = np.linalg.norm(dpo, axis=1) > 1e-3 * np.median(np.linalg.norm(dpo, axis=1))
+    sel = ok & big
+    print("pairs", len(p), "compared", sel.sum(), "max rel dq %.2e dp %.2e" %
+          (_rel(dq[sel], dqo[sel]).max(), _rel(dp[sel], dpo[sel]).max()), flush=True)
+    assert sel.sum() > 0.95 * len(p)
+    assert _rel(dq[sel], dqo[sel]).max() < 1e-4
+    assert _rel(dp[sel], dpo[sel]).max() < 1e-4
+
+
+def test_central_differences(smooth_setup, synth_mod):
+    w, ctx, orc, p, q = smooth_setup
+    # the first station of the tool (four rim points): with few samples some
+    # pairs keep every stencil inside its cells
+    smp = synth_mod.tool_samples(synth_mod.cylinder_tool(), 16)[:4]
+    s, dq, dp = _gpu_eval(ctx, p, q, smp)
+    so, dqo, dpo, face = orc.smooth(p, q, smp, C, TS)
+    h = 1e-3
+    # a step of h moves a sample by at most h (p) or 2 h |o| (q): keep pairs
+    # whose samples stay inside their cells
+    reach = 2 * np.linalg.norm(smp, axis=1).max() * h / w.voxel
+    keep = face > 1.5 * max(h / w.voxel, reach)
+    fd_p = np.zeros_like(dp)
+    fd_q = np.zeros_like(dq)
+    for a in range(3):
+        e = np.zeros(3, np.float32)
+        e[a] = h
+        sp, _, _ = _gpu_eval(ctx, p + e, q, smp, grads=False)
+        sm, _, _ = _gpu_eval(ctx, p - e, q, smp, grads=False)
+        fd_p[:, a] = (sp.astype(np.float64) - sm) / (2 * h)
+    for a in range(4):
+        e = np.zeros(4, np.float32)
+        e[a] = h
+        sp, _, _ = _gpu_eval(ctx, p, q + e, smp, grads=False)
+        sm, _, _ = _gpu_eval(ctx, p, q - e, smp, grads=False)
+        fd_q[:, a] = (sp.astype(np.float64) - sm) / (2 * h)
+    print("fd pairs", keep.sum(), flush=True)
+    assert keep.sum() >= 20
+    scale_p = np.linalg.norm(dpo[keep], axis=1).mean()
+    scale_q = np.linalg.norm(dqo[keep], axis=1).mean()
+    assert np.abs(fd_p[keep] - dp[keep]).max() < 2e-2 * scale_p
+    assert np.abs(fd_q[keep] - dq[keep]).max() < 2e-2 * scale_q
+
+
+def test_autograd_function(smooth_setup, synth_mod):
+    import torch
+    from paper_2608_06412_amd.smooth import smooth_score
+    w, ctx, orc, p, q = smooth_setup
+    smp = _cuda(synth_mod.tool_samples(synth_mod.cylinder_tool(), 16))
+    pt = _cuda(p[:256]).requires_grad_(True)
+    qt = _cuda(q[:256]).requires_grad_(True)
+    wts = torch.linspace(-1.0, 2.0, 256, device="cuda")
+    s = smooth_score(ctx, pt, qt, smp, C, TS)
+    (s * wts).sum().backward()
+    s0, dq0, dp0 = _gpu_eval(ctx, p[:256], q[:256], smp.cpu().numpy())
+    assert np.array_equal(s.detach().cpu().numpy(), s0)
+    wn = wts.cpu().numpy()[:, None]
+    assert np.allclose(qt.grad.cpu().numpy(), wn * dq0, rtol=1e-5, atol=1e-6 * np.abs(dq0).max())
+    assert np.allclose(pt.grad.cpu().numpy(), wn * dp0, rtol=1e-5, atol=1e-6 * np.abs(dp0).max())
+
+
+def test_refine_against_fp64_ascent(smooth_setup, synth_mod):
+    import torch
+    w, ctx, orc, p, q = smooth_setup
+    smp = synth_mod.tool_samples(synth_mod.cylinder_tool(), 16)
+    pts = p[::4][:64]
+    q0 = np.tile(synth_mod.quaternion_towards(synth_mod.fibonacci_directions(8)), (len(pts), 1))
+    eta, mx = 2e-5, 0.05
+    qg, sg = ctx.smooth_refine(_cuda(pts), _cuda(q0), _cuda(smp), steps=20, eta=eta, max_step=mx,
+                               c=C, tau_s=TS)
+    torch.cuda.synchronize()
+    qg, sg = qg.cpu().numpy(), sg.cpu().numpy()
+    qo, so, face = orc.smooth_refine(pts, q0, smp, steps=20, eta=eta, max_step=mx, c=C, tau_s=TS)
+    ok = face > 1e-6
+    moved = np.linalg.norm(qo - q0, axis=1) > 1e-3
+    print("refine pairs", len(q0), "smooth", ok.sum(), "moved", (ok & moved).sum(), flush=True)
+    assert (ok & moved).sum() >= 20
+    qgs = qg * np.sign(np.sum(qg * qo, axis=1, keepdims=True))
+    assert np.abs(qgs[ok] - qo[ok]).max() < 1e-3
+    assert np.all(np.abs(sg[ok] - so[ok]) <= 1e-4 * np.abs(so[ok]) + 1e-3)
+    # zero steps: the start, normalised, and its score
+    qz, sz = ctx.smooth_refine(_cuda(pts), _cuda(q0), _cuda(smp), steps=0, eta=eta, max_step=mx,
+                               c=C, tau_s=TS)
+    s0, _, _ = _gpu_eval(ctx, np.repeat(pts, 8, axis=0), q0, smp, grads=False)
+    assert np.array_equal(sz.cpu().numpy(), s0)
+    assert np.allclose(qz.cpu().numpy(), q0 / np.linalg.norm(q0, axis=1, keepdims=True),
+                       atol=1e-7)
+
+
+def test_edge_cases(smooth_setup, synth_mod):
+    import torch
+    from paper_2608_06412_amd import AFError
+    w, ctx, orc, p, q = smooth_setup
+    smp1 = np.array([[0.05, 0.0, 0.0]], np.float32)
+    s, dq, dp = _gpu_eval(ctx, p[:50], q[:50], smp1)
+    so, dqo, dpo, face = orc.smooth(p[:50], q[:50], smp1, C, TS)
+    assert np.all(np.abs(s - so) <= 1e-5 * np.abs(so) + 1e-5)
+    far = np.full((3, 3), 100.0, np.float32)
+    smp = synth_mod.tool_samples(synth_mod.cylinder_tool(), 16)
+    s, dq, dp = _gpu_eval(ctx, far, q[:3], smp)
+    tau = orc.params()["tau_u"] / orc.params()["scale"]
+    ref = len(smp) * -np.logaddexp(0.0, -(tau - C) / TS)
+    assert np.allclose(s, ref, rtol=1e-5)
+    assert np.abs(dq).max() < 1e-4 and np.abs(dp).max() < 1e-4   # flat field: rounding only
+    e = torch.empty(0, 3, device="cuda")
+    ctx.smooth_eval(e, torch.empty(0, 4, device="cuda"), _cuda(smp), C, TS,
+                    s=torch.empty(0, device="cuda"))
+    sm = _cuda(smp)
+    pt, qt, st = _cuda(p[:4]), _cuda(q[:4]), torch.empty(4, device="cuda")
+    for bad in (dict(tau_s=0.0), dict(samples=sm[:0]), dict(samples=_cuda(np.zeros((1025, 3))))):
+        kw = dict(tau_s=TS, samples=sm)
+        kw.update(bad)
+        with pytest.raises(AFError):
+            ctx.smooth_eval(pt, qt, kw["samples"], C, kw["tau_s"], s=st)
+    with pytest.raises(AFError):
+        ctx.smooth_eval(pt, qt, sm, C, TS, s=st, dq=torch.empty(4, 4, device="cuda"))
