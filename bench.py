@@ -428,6 +428,109 @@ def run_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def run_smooth(args):
+    """Differentiation workload: the tree map after frames 0..F-1, 1,000,000
+    of its surface points (voxel centres) x 64 starting directions (Fibonacci,
+    tool axis turned onto each), the saw box as 64 samples (16 stations x 4
+    corners over body and corridor), 20 ascent steps of the smoothed score
+    (c = 1 cm, tau_s = 0.5 cm) in one kernel.  W untimed warm-up refinements
+    on 1/16 of the pairs, then K timed full refinements."""
+    import torch
+    import synth
+    from paper_2608_06412_amd import Context, default_config
+    from paper_2608_06412_amd.af import unpack_keys
+
+    F = 250
+    W = args.warmup if args.warmup != 100 else 1
+    K = args.steps if args.steps != 400 else 3
+    w = synth.tree()
+    frames = w.frames(F)
+    torch.cuda.set_device(0)
+    ctx = Context(default_config(w.voxel, w.trunc, r_c=w.r_c, max_blocks=1 << 17,
+                                 max_points=1 << 22))
+    for f in frames:
+        ctx.integrate_frame(torch.from_numpy(f.xyz).cuda(), f.origin, f.frame_id)
+    n_map = ctx.num_points()
+    allk = ctx.read_points()["key"]
+    rng = np.random.default_rng(11)
+    n_pts = 1000000
+    sel = allk[rng.choice(len(allk), n_pts, replace=len(allk) < n_pts)]
+    p = ((unpack_keys(sel) + 0.5) * w.voxel).astype(np.float32)
+    S = 64
+    q0 = np.tile(synth.quaternion_towards(synth.fibonacci_directions(S)), (n_pts, 1))
+    smp = synth.tool_samples(w.tool, 16)
+    pd = torch.from_numpy(p).cuda()
+    qd = torch.from_numpy(q0).cuda()
+    sd = torch.from_numpy(smp).cuda()
+    steps, eta, mx = 20, 1e-5, 0.05
+    pairs = n_pts * S
+    log("map %d points, %d blocks; %d pairs x %d steps, M = %d" %
+        (n_map, ctx.num_blocks(), pairs, steps, len(smp)))
+    sub = n_pts // 16
+    for _ in range(W):
+        ctx.smooth_refine(pd[:sub], qd[:sub * S], sd, steps=steps, eta=eta, max_step=mx)
+    torch.cuda.synchronize()
+    ctx.timing_enable(True)
+    ctx.timing_read(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(K):
+        q, s = ctx.smooth_refine(pd, qd, sd, steps=steps, eta=eta, max_step=mx)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / K
+    tm = ctx.timing_read(reset=True)
+    k_ms = tm["k_smooth_ms"] / K
+    # the ascent's own check: s at the start against s at the end, per pair
+    s_start = torch.empty(pairs, device="cuda")
+    ctx.smooth_eval(pd.repeat_interleave(S, 0), qd, sd, s=s_start)
+    torch.cuda.synchronize()
+    gain = (s - s_start).cpu().numpy()
+    taps = pairs * (steps + 1) * len(smp) * 8
+    bytes_alg = taps * 8.0          # a float of T and a brick id per tap
+    ach = bytes_alg / (k_ms / 1e3) / 1e9
+    out = {
+        "metric": "smoothed-score ascent: (point, start) pairs x steps per second",
+        "value": pairs * steps / (k_ms / 1e3),
+        "unit": "pair-steps/s",
+        "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": k_ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "smooth: tree map after %d frames, 1,000,000 surface points x 64 "
+                               "starts, saw box as 64 samples, 20 ascent steps, c = 1 cm, "
+                               "tau_s = 0.5 cm" % F,
+                   "map_points": int(n_map), "pairs": pairs, "ascent_steps": steps,
+                   "samples": len(smp), "eta": eta, "max_step": mx},
+        "wall_ms_per_refine": wall * 1e3,
+        "sample_evaluations_per_s": pairs * (steps + 1) * len(smp) / (k_ms / 1e3),
+        "taps_per_s": taps / (k_ms / 1e3),
+        "ascent": {"improved_frac": float((gain > 0).mean()),
+                   "unchanged_frac": float((gain == 0).mean()),
+                   "mean_gain": float(gain.mean())},
+        "roofline": {"kernel": "k_smooth_refine", "bound": "hbm", "achieved": ach, "peak": 8000.0,
+                     "unit": "GB/s", "frac": ach / 8000.0, "traffic": None,
+                     "bytes_model": "8 B per trilinear tap (T value + brick id), 8 taps per "
+                                    "sample, 64 samples, 21 evaluations per pair"},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        orc = oracle.Oracle(voxel=w.voxel, trunc=w.trunc, r_c=w.r_c)
+        t0 = time.perf_counter()
+        for f in frames[:args.cpu_frames]:
+            orc.integrate_frame(f.xyz, f.origin, f.frame_id)
+        okeys = orc.read_points()["key"]
+        po = ((oracle.unpack_keys(okeys[rng.choice(len(okeys), 64)]) + 0.5) * w.voxel)
+        po = po.astype(np.float32)
+        qo = np.tile(synth.quaternion_towards(synth.fibonacci_directions(8)), (64, 1))
+        t0 = time.perf_counter()
+        orc.smooth_refine(po, qo, smp, steps=steps, eta=eta, max_step=mx)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": 64 * 8 * steps / dt, "unit": "pair-steps/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": "oracle fp64 ascent, 64 points x 8 starts x 20 steps "
+                                         "on the map of the first %d frames" % args.cpu_frames}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -442,7 +545,7 @@ def main():
     ap.add_argument("--score-variant", default=None,
                     help="scoring configuration (index or name) when not tuning; default: "
                          "the library's default configuration")
-    ap.add_argument("--workload", default="tree", choices=["tree", "batch", "serve"],
+    ap.add_argument("--workload", default="tree", choices=["tree", "batch", "serve", "smooth"],
                     help="tree: the default single-tool workload; batch: 8 tools x 512 "
                          "orientations scored in one launch, frames of 5k-40k returns")
     ap.add_argument("--trace-summary", default=None,
@@ -478,6 +581,8 @@ def main():
     synth.build(force=False)
     if args.workload == "serve":
         return run_serve(args)
+    if args.workload == "smooth":
+        return run_smooth(args)
     if args.workload == "batch":
         run_batch(args)
         return

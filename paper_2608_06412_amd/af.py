@@ -201,6 +201,14 @@ def _stream_handle(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+def unpack_keys(keys) -> np.ndarray:
+    """Voxel indices [n, 3] of packed voxel keys (21 bits per axis holding
+    index + 2^20, x lowest; the layout include/af.h states)."""
+    k = np.asarray(keys, dtype=np.int64)
+    m = (1 << 21) - 1
+    return np.stack([(k & m), ((k >> 21) & m), ((k >> 42) & m)], axis=1) - (1 << 20)
+
+
 def _check_f32(t, shape, name):
     if not (getattr(t, "is_cuda", False) and str(t.dtype) == "torch.float32"
             and t.is_contiguous() and tuple(t.shape) == tuple(shape)):

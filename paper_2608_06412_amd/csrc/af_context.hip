@@ -43,11 +43,10 @@ struct af_ctx {
   int64_t slot_cap;
   bool graph_dirty;             // recorded frames ran since the host mirrors were refreshed
   bool graph_stale;             // a buffer the graph holds was reallocated
-  // smoothed score: per-voxel TSDF values and the brick-to-block table
-  float *sm_T;
-  int64_t sm_T_cap;             // voxels
-  int32_t *sm_bid;
-  int64_t sm_bid_cap;           // bricks
+  // smoothed score: apron bricks and their tables (SmoothBuffers), grown on demand
+  SmoothBuffers sm;
+  int64_t sm_T_cap;             // voxels of sm.T
+  int64_t sm_bid_cap;           // bricks of sm.bid and sm.bid9
   std::vector<char> own_mask;   // tool has its own mask and plane buffers
   unsigned *work;               // point counter of the dynamic score variants
   int score_variant;
@@ -952,30 +951,47 @@ static int smooth_prepare(af_ctx *c, hipStream_t s, SmoothField &f) {
   int rc;
   if (c->graph_dirty && (rc = graph_settle(c)) != AF_OK) return rc;
   if ((rc = regrid(c, s)) != AF_OK) return rc;
+  SmoothBuffers &b = c->sm;
   const int64_t nv = std::max<int64_t>(1, c->n_blocks * kBlockVox);
-  if (nv > c->sm_T_cap) {
-    HIP_TRY(c, hipStreamSynchronize(s));
-    if (c->sm_T) dev_free(c, c->sm_T, sizeof(float) * c->sm_T_cap);
-    c->sm_T = nullptr;
-    c->sm_T_cap = 0;
-    const int64_t cap = std::min<int64_t>(c->cfg.max_blocks * kBlockVox, nv + nv / 2 + kBlockVox);
-    ALLOC(c, c->sm_T, cap);
-    c->sm_T_cap = cap;
-  }
   const int64_t nb = std::max<int64_t>(1, c->grid_bricks);
-  if (nb > c->sm_bid_cap) {
+  // every mapped block marks itself and its -1 neighbours: at most 8 aprons each
+  const int64_t na = std::max<int64_t>(1, std::min<int64_t>(8 * c->n_blocks, c->grid_bricks));
+  if (nv > c->sm_T_cap || nb > c->sm_bid_cap || na > b.apron_cap || !b.count) {
     HIP_TRY(c, hipStreamSynchronize(s));
-    if (c->sm_bid) dev_free(c, c->sm_bid, sizeof(int32_t) * c->sm_bid_cap);
-    c->sm_bid = nullptr;
-    c->sm_bid_cap = 0;
-    ALLOC(c, c->sm_bid, nb);
-    c->sm_bid_cap = nb;
+    if (nv > c->sm_T_cap) {
+      if (b.T) dev_free(c, b.T, sizeof(float) * c->sm_T_cap);
+      b.T = nullptr;
+      c->sm_T_cap = 0;
+      const int64_t cap = std::min<int64_t>(c->cfg.max_blocks * kBlockVox, nv + nv / 2 + kBlockVox);
+      ALLOC(c, b.T, cap);
+      c->sm_T_cap = cap;
+    }
+    if (nb > c->sm_bid_cap) {
+      if (b.bid) dev_free(c, b.bid, sizeof(int32_t) * c->sm_bid_cap);
+      if (b.bid9) dev_free(c, b.bid9, sizeof(int32_t) * c->sm_bid_cap);
+      b.bid = b.bid9 = nullptr;
+      c->sm_bid_cap = 0;
+      ALLOC(c, b.bid, nb);
+      ALLOC(c, b.bid9, nb);
+      c->sm_bid_cap = nb;
+    }
+    if (na > b.apron_cap) {
+      if (b.T9) dev_free(c, b.T9, sizeof(float) * 729 * b.apron_cap);
+      if (b.brick_of) dev_free(c, b.brick_of, sizeof(int32_t) * b.apron_cap);
+      b.T9 = nullptr;
+      b.brick_of = nullptr;
+      b.apron_cap = 0;
+      const int64_t cap = std::min<int64_t>(std::max<int64_t>(1, c->grid_bricks), na + na / 2 + 64);
+      ALLOC(c, b.T9, cap * 729);
+      ALLOC(c, b.brick_of, cap);
+      b.apron_cap = cap;
+    }
+    if (!b.count) ALLOC(c, b.count, 1);
   }
   const float tau = (float)((double)c->p.tau_u / c->p.scale);
-  launch_smooth_prepare(c->p, c->map, c->n_blocks, c->grid, c->sm_T, c->sm_bid, c->grid_bricks,
-                        tau, s);
-  f.T = c->sm_T;
-  f.bid = c->sm_bid;
+  launch_smooth_prepare(c->p, c->map, c->n_blocks, c->grid, c->grid_bricks, tau, b, s);
+  f.T9 = b.T9;
+  f.bid9 = b.bid9;
   for (int a = 0; a < 3; ++a) {
     f.g0[a] = c->grid.g0[a];
     f.gd[a] = c->grid_bricks > 0 ? c->grid.gd[a] : 0;

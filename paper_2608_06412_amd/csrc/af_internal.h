@@ -232,16 +232,28 @@ struct FrameArgs {
 };
 void launch_set_frame_args(FrameArgs *fa, int64_t n, int3 Q, int32_t frame, hipStream_t s);
 
-// Smoothed clearance score: the TSDF as one float per voxel of every block
-// (tau where W = 0) and the block id of every brick of the dense grid.
+// Smoothed clearance score.  T9: apron bricks of 9^3 floats (a brick's 8^3
+// voxels and the first layer of its +1 neighbours; tau where unmapped);
+// bid9: apron index of every brick of the dense grid (-1: no mapped voxel
+// within reach of a cell based in that brick).
 struct SmoothField {
-  const float *T;       // [n_blocks * 512], metres
-  const int32_t *bid;   // [grid bricks], -1 for no block
+  const float *T9;
+  const int32_t *bid9;
   int32_t g0[3], gd[3];
   float tau;            // metres
 };
-void launch_smooth_prepare(const Params &p, MapDev m, int64_t n_blocks, GridDev g, float *T,
-                           int32_t *bid, int64_t grid_bricks, float tau, hipStream_t s);
+struct SmoothBuffers {
+  float *T;             // [n_blocks * 512] per-voxel values (intermediate)
+  int32_t *bid;         // [grid bricks] block id or -1 (intermediate)
+  int32_t *bid9;        // [grid bricks]
+  int32_t *brick_of;    // [apron_cap] grid brick of each apron
+  float *T9;            // [apron_cap * 729]
+  int32_t *count;       // aprons made
+  int64_t apron_cap;
+};
+void launch_smooth_prepare(const Params &p, MapDev m, int64_t n_blocks, GridDev g,
+                           int64_t grid_bricks, float tau, const SmoothBuffers &b,
+                           hipStream_t s);
 void launch_smooth_eval(const SmoothField &f, double v, const float *p, const float *q, int64_t n,
                         const float *samples, int32_t M, float c, float tau_s,
                         const float *grad_s, float *s_out, float *dq, float *dp, hipStream_t s);

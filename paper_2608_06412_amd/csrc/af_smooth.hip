@@ -10,9 +10,14 @@
 //
 // Layout: one wave per (point, orientation) pair, one tool sample per lane,
 // so the 64 lanes read neighbouring voxels along the tool and the sums are a
-// wave reduction.  The TSDF is first expanded to one float per voxel of every
-// allocated block and a brick-to-block table over the dense brick grid, so a
-// tap is two loads with no hashing.
+// wave reduction.  The TSDF is first expanded into "apron" bricks of 9^3
+// floats: brick b holds voxels 8b .. 8b + 8 on each axis, i.e. its own 8^3
+// voxels plus the first layer of its +x/+y/+z neighbours, so the 2^3 voxels
+// of any interpolation cell whose lowest corner lies in b are all in b's
+// apron brick.  Apron bricks exist for every mapped brick and every brick
+// with a mapped +1 neighbour (the "halo"); a brick-to-apron table over the
+// dense brick grid finds them, so a sample costs one table load and eight
+// value loads, with no hashing and no per-tap bounds logic.
 //
 // Precision: the placement of a sample in its voxel cell (p + R o, divided by
 // v) is computed in double precision, because an fp32 position is only good
@@ -37,10 +42,11 @@ k_smooth_values(MapDev m, int64_t n_vox, double scale, float tau, float *T) {
   T[i] = W > 0 ? (float)(((double)m.S[i] / (double)W) / scale) : tau;
 }
 
-__global__ void __launch_bounds__(kSmoothThreads) k_smooth_bid_clear(int32_t *bid, int64_t n) {
+__global__ void __launch_bounds__(kSmoothThreads)
+k_smooth_fill(int32_t *a, int64_t n, int32_t value) {
   for (int64_t i = (int64_t)blockIdx.x * kSmoothThreads + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * kSmoothThreads)
-    bid[i] = -1;
+    a[i] = value;
 }
 
 __global__ void __launch_bounds__(kSmoothThreads)
@@ -55,20 +61,83 @@ k_smooth_bid(MapDev m, int64_t n_blocks, GridDev g, int32_t *bid) {
     bid[((int64_t)z * g.gd[1] + y) * g.gd[0] + x] = (int32_t)id;
 }
 
+// Apron bricks: mark every brick whose cell may reach a mapped brick (the
+// mapped brick itself and its -1 neighbours along any set of axes).
+__global__ void __launch_bounds__(kSmoothThreads)
+k_apron_mark(MapDev m, int64_t n_blocks, GridDev g, int32_t *bid9) {
+  const int64_t id = (int64_t)blockIdx.x * kSmoothThreads + threadIdx.x;
+  if (id >= n_blocks) return;
+  int32_t b[3];
+  unpack_key(m.bkey[id], b[0], b[1], b[2]);
+  for (int k = 0; k < 8; ++k) {
+    const int x = b[0] - g.g0[0] - (k & 1), y = b[1] - g.g0[1] - ((k >> 1) & 1),
+              z = b[2] - g.g0[2] - (k >> 2);
+    if ((unsigned)x < (unsigned)g.gd[0] && (unsigned)y < (unsigned)g.gd[1] &&
+        (unsigned)z < (unsigned)g.gd[2])
+      bid9[((int64_t)z * g.gd[1] + y) * g.gd[0] + x] = -2;
+  }
+}
+
+// Number the marked bricks (any order) and record each apron's brick.
+// (cap is at least the number of marked bricks, 8 per mapped block at most;
+// an index past it would be left unmapped rather than read out of bounds.)
+__global__ void __launch_bounds__(kSmoothThreads)
+k_apron_assign(int32_t *bid9, int64_t n_bricks, int32_t *count, int32_t *brick_of, int64_t cap) {
+  for (int64_t i = (int64_t)blockIdx.x * kSmoothThreads + threadIdx.x; i < n_bricks;
+       i += (int64_t)gridDim.x * kSmoothThreads)
+    if (bid9[i] == -2) {
+      const int32_t e = atomicAdd(count, 1);
+      if (e >= 0 && e < cap) {
+        bid9[i] = e;
+        brick_of[e] = (int32_t)i;
+      } else {
+        bid9[i] = -1;
+      }
+    }
+}
+
+// Fill apron e: voxel (lx, ly, lz) in [0, 9)^3 of brick brick_of[e].
+__global__ void __launch_bounds__(kSmoothThreads)
+k_apron_fill(const int32_t *count, const int32_t *brick_of, GridDev g, const int32_t *bid,
+             const float *T, float tau, int64_t cap, float *T9) {
+  const int64_t i = (int64_t)blockIdx.x * kSmoothThreads + threadIdx.x;
+  const int64_t e = i / 729;
+  if (e >= cap || e >= *count) return;
+  const int v = (int)(i - e * 729);
+  const int lx = v % 9, ly = (v / 9) % 9, lz = v / 81;
+  const int64_t br = brick_of[e];
+  const int bx = (int)(br % g.gd[0]), by = (int)((br / g.gd[0]) % g.gd[1]),
+            bz = (int)(br / ((int64_t)g.gd[0] * g.gd[1]));
+  const int x = bx + (lx >> 3), y = by + (ly >> 3), z = bz + (lz >> 3);
+  float t = tau;
+  if (x < g.gd[0] && y < g.gd[1] && z < g.gd[2]) {
+    const int32_t id = bid[((int64_t)z * g.gd[1] + y) * g.gd[0] + x];
+    if (id >= 0) t = T[(int64_t)id * 512 + ((lx & 7) | ((ly & 7) << 3) | ((lz & 7) << 6))];
+  }
+  T9[i] = t;
+}
+
 __device__ inline float wave_sum(float x) {
   for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off);
   return x;
 }
 
-// T of voxel (X, Y, Z): tau outside the grid or in an unallocated brick.
-__device__ inline float smooth_tap(const SmoothField &f, int X, int Y, int Z) {
+// The 2^3 voxel values of the cell whose lowest corner is voxel (X, Y, Z),
+// t[a | b << 1 | c << 2] for corner (X + a, Y + b, Z + c); tau where unmapped.
+__device__ inline void cell_values(const SmoothField &f, int X, int Y, int Z, float t[8]) {
   const int bx = (X >> 3) - f.g0[0], by = (Y >> 3) - f.g0[1], bz = (Z >> 3) - f.g0[2];
-  if ((unsigned)bx >= (unsigned)f.gd[0] || (unsigned)by >= (unsigned)f.gd[1] ||
-      (unsigned)bz >= (unsigned)f.gd[2])
-    return f.tau;
-  const int32_t id = f.bid[((int64_t)bz * f.gd[1] + by) * f.gd[0] + bx];
-  if (id < 0) return f.tau;
-  return f.T[(int64_t)id * 512 + ((X & 7) | ((Y & 7) << 3) | ((Z & 7) << 6))];
+  int32_t e = -1;
+  if ((unsigned)bx < (unsigned)f.gd[0] && (unsigned)by < (unsigned)f.gd[1] &&
+      (unsigned)bz < (unsigned)f.gd[2])
+    e = f.bid9[((int64_t)bz * f.gd[1] + by) * f.gd[0] + bx];
+  if (e < 0) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) t[k] = f.tau;
+    return;
+  }
+  const float *c = f.T9 + (int64_t)e * 729 + (Z & 7) * 81 + (Y & 7) * 9 + (X & 7);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) t[k] = c[(k & 1) + ((k >> 1) & 1) * 9 + (k >> 2) * 81];
 }
 
 // A pair's point as integer voxel coordinate + fraction of p / v - 1/2.
@@ -147,11 +216,13 @@ __device__ inline float smooth_sample(const SmoothField &f, const PairBase &pb, 
     fr[a] = (float)(gl - fl);
     u[a] = (float)ud;
   }
+  float tv[8];
+  cell_values(f, cell[0], cell[1], cell[2], tv);
   float val = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     const int a = k & 1, b = (k >> 1) & 1, cc = k >> 2;
-    const float t = smooth_tap(f, cell[0] + a, cell[1] + b, cell[2] + cc);
+    const float t = tv[k];
     const float wx = a ? fr[0] : 1.f - fr[0], wy = b ? fr[1] : 1.f - fr[1],
                 wz = cc ? fr[2] : 1.f - fr[2];
     val += wx * wy * wz * t;
@@ -185,7 +256,7 @@ __device__ inline float smooth_sample(const SmoothField &f, const PairBase &pb, 
     dqn[3] += 2.f * (g0 * (-zz * ox - w * oy + x * oz) + g1 * (w * ox - zz * oy + y * oz) +
                      g2 * (x * ox + y * oy + zz * oz)) - 2.f * zz * gu;
   }
-  return log_sigmoid(z);
+  return G == 2 ? 0.f : log_sigmoid(z);
 }
 
 // s of one pair (wave-uniform result), gradients reduced over the wave.
@@ -204,7 +275,7 @@ __device__ inline float smooth_pair(const SmoothField &f, const PairBase &pb, co
       s += smooth_sample<G>(f, pb, r, inv_v, o, c, inv_ts, gs, dp, dqn);
     }
   }
-  s = wave_sum(s);
+  if (G != 2) s = wave_sum(s);
   if (G == 1)
     for (int a = 0; a < 3; ++a) dp[a] = wave_sum(dp[a]);
   if (G > 0)
@@ -298,20 +369,27 @@ unsigned smooth_grid(int64_t pairs) {
 
 }  // namespace
 
-void launch_smooth_prepare(const Params &p, MapDev m, int64_t n_blocks, GridDev g, float *T,
-                           int32_t *bid, int64_t grid_bricks, float tau, hipStream_t s) {
+void launch_smooth_prepare(const Params &p, MapDev m, int64_t n_blocks, GridDev g,
+                           int64_t grid_bricks, float tau, const SmoothBuffers &b,
+                           hipStream_t s) {
   const int64_t nv = n_blocks * 512;
-  if (nv > 0)
-    hipLaunchKernelGGL(k_smooth_values, dim3((unsigned)((nv + kSmoothThreads - 1) / kSmoothThreads)),
-                       dim3(kSmoothThreads), 0, s, m, nv, p.scale, tau, T);
-  if (grid_bricks > 0) {
-    const int64_t wg = std::min<int64_t>(4096, (grid_bricks + kSmoothThreads - 1) / kSmoothThreads);
-    hipLaunchKernelGGL(k_smooth_bid_clear, dim3((unsigned)wg), dim3(kSmoothThreads), 0, s, bid,
-                       grid_bricks);
-  }
-  if (n_blocks > 0 && grid_bricks > 0)
-    hipLaunchKernelGGL(k_smooth_bid, dim3((unsigned)((n_blocks + kSmoothThreads - 1) / kSmoothThreads)),
-                       dim3(kSmoothThreads), 0, s, m, n_blocks, g, bid);
+  auto blocks = [](int64_t n) { return dim3((unsigned)((n + kSmoothThreads - 1) / kSmoothThreads)); };
+  const dim3 strided((unsigned)std::min<int64_t>(4096, (grid_bricks + kSmoothThreads - 1) / kSmoothThreads));
+  hipLaunchKernelGGL(k_smooth_fill, dim3(1), dim3(kSmoothThreads), 0, s, b.count, 1, 0);
+  if (grid_bricks <= 0) return;
+  hipLaunchKernelGGL(k_smooth_fill, strided, dim3(kSmoothThreads), 0, s, b.bid, grid_bricks, -1);
+  hipLaunchKernelGGL(k_smooth_fill, strided, dim3(kSmoothThreads), 0, s, b.bid9, grid_bricks, -1);
+  if (n_blocks <= 0) return;
+  hipLaunchKernelGGL(k_smooth_values, blocks(nv), dim3(kSmoothThreads), 0, s, m, nv, p.scale, tau,
+                     b.T);
+  hipLaunchKernelGGL(k_smooth_bid, blocks(n_blocks), dim3(kSmoothThreads), 0, s, m, n_blocks, g,
+                     b.bid);
+  hipLaunchKernelGGL(k_apron_mark, blocks(n_blocks), dim3(kSmoothThreads), 0, s, m, n_blocks, g,
+                     b.bid9);
+  hipLaunchKernelGGL(k_apron_assign, strided, dim3(kSmoothThreads), 0, s, b.bid9, grid_bricks,
+                     b.count, b.brick_of, b.apron_cap);
+  hipLaunchKernelGGL(k_apron_fill, blocks(b.apron_cap * 729), dim3(kSmoothThreads), 0, s, b.count,
+                     b.brick_of, g, b.bid, b.T, tau, b.apron_cap, b.T9);
 }
 
 void launch_smooth_eval(const SmoothField &f, double v, const float *p, const float *q, int64_t n,
