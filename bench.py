@@ -453,9 +453,23 @@ def run_smooth(args):
     n_map = ctx.num_points()
     allk = ctx.read_points()["key"]
     rng = np.random.default_rng(11)
-    n_pts = 1000000
+    n_pts = args.smooth_points
     sel = allk[rng.choice(len(allk), n_pts, replace=len(allk) < n_pts)]
-    p = ((unpack_keys(sel) + 0.5) * w.voxel).astype(np.float32)
+    ijk = unpack_keys(sel)
+
+    def morton(b):
+        # interleaved bits of the brick coordinates (16 bits per axis)
+        b = (b - b.min(0)).astype(np.uint64)
+        code = np.zeros(len(b), np.uint64)
+        for bit in range(16):
+            for a in range(3):
+                code |= ((b[:, a] >> np.uint64(bit)) & np.uint64(1)) << np.uint64(3 * bit + a)
+        return code
+    # the caller's pair order: points in Morton order of their bricks, so the
+    # waves that share an L2 read neighbouring parts of the map
+    order = np.lexsort((sel, morton(ijk >> 3)))
+    p = ((ijk[order] + 0.5) * w.voxel).astype(np.float32)
+    p_random = ((ijk + 0.5) * w.voxel).astype(np.float32)
     S = 64
     q0 = np.tile(synth.quaternion_towards(synth.fibonacci_directions(S)), (n_pts, 1))
     smp = synth.tool_samples(w.tool, 16)
@@ -479,13 +493,20 @@ def run_smooth(args):
     wall = (time.perf_counter() - t0) / K
     tm = ctx.timing_read(reset=True)
     k_ms = tm["k_smooth_ms"] / K
+    # the same pairs in random point order, for comparison
+    pr = torch.from_numpy(p_random).cuda()
+    ctx.smooth_refine(pr, qd, sd, steps=steps, eta=eta, max_step=mx)
+    torch.cuda.synchronize()
+    k_ms_random = ctx.timing_read(reset=True)["k_smooth_ms"]
+    del pr
     # the ascent's own check: s at the start against s at the end, per pair
     s_start = torch.empty(pairs, device="cuda")
     ctx.smooth_eval(pd.repeat_interleave(S, 0), qd, sd, s=s_start)
     torch.cuda.synchronize()
     gain = (s - s_start).cpu().numpy()
     taps = pairs * (steps + 1) * len(smp) * 8
-    bytes_alg = taps * 8.0          # a float of T and a brick id per tap
+    # per sample: the apron index of its cell's brick and the cell's 8 values
+    bytes_alg = pairs * (steps + 1) * len(smp) * 36.0
     ach = bytes_alg / (k_ms / 1e3) / 1e9
     out = {
         "metric": "smoothed-score ascent: (point, start) pairs x steps per second",
@@ -495,12 +516,13 @@ def run_smooth(args):
         "ms_per_step": k_ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "smooth: tree map after %d frames, 1,000,000 surface points x 64 "
+        "config": {"workload": "smooth: tree map after %d frames, %d surface points x 64 "
                                "starts, saw box as 64 samples, 20 ascent steps, c = 1 cm, "
-                               "tau_s = 0.5 cm" % F,
+                               "tau_s = 0.5 cm" % (F, n_pts),
                    "map_points": int(n_map), "pairs": pairs, "ascent_steps": steps,
                    "samples": len(smp), "eta": eta, "max_step": mx},
         "wall_ms_per_refine": wall * 1e3,
+        "random_point_order_ms": k_ms_random,
         "sample_evaluations_per_s": pairs * (steps + 1) * len(smp) / (k_ms / 1e3),
         "taps_per_s": taps / (k_ms / 1e3),
         "ascent": {"improved_frac": float((gain > 0).mean()),
@@ -508,8 +530,9 @@ def run_smooth(args):
                    "mean_gain": float(gain.mean())},
         "roofline": {"kernel": "k_smooth_refine", "bound": "hbm", "achieved": ach, "peak": 8000.0,
                      "unit": "GB/s", "frac": ach / 8000.0, "traffic": None,
-                     "bytes_model": "8 B per trilinear tap (T value + brick id), 8 taps per "
-                                    "sample, 64 samples, 21 evaluations per pair"},
+                     "bytes_model": "36 B per sample evaluation (apron index + 8 cell values "
+                                    "of 4 B), 64 samples, 21 evaluations per pair; mostly "
+                                    "L2 hits, so this is demand, not DRAM traffic"},
     }
     if not args.no_cpu_baseline:
         import oracle
@@ -548,6 +571,8 @@ def main():
     ap.add_argument("--workload", default="tree", choices=["tree", "batch", "serve", "smooth"],
                     help="tree: the default single-tool workload; batch: 8 tools x 512 "
                          "orientations scored in one launch, frames of 5k-40k returns")
+    ap.add_argument("--smooth-points", type=int, default=1000000,
+                    help="surface points of the smooth workload (64 starts each)")
     ap.add_argument("--trace-summary", default=None,
                     help="only summarise a rocprofv3 kernel_trace.csv of a bench run "
                          "with the same --warmup/--steps")

@@ -956,7 +956,7 @@ static int smooth_prepare(af_ctx *c, hipStream_t s, SmoothField &f) {
   const int64_t nb = std::max<int64_t>(1, c->grid_bricks);
   // every mapped block marks itself and its -1 neighbours: at most 8 aprons each
   const int64_t na = std::max<int64_t>(1, std::min<int64_t>(8 * c->n_blocks, c->grid_bricks));
-  if (nv > c->sm_T_cap || nb > c->sm_bid_cap || na > b.apron_cap || !b.count) {
+  if (nv > c->sm_T_cap || nb > c->sm_bid_cap || na > b.apron_cap || !b.count || !b.work) {
     HIP_TRY(c, hipStreamSynchronize(s));
     if (nv > c->sm_T_cap) {
       if (b.T) dev_free(c, b.T, sizeof(float) * c->sm_T_cap);
@@ -987,6 +987,7 @@ static int smooth_prepare(af_ctx *c, hipStream_t s, SmoothField &f) {
       b.apron_cap = cap;
     }
     if (!b.count) ALLOC(c, b.count, 1);
+    if (!b.work) ALLOC(c, b.work, 8);   // one counter per XCD
   }
   const float tau = (float)((double)c->p.tau_u / c->p.scale);
   launch_smooth_prepare(c->p, c->map, c->n_blocks, c->grid, c->grid_bricks, tau, b, s);
@@ -1016,7 +1017,7 @@ int af_smooth_eval(af_ctx *c, const float *p, const float *q, int64_t n, const f
   int rc = smooth_prepare(c, s, f);
   if (rc != AF_OK) return rc;
   launch_smooth_eval(f, 256.0 / c->p.scale, p, q, n, samples, M, c_thr, tau_s, grad_s, s_out, dq,
-                     dp, s);
+                     dp, c->sm.work, s);
   c->last_stream = s;
   return hip_check(c, "smooth eval");
 }
@@ -1037,7 +1038,7 @@ int af_smooth_refine(af_ctx *c, const float *p, int64_t n_points, const float *q
   if (rc != AF_OK) return rc;
   hipEvent_t t0 = timing_mark(c, s);
   launch_smooth_refine(f, 256.0 / c->p.scale, p, n_points, q0, n_starts, samples, M, c_thr, tau_s,
-                       steps, eta, max_step, q_out, s_out, s);
+                       steps, eta, max_step, q_out, s_out, c->sm.work, s);
   hipEvent_t t1 = timing_mark(c, s);
   if (c->timing) timing_pair(c, ST_K_SMOOTH, t0, t1);
   c->last_stream = s;

@@ -249,6 +249,7 @@ struct SmoothBuffers {
   int32_t *brick_of;    // [apron_cap] grid brick of each apron
   float *T9;            // [apron_cap * 729]
   int32_t *count;       // aprons made
+  unsigned long long *work;   // [8] pairs handed out from each XCD's range
   int64_t apron_cap;
 };
 void launch_smooth_prepare(const Params &p, MapDev m, int64_t n_blocks, GridDev g,
@@ -256,11 +257,12 @@ void launch_smooth_prepare(const Params &p, MapDev m, int64_t n_blocks, GridDev 
                            hipStream_t s);
 void launch_smooth_eval(const SmoothField &f, double v, const float *p, const float *q, int64_t n,
                         const float *samples, int32_t M, float c, float tau_s,
-                        const float *grad_s, float *s_out, float *dq, float *dp, hipStream_t s);
+                        const float *grad_s, float *s_out, float *dq, float *dp,
+                        unsigned long long *work, hipStream_t s);
 void launch_smooth_refine(const SmoothField &f, double v, const float *p, int64_t n_points,
                           const float *q0, int32_t n_starts, const float *samples, int32_t M,
                           float c, float tau_s, int32_t steps, float eta, float max_step,
-                          float *q_out, float *s_out, hipStream_t s);
+                          float *q_out, float *s_out, unsigned long long *work, hipStream_t s);
 void launch_stick_status(FrameCounters *c, hipStream_t s);
 void launch_zero_words(void *p, int64_t bytes, hipStream_t s);   // a fill kernel (graph-safe)
 // nb: an upper bound of the frame's returns (sizes the launches)

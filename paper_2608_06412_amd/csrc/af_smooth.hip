@@ -23,11 +23,17 @@
 // v) is computed in double precision, because an fp32 position is only good
 // to ~1e-5 voxel at metre scale and the gradient's relative error follows the
 // cell fractions; interpolation, score and adjoint are fp32.  The quaternion
-// derivative uses the degree-0 homogeneous form of the rotation,
-// R(q) = P(q) / |q|^2, whose gradient has no radial part, so no projection
-// (and no cancellation) is needed to pass through the normalisation.
+// derivative comes from the torque: a small rotation dtheta applied after R
+// moves sample u = R o by dtheta x u, so s changes by dtheta . sum(u x g) with
+// g the weighted TSDF gradient; with dq = (0, dtheta) q / 2 this gives
+// ds/dq = 2 (-tau.v, w tau + tau x v) / |q| for q / |q| = (w, v) and
+// tau = sum(u x g) -- three sums per pair instead of four, no projection.
+// This file lets the compiler fuse multiply-adds (unlike the table builder,
+// nothing here needs to round like the oracle).
 
 #include "af_internal.h"
+
+#pragma clang fp contract(fast)
 
 namespace af {
 namespace {
@@ -191,20 +197,18 @@ __device__ inline float log_sigmoid(float z) {
   return z >= 0.f ? -log1pf(expf(-z)) : z - log1pf(expf(z));
 }
 
+// sigma(-z) = 1 / (1 + e^z) with the hardware exponential and reciprocal
+// (about 1 ulp each; e^z = inf gives 0).
 __device__ inline float sigmoid_neg(float z) {
-  if (z >= 0.f) {
-    const float e = expf(-z);
-    return e / (1.f + e);
-  }
-  return 1.f / (1.f + expf(z));
+  return __builtin_amdgcn_rcpf(1.f + __expf(z));
 }
 
-// One sample: returns its log sigma term; with G > 0 adds gs |q| ds/dq (4)
-// and, with G == 1, gs ds/dp (3).
+// One sample: returns its log sigma term (not with G == 2); with G > 0 adds
+// the torque gs (u x dT/dx) into tq and, with G == 1, gs dT/dx into dp.
 template <int G>
 __device__ inline float smooth_sample(const SmoothField &f, const PairBase &pb, const Rot &r,
                                       double inv_v, const float o[3], float c, float inv_ts,
-                                      float gs, float dp[3], float dqn[4]) {
+                                      float gs, float dp[3], float tq[3]) {
   int cell[3];
   float fr[3], u[3];
   for (int a = 0; a < 3; ++a) {
@@ -216,95 +220,140 @@ __device__ inline float smooth_sample(const SmoothField &f, const PairBase &pb, 
     fr[a] = (float)(gl - fl);
     u[a] = (float)ud;
   }
-  float tv[8];
-  cell_values(f, cell[0], cell[1], cell[2], tv);
-  float val = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const int a = k & 1, b = (k >> 1) & 1, cc = k >> 2;
-    const float t = tv[k];
-    const float wx = a ? fr[0] : 1.f - fr[0], wy = b ? fr[1] : 1.f - fr[1],
-                wz = cc ? fr[2] : 1.f - fr[2];
-    val += wx * wy * wz * t;
-    if (G > 0) {
-      gx += (a ? 1.f : -1.f) * wy * wz * t;
-      gy += wx * (b ? 1.f : -1.f) * wz * t;
-      gz += wx * wy * (cc ? 1.f : -1.f) * t;
-    }
-  }
+  float t[8];
+  cell_values(f, cell[0], cell[1], cell[2], t);
+  const float fx = fr[0], fy = fr[1], fz = fr[2];
+  // trilinear interpolation as lerps along x, then y, then z
+  const float a00 = t[0] + fx * (t[1] - t[0]), a10 = t[2] + fx * (t[3] - t[2]);
+  const float a01 = t[4] + fx * (t[5] - t[4]), a11 = t[6] + fx * (t[7] - t[6]);
+  const float b0 = a00 + fy * (a10 - a00), b1 = a01 + fy * (a11 - a01);
+  const float val = b0 + fz * (b1 - b0);
   const float z = (val - c) * inv_ts;
   if (G > 0) {
-    const float wgt = sigmoid_neg(z) * inv_ts * gs;
-    const float iv = (float)inv_v;
-    const float g0 = wgt * gx * iv, g1 = wgt * gy * iv, g2 = wgt * gz * iv;
+    // derivatives of the interpolant in cell units
+    const float dx0 = (t[1] - t[0]) + fy * ((t[3] - t[2]) - (t[1] - t[0]));
+    const float dx1 = (t[5] - t[4]) + fy * ((t[7] - t[6]) - (t[5] - t[4]));
+    const float gx = dx0 + fz * (dx1 - dx0);
+    const float gy = (a10 - a00) + fz * ((a11 - a01) - (a10 - a00));
+    const float gz = b1 - b0;
+    const float wgt = sigmoid_neg(z) * inv_ts * gs * (float)inv_v;
+    const float g0 = wgt * gx, g1 = wgt * gy, g2 = wgt * gz;
     if (G == 1) {
       dp[0] += g0;
       dp[1] += g1;
       dp[2] += g2;
     }
-    // R o = P(q) o / |q|^2 with P quadratic: at |q| = 1,
-    // d(R o)/dq_a = dP/dq_a o - 2 q_a (R o), which is orthogonal to q.
-    const float w = r.qn[0], x = r.qn[1], y = r.qn[2], zz = r.qn[3];
-    const float ox = o[0], oy = o[1], oz = o[2];
-    const float gu = g0 * u[0] + g1 * u[1] + g2 * u[2];
-    dqn[0] += 2.f * (g0 * (w * ox - zz * oy + y * oz) + g1 * (zz * ox + w * oy - x * oz) +
-                     g2 * (-y * ox + x * oy + w * oz)) - 2.f * w * gu;
-    dqn[1] += 2.f * (g0 * (x * ox + y * oy + zz * oz) + g1 * (y * ox - x * oy - w * oz) +
-                     g2 * (zz * ox + w * oy - x * oz)) - 2.f * x * gu;
-    dqn[2] += 2.f * (g0 * (-y * ox + x * oy + w * oz) + g1 * (x * ox + y * oy + zz * oz) +
-                     g2 * (-w * ox + zz * oy - y * oz)) - 2.f * y * gu;
-    dqn[3] += 2.f * (g0 * (-zz * ox - w * oy + x * oz) + g1 * (w * ox - zz * oy + y * oz) +
-                     g2 * (x * ox + y * oy + zz * oz)) - 2.f * zz * gu;
+    tq[0] += u[1] * g2 - u[2] * g1;
+    tq[1] += u[2] * g0 - u[0] * g2;
+    tq[2] += u[0] * g1 - u[1] * g0;
   }
   return G == 2 ? 0.f : log_sigmoid(z);
 }
 
 // s of one pair (wave-uniform result), gradients reduced over the wave.
+// o0: the lane's sample of the first 64 (loaded once per kernel).
 template <int G>
 __device__ inline float smooth_pair(const SmoothField &f, const PairBase &pb, const Rot &r,
-                                    double inv_v, const float *samples, int M, float c,
-                                    float inv_ts, float gs, float dp[3], float dqn[4]) {
+                                    double inv_v, const float *samples, int M, const float o0[3],
+                                    float c, float inv_ts, float gs, float dp[3], float tq[3]) {
   const int lane = threadIdx.x & 63;
   float s = 0.f;
-  for (int a = 0; a < 3; ++a) dp[a] = 0.f;
-  for (int a = 0; a < 4; ++a) dqn[a] = 0.f;
-  for (int m0 = 0; m0 < M; m0 += 64) {
+  for (int a = 0; a < 3; ++a) dp[a] = tq[a] = 0.f;
+  if (lane < M) s += smooth_sample<G>(f, pb, r, inv_v, o0, c, inv_ts, gs, dp, tq);
+  for (int m0 = 64; m0 < M; m0 += 64) {
     const int m = m0 + lane;
     if (m < M) {
       const float o[3] = {samples[3 * m], samples[3 * m + 1], samples[3 * m + 2]};
-      s += smooth_sample<G>(f, pb, r, inv_v, o, c, inv_ts, gs, dp, dqn);
+      s += smooth_sample<G>(f, pb, r, inv_v, o, c, inv_ts, gs, dp, tq);
     }
   }
   if (G != 2) s = wave_sum(s);
   if (G == 1)
     for (int a = 0; a < 3; ++a) dp[a] = wave_sum(dp[a]);
   if (G > 0)
-    for (int a = 0; a < 4; ++a) dqn[a] = wave_sum(dqn[a]);
+    for (int a = 0; a < 3; ++a) tq[a] = wave_sum(tq[a]);
   return s;
 }
 
-// The homogeneous form's gradient at q / |q| scales by 1 / |q| at q.
-__device__ inline void unnormalise(const Rot &r, const float dqn[4], float dq[4]) {
-  for (int a = 0; a < 4; ++a) dq[a] = dqn[a] / r.nq;
+// ds/dq from the torque tau: 2 (-tau.v, w tau + tau x v) / |q|.
+__device__ inline void unnormalise(const Rot &r, const float tq[3], float dq[4]) {
+  const float w = r.qn[0], x = r.qn[1], y = r.qn[2], z = r.qn[3];
+  const float k = 2.f / r.nq;
+  dq[0] = -k * (tq[0] * x + tq[1] * y + tq[2] * z);
+  dq[1] = k * (w * tq[0] + tq[1] * z - tq[2] * y);
+  dq[2] = k * (w * tq[1] + tq[2] * x - tq[0] * z);
+  dq[3] = k * (w * tq[2] + tq[0] * y - tq[1] * x);
+}
+
+constexpr int kSmoothBatch = 16;   // pairs a wave takes from a work counter at once
+constexpr int kXcds = 8;           // workgroup i runs on XCD i mod 8, each with its own L2
+
+// Work distribution: the pairs are cut into kXcds contiguous ranges, one per
+// XCD, so that (with pairs ordered in space) the waves sharing an L2 read the
+// same part of the map; a wave whose range is exhausted helps the next ones.
+// work[x] counts the pairs handed out from range x.
+struct PairQueue {
+  unsigned long long *work;
+  int64_t n;
+  int x;       // range being taken from
+  int tried;   // ranges exhausted so far
+};
+
+__device__ inline PairQueue pair_queue(unsigned long long *work, int64_t n) {
+  PairQueue pq;
+  pq.work = work;
+  pq.n = n;
+  pq.x = blockIdx.x % kXcds;
+  pq.tried = 0;
+  return pq;
+}
+
+// First pair of the wave's next batch, -1 when every range is done
+// (wave-uniform); the batch ends at the range's end.
+__device__ inline int64_t take_batch(PairQueue &pq, int64_t &end) {
+  while (pq.tried < kXcds) {
+    const int64_t lo = pq.n * pq.x / kXcds, hi = pq.n * (pq.x + 1) / kXcds;
+    unsigned long long b = 0;
+    if ((threadIdx.x & 63) == 0) b = atomicAdd(&pq.work[pq.x], (unsigned long long)kSmoothBatch);
+    const int64_t i = lo + (int64_t)__shfl(b, 0);
+    if (i < hi) {
+      end = i + kSmoothBatch < hi ? i + kSmoothBatch : hi;
+      return i;
+    }
+    pq.x = (pq.x + 1) % kXcds;
+    ++pq.tried;
+  }
+  return -1;
+}
+
+__device__ inline void lane_sample(const float *samples, int M, float o[3]) {
+  const int lane = threadIdx.x & 63;
+  const int m = lane < M ? lane : 0;
+  o[0] = samples[3 * m];
+  o[1] = samples[3 * m + 1];
+  o[2] = samples[3 * m + 2];
 }
 
 template <int G>
 __global__ void __launch_bounds__(kSmoothThreads)
 k_smooth_eval(SmoothField f, double v, const float *p, const float *q, int64_t n,
               const float *samples, int M, float c, float tau_s, const float *grad_s,
-              float *s_out, float *dq_out, float *dp_out) {
+              float *s_out, float *dq_out, float *dp_out, unsigned long long *work) {
   const int lane = threadIdx.x & 63;
-  const int64_t nwaves = ((int64_t)gridDim.x * kSmoothThreads) >> 6;
   const double inv_v = 1.0 / v;
   const float inv_ts = 1.f / tau_s;
-  for (int64_t i = ((int64_t)blockIdx.x * kSmoothThreads + threadIdx.x) >> 6; i < n;
-       i += nwaves) {
+  float o0[3];
+  lane_sample(samples, M, o0);
+  PairQueue pq = pair_queue(work, n);
+  int64_t end = 0;
+  for (int64_t b0 = take_batch(pq, end); b0 >= 0; b0 = take_batch(pq, end))
+  for (int64_t i = b0; i < end; ++i) {
     const PairBase pb = pair_base(p + 3 * i, v);
     const float q4[4] = {q[4 * i], q[4 * i + 1], q[4 * i + 2], q[4 * i + 3]};
     const Rot r = make_rot(q4);
     const float gs = grad_s ? grad_s[i] : 1.f;
-    float dp[3], dqn[4];
-    const float s = smooth_pair<G>(f, pb, r, inv_v, samples, M, c, inv_ts, gs, dp, dqn);
+    float dp[3], dqn[3];
+    const float s = smooth_pair<G>(f, pb, r, inv_v, samples, M, o0, c, inv_ts, gs, dp, dqn);
     if (lane == 0) {
       if (s_out) s_out[i] = s;
       if (G == 1) {
@@ -323,20 +372,24 @@ k_smooth_eval(SmoothField f, double v, const float *p, const float *q, int64_t n
 __global__ void __launch_bounds__(kSmoothThreads)
 k_smooth_refine(SmoothField f, double v, const float *p, int64_t n_points, const float *q0,
                 int n_starts, const float *samples, int M, float c, float tau_s, int steps,
-                float eta, float max_step, float *q_out, float *s_out) {
+                float eta, float max_step, float *q_out, float *s_out,
+                unsigned long long *work) {
   const int lane = threadIdx.x & 63;
   const int64_t n = n_points * n_starts;
-  const int64_t nwaves = ((int64_t)gridDim.x * kSmoothThreads) >> 6;
   const double inv_v = 1.0 / v;
   const float inv_ts = 1.f / tau_s;
-  for (int64_t i = ((int64_t)blockIdx.x * kSmoothThreads + threadIdx.x) >> 6; i < n;
-       i += nwaves) {
+  float o0[3];
+  lane_sample(samples, M, o0);
+  PairQueue pq = pair_queue(work, n);
+  int64_t end = 0;
+  for (int64_t b0 = take_batch(pq, end); b0 >= 0; b0 = take_batch(pq, end))
+  for (int64_t i = b0; i < end; ++i) {
     const PairBase pb = pair_base(p + 3 * (i / n_starts), v);
     float q[4] = {q0[4 * i], q0[4 * i + 1], q0[4 * i + 2], q0[4 * i + 3]};
-    float dp[3], dqn[4], dq[4];
+    float dp[3], dqn[3], dq[4];
     for (int t = 0; t < steps; ++t) {
       const Rot r = make_rot(q);
-      smooth_pair<2>(f, pb, r, inv_v, samples, M, c, inv_ts, 1.f, dp, dqn);
+      smooth_pair<2>(f, pb, r, inv_v, samples, M, o0, c, inv_ts, 1.f, dp, dqn);
       unnormalise(r, dqn, dq);
       float D[4], len = 0.f;
       for (int a = 0; a < 4; ++a) {
@@ -354,7 +407,7 @@ k_smooth_refine(SmoothField f, double v, const float *p, int64_t n_points, const
       for (int a = 0; a < 4; ++a) q[a] /= nn;
     }
     const Rot r = make_rot(q);
-    const float s = smooth_pair<0>(f, pb, r, inv_v, samples, M, c, inv_ts, 1.f, dp, dqn);
+    const float s = smooth_pair<0>(f, pb, r, inv_v, samples, M, o0, c, inv_ts, 1.f, dp, dqn);
     if (lane == 0) {
       s_out[i] = s;
       for (int a = 0; a < 4; ++a) q_out[4 * i + a] = r.qn[a];
@@ -362,9 +415,24 @@ k_smooth_refine(SmoothField f, double v, const float *p, int64_t n_points, const
   }
 }
 
-unsigned smooth_grid(int64_t pairs) {
-  const int64_t wg = (pairs + 3) / 4;   // four waves per workgroup
-  return (unsigned)(wg < 2048 ? (wg > 0 ? wg : 1) : 2048);
+// Workgroups that fit on the chip at once (the pairs are handed out by the
+// work counter, so a grid larger than that would only queue).
+unsigned smooth_grid(const void *fn, int64_t pairs) {
+  static int n_cu = 0;
+  if (n_cu == 0) {
+    int dev = 0;
+    hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        n_cu <= 0)
+      n_cu = 1;
+  }
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kSmoothThreads, 0) != hipSuccess ||
+      per_cu <= 0)
+    per_cu = 1;
+  const int64_t need = (pairs + 4 * kSmoothBatch - 1) / (4 * kSmoothBatch);
+  const int64_t wg = std::min<int64_t>((int64_t)per_cu * n_cu, need);
+  return (unsigned)std::max<int64_t>(1, wg);
 }
 
 }  // namespace
@@ -394,25 +462,33 @@ void launch_smooth_prepare(const Params &p, MapDev m, int64_t n_blocks, GridDev 
 
 void launch_smooth_eval(const SmoothField &f, double v, const float *p, const float *q, int64_t n,
                         const float *samples, int32_t M, float c, float tau_s,
-                        const float *grad_s, float *s_out, float *dq, float *dp, hipStream_t s) {
+                        const float *grad_s, float *s_out, float *dq, float *dp,
+                        unsigned long long *work, hipStream_t s) {
   if (n <= 0) return;
-  if (dq)
-    hipLaunchKernelGGL(k_smooth_eval<1>, dim3(smooth_grid(n)), dim3(kSmoothThreads), 0, s, f, v,
-                       p, q, n, samples, M, c, tau_s, grad_s, s_out, dq, dp);
-  else
-    hipLaunchKernelGGL(k_smooth_eval<0>, dim3(smooth_grid(n)), dim3(kSmoothThreads), 0, s, f, v,
-                       p, q, n, samples, M, c, tau_s, grad_s, s_out, dq, dp);
+  hipLaunchKernelGGL(k_smooth_fill, dim3(1), dim3(kSmoothThreads), 0, s, (int32_t *)work,
+                     2 * kXcds, 0);
+  if (dq) {
+    const void *fn = (const void *)k_smooth_eval<1>;
+    hipLaunchKernelGGL(k_smooth_eval<1>, dim3(smooth_grid(fn, n)), dim3(kSmoothThreads), 0, s, f,
+                       v, p, q, n, samples, M, c, tau_s, grad_s, s_out, dq, dp, work);
+  } else {
+    const void *fn = (const void *)k_smooth_eval<0>;
+    hipLaunchKernelGGL(k_smooth_eval<0>, dim3(smooth_grid(fn, n)), dim3(kSmoothThreads), 0, s, f,
+                       v, p, q, n, samples, M, c, tau_s, grad_s, s_out, dq, dp, work);
+  }
 }
 
 void launch_smooth_refine(const SmoothField &f, double v, const float *p, int64_t n_points,
                           const float *q0, int32_t n_starts, const float *samples, int32_t M,
                           float c, float tau_s, int32_t steps, float eta, float max_step,
-                          float *q_out, float *s_out, hipStream_t s) {
+                          float *q_out, float *s_out, unsigned long long *work, hipStream_t s) {
   const int64_t n = n_points * n_starts;
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_smooth_refine, dim3(smooth_grid(n)), dim3(kSmoothThreads), 0, s, f, v, p,
-                     n_points, q0, n_starts, samples, M, c, tau_s, steps, eta, max_step, q_out,
-                     s_out);
+  hipLaunchKernelGGL(k_smooth_fill, dim3(1), dim3(kSmoothThreads), 0, s, (int32_t *)work,
+                     2 * kXcds, 0);
+  hipLaunchKernelGGL(k_smooth_refine, dim3(smooth_grid((const void *)k_smooth_refine, n)),
+                     dim3(kSmoothThreads), 0, s, f, v, p, n_points, q0, n_starts, samples, M, c,
+                     tau_s, steps, eta, max_step, q_out, s_out, work);
 }
 
 }  // namespace af
