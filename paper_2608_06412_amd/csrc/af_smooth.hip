@@ -123,9 +123,25 @@ k_apron_fill(const int32_t *count, const int32_t *brick_of, GridDev g, const int
   T9[i] = t;
 }
 
+// x + the value DPP control `ctrl` routes to this lane (0 in rows outside
+// row_mask).
+template <int ctrl, int row_mask>
+__device__ inline float dpp_add(float x) {
+  const int y = __builtin_amdgcn_update_dpp(0, __float_as_int(x), ctrl, row_mask, 0xf, false);
+  return x + __int_as_float(y);
+}
+
+// Sum over the wave, returned in every lane: swaps within quads, mirrors
+// within half-rows and rows, then row broadcasts carry the row sums up to
+// lane 63, which is read back.
 __device__ inline float wave_sum(float x) {
-  for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off);
-  return x;
+  x = dpp_add<0xb1, 0xf>(x);    // quad_perm [1, 0, 3, 2]
+  x = dpp_add<0x4e, 0xf>(x);    // quad_perm [2, 3, 0, 1]
+  x = dpp_add<0x141, 0xf>(x);   // row_half_mirror
+  x = dpp_add<0x140, 0xf>(x);   // row_mirror
+  x = dpp_add<0x142, 0xa>(x);   // row_bcast:15 into rows 1 and 3
+  x = dpp_add<0x143, 0xc>(x);   // row_bcast:31 into rows 2 and 3
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
 }
 
 // The 2^3 voxel values of the cell whose lowest corner is voxel (X, Y, Z),
@@ -175,7 +191,8 @@ __device__ inline Rot make_rot(const float q[4]) {
   Rot r;
   const double q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3];
   const double n = sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
-  const double w = q0 / n, x = q1 / n, y = q2 / n, z = q3 / n;
+  const double in = 1.0 / n;
+  const double w = q0 * in, x = q1 * in, y = q2 * in, z = q3 * in;
   r.nq = (float)n;
   r.qn[0] = (float)w;
   r.qn[1] = (float)x;
