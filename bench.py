@@ -36,6 +36,8 @@ METRIC = ("point×orientation tests/s + returns integrated/s; p99 frame latency 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_score_tree.json")
 SCORE_SRC = os.path.join(ROOT, "paper_2608_06412_amd", "csrc", "af_score.hip")
+SMOOTH_SRC = os.path.join(ROOT, "paper_2608_06412_amd", "csrc", "af_smooth.hip")
+SMOOTH_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_smooth_refine.json")
 # kernels whose per-launch device time the bench reports (symbol prefixes)
 TRACE_KERNELS = ("k_score", "k_integrate_fold", "k_normals", "k_mask")
 
@@ -120,6 +122,76 @@ def trace_summary(csv_path, warmup, steps):
         out[base] = {"launches": int(len(d)), "avg_ms_all": float(d.mean()),
                      "avg_ms_timed": float(timed.mean()) if len(timed) else None,
                      "timed_launches": int(len(timed)), "symbol": rows[0][2][:120]}
+    return out
+
+
+def _counter_rows(csv_path, counter):
+    """(start time, kernel name, value) of every dispatch in a rocprofv3
+    counter-collection CSV (values of one dispatch summed)."""
+    import csv
+    per = {}
+    with open(csv_path) as f:
+        for row in csv.DictReader(f):
+            if row["Counter_Name"] != counter:
+                continue
+            key = row["Dispatch_Id"]
+            if key not in per:
+                per[key] = [int(row["Start_Timestamp"]), row["Kernel_Name"], 0.0]
+            per[key][2] += float(row["Counter_Value"])
+    return sorted(per.values())
+
+
+TRAFFIC_TARGETS = {
+    # workload: (kernel name pattern, source file, traffic file, description)
+    "tree": (r"\bk_score[A-Za-z0-9_]*\s*[<(]", "SCORE", "traffic_k_score_tree.json",
+             "k_score (default scoring configuration)"),
+    "smooth": (r"\bk_smooth_refine\s*[<(]", "SMOOTH", "traffic_k_smooth_refine.json",
+               "k_smooth_refine"),
+}
+
+
+def traffic_summary(paths, warmup, steps, copy_bytes, workload="tree"):
+    """The traffic file of a workload's dominant kernel from four rocprofv3
+    --pmc CSVs: FETCH_SIZE and WRITE_SIZE of a bench run of that workload
+    (the kernel's timed launches warmup..warmup+steps-1), and of the copy
+    probe of copy_bytes, which fixes the KiB-per-byte scale of each counter."""
+    fetch, write, cfetch, cwrite = paths
+    pattern, src_key, fname, desc = TRAFFIC_TARGETS[workload]
+    src = SCORE_SRC if src_key == "SCORE" else SMOOTH_SRC
+
+    def score_mean(path, counter):
+        rows = [v for _, name, v in _counter_rows(path, counter) if re.search(pattern, name)]
+        timed = rows[warmup:warmup + steps]
+        return float(np.mean(timed)), len(rows)
+
+    def copy_kib(path, counter):
+        rows = [v for _, name, v in _counter_rows(path, counter) if "copyBuffer" in name]
+        return float(np.median(rows))
+    f_kib, nf = score_mean(fetch, "FETCH_SIZE")
+    w_kib, nw = score_mean(write, "WRITE_SIZE")
+    # a copy of B bytes reads B and writes B: scale = B / (counter KiB * 1024)
+    f_scale = copy_bytes / (copy_kib(cfetch, "FETCH_SIZE") * 1024.0)
+    w_scale = copy_bytes / (copy_kib(cwrite, "WRITE_SIZE") * 1024.0)
+    out = {
+        "kernel": desc,
+        "workload": "%s, launches %d-%d (timed launches of bench.py)" % (workload, warmup,
+                                                                         warmup + steps - 1),
+        "file": fname,
+        "src_sha": src_sha(src),
+        "fetch_kib_per_launch": f_kib, "write_kib_per_launch": w_kib,
+        "fetch_scale": round(f_scale, 3), "write_scale": round(w_scale, 3),
+        "bytes_per_launch": (f_kib * f_scale + w_kib * w_scale) * 1024.0,
+        "launches_seen": [nf, nw],
+        "commands": [
+            "rocprofv3 --pmc FETCH_SIZE -d <dir> -o p --output-format csv -- python3 bench.py "
+            "--workload %s --no-cpu-baseline --latency-frames 0" % workload,
+            "rocprofv3 --pmc WRITE_SIZE -d <dir> -o p --output-format csv -- python3 bench.py "
+            "--workload %s --no-cpu-baseline --latency-frames 0" % workload,
+            "rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) -d <dir> -o p --output-format csv -- "
+            "python3 bench.py --copy-probe %d" % copy_bytes,
+            "python3 bench.py --workload %s --traffic-summary "
+            "fetch.csv,write.csv,copy_fetch.csv,copy_write.csv" % workload],
+    }
     return out
 
 
@@ -428,6 +500,15 @@ def run_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def smooth_traffic():
+    """HBM bytes per refinement launch from the committed counter summary,
+    None once the kernel source has changed since it was measured."""
+    if not os.path.exists(SMOOTH_TRAFFIC_FILE):
+        return None
+    tr = json.load(open(SMOOTH_TRAFFIC_FILE))
+    return tr.get("bytes_per_launch") if tr.get("src_sha") == src_sha(SMOOTH_SRC) else None
+
+
 def run_smooth(args):
     """Differentiation workload: the tree map after frames 0..F-1, 1,000,000
     of its surface points (voxel centres) x 64 starting directions (Fibonacci,
@@ -529,7 +610,7 @@ def run_smooth(args):
                    "unchanged_frac": float((gain == 0).mean()),
                    "mean_gain": float(gain.mean())},
         "roofline": {"kernel": "k_smooth_refine", "bound": "hbm", "achieved": ach, "peak": 8000.0,
-                     "unit": "GB/s", "frac": ach / 8000.0, "traffic": None,
+                     "unit": "GB/s", "frac": ach / 8000.0, "traffic": smooth_traffic(),
                      "bytes_model": "36 B per sample evaluation (apron index + 8 cell values "
                                     "of 4 B), 64 samples, 21 evaluations per pair; mostly "
                                     "L2 hits, so this is demand, not DRAM traffic"},
@@ -576,12 +657,28 @@ def main():
     ap.add_argument("--trace-summary", default=None,
                     help="only summarise a rocprofv3 kernel_trace.csv of a bench run "
                          "with the same --warmup/--steps")
+    ap.add_argument("--traffic-summary", default=None,
+                    help="only write profiles/traffic_k_score_tree.json from four rocprofv3 "
+                         "--pmc CSVs: FETCH_SIZE,WRITE_SIZE of a default run, then of the "
+                         "copy probe (comma-separated)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a device-to-device copy of this many bytes (3 times); "
                          "used to calibrate rocprofv3 FETCH_SIZE/WRITE_SIZE")
     args = ap.parse_args()
     if args.trace_summary:
         print(json.dumps(trace_summary(args.trace_summary, args.warmup, args.steps), indent=1))
+        return
+    if args.traffic_summary:
+        wl = "smooth" if args.workload == "smooth" else "tree"
+        warm, steps = args.warmup, args.steps
+        if wl == "smooth":   # the smooth workload's own defaults (see run_smooth)
+            warm = warm if warm != 100 else 1
+            steps = steps if steps != 400 else 3
+        out = traffic_summary(args.traffic_summary.split(","), warm, steps,
+                              args.copy_probe or (1 << 30), wl)
+        with open(os.path.join(ROOT, "profiles", out["file"]), "w") as f:
+            json.dump(out, f, indent=1)
+        print(json.dumps(out, indent=1))
         return
     if args.copy_probe:
         import torch
