@@ -112,6 +112,10 @@ def _load():
     L.orc_key.argtypes = [i64, i64, i64]
     L.orc_unkey.argtypes = [i64, vp]
     L.orc_params.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.orc_changed_voxels.restype = i64
+    L.orc_changed_voxels.argtypes = [vp, vp, i64]
+    L.orc_body_hits.restype = ctypes.c_int
+    L.orc_body_hits.argtypes = [vp, ctypes.c_int, i64, i32]
     L.orc_smooth.restype = ctypes.c_int
     L.orc_smooth.argtypes = [vp, vp, vp, i64, vp, i32, dbl, dbl, vp, vp, vp, vp]
     L.orc_smooth_dense.restype = ctypes.c_int
@@ -317,6 +321,19 @@ class Oracle:
         if rc != 0:
             raise ValueError("orc_smooth_refine rejected its arguments")
         return q, s, face
+
+    def changed_voxels(self):
+        """Keys of the voxels that received a contribution in the last frame."""
+        m = self.L.orc_changed_voxels(self.h, None, 0)
+        k = np.zeros(max(1, m), np.int64)
+        self.L.orc_changed_voxels(self.h, _p(k), m)
+        return k[:m]
+
+    def body_hits(self, tool_id, key, k):
+        r = self.L.orc_body_hits(self.h, int(tool_id), int(key), int(k))
+        if r < 0:
+            raise ValueError("bad tool, key or orientation")
+        return r
 
     def labels(self, K, keys=None):
         """(keys, label, first_free) for all points (canonical order) or the

@@ -153,6 +153,7 @@ struct orc {
   int32_t *W, *dW;
   uint8_t *clr;
   int64_t *dirty, ndirty, dcap;
+  int64_t *changed, nchanged, ccap;   /* keys of the voxels folded by the last frame */
   /* surface points, canonical order */
   hmap pmap;
   int64_t np, pcap;
@@ -208,6 +209,7 @@ void orc_destroy(orc_t *o) {
   hm_free(&o->pmap);
   free(o->vkey); free(o->S); free(o->dS); free(o->W); free(o->dW); free(o->clr);
   free(o->dirty);
+  free(o->changed);
   free(o->pkey); free(o->sumq); free(o->first_frame); free(o->nvp);
   free(o->vphead); free(o->vp); free(o->nq); free(o->last_frame);
   for (int t = 0; t < MAX_TOOLS; ++t) {
@@ -404,8 +406,11 @@ int orc_integrate_frame(orc_t *o, const float *xyz, int64_t n,
 
   /* Fold the frame: S += dS, W += dW; weights saturate at the cap with
    * proportional rescaling of S (Section 3.6, "TSDF integration"). */
+  o->nchanged = 0;
   for (int64_t j = 0; j < o->ndirty; ++j) {
     int64_t s = o->dirty[j];
+    o->changed = (int64_t *)grow_array(o->changed, sizeof(int64_t), &o->ccap, o->nchanged + 1);
+    o->changed[o->nchanged++] = o->vkey[s];
     o->S[s] += o->dS[s];
     o->W[s] += o->dW[s];
     if (o->W[s] > o->cfg.weight_cap) {
@@ -937,6 +942,32 @@ int orc_score(orc_t *o, int tool_id, const int64_t *keys, int64_t n_keys) {
       o->sst.n_blocked++;
   }
   return 0;
+}
+
+/* Keys of the voxels that received a contribution in the last frame (in
+ * fold order); returns their number. */
+int64_t orc_changed_voxels(const orc_t *o, int64_t *keys, int64_t cap) {
+  int64_t m = o->nchanged < cap ? o->nchanged : cap;
+  for (int64_t j = 0; j < m; ++j) keys[j] = o->changed[j];
+  return o->nchanged;
+}
+
+/* Number of body voxels of orientation k with TSDF < r_c at point `key`
+ * (the raw collision count of Section 3.5, all body entries visited). */
+int orc_body_hits(const orc_t *o, int tool_id, int64_t key, int32_t k) {
+  if (tool_id < 0 || tool_id >= MAX_TOOLS) return -1;
+  const tool_tab *tt = &o->tools[tool_id];
+  if (tt->K <= 0 || k < 0 || k >= tt->K) return -1;
+  int64_t s[3];
+  orc_unkey(key, s);
+  int hits = 0;
+  for (int64_t e = tt->begin[k]; e < tt->begin[k + 1]; ++e) {
+    if (tt->cls[e] != CLS_BODY) continue;
+    const int32_t *d = tt->off + 3 * e;
+    vrec r = lookup(o, s[0] + d[0], s[1] + d[1], s[2] + d[2]);
+    if (r.W > 0 && r.S < o->rc_u * (int64_t)r.W) ++hits;
+  }
+  return hits;
 }
 
 int orc_score_stats_get(const orc_t *o, orc_score_stats *st) {

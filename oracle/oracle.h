@@ -97,6 +97,12 @@ int orc_point_result(const orc_t *o, int64_t key, uint8_t *label,
                      int32_t *first_free, int64_t normal[3], int32_t *has_normal,
                      uint64_t *mask, int32_t mask_words);
 
+/* Keys of the voxels that received a contribution in the last frame; returns
+ * their number (keys: up to cap of them). */
+int64_t orc_changed_voxels(const orc_t *o, int64_t *keys, int64_t cap);
+/* Body voxels of orientation k with TSDF < r_c at point `key` (all visited). */
+int orc_body_hits(const orc_t *o, int tool_id, int64_t key, int32_t k);
+
 /* Smoothed clearance score (smooth.c): sum over tool samples o of
  * log sigma((T(p + R(q) o) - c) / tau_s) with trilinear T, and its gradients
  * with respect to the quaternion q (w, x, y, z) and the point p. */

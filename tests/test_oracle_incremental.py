@@ -1,0 +1,184 @@
+"""Pins of the oracle's incremental mode (oracle/incremental.py and the C
+helpers it uses), each against something other than the oracle itself:
+
+* the sample hash is SplitMix64: its first outputs for seed 0 are the
+  published ones;
+* the confidence arithmetic is the paper's: a falls 1 -> 0.75 -> 0.5625 on
+  conflicting evaluations, so for a well-observed point (c close to 1) one
+  outlier keeps it accessible and two remove it; recovery adds 0.15 (1 - a);
+  c = w / (w + 5) is 0.5 at w = 5 and first exceeds 0.7 at w = 12; the
+  stored score never increases;
+* the raw collision count of an orientation equals a table-free count of
+  occupied voxels inside the analytic tool body;
+* on the tiny scene: every evaluation equals the stateless per-point test at
+  that frame; the budget takes queued points in canonical order and carries
+  the rest; a sensor move of less than 0.1 m re-queues nothing, one of more
+  re-queues exactly the points labelled inaccessible; the sample holds the
+  256 changed voxels of smallest hash."""
+import math
+
+import numpy as np
+import pytest
+
+from test_oracle_scoring import _membership
+
+
+def test_splitmix64_published_outputs(oracle_mod):
+    from oracle.incremental import GOLDEN, mix64
+    # SplitMix64 seeded with 0: state advances by the golden gamma, output = mix(state)
+    assert [mix64(GOLDEN * i) for i in (1, 2, 3)] == [
+        0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
+def test_confidence_arithmetic(oracle_mod):
+    from oracle.incremental import (LABEL_TENTATIVE, apply_evaluation, label_of)
+    from oracle import LABEL_ACCESSIBLE, LABEL_BLOCKED, LABEL_UNSCORED
+    n_c = 5
+    st = dict(best=n_c, best_dir=-1, a=1.0, outcome=LABEL_UNSCORED)
+    apply_evaluation(st, 2, 17, LABEL_ACCESSIBLE, n_c)        # first evaluation: a unchanged
+    assert (st["best"], st["best_dir"], st["a"]) == (2, 17, 1.0)
+    W = 2000                                                   # c = 2000/2005, close to 1
+    assert label_of(st, W, n_c) == LABEL_ACCESSIBLE
+    apply_evaluation(st, n_c, -1, LABEL_BLOCKED, n_c)         # one outlier
+    assert st["a"] == 0.75 and st["best"] == 2                 # stored score kept
+    assert label_of(st, W, n_c) == LABEL_ACCESSIBLE            # 0.748 > 0.7
+    apply_evaluation(st, n_c, -1, LABEL_BLOCKED, n_c)         # two in a row
+    assert st["a"] == 0.5625
+    assert label_of(st, W, n_c) == LABEL_TENTATIVE             # 0.561 < 0.7
+    apply_evaluation(st, 4, 3, LABEL_ACCESSIBLE, n_c)         # confirming, higher score
+    assert st["a"] == 0.5625 + 0.15 * (1 - 0.5625) and st["best"] == 2
+    apply_evaluation(st, 1, 9, LABEL_ACCESSIBLE, n_c)         # lower score is stored
+    assert (st["best"], st["best_dir"]) == (1, 9)
+    fresh = dict(best=1, best_dir=0, a=1.0, outcome=LABEL_ACCESSIBLE)
+    assert label_of(fresh, 5, n_c) == LABEL_TENTATIVE          # c = 0.5 at w = k_c
+    assert label_of(fresh, 11, n_c) == LABEL_TENTATIVE         # 11/16 = 0.6875
+    assert label_of(fresh, 12, n_c) == LABEL_ACCESSIBLE        # 12/17 = 0.706
+    blocked = dict(best=n_c, best_dir=-1, a=1.0, outcome=LABEL_UNSCORED)
+    apply_evaluation(blocked, n_c, -1, LABEL_BLOCKED, n_c)
+    apply_evaluation(blocked, n_c, -1, LABEL_BLOCKED, n_c)
+    assert blocked["a"] == 1.0                                 # nothing stored to contradict
+    assert label_of(blocked, W, n_c) == LABEL_BLOCKED
+
+
+@pytest.fixture(scope="module")
+def tiny_incr(oracle_mod, synth_mod):
+    from oracle.incremental import IncrementalOracle
+    w = synth_mod.tiny()
+    frames = w.frames(8)
+    orc = oracle_mod.Oracle(voxel=w.voxel, trunc=w.trunc, r_c=w.r_c)
+    orc.set_tool(0, w.tool, w.rot)
+    return w, frames, orc, IncrementalOracle(orc, 0, len(w.rot), budget=700)
+
+
+def test_body_count_against_analytic_solid(tiny_incr, oracle_mod):
+    w, frames, orc, inc = tiny_incr
+    for f in frames[:4]:
+        orc.integrate_frame(f.xyz, f.origin, f.frame_id)
+    orc.score(0)
+    p = orc.params()
+    key, S, W, c = orc.read_tsdf()
+    ijk = oracle_mod.unpack_keys(key)
+    occ_ijk = ijk[(W > 0) & (S < p["rc_u"] * W.astype(np.int64))]
+    checked = 0
+    for k in orc.read_points()["key"][::7]:
+        r = orc.point_result(k, len(w.rot))
+        if r["label"] != 1:
+            continue
+        s = np.array(oracle_mod.unkey(k))
+        rel = occ_ijk - s
+        near = np.abs(rel).max(1) <= math.ceil((w.tool.length + w.tool.corridor) / w.voxel) + 2
+        body, far, amb = _membership(w.tool, w.rot[r["first_free"]], w.voxel, rel[near])
+        if amb.any():
+            continue
+        assert orc.body_hits(0, k, r["first_free"]) == int(body.sum())
+        checked += 1
+    assert checked >= 20
+
+
+def test_sample_and_move_rule(oracle_mod, synth_mod):
+    """The sample is the smallest hashes of the frame's changed voxels; a
+    sensor move below 0.1 m re-queues nothing, one above re-queues exactly
+    the points labelled inaccessible after the previous frame."""
+    from oracle.incremental import IncrementalOracle, sample_hash
+    w = synth_mod.tiny()
+    frames = w.frames(6)
+    orc = oracle_mod.Oracle(voxel=w.voxel, trunc=w.trunc, r_c=w.r_c)
+    orc.set_tool(0, w.tool, w.rot)
+    inc = IncrementalOracle(orc, 0, len(w.rot), budget=700)
+    moves = []
+    for j, f in enumerate(frames):
+        origin = np.asarray(f.origin, np.float32)
+        if j == 4:
+            origin = (np.asarray(frames[3].origin, np.float64) + [0.05, 0, 0]).astype(np.float32)
+        if j == 5:
+            origin = (np.asarray(frames[3].origin, np.float64) + [0.15, 0, 0]).astype(np.float32)
+        prev = inc.labels()[1] if inc.state else np.zeros(0, np.uint8)
+        st = inc.frame(f.xyz, origin, f.frame_id)
+        ch = orc.changed_voxels()
+        assert st["sampled"] == min(256, len(ch))
+        hs = [sample_hash(c, f.frame_id) for c in ch]
+        assert len(set(hs)) == len(hs)                      # no ties to break
+        moves.append((st["trig_iii"], int(np.isin(prev, (2, 3)).sum())))
+    assert moves[4][0] == 0
+    assert moves[5][0] == moves[5][1] > 0
+
+
+def test_evaluations_equal_stateless_labels(oracle_mod, synth_mod):
+    """Budget large enough for everything: after each frame, every point
+    evaluated in that frame carries the stateless label and, if accessible,
+    the body count of its first free orientation."""
+    from oracle.incremental import IncrementalOracle
+    w = synth_mod.tiny()
+    frames = w.frames(4)
+    orc = oracle_mod.Oracle(voxel=w.voxel, trunc=w.trunc, r_c=w.r_c)
+    ref = oracle_mod.Oracle(voxel=w.voxel, trunc=w.trunc, r_c=w.r_c)
+    orc.set_tool(0, w.tool, w.rot)
+    ref.set_tool(0, w.tool, w.rot)
+    inc = IncrementalOracle(orc, 0, len(w.rot), budget=10 ** 9)
+    K = len(w.rot)
+    for f in frames:
+        inc.frame(f.xyz, f.origin, f.frame_id)
+        ref.integrate_frame(f.xyz, f.origin, f.frame_id)
+        ref.score(0)
+        assert len(inc.last_evaluated) > 0
+        for k in inc.last_evaluated:
+            s2 = inc.state[k]
+            r = ref.point_result(k, K)
+            assert s2["outcome"] == r["label"] != 0
+        # with an unlimited budget nothing confident stays queued
+        for k in orc.read_points()["key"]:
+            assert not inc.state[int(k)]["pending"] or ref.voxel(int(k))[1] < 2
+    # the first frame evaluates every confident point: outcome == stateless label
+    inc2 = IncrementalOracle(oracle_mod.Oracle(voxel=w.voxel, trunc=w.trunc, r_c=w.r_c), 0, K,
+                             budget=10 ** 9)
+    inc2.orc.set_tool(0, w.tool, w.rot)
+    ref2 = oracle_mod.Oracle(voxel=w.voxel, trunc=w.trunc, r_c=w.r_c)
+    ref2.set_tool(0, w.tool, w.rot)
+    inc2.frame(frames[0].xyz, frames[0].origin, frames[0].frame_id)
+    ref2.integrate_frame(frames[0].xyz, frames[0].origin, frames[0].frame_id)
+    ref2.score(0)
+    for k in inc2.orc.read_points()["key"]:
+        s2 = inc2.state[int(k)]
+        r = ref2.point_result(k, K)
+        assert s2["outcome"] == r["label"]
+        if r["label"] == 1:
+            assert s2["best"] == ref2.body_hits(0, k, r["first_free"]) < 5
+            assert s2["best_dir"] == r["first_free"]
+        else:
+            assert s2["best"] == 5
+
+
+def test_budget_and_backlog(oracle_mod, synth_mod):
+    from oracle.incremental import IncrementalOracle
+    w = synth_mod.tiny()
+    f = w.frames(1)[0]
+    orc = oracle_mod.Oracle(voxel=w.voxel, trunc=w.trunc, r_c=w.r_c)
+    orc.set_tool(0, w.tool, w.rot)
+    inc = IncrementalOracle(orc, 0, len(w.rot), budget=100)
+    st = inc.frame(f.xyz, f.origin, f.frame_id)
+    keys = orc.read_points()["key"]
+    conf = [int(k) for k in keys if orc.voxel(int(k))[1] >= 2]
+    assert st["evaluated"] == min(100, len(conf)) == 100
+    done = [k for k in keys if inc.state[int(k)]["outcome"] != 0]
+    assert [int(k) for k in done] == conf[:100]                 # canonical order
+    assert st["backlog"] == len(keys) - 100                     # the rest stay queued
