@@ -53,7 +53,9 @@ enum {
   AF_UNSCORED = 0,     /* TSDF confidence w/(w+5) < 0.2, i.e. W < 2 (Section 3.5) */
   AF_ACCESSIBLE = 1,   /* some candidate orientation is free */
   AF_BLOCKED = 2,      /* every candidate orientation collides */
-  AF_NO_CANDIDATE = 3  /* no orientation passes the normal/observation filters */
+  AF_NO_CANDIDATE = 3, /* no orientation passes the normal/observation filters */
+  AF_TENTATIVE = 4     /* incremental mode: a free direction is stored, but the
+                          combined confidence c * a is not above 0.7 yet */
 };
 
 /* table entry classes */
@@ -329,6 +331,47 @@ int af_smooth_refine(af_ctx *ctx, const float *p, int64_t n_points, const float 
                      int32_t n_starts, const float *samples, int32_t M, float c, float tau_s,
                      int32_t steps, float eta, float max_step, float *q_out, float *s_out,
                      void *stream);
+
+/* Incremental mode (Section 3.5, "Incremental Updates and Confidence"):
+ * instead of re-testing every point each frame, a per-point state is kept
+ * and a point is re-evaluated only when (i) the TSDF at its voxel moved by
+ * more than 2v since the previous frame, (ii) a voxel within 3v of it
+ * received a contribution -- judged from a sample of 256 of the frame's
+ * changed voxels, those with the smallest SplitMix64 hash of
+ * (voxel key XOR frame id * 0x9E3779B97F4A7C15) -- or (iii) the sensor moved
+ * more than 0.1 m since the last time this fired and the point is labelled
+ * AF_BLOCKED or AF_NO_CANDIDATE; new points are queued on first observation.
+ * Queued points with W >= conf_min_w are evaluated, at most `budget` per
+ * frame in point order; the rest stay queued.  An evaluation is the per-point
+ * test of af_score_points; its score is the raw collision count (body voxels
+ * with TSDF < r_c) of the first free orientation, n_c if none is free.  The
+ * stored score only decreases (its orientation is kept with it); the
+ * accessibility confidence a (1 at first) becomes 0.75 a when an evaluation
+ * finds no free orientation while a free one is stored, and a + 0.15 (1 - a)
+ * when it finds one.  Labels: AF_ACCESSIBLE iff the stored score is below
+ * n_c and c a > 0.7 with c = W / (W + 5); AF_TENTATIVE when a score below
+ * n_c is stored but c a <= 0.7; otherwise the last evaluation's AF_BLOCKED or
+ * AF_NO_CANDIDATE; AF_UNSCORED before the first evaluation.
+ *
+ * af_incremental_enable: tool `tool_id` (K <= 1024, reach <= 255 voxels),
+ * budget >= 1; before the context's first frame (AF_EINVAL otherwise).
+ * Allocates the state (23 B per point of capacity) and a changed-voxel list
+ * (4 B per voxel of block capacity).  af_incremental_frame integrates one
+ * frame as af_integrate_frame does, then runs the steps above; it
+ * synchronises `stream` once (inside the integration).  af_incremental_stats
+ * synchronises and reports the last frame's counts.  af_read_incremental
+ * copies state in canonical point order into host arrays (any may be NULL). */
+typedef struct af_incr_stats {
+  int64_t new_points, trig_i, trig_ii, trig_iii;   /* points queued by each cause */
+  int64_t changed, sampled;                        /* changed voxels, sampled ones */
+  int64_t queued, evaluated, backlog;              /* before selection, chosen, left */
+} af_incr_stats;
+int af_incremental_enable(af_ctx *ctx, int32_t tool_id, int32_t budget);
+int af_incremental_frame(af_ctx *ctx, const float *xyz, int64_t n, const float origin[3],
+                         int64_t frame_id, void *stream);
+int af_incremental_stats(af_ctx *ctx, af_incr_stats *out);
+int af_read_incremental(af_ctx *ctx, int64_t first, int64_t count, int64_t *key, uint8_t *label,
+                        uint8_t *best, int16_t *best_dir, double *a, int64_t *n_written);
 
 /* Serving several concurrent sensor streams (the real-time frame budget of
  * Section 3.6, for several sensors on one GPU).

@@ -17,7 +17,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libaf.so")
 
 AF_OK, AF_EINVAL, AF_ENOMEM, AF_EDEVICE, AF_ENOTOOL, AF_EOVERFLOW, AF_EBUSY = 0, -1, -2, -3, -4, -5, -6
-UNSCORED, ACCESSIBLE, BLOCKED, NO_CANDIDATE = 0, 1, 2, 3
+UNSCORED, ACCESSIBLE, BLOCKED, NO_CANDIDATE, TENTATIVE = 0, 1, 2, 3, 4
 CLS_BODY, CLS_NEAR, CLS_FAR = 0, 1, 2
 TOOL_CYLINDER, TOOL_BOX = 0, 1
 
@@ -67,6 +67,15 @@ class ScoreStats(ctypes.Structure):
                  "canonical_lookups", "deep_tests", "deep_chunks_max",
                                    "coarse_checks", "coarse_clear", "chunks_body",
                                    "chunks_far", "arm_lookups")]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class IncrStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in
+                ("new_points", "trig_i", "trig_ii", "trig_iii", "changed", "sampled",
+                 "queued", "evaluated", "backlog")]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -125,6 +134,13 @@ SIGNATURES = {
                                         ctypes.c_int32, ctypes.c_float, ctypes.c_float,
                                         ctypes.c_int32, ctypes.c_float, ctypes.c_float,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "af_incremental_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
+    "af_incremental_frame": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                            ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
+    "af_incremental_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "af_read_incremental": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "af_server_create": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p]),
     "af_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "af_server_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
@@ -451,6 +467,39 @@ class Context:
             ctypes.c_void_p(q.data_ptr()), ctypes.c_void_p(s.data_ptr()),
             _stream_handle(stream)))
         return q, s
+
+    def incremental_enable(self, tool_id: int, budget: int):
+        """Switch this (still empty) map to the incremental mode for one tool."""
+        self._check(self._lib.af_incremental_enable(self.h, int(tool_id), int(budget)))
+
+    def incremental_frame(self, xyz, origin, frame_id: int, stream=None):
+        """Integrate a frame, then re-evaluate only the queued points."""
+        if not (getattr(xyz, "is_cuda", False) and str(xyz.dtype) == "torch.float32"
+                and xyz.is_contiguous() and xyz.dim() == 2 and xyz.shape[1] == 3):
+            raise TypeError("xyz must be a contiguous CUDA float32 tensor of shape [n, 3]")
+        o = np.ascontiguousarray(origin, dtype=np.float32).reshape(3)
+        self._check(self._lib.af_incremental_frame(self.h, ctypes.c_void_p(xyz.data_ptr()),
+                                                   int(xyz.shape[0]), _p(o), int(frame_id),
+                                                   _stream_handle(stream)))
+
+    def incremental_stats(self):
+        st = IncrStats()
+        self._check(self._lib.af_incremental_stats(self.h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def read_incremental(self):
+        """Incremental state in canonical point order: key, label, best
+        (stored collision count; n_c = none), best_dir, a."""
+        n = self.num_points()
+        key = np.zeros(n, np.int64)
+        lbl = np.zeros(n, np.uint8)
+        best = np.zeros(n, np.uint8)
+        bdir = np.zeros(n, np.int16)
+        a = np.zeros(n, np.float64)
+        nw = ctypes.c_int64()
+        self._check(self._lib.af_read_incremental(self.h, 0, n, _p(key), _p(lbl), _p(best),
+                                                  _p(bdir), _p(a), ctypes.byref(nw)))
+        return dict(key=key, label=lbl, best=best, best_dir=bdir, a=a)
 
     def score_variant_default(self) -> int:
         return self._lib.af_score_variant_default()

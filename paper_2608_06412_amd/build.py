@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build", "af")
 LIB = os.path.join(PKG, "libaf.so")
 SOURCES = ["af_context.hip", "af_integrate.hip", "af_table.hip", "af_score.hip",
-           "af_server.hip", "af_smooth.hip"]
+           "af_server.hip", "af_smooth.hip", "af_incr.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

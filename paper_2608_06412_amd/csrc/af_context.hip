@@ -43,6 +43,13 @@ struct af_ctx {
   int64_t slot_cap;
   bool graph_dirty;             // recorded frames ran since the host mirrors were refreshed
   bool graph_stale;             // a buffer the graph holds was reallocated
+  // incremental mode
+  bool incr_on;
+  int32_t incr_tool;
+  IncrDev incr;
+  int32_t *incr_changed;        // [max_blocks * 512] changed voxel addresses of a frame
+  int32_t q_last[3];            // sensor position when trigger (iii) last fired
+  bool have_q;
   // smoothed score: apron bricks and their tables (SmoothBuffers), grown on demand
   SmoothBuffers sm;
   int64_t sm_T_cap;             // voxels of sm.T
@@ -1043,6 +1050,138 @@ int af_smooth_refine(af_ctx *c, const float *p, int64_t n_points, const float *q
   if (c->timing) timing_pair(c, ST_K_SMOOTH, t0, t1);
   c->last_stream = s;
   return hip_check(c, "smooth refine");
+}
+
+int af_incremental_enable(af_ctx *c, int32_t tool_id, int32_t budget) {
+  if (!c) return AF_EINVAL;
+  if (tool_id < 0 || tool_id >= c->cfg.max_tools) return fail(c, AF_EINVAL, "bad tool id");
+  const ToolDev &t = c->tools[tool_id];
+  if (!t.entries) return fail(c, AF_ENOTOOL, "tool %d has no kernels", tool_id);
+  if (budget < 1) return fail(c, AF_EINVAL, "budget must be positive");
+  if (c->p.n_c > 255) return fail(c, AF_EINVAL, "n_c above 255");
+  if (c->last_frame >= 0 || c->n_points > 0)
+    return fail(c, AF_EINVAL, "the incremental mode starts before the first frame");
+  if (!score_variant_takes_list(score_variant_default(), t))
+    return fail(c, AF_EINVAL, "tool %d: K above 1024 or reach above 255 voxels", tool_id);
+  budget = (int32_t)std::min<int64_t>(budget, c->cfg.max_points);
+  IncrDev &I = c->incr;
+  if (!c->incr_on) {
+    const int64_t NP = c->cfg.max_points;
+    memset(&I, 0, sizeof(I));
+    ALLOC(c, I.best, NP);
+    ALLOC(c, I.best_dir, NP);
+    ALLOC(c, I.a, NP);
+    ALLOC(c, I.S_prev, NP);
+    ALLOC(c, I.W_prev, NP);
+    ALLOC(c, I.pending, NP);
+    ALLOC(c, I.outcome, NP);
+    ALLOC(c, I.label, NP);
+    ALLOC(c, I.n_sel, 1);
+    ALLOC(c, I.bsum, (NP + 1023) / 1024);
+    ALLOC(c, I.hist, 2 * 65536);
+    ALLOC(c, I.cand_h, 1024);
+    ALLOC(c, I.cand_k, 1024);
+    ALLOC(c, I.sampled, 256);
+    ALLOC(c, I.ctr, 1);
+    ALLOC(c, c->incr_changed, c->cfg.max_blocks * kBlockVox);
+    I.max_points = NP;
+  }
+  if (!c->incr_on || budget > I.budget) {
+    if (I.sel) dev_free(c, I.sel, sizeof(int32_t) * I.budget);
+    if (I.score_new) dev_free(c, I.score_new, I.budget);
+    I.sel = nullptr;
+    I.score_new = nullptr;
+    ALLOC(c, I.sel, budget);
+    ALLOC(c, I.score_new, budget);
+  }
+  I.budget = budget;
+  c->incr_on = true;
+  c->incr_tool = tool_id;
+  c->have_q = false;
+  launch_incr_init(I, c->p.n_c, nullptr);
+  return hip_check(c, "incremental enable");
+}
+
+int af_incremental_frame(af_ctx *c, const float *xyz, int64_t n, const float origin[3],
+                         int64_t frame_id, void *stream) {
+  if (!c) return AF_EINVAL;
+  if (!c->incr_on) return fail(c, AF_EINVAL, "incremental mode not enabled");
+  hipStream_t s = (hipStream_t)stream;
+  c->fs.changed = c->incr_changed;
+  int rc = af_integrate_frame(c, xyz, n, origin, frame_id, stream);
+  c->fs.changed = nullptr;
+  if (rc != AF_OK) return rc;
+  // trigger (iii): the sensor position as integrated (fixed point), against
+  // where the trigger last fired
+  int32_t Q[3];
+  for (int a = 0; a < 3; ++a) Q[a] = (int32_t)llrint((double)origin[a] * c->p.scale);
+  bool moved = false;
+  if (!c->have_q) {
+    c->have_q = true;
+    memcpy(c->q_last, Q, sizeof(Q));
+  } else {
+    int64_t d2 = 0;
+    for (int a = 0; a < 3; ++a) d2 += (int64_t)(Q[a] - c->q_last[a]) * (Q[a] - c->q_last[a]);
+    if (d2 > c->p.dmin2) {
+      moved = true;
+      memcpy(c->q_last, Q, sizeof(Q));
+    }
+  }
+  IncrDev &I = c->incr;
+  launch_incr_frame_front(c->pts, c->map, I, c->incr_changed, c->counters, c->n_points,
+                          (int32_t)frame_id, moved, c->p.conf_min_w, s);
+  PointsDev ps = c->pts;
+  ps.sel = I.sel;
+  ps.n_sel = I.n_sel;
+  ToolDev &t = c->tools[c->incr_tool];
+  HIP_TRY(c, hipMemsetAsync(t.counters, 0, sizeof(ScoreCounters), s));
+  launch_normals(c->p, c->map, ps, c->grid, I.budget, s, true);
+  launch_mask(c->p, ps, t, c->grid, I.budget, s, true);
+  launch_score(c->p, ps, t, c->grid, I.budget, score_variant_default(), c->work, s, true);
+  launch_incr_frame_back(ps, c->map, t, c->grid, I, c->n_points, c->p.n_c, s);
+  c->last_stream = s;
+  return hip_check(c, "incremental frame");
+}
+
+int af_incremental_stats(af_ctx *c, af_incr_stats *st) {
+  if (!c || !st) return AF_EINVAL;
+  if (!c->incr_on) return fail(c, AF_EINVAL, "incremental mode not enabled");
+  int rc = sync_last(c);
+  if (rc != AF_OK) return rc;
+  IncrCounters h;
+  int32_t nsel = 0, nch = 0;
+  HIP_TRY(c, hipMemcpy(&h, c->incr.ctr, sizeof(h), hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipMemcpy(&nsel, c->incr.n_sel, sizeof(int32_t), hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipMemcpy(&nch, &c->counters->n_changed, sizeof(int32_t), hipMemcpyDeviceToHost));
+  st->new_points = h.new_points;
+  st->trig_i = h.trig_i;
+  st->trig_ii = h.trig_ii;
+  st->trig_iii = h.trig_iii;
+  st->changed = nch;
+  st->sampled = h.sampled;
+  st->queued = h.queued;
+  st->evaluated = nsel;
+  st->backlog = (int64_t)h.queued - nsel;
+  return AF_OK;
+}
+
+int af_read_incremental(af_ctx *c, int64_t first, int64_t count, int64_t *key, uint8_t *label,
+                        uint8_t *best, int16_t *best_dir, double *a, int64_t *n_written) {
+  if (!c) return AF_EINVAL;
+  if (!c->incr_on) return fail(c, AF_EINVAL, "incremental mode not enabled");
+  int rc = sync_last(c);
+  if (rc != AF_OK) return rc;
+  const int64_t m = std::max<int64_t>(0, std::min<int64_t>(count, c->n_points - first));
+  if (n_written) *n_written = m;
+  if (m == 0 || first < 0) return first < 0 ? fail(c, AF_EINVAL, "bad range") : AF_OK;
+  const IncrDev &I = c->incr;
+  if (key) HIP_TRY(c, hipMemcpy(key, c->pts.key + first, sizeof(int64_t) * m, hipMemcpyDeviceToHost));
+  if (label) HIP_TRY(c, hipMemcpy(label, I.label + first, m, hipMemcpyDeviceToHost));
+  if (best) HIP_TRY(c, hipMemcpy(best, I.best + first, m, hipMemcpyDeviceToHost));
+  if (best_dir)
+    HIP_TRY(c, hipMemcpy(best_dir, I.best_dir + first, sizeof(int16_t) * m, hipMemcpyDeviceToHost));
+  if (a) HIP_TRY(c, hipMemcpy(a, I.a + first, sizeof(double) * m, hipMemcpyDeviceToHost));
+  return AF_OK;
 }
 
 int af_score_variant_count(void) { return score_variants(); }

@@ -15,11 +15,6 @@ constexpr int kThreads = 256;
 
 __device__ inline int lane_id() { return (int)(threadIdx.x & 63u); }
 
-__device__ inline uint32_t slot_of(int64_t key, uint32_t mask) {
-  uint64_t h = (uint64_t)key * 0x9E3779B97F4A7C15ull;
-  return (uint32_t)(h >> 29) & mask;
-}
-
 // Insert `key`; returns its slot (fresh = newly inserted) or -1 if full.
 __device__ int32_t hash_insert(HashTable t, int64_t key, bool &fresh) {
   uint32_t s = slot_of(key, t.mask);
@@ -45,17 +40,6 @@ __device__ int32_t hash_insert(HashTable t, int64_t key, bool &fresh) {
     s = (s + 1) & t.mask;
   }
   fresh = false;
-  return -1;
-}
-
-__device__ int32_t hash_find(HashTable t, int64_t key) {
-  uint32_t s = slot_of(key, t.mask);
-  for (uint32_t i = 0; i <= t.mask; ++i) {
-    int64_t cur = t.keys[s];
-    if (cur == key) return (int32_t)s;
-    if (cur == kEmpty) return -1;
-    s = (s + 1) & t.mask;
-  }
   return -1;
 }
 
@@ -181,6 +165,7 @@ __global__ void k_reset_counters(FrameCounters *c, MapDev m, PointsDev pts) {
   c->n_valid = c->n_dropped = c->pairs_applied = c->pairs_excluded = 0;
   c->band_marks = c->voxels_folded = 0;
   c->n_new_blocks = c->n_touched = c->n_new_points = c->status = 0;
+  c->n_changed = 0;
   for (int i = 0; i < kStatSlots; ++i) c->fold[i][0] = c->fold[i][1] = c->fold[i][2] = 0ull;
   for (int i = 0; i < 3; ++i) {
     c->bmin[i] = 0x7fffffff;
@@ -610,6 +595,17 @@ k_integrate_fold(const FrameArgs *fa, Params p, MapDev m, FrameScratch fs, Frame
       m.S[v] = S;
       m.W[v] = (uint16_t)W;
       ++folded;
+    }
+    if (fs.changed) {   // list this voxel if it received a contribution (one atomic per wave)
+      const unsigned long long bal = __ballot(dW > 0);
+      if (bal) {
+        const int lane = (int)(threadIdx.x & 63u);
+        int base = 0;
+        if (lane == 0) base = atomicAdd(&c->n_changed, __popcll(bal));
+        base = __shfl(base, 0);
+        if (dW > 0)
+          fs.changed[base + __popcll(bal & ((1ull << lane) - 1ull))] = (int32_t)v;
+      }
     }
     write_brick(p, m, g, id, S, W, code, clrw, surfw, bkey);
   }

@@ -66,6 +66,7 @@ struct FrameCounters {
   unsigned long long n_valid, n_dropped, pairs_applied, pairs_excluded;
   unsigned long long band_marks, voxels_folded;
   int32_t n_new_blocks, n_touched, n_new_points, status;
+  int32_t n_changed;   // voxels that received a contribution (listed when fs.changed is set)
   int32_t bmin[3], bmax[3];
   int32_t blocks_before, points_before;
   int32_t sticky;   // status bits of recorded frames since the host last looked (not reset per frame)
@@ -126,6 +127,10 @@ struct PointsDev {
   int32_t *has_normal;// 1 normal, 0 none, -1 not confident
   int32_t *n_points;  // device counter
   int64_t max_points;
+  // optional point list: when sel is set, the normal, mask and default
+  // scoring kernels visit points sel[0 .. *n_sel) instead of 0 .. n_points
+  const int32_t *sel;
+  const int32_t *n_sel;
 };
 
 // Per-frame scratch, sized for `cap` returns.
@@ -144,6 +149,8 @@ struct FrameScratch {
   int32_t *bin_fill;  // [cap * (kMaxSpan + kMaxBand)] insertion cursors
   int32_t *bin_list;  // [cap * kMaxSpan] return ids grouped by block
   int64_t cap;
+  int32_t *changed;   // null, or [max_blocks * 512]: voxel addresses (block * 512 + index)
+                      // that received a contribution this frame (incremental mode)
 };
 
 struct GridDev {
@@ -202,6 +209,23 @@ __host__ __device__ inline int entry_y(uint32_t e) { return (int)(e << 12) >> 22
 __host__ __device__ inline int entry_z(uint32_t e) { return (int)(e << 2) >> 22; }
 __host__ __device__ inline int entry_cls(uint32_t e) { return (int)(e >> 30); }
 
+// Open-addressing hash (linear probing) shared by the block and point maps.
+__device__ inline uint32_t slot_of(int64_t key, uint32_t mask) {
+  uint64_t h = (uint64_t)key * 0x9E3779B97F4A7C15ull;
+  return (uint32_t)(h >> 29) & mask;
+}
+
+__device__ inline int32_t hash_find(HashTable t, int64_t key) {
+  uint32_t s = slot_of(key, t.mask);
+  for (uint32_t i = 0; i <= t.mask; ++i) {
+    int64_t cur = t.keys[s];
+    if (cur == key) return (int32_t)s;
+    if (cur == kEmpty) return -1;
+    s = (s + 1) & t.mask;
+  }
+  return -1;
+}
+
 __host__ __device__ inline int64_t pack_key(int64_t x, int64_t y, int64_t z) {
   return ((x + kKeyBias) & kKeyMask) | (((y + kKeyBias) & kKeyMask) << 21) |
          (((z + kKeyBias) & kKeyMask) << 42);
@@ -231,6 +255,40 @@ struct FrameArgs {
   int32_t frame;  // frame id
 };
 void launch_set_frame_args(FrameArgs *fa, int64_t n, int3 Q, int32_t frame, hipStream_t s);
+
+// Incremental mode: per-point state and per-frame scratch.
+struct IncrCounters {
+  int32_t new_points, trig_i, trig_ii, trig_iii;
+  int32_t sampled, n_cand, queued, selectable;
+  int32_t b1, b2, need, take_all;   // sample selection: top bin, second bin, count, all
+};
+struct IncrDev {
+  uint8_t *best;          // [max_points] stored score; n_c = no free direction stored
+  int16_t *best_dir;      // its orientation, -1 none
+  double *a;              // accessibility confidence
+  int32_t *S_prev;        // S, W of the point's voxel after the previous frame
+  uint16_t *W_prev;
+  uint32_t *pending;      // queued for evaluation
+  uint8_t *outcome;       // label of the last evaluation (AF_UNSCORED: never)
+  uint8_t *label;         // incremental label
+  int32_t *sel;           // [budget] points evaluated this frame
+  int32_t *n_sel;
+  int32_t *bsum;          // [ceil(max_points / 1024)] selection block counts / offsets
+  uint8_t *score_new;     // [budget] raw collision count of this frame's evaluation
+  uint32_t *hist;         // [2 * 65536] sample histograms
+  unsigned long long *cand_h;   // [1024] sample candidates: hash, key
+  int64_t *cand_k;
+  int64_t *sampled;       // [256] sampled changed voxels (keys)
+  IncrCounters *ctr;
+  int64_t max_points;
+  int32_t budget;
+};
+void launch_incr_init(const IncrDev &I, int32_t n_c, hipStream_t s);
+void launch_incr_frame_front(PointsDev pts, MapDev m, const IncrDev &I, const int32_t *changed,
+                             const FrameCounters *fc, int64_t n_points, int32_t frame, bool moved,
+                             int32_t min_w, hipStream_t s);
+void launch_incr_frame_back(PointsDev pts, MapDev m, ToolDev t, GridDev g, const IncrDev &I,
+                            int64_t n_points, int32_t n_c, hipStream_t s);
 
 // Smoothed clearance score.  T9: apron bricks of 9^3 floats (a brick's 8^3
 // voxels and the first layer of its +1 neighbours; tau where unmapped);
@@ -319,6 +377,8 @@ void launch_score(const Params &p, PointsDev pts, ToolDev t, GridDev g, int64_t 
                   int variant, unsigned *work, hipStream_t s, bool dev_n = false);
 int score_variants();
 int score_variant_default();
+// whether the configuration (after its fallbacks for this tool) honours PointsDev::sel
+bool score_variant_takes_list(int variant, const ToolDev &t);
 const char *score_variant_name(int v);
 
 }  // namespace af

@@ -58,9 +58,11 @@ __device__ inline int bit_length(uint64_t m) { return m ? 64 - __clzll((long lon
 // 28-bit renormalisation by rounded shifts) as its largest-norm column.
 __global__ void __launch_bounds__(kThreads)
 k_normals(Params p, MapDev m, PointsDev pts, GridDev g, int64_t n) {
-  if (n < 0) n = *pts.n_points;   // the point count on the device (recorded graphs)
-  int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (i >= n) return;
+  // n < 0: the point count on the device (recorded graphs, point lists)
+  if (n < 0) n = pts.sel ? (int64_t)*pts.n_sel : (int64_t)*pts.n_points;
+  const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (j >= n) return;
+  const int64_t i = pts.sel ? (int64_t)pts.sel[j] : j;
   int32_t addr = pts.addr[i];
   int W = addr >= 0 ? (int)m.W[addr] : 0;
   if (W < p.conf_min_w) {
@@ -279,11 +281,14 @@ constexpr int kMaskStageMw = 8;
 
 __global__ void __launch_bounds__(kThreads)
 k_mask(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t mw, int stage) {
-  if (n < 0) n = *pts.n_points;   // the point count on the device (recorded graphs)
+  // n < 0: the point count on the device (recorded graphs, point lists)
+  if (n < 0) n = pts.sel ? (int64_t)*pts.n_sel : (int64_t)*pts.n_points;
   if ((int64_t)blockIdx.x * kThreads >= n) return;   // whole workgroup past the end
   extern __shared__ uint64_t s_out[];   // [kThreads * mw] mask, then [kThreads * 2 mw] planes
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  const bool act = i < n;
+  const int64_t jj = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const bool act = jj < n;
+  // a point list scatters the rows: it is launched without staging
+  const int64_t i = pts.sel ? (act ? (int64_t)pts.sel[jj] : 0) : jj;
   const int hn = act ? pts.has_normal[i] : -1;
   double n0 = 0, n1 = 0, n2 = 0, nn = 0;
   double wx[kMaxVp], wy[kMaxVp], wz[kMaxVp], ww[kMaxVp];
@@ -1051,7 +1056,8 @@ template <int NT, int UN, int FB, int CO, int B1, int DIAG, int PF = 1, int RE =
 __global__ void __launch_bounds__(NT)
 k_score_near(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t mw,
              unsigned *work) {
-  if (n < 0) n = *pts.n_points;   // the point count on the device (recorded graphs)
+  // n < 0: the point count on the device (recorded graphs, point lists)
+  if (n < 0) n = pts.sel ? (int64_t)*pts.n_sel : (int64_t)*pts.n_points;
   constexpr int NW = NT / 64;
   __shared__ uint32_t s_begin[kNearK + 1];
   const int K = t.K;
@@ -1072,7 +1078,8 @@ k_score_near(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t m
     batch_end = i + FB;
   }
   for (; i < n;) {
-    near_point<UN, CO, B1, PF, RE>(p, pts, t, g, q, s_begin, mw, i, lane, a);
+    const int64_t pi = pts.sel ? (int64_t)__builtin_amdgcn_readfirstlane(pts.sel[i]) : i;
+    near_point<UN, CO, B1, PF, RE>(p, pts, t, g, q, s_begin, mw, pi, lane, a);
     if (a.lookups > (1u << 30)) near_flush<DIAG>(sc, a, lane);
     if (FB > 0) {
       if (++i >= batch_end) {
@@ -1208,7 +1215,7 @@ void launch_mask(const Params &p, PointsDev pts, ToolDev t, GridDev g, int64_t n
                  hipStream_t s, bool dev_n) {
   int32_t mw = (t.K + 63) / 64;
   if (n <= 0) return;
-  const int stage = mw <= kMaskStageMw ? 1 : 0;
+  const int stage = mw <= kMaskStageMw && !pts.sel ? 1 : 0;   // a point list scatters rows
   const size_t lds = stage ? sizeof(uint64_t) * kThreads * 3 * mw : 0;
   hipLaunchKernelGGL(k_mask, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads),
                      lds, s, p, pts, t, g, dev_n ? (int64_t)-1 : n, mw, stage);
@@ -1266,13 +1273,23 @@ void launch_score_multi(const Params &p, PointsDev pts, const ToolDev *tools_dev
                      dev_n ? (int64_t)-1 : n, work);
 }
 
+static int effective_variant(int variant, const ToolDev &t) {
+  if (variant < 0 || variant >= kNumVariants) variant = 0;
+  if (kVariants[variant].max_k && t.K > kVariants[variant].max_k) variant = 0;
+  if (kVariants[variant].needs_rel && !t.rent) variant = 0;
+  return variant;
+}
+
+bool score_variant_takes_list(int variant, const ToolDev &t) {
+  return strncmp(kVariants[effective_variant(variant, t)].name, "near", 4) == 0;
+}
+
 void launch_score(const Params &p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int variant,
                   unsigned *work, hipStream_t s, bool dev_n) {
   int32_t mw = (t.K + 63) / 64;
   if (n <= 0) return;
-  if (variant < 0 || variant >= kNumVariants) variant = 0;
-  if (kVariants[variant].max_k && t.K > kVariants[variant].max_k) variant = 0;
-  if (kVariants[variant].needs_rel && !t.rent) variant = 0;
+  variant = effective_variant(variant, t);
+  if (pts.sel && !score_variant_takes_list(variant, t)) return;   // callers check first
   const ScoreVariant &v = kVariants[variant];
   if (g_num_cu == 0) {
     int dev = 0;

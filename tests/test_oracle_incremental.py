@@ -182,3 +182,37 @@ def test_budget_and_backlog(oracle_mod, synth_mod):
     done = [k for k in keys if inc.state[int(k)]["outcome"] != 0]
     assert [int(k) for k in done] == conf[:100]                 # canonical order
     assert st["backlog"] == len(keys) - 100                     # the rest stay queued
+
+
+def _plane(depth, n=60, seed=0):
+    rng = np.random.default_rng(seed)
+    yz = rng.uniform(-0.3, 0.3, size=(n, 2))
+    return np.concatenate([np.full((n, 1), depth), yz], axis=1).astype(np.float32)
+
+
+def plane_frames():
+    """A 60 cm plane at 1 m seen head-on twice, then moved 9 cm back (v = 2 cm,
+    tau = 10 cm): the TSDF at some old surface voxels jumps by more than 2v."""
+    return [(_plane(d, seed=j), np.zeros(3, np.float32), j)
+            for j, d in enumerate([1.0, 1.0, 1.09, 1.09])]
+
+
+def test_trigger_i_on_a_moving_surface(oracle_mod, synth_mod):
+    from oracle.incremental import IncrementalOracle
+    w = synth_mod.tiny()
+    orc = oracle_mod.Oracle(voxel=0.02, trunc=0.10, r_c=0.01)
+    orc.set_tool(0, w.tool, w.rot)
+    inc = IncrementalOracle(orc, 0, len(w.rot), budget=10 ** 6)
+    par = orc.params()
+    for xyz, o, fid in plane_frames():
+        before = {int(k): orc.voxel(int(k))[:2] for k in orc.read_points()["key"]}
+        st = inc.frame(xyz, o, fid)
+        # the same test in metres, floating point: |T - T'| > 2v
+        n_i = 0
+        for k, (S0, W0) in before.items():
+            S1, W1 = orc.voxel(k)[:2]
+            if W0 > 0 and W1 > 0 and abs(S1 / W1 - S0 / W0) / par["scale"] > 2 * 0.02 + 1e-12:
+                n_i += 1
+        assert st["trig_i"] == n_i
+        if fid == 2:
+            assert n_i > 0
