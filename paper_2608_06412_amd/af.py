@@ -487,16 +487,21 @@ class Context:
         self._check(self._lib.af_incremental_stats(self.h, ctypes.byref(st)))
         return st.as_dict()
 
-    def read_incremental(self):
+    def read_incremental(self, labels_only: bool = False):
         """Incremental state in canonical point order: key, label, best
-        (stored collision count; n_c = none), best_dir, a."""
+        (stored collision count; n_c = none), best_dir, a (only key and label
+        with labels_only)."""
         n = self.num_points()
         key = np.zeros(n, np.int64)
         lbl = np.zeros(n, np.uint8)
+        nw = ctypes.c_int64()
+        if labels_only:
+            self._check(self._lib.af_read_incremental(self.h, 0, n, _p(key), _p(lbl), None, None,
+                                                      None, ctypes.byref(nw)))
+            return dict(key=key, label=lbl)
         best = np.zeros(n, np.uint8)
         bdir = np.zeros(n, np.int16)
         a = np.zeros(n, np.float64)
-        nw = ctypes.c_int64()
         self._check(self._lib.af_read_incremental(self.h, 0, n, _p(key), _p(lbl), _p(best),
                                                   _p(bdir), _p(a), ctypes.byref(nw)))
         return dict(key=key, label=lbl, best=best, best_dir=bdir, a=a)
