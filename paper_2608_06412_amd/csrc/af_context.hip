@@ -49,6 +49,7 @@ struct af_ctx {
   IncrDev incr;
   int32_t *incr_changed;        // [max_blocks * 512] changed voxel addresses of a frame
   int32_t q_last[3];            // sensor position when trigger (iii) last fired
+  int64_t incr_seen;            // points that already have a state
   bool have_q;
   // smoothed score: apron bricks and their tables (SmoothBuffers), grown on demand
   SmoothBuffers sm;
@@ -854,6 +855,8 @@ int af_graph_prepare(af_ctx *c, const float lo[3], const float hi[3], int64_t ma
                      const int32_t *tool_ids, int32_t n_tools, void *stream) {
   if (!c) return AF_EINVAL;
   if (!lo || !hi || max_returns < 1) return fail(c, AF_EINVAL, "bad graph arguments");
+  if (c->incr_on)
+    return fail(c, AF_EINVAL, "a context in incremental mode runs its frames eagerly");
   int rc;
   if (c->graph_dirty && (rc = graph_settle(c)) != AF_OK) return rc;
   ToolSet set;
@@ -934,8 +937,7 @@ int af_graph_frame(af_ctx *c, const float *xyz, int64_t n, const float origin[3]
   }
   hipStream_t s = (hipStream_t)stream;
   if (n > 0 && xyz != c->slot_xyz)
-    HIP_TRY(c, hipMemcpyAsync(c->slot_xyz, xyz, sizeof(float) * 3 * n, hipMemcpyDeviceToDevice,
-                              s));
+    HIP_TRY(c, hipMemcpyAsync(c->slot_xyz, xyz, sizeof(float) * 3 * n, hipMemcpyDefault, s));
   launch_set_frame_args(c->fargs, n, Q, (int32_t)frame_id, s);
   HIP_TRY(c, hipGraphLaunch(c->gexec, s));
   c->last_frame = frame_id;
@@ -1098,6 +1100,7 @@ int af_incremental_enable(af_ctx *c, int32_t tool_id, int32_t budget) {
   c->incr_on = true;
   c->incr_tool = tool_id;
   c->have_q = false;
+  c->incr_seen = 0;
   launch_incr_init(I, c->p.n_c, nullptr);
   return hip_check(c, "incremental enable");
 }
@@ -1129,7 +1132,8 @@ int af_incremental_frame(af_ctx *c, const float *xyz, int64_t n, const float ori
   }
   IncrDev &I = c->incr;
   launch_incr_frame_front(c->pts, c->map, I, c->incr_changed, c->counters, c->n_points,
-                          (int32_t)frame_id, moved, c->p.conf_min_w, s);
+                          c->incr_seen, (int32_t)frame_id, moved, c->p.conf_min_w, s);
+  c->incr_seen = c->n_points;
   PointsDev ps = c->pts;
   ps.sel = I.sel;
   ps.n_sel = I.n_sel;

@@ -92,14 +92,14 @@ __global__ void __launch_bounds__(kT) k_incr_init(IncrDev I, int32_t n_c) {
 // Triggers (i), (iii) and first observation; the point's S and W are kept
 // for the next frame.
 __global__ void __launch_bounds__(kT)
-k_incr_triggers(PointsDev pts, MapDev m, IncrDev I, int64_t n, int32_t frame, int moved) {
+k_incr_triggers(PointsDev pts, MapDev m, IncrDev I, int64_t n, int64_t seen, int moved) {
   const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
   int c_new = 0, c_i = 0, c_iii = 0;
   if (i < n) {
     const int32_t addr = pts.addr[i];
     const int64_t S = addr >= 0 ? (int64_t)m.S[addr] : 0;
     const int64_t W = addr >= 0 ? (int64_t)m.W[addr] : 0;
-    if (pts.first[i] == frame) {
+    if (i >= seen) {   // first observation (points are appended, never removed)
       I.pending[i] = 1u;
       c_new = 1;
     } else {
@@ -430,14 +430,14 @@ void launch_incr_init(const IncrDev &I, int32_t n_c, hipStream_t s) {
 }
 
 void launch_incr_frame_front(PointsDev pts, MapDev m, const IncrDev &I, const int32_t *changed,
-                             const FrameCounters *fc, int64_t n_points, int32_t frame, bool moved,
-                             int32_t min_w, hipStream_t s) {
+                             const FrameCounters *fc, int64_t n_points, int64_t seen, int32_t frame,
+                             bool moved, int32_t min_w, hipStream_t s) {
   hipLaunchKernelGGL(k_incr_fill, dim3(1), dim3(kT), 0, s, (uint32_t *)I.ctr,
                      (int64_t)(sizeof(IncrCounters) / 4), 0u);
   hipLaunchKernelGGL(k_incr_fill, dim3(256), dim3(kT), 0, s, I.hist, (int64_t)2 * 65536, 0u);
   if (n_points > 0)
     hipLaunchKernelGGL(k_incr_triggers, dim3(grid_of(n_points, kT)), dim3(kT), 0, s, pts, m, I,
-                       n_points, frame, moved ? 1 : 0);
+                       n_points, seen, moved ? 1 : 0);
   const dim3 wide(2048);
   hipLaunchKernelGGL(k_incr_hist, wide, dim3(kT), 0, s, m, changed, fc, frame, I, 0);
   hipLaunchKernelGGL(k_incr_pick, dim3(1), dim3(kSelT), 0, s, fc, I, 0);

@@ -285,8 +285,8 @@ struct IncrDev {
 };
 void launch_incr_init(const IncrDev &I, int32_t n_c, hipStream_t s);
 void launch_incr_frame_front(PointsDev pts, MapDev m, const IncrDev &I, const int32_t *changed,
-                             const FrameCounters *fc, int64_t n_points, int32_t frame, bool moved,
-                             int32_t min_w, hipStream_t s);
+                             const FrameCounters *fc, int64_t n_points, int64_t seen, int32_t frame,
+                             bool moved, int32_t min_w, hipStream_t s);
 void launch_incr_frame_back(PointsDev pts, MapDev m, ToolDev t, GridDev g, const IncrDev &I,
                             int64_t n_points, int32_t n_c, hipStream_t s);
 
