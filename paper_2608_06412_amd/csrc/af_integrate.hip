@@ -514,6 +514,9 @@ k_bin_fill(const FrameArgs *fa, Params p, MapDev m, FrameScratch fs) {
   }
 }
 
+// LIST: also list every voxel that received a contribution (incremental
+// mode); a separate instance, so the plain fold keeps its register budget.
+template <int LIST>
 __global__ void __launch_bounds__(kBlockVox)
 k_integrate_fold(const FrameArgs *fa, Params p, MapDev m, FrameScratch fs, FrameCounters *c,
                  GridDev g) {
@@ -596,7 +599,7 @@ k_integrate_fold(const FrameArgs *fa, Params p, MapDev m, FrameScratch fs, Frame
       m.W[v] = (uint16_t)W;
       ++folded;
     }
-    if (fs.changed) {   // list this voxel if it received a contribution (one atomic per wave)
+    if (LIST) {   // list this voxel if it received a contribution (one atomic per wave)
       const unsigned long long bal = __ballot(dW > 0);
       if (bal) {
         const int lane = (int)(threadIdx.x & 63u);
@@ -718,9 +721,14 @@ void launch_integrate(const FrameArgs *fa, int64_t nb, const Params &p, MapDev m
     hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, s, fs, c);
   }
   int64_t wg = max_touched < 8192 ? max_touched : 8192;
-  if (wg > 0)
-    hipLaunchKernelGGL(k_integrate_fold, dim3((unsigned)wg), dim3(kBlockVox), 0, s, fa, p, m,
-                       fs, c, g);
+  if (wg > 0) {
+    if (fs.changed)
+      hipLaunchKernelGGL(k_integrate_fold<1>, dim3((unsigned)wg), dim3(kBlockVox), 0, s, fa, p,
+                         m, fs, c, g);
+    else
+      hipLaunchKernelGGL(k_integrate_fold<0>, dim3((unsigned)wg), dim3(kBlockVox), 0, s, fa, p,
+                         m, fs, c, g);
+  }
 }
 
 void launch_touch_band(const FrameArgs *fa, int64_t nb, const Params &p, MapDev m,
