@@ -55,6 +55,9 @@ struct af_ctx {
   SmoothBuffers sm;
   int64_t sm_T_cap;             // voxels of sm.T
   int64_t sm_bid_cap;           // bricks of sm.bid and sm.bid9
+  // cached normal axes of the eager scoring calls (allocated on first use)
+  NormalCache ncache;
+  int64_t nc_seen;              // points whose neighbourhood the cache reflects
   std::vector<char> own_mask;   // tool has its own mask and plane buffers
   unsigned *work;               // point counter of the dynamic score variants
   int score_variant;
@@ -704,6 +707,8 @@ int af_integrate_frame(af_ctx *c, const float *xyz, int64_t n, const float origi
   return AF_OK;
 }
 
+static int cached_normals(af_ctx *c, hipStream_t s);
+
 int af_score_points(af_ctx *c, int32_t tool_id, void *stream) {
   if (!c) return AF_EINVAL;
   if (c->graph_dirty) {
@@ -719,7 +724,7 @@ int af_score_points(af_ctx *c, int32_t tool_id, void *stream) {
   hipEvent_t t0 = timing_mark(c, s);
   HIP_TRY(c, hipMemsetAsync(t.counters, 0, sizeof(ScoreCounters), s));
   hipEvent_t t1 = timing_mark(c, s);
-  launch_normals(c->p, c->map, c->pts, c->grid, c->n_points, s);
+  if ((rc = cached_normals(c, s)) != AF_OK) return rc;
   hipEvent_t t2 = timing_mark(c, s);
   launch_mask(c->p, c->pts, t, c->grid, c->n_points, s);
   hipEvent_t t3 = timing_mark(c, s);
@@ -778,6 +783,33 @@ static int make_toolset(af_ctx *c, const int32_t *tool_ids, int32_t n_tools, Too
 
 static int sync_last(af_ctx *c);
 
+// Normals of every point, recomputing only the axes that points appended
+// since the last call can have changed.
+static int cached_normals(af_ctx *c, hipStream_t s) {
+  NormalCache &nc = c->ncache;
+  if (!nc.axis) {
+    ALLOC(c, nc.axis, 3 * c->cfg.max_points);
+    ALLOC(c, nc.state, c->cfg.max_points);
+    ALLOC(c, nc.list, c->cfg.max_points);
+    ALLOC(c, nc.count, 1);
+    c->nc_seen = 0;
+  }
+  if (nc.stale_words < 16 * c->grid_bricks) {
+    if (nc.stale) {
+      HIP_TRY(c, hipStreamSynchronize(s));
+      dev_free(c, nc.stale, sizeof(uint32_t) * nc.stale_words);
+    }
+    nc.stale = nullptr;
+    nc.stale_words = 0;
+    ALLOC(c, nc.stale, 16 * c->grid_bricks);
+    nc.stale_words = 16 * c->grid_bricks;
+    HIP_TRY(c, hipMemsetAsync(nc.stale, 0, sizeof(uint32_t) * nc.stale_words, s));
+  }
+  launch_normals_cached(c->p, c->map, c->pts, c->grid, nc, c->nc_seen, c->n_points, s);
+  c->nc_seen = c->n_points;
+  return AF_OK;
+}
+
 int af_score_tools(af_ctx *c, const int32_t *tool_ids, int32_t n_tools, void *stream) {
   if (!c) return AF_EINVAL;
   int rc;
@@ -791,7 +823,7 @@ int af_score_tools(af_ctx *c, const int32_t *tool_ids, int32_t n_tools, void *st
   for (int32_t i = 0; i < n_tools; ++i)
     HIP_TRY(c, hipMemsetAsync(host[i].counters, 0, sizeof(ScoreCounters), s));
   hipEvent_t t1 = timing_mark(c, s);
-  launch_normals(c->p, c->map, c->pts, c->grid, c->n_points, s);
+  if ((rc = cached_normals(c, s)) != AF_OK) return rc;
   hipEvent_t t2 = timing_mark(c, s);
   for (int32_t i = 0; i < n_tools; ++i)
     launch_mask(c->p, c->pts, host[i], c->grid, c->n_points, s);

@@ -256,6 +256,21 @@ struct FrameArgs {
 };
 void launch_set_frame_args(FrameArgs *fa, int64_t n, int3 Q, int32_t frame, hipStream_t s);
 
+// Cached normal axes (state: -2 pending, 0 none, 1 axis valid).
+struct NormalCache {
+  int64_t *axis;      // [max_points * 3]
+  int32_t *state;     // [max_points]
+  int32_t *list;      // [max_points] points whose axis is recomputed
+  int32_t *count;
+  uint32_t *stale;    // [grid bricks * 16] voxels near new points; zero between calls
+  int64_t stale_words;
+};
+// Normals of points [0, n) where only the axes of points within +-3 voxels of
+// points [seen, n) are recomputed; `seen` is n of the previous call (0: all).
+// nc.stale must cover the current grid.
+void launch_normals_cached(const Params &p, MapDev m, PointsDev pts, GridDev g,
+                           const NormalCache &nc, int64_t seen, int64_t n, hipStream_t s);
+
 // Incremental mode: per-point state and per-frame scratch.
 struct IncrCounters {
   int32_t new_points, trig_i, trig_ii, trig_iii;

@@ -51,6 +51,104 @@ __device__ inline int64_t round_shift(int64_t x, int sh) {
 
 __device__ inline int bit_length(uint64_t m) { return m ? 64 - __clzll((long long)m) : 0; }
 
+// The least principal axis of point s's neighbourhood (before orientation):
+// returns 1 and the axis, or 0 when there is none (fewer than 3 neighbours,
+// or a degenerate scatter).  B and its powers are symmetric, so a squaring
+// forms six entries; every entry is at most 2^28 in magnitude after the
+// renormalisation, so products take 32-bit operands and 64-bit results.
+__device__ inline int normal_axis(const Params &p, const GridDev &g, const int32_t s[3],
+                                  int64_t axis[3]) {
+  // the point's brick and, when it is at least one brick inside the grid,
+  // its neighbours' words by brick deltas (no per-voxel bounds test)
+  const int bx = (s[0] >> 3) - g.g0[0], by = (s[1] >> 3) - g.g0[1], bz = (s[2] >> 3) - g.g0[2];
+  const bool interior = bx >= 1 && by >= 1 && bz >= 1 && bx <= g.gd[0] - 2 &&
+                        by <= g.gd[1] - 2 && bz <= g.gd[2] - 2;
+  const int gx = g.gd[0], gxy = g.gd[0] * g.gd[1];
+  const int b0 = (bz * g.gd[1] + by) * gx + bx;
+  const int lx0 = s[0] & 7, ly0 = s[1] & 7, lz0 = s[2] & 7;
+  int cnt = 0, last = -1;
+  int sx[3] = {0, 0, 0}, sxx[6] = {0, 0, 0, 0, 0, 0};
+  for (int j = 0; j < 343; ++j) {
+    int d2 = c_nb[4 * j + 3];
+    if (cnt >= p.knn_k && d2 != last) break;
+    int dx = c_nb[4 * j], dy = c_nb[4 * j + 1], dz = c_nb[4 * j + 2];
+    bool hit;
+    if (interior) {
+      const int rx = lx0 + dx, ry = ly0 + dy, rz = lz0 + dz;
+      const int dbx = rx >> 3, dby = ry >> 3, dbz = rz >> 3;
+      const int b = b0 + dbx + (dby == 0 ? 0 : (dby > 0 ? gx : -gx)) +
+                    (dbz == 0 ? 0 : (dbz > 0 ? gxy : -gxy));
+      const int ly = ry & 7, lz = rz & 7;
+      const uint32_t w = g.surf[b * 16 + ((ly >> 2) | (lz << 1))];
+      hit = (w >> ((rx & 7) | ((ly & 3) << 3))) & 1u;
+    } else {
+      hit = surf_bit(g, s[0] + dx, s[1] + dy, s[2] + dz);
+    }
+    if (!hit) continue;
+    ++cnt;
+    last = d2;
+    sx[0] += dx; sx[1] += dy; sx[2] += dz;
+    sxx[0] += dx * dx; sxx[1] += dx * dy; sxx[2] += dx * dz;
+    sxx[3] += dy * dy; sxx[4] += dy * dz; sxx[5] += dz * dz;
+  }
+  if (cnt < 3) return 0;
+  // M = cnt sxx - sx sx^T; B = tr(M) I - M, entries 00 01 02 11 12 22
+  const int32_t m00 = cnt * sxx[0] - sx[0] * sx[0], m01 = cnt * sxx[1] - sx[0] * sx[1];
+  const int32_t m02 = cnt * sxx[2] - sx[0] * sx[2], m11 = cnt * sxx[3] - sx[1] * sx[1];
+  const int32_t m12 = cnt * sxx[4] - sx[1] * sx[2], m22 = cnt * sxx[5] - sx[2] * sx[2];
+  const int32_t tr = m00 + m11 + m22;
+  int32_t e[6] = {tr - m00, -m01, -m02, tr - m11, -m12, tr - m22};
+  for (int it = 0; it < 8; ++it) {
+    auto mul = [](int32_t u, int32_t v) { return (int64_t)u * (int64_t)v; };
+    int64_t c[6];
+    c[0] = mul(e[0], e[0]) + mul(e[1], e[1]) + mul(e[2], e[2]);
+    c[1] = mul(e[0], e[1]) + mul(e[1], e[3]) + mul(e[2], e[4]);
+    c[2] = mul(e[0], e[2]) + mul(e[1], e[4]) + mul(e[2], e[5]);
+    c[3] = mul(e[1], e[1]) + mul(e[3], e[3]) + mul(e[4], e[4]);
+    c[4] = mul(e[1], e[2]) + mul(e[3], e[4]) + mul(e[4], e[5]);
+    c[5] = mul(e[2], e[2]) + mul(e[4], e[4]) + mul(e[5], e[5]);
+    uint64_t mx = 0;
+    for (int k = 0; k < 6; ++k) {
+      const uint64_t mag = (uint64_t)(c[k] < 0 ? -c[k] : c[k]);
+      mx = mag > mx ? mag : mx;
+    }
+    const int sh = bit_length(mx) - 28;
+    for (int k = 0; k < 6; ++k) e[k] = (int32_t)round_shift(c[k], sh);
+  }
+  const int64_t B[3][3] = {{e[0], e[1], e[2]}, {e[1], e[3], e[4]}, {e[2], e[4], e[5]}};
+  int best = 0;
+  int64_t bn = -1;
+  for (int c = 0; c < 3; ++c) {
+    int64_t nrm = B[0][c] * B[0][c] + B[1][c] * B[1][c] + B[2][c] * B[2][c];
+    if (nrm > bn) {
+      bn = nrm;
+      best = c;
+    }
+  }
+  if (bn <= 0) return 0;
+  for (int a = 0; a < 3; ++a) axis[a] = B[a][best];
+  return 1;
+}
+
+// Orient the axis towards the point's mean sensor position and store it.
+__device__ inline void store_normal(const PointsDev &pts, int64_t i, const int32_t s[3],
+                                    int has, const int64_t axis[3]) {
+  int32_t *nout = pts.normal + 3 * i;
+  if (!has) {
+    pts.has_normal[i] = 0;
+    nout[0] = nout[1] = nout[2] = 0;
+    return;
+  }
+  __int128 gdot = 0;
+  for (int a = 0; a < 3; ++a) {
+    int64_t ga = pts.sumq[3 * i + a] - (int64_t)pts.nq[i] * (256 * (int64_t)s[a] + 128);
+    gdot += (__int128)axis[a] * ga;
+  }
+  int sgn = gdot < 0 ? -1 : 1;
+  for (int a = 0; a < 3; ++a) nout[a] = (int32_t)(sgn * axis[a]);
+  pts.has_normal[i] = 1;
+}
+
 // Least principal axis of the k nearest surface voxels (ties at the k-th
 // distance included), oriented towards the mean sensor position.  The
 // scatter matrix M = n sum(dd^T) - (sum d)(sum d)^T is exact; the dominant
@@ -71,67 +169,117 @@ k_normals(Params p, MapDev m, PointsDev pts, GridDev g, int64_t n) {
   }
   int32_t s[3];
   unpack_key(pts.key[i], s[0], s[1], s[2]);
-  int cnt = 0, last = -1;
-  int sx[3] = {0, 0, 0}, sxx[6] = {0, 0, 0, 0, 0, 0};
-  for (int j = 0; j < 343; ++j) {
-    int d2 = c_nb[4 * j + 3];
-    if (cnt >= p.knn_k && d2 != last) break;
-    int dx = c_nb[4 * j], dy = c_nb[4 * j + 1], dz = c_nb[4 * j + 2];
-    if (!surf_bit(g, s[0] + dx, s[1] + dy, s[2] + dz)) continue;
-    ++cnt;
-    last = d2;
-    sx[0] += dx; sx[1] += dy; sx[2] += dz;
-    sxx[0] += dx * dx; sxx[1] += dx * dy; sxx[2] += dx * dz;
-    sxx[3] += dy * dy; sxx[4] += dy * dz; sxx[5] += dz * dz;
+  int64_t axis[3];
+  const int has = normal_axis(p, g, s, axis);
+  store_normal(pts, i, s, has, axis);
+}
+
+// Cached normals.  A point's axis depends only on the surface voxels within
+// +-3 of it, and surface voxels are only ever added (with new points), so an
+// axis changes only for points within +-3 of a point appended since the last
+// update.  Those voxels are marked in a bit plane over the brick grid (the
+// surf plane's layout), the points on marked voxels are listed and their axes
+// recomputed; every other point keeps its axis and is oriented anew (its
+// mean sensor position moves whenever it is observed).
+
+// One thread per (row of 7 voxels along x, brick it reaches): SET ors the
+// row's bits into the plane, !SET clears the words again.
+template <int SET>
+__global__ void __launch_bounds__(128) k_normals_mark(PointsDev pts, GridDev g, NormalCache nc,
+                                                      int64_t first) {
+  const int t = threadIdx.x;
+  if (t >= 98) return;
+  int32_t s[3];
+  unpack_key(pts.key[first + blockIdx.x], s[0], s[1], s[2]);
+  const int r = t >> 1, y = s[1] + r % 7 - 3, z = s[2] + r / 7 - 3;
+  const int xl = s[0] - 3, xh = s[0] + 3;
+  int x0, x1;
+  if ((t & 1) == 0) {
+    x0 = xl;
+    x1 = (xl | 7) < xh ? (xl | 7) : xh;
+  } else {
+    if ((xl >> 3) == (xh >> 3)) return;
+    x0 = xh & ~7;
+    x1 = xh;
   }
-  int32_t *nout = pts.normal + 3 * i;
-  if (cnt < 3) {
-    pts.has_normal[i] = 0;
-    nout[0] = nout[1] = nout[2] = 0;
-    return;
-  }
-  const int sym[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
-  int64_t B[3][3];
-  int64_t tr = 0;
-  for (int a = 0; a < 3; ++a) tr += (int64_t)cnt * sxx[sym[a][a]] - (int64_t)sx[a] * sx[a];
-  for (int a = 0; a < 3; ++a)
-    for (int b = 0; b < 3; ++b)
-      B[a][b] = (a == b ? tr : 0) - ((int64_t)cnt * sxx[sym[a][b]] - (int64_t)sx[a] * sx[b]);
-  for (int it = 0; it < 8; ++it) {
-    int64_t C[3][3];
-    uint64_t mx = 0;
-    for (int a = 0; a < 3; ++a)
-      for (int b = 0; b < 3; ++b) {
-        C[a][b] = B[a][0] * B[0][b] + B[a][1] * B[1][b] + B[a][2] * B[2][b];
-        uint64_t mag = (uint64_t)(C[a][b] < 0 ? -C[a][b] : C[a][b]);
-        mx = mag > mx ? mag : mx;
-      }
-    int sh = bit_length(mx) - 28;
-    for (int a = 0; a < 3; ++a)
-      for (int b = 0; b < 3; ++b) B[a][b] = round_shift(C[a][b], sh);
-  }
-  int best = 0;
-  int64_t bn = -1;
-  for (int c = 0; c < 3; ++c) {
-    int64_t nrm = B[0][c] * B[0][c] + B[1][c] * B[1][c] + B[2][c] * B[2][c];
-    if (nrm > bn) {
-      bn = nrm;
-      best = c;
+  const int64_t b = brick_index(g, x0, y, z);
+  if (b < 0) return;
+  const int row = ((y & 7) << 3) | ((z & 7) << 6);
+  uint32_t *w = nc.stale + b * 16 + (row >> 5);
+  if (SET)
+    atomicOr(w, ((1u << (x1 - x0 + 1)) - 1u) << ((row & 31) + (x0 & 7)));
+  else
+    *w = 0u;
+}
+
+__global__ void __launch_bounds__(kThreads) k_normals_reset(NormalCache nc, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i < n) nc.state[i] = -2;
+}
+
+// Every point: confidence gate; a confident point on a marked voxel, or one
+// whose axis is pending, is listed (one list append per workgroup); any other
+// confident point is oriented from its cached axis.
+constexpr int kOrientThreads = 1024;
+__global__ void __launch_bounds__(kOrientThreads)
+k_normals_orient(Params p, MapDev m, PointsDev pts, GridDev g, NormalCache nc, int64_t n,
+                 int marked) {
+  __shared__ int part[kOrientThreads / 64 + 1];
+  const int64_t i = (int64_t)blockIdx.x * kOrientThreads + threadIdx.x;
+  bool take = false;
+  if (i < n) {
+    const int32_t addr = pts.addr[i];
+    const bool conf = (addr >= 0 ? (int)m.W[addr] : 0) >= p.conf_min_w;
+    int32_t s[3];
+    unpack_key(pts.key[i], s[0], s[1], s[2]);
+    bool stale = nc.state[i] == -2;
+    if (marked && !stale) {
+      const int64_t b = brick_index(g, s[0], s[1], s[2]);
+      const int lin = (s[0] & 7) | ((s[1] & 7) << 3) | ((s[2] & 7) << 6);
+      stale = b >= 0 && ((nc.stale[b * 16 + (lin >> 5)] >> (lin & 31)) & 1u);
+    }
+    if (!conf) {
+      if (stale) nc.state[i] = -2;
+      pts.has_normal[i] = -1;
+    } else if (stale) {
+      take = true;
+    } else {
+      const int64_t axis[3] = {nc.axis[3 * i], nc.axis[3 * i + 1], nc.axis[3 * i + 2]};
+      store_normal(pts, i, s, nc.state[i] == 1, axis);
     }
   }
-  if (bn <= 0) {
-    pts.has_normal[i] = 0;
-    nout[0] = nout[1] = nout[2] = 0;
-    return;
+  const uint64_t bal = __ballot(take);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) part[wave] = __popcll(bal);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int w = 0; w < kOrientThreads / 64; ++w) {
+      const int c = part[w];
+      part[w] = t;
+      t += c;
+    }
+    part[kOrientThreads / 64] = t ? atomicAdd(nc.count, t) : 0;
   }
-  __int128 gdot = 0;
-  for (int a = 0; a < 3; ++a) {
-    int64_t ga = pts.sumq[3 * i + a] - (int64_t)pts.nq[i] * (256 * (int64_t)s[a] + 128);
-    gdot += (__int128)B[a][best] * ga;
-  }
-  int sgn = gdot < 0 ? -1 : 1;
-  for (int a = 0; a < 3; ++a) nout[a] = (int32_t)(sgn * B[a][best]);
-  pts.has_normal[i] = 1;
+  __syncthreads();
+  if (take)
+    nc.list[part[kOrientThreads / 64] + part[wave] + __popcll(bal & ((1ull << lane) - 1ull))] =
+        (int32_t)i;
+}
+
+// Listed (confident) points: recompute, cache and orient the axis.
+__global__ void __launch_bounds__(kThreads)
+k_normals_axis(Params p, PointsDev pts, GridDev g, NormalCache nc) {
+  const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (j >= *nc.count) return;
+  const int32_t i = nc.list[j];
+  int32_t s[3];
+  unpack_key(pts.key[i], s[0], s[1], s[2]);
+  int64_t axis[3] = {0, 0, 0};
+  const int has = normal_axis(p, g, s, axis);
+  for (int a = 0; a < 3; ++a) nc.axis[3 * (int64_t)i + a] = axis[a];
+  nc.state[i] = has;
+  store_normal(pts, i, s, has, axis);
 }
 
 // ---------------------------------------------------------------------------
@@ -1202,6 +1350,27 @@ void init_tables() {
 }
 
 }  // namespace
+
+void launch_normals_cached(const Params &p, MapDev m, PointsDev pts, GridDev g,
+                           const NormalCache &nc, int64_t seen, int64_t n, hipStream_t s) {
+  init_tables();
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_zero, dim3(1), dim3(1), 0, s, (unsigned *)nc.count);
+  const unsigned blocks = (unsigned)((n + kThreads - 1) / kThreads);
+  const bool all = seen <= 0 || (n - seen) * 8 > n;   // most of the map is new
+  const bool marked = !all && n > seen;
+  if (all)
+    hipLaunchKernelGGL(k_normals_reset, dim3(blocks), dim3(kThreads), 0, s, nc, n);
+  else if (marked)
+    hipLaunchKernelGGL(k_normals_mark<1>, dim3((unsigned)(n - seen)), dim3(128), 0, s, pts, g, nc,
+                       seen);
+  hipLaunchKernelGGL(k_normals_orient, dim3((unsigned)((n + kOrientThreads - 1) / kOrientThreads)),
+                     dim3(kOrientThreads), 0, s, p, m, pts, g, nc, n, marked ? 1 : 0);
+  if (marked)
+    hipLaunchKernelGGL(k_normals_mark<0>, dim3((unsigned)(n - seen)), dim3(128), 0, s, pts, g, nc,
+                       seen);
+  hipLaunchKernelGGL(k_normals_axis, dim3(blocks), dim3(kThreads), 0, s, p, pts, g, nc);
+}
 
 void launch_normals(const Params &p, MapDev m, PointsDev pts, GridDev g, int64_t n,
                     hipStream_t s, bool dev_n) {

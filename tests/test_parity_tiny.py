@@ -227,3 +227,37 @@ def test_capacity_overflow_reported(synth_mod):
     with pytest.raises(AFError) as e:
         ctx.integrate_frame(torch.from_numpy(f.xyz).cuda(), f.origin, 0)
     assert e.value.code == af.AF_EOVERFLOW
+
+
+def test_scoring_every_frame(synth_mod, oracle_mod):
+    """Scoring after every frame: the normal axes are cached between calls
+    and only those within reach of the frame's new points are recomputed
+    (from the sixth frame on, new points are under an eighth of the map);
+    labels after every frame and every normal after several frames equal
+    the oracle's fresh computation."""
+    torch = _torch()
+    w = synth_mod.tiny()
+    K = len(w.rot)
+    ctx = _ctx(w)
+    orc = _oracle(w)
+    ctx.set_tool_kernels(0, w.tool, w.rot)
+    orc.set_tool(0, w.tool, w.rot)
+    for f in w.frames():
+        print("tiny frame", f.frame_id, flush=True)
+        ctx.integrate_frame(torch.from_numpy(f.xyz).cuda(), f.origin, f.frame_id)
+        orc.integrate_frame(f.xyz, f.origin, f.frame_id)
+        ctx.score_points(0)
+        orc.score(0)
+        lab = ctx.read_labels(0)
+        keys, lbl, ff = orc.labels(K, lab["key"])
+        assert np.array_equal(lab["label"], lbl), f.frame_id
+        assert np.array_equal(lab["first_free"].astype(np.int32), ff), f.frame_id
+        if f.frame_id % 4 == 3:
+            dbg = ctx.read_point_debug(0)
+            for i, k in enumerate(lab["key"]):
+                r = orc.point_result(k, K)
+                if r["label"] == 0:
+                    assert dbg["has_normal"][i] == -1
+                    continue
+                assert dbg["has_normal"][i] == r["has_normal"], (f.frame_id, k)
+                assert np.array_equal(dbg["normal"][i].astype(np.int64), r["normal"]), k

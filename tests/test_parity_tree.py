@@ -126,3 +126,28 @@ def test_whole_map_properties(tree_run):
     ff = lab["first_free"][acc].astype(np.int64)
     words = dbg["mask"][acc][np.arange(acc.sum()), ff // 64]
     assert np.all((words >> (ff % 64).astype(np.uint64)) & np.uint64(1) == 1)
+
+
+def test_scoring_every_frame_matches_one_scoring(tree_run, synth_mod):
+    """A second context scores after every frame (normal axes cached and
+    recomputed near new points only); after the last frame its normals,
+    labels and first free orientations equal those of the context that
+    scored once, with every axis computed afresh."""
+    import torch
+    from paper_2608_06412_amd import Context, default_config
+    w, ctx, _, _, _, _ = tree_run
+    cfg = default_config(w.voxel, w.trunc, r_c=w.r_c, max_blocks=1 << 16, max_points=1 << 21,
+                         max_orientations=256, max_tools=1)
+    c2 = Context(cfg)
+    c2.set_tool_kernels(0, w.tool, w.rot)
+    for f in w.frames(N_FRAMES):
+        c2.integrate_frame(torch.from_numpy(f.xyz).cuda(), f.origin, f.frame_id)
+        c2.score_points(0)
+    ctx.score_points(0)
+    a, b = ctx.read_point_debug(0), c2.read_point_debug(0)
+    assert np.array_equal(a["has_normal"], b["has_normal"])
+    assert np.array_equal(a["normal"], b["normal"])
+    la, lb = ctx.read_labels(0), c2.read_labels(0)
+    assert np.array_equal(la["key"], lb["key"])
+    assert np.array_equal(la["label"], lb["label"])
+    assert np.array_equal(la["first_free"], lb["first_free"])
