@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <utility>
 #include <vector>
 
 #pragma clang fp contract(off)
@@ -16,6 +17,72 @@ constexpr int kWaves = kThreads / 64;
 
 // Neighbour window [-3, 3]^3 as (dx, dy, dz, |d|^2), sorted by |d|^2.
 __constant__ int8_t c_nb[343 * 4];
+
+// The same window as a compile-time table, shell by shell (order inside a
+// shell is irrelevant: the kNN keeps or drops whole shells).
+struct NbOrder {
+  int8_t e[343][4];
+};
+constexpr NbOrder make_nb_order() {
+  NbOrder o{};
+  int n = 0;
+  for (int d2 = 0; d2 <= 27; ++d2)
+    for (int z = -3; z <= 3; ++z)
+      for (int y = -3; y <= 3; ++y)
+        for (int x = -3; x <= 3; ++x)
+          if (x * x + y * y + z * z == d2) {
+            o.e[n][0] = (int8_t)x;
+            o.e[n][1] = (int8_t)y;
+            o.e[n][2] = (int8_t)z;
+            o.e[n][3] = (int8_t)d2;
+            ++n;
+          }
+  return o;
+}
+constexpr NbOrder kNbOrder = make_nb_order();
+
+// Shell boundaries of that table: shell s is entries [start[s], start[s + 1]).
+struct NbShells {
+  int n;
+  int start[29];
+};
+constexpr NbShells make_nb_shells() {
+  NbShells sh{};
+  for (int j = 0; j < 343; ++j)
+    if (j == 0 || kNbOrder.e[j][3] != kNbOrder.e[j - 1][3]) sh.start[sh.n++] = j;
+  sh.start[sh.n] = 343;
+  return sh;
+}
+constexpr NbShells kNbShells = make_nb_shells();
+
+// Window accumulation from the 7 slices: one entry (compile-time offsets).
+struct NbSums {
+  int cnt;
+  int sx[3], sxx[6];
+};
+template <int J>
+__device__ inline void nb_entry(const uint64_t (&slice)[7], NbSums &a) {
+  constexpr int dx = kNbOrder.e[J][0], dy = kNbOrder.e[J][1], dz = kNbOrder.e[J][2];
+  const int h = (int)((slice[dz + 3] >> (7 * (dy + 3) + dx + 3)) & 1u);
+  a.cnt += h;
+  a.sx[0] += dx * h; a.sx[1] += dy * h; a.sx[2] += dz * h;
+  a.sxx[0] += dx * dx * h; a.sxx[1] += dx * dy * h; a.sxx[2] += dx * dz * h;
+  a.sxx[3] += dy * dy * h; a.sxx[4] += dy * dz * h; a.sxx[5] += dz * dz * h;
+}
+template <int Lo, int... I>
+__device__ inline void nb_range(std::integer_sequence<int, I...>, const uint64_t (&slice)[7],
+                                NbSums &a) {
+  (nb_entry<Lo + I>(slice, a), ...);
+}
+// Shells S, S+1, ... until one ends with at least k voxels found.
+template <int S>
+__device__ inline void nb_shells(const uint64_t (&slice)[7], NbSums &a, int k) {
+  constexpr int lo = kNbShells.start[S], hi = kNbShells.start[S + 1];
+  nb_range<lo>(std::make_integer_sequence<int, hi - lo>{}, slice, a);
+  if constexpr (S + 1 < kNbShells.n) {
+    if (a.cnt < k) nb_shells<S + 1>(slice, a, k);
+  }
+}
 
 __device__ inline int lane_id() { return (int)(threadIdx.x & 63u); }
 
@@ -66,30 +133,72 @@ __device__ inline int normal_axis(const Params &p, const GridDev &g, const int32
   const int gx = g.gd[0], gxy = g.gd[0] * g.gd[1];
   const int b0 = (bz * g.gd[1] + by) * gx + bx;
   const int lx0 = s[0] & 7, ly0 = s[1] & 7, lz0 = s[2] & 7;
-  int cnt = 0, last = -1;
+  int cnt = 0;
   int sx[3] = {0, 0, 0}, sxx[6] = {0, 0, 0, 0, 0, 0};
-  for (int j = 0; j < 343; ++j) {
-    int d2 = c_nb[4 * j + 3];
-    if (cnt >= p.knn_k && d2 != last) break;
-    int dx = c_nb[4 * j], dy = c_nb[4 * j + 1], dz = c_nb[4 * j + 2];
-    bool hit;
-    if (interior) {
-      const int rx = lx0 + dx, ry = ly0 + dy, rz = lz0 + dz;
-      const int dbx = rx >> 3, dby = ry >> 3, dbz = rz >> 3;
-      const int b = b0 + dbx + (dby == 0 ? 0 : (dby > 0 ? gx : -gx)) +
-                    (dbz == 0 ? 0 : (dbz > 0 ? gxy : -gxy));
-      const int ly = ry & 7, lz = rz & 7;
-      const uint32_t w = g.surf[b * 16 + ((ly >> 2) | (lz << 1))];
-      hit = (w >> ((rx & 7) | ((ly & 3) << 3))) & 1u;
-    } else {
-      hit = surf_bit(g, s[0] + dx, s[1] + dy, s[2] + dz);
+  if (interior) {
+    // The window's surface bits as seven 49-bit slices (bit 7 (dy + 3) +
+    // dx + 3 of slice dz + 3), read up front: per z, up to three 4-row y
+    // groups in each of up to two x bricks, 42 independent word loads.
+    const int dbxl = (lx0 - 3) >> 3, dbxr = (lx0 + 3) >> 3;
+    const int glo = (ly0 - 3) >> 2;
+    const int xsh = lx0 - 3 - 8 * dbxl;
+    const __amdgpu_buffer_rsrc_t sr = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)g.surf, (short)0, (int)((uint32_t)gxy * (uint32_t)g.gd[2] << 6), 0x00020000);
+    uint64_t slice[7];
+#pragma unroll
+    for (int zz = 0; zz < 7; ++zz) {
+      const int rz = lz0 + zz - 3;
+      const int zb = b0 + ((rz >> 3) == 0 ? 0 : ((rz >> 3) > 0 ? gxy : -gxy));
+      const int zw = (rz & 7) << 1;
+      uint32_t wl[3], wr[3];
+#pragma unroll
+      for (int gi = 0; gi < 3; ++gi) {
+        const int gg = glo + gi;
+        const int yb = zb + ((gg >> 1) == 0 ? 0 : ((gg >> 1) > 0 ? gx : -gx));
+        const int w = (gg & 1) | zw;
+        wl[gi] = __builtin_amdgcn_raw_buffer_load_b32(sr, ((yb + dbxl) * 16 + w) << 2, 0, 0);
+        wr[gi] = __builtin_amdgcn_raw_buffer_load_b32(sr, ((yb + dbxr) * 16 + w) << 2, 0, 0);
+      }
+      uint64_t sl = 0;
+#pragma unroll
+      for (int yy = 0; yy < 7; ++yy) {
+        const int ry = ly0 + yy - 3;
+        const int gi = (ry >> 2) - glo;
+        const uint32_t l = gi == 0 ? wl[0] : (gi == 1 ? wl[1] : wl[2]);
+        const uint32_t r = gi == 0 ? wr[0] : (gi == 1 ? wr[1] : wr[2]);
+        const int yb8 = (ry & 3) << 3;
+        const uint32_t v16 = ((l >> yb8) & 0xffu) | (((r >> yb8) & 0xffu) << 8);
+        sl |= (uint64_t)((v16 >> xsh) & 0x7fu) << (7 * yy);
+      }
+      slice[zz] = sl;
     }
-    if (!hit) continue;
-    ++cnt;
-    last = d2;
-    sx[0] += dx; sx[1] += dy; sx[2] += dz;
-    sxx[0] += dx * dx; sxx[1] += dx * dy; sxx[2] += dx * dz;
-    sxx[3] += dy * dy; sxx[4] += dy * dz; sxx[5] += dz * dz;
+    // keep the window reads ahead of the shells (the compiler would sink
+    // each slice into the first shell that uses it, serialising the reads)
+#pragma unroll
+    for (int zz = 0; zz < 7; ++zz) {
+      uint32_t lo = (uint32_t)slice[zz], hi = (uint32_t)(slice[zz] >> 32);
+      asm volatile("" : "+v"(lo), "+v"(hi));
+      slice[zz] = ((uint64_t)hi << 32) | lo;
+    }
+    // whole shells in order until one ends with k found (ties included)
+    NbSums a{};
+    nb_shells<0>(slice, a, p.knn_k);
+    cnt = a.cnt;
+    for (int c = 0; c < 3; ++c) sx[c] = a.sx[c];
+    for (int c = 0; c < 6; ++c) sxx[c] = a.sxx[c];
+  } else {
+    int last = -1;
+    for (int j = 0; j < 343; ++j) {
+      int d2 = c_nb[4 * j + 3];
+      if (cnt >= p.knn_k && d2 != last) break;
+      int dx = c_nb[4 * j], dy = c_nb[4 * j + 1], dz = c_nb[4 * j + 2];
+      if (!surf_bit(g, s[0] + dx, s[1] + dy, s[2] + dz)) continue;
+      ++cnt;
+      last = d2;
+      sx[0] += dx; sx[1] += dy; sx[2] += dz;
+      sxx[0] += dx * dx; sxx[1] += dx * dy; sxx[2] += dx * dz;
+      sxx[3] += dy * dy; sxx[4] += dy * dz; sxx[5] += dz * dz;
+    }
   }
   if (cnt < 3) return 0;
   // M = cnt sxx - sx sx^T; B = tr(M) I - M, entries 00 01 02 11 12 22
