@@ -590,16 +590,20 @@ k_mask(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t mw, int
   bool ok = false;     // candidate bit of the previous orientation
   uint32_t nb = 0u;    // its arm-sample result
   for (int w = 0; w < mw; ++w) {
-    uint64_t word = 0, pl0 = 0, pl1 = 0;
     const int kend = t.K - 64 * w < 64 ? t.K - 64 * w : 64;
-    const uint64_t same = t.same[w];
-    for (int j = 0; j < kend; ++j) {
-      if ((same >> j) & 1ull) {   // same direction as orientation k - 1
-        word |= (uint64_t)ok << j;
-        pl0 |= (uint64_t)(nb & 1u) << j;
-        pl1 |= (uint64_t)(nb >> 1) << j;
-        continue;
-      }
+    const uint64_t valid = kend == 64 ? ~0ull : ((1ull << kend) - 1ull);
+    const uint64_t heads = ~t.same[w] & valid;   // orientations with their own direction
+    // An orientation that shares its predecessor's approach direction takes
+    // its candidate bit and arm-sample result, so only heads are evaluated
+    // and each head's result covers its run of orientations (bits below the
+    // first head continue the previous word's last run).
+    const uint64_t carry = heads ? ((heads & (~heads + 1ull)) - 1ull) : valid;
+    uint64_t word = ok ? carry : 0ull;
+    uint64_t pl0 = (nb & 1u) ? carry : 0ull, pl1 = (nb >> 1) ? carry : 0ull;
+    for (uint64_t rem = heads; rem; rem &= rem - 1ull) {
+      const int j = __ffsll((unsigned long long)rem) - 1;
+      const uint64_t above = j == 63 ? 0ull : heads & ~((2ull << j) - 1ull);
+      const uint64_t run = (above ? (above & (~above + 1ull)) - 1ull : valid) & ~((1ull << j) - 1ull);
       const double *R = t.rot + 9 * (int64_t)(64 * w + j);
       const double d0 = R[0], d1 = R[3], d2 = R[6];
       ok = hn >= 0;
@@ -626,9 +630,9 @@ k_mask(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t mw, int
         const uint32_t h2 = code_sw(q, f, t.xent[b + 2]) != 0u;
         nb = h0 ? 1u : (h1 ? 2u : (h2 ? 3u : 0u));
       }
-      word |= (uint64_t)ok << j;
-      pl0 |= (uint64_t)(nb & 1u) << j;
-      pl1 |= (uint64_t)(nb >> 1) << j;
+      word |= ok ? run : 0ull;
+      pl0 |= (nb & 1u) ? run : 0ull;
+      pl1 |= (nb >> 1) ? run : 0ull;
     }
     if (stage) {
       s_out[threadIdx.x * mw + w] = word;
