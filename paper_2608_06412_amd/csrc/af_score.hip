@@ -544,6 +544,7 @@ k_mask(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t mw, int
   extern __shared__ uint64_t s_out[];   // [kThreads * mw] mask, then [kThreads * 2 mw] planes
   const int64_t jj = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const bool act = jj < n;
+  const int lane = lane_id();
   // a point list scatters the rows: it is launched without staging
   const int64_t i = pts.sel ? (act ? (int64_t)pts.sel[jj] : 0) : jj;
   const int hn = act ? pts.has_normal[i] : -1;
@@ -597,6 +598,14 @@ k_mask(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t mw, int
     // its candidate bit and arm-sample result, so only heads are evaluated
     // and each head's result covers its run of orientations (bits below the
     // first head continue the previous word's last run).
+    // lane j holds the three arm entries of orientation 64 w + j (read
+    // once per word, their latency hidden behind the first heads' tests)
+    uint2 ae[3] = {{0u, 0u}, {0u, 0u}, {0u, 0u}};
+    if (lane < kend) {
+      const uint32_t b = t.begin[64 * w + lane];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) ae[a] = t.xent[b + a];
+    }
     const uint64_t carry = heads ? ((heads & (~heads + 1ull)) - 1ull) : valid;
     uint64_t word = ok ? carry : 0ull;
     uint64_t pl0 = (nb & 1u) ? carry : 0ull, pl1 = (nb >> 1) ? carry : 0ull;
@@ -624,11 +633,14 @@ k_mask(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t mw, int
       }
       nb = 0u;
       if (ok) {
-        const uint32_t b = t.begin[64 * w + j];
-        const uint32_t h0 = code_sw(q, f, t.xent[b]) != 0u;
-        const uint32_t h1 = code_sw(q, f, t.xent[b + 1]) != 0u;
-        const uint32_t h2 = code_sw(q, f, t.xent[b + 2]) != 0u;
-        nb = h0 ? 1u : (h1 ? 2u : (h2 ? 3u : 0u));
+        uint32_t h[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const uint2 e = {(uint32_t)__builtin_amdgcn_readlane((int)ae[a].x, j),
+                           (uint32_t)__builtin_amdgcn_readlane((int)ae[a].y, j)};
+          h[a] = code_sw(q, f, e) != 0u;
+        }
+        nb = h[0] ? 1u : (h[1] ? 2u : (h[2] ? 3u : 0u));
       }
       word |= ok ? run : 0ull;
       pl0 |= (nb & 1u) ? run : 0ull;
