@@ -883,10 +883,14 @@ __device__ inline uint32_t plane_sum(const uint64_t pl[4], uint64_t m) {
 // entries loaded while this step's voxel words are gathered.  B1: the
 // entries are body or corridor entries only (no arm samples), read from the
 // one-bit plane.  RE: the 4-byte entry form.
+// With `first` (UN = 1), the first step's entries were already read by the
+// caller (entry min(b + lane, any index of the orientation): lanes past e are
+// masked out below).
 template <int UN, int B1, int RE>
 __device__ inline bool scan_fine_sw(const Params &p, const ToolDev &t, const SwGrid &q,
                                     const SwFrame &f, uint32_t b, uint32_t e, int &body,
-                                    uint32_t &lookups, uint32_t &steps) {
+                                    uint32_t &lookups, uint32_t &steps,
+                                    const typename EntryOf<RE>::T *first = nullptr) {
   using Ent = typename EntryOf<RE>::T;
   if (b >= e) return true;
   const uint32_t lane = (uint32_t)lane_id();
@@ -894,7 +898,10 @@ __device__ inline bool scan_fine_sw(const Params &p, const ToolDev &t, const SwG
 #pragma unroll
   for (int u = 0; u < UN; ++u) {
     const uint32_t idx = b + 64 * u + lane;
-    ent[u] = load_entry<RE>(t, idx < e ? idx : e - 1);
+    if (UN == 1 && first)
+      ent[u] = *first;
+    else
+      ent[u] = load_entry<RE>(t, idx < e ? idx : e - 1);
   }
   for (uint32_t base = b; base < e; base += 64 * UN) {
     ++steps;
@@ -962,11 +969,12 @@ __device__ inline bool scan_rest_sw(const Params &p, const ToolDev &t, const SwG
                                     const SwFrame &f, int k, uint32_t b, uint32_t e, int body,
                                     uint32_t &lookups, uint32_t &cchecks, uint32_t &cclear,
                                     uint32_t &sbody, uint32_t &sfar, const uint32_t c4[3],
-                                    const uint8_t *occ4) {
-  if (!CO) return scan_fine_sw<UN, B1, RE>(p, t, q, f, b, e, body, lookups, sbody);
+                                    const uint8_t *occ4,
+                                    const typename EntryOf<RE>::T *first = nullptr) {
+  if (!CO) return scan_fine_sw<UN, B1, RE>(p, t, q, f, b, e, body, lookups, sbody, first);
   const uint32_t fb = t.far_begin[k];
   const uint32_t mid = fb > b ? fb : b;
-  if (!scan_fine_sw<UN, B1, RE>(p, t, q, f, b, mid, body, lookups, sbody)) return false;
+  if (!scan_fine_sw<UN, B1, RE>(p, t, q, f, b, mid, body, lookups, sbody, first)) return false;
   if (mid >= e) return true;
   if (t.c4flag[k] != 0) {
     ++cchecks;
@@ -1233,6 +1241,17 @@ __device__ inline void near_point(const Params &p, const PointsDev &pts, const T
                               readlane64(mine, 2 * mw + w) & word, 0ull, 0ull};
       uint64_t open = word & ~(pl[0] | pl[1]);
       uint64_t left = word;
+      // PF = 1: the first step's entries of the next candidate are requested
+      // before the current candidate is scanned
+      using Ent = typename EntryOf<RE>::T;
+      Ent pre{};
+      auto first_step = [&](uint64_t o) {
+        const int kn = 64 * w + (__ffsll((long long)o) - 1);
+        const uint32_t bn = s_begin[kn] + E, en = s_begin[kn + 1];
+        const uint32_t idx = bn + (uint32_t)lane;
+        return load_entry<RE>(t, idx < en ? idx : en - 1);
+      };
+      if (PF == 1 && open) pre = first_step(open);
       while (open && ff < 0) {
         // the next PF candidates that need their body and corridor
         int js[PF];
@@ -1243,6 +1262,8 @@ __device__ inline void near_point(const Params &p, const PointsDev &pts, const T
           nb += open != 0ull;
           open &= open - 1;
         }
+        const Ent cur = pre;
+        if (PF == 1 && open) pre = first_step(open);
         // their first F entries after the arm samples, F lanes each
         uint64_t nf = 0, bm = 0;
         if (PF > 1) {
@@ -1292,7 +1313,8 @@ __device__ inline void near_point(const Params &p, const PointsDev &pts, const T
             start = b + nin;
           }
           if (scan_rest_sw<UN, CO, B1, RE>(p, t, q, f, kj, start, e, body, acc.lookups, acc.cchecks,
-                                           acc.cclear, acc.sbody, acc.sfar, c4, g.occ4)) {
+                                           acc.cclear, acc.sbody, acc.sfar, c4, g.occ4,
+                                           PF == 1 && UN == 1 ? &cur : nullptr)) {
             ff = (int16_t)kj;
             break;
           }
