@@ -1179,6 +1179,21 @@ struct NearAcc {
   uint32_t tests, lookups, arm, deep, chunks, cchecks, cclear, sbody, sfar;
 };
 
+// A zeroed accumulator set held in vector registers: the counts are
+// wave-uniform, but in scalar registers they cost this kernel occupancy.
+__device__ inline NearAcc near_acc_zero() {
+  NearAcc a;
+  uint32_t *f = &a.labv;
+  static_assert(sizeof(NearAcc) == 10 * sizeof(uint32_t), "ten counters");
+#pragma unroll
+  for (int k = 0; k < 10; ++k) {
+    uint32_t z;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+    f[k] = z;
+  }
+  return a;
+}
+
 template <int DIAG>
 __device__ inline void near_flush(ScoreCounterBlock &sc, NearAcc &a, int lane) {
   if (lane < 4 && a.labv) {
@@ -1201,7 +1216,7 @@ __device__ inline void near_flush(ScoreCounterBlock &sc, NearAcc &a, int lane) {
       if (a.sfar) atomicAdd(&sc.chunks_far, (unsigned long long)a.sfar);
     }
   }
-  a = NearAcc{0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+  a = near_acc_zero();
 }
 
 // One point of the "near" scoring (see k_score_near): label and first free
@@ -1348,7 +1363,7 @@ __device__ inline void near_point(const Params &p, const PointsDev &pts, const T
 // Same labels, first free orientations and canonical counts as the plain
 // scan.
 template <int NT, int UN, int FB, int CO, int B1, int DIAG, int PF = 1, int RE = 0>
-__global__ void __launch_bounds__(NT)
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8)))
 k_score_near(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t mw,
              unsigned *work) {
   // n < 0: the point count on the device (recorded graphs, point lists)
@@ -1364,7 +1379,7 @@ k_score_near(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t m
       (int64_t)blockIdx.x * NW + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t nwaves = (int64_t)gridDim.x * NW;
   ScoreCounterBlock &sc = t.counters->s[(blockIdx.x * NW + (threadIdx.x >> 6)) % kStatSlots];
-  NearAcc a{0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+  NearAcc a = near_acc_zero();
   int64_t i = wave0, batch_end = wave0 + 1;
   if (FB > 0) {
     unsigned got = 0;
@@ -1398,7 +1413,7 @@ k_score_near(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t m
 constexpr int kMultiBegin = 8 * (kNearK + 1);
 
 template <int NT, int UN, int FB, int CO, int B1, int PF, int RE>
-__global__ void __launch_bounds__(NT)
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8)))
 k_score_near_multi(Params p, PointsDev pts, const ToolDev *tools, ToolSet set, GridDev g,
                    int64_t n, unsigned *work) {
   if (n < 0) n = *pts.n_points;   // the point count on the device (recorded graphs)
@@ -1413,7 +1428,7 @@ k_score_near_multi(Params p, PointsDev pts, const ToolDev *tools, ToolSet set, G
   const SwGrid q = sw_grid(g);
   const int lane = lane_id();
   const int slot = (blockIdx.x * NW + (threadIdx.x >> 6)) % kStatSlots;
-  NearAcc a{0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+  NearAcc a = near_acc_zero();
   const int64_t total = n * set.n;
   int64_t j = 0, batch_end = 0;
   int cur = -1;
