@@ -294,22 +294,38 @@ class Context:
         self._check(self._lib.af_score_points(self.h, int(tool_id), _stream_handle(stream)))
 
     def read_labels(self, tool_id: int, first: int = 0, count: int | None = None,
-                    with_w: bool = False):
+                    with_w: bool = False, out: dict | None = None, keys: bool = True):
+        """Labels of points [first, first + count) in canonical order.  `out`
+        may hold preallocated host arrays ("key" int64, "label" uint8,
+        "first_free" int16, at least count long; pinned memory makes the copy
+        fast), which are filled and returned as views; keys=False skips the
+        keys."""
         n = self.num_points()
         count = n - first if count is None else count
         count = max(0, min(count, n - first))
-        key = np.zeros(count, np.int64)
-        lbl = np.zeros(count, np.uint8)
-        ff = np.zeros(count, np.int16)
+
+        def buf(name, dtype):
+            a = None if out is None else out.get(name)
+            if a is None:
+                return np.zeros(count, dtype)
+            if a.dtype != dtype or not a.flags["C_CONTIGUOUS"] or len(a) < count:
+                raise ValueError("out[%r]: need a contiguous %s array of at least %d"
+                                 % (name, np.dtype(dtype).name, count))
+            return a
+        key = buf("key", np.int64) if keys else None
+        lbl = buf("label", np.uint8)
+        ff = buf("first_free", np.int16)
         w = np.zeros(count, np.uint16) if with_w else None
         nw = ctypes.c_int64()
         self._check(self._lib.af_read_labels(self.h, int(tool_id), int(first), int(count),
-                                             _p(key), _p(lbl), _p(ff),
+                                             _p(key) if keys else None, _p(lbl), _p(ff),
                                              _p(w) if with_w else None, ctypes.byref(nw)))
-        out = dict(key=key[:nw.value], label=lbl[:nw.value], first_free=ff[:nw.value])
+        res = dict(label=lbl[:nw.value], first_free=ff[:nw.value])
+        if keys:
+            res["key"] = key[:nw.value]
         if with_w:
-            out["w"] = w[:nw.value]
-        return out
+            res["w"] = w[:nw.value]
+        return res
 
     # ---- inspection ----
     def num_points(self) -> int:
@@ -487,24 +503,37 @@ class Context:
         self._check(self._lib.af_incremental_stats(self.h, ctypes.byref(st)))
         return st.as_dict()
 
-    def read_incremental(self, labels_only: bool = False):
-        """Incremental state in canonical point order: key, label, best
-        (stored collision count; n_c = none), best_dir, a (only key and label
-        with labels_only)."""
-        n = self.num_points()
-        key = np.zeros(n, np.int64)
-        lbl = np.zeros(n, np.uint8)
+    def read_incremental(self, labels_only: bool = False, first: int = 0,
+                         label_out: np.ndarray | None = None, keys: bool = True):
+        """Incremental state in canonical point order from point `first`:
+        key, label, best (stored collision count; n_c = none), best_dir, a
+        (only key and label with labels_only).  label_out: a preallocated
+        uint8 host array (pinned memory makes the copy fast) for the labels;
+        keys=False skips the keys."""
+        n = max(0, self.num_points() - first)
+        key = np.zeros(n, np.int64) if keys else None
+        if label_out is not None:
+            if label_out.dtype != np.uint8 or not label_out.flags["C_CONTIGUOUS"] \
+                    or len(label_out) < n:
+                raise ValueError("label_out: need a contiguous uint8 array of at least %d" % n)
+            lbl = label_out[:n]
+        else:
+            lbl = np.zeros(n, np.uint8)
+        kp = _p(key) if keys else None
         nw = ctypes.c_int64()
         if labels_only:
-            self._check(self._lib.af_read_incremental(self.h, 0, n, _p(key), _p(lbl), None, None,
-                                                      None, ctypes.byref(nw)))
-            return dict(key=key, label=lbl)
+            self._check(self._lib.af_read_incremental(self.h, int(first), n, kp, _p(lbl), None,
+                                                      None, None, ctypes.byref(nw)))
+            return dict(key=key, label=lbl) if keys else dict(label=lbl)
         best = np.zeros(n, np.uint8)
         bdir = np.zeros(n, np.int16)
         a = np.zeros(n, np.float64)
-        self._check(self._lib.af_read_incremental(self.h, 0, n, _p(key), _p(lbl), _p(best),
+        self._check(self._lib.af_read_incremental(self.h, int(first), n, kp, _p(lbl), _p(best),
                                                   _p(bdir), _p(a), ctypes.byref(nw)))
-        return dict(key=key, label=lbl, best=best, best_dir=bdir, a=a)
+        out = dict(label=lbl, best=best, best_dir=bdir, a=a)
+        if keys:
+            out["key"] = key
+        return out
 
     def score_variant_default(self) -> int:
         return self._lib.af_score_variant_default()
