@@ -885,8 +885,9 @@ __device__ inline uint32_t plane_sum(const uint64_t pl[4], uint64_t m) {
 // one-bit plane.  RE: the 4-byte entry form.
 // With `first` (UN = 1), the first step's entries were already read by the
 // caller (entry min(b + lane, any index of the orientation): lanes past e are
-// masked out below).
-template <int UN, int B1, int RE>
+// masked out below).  CL: 0 entries of any class, 1 body entries only (a
+// table lists body entries before corridor entries), 2 corridor entries only.
+template <int UN, int B1, int RE, int CL = 0>
 __device__ inline bool scan_fine_sw(const Params &p, const ToolDev &t, const SwGrid &q,
                                     const SwFrame &f, uint32_t b, uint32_t e, int &body,
                                     uint32_t &lookups, uint32_t &steps,
@@ -917,13 +918,22 @@ __device__ inline bool scan_fine_sw(const Params &p, const ToolDev &t, const SwG
 #pragma unroll
     for (int u = 0; u < UN; ++u) {
       const uint32_t cb = base + 64 * u;
-      const uint32_t cls = ent_cls(ent[u]);
-      const bool hit = cb + lane < e &&
-                       (B1 || cls != AF_CLS_NEAR ? (code[u] & 1u) != 0u : code[u] != 0u);
-      const uint64_t nf = __ballot(hit && cls != AF_CLS_BODY);
-      const uint64_t bm = __ballot(hit && cls == AF_CLS_BODY);
+      uint64_t nf, bm;
+      if (CL == 0) {
+        const uint32_t cls = ent_cls(ent[u]);
+        const bool hit = cb + lane < e &&
+                         (B1 || cls != AF_CLS_NEAR ? (code[u] & 1u) != 0u : code[u] != 0u);
+        nf = __ballot(hit && cls != AF_CLS_BODY);
+        bm = __ballot(hit && cls == AF_CLS_BODY);
+      } else {
+        const uint64_t hm = __ballot(cb + lane < e && (code[u] & 1u) != 0u);
+        nf = CL == 2 ? hm : 0ull;
+        bm = CL == 1 ? hm : 0ull;
+      }
       if (cb >= e) break;
-      const int stop = chunk_stop(nf, bm, p.n_c - body);
+      const int stop = CL == 1   ? nth_bit(bm, p.n_c - body)
+                       : CL == 2 ? (nf ? __ffsll((long long)nf) - 1 : 64)
+                                 : chunk_stop(nf, bm, p.n_c - body);
       if (stop < 64) {
         lookups += (uint32_t)stop + 1u;
         return false;
@@ -974,7 +984,8 @@ __device__ inline bool scan_rest_sw(const Params &p, const ToolDev &t, const SwG
   if (!CO) return scan_fine_sw<UN, B1, RE>(p, t, q, f, b, e, body, lookups, sbody, first);
   const uint32_t fb = t.far_begin[k];
   const uint32_t mid = fb > b ? fb : b;
-  if (!scan_fine_sw<UN, B1, RE>(p, t, q, f, b, mid, body, lookups, sbody, first)) return false;
+  if (!scan_fine_sw<UN, B1, RE, B1 ? 1 : 0>(p, t, q, f, b, mid, body, lookups, sbody, first))
+    return false;
   if (mid >= e) return true;
   if (t.c4flag[k] != 0) {
     ++cchecks;
@@ -984,7 +995,7 @@ __device__ inline bool scan_rest_sw(const Params &p, const ToolDev &t, const SwG
       return true;
     }
   }
-  return scan_fine_sw<UN, B1, RE>(p, t, q, f, mid, e, body, lookups, sfar);
+  return scan_fine_sw<UN, B1, RE, B1 ? 2 : 0>(p, t, q, f, mid, e, body, lookups, sfar);
 }
 
 // Candidate-parallel scoring with grid-relative lookups (the configurations
