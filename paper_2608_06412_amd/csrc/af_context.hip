@@ -210,6 +210,10 @@ int ensure_grid(af_ctx *c, hipStream_t s, bool &rebuilt) {
   ng.margin = need;
   if (nb * 128 >= (int64_t(1) << 32))
     return fail(c, AF_ENOMEM, "brick grid of %lld bricks exceeds 4 GiB", (long long)nb);
+  // the lookups multiply brick strides in 24 bits (always true here: every
+  // axis spans at least 2 * 4 + 1 bricks)
+  if ((int64_t)ng.gd[0] * ng.gd[1] >= (int64_t(1) << 24))
+    return fail(c, AF_ENOMEM, "brick grid of %d x %d bricks per layer", ng.gd[0], ng.gd[1]);
   c->graph_stale = true;
   if (c->grid_bricks > 0) {
     HIP_TRY(c, hipStreamSynchronize(s));

@@ -481,7 +481,10 @@ __device__ inline SwFrame rel_frame(const GridDev &g, const SwGrid &q, const int
 }
 
 __device__ inline uint32_t rel_brick(const SwGrid &q, const SwFrame &f, uint32_t tt) {
-  return f.Bp + ((tt >> 3) & 127u) + q.gx * ((tt >> 13) & 127u) + q.gxy * ((tt >> 23) & 127u);
+  // 24-bit multiplies: every grid axis spans at least 9 bricks and the grid
+  // holds fewer than 2^25 bricks, so gx and gxy stay below 2^22
+  return f.Bp + ((tt >> 3) & 127u) + __umul24(q.gx, (tt >> 13) & 127u) +
+         __umul24(q.gxy, (tt >> 23) & 127u);
 }
 
 __device__ inline uint32_t code_rel(const SwGrid &q, const SwFrame &f, uint32_t e) {
