@@ -513,7 +513,12 @@ template <> struct EntryOf<1> { using T = uint32_t; };
 
 template <int RE>
 __device__ inline typename EntryOf<RE>::T load_entry(const ToolDev &t, uint32_t idx) {
-  if constexpr (RE) return t.rent[idx]; else return t.xent[idx];
+  // a 32-bit byte offset from the table's base: one vector register per
+  // address instead of a 64-bit pointer per lane
+  if constexpr (RE)
+    return *(const uint32_t *)((const char *)t.rent + (uint32_t)(idx << 2));
+  else
+    return t.xent[idx];
 }
 __device__ inline uint32_t ent_cls(uint2 xe) { return xe.y >> 30; }
 __device__ inline uint32_t ent_cls(uint32_t e) { return e >> 30; }
