@@ -65,36 +65,113 @@ def kscore_bytes(lookups, arm_lookups, confident, K):
     return 8.0 * (lookups - arm_lookups) + confident * (8 + 3 * K / 8 + 4 + 3)
 
 
-def cpu_baseline(w, frames, n_frames, n_points, seed=17):
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _in_thread(fn, core):
+    """Run fn() in a thread pinned to one host core (Linux affinity is per
+    thread, so the process's other threads keep theirs); returns fn's value."""
+    import threading
+    box = {}
+
+    def body():
+        try:
+            os.sched_setaffinity(0, {core})
+        except (AttributeError, OSError):
+            pass
+        try:
+            box["v"] = fn()
+        except BaseException as e:   # re-raised in the caller
+            box["e"] = e
+    th = threading.Thread(target=body)
+    th.start()
+    th.join()
+    if "e" in box:
+        raise box["e"]
+    return box["v"]
+
+
+def cpu_baseline(w, frames, n_frames, n_points, seed=17, max_threads=16):
+    """The oracle, unchanged: single-threaded on one pinned host core, then
+    the same scoring loop on several cores over disjoint slices of the same
+    seeded point sample (each thread with its own oracle holding the same
+    map, since a scoring call owns its oracle's result arrays)."""
+    import concurrent.futures as cf
+
     import oracle
     oracle.build(force=False)
-    orc = oracle.Oracle(voxel=w.voxel, trunc=w.trunc, r_c=w.r_c)
-    t = time.perf_counter()
-    nret = 0
-    for f in frames[:n_frames]:
-        orc.integrate_frame(f.xyz, f.origin, f.frame_id)
-        nret += len(f.xyz)
-    t_int = time.perf_counter() - t
-    orc.set_tool(0, w.tool, w.rot)
+    cores = sorted(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else [0]
+
+    def make_map():
+        orc = oracle.Oracle(voxel=w.voxel, trunc=w.trunc, r_c=w.r_c)
+        t = time.perf_counter()
+        nret = 0
+        for f in frames[:n_frames]:
+            orc.integrate_frame(f.xyz, f.origin, f.frame_id)
+            nret += len(f.xyz)
+        orc.set_tool(0, w.tool, w.rot)
+        return orc, nret, time.perf_counter() - t
+
+    def score(orc, keys):
+        t = time.perf_counter()
+        orc.score(0, keys=keys)
+        return orc.score_stats()["canonical_tests"], time.perf_counter() - t
+
+    orc, nret, t_int = _in_thread(make_map, cores[0])
     keys = orc.read_points()["key"]
     rng = np.random.default_rng(seed)
     sample = rng.choice(keys, size=min(n_points, len(keys)), replace=False)
-    t = time.perf_counter()
-    orc.score(0, keys=sample)
-    t_score = time.perf_counter() - t
-    st = orc.score_stats()
-    return {
-        "value": st["canonical_tests"] / t_score,
+    tests, t_score = _in_thread(lambda: score(orc, sample), cores[0])
+    out = {
+        "value": tests / t_score,
         "unit": "point-orientation tests/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": ("single-threaded C oracle: frames 0-%d of the tree workload integrated "
-                   "(%d returns, %.1f s -> %.0f returns/s), then %d seeded-random points of "
-                   "that map scored against all %d orientations (%d canonical tests in %.1f s)"
-                   % (n_frames - 1, nret, t_int, nret / t_int, len(sample), len(w.rot),
-                      st["canonical_tests"], t_score)),
+        "sample": ("single-threaded C oracle pinned to host core %d: frames 0-%d of the tree "
+                   "workload integrated (%d returns, %.1f s -> %.0f returns/s), then %d "
+                   "seeded-random points of that map scored against all %d orientations "
+                   "(%d canonical tests in %.1f s)"
+                   % (cores[0], n_frames - 1, nret, t_int, nret / t_int, len(sample),
+                      len(w.rot), tests, t_score)),
         "returns_per_s": nret / t_int,
+        "cpu_model": _cpu_model(),
+        "host_cpus_visible": len(cores),
     }
+    # all cores of this process's share (at most max_threads): maps built in
+    # parallel, then the timed scoring of disjoint slices
+    P = max(1, min(max_threads, len(cores)))
+    slices = np.array_split(sample, P)
+    with cf.ThreadPoolExecutor(P) as ex:
+        maps = list(ex.map(lambda c: _pinned_call(make_map, c), cores[:P]))
+        t = time.perf_counter()
+        res = list(ex.map(lambda a: _pinned_call(lambda: score(a[0][0], a[1]), a[2]),
+                          zip(maps, slices, cores[:P])))
+        wall = time.perf_counter() - t
+    tests_all = sum(r[0] for r in res)
+    out["all_cores"] = {
+        "value": tests_all / wall, "unit": "point-orientation tests/s", "cores": P,
+        "kind": "oracle", "same_tests": bool(tests_all == tests),
+        "sample": ("the same %d points in %d disjoint slices, one oracle per thread, each "
+                   "thread pinned to its own host core (%d canonical tests in %.1f s wall)"
+                   % (len(sample), P, tests_all, wall)),
+    }
+    return out
+
+
+def _pinned_call(fn, core):
+    try:
+        os.sched_setaffinity(0, {core})
+    except (AttributeError, OSError):
+        pass
+    return fn()
 
 
 def trace_summary(csv_path, warmup, steps):
