@@ -282,6 +282,20 @@ static int cmp_i64(const void *a, const void *b) {
   return x < y ? -1 : (x > y ? 1 : 0);
 }
 
+/* Whether voxels within reach of return P (fixed point) can lie in the
+ * region of interest: Chebyshev distance from P's voxel to the region at
+ * most max(R, ceil(2.25 tau / v)) + 2 voxels. */
+static int roi_reachable(const orc_t *o, const int64_t P[3]) {
+  if (!o->roi) return 1;
+  int64_t band = (9 * o->tau_u + 4 * 256 - 1) / (4 * 256);
+  int64_t m = (o->R > band ? o->R : band) + 2;
+  for (int i = 0; i < 3; ++i) {
+    int64_t x = orc_floor_div(P[i], 256);
+    if (x < o->roi_lo[i] - m || x > o->roi_hi[i] + m) return 0;
+  }
+  return 1;
+}
+
 /* Fixed-point quantisation: rint of the fp64 product (round half to even). */
 static int quantize(double x, double scale, int64_t *out) {
   if (!isfinite(x)) return 0;
@@ -390,6 +404,11 @@ int orc_integrate_frame(orc_t *o, const float *xyz, int64_t n,
       continue;
     }
     o->fst.n_valid += 1;
+    /* With a region of interest, a return whose voxel lies farther from the
+     * region than anything it touches (its cube reaches R voxels; its band
+     * samples lie within 2.25 tau of it along the ray, plus rounding) cannot
+     * change a voxel inside it, and is not expanded. */
+    if (!roi_reachable(o, &P[3 * r])) continue;
     accumulate_cube(o, &P[3 * r], Q);
     mark_band(o, &P[3 * r], Q);
     /* Section 3.1: the voxel holding a return becomes a surface point. */

@@ -280,3 +280,36 @@ def test_points_and_viewpoints(oracle_mod):
     stored = [[0, 0, 0], [1700, 0, 0], [1700, 1639, 0]] + origins[4:]
     assert pts["vp"][i30].tolist() == stored[-8:]
     assert list(pts["sumq"][i30]) == list(np.sum(origins, axis=0))
+
+
+def test_region_of_interest_is_exact(oracle_mod, synth_mod):
+    """With a region of interest (which also skips returns out of its reach),
+    every voxel and point inside the region equals the unrestricted oracle's,
+    on the tiny scene, for small regions placed around surface points."""
+    w = synth_mod.tiny()
+    frames = w.frames(8)
+    full = oracle_mod.Oracle(voxel=w.voxel, trunc=w.trunc, r_c=w.r_c)
+    for f in frames:
+        full.integrate_frame(f.xyz, f.origin, f.frame_id)
+    fk, fS, fW, fc = full.read_tsdf()
+    fijk = oracle_mod.unpack_keys(fk)
+    pts = full.read_points()
+    rng = np.random.default_rng(5)
+    for c in oracle_mod.unpack_keys(rng.choice(pts["key"], 4, replace=False)):
+        lo, hi = c - 3, c + 3
+        roi = oracle_mod.Oracle(voxel=w.voxel, trunc=w.trunc, r_c=w.r_c)
+        roi.set_roi(lo, hi)
+        for f in frames:
+            roi.integrate_frame(f.xyz, f.origin, f.frame_id)
+        inside = np.all((fijk >= lo) & (fijk <= hi), axis=1)
+        rk, rS, rW, rc = roi.read_tsdf()
+        want = {int(k): (int(s), int(ww), int(cc)) for k, s, ww, cc in
+                zip(fk[inside], fS[inside], fW[inside], fc[inside])}
+        got = {int(k): (int(s), int(ww), int(cc)) for k, s, ww, cc in zip(rk, rS, rW, rc)}
+        assert got == want and len(want) > 20
+        rp = roi.read_points()
+        pin = np.all((oracle_mod.unpack_keys(pts["key"]) >= lo) &
+                     (oracle_mod.unpack_keys(pts["key"]) <= hi), axis=1)
+        assert np.array_equal(rp["key"], pts["key"][pin])
+        for name in ("n_vp", "vp", "sumq", "nq", "first_frame"):
+            assert np.array_equal(rp[name], pts[name][pin]), name
