@@ -522,6 +522,7 @@ k_integrate_fold(const FrameArgs *fa, Params p, MapDev m, FrameScratch fs, Frame
                  GridDev g) {
   const int3 Q = fa->Q;
   __shared__ int4 tile[kBlockVox];
+  __shared__ int64_t tile_bb[kBlockVox];   // |P - Q|^2 of each return of the tile
   __shared__ uint8_t code[kBlockVox];
   __shared__ unsigned long long s_stat[3];
   if (threadIdx.x < 3) s_stat[threadIdx.x] = 0ull;
@@ -556,7 +557,12 @@ k_integrate_fold(const FrameArgs *fa, Params p, MapDev m, FrameScratch fs, Frame
     int dW = 0;
     for (int tb = beg; tb < end; tb += kBlockVox) {
       __syncthreads();
-      if (tb + t < end) tile[t] = fs.P[fs.bin_list[tb + t]];
+      if (tb + t < end) {
+        const int4 P = fs.P[fs.bin_list[tb + t]];
+        tile[t] = P;
+        const int64_t b0 = (int64_t)P.x - Q.x, b1 = (int64_t)P.y - Q.y, b2 = (int64_t)P.z - Q.z;
+        tile_bb[t] = b0 * b0 + b1 * b1 + b2 * b2;
+      }
       __syncthreads();
       const int cnt = end - tb < kBlockVox ? end - tb : kBlockVox;
       for (int j = 0; j < cnt; ++j) {
@@ -566,17 +572,33 @@ k_integrate_fold(const FrameArgs *fa, Params p, MapDev m, FrameScratch fs, Frame
         ey = ey < 0 ? -ey : ey;
         ez = ez < 0 ? -ez : ez;
         if (ex > p.R || ey > p.R || ez > p.R) continue;
-        const int64_t a0 = 256 * (int64_t)vx + 128 - P.x;
-        const int64_t a1 = 256 * (int64_t)vy + 128 - P.y;
-        const int64_t a2 = 256 * (int64_t)vz + 128 - P.z;
-        const int64_t b0 = (int64_t)P.x - Q.x, b1 = (int64_t)P.y - Q.y, b2 = (int64_t)P.z - Q.z;
-        const int64_t ab = a0 * b0 + a1 * b1 + a2 * b2;
-        const int64_t aa = a0 * a0 + a1 * a1 + a2 * a2;
-        const int64_t bb = b0 * b0 + b1 * b1 + b2 * b2;
-        // behind the return within the cos > 0.95 cone: 400 (a.b)^2 > 361 |a|^2 |b|^2
-        if (ab > 0 && (__int128)400 * ab * ab > (__int128)361 * aa * bb) {
-          ++excluded;
-          continue;
+        // 32-bit components: |a| <= 256 (R + 1) inside the cube, |b| < 2^29
+        // (fixed-point coordinates are bounded by 2^28)
+        const int32_t a0 = 256 * vx + 128 - P.x, a1 = 256 * vy + 128 - P.y,
+                      a2 = 256 * vz + 128 - P.z;
+        const int32_t b0 = P.x - Q.x, b1 = P.y - Q.y, b2 = P.z - Q.z;
+        const int64_t ab = (int64_t)a0 * b0 + (int64_t)a1 * b1 + (int64_t)a2 * b2;
+        // behind the return within the cos > 0.95 cone: 400 (a.b)^2 > 361 |a|^2 |b|^2.
+        // Decided in double when the sides differ by more than 2^-40 relative
+        // (each side is within 2^-50 of its exact value: |a.b| < 2^53 converts
+        // exactly, |b|^2 rounds once, three roundings per product), otherwise
+        // in 128-bit integers.
+        if (ab > 0) {
+          const int64_t aa = (int64_t)a0 * a0 + (int64_t)a1 * a1 + (int64_t)a2 * a2;
+          const int64_t bb = tile_bb[j];
+          const double x = 400.0 * (double)ab * (double)ab;
+          const double y = 361.0 * (double)aa * (double)bb;
+          bool behind;
+          if (x > y * (1.0 + 0x1p-40))
+            behind = true;
+          else if (x < y * (1.0 - 0x1p-40))
+            behind = false;
+          else
+            behind = (__int128)400 * ab * ab > (__int128)361 * aa * bb;
+          if (behind) {
+            ++excluded;
+            continue;
+          }
         }
         ++applied;
         int64_t d = (int64_t)P.w - dist_c;
