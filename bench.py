@@ -871,9 +871,9 @@ def main():
         print(json.dumps({"copy_probe_bytes": n * 4}))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU; this build has no multi-GPU path "
-              "(see DESIGN.md for how the map would shard). Run with --gpus 1.",
-              file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (a scene would "
+              "shard by block-key owner, each GPU integrating and scoring its own blocks). "
+              "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch
