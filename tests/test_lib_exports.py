@@ -69,3 +69,14 @@ def test_config_default_and_argument_errors(libaf):
     bad2.n_vp = 9
     assert libaf.af_create(ctypes.byref(bad2), ctypes.byref(h)) == af.AF_EINVAL
     assert not h.value
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU and says so (before touching any device)."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr and not r.stdout
