@@ -433,6 +433,17 @@ __device__ inline SwFrame sw_frame(const GridDev &g, const SwGrid &q, const int3
   return f;
 }
 
+// The byte offset of an entry's 2-bit code word, and the code's bit position.
+__device__ inline uint32_t code_sw_at(const SwGrid &q, const SwFrame &f, uint2 xe, uint32_t &bit) {
+  const uint32_t tt = f.rp + xe.y;
+  uint32_t brick = f.Bp + xe.x + ((tt >> 3) & 1u);
+  brick += ((tt >> 7) & 1u) * q.gx;
+  brick += ((tt >> 11) & 1u) * q.gxy;
+  const uint32_t wib = ((tt >> 5) & 3u) | ((tt >> 6) & 0x1cu);   // (ly >> 1) | lz << 2
+  bit = ((tt & 7u) << 1) | (tt & 0x10u);                          // 2 (lx + 8 (ly & 1))
+  return ((brick << 5) | wib) << 2;
+}
+
 __device__ inline uint32_t code_sw(const SwGrid &q, const SwFrame &f, uint2 xe) {
   const uint32_t tt = f.rp + xe.y;
   uint32_t brick = f.Bp + xe.x + ((tt >> 3) & 1u);
@@ -617,6 +628,19 @@ k_mask(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t mw, int
     const uint64_t carry = heads ? ((heads & (~heads + 1ull)) - 1ull) : valid;
     uint64_t word = ok ? carry : 0ull;
     uint64_t pl0 = (nb & 1u) ? carry : 0ull, pl1 = (nb >> 1) ? carry : 0ull;
+    // A head's arm-sample words are requested in its iteration and decoded in
+    // the next one, so their latency overlaps the next head's tests.
+    uint32_t pw[3] = {0u, 0u, 0u}, pb[3] = {0u, 0u, 0u};
+    uint64_t prun = 0ull;   // run of the head whose words are in flight (0: none)
+    auto settle = [&]() {
+      if (!prun) return;
+      nb = ((pw[0] >> pb[0]) & 3u) ? 1u
+           : ((pw[1] >> pb[1]) & 3u) ? 2u
+           : ((pw[2] >> pb[2]) & 3u) ? 3u
+                                     : 0u;
+      pl0 |= (nb & 1u) ? prun : 0ull;
+      pl1 |= (nb >> 1) ? prun : 0ull;
+    };
     for (uint64_t rem = heads; rem; rem &= rem - 1ull) {
       const int j = __ffsll((unsigned long long)rem) - 1;
       const uint64_t above = j == 63 ? 0ull : heads & ~((2ull << j) - 1ull);
@@ -639,21 +663,25 @@ k_mask(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t mw, int
         }
         ok = seen;
       }
-      nb = 0u;
+      settle();   // the previous head's words, requested an iteration ago
+      uint32_t cw[3] = {0u, 0u, 0u}, cb[3] = {0u, 0u, 0u};
       if (ok) {
-        uint32_t h[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
           const uint2 e = {(uint32_t)__builtin_amdgcn_readlane((int)ae[a].x, j),
                            (uint32_t)__builtin_amdgcn_readlane((int)ae[a].y, j)};
-          h[a] = code_sw(q, f, e) != 0u;
+          cw[a] = __builtin_amdgcn_raw_buffer_load_b32(q.pred, code_sw_at(q, f, e, cb[a]), 0, 0);
         }
-        nb = h[0] ? 1u : (h[1] ? 2u : (h[2] ? 3u : 0u));
       }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        pw[a] = cw[a];
+        pb[a] = cb[a];
+      }
+      prun = run;
       word |= ok ? run : 0ull;
-      pl0 |= (nb & 1u) ? run : 0ull;
-      pl1 |= (nb >> 1) ? run : 0ull;
     }
+    settle();
     if (stage) {
       s_out[threadIdx.x * mw + w] = word;
       s_out[kThreads * mw + threadIdx.x * 2 * mw + w] = pl0;
