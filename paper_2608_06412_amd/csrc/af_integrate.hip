@@ -523,6 +523,7 @@ k_integrate_fold(const FrameArgs *fa, Params p, MapDev m, FrameScratch fs, Frame
   const int3 Q = fa->Q;
   __shared__ int4 tile[kBlockVox];
   __shared__ int64_t tile_bb[kBlockVox];   // |P - Q|^2 of each return of the tile
+  __shared__ int s_list[kBlockVox / 64 + 1]; // LIST: per-wave offsets, then the block's base
   __shared__ uint8_t code[kBlockVox];
   __shared__ unsigned long long s_stat[3];
   if (threadIdx.x < 3) s_stat[threadIdx.x] = 0ull;
@@ -621,16 +622,24 @@ k_integrate_fold(const FrameArgs *fa, Params p, MapDev m, FrameScratch fs, Frame
       m.W[v] = (uint16_t)W;
       ++folded;
     }
-    if (LIST) {   // list this voxel if it received a contribution (one atomic per wave)
+    if (LIST) {   // list this voxel if it received a contribution (one atomic per block)
       const unsigned long long bal = __ballot(dW > 0);
-      if (bal) {
-        const int lane = (int)(threadIdx.x & 63u);
-        int base = 0;
-        if (lane == 0) base = atomicAdd(&c->n_changed, __popcll(bal));
-        base = __shfl(base, 0);
-        if (dW > 0)
-          fs.changed[base + __popcll(bal & ((1ull << lane) - 1ull))] = (int32_t)v;
+      const int lane = (int)(threadIdx.x & 63u), wave = (int)(threadIdx.x >> 6);
+      if (lane == 0) s_list[wave] = __popcll(bal);
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        int tot = 0;
+        for (int k = 0; k < kBlockVox / 64; ++k) {
+          const int n = s_list[k];
+          s_list[k] = tot;
+          tot += n;
+        }
+        s_list[kBlockVox / 64] = tot ? atomicAdd(&c->n_changed, tot) : 0;
       }
+      __syncthreads();
+      if (dW > 0)
+        fs.changed[s_list[kBlockVox / 64] + s_list[wave] +
+                   __popcll(bal & ((1ull << lane) - 1ull))] = (int32_t)v;
     }
     write_brick(p, m, g, id, S, W, code, clrw, surfw, bkey);
   }
