@@ -354,10 +354,13 @@ k_incr_count(PointsDev pts, ToolDev t, GridDev g, IncrDev I, int32_t n_c) {
       int32_t s[3];
       unpack_key(pts.key[pi], s[0], s[1], s[2]);
       cnt = 0;
-      for (uint32_t e0 = t.begin[k]; e0 < t.begin[k + 1]; e0 += 64) {
+      // a table lists 3 arm samples, then the body entries, then the corridor
+      // entries (from far_begin): only the body range is visited
+      const uint32_t eb = t.far_begin[k];
+      for (uint32_t e0 = t.begin[k] + 3; e0 < eb; e0 += 64) {
         const uint32_t e = e0 + lane;
         bool hit = false;
-        if (e < t.begin[k + 1]) {
+        if (e < eb) {
           const uint32_t ent = t.entries[e];
           if (entry_cls(ent) == AF_CLS_BODY) {
             const int x = s[0] + entry_x(ent), y = s[1] + entry_y(ent), z = s[2] + entry_z(ent);
