@@ -1428,14 +1428,27 @@ k_score_near(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t m
   ScoreCounterBlock &sc = t.counters->s[(blockIdx.x * NW + (threadIdx.x >> 6)) % kStatSlots];
   NearAcc a = near_acc_zero();
   int64_t i = wave0, batch_end = wave0 + 1;
+  // with a point list, lane k holds the batch's k-th listed point (one read
+  // per batch instead of one dependent read per point)
+  int32_t selv = 0;
+  auto fetch_list = [&]() {
+    if (FB > 0 && pts.sel) {
+      const int64_t idx = i + lane;
+      selv = (lane < FB && idx < n) ? pts.sel[idx] : 0;
+    }
+  };
   if (FB > 0) {
     unsigned got = 0;
     if (lane == 0) got = atomicAdd(work, (unsigned)FB);
     i = (int64_t)__builtin_amdgcn_readfirstlane(__shfl(got, 0));
     batch_end = i + FB;
+    fetch_list();
   }
   for (; i < n;) {
-    const int64_t pi = pts.sel ? (int64_t)__builtin_amdgcn_readfirstlane(pts.sel[i]) : i;
+    const int64_t pi =
+        !pts.sel ? i
+        : FB > 0 ? (int64_t)__builtin_amdgcn_readlane(selv, (int)(FB - (batch_end - i)))
+                 : (int64_t)__builtin_amdgcn_readfirstlane(pts.sel[i]);
     near_point<UN, CO, B1, PF, RE>(p, pts, t, g, q, s_begin, mw, pi, lane, a);
     if (a.lookups > (1u << 30)) near_flush<DIAG>(sc, a, lane);
     if (FB > 0) {
@@ -1444,6 +1457,7 @@ k_score_near(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t m
         if (lane == 0) got = atomicAdd(work, (unsigned)FB);
         i = (int64_t)__builtin_amdgcn_readfirstlane(__shfl(got, 0));
         batch_end = i + FB;
+        fetch_list();
       }
     } else {
       i += nwaves;
