@@ -180,13 +180,18 @@ int af_integrate_frame(af_ctx *ctx, const float *xyz, int64_t n,
  * and not ray-cleared), fewer than n_c body voxels with TSDF < r_c and no
  * corridor voxel with TSDF < r_c is the point's first free orientation
  * (AF_ACCESSIBLE); none -> AF_BLOCKED; no candidate -> AF_NO_CANDIDATE.
+ * Normal axes are kept between calls (this call and af_score_tools) and
+ * recomputed only for points within 3 voxels of points added since; the
+ * first call allocates that cache (32 bytes per point of capacity, 64 per
+ * brick of the grid), AF_ENOMEM if the device budget cannot hold it.
  * Asynchronous on `stream`.  AF_ENOTOOL if the tool was never set. */
 int af_score_points(af_ctx *ctx, int32_t tool_id, void *stream);
 
 /* Copy labels of points [first, first + count) in canonical order (by first
  * frame, then key) into HOST arrays (any may be NULL): voxel key, label,
  * first free orientation (-1 if none) and the point voxel's weight W.
- * Synchronises the context's last stream.  *n_written = number copied. */
+ * Host arrays in pinned memory make the copies fast.  Synchronises the
+ * context's last stream.  *n_written = number copied. */
 int af_read_labels(af_ctx *ctx, int32_t tool_id, int64_t first, int64_t count,
                    int64_t *key, uint8_t *label, int16_t *first_free,
                    uint16_t *w, int64_t *n_written);
