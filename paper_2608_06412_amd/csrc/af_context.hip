@@ -791,12 +791,12 @@ static int sync_last(af_ctx *c);
 // since the last call can have changed.
 static int cached_normals(af_ctx *c, hipStream_t s) {
   NormalCache &nc = c->ncache;
-  if (!nc.axis) {
-    ALLOC(c, nc.axis, 3 * c->cfg.max_points);
-    ALLOC(c, nc.state, c->cfg.max_points);
-    ALLOC(c, nc.list, c->cfg.max_points);
-    ALLOC(c, nc.count, 1);
+  if (!nc.axis || !nc.state || !nc.list || !nc.count) {   // (a failed call may have left a part)
     c->nc_seen = 0;
+    if (!nc.axis) ALLOC(c, nc.axis, 3 * c->cfg.max_points);
+    if (!nc.state) ALLOC(c, nc.state, c->cfg.max_points);
+    if (!nc.list) ALLOC(c, nc.list, c->cfg.max_points);
+    if (!nc.count) ALLOC(c, nc.count, 1);
   }
   if (nc.stale_words < 16 * c->grid_bricks) {
     if (nc.stale) {

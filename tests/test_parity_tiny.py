@@ -261,3 +261,40 @@ def test_scoring_every_frame(synth_mod, oracle_mod):
                     continue
                 assert dbg["has_normal"][i] == r["has_normal"], (f.frame_id, k)
                 assert np.array_equal(dbg["normal"][i].astype(np.int64), r["normal"]), k
+
+
+def test_normal_cache_budget_refusal(synth_mod, oracle_mod):
+    """A device budget that holds the map but not the normal-axis cache makes
+    scoring fail with AF_ENOMEM, again on a second call (nothing half-made is
+    used), and the context stays usable; with the budget to spare, the same
+    frames score to the oracle's labels."""
+    torch = _torch()
+    from paper_2608_06412_amd import AFError, af
+    w = synth_mod.tiny()
+    frames = w.frames(3)
+
+    def run(budget):
+        ctx = _ctx(w, hbm_budget=budget)
+        ctx.set_tool_kernels(0, w.tool, w.rot)
+        for f in frames[:2]:
+            ctx.integrate_frame(torch.from_numpy(f.xyz).cuda(), f.origin, f.frame_id)
+        return ctx
+
+    probe = run(0)
+    held = probe.device_bytes()
+    ctx = run(held + 4096)
+    for _ in range(2):
+        with pytest.raises(AFError) as e:
+            ctx.score_points(0)
+        assert e.value.code == af.AF_ENOMEM
+    assert ctx.num_points() == probe.num_points() > 0
+    probe.integrate_frame(torch.from_numpy(frames[2].xyz).cuda(), frames[2].origin, 2)
+    probe.score_points(0)
+    orc = _oracle(w)
+    orc.set_tool(0, w.tool, w.rot)
+    for f in frames:
+        orc.integrate_frame(f.xyz, f.origin, f.frame_id)
+    orc.score(0)
+    lab = probe.read_labels(0)
+    keys, lbl, ff = orc.labels(len(w.rot), lab["key"])
+    assert np.array_equal(lab["label"], lbl)
