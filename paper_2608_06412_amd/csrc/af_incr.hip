@@ -54,6 +54,31 @@ __device__ inline unsigned long long sample_hash(int64_t key, int32_t frame) {
   return mix64((unsigned long long)key ^ ((unsigned long long)(int64_t)frame * kGolden));
 }
 
+// Workgroup counts of three per-thread flags (ballots, one exchange), added
+// to d0, d1, d2 by thread 0.
+template <int NT>
+__device__ inline void wg_count3(bool f0, bool f1, bool f2, int *d0, int *d1, int *d2) {
+  __shared__ int part[3][NT / 64];
+  const uint64_t b0 = __ballot(f0), b1 = __ballot(f1), b2 = __ballot(f2);
+  if ((threadIdx.x & 63) == 0) {
+    part[0][threadIdx.x >> 6] = __popcll(b0);
+    part[1][threadIdx.x >> 6] = __popcll(b1);
+    part[2][threadIdx.x >> 6] = __popcll(b2);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t0 = 0, t1 = 0, t2 = 0;
+    for (int w = 0; w < NT / 64; ++w) {
+      t0 += part[0][w];
+      t1 += part[1][w];
+      t2 += part[2][w];
+    }
+    if (t0) atomicAdd(d0, t0);
+    if (t1) atomicAdd(d1, t1);
+    if (t2) atomicAdd(d2, t2);
+  }
+}
+
 // Workgroup sum of one value per thread, added to *dst by thread 0.
 template <int NT>
 __device__ inline void wg_add(int v, int *dst) {
@@ -116,9 +141,8 @@ k_incr_triggers(PointsDev pts, MapDev m, IncrDev I, int64_t n, int64_t seen, int
     I.S_prev[i] = (int32_t)S;
     I.W_prev[i] = (uint16_t)W;
   }
-  wg_add<kT>(c_new, &I.ctr->new_points);
-  wg_add<kT>(c_i, &I.ctr->trig_i);
-  wg_add<kT>(c_iii, &I.ctr->trig_iii);
+  wg_count3<kT>(c_new != 0, c_i != 0, c_iii != 0, &I.ctr->new_points, &I.ctr->trig_i,
+                 &I.ctr->trig_iii);
 }
 
 // Histogram of the top 16 hash bits over the frame's changed voxels (level 0),
