@@ -923,7 +923,7 @@ __device__ inline uint32_t plane_sum(const uint64_t pl[4], uint64_t m) {
 // caller (entry min(b + lane, any index of the orientation): lanes past e are
 // masked out below).  CL: 0 entries of any class, 1 body entries only (a
 // table lists body entries before corridor entries), 2 corridor entries only.
-template <int UN, int B1, int RE, int CL = 0>
+template <int UN, int B1, int RE, int CL = 0, int LZ = 0>
 __device__ inline bool scan_fine_sw(const Params &p, const ToolDev &t, const SwGrid &q,
                                     const SwFrame &f, uint32_t b, uint32_t e, int &body,
                                     uint32_t &lookups, uint32_t &steps,
@@ -940,8 +940,10 @@ __device__ inline bool scan_fine_sw(const Params &p, const ToolDev &t, const SwG
     else
       ent[u] = load_entry<RE>(t, idx < e ? idx : e - 1);
   }
+  // LZ: lookups and steps are added once, when the scan ends (a completed
+  // range counts e - b lookups; a stop counts those before it plus stop + 1)
   for (uint32_t base = b; base < e; base += 64 * UN) {
-    ++steps;
+    if (!LZ) ++steps;
     uint32_t code[UN];
     Ent nxt[UN];
 #pragma unroll
@@ -971,14 +973,23 @@ __device__ inline bool scan_fine_sw(const Params &p, const ToolDev &t, const SwG
                        : CL == 2 ? (nf ? __ffsll((long long)nf) - 1 : 64)
                                  : chunk_stop(nf, bm, p.n_c - body);
       if (stop < 64) {
-        lookups += (uint32_t)stop + 1u;
+        if (LZ) {
+          lookups += (cb - b) + (uint32_t)stop + 1u;
+          steps += (base - b) / (64u * UN) + 1u;
+        } else {
+          lookups += (uint32_t)stop + 1u;
+        }
         return false;
       }
       body += __popcll(bm);
-      lookups += (e - cb) < 64u ? (e - cb) : 64u;
+      if (!LZ) lookups += (e - cb) < 64u ? (e - cb) : 64u;
     }
 #pragma unroll
     for (int u = 0; u < UN; ++u) ent[u] = nxt[u];
+  }
+  if (LZ) {
+    lookups += e - b;
+    steps += (e - b + 64u * UN - 1u) / (64u * UN);
   }
   return true;
 }
@@ -1010,17 +1021,17 @@ __device__ inline bool corridor_clear4_sw(const ToolDev &t, const SwGrid &q, con
 // Entries [b, e) of orientation k after its first E: body entries finely,
 // then the corridor -- skipped when its 4^3 cells are clear (CO), finely
 // otherwise.  Canonical lookups stay the table-order count.
-template <int UN, int CO, int B1, int RE = 0>
+template <int UN, int CO, int B1, int RE = 0, int LZ = 0>
 __device__ inline bool scan_rest_sw(const Params &p, const ToolDev &t, const SwGrid &q,
                                     const SwFrame &f, int k, uint32_t b, uint32_t e, int body,
                                     uint32_t &lookups, uint32_t &cchecks, uint32_t &cclear,
                                     uint32_t &sbody, uint32_t &sfar, const uint32_t c4[3],
                                     const uint8_t *occ4,
                                     const typename EntryOf<RE>::T *first = nullptr) {
-  if (!CO) return scan_fine_sw<UN, B1, RE>(p, t, q, f, b, e, body, lookups, sbody, first);
+  if (!CO) return scan_fine_sw<UN, B1, RE, 0, LZ>(p, t, q, f, b, e, body, lookups, sbody, first);
   const uint32_t fb = t.far_begin[k];
   const uint32_t mid = fb > b ? fb : b;
-  if (!scan_fine_sw<UN, B1, RE, B1 ? 1 : 0>(p, t, q, f, b, mid, body, lookups, sbody, first))
+  if (!scan_fine_sw<UN, B1, RE, B1 ? 1 : 0, LZ>(p, t, q, f, b, mid, body, lookups, sbody, first))
     return false;
   if (mid >= e) return true;
   if (t.c4flag[k] != 0) {
@@ -1031,7 +1042,7 @@ __device__ inline bool scan_rest_sw(const Params &p, const ToolDev &t, const SwG
       return true;
     }
   }
-  return scan_fine_sw<UN, B1, RE, B1 ? 2 : 0>(p, t, q, f, mid, e, body, lookups, sfar);
+  return scan_fine_sw<UN, B1, RE, B1 ? 2 : 0, LZ>(p, t, q, f, mid, e, body, lookups, sfar);
 }
 
 // Candidate-parallel scoring with grid-relative lookups (the configurations
@@ -1268,7 +1279,7 @@ __device__ inline void near_flush(ScoreCounterBlock &sc, NearAcc &a, int lane) {
 
 // One point of the "near" scoring (see k_score_near): label and first free
 // orientation of point i for tool t, whose begin offsets are s_begin.
-template <int UN, int CO, int B1, int PF, int RE>
+template <int UN, int CO, int B1, int PF, int RE, int LZ = 0>
 __device__ inline void near_point(const Params &p, const PointsDev &pts, const ToolDev &t,
                                   const GridDev &g, const SwGrid &q, const uint32_t *s_begin,
                                   int32_t mw, int64_t i, int lane, NearAcc &acc) {
@@ -1374,7 +1385,7 @@ __device__ inline void near_point(const Params &p, const PointsDev &pts, const T
             body = __popcll(bm1);
             start = b + nin;
           }
-          if (scan_rest_sw<UN, CO, B1, RE>(p, t, q, f, kj, start, e, body, acc.lookups, acc.cchecks,
+          if (scan_rest_sw<UN, CO, B1, RE, LZ>(p, t, q, f, kj, start, e, body, acc.lookups, acc.cchecks,
                                            acc.cclear, acc.sbody, acc.sfar, c4, g.occ4,
                                            PF == 1 && UN == 1 ? &cur : nullptr)) {
             ff = (int16_t)kj;
@@ -1449,7 +1460,7 @@ k_score_near(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t m
         !pts.sel ? i
         : FB > 0 ? (int64_t)__builtin_amdgcn_readlane(selv, (int)(FB - (batch_end - i)))
                  : (int64_t)__builtin_amdgcn_readfirstlane(pts.sel[i]);
-    near_point<UN, CO, B1, PF, RE>(p, pts, t, g, q, s_begin, mw, pi, lane, a);
+    near_point<UN, CO, B1, PF, RE, 1>(p, pts, t, g, q, s_begin, mw, pi, lane, a);
     if (a.lookups > (1u << 30)) near_flush<DIAG>(sc, a, lane);
     if (FB > 0) {
       if (++i >= batch_end) {
