@@ -508,14 +508,15 @@ __device__ inline uint32_t code_rel(const SwGrid &q, const SwFrame &f, uint32_t 
   return (w >> bit) & 3u;
 }
 
+// The plane's words hold bit lx + 8 (ly & 3) of word (ly >> 2) + 2 lz, so
+// (little-endian) voxel (lx, ly, lz) is bit lx of byte ly + 8 lz of the
+// brick's 64 bytes: one byte read, fewer address operations.
 __device__ inline uint32_t occ_rel(const SwGrid &q, const SwFrame &f, uint32_t e) {
   const uint32_t tt = f.rp + e;
   const uint32_t brick = rel_brick(q, f, tt);
-  const uint32_t wib = ((tt >> 12) & 1u) | ((tt >> 19) & 0xeu);    // (ly >> 2) | lz << 1
-  const uint32_t bit = (tt & 7u) | ((tt >> 7) & 0x18u);            // lx | (ly & 3) << 3
-  const uint32_t w =
-      __builtin_amdgcn_raw_buffer_load_b32(q.occ1, ((brick << 4) | wib) << 2, 0, 0);
-  return (w >> bit) & 1u;
+  const uint32_t byte = ((tt >> 10) & 7u) | ((tt >> 17) & 0x38u);  // ly + 8 lz
+  const uint32_t w = __builtin_amdgcn_raw_buffer_load_b8(q.occ1, (brick << 6) | byte, 0, 0);
+  return (w >> (tt & 7u)) & 1u;
 }
 
 // Uniform access to the two entry forms (RE: the 4-byte form).
