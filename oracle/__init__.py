@@ -104,6 +104,10 @@ def _load():
     L.orc_score_stats_get.argtypes = [vp, ctypes.POINTER(ScoreStats)]
     L.orc_point_result.restype = ctypes.c_int
     L.orc_point_result.argtypes = [vp, i64, vp, vp, vp, vp, vp, i32]
+    L.orc_pca_axis.restype = ctypes.c_int
+    L.orc_pca_axis.argtypes = [i64, vp, vp, vp]
+    L.orc_pca_axes.restype = None
+    L.orc_pca_axes.argtypes = [vp, i64, vp, vp]
     L.orc_isqrt.restype = i64
     L.orc_isqrt.argtypes = [i64]
     L.orc_floor_div.restype = i64
@@ -134,6 +138,26 @@ def _p(a: np.ndarray):
 
 def isqrt(n: int) -> int:
     return _load().orc_isqrt(int(n))
+
+
+def pca_axis(cnt: int, sx, sxx):
+    """(has, axis) of the oracle's PCA step for neighbourhood moments: cnt,
+    sum d (3) and sum dd^T (00 01 02 11 12 22); axis in fixed point 2^30."""
+    a = np.ascontiguousarray(sx, dtype=np.int64).reshape(3)
+    b = np.ascontiguousarray(sxx, dtype=np.int64).reshape(6)
+    out = np.zeros(3, np.int64)
+    has = _load().orc_pca_axis(int(cnt), _p(a), _p(b), _p(out))
+    return has, out
+
+
+def pca_axes(moments):
+    """pca_axis over rows [n][10] of (cnt, sum d [3], sum dd^T [6]):
+    (axes [n][3], has [n])."""
+    m = np.ascontiguousarray(moments, dtype=np.int32).reshape(-1, 10)
+    axes = np.zeros((len(m), 3), np.int64)
+    has = np.zeros(len(m), np.int32)
+    _load().orc_pca_axes(_p(m), len(m), _p(axes), _p(has))
+    return axes, has
 
 
 def floor_div(a: int, b: int) -> int:

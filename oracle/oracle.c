@@ -738,84 +738,102 @@ static int nb_cmp(const void *a, const void *b) {
   return 0;
 }
 
-static int bitlen64(uint64_t m) {
-  int n = 0;
-  while (m) {
-    n++;
-    m >>= 1;
-  }
-  return n;
-}
-
 /* Section 3.4 "Approach directions": the normal is the least principal axis
  * (PCA) of the k nearest surface voxels, oriented towards the mean of the
- * sensor positions recorded for the point.  Neighbours: surface voxels within
- * +-3 voxels, the point itself included, taken nearest first; every voxel tied
- * with the k-th at its distance is included too, so the set does not depend
- * on the axis convention.  The scatter M = n sum(dd^T) - (sum d)(sum d)^T is exact in
- * int64.  Its least eigenvector is the dominant one of B = trace(M) I - M,
- * obtained by squaring B eight times (B^256) in integer arithmetic, keeping 28
- * significant bits after each squaring (shifts round to nearest, halves away
- * from zero, so the result turns exactly with the scene under axis flips and
- * permutations), and taking the column of largest norm.  Returns 0 when
- * fewer than 3 neighbours exist. */
-static int64_t round_shift(int64_t x, int sh) {
-  if (sh <= 0) return x;
-  int64_t m = x < 0 ? -x : x;
-  int64_t q = (m + (1LL << (sh - 1))) >> sh;
-  return x < 0 ? -q : q;
+ * sensor positions recorded for the point.
+ *
+ * Neighbours: surface voxels within +-3 voxels of the point, the point itself
+ * included, nearest first; voxels at equal distance are taken in ascending
+ * (dz, dy, dx) order, and the walk stops at exactly k.  The scatter
+ * M = n sum(dd^T) - (sum d)(sum d)^T (n^2 times the covariance) is exact in
+ * int64 and converted exactly to double.
+ *
+ * Eigen-decomposition: cyclic Jacobi (Golub & Van Loan, "Matrix
+ * Computations", the cyclic Jacobi method built on the 2x2 symmetric Schur
+ * decomposition).  Eight sweeps over the pairs (0,1), (0,2), (1,2); a pair
+ * whose off-diagonal entry is exactly zero is skipped.  For a pair (p, q):
+ *   theta = (a_qq - a_pp) / (2 a_pq)
+ *   t = sign(theta) / (|theta| + sqrt(theta^2 + 1)),  sign(0) = +1
+ *   c = 1 / sqrt(t^2 + 1),  s = t c
+ *   a_pp -= t a_pq,  a_qq += t a_pq,  a_pq = a_qp = 0
+ *   for the third index r: a_rp <- c a_rp - s a_rq,  a_rq <- s a_rp + c a_rq
+ *   for every row i of V:  v_ip <- c v_ip - s v_iq,  v_iq <- s v_ip + c v_iq
+ * The axis is the column of V at the smallest diagonal entry (ties: lowest
+ * index), stored in fixed point as llrint(2^30 v) per component.  Every
+ * operation is an IEEE basic operation (+, -, *, /, sqrt) with contraction
+ * off, written in this order.  Returns 0 with fewer than 3 neighbours. */
+int orc_pca_axis(int64_t cnt, const int64_t sx[3], const int64_t sxx[6], int64_t out[3]) {
+  out[0] = out[1] = out[2] = 0;
+  if (cnt < 3) return 0;
+  /* sxx: 00 01 02 11 12 22 */
+  const int64_t m00 = cnt * sxx[0] - sx[0] * sx[0], m01 = cnt * sxx[1] - sx[0] * sx[1];
+  const int64_t m02 = cnt * sxx[2] - sx[0] * sx[2], m11 = cnt * sxx[3] - sx[1] * sx[1];
+  const int64_t m12 = cnt * sxx[4] - sx[1] * sx[2], m22 = cnt * sxx[5] - sx[2] * sx[2];
+  double a[3][3] = {{(double)m00, (double)m01, (double)m02},
+                    {(double)m01, (double)m11, (double)m12},
+                    {(double)m02, (double)m12, (double)m22}};
+  double v[3][3] = {{1.0, 0.0, 0.0}, {0.0, 1.0, 0.0}, {0.0, 0.0, 1.0}};
+  static const int pairs[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+  for (int sweep = 0; sweep < 8; ++sweep)
+    for (int k = 0; k < 3; ++k) {
+      const int p = pairs[k][0], q = pairs[k][1], r = 3 - p - q;
+      const double apq = a[p][q];
+      if (apq == 0.0) continue;
+      const double theta = (a[q][q] - a[p][p]) / (2.0 * apq);
+      double t = 1.0 / (fabs(theta) + sqrt(theta * theta + 1.0));
+      if (theta < 0.0) t = -t;
+      const double c = 1.0 / sqrt(t * t + 1.0);
+      const double s = t * c;
+      a[p][p] = a[p][p] - t * apq;
+      a[q][q] = a[q][q] + t * apq;
+      a[p][q] = a[q][p] = 0.0;
+      const double arp = a[r][p], arq = a[r][q];
+      a[r][p] = a[p][r] = c * arp - s * arq;
+      a[r][q] = a[q][r] = s * arp + c * arq;
+      for (int i = 0; i < 3; ++i) {
+        const double vip = v[i][p], viq = v[i][q];
+        v[i][p] = c * vip - s * viq;
+        v[i][q] = s * vip + c * viq;
+      }
+    }
+  int best = 0;
+  for (int j = 1; j < 3; ++j)
+    if (a[j][j] < a[best][best]) best = j;
+  for (int i = 0; i < 3; ++i) out[i] = llrint(v[i][best] * 1073741824.0);
+  return 1;
+}
+
+/* orc_pca_axis over n moment rows [n][10] (cnt, sum d [3], sum dd^T [6]). */
+void orc_pca_axes(const int32_t *mom, int64_t n, int64_t *axes, int32_t *has) {
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t *m = mom + 10 * i;
+    const int64_t sx[3] = {m[1], m[2], m[3]};
+    const int64_t sxx[6] = {m[4], m[5], m[6], m[7], m[8], m[9]};
+    has[i] = orc_pca_axis(m[0], sx, sxx, axes + 3 * i);
+  }
 }
 
 static int point_normal(const orc_t *o, int64_t p, const int32_t *nbo, int nnb,
                         int64_t n_out[3]) {
   int64_t s[3];
   orc_unkey(o->pkey[p], s);
-  int64_t sx[3] = {0, 0, 0}, sxx[3][3] = {{0}};
-  int cnt = 0;
-  int32_t last_d2 = -1;
-  for (int j = 0; j < nnb; ++j) {
+  int64_t sx[3] = {0, 0, 0}, sxx[6] = {0, 0, 0, 0, 0, 0};
+  int64_t cnt = 0;
+  for (int j = 0; j < nnb && cnt < o->cfg.knn_k; ++j) {
     const int32_t *d = nbo + 3 * j;
-    int32_t d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-    if (cnt >= o->cfg.knn_k && d2 != last_d2) break;
     if (hm_get(&o->pmap, orc_key(s[0] + d[0], s[1] + d[1], s[2] + d[2])) < 0) continue;
     cnt++;
-    last_d2 = d2;
-    for (int a = 0; a < 3; ++a) {
-      sx[a] += d[a];
-      for (int b = 0; b < 3; ++b) sxx[a][b] += (int64_t)d[a] * d[b];
-    }
+    for (int a = 0; a < 3; ++a) sx[a] += d[a];
+    sxx[0] += (int64_t)d[0] * d[0];
+    sxx[1] += (int64_t)d[0] * d[1];
+    sxx[2] += (int64_t)d[0] * d[2];
+    sxx[3] += (int64_t)d[1] * d[1];
+    sxx[4] += (int64_t)d[1] * d[2];
+    sxx[5] += (int64_t)d[2] * d[2];
   }
-  if (cnt < 3) return 0;
-  int64_t M[3][3], B[3][3];
-  for (int a = 0; a < 3; ++a)
-    for (int b = 0; b < 3; ++b) M[a][b] = (int64_t)cnt * sxx[a][b] - sx[a] * sx[b];
-  int64_t tr = M[0][0] + M[1][1] + M[2][2];
-  for (int a = 0; a < 3; ++a)
-    for (int b = 0; b < 3; ++b) B[a][b] = (a == b ? tr : 0) - M[a][b];
-  for (int it = 0; it < 8; ++it) {
-    int64_t C[3][3];
-    uint64_t mx = 0;
-    for (int a = 0; a < 3; ++a)
-      for (int b = 0; b < 3; ++b) {
-        C[a][b] = B[a][0] * B[0][b] + B[a][1] * B[1][b] + B[a][2] * B[2][b];
-        uint64_t m = (uint64_t)(C[a][b] < 0 ? -C[a][b] : C[a][b]);
-        if (m > mx) mx = m;
-      }
-    int sh = bitlen64(mx) - 28;
-    for (int a = 0; a < 3; ++a)
-      for (int b = 0; b < 3; ++b) B[a][b] = round_shift(C[a][b], sh);
-  }
-  int best = 0;
-  int64_t bn = -1;
-  for (int c = 0; c < 3; ++c) {
-    int64_t nrm = B[0][c] * B[0][c] + B[1][c] * B[1][c] + B[2][c] * B[2][c];
-    if (nrm > bn) {
-      bn = nrm;
-      best = c;
-    }
-  }
-  if (bn <= 0) return 0;
-  for (int a = 0; a < 3; ++a) n_out[a] = B[a][best];
+  if (!orc_pca_axis(cnt, sx, sxx, n_out)) return 0;
+  /* orientation: towards the mean sensor position, sum(q) / n_q, compared
+   * exactly as n . (sum(q) - n_q c(s)) (a zero product keeps the sign) */
   __int128 g = 0;
   for (int a = 0; a < 3; ++a) {
     int64_t ga = o->sumq[3 * p + a] - (int64_t)o->nq[p] * (256 * s[a] + 128);

@@ -118,6 +118,11 @@ int orc_smooth_refine(const orc_t *o, const float *p, int64_t n, const float *q0
                       double eta, double max_step, double *q_out, double *s_out, double *face);
 
 /* Exposed for unit tests. */
+/* Least principal axis of a neighbourhood from its moments (cnt, sum d,
+ * sum dd^T as 00 01 02 11 12 22), in fixed point 2^30, unoriented; returns
+ * 0 (axis zero) when cnt < 3. */
+int orc_pca_axis(int64_t cnt, const int64_t sx[3], const int64_t sxx[6], int64_t out[3]);
+void orc_pca_axes(const int32_t *mom, int64_t n, int64_t *axes, int32_t *has);
 int64_t orc_isqrt(int64_t n);
 int64_t orc_floor_div(int64_t a, int64_t b);
 int64_t orc_key(int64_t x, int64_t y, int64_t z);
