@@ -10,10 +10,12 @@ corridor at 256 orientations (64 Fibonacci directions x 4 rolls).
 One step = one frame through the whole hot path: integrate_frame (scan-centric
 TSDF integration, ray-cleared band, surface points, fold) then score_points
 (normals, candidate masks, collision-count search for every confident point).
-Frames 0..W-1 are untimed warm-up, frames W..W+K-1 are timed back to back with
-their returns already in HBM, and the remaining frames (default 100) are
-replayed under 10 Hz pacing from pinned host memory to measure frame latency
-(release -> labels on the host).  The defaults cover the workload's 600 frames.
+The K timed frames are centred on frame 300 of the 600-frame sequence (never
+before frame 100 or before --warmup): frames 0..F0-1 are an untimed pre-roll
+(integrate + score), frames F0..F0+K-1 are timed back to back with their
+returns already in HBM.  Frame latency (release -> labels on the host) is then
+measured on a fresh map by replaying the sequence's first L frames (default:
+all 600) at 10 Hz from pinned host memory.
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -174,10 +176,19 @@ def _pinned_call(fn, core):
     return fn()
 
 
+def tree_window(warmup, steps):
+    """First timed frame of the tree workload: the timed frames are centred on
+    frame 300 of the 600-frame sequence, and start no earlier than frame 100
+    or than `warmup`."""
+    return max(warmup, 100, 300 - steps // 2)
+
+
 def trace_summary(csv_path, warmup, steps):
     """Per-launch device time of the hot kernels from a rocprofv3 kernel-trace
-    CSV of a default bench run: mean over all launches and over the timed
-    frames' launches only (one launch per frame, frames warmup..warmup+steps-1)."""
+    CSV of a tree bench run with the same --warmup/--steps: mean over all
+    launches and over the timed frames' launches only (one launch per frame,
+    frames F0..F0+steps-1 with F0 = tree_window(warmup, steps))."""
+    first = tree_window(warmup, steps)
     import csv
     per = {}
     with open(csv_path) as f:
@@ -195,8 +206,9 @@ def trace_summary(csv_path, warmup, steps):
     for base, rows in per.items():
         rows.sort()
         d = np.array([(e - b) / 1e6 for b, e, _ in rows])
-        timed = d[warmup:warmup + steps]
+        timed = d[first:first + steps]
         out[base] = {"launches": int(len(d)), "avg_ms_all": float(d.mean()),
+                     "timed_frames": [first, first + steps - 1],
                      "avg_ms_timed": float(timed.mean()) if len(timed) else None,
                      "timed_launches": int(len(timed)), "symbol": rows[0][2][:120]}
     return out
@@ -236,9 +248,11 @@ def traffic_summary(paths, warmup, steps, copy_bytes, workload="tree"):
     pattern, src_key, fname, desc = TRAFFIC_TARGETS[workload]
     src = SCORE_SRC if src_key == "SCORE" else SMOOTH_SRC
 
+    first = tree_window(warmup, steps) if workload == "tree" else warmup
+
     def score_mean(path, counter):
         rows = [v for _, name, v in _counter_rows(path, counter) if re.search(pattern, name)]
-        timed = rows[warmup:warmup + steps]
+        timed = rows[first:first + steps]
         return float(np.mean(timed)), len(rows)
 
     def copy_kib(path, counter):
@@ -251,8 +265,9 @@ def traffic_summary(paths, warmup, steps, copy_bytes, workload="tree"):
     w_scale = copy_bytes / (copy_kib(cwrite, "WRITE_SIZE") * 1024.0)
     out = {
         "kernel": desc,
-        "workload": "%s, launches %d-%d (timed launches of bench.py)" % (workload, warmup,
-                                                                         warmup + steps - 1),
+        "workload": "%s, launches %d-%d (timed launches of bench.py --warmup %d --steps %d)" % (
+            workload, first, first + steps - 1, warmup, steps),
+        "window": [first, first + steps - 1],
         "file": fname,
         "src_sha": src_sha(src),
         "fetch_kib_per_launch": f_kib, "write_kib_per_launch": w_kib,
@@ -261,13 +276,15 @@ def traffic_summary(paths, warmup, steps, copy_bytes, workload="tree"):
         "launches_seen": [nf, nw],
         "commands": [
             "rocprofv3 --pmc FETCH_SIZE -d <dir> -o p --output-format csv -- python3 bench.py "
-            "--workload %s --no-cpu-baseline --latency-frames 0" % workload,
+            "--workload %s --warmup %d --steps %d --no-cpu-baseline --latency-frames 0" % (
+                workload, warmup, steps),
             "rocprofv3 --pmc WRITE_SIZE -d <dir> -o p --output-format csv -- python3 bench.py "
-            "--workload %s --no-cpu-baseline --latency-frames 0" % workload,
+            "--workload %s --warmup %d --steps %d --no-cpu-baseline --latency-frames 0" % (
+                workload, warmup, steps),
             "rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) -d <dir> -o p --output-format csv -- "
             "python3 bench.py --copy-probe %d" % copy_bytes,
-            "python3 bench.py --workload %s --traffic-summary "
-            "fetch.csv,write.csv,copy_fetch.csv,copy_write.csv" % workload],
+            "python3 bench.py --workload %s --warmup %d --steps %d --traffic-summary "
+            "fetch.csv,write.csv,copy_fetch.csv,copy_write.csv" % (workload, warmup, steps)],
     }
     return out
 
@@ -818,7 +835,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--latency-frames", type=int, default=100)
+    ap.add_argument("--latency-frames", type=int, default=600,
+                    help="frames of the tree sequence replayed at 10 Hz on a fresh map")
     ap.add_argument("--cpu-frames", type=int, default=12)
     ap.add_argument("--cpu-points", type=int, default=100000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -891,18 +909,16 @@ def main():
         run_batch(args)
         return
     W, K, L = args.warmup, args.steps, args.latency_frames
-    total = W + K + L
-    w = synth.tree(n_frames=total)
+    F0 = tree_window(W, K)
+    total = max(F0 + K, L)
+    w = synth.tree(n_frames=max(600, total))
     t = time.perf_counter()
     frames = w.frames(total)
     log("generated %d frames in %.1f s" % (total, time.perf_counter() - t))
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
-    resident = [torch.from_numpy(f.xyz).to(dev) for f in frames[:W + K]]
-    pinned = [torch.from_numpy(f.xyz).pin_memory() for f in frames[W + K:]]
-    nmax = max(len(f.xyz) for f in frames)
-    staging = torch.empty((nmax, 3), dtype=torch.float32, device=dev)
+    resident = [torch.from_numpy(f.xyz).to(dev) for f in frames[:F0 + K]]
 
     cfg = default_config(w.voxel, w.trunc, r_c=w.r_c, max_blocks=1 << 17,
                          max_points=1 << 22, max_orientations=len(w.rot), max_tools=1)
@@ -915,19 +931,20 @@ def main():
         v = args.score_variant
         idx = int(v) if str(v).isdigit() else names.index(v)
         ctx.set_score_variant(idx)
+    idx = ctx.score_variant()
     t = time.perf_counter()
-    for i in range(W):
+    for i in range(F0):
         ctx.integrate_frame(resident[i], frames[i].origin, frames[i].frame_id)
         ctx.score_points(0)
-        if i % 20 == 0:
-            log("warm-up frame %d, %d points" % (i, ctx.num_points()))
+        if i % 50 == 0:
+            log("pre-roll frame %d, %d points" % (i, ctx.num_points()))
     torch.cuda.synchronize()
-    log("warm-up %d frames in %.1f s" % (W, time.perf_counter() - t))
+    log("pre-roll %d frames (warm-up %d) in %.1f s" % (F0, W, time.perf_counter() - t))
     if args.tune:
         best, ms = ctx.tune_score(0, reps=3)
         tuning = {"chosen": names[best], "ms": {n: round(m, 3) for n, m in zip(names, ms)},
-                  "at_frame": W}
-        log("score tuning at frame %d: %s" % (W, json.dumps(tuning)))
+                  "at_frame": F0}
+        log("score tuning at frame %d: %s" % (F0, json.dumps(tuning)))
     else:
         tuning = {"chosen": names[ctx.score_variant()], "tuned": False}
 
@@ -938,7 +955,7 @@ def main():
     byts = kbyts = 0.0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(W, W + K):
+    for i in range(F0, F0 + K):
         ctx.integrate_frame(resident[i], frames[i].origin, frames[i].frame_id)
         ctx.score_points(0)
         st = ctx.score_stats(0)
@@ -957,48 +974,63 @@ def main():
         byts += score_bytes(st["canonical_lookups"], st["n_confident"], Krot)
         kbyts += kscore_bytes(st["canonical_lookups"], st["arm_lookups"], st["n_confident"], Krot)
         returns += len(frames[i].xyz)
-        if (i - W) % 50 == 0:
+        if (i - F0) % 50 == 0:
             log("timed frame %d: %d points, %d confident, %d canonical tests" %
                 (i, st["n_points"], st["n_confident"], st["canonical_tests"]))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     tm = ctx.timing_read(reset=True)
     wall = t1 - t0
-    log("timed %d frames in %.2f s" % (K, wall))
+    log("timed frames %d-%d in %.2f s" % (F0, F0 + K - 1, wall))
     map_points = ctx.num_points()
     map_blocks = ctx.num_blocks()
+    ctx.close()
+    del resident
 
-    # 10 Hz paced latency: release -> labels on the host.  The host keeps the
-    # keys in canonical order (points are only appended), so each frame copies
-    # every point's label and first free orientation and the new points' keys,
-    # into pinned arrays allocated once.
-    cap = cfg.max_points
-    host = {"label": torch.empty(cap, dtype=torch.uint8, pin_memory=True).numpy(),
-            "first_free": torch.empty(cap, dtype=torch.int16, pin_memory=True).numpy(),
-            "key": torch.empty(cap, dtype=torch.int64, pin_memory=True).numpy()}
-    known = ctx.num_points()
-    ctx.read_labels(0, out=host)
-    lat = []
-    tstart = time.perf_counter() + 0.05
-    for j, f in enumerate(frames[W + K:]):
-        release = tstart + 0.1 * j
-        while time.perf_counter() < release:
-            time.sleep(0.0005)
-        n = len(f.xyz)
-        staging[:n].copy_(pinned[j], non_blocking=True)
-        ctx.integrate_frame(staging[:n], f.origin, f.frame_id)
-        ctx.score_points(0)
-        got = ctx.read_labels(0, out=host, keys=False)
-        m = len(got["label"])
-        if m > known:
-            ctx.read_labels(0, first=known, count=m - known,
-                            out={"key": host["key"][known:], "label": host["label"][known:],
-                                 "first_free": host["first_free"][known:]})
-            known = m
-        lat.append((time.perf_counter() - release) * 1e3)
-    lat = np.array(lat) if lat else np.zeros(1)
-    log("latency over %d paced frames: p50 %.1f ms, p99 %.1f ms" %
-        (len(lat), np.percentile(lat, 50), np.percentile(lat, 99)))
+    # 10 Hz paced latency on a fresh map: release -> labels on the host, for
+    # the sequence's first L frames.  The host keeps the keys in canonical
+    # order (points are only appended), so each frame copies every point's
+    # label and first free orientation and the new points' keys, into pinned
+    # arrays allocated once.
+    lat = np.zeros(0)
+    if L > 0:
+        pinned = [torch.from_numpy(f.xyz).pin_memory() for f in frames[:L]]
+        nmax = max(len(f.xyz) for f in frames[:L])
+        staging = torch.empty((nmax, 3), dtype=torch.float32, device=dev)
+        lctx = Context(cfg)
+        lctx.set_tool_kernels(0, w.tool, w.rot)
+        if not args.tune and args.score_variant is not None:
+            lctx.set_score_variant(idx)
+        cap = cfg.max_points
+        host = {"label": torch.empty(cap, dtype=torch.uint8, pin_memory=True).numpy(),
+                "first_free": torch.empty(cap, dtype=torch.int16, pin_memory=True).numpy(),
+                "key": torch.empty(cap, dtype=torch.int64, pin_memory=True).numpy()}
+        known = 0
+        lat_l = []
+        torch.cuda.synchronize()
+        tstart = time.perf_counter() + 0.05
+        for j, f in enumerate(frames[:L]):
+            release = tstart + 0.1 * j
+            while time.perf_counter() < release:
+                time.sleep(0.0005)
+            n = len(f.xyz)
+            staging[:n].copy_(pinned[j], non_blocking=True)
+            lctx.integrate_frame(staging[:n], f.origin, f.frame_id)
+            lctx.score_points(0)
+            got = lctx.read_labels(0, out=host, keys=False)
+            m = len(got["label"])
+            if m > known:
+                lctx.read_labels(0, first=known, count=m - known,
+                                 out={"key": host["key"][known:], "label": host["label"][known:],
+                                      "first_free": host["first_free"][known:]})
+                known = m
+            lat_l.append((time.perf_counter() - release) * 1e3)
+            if j % 100 == 0:
+                log("paced frame %d: %.1f ms, %d points" % (j, lat_l[-1], m))
+        lat = np.array(lat_l)
+        lctx.close()
+        log("latency over %d paced frames: p50 %.1f ms, p99 %.1f ms" %
+            (len(lat), np.percentile(lat, 50), np.percentile(lat, 99)))
 
     kernels = {"k_score": tm["k_score_ms"], "k_integrate_fold": tm["k_integrate_ms"],
                "k_normals": tm["k_normals_ms"], "k_mask": tm["k_mask_ms"]}
@@ -1007,15 +1039,22 @@ def main():
     achieved = kbyts / score_s / 1e9 if score_s > 0 else 0.0
     path_s = (tm["k_score_ms"] + tm["k_mask_ms"]) / 1e3
     path_achieved = byts / path_s / 1e9 if path_s > 0 else 0.0
+    # measured HBM bytes per launch, only when the counters were taken on this
+    # scoring source and on this frame window
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         tr = json.load(open(TRAFFIC_FILE))
-        if tr.get("src_sha") == src_sha(SCORE_SRC):
+        if tr.get("src_sha") == src_sha(SCORE_SRC) and tr.get("window") == [F0, F0 + K - 1]:
             traffic = tr.get("bytes_per_launch")
+    alg_launch = kbyts / max(K, 1)
     roofline = {"kernel": "k_score", "bound": "hbm", "achieved": achieved,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                 "traffic": traffic,
-                "algorithmic_bytes_per_launch": kbyts / max(K, 1),
+                "limiter": "priced against HBM (algorithmic bytes); the measured limiter is "
+                           "the latency of L2-resident gathers (DRAM traffic is a few percent "
+                           "of the algorithmic bytes)",
+                "dram_over_algorithmic": (traffic / alg_launch) if traffic and alg_launch else None,
+                "algorithmic_bytes_per_launch": alg_launch,
                 "bytes_model": "8 B per canonical lookup not answered by the mask kernel + "
                                "per confident point 8 B key + 3K/8 B mask and arm planes + "
                                "4 B weight + 3 B outputs",
@@ -1042,18 +1081,21 @@ def main():
             "workload": "tree: procedural 8 m tree, 20,000 returns/frame from an orbiting "
                         "Mid-360-shaped sensor, v=1 cm, tau=4 cm, saw box 30x5x2 cm + 1 m "
                         "corridor, K=256 (64 directions x 4 rolls)",
-            "frames_timed": [W, W + K - 1], "returns_per_frame": int(np.mean([len(f.xyz) for f in frames])),
+            "frames_timed": [F0, F0 + K - 1], "preroll_frames": F0,
+            "returns_per_frame": int(np.mean([len(f.xyz) for f in frames])),
             "orientations": Krot, "voxel_m": w.voxel, "trunc_m": w.trunc,
             "map_points_end": int(map_points), "map_blocks_end": int(map_blocks),
         },
         "returns_integrated_per_s": returns / (tm["integrate_ms"] / 1e3),
         "nominal_tests_per_s": nominal / wall,
         "canonical_lookups_per_s": lookups / wall,
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                       "max": float(lat.max()), "frames": int(len(lat)), "rate_hz": 10,
-                       "includes": "H2D of the frame, integrate, score, D2H of every point's "
-                                   "label and first free orientation and of the new points' keys "
-                                   "(pinned host arrays)"},
+        "latency_ms": None if len(lat) == 0 else {
+            "p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+            "max": float(lat.max()), "frames": int(len(lat)), "rate_hz": 10,
+            "sequence_frames": [0, int(len(lat)) - 1],
+            "includes": "H2D of the frame, integrate, score, D2H of every point's label and "
+                        "first free orientation and of the new points' keys (pinned host "
+                        "arrays); frames replayed on a fresh map"},
         "stage_ms_per_step": {k: v / max(K, 1) for k, v in
                               {"integrate": tm["integrate_ms"], "score": tm["score_ms"],
                                **kernels}.items()},

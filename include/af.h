@@ -157,6 +157,41 @@ const char *af_last_error(const af_ctx *ctx);
 int af_set_tool_kernels(af_ctx *ctx, int32_t tool_id, const af_tool *tool,
                         int32_t K, const double *rot, void *stream);
 
+/* Section 3.4 "Tool kernel": set tool `tool_id` from a caller-built table,
+ * for tools that are not primitives (for instance a point cloud sampled from
+ * the tool's 3D model, rotated and voxelised by the caller).  All arrays are
+ * HOST memory owned by the caller; the library copies them.
+ *   K             orientations, 1..max_orientations
+ *   dir[K][3]     unit approach direction of each orientation (the normal
+ *                 and observation filters use it; |norm - 1| <= 1e-9)
+ *   offset_begin  [K + 1] entry ranges: orientation k owns entries
+ *                 [offset_begin[k], offset_begin[k + 1]); offset_begin[0] = 0,
+ *                 non-decreasing
+ *   off[n][3]     voxel offsets (x, y, z) from the point's voxel, each
+ *                 component within +-511
+ *   cls[n]        AF_CLS_NEAR (exactly three per orientation: the arm samples
+ *                 of Section 3.4 "Arm path checking"), AF_CLS_BODY (tool solid)
+ *                 or AF_CLS_FAR (approach corridor)
+ * The library stores each orientation's entries as its three NEAR entries in
+ * the given order, then BODY and then FAR each sorted by (|o|^2, z, y, x); an
+ * offset may appear once per class, and at most 16384 times per class and
+ * orientation.  Labels do not depend on the entry order; canonical lookup
+ * counts are counted in this stored order.  af_set_tool_kernels builds the
+ * same form for its primitives, so af_read_tool_table of a primitive tool fed
+ * back here gives identical results.  Synchronises `stream`.  Errors:
+ * AF_EINVAL (bad id, K, direction, range, class, NEAR count, repeated offset;
+ * the tool is then unchanged), AF_ENOMEM.  Replacing a tool invalidates its
+ * labels. */
+typedef struct af_kernel_table {
+  int32_t K;
+  int32_t pad;
+  const double *dir;
+  const uint32_t *offset_begin;
+  const int16_t *off;
+  const uint8_t *cls;
+} af_kernel_table;
+int af_set_tool_table(af_ctx *ctx, int32_t tool_id, const af_kernel_table *table, void *stream);
+
 /* Section 3.2: integrate one frame.  `xyz` is a DEVICE array of n float32
  * triples (world frame), `origin` a HOST array of 3 floats (the sensor
  * position of the frame).  For every valid return the voxels of the index
@@ -212,11 +247,23 @@ int af_read_points(af_ctx *ctx, int64_t first, int64_t count, int64_t *key,
 /* Table of orientation k: offsets [m][3] and classes; *m = entry count. */
 int af_read_tool_table(af_ctx *ctx, int32_t tool_id, int32_t k, int32_t *off,
                        uint8_t *cls, int64_t cap, int64_t *m);
-/* Normals (int32 [3], has_normal) and candidate masks ([ceil(K/64)] words)
- * from the last af_score_points of tool_id, for points [first, first+count). */
+/* Normals (int32 [3]: the oriented least principal axis in fixed point 2^30,
+ * has_normal 1; 0 when the point has fewer than 3 neighbours, -1 when it is
+ * not confident) and candidate masks ([ceil(K/64)] words) from the last
+ * af_score_points of tool_id, for points [first, first+count). */
 int af_read_point_debug(af_ctx *ctx, int32_t tool_id, int64_t first,
                         int64_t count, int32_t *normal, int32_t *has_normal,
                         uint64_t *mask, int64_t *n_written);
+/* The PCA step of the normals (Section 3.4 "Approach directions") on
+ * caller-given neighbourhoods, for tests: moments is a HOST array [n][10] of
+ * (voxel count, sum of offsets [3], sum of offset products 00 01 02 11 12 22),
+ * offsets in voxels; axes [n][3] receives the least principal axis of the
+ * scatter count * sum(dd^T) - (sum d)(sum d)^T in fixed point 2^30 (unit
+ * length, sign as the eigen-solver leaves it) and has[n] 1, or 0 and a zero
+ * axis when the count is below 3.  No context; synchronous; uses its own
+ * device buffers.  AF_EINVAL on n < 0 or NULL arrays, AF_EDEVICE on a HIP
+ * error. */
+int af_pca_axes(const int32_t *moments, int64_t n, int64_t *axes, int32_t *has);
 int af_frame_stats_get(af_ctx *ctx, af_frame_stats *st);
 int af_score_stats_get(af_ctx *ctx, int32_t tool_id, af_score_stats *st);
 /* Bytes of device memory the context holds. */

@@ -97,6 +97,8 @@ def _load():
     L.orc_read_points.argtypes = [vp, vp, vp, vp, vp, vp, vp, i64]
     L.orc_set_tool.restype = ctypes.c_int
     L.orc_set_tool.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ToolDesc), i32, vp]
+    L.orc_set_tool_table.restype = ctypes.c_int
+    L.orc_set_tool_table.argtypes = [vp, ctypes.c_int, i32, vp, vp, vp, vp]
     L.orc_tool_table.restype = i64
     L.orc_tool_table.argtypes = [vp, ctypes.c_int, i32, vp, vp, i64]
     L.orc_score.restype = ctypes.c_int
@@ -280,6 +282,19 @@ class Oracle:
         if rc != 0:
             raise ValueError("oracle set_tool failed (%d)" % rc)
         self.K[tool_id] = len(rot)
+
+    def set_tool_table(self, tool_id, dirs, offset_begin, off, cls):
+        d = np.ascontiguousarray(dirs, dtype=np.float64).reshape(-1, 3)
+        b = np.ascontiguousarray(offset_begin, dtype=np.uint32).reshape(-1)
+        o = np.ascontiguousarray(off, dtype=np.int16).reshape(-1, 3)
+        c = np.ascontiguousarray(cls, dtype=np.uint8).reshape(-1)
+        assert len(b) == len(d) + 1
+        o1 = o if len(o) else np.zeros((1, 3), np.int16)
+        c1 = c if len(c) else np.zeros(1, np.uint8)
+        rc = self.L.orc_set_tool_table(self.h, int(tool_id), len(d), _p(d), _p(b), _p(o1), _p(c1))
+        if rc != 0:
+            raise ValueError("oracle set_tool_table rejected the table")
+        self.K[tool_id] = len(d)
 
     def tool_table(self, tool_id, k):
         cap = 1 << 17

@@ -697,6 +697,84 @@ int orc_set_tool(orc_t *o, int tool_id, const orc_tool *t, int32_t K,
   return 0;
 }
 
+/* Section 3.4 "Tool kernel": a tool given as a caller-built table of voxel
+ * offsets (for a tool that is not a primitive, e.g. a point cloud sampled
+ * from its 3D model and voxelised under each orientation).  Orientation k
+ * has approach direction dir[k] (used by the candidate filters) and the
+ * entries [begin[k], begin[k+1]) of off/cls.  They are kept in the order the
+ * scoring visits them: the three arm samples (NEAR) in the given order, then
+ * the BODY offsets and then the FAR offsets, each sorted by
+ * (|o|^2, z, y, x).  Returns -1 (tool unchanged) for K < 1, a direction whose
+ * length is off 1 by more than 1e-9, a non-monotone begin, a class outside
+ * 0..2, other than three NEAR entries, an offset component beyond 511 voxels
+ * or an offset listed twice in one class. */
+int orc_set_tool_table(orc_t *o, int tool_id, int32_t K, const double *dir,
+                       const uint32_t *begin, const int16_t *off, const uint8_t *cls) {
+  if (tool_id < 0 || tool_id >= MAX_TOOLS || K <= 0 || begin[0] != 0) return -1;
+  for (int32_t k = 0; k < K; ++k) {
+    const double *d = dir + 3 * k;
+    if (!(fabs(sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) - 1.0) <= 1e-9)) return -1;
+    if (begin[k + 1] < begin[k]) return -1;
+  }
+  int64_t n = begin[K];
+  int32_t *toff = (int32_t *)malloc(sizeof(int32_t) * 3 * (n > 0 ? n : 1));
+  uint8_t *tcls = (uint8_t *)malloc(n > 0 ? n : 1);
+  int64_t *tbeg = (int64_t *)malloc(sizeof(int64_t) * (K + 1));
+  ent *grp = (ent *)malloc(sizeof(ent) * (n > 0 ? n : 1));
+  int64_t m = 0;
+  int ok = 1;
+  tbeg[0] = 0;
+  for (int32_t k = 0; k < K && ok; ++k) {
+    int nnear = 0;
+    for (uint32_t e = begin[k]; e < begin[k + 1] && ok; ++e) {
+      if (cls[e] > CLS_FAR) ok = 0;
+      for (int i = 0; i < 3; ++i)
+        if (off[3 * e + i] < -511 || off[3 * e + i] > 511) ok = 0;
+      if (ok && cls[e] == CLS_NEAR) {
+        if (++nnear > 3) ok = 0;
+        for (int i = 0; i < 3; ++i) toff[3 * m + i] = off[3 * e + i];
+        tcls[m++] = CLS_NEAR;
+      }
+    }
+    if (nnear != 3) ok = 0;
+    const uint8_t order[2] = {CLS_BODY, CLS_FAR};
+    for (int g = 0; g < 2 && ok; ++g) {
+      int64_t ng = 0;
+      for (uint32_t e = begin[k]; e < begin[k + 1]; ++e) {
+        if (cls[e] != order[g]) continue;
+        ent x;
+        for (int i = 0; i < 3; ++i) x.o[i] = off[3 * e + i];
+        x.n2 = (int64_t)x.o[0] * x.o[0] + (int64_t)x.o[1] * x.o[1] + (int64_t)x.o[2] * x.o[2];
+        grp[ng++] = x;
+      }
+      qsort(grp, (size_t)ng, sizeof(ent), cmp_ent);
+      for (int64_t j = 0; j < ng; ++j) {
+        if (j > 0 && cmp_ent(&grp[j - 1], &grp[j]) == 0) ok = 0;
+        for (int i = 0; i < 3; ++i) toff[3 * m + i] = grp[j].o[i];
+        tcls[m++] = order[g];
+      }
+    }
+    tbeg[k + 1] = m;
+  }
+  free(grp);
+  if (!ok) {
+    free(toff); free(tcls); free(tbeg);
+    return -1;
+  }
+  tool_tab *tt = &o->tools[tool_id];
+  free(tt->begin); free(tt->off); free(tt->cls); free(tt->rot);
+  memset(tt, 0, sizeof(*tt));
+  tt->K = K;
+  tt->begin = tbeg;
+  tt->off = toff;
+  tt->cls = tcls;
+  /* the candidate filters read the approach direction as column 0 */
+  tt->rot = (double *)calloc(9 * (size_t)K, sizeof(double));
+  for (int32_t k = 0; k < K; ++k)
+    for (int i = 0; i < 3; ++i) tt->rot[9 * k + 3 * i] = dir[3 * k + i];
+  return 0;
+}
+
 int64_t orc_tool_table(const orc_t *o, int tool_id, int32_t k, int32_t *off,
                        uint8_t *cls, int64_t cap) {
   if (tool_id < 0 || tool_id >= MAX_TOOLS) return -1;

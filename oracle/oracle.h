@@ -84,6 +84,11 @@ int orc_set_tool(orc_t *o, int tool_id, const orc_tool *t, int32_t K,
                  const double *rot);
 /* Table of one orientation: offsets [m][3] and classes (0 body, 1 near arm
  * sample, 2 far corridor); returns m, or -1. */
+/* A caller-built table: K directions [K][3], entry ranges begin[K + 1],
+ * offsets off[n][3] and classes cls[n] (0 body, 1 arm sample, 2 corridor);
+ * see oracle.c.  Returns 0, or -1 for an invalid table. */
+int orc_set_tool_table(orc_t *o, int tool_id, int32_t K, const double *dir,
+                       const uint32_t *begin, const int16_t *off, const uint8_t *cls);
 int64_t orc_tool_table(const orc_t *o, int tool_id, int32_t k, int32_t *off,
                        uint8_t *cls, int64_t cap);
 

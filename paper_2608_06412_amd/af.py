@@ -50,6 +50,12 @@ class Tool(ctypes.Structure):
                 ("width", ctypes.c_double), ("height", ctypes.c_double)]
 
 
+class KernelTable(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("dir", ctypes.c_void_p), ("offset_begin", ctypes.c_void_p),
+                ("off", ctypes.c_void_p), ("cls", ctypes.c_void_p)]
+
+
 class FrameStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
                 ("n_in", "n_valid", "n_dropped", "pairs_applied", "pairs_excluded",
@@ -109,6 +115,8 @@ SIGNATURES = {
     "af_read_points": (ctypes.c_int, [_vp, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "af_read_tool_table": (ctypes.c_int, [_vp, _i32, _i32, _vp, _vp, _i64, _vp]),
     "af_read_point_debug": (ctypes.c_int, [_vp, _i32, _i64, _i64, _vp, _vp, _vp, _vp]),
+    "af_pca_axes": (ctypes.c_int, [_vp, _i64, _vp, _vp]),
+    "af_set_tool_table": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(KernelTable), _vp]),
     "af_frame_stats_get": (ctypes.c_int, [_vp, ctypes.POINTER(FrameStats)]),
     "af_score_stats_get": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(ScoreStats)]),
     "af_device_bytes": (_i64, [_vp]),
@@ -231,6 +239,18 @@ def _check_f32(t, shape, name):
         raise TypeError("%s must be a contiguous CUDA float32 tensor of shape %s" % (name, shape))
 
 
+def pca_axes(moments) -> tuple:
+    """af_pca_axes: (axes [n][3] int64, has [n] int32) for neighbourhood
+    moments [n][10] (count, sum d [3], sum dd^T [6])."""
+    m = np.ascontiguousarray(moments, dtype=np.int32).reshape(-1, 10)
+    axes = np.zeros((len(m), 3), np.int64)
+    has = np.zeros(len(m), np.int32)
+    rc = lib().af_pca_axes(_p(m), len(m), _p(axes), _p(has))
+    if rc != AF_OK:
+        raise AFError(rc, "af_pca_axes failed")
+    return axes, has
+
+
 class Context:
     """One accessibility-field map on the current GPU (af_ctx)."""
 
@@ -279,6 +299,21 @@ class Context:
         self._check(self._lib.af_set_tool_kernels(self.h, int(tool_id), ctypes.byref(t),
                                                   len(rot), _p(rot), _stream_handle(stream)))
         self.K[tool_id] = len(rot)
+
+    def set_tool_table(self, tool_id: int, dirs, offset_begin, off, cls, stream=None):
+        """Caller-built kernel table (af_set_tool_table): dirs [K, 3] float64,
+        offset_begin [K + 1] uint32, off [n, 3] int16, cls [n] uint8."""
+        d = np.ascontiguousarray(dirs, dtype=np.float64).reshape(-1, 3)
+        b = np.ascontiguousarray(offset_begin, dtype=np.uint32).reshape(-1)
+        o = np.ascontiguousarray(off, dtype=np.int16).reshape(-1, 3)
+        c = np.ascontiguousarray(cls, dtype=np.uint8).reshape(-1)
+        if len(b) != len(d) + 1:
+            raise ValueError("offset_begin needs K + 1 entries")
+        t = KernelTable(len(d), 0, d.ctypes.data, b.ctypes.data,
+                        o.ctypes.data if len(o) else None, c.ctypes.data if len(c) else None)
+        self._check(self._lib.af_set_tool_table(self.h, int(tool_id), ctypes.byref(t),
+                                                _stream_handle(stream)))
+        self.K[tool_id] = len(d)
 
     def integrate_frame(self, xyz, origin, frame_id: int, stream=None):
         """xyz: CUDA float32 tensor [n, 3] (contiguous); origin: 3 floats."""

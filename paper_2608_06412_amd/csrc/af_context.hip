@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <string>
 #include <vector>
@@ -471,6 +472,98 @@ int64_t af_device_bytes(af_ctx *c) { return c ? c->bytes : 0; }
 
 static int graph_settle(af_ctx *c);
 
+// Release tool `tool_id`'s device buffers (after the stream has drained).
+static int tool_release(af_ctx *c, int32_t tool_id, hipStream_t s) {
+  ToolDev &t = c->tools[tool_id];
+  if (!t.entries) return AF_OK;
+  HIP_TRY(c, hipStreamSynchronize(s));
+  dev_free(c, t.entries, c->tool_bytes[tool_id]);
+  dev_free(c, t.begin, sizeof(uint32_t) * (t.K + 1));
+  dev_free(c, t.rot, sizeof(double) * 9 * t.K);
+  dev_free(c, t.label, c->cfg.max_points);
+  dev_free(c, t.first_free, sizeof(int16_t) * c->cfg.max_points);
+  dev_free(c, t.counters, sizeof(ScoreCounters));
+  dev_free(c, t.far_begin, sizeof(uint32_t) * t.K);
+  dev_free(c, t.same, sizeof(uint64_t) * ((t.K + 63) / 64));
+  dev_free(c, t.xent, sizeof(uint2) * std::max<int64_t>(1, t.n_entries));
+  if (t.rent) dev_free(c, t.rent, sizeof(uint32_t) * std::max<int64_t>(1, t.n_entries));
+  if (c->own_mask[tool_id]) {
+    const int64_t mw = (t.K + 63) / 64;
+    dev_free(c, t.mask, sizeof(uint64_t) * c->cfg.max_points * mw);
+    dev_free(c, t.nearp, sizeof(uint64_t) * c->cfg.max_points * 2 * mw);
+    c->own_mask[tool_id] = 0;
+  }
+  dev_free(c, t.c4begin, sizeof(uint32_t) * (t.K + 1));
+  dev_free(c, t.c4flag, t.K);
+  dev_free(c, t.c4entries, sizeof(uint32_t) * std::max<int64_t>(1, t.n_c4entries));
+  memset(&t, 0, sizeof(t));
+  return AF_OK;
+}
+
+// Common tail of both table forms.  nt holds rot, begin, same and the
+// packed entries (NEAR x3, BODY, FAR per orientation); counts[2k], counts[2k+1]
+// are orientation k's BODY and FAR counts (device).  Builds the corridor
+// lists, the grid-independent and grid-relative entry forms, the per-tool
+// outputs, and installs the tool.
+static int tool_finish(af_ctx *c, int32_t tool_id, ToolDev &nt, uint32_t *counts, uint32_t total,
+                       hipStream_t s) {
+  const int32_t K = nt.K;
+  ALLOC(c, nt.label, c->cfg.max_points);
+  ALLOC(c, nt.first_free, c->cfg.max_points);
+  ALLOC(c, nt.counters, 1);
+  HIP_TRY(c, hipMemsetAsync(nt.label, 0, c->cfg.max_points, s));
+  HIP_TRY(c, hipMemsetAsync(nt.counters, 0, sizeof(ScoreCounters), s));
+  uint32_t *ccounts = nullptr;
+  ALLOC(c, nt.far_begin, K);
+  ALLOC(c, ccounts, K);
+  // coarse corridor lists over 4^3 cells
+  ALLOC(c, nt.c4begin, K + 1);
+  ALLOC(c, nt.c4flag, K);
+  if (launch_table_coarse(K, nt.begin, counts, nt.entries, nt.far_begin, ccounts, nt.c4begin,
+                          nullptr, nt.c4flag, 0, 2, s) != 0)
+    return hip_check(c, "coarse4 count");
+  uint32_t c4total = 0;
+  HIP_TRY(c, hipMemcpyAsync(&c4total, nt.c4begin + K, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  ALLOC(c, nt.c4entries, std::max<uint32_t>(1u, c4total));
+  if (launch_table_coarse(K, nt.begin, counts, nt.entries, nt.far_begin, ccounts, nt.c4begin,
+                          nt.c4entries, nt.c4flag, 1, 2, s) != 0)
+    return hip_check(c, "coarse4 fill");
+  nt.n_c4entries = c4total;
+  HIP_TRY(c, hipStreamSynchronize(s));
+  dev_free(c, ccounts, sizeof(uint32_t) * K);
+  {
+    std::vector<uint32_t> he(total);
+    HIP_TRY(c, hipMemcpy(he.data(), nt.entries, sizeof(uint32_t) * total, hipMemcpyDeviceToHost));
+    int32_t reach = 0;
+    for (uint32_t e : he)
+      reach = std::max({reach, std::abs(entry_x(e)), std::abs(entry_y(e)), std::abs(entry_z(e))});
+    nt.reach = reach;
+    if (reach <= 255) {
+      std::vector<uint32_t> rel(total);
+      for (uint32_t j = 0; j < total; ++j) {
+        const uint32_t e = he[j];
+        rel[j] = (uint32_t)(entry_x(e) + 256) | ((uint32_t)(entry_y(e) + 256) << 10) |
+                 ((uint32_t)(entry_z(e) + 256) << 20) | ((uint32_t)entry_cls(e) << 30);
+      }
+      ALLOC(c, nt.rent, std::max<int64_t>(1, total));
+      HIP_TRY(c, hipMemcpy(nt.rent, rel.data(), sizeof(uint32_t) * total, hipMemcpyHostToDevice));
+    }
+  }
+  nt.n_entries = total;
+  ALLOC(c, nt.xent, std::max<int64_t>(1, total));
+  nt.mask = c->mask;
+  nt.nearp = c->nearp;
+  ToolDev &t = c->tools[tool_id];
+  t = nt;
+  c->tool_bytes[tool_id] = sizeof(uint32_t) * (int64_t)total;
+  c->last_stream = s;
+  if (c->grid_bricks > 0 && launch_table_grid(t, c->grid, s) != 0) return hip_check(c, "table grid");
+  HIP_TRY(c, hipMemcpy(&c->tools_dev[tool_id], &t, sizeof(ToolDev), hipMemcpyHostToDevice));
+  c->graph_stale = true;
+  return regrid(c, s);
+}
+
 int af_set_tool_kernels(af_ctx *c, int32_t tool_id, const af_tool *tool, int32_t K,
                         const double *rot, void *stream) {
   if (!c) return AF_EINVAL;
@@ -514,32 +607,11 @@ int af_set_tool_kernels(af_ctx *c, int32_t tool_id, const af_tool *tool, int32_t
   const double fr[3] = {0.6, 1.25, 2.25};
   for (int j = 0; j < 3; ++j) tg.lam[j] = (fr[j] * c->tau) / v;
 
-  ToolDev &t = c->tools[tool_id];
-  if (t.entries) {
-    HIP_TRY(c, hipStreamSynchronize(s));
-    dev_free(c, t.entries, c->tool_bytes[tool_id]);
-    dev_free(c, t.begin, sizeof(uint32_t) * (t.K + 1));
-    dev_free(c, t.rot, sizeof(double) * 9 * t.K);
-    dev_free(c, t.label, c->cfg.max_points);
-    dev_free(c, t.first_free, sizeof(int16_t) * c->cfg.max_points);
-    dev_free(c, t.counters, sizeof(ScoreCounters));
-    dev_free(c, t.far_begin, sizeof(uint32_t) * t.K);
-    dev_free(c, t.same, sizeof(uint64_t) * ((t.K + 63) / 64));
-    dev_free(c, t.xent, sizeof(uint2) * std::max<int64_t>(1, t.n_entries));
-    if (t.rent) dev_free(c, t.rent, sizeof(uint32_t) * std::max<int64_t>(1, t.n_entries));
-    if (c->own_mask[tool_id]) {
-      const int64_t mw = (t.K + 63) / 64;
-      dev_free(c, t.mask, sizeof(uint64_t) * c->cfg.max_points * mw);
-      dev_free(c, t.nearp, sizeof(uint64_t) * c->cfg.max_points * 2 * mw);
-      c->own_mask[tool_id] = 0;
-    }
-    dev_free(c, t.c4begin, sizeof(uint32_t) * (t.K + 1));
-    dev_free(c, t.c4flag, t.K);
-    dev_free(c, t.c4entries, sizeof(uint32_t) * std::max<int64_t>(1, t.n_c4entries));
-    memset(&t, 0, sizeof(t));
-  }
+  int rc = tool_release(c, tool_id, s);
+  if (rc != AF_OK) return rc;
   ToolDev nt;
   memset(&nt, 0, sizeof(nt));
+  nt.K = K;
   uint32_t *counts = nullptr;
   int32_t *err = nullptr;
   ALLOC(c, nt.rot, 9 * (int64_t)K);
@@ -571,70 +643,122 @@ int af_set_tool_kernels(af_ctx *c, int32_t tool_id, const af_tool *tool, int32_t
     dev_free(c, err, sizeof(int32_t));
     dev_free(c, nt.rot, sizeof(double) * 9 * K);
     dev_free(c, nt.begin, sizeof(uint32_t) * (K + 1));
+    dev_free(c, nt.same, sizeof(uint64_t) * ((K + 63) / 64));
     return fail(c, AF_EINVAL, "tool too large for the voxel size (%s)",
                 herr & 2 ? "more than 16384 entries in one class" : "offset beyond 511 voxels");
   }
   ALLOC(c, nt.entries, total);
-  ALLOC(c, nt.label, c->cfg.max_points);
-  ALLOC(c, nt.first_free, c->cfg.max_points);
-  ALLOC(c, nt.counters, 1);
   if (launch_table_build(tg, K, nt.rot, counts, nt.begin, err, nt.entries, 1, s) != 0)
     return hip_check(c, "table fill");
-  HIP_TRY(c, hipMemsetAsync(nt.label, 0, c->cfg.max_points, s));
-  HIP_TRY(c, hipMemsetAsync(nt.counters, 0, sizeof(ScoreCounters), s));
   HIP_TRY(c, hipMemcpyAsync(&herr, err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  uint32_t *ccounts = nullptr;
-  ALLOC(c, nt.far_begin, K);
-  ALLOC(c, ccounts, K);
-  // coarse corridor lists over 4^3 cells
-  ALLOC(c, nt.c4begin, K + 1);
-  ALLOC(c, nt.c4flag, K);
-  if (launch_table_coarse(K, nt.begin, counts, nt.entries, nt.far_begin, ccounts, nt.c4begin,
-                          nullptr, nt.c4flag, 0, 2, s) != 0)
-    return hip_check(c, "coarse4 count");
-  uint32_t c4total = 0;
-  HIP_TRY(c, hipMemcpyAsync(&c4total, nt.c4begin + K, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   HIP_TRY(c, hipStreamSynchronize(s));
-  ALLOC(c, nt.c4entries, std::max<uint32_t>(1u, c4total));
-  if (launch_table_coarse(K, nt.begin, counts, nt.entries, nt.far_begin, ccounts, nt.c4begin,
-                          nt.c4entries, nt.c4flag, 1, 2, s) != 0)
-    return hip_check(c, "coarse4 fill");
-  nt.n_c4entries = c4total;
-  HIP_TRY(c, hipStreamSynchronize(s));
-  dev_free(c, ccounts, sizeof(uint32_t) * K);
-  dev_free(c, counts, sizeof(uint32_t) * 2 * K);
   dev_free(c, err, sizeof(int32_t));
   if (herr) return fail(c, AF_EINVAL, "tool table build failed (%d)", herr);
-  {
-    std::vector<uint32_t> he(total);
-    HIP_TRY(c, hipMemcpy(he.data(), nt.entries, sizeof(uint32_t) * total, hipMemcpyDeviceToHost));
-    int32_t reach = 0;
-    for (uint32_t e : he)
-      reach = std::max({reach, std::abs(entry_x(e)), std::abs(entry_y(e)), std::abs(entry_z(e))});
-    nt.reach = reach;
-    if (reach <= 255) {
-      std::vector<uint32_t> rel(total);
-      for (uint32_t j = 0; j < total; ++j) {
-        const uint32_t e = he[j];
-        rel[j] = (uint32_t)(entry_x(e) + 256) | ((uint32_t)(entry_y(e) + 256) << 10) |
-                 ((uint32_t)(entry_z(e) + 256) << 20) | ((uint32_t)entry_cls(e) << 30);
-      }
-      ALLOC(c, nt.rent, std::max<int64_t>(1, total));
-      HIP_TRY(c, hipMemcpy(nt.rent, rel.data(), sizeof(uint32_t) * total, hipMemcpyHostToDevice));
-    }
+  rc = tool_finish(c, tool_id, nt, counts, total, s);
+  dev_free(c, counts, sizeof(uint32_t) * 2 * K);
+  return rc;
+}
+
+int af_set_tool_table(af_ctx *c, int32_t tool_id, const af_kernel_table *tab, void *stream) {
+  if (!c) return AF_EINVAL;
+  if (c->graph_dirty) {
+    const int rc = graph_settle(c);
+    if (rc != AF_OK) return rc;
   }
-  nt.n_entries = total;
-  ALLOC(c, nt.xent, std::max<int64_t>(1, total));
+  if (tool_id < 0 || tool_id >= c->cfg.max_tools)
+    return fail(c, AF_EINVAL, "tool id %d outside [0, %d)", tool_id, c->cfg.max_tools);
+  if (!tab || !tab->dir || !tab->offset_begin || tab->K < 1 || tab->K > c->cfg.max_orientations)
+    return fail(c, AF_EINVAL, "bad table or K");
+  const int32_t K = tab->K;
+  if (tab->offset_begin[0] != 0) return fail(c, AF_EINVAL, "offset_begin[0] must be 0");
+  for (int32_t k = 0; k < K; ++k)
+    if (tab->offset_begin[k + 1] < tab->offset_begin[k])
+      return fail(c, AF_EINVAL, "offset_begin decreases at orientation %d", k);
+  const uint32_t n_in = tab->offset_begin[K];
+  if (n_in > 0 && (!tab->off || !tab->cls)) return fail(c, AF_EINVAL, "missing offsets or classes");
+  for (int32_t k = 0; k < K; ++k) {
+    const double *d = tab->dir + 3 * k;
+    const double n2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    if (!(fabs(sqrt(n2) - 1.0) <= 1e-9))
+      return fail(c, AF_EINVAL, "direction %d is not a unit vector", k);
+  }
+  // canonical order per orientation: the three NEAR entries as given, then
+  // BODY and FAR each sorted by (|o|^2, z, y, x)
+  std::vector<uint32_t> entries;
+  std::vector<uint32_t> begin(K + 1), counts(2 * (size_t)K);
+  std::vector<std::array<int, 3>> near3((size_t)K * 3);
+  entries.reserve(n_in);
+  for (int32_t k = 0; k < K; ++k) {
+    begin[k] = (uint32_t)entries.size();
+    std::vector<std::array<int, 4>> body, far_;
+    int nn = 0;
+    for (uint32_t e = tab->offset_begin[k]; e < tab->offset_begin[k + 1]; ++e) {
+      const int ox = tab->off[3 * (size_t)e], oy = tab->off[3 * (size_t)e + 1],
+                oz = tab->off[3 * (size_t)e + 2];
+      const int cl = tab->cls[e];
+      if (cl != AF_CLS_BODY && cl != AF_CLS_NEAR && cl != AF_CLS_FAR)
+        return fail(c, AF_EINVAL, "entry %u of orientation %d has class %d", e, k, cl);
+      if (std::abs(ox) > 511 || std::abs(oy) > 511 || std::abs(oz) > 511)
+        return fail(c, AF_EINVAL, "entry %u of orientation %d is beyond 511 voxels", e, k);
+      if (cl == AF_CLS_NEAR) {
+        if (nn >= 3) return fail(c, AF_EINVAL, "orientation %d has more than 3 NEAR entries", k);
+        near3[3 * (size_t)k + nn] = {ox, oy, oz};
+        entries.push_back(pack_entry(ox, oy, oz, AF_CLS_NEAR));
+        ++nn;
+      } else {
+        (cl == AF_CLS_BODY ? body : far_).push_back({ox * ox + oy * oy + oz * oz, oz, oy, ox});
+      }
+    }
+    if (nn != 3) return fail(c, AF_EINVAL, "orientation %d has %d NEAR entries (3 needed)", k, nn);
+    for (auto *grp : {&body, &far_}) {
+      std::sort(grp->begin(), grp->end());
+      if (std::adjacent_find(grp->begin(), grp->end()) != grp->end())
+        return fail(c, AF_EINVAL, "orientation %d lists an offset twice in one class", k);
+      if ((int64_t)grp->size() > kTableMaxClass)
+        return fail(c, AF_EINVAL, "orientation %d has more than %d entries in one class", k,
+                    kTableMaxClass);
+      const int cl = grp == &body ? AF_CLS_BODY : AF_CLS_FAR;
+      for (const auto &q : *grp) entries.push_back(pack_entry(q[3], q[2], q[1], cl));
+    }
+    counts[2 * (size_t)k] = (uint32_t)body.size();
+    counts[2 * (size_t)k + 1] = (uint32_t)far_.size();
+  }
+  begin[K] = (uint32_t)entries.size();
+  // orientations sharing their predecessor's direction and arm samples
+  std::vector<uint64_t> same((K + 63) / 64, 0ull);
+  for (int32_t k = 1; k < K; ++k) {
+    const double *d = tab->dir + 3 * k, *e = tab->dir + 3 * (k - 1);
+    bool eq = d[0] == e[0] && d[1] == e[1] && d[2] == e[2];
+    for (int j = 0; j < 3 && eq; ++j) eq = near3[3 * (size_t)k + j] == near3[3 * (size_t)(k - 1) + j];
+    if (eq) same[k >> 6] |= 1ull << (k & 63);
+  }
+  // orientation frames for the candidate filters: column 0 is the direction
+  std::vector<double> rot(9 * (size_t)K, 0.0);
+  for (int32_t k = 0; k < K; ++k)
+    for (int i = 0; i < 3; ++i) rot[9 * (size_t)k + 3 * i] = tab->dir[3 * k + i];
+
+  hipStream_t s = (hipStream_t)stream;
+  int rc = tool_release(c, tool_id, s);
+  if (rc != AF_OK) return rc;
+  ToolDev nt;
+  memset(&nt, 0, sizeof(nt));
   nt.K = K;
-  nt.mask = c->mask;
-  nt.nearp = c->nearp;
-  t = nt;
-  c->tool_bytes[tool_id] = sizeof(uint32_t) * (int64_t)total;
-  c->last_stream = s;
-  if (c->grid_bricks > 0 && launch_table_grid(t, c->grid, s) != 0) return hip_check(c, "table grid");
-  HIP_TRY(c, hipMemcpy(&c->tools_dev[tool_id], &t, sizeof(ToolDev), hipMemcpyHostToDevice));
-  c->graph_stale = true;
-  return regrid(c, s);
+  const uint32_t total = begin[K];
+  uint32_t *dcounts = nullptr;
+  ALLOC(c, nt.rot, 9 * (int64_t)K);
+  ALLOC(c, nt.begin, K + 1);
+  ALLOC(c, nt.same, (K + 63) / 64);
+  ALLOC(c, nt.entries, std::max<uint32_t>(1u, total));
+  ALLOC(c, dcounts, 2 * (int64_t)K);
+  HIP_TRY(c, hipMemcpy(nt.rot, rot.data(), sizeof(double) * rot.size(), hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(nt.begin, begin.data(), sizeof(uint32_t) * begin.size(), hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(nt.same, same.data(), sizeof(uint64_t) * same.size(), hipMemcpyHostToDevice));
+  if (total > 0)
+    HIP_TRY(c, hipMemcpy(nt.entries, entries.data(), sizeof(uint32_t) * total, hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(dcounts, counts.data(), sizeof(uint32_t) * counts.size(), hipMemcpyHostToDevice));
+  rc = tool_finish(c, tool_id, nt, dcounts, total, s);
+  dev_free(c, dcounts, sizeof(uint32_t) * 2 * K);
+  return rc;
 }
 
 int af_integrate_frame(af_ctx *c, const float *xyz, int64_t n, const float origin[3],
@@ -1444,6 +1568,27 @@ int af_read_point_debug(af_ctx *c, int32_t tool_id, int64_t first, int64_t count
   if (mask)
     HIP_TRY(c, hipMemcpy(mask, t.mask + first * mw, sizeof(uint64_t) * mw * m, hipMemcpyDeviceToHost));
   return AF_OK;
+}
+
+int af_pca_axes(const int32_t *moments, int64_t n, int64_t *axes, int32_t *has) {
+  if (n < 0 || (n > 0 && (!moments || !axes || !has))) return AF_EINVAL;
+  if (n == 0) return AF_OK;
+  int32_t *dm = nullptr, *dh = nullptr;
+  int64_t *da = nullptr;
+  hipError_t e = hipMalloc((void **)&dm, sizeof(int32_t) * 10 * n);
+  if (e == hipSuccess) e = hipMalloc((void **)&da, sizeof(int64_t) * 3 * n);
+  if (e == hipSuccess) e = hipMalloc((void **)&dh, sizeof(int32_t) * n);
+  if (e == hipSuccess) e = hipMemcpy(dm, moments, sizeof(int32_t) * 10 * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    launch_pca_axes(dm, n, da, dh, nullptr);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpy(axes, da, sizeof(int64_t) * 3 * n, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(has, dh, sizeof(int32_t) * n, hipMemcpyDeviceToHost);
+  hipFree(dm);
+  hipFree(da);
+  hipFree(dh);
+  return e == hipSuccess ? AF_OK : AF_EDEVICE;
 }
 
 int af_frame_stats_get(af_ctx *c, af_frame_stats *st) {

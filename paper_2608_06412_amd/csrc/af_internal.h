@@ -373,6 +373,8 @@ int launch_table_coarse(int32_t K, const uint32_t *begin, const uint32_t *counts
 // is then only an upper bound that sizes the launch
 void launch_normals(const Params &p, MapDev m, PointsDev pts, GridDev g,
                     int64_t n_points, hipStream_t s, bool dev_n = false);
+void launch_pca_axes(const int32_t *mom, int64_t n, int64_t *axes, int32_t *has,
+                     hipStream_t s);
 void launch_mask(const Params &p, PointsDev pts, ToolDev t, GridDev g, int64_t n_points,
                  hipStream_t s, bool dev_n = false);
 // Up to kMultiTools tools scored in one launch: their ids in the context's

@@ -18,8 +18,9 @@ constexpr int kWaves = kThreads / 64;
 // Neighbour window [-3, 3]^3 as (dx, dy, dz, |d|^2), sorted by |d|^2.
 __constant__ int8_t c_nb[343 * 4];
 
-// The same window as a compile-time table, shell by shell (order inside a
-// shell is irrelevant: the kNN keeps or drops whole shells).
+// The same window as a compile-time table, shell by shell, and inside a
+// shell in ascending (dz, dy, dx) order: the order in which the kNN takes
+// voxels tied at the same distance.
 struct NbOrder {
   int8_t e[343][4];
 };
@@ -61,9 +62,9 @@ struct NbSums {
   int sx[3], sxx[6];
 };
 template <int J>
-__device__ inline void nb_entry(const uint64_t (&slice)[7], NbSums &a) {
+__device__ inline void nb_entry(const uint64_t (&slice)[7], NbSums &a, int k) {
   constexpr int dx = kNbOrder.e[J][0], dy = kNbOrder.e[J][1], dz = kNbOrder.e[J][2];
-  const int h = (int)((slice[dz + 3] >> (7 * (dy + 3) + dx + 3)) & 1u);
+  const int h = (int)((slice[dz + 3] >> (7 * (dy + 3) + dx + 3)) & 1u) & (a.cnt < k ? 1 : 0);
   a.cnt += h;
   a.sx[0] += dx * h; a.sx[1] += dy * h; a.sx[2] += dz * h;
   a.sxx[0] += dx * dx * h; a.sxx[1] += dx * dy * h; a.sxx[2] += dx * dz * h;
@@ -71,14 +72,15 @@ __device__ inline void nb_entry(const uint64_t (&slice)[7], NbSums &a) {
 }
 template <int Lo, int... I>
 __device__ inline void nb_range(std::integer_sequence<int, I...>, const uint64_t (&slice)[7],
-                                NbSums &a) {
-  (nb_entry<Lo + I>(slice, a), ...);
+                                NbSums &a, int k) {
+  (nb_entry<Lo + I>(slice, a, k), ...);
 }
-// Shells S, S+1, ... until one ends with at least k voxels found.
+// Shells S, S+1, ... until k voxels are taken (the last shell's voxels in
+// table order, so ties at the k-th distance go to the lowest (dz, dy, dx)).
 template <int S>
 __device__ inline void nb_shells(const uint64_t (&slice)[7], NbSums &a, int k) {
   constexpr int lo = kNbShells.start[S], hi = kNbShells.start[S + 1];
-  nb_range<lo>(std::make_integer_sequence<int, hi - lo>{}, slice, a);
+  nb_range<lo>(std::make_integer_sequence<int, hi - lo>{}, slice, a, k);
   if constexpr (S + 1 < kNbShells.n) {
     if (a.cnt < k) nb_shells<S + 1>(slice, a, k);
   }
@@ -109,20 +111,72 @@ __device__ inline uint32_t code_at(const GridDev &g, int x, int y, int z) {
   return (g.pred[b * 32 + (lin >> 4)] >> (2 * (lin & 15))) & 3u;
 }
 
-__device__ inline int64_t round_shift(int64_t x, int sh) {
-  if (sh <= 0) return x;
-  int64_t m = x < 0 ? -x : x;
-  int64_t q = (m + (1LL << (sh - 1))) >> sh;
-  return x < 0 ? -q : q;
+// Least principal axis of a neighbourhood from its moments: cnt voxels, sum
+// d, sum dd^T (00 01 02 11 12 22).  The scatter M = cnt sum(dd^T) -
+// (sum d)(sum d)^T is exact in integers; its eigenvectors come from cyclic
+// Jacobi in fp64 (Golub & Van Loan's cyclic Jacobi method: eight sweeps over
+// the pairs (0,1), (0,2), (1,2), a pair with a zero off-diagonal entry
+// skipped, each rotation the 2x2 symmetric Schur decomposition with
+// t = sign(theta) / (|theta| + sqrt(theta^2 + 1))), and the axis is the
+// rotation product's column at the smallest diagonal entry (ties: lowest
+// index), rounded to fixed point 2^30.  Only IEEE basic operations, with
+// contraction off, in a fixed order, so the result is the same on any IEEE
+// machine.  Returns 0 (no axis) with fewer than 3 voxels.
+__device__ inline int pca_axis(int cnt, const int32_t sx[3], const int32_t sxx[6],
+                               int64_t axis[3]) {
+  axis[0] = axis[1] = axis[2] = 0;
+  if (cnt < 3) return 0;
+  const int64_t c = cnt;
+  double a00 = (double)(c * sxx[0] - (int64_t)sx[0] * sx[0]);
+  double a01 = (double)(c * sxx[1] - (int64_t)sx[0] * sx[1]);
+  double a02 = (double)(c * sxx[2] - (int64_t)sx[0] * sx[2]);
+  double a11 = (double)(c * sxx[3] - (int64_t)sx[1] * sx[1]);
+  double a12 = (double)(c * sxx[4] - (int64_t)sx[1] * sx[2]);
+  double a22 = (double)(c * sxx[5] - (int64_t)sx[2] * sx[2]);
+  double v[3][3] = {{1.0, 0.0, 0.0}, {0.0, 1.0, 0.0}, {0.0, 0.0, 1.0}};
+  // one plane rotation on (p, q) with r the third index; app, aqq, apq,
+  // arp, arq name the entries of A it reads and writes
+  auto rotate = [&](double &app, double &aqq, double &apq, double &arp, double &arq, int p,
+                    int q) {
+    const double b = apq;
+    if (b == 0.0) return;
+    const double theta = (aqq - app) / (2.0 * b);
+    double t = 1.0 / (fabs(theta) + sqrt(theta * theta + 1.0));
+    if (theta < 0.0) t = -t;
+    const double cs = 1.0 / sqrt(t * t + 1.0);
+    const double sn = t * cs;
+    app = app - t * b;
+    aqq = aqq + t * b;
+    apq = 0.0;
+    const double rp = arp, rq = arq;
+    arp = cs * rp - sn * rq;
+    arq = sn * rp + cs * rq;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double vip = v[i][p], viq = v[i][q];
+      v[i][p] = cs * vip - sn * viq;
+      v[i][q] = sn * vip + cs * viq;
+    }
+  };
+  for (int sweep = 0; sweep < 8; ++sweep) {
+    rotate(a00, a11, a01, a02, a12, 0, 1);   // r = 2: a_20 = a02, a_21 = a12
+    rotate(a00, a22, a02, a01, a12, 0, 2);   // r = 1: a_10 = a01, a_12 = a12
+    rotate(a11, a22, a12, a01, a02, 1, 2);   // r = 0: a_01 = a01, a_02 = a02
+  }
+  int best = 0;
+  double dmin = a00;
+  if (a11 < dmin) { best = 1; dmin = a11; }
+  if (a22 < dmin) best = 2;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const double e = best == 0 ? v[i][0] : (best == 1 ? v[i][1] : v[i][2]);
+    axis[i] = (int64_t)__builtin_rint(e * 1073741824.0);
+  }
+  return 1;
 }
 
-__device__ inline int bit_length(uint64_t m) { return m ? 64 - __clzll((long long)m) : 0; }
-
 // The least principal axis of point s's neighbourhood (before orientation):
-// returns 1 and the axis, or 0 when there is none (fewer than 3 neighbours,
-// or a degenerate scatter).  B and its powers are symmetric, so a squaring
-// forms six entries; every entry is at most 2^28 in magnitude after the
-// renormalisation, so products take 32-bit operands and 64-bit results.
+// returns 1 and the axis, or 0 when there is none (fewer than 3 neighbours).
 __device__ inline int normal_axis(const Params &p, const GridDev &g, const int32_t s[3],
                                   int64_t axis[3]) {
   // the point's brick and, when it is at least one brick inside the grid,
@@ -187,56 +241,16 @@ __device__ inline int normal_axis(const Params &p, const GridDev &g, const int32
     for (int c = 0; c < 3; ++c) sx[c] = a.sx[c];
     for (int c = 0; c < 6; ++c) sxx[c] = a.sxx[c];
   } else {
-    int last = -1;
-    for (int j = 0; j < 343; ++j) {
-      int d2 = c_nb[4 * j + 3];
-      if (cnt >= p.knn_k && d2 != last) break;
+    for (int j = 0; j < 343 && cnt < p.knn_k; ++j) {
       int dx = c_nb[4 * j], dy = c_nb[4 * j + 1], dz = c_nb[4 * j + 2];
       if (!surf_bit(g, s[0] + dx, s[1] + dy, s[2] + dz)) continue;
       ++cnt;
-      last = d2;
       sx[0] += dx; sx[1] += dy; sx[2] += dz;
       sxx[0] += dx * dx; sxx[1] += dx * dy; sxx[2] += dx * dz;
       sxx[3] += dy * dy; sxx[4] += dy * dz; sxx[5] += dz * dz;
     }
   }
-  if (cnt < 3) return 0;
-  // M = cnt sxx - sx sx^T; B = tr(M) I - M, entries 00 01 02 11 12 22
-  const int32_t m00 = cnt * sxx[0] - sx[0] * sx[0], m01 = cnt * sxx[1] - sx[0] * sx[1];
-  const int32_t m02 = cnt * sxx[2] - sx[0] * sx[2], m11 = cnt * sxx[3] - sx[1] * sx[1];
-  const int32_t m12 = cnt * sxx[4] - sx[1] * sx[2], m22 = cnt * sxx[5] - sx[2] * sx[2];
-  const int32_t tr = m00 + m11 + m22;
-  int32_t e[6] = {tr - m00, -m01, -m02, tr - m11, -m12, tr - m22};
-  for (int it = 0; it < 8; ++it) {
-    auto mul = [](int32_t u, int32_t v) { return (int64_t)u * (int64_t)v; };
-    int64_t c[6];
-    c[0] = mul(e[0], e[0]) + mul(e[1], e[1]) + mul(e[2], e[2]);
-    c[1] = mul(e[0], e[1]) + mul(e[1], e[3]) + mul(e[2], e[4]);
-    c[2] = mul(e[0], e[2]) + mul(e[1], e[4]) + mul(e[2], e[5]);
-    c[3] = mul(e[1], e[1]) + mul(e[3], e[3]) + mul(e[4], e[4]);
-    c[4] = mul(e[1], e[2]) + mul(e[3], e[4]) + mul(e[4], e[5]);
-    c[5] = mul(e[2], e[2]) + mul(e[4], e[4]) + mul(e[5], e[5]);
-    uint64_t mx = 0;
-    for (int k = 0; k < 6; ++k) {
-      const uint64_t mag = (uint64_t)(c[k] < 0 ? -c[k] : c[k]);
-      mx = mag > mx ? mag : mx;
-    }
-    const int sh = bit_length(mx) - 28;
-    for (int k = 0; k < 6; ++k) e[k] = (int32_t)round_shift(c[k], sh);
-  }
-  const int64_t B[3][3] = {{e[0], e[1], e[2]}, {e[1], e[3], e[4]}, {e[2], e[4], e[5]}};
-  int best = 0;
-  int64_t bn = -1;
-  for (int c = 0; c < 3; ++c) {
-    int64_t nrm = B[0][c] * B[0][c] + B[1][c] * B[1][c] + B[2][c] * B[2][c];
-    if (nrm > bn) {
-      bn = nrm;
-      best = c;
-    }
-  }
-  if (bn <= 0) return 0;
-  for (int a = 0; a < 3; ++a) axis[a] = B[a][best];
-  return 1;
+  return pca_axis(cnt, sx, sxx, axis);
 }
 
 // Orient the axis towards the point's mean sensor position and store it.
@@ -259,10 +273,8 @@ __device__ inline void store_normal(const PointsDev &pts, int64_t i, const int32
 }
 
 // Least principal axis of the k nearest surface voxels (ties at the k-th
-// distance included), oriented towards the mean sensor position.  The
-// scatter matrix M = n sum(dd^T) - (sum d)(sum d)^T is exact; the dominant
-// eigenvector of B = tr(M) I - M is read from B^256 (eight squarings with
-// 28-bit renormalisation by rounded shifts) as its largest-norm column.
+// distance taken in (dz, dy, dx) order), oriented towards the mean sensor
+// position (Section 3.4 "Approach directions").
 __global__ void __launch_bounds__(kThreads)
 k_normals(Params p, MapDev m, PointsDev pts, GridDev g, int64_t n) {
   // n < 0: the point count on the device (recorded graphs, point lists)
@@ -1558,6 +1570,20 @@ constexpr int kNumVariants = (int)(sizeof(kVariants) / sizeof(kVariants[0]));
 int g_resident[kNumVariants];   // workgroups per CU, from the occupancy query
 int g_num_cu = 0;
 
+// Test hook: the PCA step alone, on caller-given moments [n][10] (cnt, sum
+// d [3], sum dd^T [6]).
+__global__ void __launch_bounds__(kThreads)
+k_pca_axes(const int32_t *mom, int64_t n, int64_t *axes, int32_t *has) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  const int32_t *m = mom + 10 * i;
+  const int32_t sx[3] = {m[1], m[2], m[3]};
+  const int32_t sxx[6] = {m[4], m[5], m[6], m[7], m[8], m[9]};
+  int64_t ax[3];
+  has[i] = pca_axis(m[0], sx, sxx, ax);
+  for (int a = 0; a < 3; ++a) axes[3 * i + a] = ax[a];
+}
+
 __global__ void k_zero(unsigned *w) { *w = 0u; }
 
 bool g_tables_ready = false;
@@ -1613,6 +1639,13 @@ void launch_normals(const Params &p, MapDev m, PointsDev pts, GridDev g, int64_t
   if (n <= 0) return;
   hipLaunchKernelGGL(k_normals, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads),
                      0, s, p, m, pts, g, dev_n ? (int64_t)-1 : n);
+}
+
+void launch_pca_axes(const int32_t *mom, int64_t n, int64_t *axes, int32_t *has,
+                     hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_pca_axes, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads),
+                     0, s, mom, n, axes, has);
 }
 
 void launch_mask(const Params &p, PointsDev pts, ToolDev t, GridDev g, int64_t n,

@@ -306,6 +306,26 @@ def tool_samples(tool: Tool, n_stations: int = 16) -> np.ndarray:
     return np.array([[x, y, z] for x in xs for y, z in rim], np.float32)
 
 
+def pencil_points(tip_length=0.04, radius=0.02, length=0.12, corridor=0.40,
+                  spacing=0.005):
+    """A pencil-shaped tool as point samples of its 3D model in its local
+    frame (approach axis +x, tip at the origin): a cone from the tip to a
+    disc of `radius` at x = tip_length, then a cylindrical shaft to x =
+    length (the body), then the approach corridor of the shaft's
+    cross-section to x = length + corridor.  Samples lie on a regular grid of
+    `spacing` inside each solid.  Returns (body [M, 3], corridor [N, 3]),
+    float64."""
+    r = np.arange(-radius, radius + 1e-12, spacing)
+    yz = np.array([(y, z) for y in r for z in r if y * y + z * z <= radius * radius + 1e-12])
+    body, far = [], []
+    for x in np.arange(0.0, length + corridor + 1e-12, spacing):
+        rad = radius * min(1.0, x / tip_length)
+        sel = yz[(yz ** 2).sum(1) <= rad * rad + 1e-12]
+        pts = np.column_stack([np.full(len(sel), x), sel])
+        (body if x <= length + 1e-12 else far).append(pts)
+    return np.concatenate(body), np.concatenate(far)
+
+
 def quaternion_towards(dirs: np.ndarray) -> np.ndarray:
     """Unit quaternions (w, x, y, z) of the shortest rotations taking the
     tool axis +x to each direction (the antipode turns about +z)."""
