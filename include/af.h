@@ -384,6 +384,25 @@ int af_smooth_refine(af_ctx *ctx, const float *p, int64_t n_points, const float 
                      int32_t steps, float eta, float max_step, float *q_out, float *s_out,
                      void *stream);
 
+/* af_smooth_eval for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * same arguments, same kernels and bit-identical outputs, but its scratch
+ * (the map's per-voxel values, brick tables, 9^3 apron bricks and work
+ * counters) lives in a static 64 MiB device array that the library holds
+ * on each GPU it runs on until the process ends; the call performs no
+ * hipMalloc/hipFree.  The map must fit: about 2 KB per allocated block plus
+ * 8 bytes per brick of the grid plus 2.9 KB per apron (at most 8 per block);
+ * a larger map is refused with AF_ENOMEM and a message giving the need.
+ * The grid must already cover the map (AF_EINVAL otherwise; every
+ * af_integrate_frame keeps it so).  The array is shared by every call on one
+ * GPU and keeps the last call's contents, so calls on one GPU must not
+ * overlap in time (different streams or threads would race on it); each
+ * call clears what it needs cleared.  The current device must be the
+ * context's (AF_EINVAL).  Asynchronous on `stream`. */
+int af_smooth_eval_static(af_ctx *ctx, const float *p, const float *q, int64_t n,
+                          const float *samples, int32_t M, float c, float tau_s,
+                          const float *grad_s, float *s_out, float *dq, float *dp, void *stream);
+
 /* Incremental mode (Section 3.5, "Incremental Updates and Confidence"):
  * instead of re-testing every point each frame, a per-point state is kept
  * and a point is re-evaluated only when (i) the TSDF at its voxel moved by

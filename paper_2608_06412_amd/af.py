@@ -137,6 +137,11 @@ SIGNATURES = {
                                       ctypes.c_float, ctypes.c_float, ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                       ctypes.c_void_p]),
+    "af_smooth_eval_static": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_int64, ctypes.c_void_p, ctypes.c_int32,
+                                             ctypes.c_float, ctypes.c_float, ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_void_p]),
     "af_smooth_refine": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                         ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                         ctypes.c_int32, ctypes.c_float, ctypes.c_float,
@@ -497,6 +502,24 @@ class Context:
                                              int(samples.shape[0]), float(c), float(tau_s),
                                              ptr(grad_s), ptr(s), ptr(dq), ptr(dp),
                                              _stream_handle(stream)))
+
+    def smooth_eval_static(self, p, q, samples, c=0.01, tau_s=0.005, grad_s=None, s=None,
+                           dq=None, dp=None, stream=None):
+        """smooth_eval through af_smooth_eval_static: the library allocates
+        nothing during the call (its scratch is a static device array)."""
+        n = int(p.shape[0])
+        _check_f32(p, (n, 3), "p")
+        _check_f32(q, (n, 4), "q")
+        _check_f32(samples, (samples.shape[0], 3), "samples")
+        for t, shp, name in ((grad_s, (n,), "grad_s"), (s, (n,), "s"), (dq, (n, 4), "dq"),
+                             (dp, (n, 3), "dp")):
+            if t is not None:
+                _check_f32(t, shp, name)
+        ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+        self._check(self._lib.af_smooth_eval_static(self.h, ptr(p), ptr(q), n, ptr(samples),
+                                                    int(samples.shape[0]), float(c),
+                                                    float(tau_s), ptr(grad_s), ptr(s), ptr(dq),
+                                                    ptr(dp), _stream_handle(stream)))
 
     def smooth_refine(self, p, q0, samples, steps=20, eta=1e-3, max_step=0.05, c=0.01,
                       tau_s=0.005, stream=None):

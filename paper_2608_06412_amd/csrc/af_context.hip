@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <array>
+#include <mutex>
 #include <cmath>
 #include <string>
 #include <vector>
@@ -189,15 +190,22 @@ int32_t grid_margin_need(const af_ctx *c) {
 // Grow the brick grid so that it covers block box [lo, hi] with the margin
 // above; new grids are filled with "unknown" (the caller rebuilds them from
 // every block) and every tool's grid-relative table is recomputed.
-int ensure_grid(af_ctx *c, hipStream_t s, bool &rebuilt) {
-  rebuilt = false;
-  if (!c->have_bbox) return AF_OK;
-  GridDev &g = c->grid;
+// Whether the grid covers the block box with the margin every tool needs.
+static bool grid_covers(const af_ctx *c) {
+  if (!c->have_bbox) return true;
+  const GridDev &g = c->grid;
   const int32_t need = grid_margin_need(c);
   bool inside = c->grid_bricks > 0;
   for (int a = 0; a < 3 && inside; ++a)
     inside = c->bbox_lo[a] - g.g0[a] >= need && g.g0[a] + g.gd[a] - 1 - c->bbox_hi[a] >= need;
-  if (inside) return AF_OK;
+  return inside;
+}
+
+int ensure_grid(af_ctx *c, hipStream_t s, bool &rebuilt) {
+  rebuilt = false;
+  if (grid_covers(c)) return AF_OK;
+  const int32_t need = grid_margin_need(c);
+  GridDev &g = c->grid;
   GridDev ng;
   memset(&ng, 0, sizeof(ng));
   int64_t nb = 1;
@@ -1114,6 +1122,19 @@ int af_graph_sync(af_ctx *c) {
   return graph_settle(c);
 }
 
+// Build the smoothed score's field in buffers b (enqueued on s).
+static void smooth_build(af_ctx *c, const SmoothBuffers &b, hipStream_t s, SmoothField &f) {
+  const float tau = (float)((double)c->p.tau_u / c->p.scale);
+  launch_smooth_prepare(c->p, c->map, c->n_blocks, c->grid, c->grid_bricks, tau, b, s);
+  f.T9 = b.T9;
+  f.bid9 = b.bid9;
+  for (int a = 0; a < 3; ++a) {
+    f.g0[a] = c->grid.g0[a];
+    f.gd[a] = c->grid_bricks > 0 ? c->grid.gd[a] : 0;
+  }
+  f.tau = tau;
+}
+
 // TSDF values and the brick table for the smoothed score, rebuilt from the
 // current map (a few tens of microseconds; the map may change between calls).
 static int smooth_prepare(af_ctx *c, hipStream_t s, SmoothField &f) {
@@ -1158,15 +1179,7 @@ static int smooth_prepare(af_ctx *c, hipStream_t s, SmoothField &f) {
     if (!b.count) ALLOC(c, b.count, 1);
     if (!b.work) ALLOC(c, b.work, 8);   // one counter per XCD
   }
-  const float tau = (float)((double)c->p.tau_u / c->p.scale);
-  launch_smooth_prepare(c->p, c->map, c->n_blocks, c->grid, c->grid_bricks, tau, b, s);
-  f.T9 = b.T9;
-  f.bid9 = b.bid9;
-  for (int a = 0; a < 3; ++a) {
-    f.g0[a] = c->grid.g0[a];
-    f.gd[a] = c->grid_bricks > 0 ? c->grid.gd[a] : 0;
-  }
-  f.tau = tau;
+  smooth_build(c, b, s, f);
   return hip_check(c, "smooth prepare");
 }
 
@@ -1212,6 +1225,95 @@ int af_smooth_refine(af_ctx *c, const float *p, int64_t n_points, const float *q
   if (c->timing) timing_pair(c, ST_K_SMOOTH, t0, t1);
   c->last_stream = s;
   return hip_check(c, "smooth refine");
+}
+
+// ---------------------------------------------------------------------------
+// The no-allocation form of af_smooth_eval.  Its scratch (the per-voxel values,
+// the brick tables, the apron bricks and the work counters that af_smooth_eval
+// keeps in context buffers grown on demand) lives in this file-scope device
+// array instead: each GPU the library runs on holds one copy, at its own
+// address, until the process ends.  In host code `scratch` names a host-side
+// stand-in, so the device address is looked up once per device with
+// hipGetSymbolAddress and only that address is ever passed to kernels.
+constexpr int64_t kStaticScratchBytes = int64_t(64) << 20;
+static __device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_dev[kMaxDevices];   // device address of `scratch`, per device id
+
+// This GPU's scratch address (looked up on the first call on the device).
+static int static_scratch(af_ctx *c, uint8_t **out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(c, AF_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+  if (dev != c->device)
+    return fail(c, AF_EINVAL, "device %d is current, the context lives on device %d", dev,
+                c->device);
+  if (dev < 0 || dev >= kMaxDevices) return fail(c, AF_EDEVICE, "device id %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(c, AF_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_dev[dev] = ptr;
+  }
+  *out = (uint8_t *)g_scratch_dev[dev];
+  return AF_OK;
+}
+
+int af_smooth_eval_static(af_ctx *c, const float *p, const float *q, int64_t n,
+                          const float *samples, int32_t M, float c_thr, float tau_s,
+                          const float *grad_s, float *s_out, float *dq, float *dp, void *stream) {
+  if (!c) return AF_EINVAL;
+  if (n < 0 || (n > 0 && (!p || !q || !samples)) || !smooth_args_ok(M, c_thr, tau_s) ||
+      (!dq) != (!dp) || (n > 0 && !s_out && !dq))
+    return fail(c, AF_EINVAL, "bad smoothed-score arguments");
+  hipStream_t s = (hipStream_t)stream;
+  uint8_t *base = nullptr;
+  int rc = static_scratch(c, &base);
+  if (rc != AF_OK) return rc;
+  if (c->graph_dirty && (rc = graph_settle(c)) != AF_OK) return rc;
+  if (!grid_covers(c))
+    return fail(c, AF_EINVAL, "the brick grid must grow before this call (af_smooth_eval "
+                              "or af_score_points grows it)");
+  // carve the scratch: every part 256-byte aligned
+  const int64_t nv = std::max<int64_t>(1, c->n_blocks * kBlockVox);
+  const int64_t nb = std::max<int64_t>(1, c->grid_bricks);
+  const int64_t na = std::max<int64_t>(1, std::min<int64_t>(8 * c->n_blocks, c->grid_bricks));
+  int64_t off = 0;
+  auto take = [&](int64_t bytes) {
+    const int64_t at = off;
+    off += (bytes + 255) & ~int64_t(255);
+    return at;
+  };
+  const int64_t oT = take(sizeof(float) * nv), oBid = take(sizeof(int32_t) * nb),
+                oBid9 = take(sizeof(int32_t) * nb), oOf = take(sizeof(int32_t) * na),
+                oT9 = take(sizeof(float) * 729 * na), oCount = take(sizeof(int32_t)),
+                oWork = take(sizeof(unsigned long long) * 8);
+  if (off > kStaticScratchBytes)
+    return fail(c, AF_ENOMEM,
+                "the map needs %lld bytes of scratch (%lld blocks, %lld grid bricks); the static "
+                "scratch holds %lld (af_smooth_eval has no such limit)",
+                (long long)off, (long long)c->n_blocks, (long long)c->grid_bricks,
+                (long long)kStaticScratchBytes);
+  SmoothBuffers b;
+  memset(&b, 0, sizeof(b));
+  b.T = (float *)(base + oT);
+  b.bid = (int32_t *)(base + oBid);
+  b.bid9 = (int32_t *)(base + oBid9);
+  b.brick_of = (int32_t *)(base + oOf);
+  b.T9 = (float *)(base + oT9);
+  b.count = (int32_t *)(base + oCount);
+  b.work = (unsigned long long *)(base + oWork);
+  b.apron_cap = na;
+  SmoothField f;
+  smooth_build(c, b, s, f);   // clears the count, the brick tables and the work counters first
+  launch_smooth_eval(f, 256.0 / c->p.scale, p, q, n, samples, M, c_thr, tau_s, grad_s, s_out, dq,
+                     dp, b.work, s);
+  c->last_stream = s;
+  return hip_check(c, "smooth eval (static scratch)");
 }
 
 int af_incremental_enable(af_ctx *c, int32_t tool_id, int32_t budget) {
