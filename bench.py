@@ -417,15 +417,18 @@ def run_serve(args):
     stream; a fifth stream is refused).  Frames 0..W-1 warm up; W..W+K-1 are
     run back to back, one frame of every stream per server step, against the
     plain sequential path (per frame: integrate, score, wait) on four other
-    contexts; W+K..W+K+L-1 arrive at 10 Hz from each stream's phase, and the
-    latency of each frame runs from its arrival to its labels on the host."""
+    contexts and against a server that scores each stream in its own launch;
+    W+K..W+K+L-1 (default 150 per stream, 600 frames) arrive at 10 Hz from
+    each stream's phase, and the latency of each frame runs from its arrival
+    to its labels on the host.  The server is in batched mode: every step
+    scores all streams that took a frame in one launch."""
     import torch
     import synth
     from paper_2608_06412_amd import AFError, Context, Server, default_config
 
     W = args.warmup if args.warmup != 100 else 20
     K = args.steps if args.steps != 400 else 40
-    L = args.latency_frames if args.latency_frames != 100 else 60
+    L = args.latency_frames if args.latency_frames != 600 else 150
     n = W + K + L
     specs = synth.serving(n_streams=4, n_frames=n)
     t = time.perf_counter()
@@ -440,26 +443,36 @@ def run_serve(args):
                            max_orientations=256, max_tools=1)
         c.hbm_budget = int(budget)
         return c
-    srv = Server(24 * GiB, max_streams=5)
-    sids = [srv.admit(cfg(6 * GiB)) for _ in specs]
-    try:
-        srv.admit(cfg(6 * GiB))
-        refused = False
-    except AFError:
-        refused = True
+    def make_server(batch):
+        srv = Server(24 * GiB, max_streams=5, batch=batch)
+        sids = [srv.admit(cfg(6 * GiB)) for _ in specs]
+        try:
+            srv.admit(cfg(6 * GiB))
+            refused = False
+        except AFError:
+            refused = True
+        for s, sp in enumerate(specs):
+            w = sp.workload
+            allx = np.concatenate([f.xyz for f in frames[s]])
+            srv.context(sids[s]).set_tool_kernels(0, w.tool, w.rot)
+            srv.prepare(sids[s], allx.min(0) - 1.0, allx.max(0) + 1.0,
+                        max(len(f.xyz) for f in frames[s]), [0])
+        return srv, sids, refused
+
+    # batched server (one scoring launch per step across the streams), the
+    # unbatched server (one scoring launch per stream, overlapped), and the
+    # plain sequential path
+    srv, sids, refused = make_server(True)
+    srv_o, sids_o, _ = make_server(False)
     seq = []
     for s, sp in enumerate(specs):
         w = sp.workload
-        allx = np.concatenate([f.xyz for f in frames[s]])
-        srv.context(sids[s]).set_tool_kernels(0, w.tool, w.rot)
-        srv.prepare(sids[s], allx.min(0) - 1.0, allx.max(0) + 1.0,
-                    max(len(f.xyz) for f in frames[s]), [0])
         c = Context(cfg(0))
         c.set_tool_kernels(0, w.tool, w.rot)
         seq.append(c)
     resident = [[torch.from_numpy(f.xyz).cuda() for f in fr[:W + K]] for fr in frames]
 
-    def serve_frames(lo, hi):
+    def serve_frames(lo, hi, srv=srv, sids=sids):
         tests = 0
         for k in range(lo, hi):
             for s, sid in enumerate(sids):
@@ -481,6 +494,7 @@ def run_serve(args):
                 tests += c.score_stats(0)["canonical_tests"]
         return tests
     serve_frames(0, W)
+    serve_frames(0, W, srv_o, sids_o)
     seq_frames(0, W)
     log("warm-up done; points per stream %s" % [srv.context(i).num_points() for i in sids])
     torch.cuda.synchronize()
@@ -488,16 +502,24 @@ def run_serve(args):
     tests_srv = serve_frames(W, W + K)
     wall_srv = time.perf_counter() - t0
     t0 = time.perf_counter()
+    tests_o = serve_frames(W, W + K, srv_o, sids_o)
+    wall_o = time.perf_counter() - t0
+    t0 = time.perf_counter()
     tests_seq = seq_frames(W, W + K)
     torch.cuda.synchronize()
     wall_seq = time.perf_counter() - t0
-    same = all(np.array_equal(srv.context(sid).read_labels(0)["label"], seq[s].read_labels(0)["label"])
-               and np.array_equal(srv.context(sid).read_labels(0)["first_free"],
+
+    def same_as_seq(server, ids):
+        return all(np.array_equal(server.context(sid).read_labels(0)["label"],
+                                  seq[s].read_labels(0)["label"]) and
+                   np.array_equal(server.context(sid).read_labels(0)["first_free"],
                                   seq[s].read_labels(0)["first_free"])
-               for s, sid in enumerate(sids))
+                   for s, sid in enumerate(ids))
+    same = same_as_seq(srv, sids) and same_as_seq(srv_o, sids_o)
+    srv_o.close()
     returns = sum(len(frames[s][k].xyz) for s in range(4) for k in range(W, W + K))
-    log("throughput: server %.1f ms per 4 frames, sequential %.1f" %
-        (wall_srv / K * 1e3, wall_seq / K * 1e3))
+    log("throughput: batched server %.1f ms per 4 frames, unbatched %.1f, sequential %.1f" %
+        (wall_srv / K * 1e3, wall_o / K * 1e3, wall_seq / K * 1e3))
 
     # paced: every stream at 10 Hz from its phase
     def paced(run_one_step):
@@ -586,9 +608,12 @@ def run_serve(args):
                                   "max": float(lat_seq.max())},
         "throughput": {"frames_per_s": 4 * K / wall_srv, "returns_per_s": returns / wall_srv,
                        "tests_per_s": tests_srv / wall_srv,
+                       "mode": "batched: one scoring launch per server step across the streams",
+                       "unbatched_frames_per_s": 4 * K / wall_o,
                        "sequential_frames_per_s": 4 * K / wall_seq,
                        "sequential_tests_per_s": tests_seq / wall_seq,
-                       "speedup": wall_seq / wall_srv, "same_tests": bool(tests_srv == tests_seq),
+                       "speedup": wall_seq / wall_srv, "speedup_over_unbatched": wall_o / wall_srv,
+                       "same_tests": bool(tests_srv == tests_seq == tests_o),
                        "labels_identical": bool(same), "labels_identical_after_paced": bool(same_end)},
     }
     print(json.dumps(out), flush=True)

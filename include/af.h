@@ -207,6 +207,13 @@ int af_set_tool_table(af_ctx *ctx, int32_t tool_id, const af_kernel_table *table
  * block or point capacity is exceeded. */
 int af_integrate_frame(af_ctx *ctx, const float *xyz, int64_t n,
                        const float origin[3], int64_t frame_id, void *stream);
+/* af_integrate_frame for returns in HOST memory: `xyz` (n float32 triples)
+ * is copied to a device buffer the context keeps (grown to the largest frame
+ * seen, from the context's device budget: AF_ENOMEM if it does not fit) and
+ * integrated from there.  The host array is no longer read when the call
+ * returns.  Everything else as af_integrate_frame. */
+int af_integrate_frame_host(af_ctx *ctx, const float *xyz, int64_t n,
+                            const float origin[3], int64_t frame_id, void *stream);
 
 /* Sections 3.4-3.5: label every surface point for tool `tool_id`: W < W_min
  * -> AF_UNSCORED; else candidates = orientations whose approach direction is
@@ -430,16 +437,50 @@ int af_smooth_eval_static(af_ctx *ctx, const float *p, const float *q, int64_t n
  * (4 B per voxel of block capacity).  af_incremental_frame integrates one
  * frame as af_integrate_frame does, then runs the steps above; it
  * synchronises `stream` once (inside the integration).  af_incremental_stats
- * synchronises and reports the last frame's counts.  af_read_incremental
+ * synchronises and reports the counts of the last frame or drain.  af_read_incremental
  * copies state in canonical point order into host arrays (any may be NULL). */
 typedef struct af_incr_stats {
   int64_t new_points, trig_i, trig_ii, trig_iii;   /* points queued by each cause */
   int64_t changed, sampled;                        /* changed voxels, sampled ones */
   int64_t queued, evaluated, backlog;              /* before selection, chosen, left */
+  int64_t budget;                                  /* the cap the selection applied */
 } af_incr_stats;
 int af_incremental_enable(af_ctx *ctx, int32_t tool_id, int32_t budget);
 int af_incremental_frame(af_ctx *ctx, const float *xyz, int64_t n, const float origin[3],
                          int64_t frame_id, void *stream);
+/* Adaptive per-frame cap (Section 3.5's budget adapts to the frame; here to
+ * a cost both the library and a checker count exactly): after a frame that
+ * evaluated n > 0 points for L > 0 canonical lookups, the next frame's cap is
+ * lookup_target * n / L (integer division) clamped to [b_min, b_max]; a frame
+ * with no evaluation or no lookup keeps the cap.  lookup_target 0 keeps the
+ * cap fixed.  The first frame's cap is the enable budget clamped to
+ * [b_min, b_max].  Set after af_incremental_enable and before the first frame
+ * (AF_EINVAL otherwise, or for b_min < 1, b_max < b_min, a negative or
+ * > 2^40 target); grows the evaluation list to b_max entries (AF_ENOMEM). */
+int af_incremental_budget(af_ctx *ctx, int64_t lookup_target, int32_t b_min, int32_t b_max);
+/* Coarse-to-fine direction search (Section 3.6, "Accessibility scoring"):
+ * each evaluation of the incremental mode tests only the orientations of a
+ * coarse pass and of a fine window around the stored direction of the
+ * nearest resolved neighbour.  Coarse pass: the orientations whose approach
+ * direction a greedy walk in index order takes (a direction at least
+ * coarse_deg from every direction taken before: dot <= cos + 1e-12), plus
+ * the orientations sharing a taken direction.  Fine window of orientation
+ * k*: the orientations within fine_deg of k*'s direction (dot >= cos -
+ * 1e-12).  The nearest resolved neighbour of a point: the other point with a
+ * stored free direction when the evaluation step starts, of smallest
+ * (|d|^2, dz, dy, dx) with |d| <= radius_m (voxel offsets d); without one
+ * only the coarse pass is searched.  The paper's setting is (20, 25, 0.3).
+ * Set after af_incremental_enable and before the first frame; radius at most
+ * 64 voxels (AF_EINVAL otherwise). */
+int af_incremental_c2f(af_ctx *ctx, double coarse_deg, double fine_deg, double radius_m);
+/* Consume the backlog between frames (Section 3.5: deferred evaluations are
+ * done between LiDAR frames): evaluate up to max_evals queued points with
+ * W >= conf_min_w in point order, update their state and every label, as a
+ * frame's evaluation does, with no integration and no trigger; the frames'
+ * cap is unchanged.  0 <= max_evals <= the largest cap (AF_EINVAL).
+ * Asynchronous on `stream`.  af_incremental_stats then reports the drain
+ * (zero trigger counts, budget = max_evals). */
+int af_incremental_drain(af_ctx *ctx, int32_t max_evals, void *stream);
 int af_incremental_stats(af_ctx *ctx, af_incr_stats *out);
 int af_read_incremental(af_ctx *ctx, int64_t first, int64_t count, int64_t *key, uint8_t *label,
                         uint8_t *best, int16_t *best_dir, double *a, int64_t *n_written);
@@ -468,8 +509,9 @@ int af_read_incremental(af_ctx *ctx, int64_t first, int64_t count, int64_t *key,
  *
  * af_server_step takes the oldest queued frame of every stream (streams
  * visited round robin), launches each (host-to-device copy, then the recorded
- * frame) on its own HIP stream so that the GPU overlaps them, then waits for
- * all of them and writes, for each frame processed, its stream id, frame id
+ * frame) on its own HIP stream so that the GPU overlaps them, in batched mode
+ * then the one scoring launch over all of them, then waits for all of them
+ * and writes, for each frame processed, its stream id, frame id
  * and status (AF_OK, or the code af_graph_sync / af_graph_frame gave; a failed
  * frame is consumed) into the caller's arrays of `cap` >= max_streams
  * entries, and their number into *n_done.  Returns AF_EINVAL if the arrays
@@ -477,6 +519,16 @@ int af_read_incremental(af_ctx *ctx, int64_t first, int64_t count, int64_t *key,
  * server. */
 typedef struct af_server af_server;
 int af_server_create(int64_t hbm_budget, int32_t max_streams, af_server **out);
+/* Batched mode (on by default; the serving workload's "frames from all
+ * streams batched into one integrate+score step"): each stream's recorded
+ * graph holds its integration, normals and candidate masks, and every step
+ * scores the points of all streams that took a frame in ONE persistent
+ * launch (each point against its own map and tools; at most 64 stream-tool
+ * pairs and 64 KiB of table offsets per launch, else the frames fail with
+ * AF_EDEVICE).  Off: each graph also holds its own scoring launch and the
+ * streams' launches overlap on the GPU.  Labels and counts are the same
+ * either way.  Set before any stream is prepared (AF_EINVAL otherwise). */
+int af_server_batch(af_server *srv, int32_t on);
 int af_server_destroy(af_server *srv);
 const char *af_server_last_error(af_server *srv);
 int64_t af_server_reserved(af_server *srv);

@@ -103,7 +103,11 @@ def _load():
     L.orc_tool_table.argtypes = [vp, ctypes.c_int, i32, vp, vp, i64]
     L.orc_score.restype = ctypes.c_int
     L.orc_score.argtypes = [vp, ctypes.c_int, vp, i64]
+    L.orc_score_allow.restype = ctypes.c_int
+    L.orc_score_allow.argtypes = [vp, ctypes.c_int, vp, i64, vp]
     L.orc_score_stats_get.argtypes = [vp, ctypes.POINTER(ScoreStats)]
+    L.orc_read_results.restype = i64
+    L.orc_read_results.argtypes = [vp, i64, vp, vp, vp, vp, vp, i32]
     L.orc_point_result.restype = ctypes.c_int
     L.orc_point_result.argtypes = [vp, i64, vp, vp, vp, vp, vp, i32]
     L.orc_pca_axis.restype = ctypes.c_int
@@ -305,8 +309,14 @@ class Oracle:
             raise ValueError("no such tool/orientation")
         return off[:m].copy(), cls[:m].copy()
 
-    def score(self, tool_id, keys=None):
-        if keys is None:
+    def score(self, tool_id, keys=None, allow=None):
+        """Score every point, or the listed keys; allow ([len(keys),
+        ceil(K/64)] uint64) restricts each listed point's orientations."""
+        if allow is not None:
+            k = np.ascontiguousarray(keys, dtype=np.int64)
+            al = np.ascontiguousarray(allow, dtype=np.uint64).reshape(len(k), -1)
+            rc = self.L.orc_score_allow(self.h, int(tool_id), _p(k), len(k), _p(al))
+        elif keys is None:
             rc = self.L.orc_score(self.h, int(tool_id), None, 0)
         else:
             k = np.ascontiguousarray(keys, dtype=np.int64)
@@ -318,6 +328,21 @@ class Oracle:
         st = ScoreStats()
         self.L.orc_score_stats_get(self.h, ctypes.byref(st))
         return st.as_dict()
+
+    def read_results(self, K):
+        """Every point's result of the last score() in canonical order:
+        label (255 = not evaluated), first_free, has_normal, normal [n, 3],
+        mask [n, ceil(K/64)]."""
+        n = self.num_points()
+        mw = (K + 63) // 64
+        lbl = np.zeros(max(n, 1), np.uint8)
+        ff = np.zeros(max(n, 1), np.int32)
+        hn = np.zeros(max(n, 1), np.int32)
+        nrm = np.zeros((max(n, 1), 3), np.int64)
+        mask = np.zeros((max(n, 1), mw), np.uint64)
+        m = self.L.orc_read_results(self.h, n, _p(lbl), _p(ff), _p(hn), _p(nrm), _p(mask), mw)
+        return dict(label=lbl[:m], first_free=ff[:m], has_normal=hn[:m], normal=nrm[:m],
+                    mask=mask[:m])
 
     def point_result(self, key, K):
         mw = (K + 63) // 64

@@ -17,7 +17,8 @@ module implements that state machine in plain Python on top of the C oracle
          fired: every point currently classified inaccessible is queued;
 3. evaluate queued points whose confidence c = w / (w + 5) is at least 0.2,
    at most `budget` of them per frame in canonical point order; the others
-   stay queued (the backlog);
+   stay queued (the backlog), and `drain` evaluates more of them between
+   frames;
 4. update each evaluated point's state: the best stored direction score
    never increases; the accessibility confidence a (initially 1) is
    multiplied by 0.75 when an evaluation finds blocked a point whose stored
@@ -33,15 +34,40 @@ voxels with TSDF < r_c, of that orientation; an evaluation that finds no free
 orientation scores n_c.  A changed voxel is one that received a contribution
 in the frame.  The sample of changed voxels is the 256 with the smallest
 SplitMix64 hash of (voxel key XOR frame * 0x9E3779B97F4A7C15).  Trigger (i)
-compares S/W exactly.  The budget is a fixed cap (the paper's cap adapts to
-the frame time, which a test cannot reproduce).  Labels: UNSCORED (never
+compares S/W exactly.  The budget is a fixed cap, or it adapts: the paper's
+cap adapts to the frame time, which no test can reproduce, so the adaptive
+cap follows a cost that both sides count exactly, the canonical lookups of
+the frame's evaluations.  After a frame that evaluated n > 0 points for L > 0
+lookups, the next frame's cap is lookup_target * n // L (integer division),
+clamped to [b_min, b_max]; otherwise it stays.  The backlog is consumed
+between frames by explicit drain calls (the caller knows when it is idle),
+each evaluating up to a given number of queued points in point order; a drain
+runs no trigger and does not change the cap.  Labels: UNSCORED (never
 evaluated), ACCESSIBLE (confident-accessible), TENTATIVE (a free direction
 is stored but c * a <= 0.7), BLOCKED / NO_CANDIDATE (no free direction ever
 stored; the last evaluation found every candidate blocked / no candidate).
 Trigger (iii) re-queues the points labelled BLOCKED or NO_CANDIDATE after the
 previous frame.
+
+Coarse-to-fine direction search (Section 3.6, optional): an evaluation tests
+only the orientations of a coarse pass and of a fine window around the best
+direction of the nearest resolved neighbour.  Readings, for any orientation
+set: the coarse pass holds the orientations whose approach direction was
+taken by a greedy walk in index order that takes a direction when it is at
+least 20 degrees from every direction taken before (dot product at most
+cos 20 + 1e-12), together with every orientation sharing a taken direction;
+the fine window of orientation k* holds the orientations whose direction is
+within 25 degrees of k*'s (dot product at least cos 25 - 1e-12).  A resolved
+point is one with a stored free direction (stored score below n_c) when the
+evaluation step starts; the nearest resolved neighbour of a point is the
+other resolved point of smallest (|d|^2, dz, dy, dx), d its voxel offset, with
+|d| at most 0.3 m; without one, only the coarse pass is searched.  Among the
+allowed orientations the evaluation is the usual one (candidate filters,
+first free in index order).
 """
 from __future__ import annotations
+
+import math
 
 import numpy as np
 
@@ -89,6 +115,34 @@ def label_of(st, W: int, n_c: int, k_c: int = 5, accept: float = 0.7) -> int:
     return LABEL_NO_CANDIDATE if st["outcome"] == LABEL_NO_CANDIDATE else LABEL_BLOCKED
 
 
+def _dot(a, b):
+    return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2]
+
+
+def coarse_fine_sets(rot, coarse_deg: float = 20.0, fine_deg: float = 25.0):
+    """(coarse [mw] uint64, fine [K, mw] uint64) of an orientation set given
+    as K row-major rotations whose column 0 is the approach direction."""
+    R = np.asarray(rot, np.float64).reshape(-1, 9)
+    d = [(float(r[0]), float(r[3]), float(r[6])) for r in R]
+    K = len(d)
+    mw = (K + 63) // 64
+    cc = math.cos(coarse_deg * (math.pi / 180.0))
+    cf = math.cos(fine_deg * (math.pi / 180.0))
+    taken = []
+    coarse = np.zeros(mw, np.uint64)
+    for k in range(K):
+        if d[k] in taken or all(_dot(d[k], c) <= cc + 1e-12 for c in taken):
+            if d[k] not in taken:
+                taken.append(d[k])
+            coarse[k // 64] |= np.uint64(1) << np.uint64(k % 64)
+    fine = np.zeros((K, mw), np.uint64)
+    for a in range(K):
+        for k in range(K):
+            if _dot(d[k], d[a]) >= cf - 1e-12:
+                fine[a, k // 64] |= np.uint64(1) << np.uint64(k % 64)
+    return coarse, fine
+
+
 def ball_offsets(r: int):
     """Integer offsets o with |o|^2 <= r^2."""
     return [(x, y, z) for z in range(-r, r + 1) for y in range(-r, r + 1)
@@ -98,8 +152,12 @@ def ball_offsets(r: int):
 class IncrementalOracle:
     def __init__(self, orc, tool_id: int, K: int, budget: int, n_sample: int = 256,
                  r_u: int = 3, k_c: int = 5, decay: float = 0.75, recover: float = 0.15,
-                 accept: float = 0.7):
+                 accept: float = 0.7, lookup_target: int = 0, b_min: int = 1,
+                 b_max: int | None = None):
         self.orc, self.tool_id, self.K, self.budget = orc, tool_id, K, budget
+        self.lookup_target, self.b_min = lookup_target, b_min
+        self.b_max = budget if b_max is None else b_max
+        self.c2f = None
         self.n_sample, self.k_c = n_sample, k_c
         self.decay, self.recover, self.accept = decay, recover, accept
         self.ball = ball_offsets(r_u)
@@ -111,6 +169,37 @@ class IncrementalOracle:
         self.state = {}       # key -> dict(best, best_dir, a, S, W, pending, outcome)
         self.q_last = None
         self.stats = {}
+
+    def enable_c2f(self, rot, coarse_deg: float = 20.0, fine_deg: float = 25.0,
+                   radius_m: float = 0.3):
+        """Search only the coarse pass and the fine window (Section 3.6)."""
+        coarse, fine = coarse_fine_sets(rot, coarse_deg, fine_deg)
+        r = radius_m / self.orc.cfg.voxel
+        self.c2f = dict(coarse=coarse, fine=fine, r2=int(math.floor(r * r + 1e-9)))
+
+    def _allow(self, chosen):
+        """Allowed orientations of each chosen point: the coarse pass, plus
+        the fine window of its nearest resolved neighbour's stored direction."""
+        c = self.c2f
+        res = [(k, st["best_dir"]) for k, st in self.state.items() if st["best"] < self.n_c]
+        allow = np.tile(c["coarse"], (len(chosen), 1))
+        self.last_neighbour = {}
+        if not res or not chosen:
+            return allow
+        rk = unpack_keys(np.array([k for k, _ in res], np.int64))
+        rdir = np.array([b for _, b in res], np.int64)
+        pk = unpack_keys(np.array(chosen, np.int64))
+        for j, s in enumerate(pk):
+            d = rk - s
+            d2 = (d * d).sum(1)
+            code = (d2 << 30) | ((d[:, 2] + 512) << 20) | ((d[:, 1] + 512) << 10) | (d[:, 0] + 512)
+            code = np.where((d2 == 0) | (d2 > c["r2"]), np.iinfo(np.int64).max, code)
+            m = int(np.argmin(code))
+            if code[m] == np.iinfo(np.int64).max:
+                continue
+            allow[j] |= c["fine"][rdir[m]]
+            self.last_neighbour[chosen[j]] = (int(res[m][0]), int(rdir[m]))
+        return allow
 
     def _label(self, st, W):
         return label_of(st, W, self.n_c, self.k_c, self.accept)
@@ -159,11 +248,40 @@ class IncrementalOracle:
                     st["pending"] = True
                     n_ii += 1
         # evaluate at most `budget` queued confident points, canonical order
+        budget = self.budget
+        chosen, lookups = self._evaluate(keys, vox, budget)
+        if self.lookup_target > 0 and chosen and lookups > 0:
+            self.budget = min(self.b_max, max(self.b_min,
+                                              self.lookup_target * len(chosen) // lookups))
+        self.stats = dict(new=n_new, trig_i=n_i, trig_ii=n_ii, trig_iii=n_iii,
+                          sampled=len(sample), evaluated=len(chosen), budget=budget,
+                          lookups=lookups,
+                          backlog=sum(1 for s in self.state.values() if s["pending"]))
+        return self.stats
+
+    def drain(self, max_evals: int):
+        """Between frames: evaluate up to max_evals queued confident points
+        in point order (no trigger, the cap unchanged)."""
+        keys = self.orc.read_points()["key"]
+        vox = {int(k): self.orc.voxel(int(k))[:2] for k in keys}
+        chosen, lookups = self._evaluate(keys, vox, max_evals)
+        self.stats = dict(new=0, trig_i=0, trig_ii=0, trig_iii=0, sampled=0,
+                          evaluated=len(chosen), budget=max_evals, lookups=lookups,
+                          backlog=sum(1 for s in self.state.values() if s["pending"]))
+        return self.stats
+
+    def _evaluate(self, keys, vox, cap):
+        """Steps 3-4 for the first `cap` queued confident points; returns
+        them and their canonical lookups."""
+        orc = self.orc
         chosen = [int(k) for k in keys
                   if self.state[int(k)]["pending"] and vox[int(k)][1] >= self.conf_min_w]
-        chosen = chosen[:self.budget]
+        chosen = chosen[:cap]
+        lookups = 0
         if chosen:
-            orc.score(self.tool_id, np.array(chosen, np.int64))
+            allow = self._allow(chosen) if self.c2f is not None else None
+            orc.score(self.tool_id, np.array(chosen, np.int64), allow=allow)
+            lookups = orc.score_stats()["canonical_lookups"]
         for k in chosen:
             st = self.state[k]
             st["pending"] = False
@@ -174,10 +292,7 @@ class IncrementalOracle:
                 score, d = self.n_c, -1
             apply_evaluation(st, score, d, r["label"], self.n_c, self.decay, self.recover)
         self.last_evaluated = chosen
-        self.stats = dict(new=n_new, trig_i=n_i, trig_ii=n_ii, trig_iii=n_iii,
-                          sampled=len(sample), evaluated=len(chosen),
-                          backlog=sum(1 for s in self.state.values() if s["pending"]))
-        return self.stats
+        return chosen, lookups
 
     def labels(self):
         """(keys, label, best, best_dir, a) in canonical point order."""

@@ -972,7 +972,26 @@ static int orientation_free(const orc_t *o, const tool_tab *tt, int32_t k,
   return 1;
 }
 
+static int score_impl(orc_t *o, int tool_id, const int64_t *keys, int64_t n_keys,
+                      const uint64_t *allow);
+
 int orc_score(orc_t *o, int tool_id, const int64_t *keys, int64_t n_keys) {
+  return score_impl(o, tool_id, keys, n_keys, NULL);
+}
+
+/* orc_score restricted to the allowed orientations of each listed point:
+ * allow holds ceil(K/64) words per key; an orientation is a candidate only
+ * when it passes the filters of Section 3.4 and its allow bit is set (the
+ * coarse-to-fine direction search of Section 3.6 narrows the search this
+ * way). */
+int orc_score_allow(orc_t *o, int tool_id, const int64_t *keys, int64_t n_keys,
+                    const uint64_t *allow) {
+  if (!keys || !allow) return -1;
+  return score_impl(o, tool_id, keys, n_keys, allow);
+}
+
+static int score_impl(orc_t *o, int tool_id, const int64_t *keys, int64_t n_keys,
+                      const uint64_t *allow) {
   if (tool_id < 0 || tool_id >= MAX_TOOLS) return -1;
   const tool_tab *tt = &o->tools[tool_id];
   if (tt->K <= 0) return -4;
@@ -1031,7 +1050,8 @@ int orc_score(orc_t *o, int tool_id, const int64_t *keys, int64_t n_keys) {
     for (int i = 0; i < 3; ++i) o->normal[3 * p + i] = n[i];
     int any = 0;
     for (int32_t k = 0; k < K; ++k)
-      if (candidate(o, p, s, n, hn, tt->rot + 9 * k)) {
+      if ((!allow || ((allow[j * mw + k / 64] >> (k % 64)) & 1)) &&
+          candidate(o, p, s, n, hn, tt->rot + 9 * k)) {
         o->mask[p * mw + k / 64] |= 1ULL << (k % 64);
         any = 1;
         o->sst.candidate_tests++;
@@ -1088,6 +1108,25 @@ int orc_body_hits(const orc_t *o, int tool_id, int64_t key, int32_t k) {
 int orc_score_stats_get(const orc_t *o, orc_score_stats *st) {
   *st = o->sst;
   return 0;
+}
+
+/* Results of the last orc_score for points [0, count) in point order (the
+ * canonical order): label (255 if not evaluated), first free orientation,
+ * has_normal, normal [3] and mask words [mask_words]; returns the count. */
+int64_t orc_read_results(const orc_t *o, int64_t count, uint8_t *label, int32_t *first_free,
+                         int32_t *has_normal, int64_t *normal, uint64_t *mask,
+                         int32_t mask_words) {
+  int64_t m = count < o->np ? count : o->np;
+  if (m > o->rcap) m = o->rcap;
+  for (int64_t p = 0; p < m; ++p) {
+    label[p] = o->label[p];
+    first_free[p] = o->first_free[p];
+    has_normal[p] = o->has_normal[p];
+    for (int i = 0; i < 3; ++i) normal[3 * p + i] = o->normal[3 * p + i];
+    for (int w = 0; w < mask_words; ++w)
+      mask[p * mask_words + w] = w < o->mask_words ? o->mask[p * o->mask_words + w] : 0;
+  }
+  return m;
 }
 
 int orc_point_result(const orc_t *o, int64_t key, uint8_t *label,

@@ -94,10 +94,18 @@ int64_t orc_tool_table(const orc_t *o, int tool_id, int32_t k, int32_t *off,
 
 /* Score all points (keys == NULL) or only the listed point keys. */
 int orc_score(orc_t *o, int tool_id, const int64_t *keys, int64_t n_keys);
+/* orc_score of the listed keys with each point's orientations restricted to
+ * the set bits of allow[key index][ceil(K/64)]. */
+int orc_score_allow(orc_t *o, int tool_id, const int64_t *keys, int64_t n_keys,
+                    const uint64_t *allow);
 int orc_score_stats_get(const orc_t *o, orc_score_stats *st);
 /* Results of the last orc_score for point `key`: label (0 unscored,
  * 1 accessible, 2 blocked, 3 no candidate), first free orientation, the
  * normal (int64 x3, has_normal), and the candidate mask words. */
+/* The same for points [0, count) in canonical order; returns the count. */
+int64_t orc_read_results(const orc_t *o, int64_t count, uint8_t *label, int32_t *first_free,
+                         int32_t *has_normal, int64_t *normal, uint64_t *mask,
+                         int32_t mask_words);
 int orc_point_result(const orc_t *o, int64_t key, uint8_t *label,
                      int32_t *first_free, int64_t normal[3], int32_t *has_normal,
                      uint64_t *mask, int32_t mask_words);

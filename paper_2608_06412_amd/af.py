@@ -81,7 +81,7 @@ class ScoreStats(ctypes.Structure):
 class IncrStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
                 ("new_points", "trig_i", "trig_ii", "trig_iii", "changed", "sampled",
-                 "queued", "evaluated", "backlog")]
+                 "queued", "evaluated", "backlog", "budget")]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -107,6 +107,7 @@ SIGNATURES = {
     "af_last_error": (ctypes.c_char_p, [_vp]),
     "af_set_tool_kernels": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(Tool), _i32, _vp, _vp]),
     "af_integrate_frame": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _vp]),
+    "af_integrate_frame_host": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _vp]),
     "af_score_points": (ctypes.c_int, [_vp, _i32, _vp]),
     "af_read_labels": (ctypes.c_int, [_vp, _i32, _i64, _i64, _vp, _vp, _vp, _vp, _vp]),
     "af_num_points": (_i64, [_vp]),
@@ -148,6 +149,10 @@ SIGNATURES = {
                                         ctypes.c_int32, ctypes.c_float, ctypes.c_float,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "af_incremental_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
+    "af_incremental_budget": (ctypes.c_int, [_vp, _i64, _i32, _i32]),
+    "af_incremental_drain": (ctypes.c_int, [_vp, _i32, _vp]),
+    "af_incremental_c2f": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double,
+                                          ctypes.c_double]),
     "af_incremental_frame": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                             ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     "af_incremental_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
@@ -155,6 +160,7 @@ SIGNATURES = {
                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "af_server_create": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p]),
+    "af_server_batch": (ctypes.c_int, [_vp, _i32]),
     "af_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "af_server_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "af_server_reserved": (ctypes.c_int64, [ctypes.c_void_p]),
@@ -321,7 +327,16 @@ class Context:
         self.K[tool_id] = len(d)
 
     def integrate_frame(self, xyz, origin, frame_id: int, stream=None):
-        """xyz: CUDA float32 tensor [n, 3] (contiguous); origin: 3 floats."""
+        """xyz: CUDA float32 tensor [n, 3] (contiguous), or a host array
+        (numpy, [n, 3] float32) that af_integrate_frame_host copies; origin:
+        3 floats."""
+        if isinstance(xyz, np.ndarray):
+            x = np.ascontiguousarray(xyz, dtype=np.float32).reshape(-1, 3)
+            o = np.ascontiguousarray(origin, dtype=np.float32).reshape(3)
+            self._check(self._lib.af_integrate_frame_host(
+                self.h, _p(x) if len(x) else None, len(x), _p(o), int(frame_id),
+                _stream_handle(stream)))
+            return
         if not (getattr(xyz, "is_cuda", False) and str(xyz.dtype) == "torch.float32"
                 and xyz.is_contiguous() and xyz.dim() == 2 and xyz.shape[1] == 3):
             raise TypeError("xyz must be a contiguous CUDA float32 tensor of shape [n, 3]")
@@ -546,6 +561,19 @@ class Context:
         """Switch this (still empty) map to the incremental mode for one tool."""
         self._check(self._lib.af_incremental_enable(self.h, int(tool_id), int(budget)))
 
+    def incremental_budget(self, lookup_target: int, b_min: int, b_max: int):
+        self._check(self._lib.af_incremental_budget(self.h, int(lookup_target), int(b_min),
+                                                    int(b_max)))
+
+    def incremental_c2f(self, coarse_deg: float = 20.0, fine_deg: float = 25.0,
+                        radius_m: float = 0.3):
+        self._check(self._lib.af_incremental_c2f(self.h, float(coarse_deg), float(fine_deg),
+                                                 float(radius_m)))
+
+    def incremental_drain(self, max_evals: int, stream=None):
+        self._check(self._lib.af_incremental_drain(self.h, int(max_evals),
+                                                   _stream_handle(stream)))
+
     def incremental_frame(self, xyz, origin, frame_id: int, stream=None):
         """Integrate a frame, then re-evaluate only the queued points."""
         if not (getattr(xyz, "is_cuda", False) and str(xyz.dtype) == "torch.float32"
@@ -617,7 +645,7 @@ class Server:
     budget, one context, HIP stream, recorded frame graph and frame queue per
     stream, and a step that runs the oldest queued frame of every stream."""
 
-    def __init__(self, hbm_budget: int, max_streams: int = 4):
+    def __init__(self, hbm_budget: int, max_streams: int = 4, batch: bool = True):
         self._lib = lib()
         h = ctypes.c_void_p()
         rc = self._lib.af_server_create(int(hbm_budget), int(max_streams), ctypes.byref(h))
@@ -626,6 +654,7 @@ class Server:
         self.h = h
         self.max_streams = int(max_streams)
         self._ctx = {}
+        self._check(self._lib.af_server_batch(self.h, 1 if batch else 0))
 
     def close(self):
         if getattr(self, "h", None):

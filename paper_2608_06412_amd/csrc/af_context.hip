@@ -61,7 +61,12 @@ struct af_ctx {
   NormalCache ncache;
   int64_t nc_seen;              // points whose neighbourhood the cache reflects
   std::vector<char> own_mask;   // tool has its own mask and plane buffers
+  int32_t incr_budget0;         // the cap given to af_incremental_enable
+  int64_t c2f_plane_bricks;     // bricks the coarse-to-fine resolved plane covers
   unsigned *work;               // point counter of the dynamic score variants
+  // device copy of host-given returns (af_integrate_frame_host), grown on demand
+  float *host_xyz;
+  int64_t host_xyz_cap;         // returns it holds
   int score_variant;
   int64_t last_frame;
   int64_t n_points, n_blocks;   // host mirrors after the last frame
@@ -769,6 +774,27 @@ int af_set_tool_table(af_ctx *c, int32_t tool_id, const af_kernel_table *tab, vo
   return rc;
 }
 
+int af_integrate_frame_host(af_ctx *c, const float *xyz, int64_t n, const float origin[3],
+                            int64_t frame_id, void *stream) {
+  if (!c) return AF_EINVAL;
+  if (n < 0 || (n > 0 && !xyz) || !origin) return fail(c, AF_EINVAL, "bad frame arguments");
+  hipStream_t s = (hipStream_t)stream;
+  if (n > c->host_xyz_cap) {
+    HIP_TRY(c, hipStreamSynchronize(s));
+    if (c->host_xyz) dev_free(c, c->host_xyz, sizeof(float) * 3 * c->host_xyz_cap);
+    c->host_xyz = nullptr;
+    c->host_xyz_cap = 0;
+    const int64_t cap = std::max<int64_t>(n, 4096);
+    ALLOC(c, c->host_xyz, 3 * cap);
+    c->host_xyz_cap = cap;
+  }
+  if (n > 0)
+    HIP_TRY(c, hipMemcpyAsync(c->host_xyz, xyz, sizeof(float) * 3 * n, hipMemcpyHostToDevice, s));
+  // af_integrate_frame synchronises the stream after block allocation, so the
+  // copy has completed when this call returns
+  return af_integrate_frame(c, c->host_xyz, n, origin, frame_id, stream);
+}
+
 int af_integrate_frame(af_ctx *c, const float *xyz, int64_t n, const float origin[3],
                        int64_t frame_id, void *stream) {
   if (!c) return AF_EINVAL;
@@ -1019,8 +1045,44 @@ static int graph_settle(af_ctx *c) {
   return AF_OK;
 }
 
+static int graph_prepare(af_ctx *c, const float lo[3], const float hi[3], int64_t max_returns,
+                         const int32_t *tool_ids, int32_t n_tools, void *stream, bool score);
+
 int af_graph_prepare(af_ctx *c, const float lo[3], const float hi[3], int64_t max_returns,
                      const int32_t *tool_ids, int32_t n_tools, void *stream) {
+  return graph_prepare(c, lo, hi, max_returns, tool_ids, n_tools, stream, true);
+}
+
+}  // extern "C"
+
+namespace af {
+int ctx_graph_prepare_unscored(af_ctx *c, const float lo[3], const float hi[3],
+                               int64_t max_returns, const int32_t *tool_ids, int32_t n_tools,
+                               void *stream) {
+  return graph_prepare(c, lo, hi, max_returns, tool_ids, n_tools, stream, false);
+}
+
+int ctx_score_jobs(af_ctx *c, const int32_t *tool_ids, int32_t n_tools, ScoreJob *out) {
+  if (!c || !out || n_tools < 1 || n_tools > kMultiTools) return AF_EINVAL;
+  for (int32_t i = 0; i < n_tools; ++i) {
+    const int32_t id = tool_ids[i];
+    if (id < 0 || id >= c->cfg.max_tools || !c->tools[id].entries) return AF_ENOTOOL;
+    ScoreJob &j = out[i];
+    memset(&j, 0, sizeof(j));
+    j.p = c->p;
+    j.pts = c->pts;
+    j.t = c->tools[id];
+    j.g = c->grid;
+    j.max_points = c->cfg.max_points;
+  }
+  return AF_OK;
+}
+}  // namespace af
+
+extern "C" {
+
+static int graph_prepare(af_ctx *c, const float lo[3], const float hi[3], int64_t max_returns,
+                         const int32_t *tool_ids, int32_t n_tools, void *stream, bool score) {
   if (!c) return AF_EINVAL;
   if (!lo || !hi || max_returns < 1) return fail(c, AF_EINVAL, "bad graph arguments");
   if (c->incr_on)
@@ -1073,7 +1135,8 @@ int af_graph_prepare(af_ctx *c, const float lo[3], const float hi[3], int64_t ma
     launch_zero_words(host[i].counters, sizeof(ScoreCounters), cs);
   launch_normals(c->p, c->map, c->pts, c->grid, NP, cs, true);
   for (int32_t i = 0; i < n_tools; ++i) launch_mask(c->p, c->pts, host[i], c->grid, NP, cs, true);
-  launch_score_multi(c->p, c->pts, c->tools_dev, host, set, c->grid, NP, c->work, cs, true);
+  if (score)
+    launch_score_multi(c->p, c->pts, c->tools_dev, host, set, c->grid, NP, c->work, cs, true);
   hipGraph_t g = nullptr;
   const hipError_t e1 = hipStreamEndCapture(cs, &g);
   if (e1 != hipSuccess || !g)
@@ -1347,6 +1410,8 @@ int af_incremental_enable(af_ctx *c, int32_t tool_id, int32_t budget) {
     ALLOC(c, I.cand_k, 1024);
     ALLOC(c, I.sampled, 256);
     ALLOC(c, I.ctr, 1);
+    ALLOC(c, I.budget_dev, 1);
+    ALLOC(c, I.frame_budget, 1);
     ALLOC(c, c->incr_changed, c->cfg.max_blocks * kBlockVox);
     I.max_points = NP;
   }
@@ -1359,12 +1424,135 @@ int af_incremental_enable(af_ctx *c, int32_t tool_id, int32_t budget) {
     ALLOC(c, I.score_new, budget);
   }
   I.budget = budget;
+  I.lookup_target = 0;
+  I.b_min = 1;
+  I.b_max = budget;
+  c->incr_budget0 = budget;
   c->incr_on = true;
   c->incr_tool = tool_id;
   c->have_q = false;
   c->incr_seen = 0;
   launch_incr_init(I, c->p.n_c, nullptr);
+  launch_incr_set_budget(I, budget, nullptr);
   return hip_check(c, "incremental enable");
+}
+
+int af_incremental_c2f(af_ctx *c, double coarse_deg, double fine_deg, double radius_m) {
+  if (!c) return AF_EINVAL;
+  if (!c->incr_on) return fail(c, AF_EINVAL, "incremental mode not enabled");
+  if (c->last_frame >= 0 || c->n_points > 0)
+    return fail(c, AF_EINVAL, "the coarse-to-fine search is set before the first frame");
+  const double r = radius_m / c->cfg.voxel;
+  if (!(coarse_deg > 0 && coarse_deg <= 180) || !(fine_deg > 0 && fine_deg <= 180) ||
+      !(radius_m > 0) || !(r <= 64.0))
+    return fail(c, AF_EINVAL, "bad coarse-to-fine parameters (radius at most 64 voxels)");
+  IncrDev &I = c->incr;
+  const ToolDev &t = c->tools[c->incr_tool];
+  const int32_t K = t.K, mw = (K + 63) / 64;
+  std::vector<double> rot(9 * (size_t)K);
+  HIP_TRY(c, hipMemcpy(rot.data(), t.rot, sizeof(double) * rot.size(), hipMemcpyDeviceToHost));
+  auto dir = [&](int k, int i) { return rot[9 * (size_t)k + 3 * i]; };
+  auto dot = [&](int a, int b) {
+    return (dir(a, 0) * dir(b, 0) + dir(a, 1) * dir(b, 1)) + dir(a, 2) * dir(b, 2);
+  };
+  // coarse pass: greedy in index order, a direction at least coarse_deg from
+  // every direction taken before is taken; orientations sharing a taken
+  // direction belong to the pass as well
+  const double cc = std::cos(coarse_deg * (M_PI / 180.0));
+  const double cf = std::cos(fine_deg * (M_PI / 180.0));
+  std::vector<int> taken;
+  std::vector<uint64_t> coarse(mw, 0ull), fine((size_t)K * mw, 0ull);
+  for (int k = 0; k < K; ++k) {
+    bool same = false, far = true;
+    for (int q : taken) {
+      if (dir(k, 0) == dir(q, 0) && dir(k, 1) == dir(q, 1) && dir(k, 2) == dir(q, 2)) same = true;
+      if (!(dot(k, q) <= cc + 1e-12)) far = false;
+    }
+    if (same || far) {
+      if (!same) taken.push_back(k);
+      coarse[k >> 6] |= 1ull << (k & 63);
+    }
+  }
+  for (int a = 0; a < K; ++a)
+    for (int k = 0; k < K; ++k)
+      if (dot(k, a) >= cf - 1e-12) fine[(size_t)a * mw + (k >> 6)] |= 1ull << (k & 63);
+  // neighbour offsets within the radius, nearest first, ties by (dz, dy, dx)
+  const int64_t r2 = (int64_t)std::floor(r * r + 1e-9);
+  const int rc = (int)std::floor(std::sqrt((double)r2));
+  std::vector<std::array<int, 4>> offs;
+  for (int z = -rc; z <= rc; ++z)
+    for (int y = -rc; y <= rc; ++y)
+      for (int x = -rc; x <= rc; ++x) {
+        const int d2 = x * x + y * y + z * z;
+        if (d2 > 0 && d2 <= r2) offs.push_back({d2, z, y, x});
+      }
+  std::sort(offs.begin(), offs.end());
+  std::vector<uint32_t> packed(offs.size());
+  for (size_t e = 0; e < offs.size(); ++e)
+    packed[e] = (uint32_t)(offs[e][3] + 512) | ((uint32_t)(offs[e][2] + 512) << 10) |
+                ((uint32_t)(offs[e][1] + 512) << 20);
+  if (I.c2f_on) {
+    dev_free(c, I.c2f_coarse, sizeof(uint64_t) * I.c2f_mw);
+    dev_free(c, I.c2f_fine, sizeof(uint64_t) * (size_t)K * I.c2f_mw);
+    dev_free(c, I.c2f_off, sizeof(uint32_t) * std::max(1, I.c2f_n_off));
+    I.c2f_on = 0;
+  }
+  ALLOC(c, I.c2f_coarse, mw);
+  ALLOC(c, I.c2f_fine, (int64_t)K * mw);
+  ALLOC(c, I.c2f_off, std::max<int64_t>(1, (int64_t)packed.size()));
+  if (!I.n_resolved) ALLOC(c, I.n_resolved, 1);
+  HIP_TRY(c, hipMemcpy(I.c2f_coarse, coarse.data(), sizeof(uint64_t) * mw, hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(I.c2f_fine, fine.data(), sizeof(uint64_t) * fine.size(),
+                       hipMemcpyHostToDevice));
+  if (!packed.empty())
+    HIP_TRY(c, hipMemcpy(I.c2f_off, packed.data(), sizeof(uint32_t) * packed.size(),
+                         hipMemcpyHostToDevice));
+  I.c2f_mw = mw;
+  I.c2f_n_off = (int32_t)packed.size();
+  I.c2f_on = 1;
+  return AF_OK;
+}
+
+// The resolved-voxel plane of the coarse-to-fine search, sized to the grid.
+static int c2f_plane(af_ctx *c) {
+  IncrDev &I = c->incr;
+  if (!I.c2f_on || c->grid_bricks <= c->c2f_plane_bricks) return AF_OK;
+  if (I.resolved) dev_free(c, I.resolved, sizeof(uint32_t) * 16 * c->c2f_plane_bricks);
+  I.resolved = nullptr;
+  c->c2f_plane_bricks = 0;
+  ALLOC(c, I.resolved, 16 * c->grid_bricks);
+  c->c2f_plane_bricks = c->grid_bricks;
+  return AF_OK;
+}
+
+int af_incremental_budget(af_ctx *c, int64_t lookup_target, int32_t b_min, int32_t b_max) {
+  if (!c) return AF_EINVAL;
+  if (!c->incr_on) return fail(c, AF_EINVAL, "incremental mode not enabled");
+  if (c->last_frame >= 0 || c->n_points > 0)
+    return fail(c, AF_EINVAL, "the budget rule is set before the first frame");
+  if (lookup_target < 0 || lookup_target > ((int64_t)1 << 40) || b_min < 1 || b_max < b_min)
+    return fail(c, AF_EINVAL, "bad budget rule (target %lld, [%d, %d])",
+                (long long)lookup_target, b_min, b_max);
+  IncrDev &I = c->incr;
+  b_max = (int32_t)std::min<int64_t>(b_max, c->cfg.max_points);
+  b_min = std::min(b_min, b_max);
+  if (b_max > I.budget) {
+    HIP_TRY(c, hipDeviceSynchronize());
+    dev_free(c, I.sel, sizeof(int32_t) * I.budget);
+    dev_free(c, I.score_new, I.budget);
+    I.sel = nullptr;
+    I.score_new = nullptr;
+    I.budget = 0;
+    ALLOC(c, I.sel, b_max);
+    ALLOC(c, I.score_new, b_max);
+    I.budget = b_max;
+  }
+  I.lookup_target = lookup_target;
+  I.b_min = b_min;
+  I.b_max = b_max;
+  const int32_t first = std::min(std::max(c->incr_budget0, b_min), b_max);
+  launch_incr_set_budget(I, first, nullptr);
+  return hip_check(c, "incremental budget");
 }
 
 int af_incremental_frame(af_ctx *c, const float *xyz, int64_t n, const float origin[3],
@@ -1393,6 +1581,7 @@ int af_incremental_frame(af_ctx *c, const float *xyz, int64_t n, const float ori
     }
   }
   IncrDev &I = c->incr;
+  if ((rc = c2f_plane(c)) != AF_OK) return rc;
   launch_incr_frame_front(c->pts, c->map, I, c->incr_changed, c->counters, c->n_points,
                           c->incr_seen, (int32_t)frame_id, moved, c->p.conf_min_w, s);
   c->incr_seen = c->n_points;
@@ -1403,10 +1592,40 @@ int af_incremental_frame(af_ctx *c, const float *xyz, int64_t n, const float ori
   HIP_TRY(c, hipMemsetAsync(t.counters, 0, sizeof(ScoreCounters), s));
   launch_normals(c->p, c->map, ps, c->grid, I.budget, s, true);
   launch_mask(c->p, ps, t, c->grid, I.budget, s, true);
+  launch_incr_c2f(c->pts, t, c->grid, I, c->n_points, c->grid_bricks, c->p.n_c, s);
+  launch_score(c->p, ps, t, c->grid, I.budget, score_variant_default(), c->work, s, true);
+  launch_incr_frame_back(ps, c->map, t, c->grid, I, c->n_points, c->p.n_c, s);
+  launch_incr_budget(I, t, s);
+  c->last_stream = s;
+  return hip_check(c, "incremental frame");
+}
+
+int af_incremental_drain(af_ctx *c, int32_t max_evals, void *stream) {
+  if (!c) return AF_EINVAL;
+  if (!c->incr_on) return fail(c, AF_EINVAL, "incremental mode not enabled");
+  IncrDev &I = c->incr;
+  if (max_evals < 0 || max_evals > I.budget)
+    return fail(c, AF_EINVAL, "max_evals %d outside [0, %d]", max_evals, I.budget);
+  if (c->graph_dirty) {
+    const int rc = graph_settle(c);
+    if (rc != AF_OK) return rc;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  PointsDev ps = c->pts;
+  ps.sel = I.sel;
+  ps.n_sel = I.n_sel;
+  ToolDev &t = c->tools[c->incr_tool];
+  int rc = c2f_plane(c);
+  if (rc != AF_OK) return rc;
+  launch_incr_drain_front(c->pts, c->map, I, c->n_points, max_evals, c->p.conf_min_w, s);
+  HIP_TRY(c, hipMemsetAsync(t.counters, 0, sizeof(ScoreCounters), s));
+  launch_normals(c->p, c->map, ps, c->grid, I.budget, s, true);
+  launch_mask(c->p, ps, t, c->grid, I.budget, s, true);
+  launch_incr_c2f(c->pts, t, c->grid, I, c->n_points, c->grid_bricks, c->p.n_c, s);
   launch_score(c->p, ps, t, c->grid, I.budget, score_variant_default(), c->work, s, true);
   launch_incr_frame_back(ps, c->map, t, c->grid, I, c->n_points, c->p.n_c, s);
   c->last_stream = s;
-  return hip_check(c, "incremental frame");
+  return hip_check(c, "incremental drain");
 }
 
 int af_incremental_stats(af_ctx *c, af_incr_stats *st) {
@@ -1425,9 +1644,12 @@ int af_incremental_stats(af_ctx *c, af_incr_stats *st) {
   st->trig_iii = h.trig_iii;
   st->changed = nch;
   st->sampled = h.sampled;
+  int32_t cap = 0;
+  HIP_TRY(c, hipMemcpy(&cap, c->incr.budget_dev, sizeof(int32_t), hipMemcpyDeviceToHost));
   st->queued = h.queued;
   st->evaluated = nsel;
   st->backlog = (int64_t)h.queued - nsel;
+  st->budget = cap;
   return AF_OK;
 }
 

@@ -329,8 +329,9 @@ __global__ void __launch_bounds__(kSelT) k_incr_sel_scan(IncrDev I, int64_t nblk
   }
   if (t == kSelT - 1) {
     const int total = part[kSelT - 1];
+    const int cap = *I.budget_dev;
     I.ctr->selectable = total;
-    *I.n_sel = total < I.budget ? total : I.budget;
+    *I.n_sel = total < cap ? total : cap;
   }
 }
 
@@ -356,7 +357,7 @@ k_incr_sel_write(PointsDev pts, MapDev m, IncrDev I, int64_t n, int32_t min_w) {
   __syncthreads();
   if (f) {
     const int rank = I.bsum[blockIdx.x] + wave_base[w] + __popcll(b & ((1ull << lane) - 1ull));
-    if (rank < I.budget) {
+    if (rank < *I.budget_dev) {
       I.sel[rank] = (int32_t)i;
       I.pending[i] = 0u;
     }
@@ -447,6 +448,94 @@ k_incr_labels(PointsDev pts, MapDev m, IncrDev I, int64_t n, int32_t n_c) {
   I.label[i] = lb;
 }
 
+// The next frame's cap from this frame's evaluation cost (one thread): n
+// points evaluated for L canonical lookups give lookup_target * n / L,
+// clamped; nothing evaluated, or no lookup, keeps the cap.
+__global__ void k_incr_budget(IncrDev I, const ScoreCounters *sc) {
+  const unsigned long long n = (unsigned long long)*I.n_sel;
+  unsigned long long L = 0;
+  for (int k = 0; k < kStatSlots; ++k) L += sc->s[k].canonical_lookups;
+  if (n == 0 || L == 0) return;
+  const unsigned long long want = (unsigned long long)I.lookup_target * n / L;
+  const int32_t b = want < (unsigned long long)I.b_min   ? I.b_min
+                    : want > (unsigned long long)I.b_max ? I.b_max
+                                                         : (int32_t)want;
+  *I.frame_budget = b;
+}
+
+// Coarse-to-fine search (Section 3.6).  The plane of resolved voxels: a
+// point with a stored free direction (best < n_c) sets its voxel's bit.
+__global__ void __launch_bounds__(kT) k_c2f_mark(PointsDev pts, GridDev g, IncrDev I, int64_t n,
+                                                 int32_t n_c) {
+  const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+  int hit = 0;
+  if (i < n && (int)I.best[i] < n_c) {
+    int32_t x, y, z;
+    unpack_key(pts.key[i], x, y, z);
+    const int bx = (x >> 3) - g.g0[0], by = (y >> 3) - g.g0[1], bz = (z >> 3) - g.g0[2];
+    if ((unsigned)bx < (unsigned)g.gd[0] && (unsigned)by < (unsigned)g.gd[1] &&
+        (unsigned)bz < (unsigned)g.gd[2]) {
+      const int64_t b = ((int64_t)bz * g.gd[1] + by) * g.gd[0] + bx;
+      const int lin = (x & 7) | ((y & 7) << 3) | ((z & 7) << 6);
+      atomicOr(&I.resolved[b * 16 + (lin >> 5)], 1u << (lin & 31));
+      hit = 1;
+    }
+  }
+  wg_add<kT>(hit, I.n_resolved);
+}
+
+// One thread per listed point: the nearest resolved other point within the
+// radius (offsets in (|d|^2, dz, dy, dx) order, the first set bit wins), its
+// stored direction k*, and the mask restricted to the coarse pass and k*'s
+// fine window.  The candidate count drops by the bits removed.
+__global__ void __launch_bounds__(kT) k_c2f_restrict(PointsDev pts, ToolDev t, GridDev g,
+                                                     IncrDev I) {
+  const int n = *I.n_sel;
+  const int64_t j = (int64_t)blockIdx.x * kT + threadIdx.x;
+  int removed = 0;
+  if (j < n) {
+    const int32_t i = I.sel[j];
+    int32_t x, y, z;
+    unpack_key(pts.key[i], x, y, z);
+    int kstar = -1;
+    if (*I.n_resolved > 0) {
+      for (int e = 0; e < I.c2f_n_off; ++e) {
+        const uint32_t o = I.c2f_off[e];
+        const int xx = x + (int)(o & 1023u) - 512, yy = y + (int)((o >> 10) & 1023u) - 512,
+                  zz = z + (int)(o >> 20) - 512;
+        const int bx = (xx >> 3) - g.g0[0], by = (yy >> 3) - g.g0[1], bz = (zz >> 3) - g.g0[2];
+        if ((unsigned)bx >= (unsigned)g.gd[0] || (unsigned)by >= (unsigned)g.gd[1] ||
+            (unsigned)bz >= (unsigned)g.gd[2])
+          continue;
+        const int64_t b = ((int64_t)bz * g.gd[1] + by) * g.gd[0] + bx;
+        const int lin = (xx & 7) | ((yy & 7) << 3) | ((zz & 7) << 6);
+        if (!((I.resolved[b * 16 + (lin >> 5)] >> (lin & 31)) & 1u)) continue;
+        const int32_t slot = hash_find(pts.h, pack_key(xx, yy, zz));
+        const int32_t pi = slot >= 0 ? pts.h.vals[slot] : -1;
+        if (pi >= 0) kstar = I.best_dir[pi];
+        break;
+      }
+    }
+    const int mw = I.c2f_mw;
+    for (int w = 0; w < mw; ++w) {
+      uint64_t allow = I.c2f_coarse[w];
+      if (kstar >= 0) allow |= I.c2f_fine[(int64_t)kstar * mw + w];
+      const uint64_t m = t.mask[(int64_t)i * mw + w];
+      removed += __popcll(m & ~allow);
+      t.mask[(int64_t)i * mw + w] = m & allow;
+    }
+  }
+  // the candidate tests the mask kernel counted for removed orientations
+  for (int off = 32; off > 0; off >>= 1) removed += __shfl_xor(removed, off);
+  if ((threadIdx.x & 63) == 0 && removed)
+    atomicAdd(&t.counters->s[(blockIdx.x * (kT / 64) + (threadIdx.x >> 6)) % kStatSlots]
+                   .candidate_tests,
+              (unsigned long long)(-(long long)removed));
+}
+
+// Copy one device int to another (the cap for a frame's selection).
+__global__ void k_incr_copy_int(const int32_t *src, int32_t *dst) { *dst = *src; }
+
 unsigned grid_of(int64_t n, int per) { return (unsigned)std::max<int64_t>(1, (n + per - 1) / per); }
 
 }  // namespace
@@ -456,11 +545,60 @@ void launch_incr_init(const IncrDev &I, int32_t n_c, hipStream_t s) {
                      dim3(kT), 0, s, I, n_c);
 }
 
+static void launch_select(PointsDev pts, MapDev m, const IncrDev &I, int64_t n_points,
+                          int32_t min_w, hipStream_t s) {
+  if (n_points > 0) {
+    const int64_t nblk = (n_points + kSelT - 1) / kSelT;
+    hipLaunchKernelGGL(k_incr_sel_count, dim3((unsigned)nblk), dim3(kSelT), 0, s, pts, m, I,
+                       n_points, min_w);
+    hipLaunchKernelGGL(k_incr_sel_scan, dim3(1), dim3(kSelT), 0, s, I, nblk);
+    hipLaunchKernelGGL(k_incr_sel_write, dim3((unsigned)nblk), dim3(kSelT), 0, s, pts, m, I,
+                       n_points, min_w);
+  } else {
+    hipLaunchKernelGGL(k_incr_fill, dim3(1), dim3(kT), 0, s, (uint32_t *)I.n_sel, (int64_t)1, 0u);
+  }
+}
+
+void launch_incr_drain_front(PointsDev pts, MapDev m, const IncrDev &I, int64_t n_points,
+                             int32_t max_evals, int32_t min_w, hipStream_t s) {
+  hipLaunchKernelGGL(k_incr_fill, dim3(1), dim3(kT), 0, s, (uint32_t *)I.ctr,
+                     (int64_t)(sizeof(IncrCounters) / 4), 0u);
+  hipLaunchKernelGGL(k_incr_fill, dim3(1), dim3(kT), 0, s, (uint32_t *)I.budget_dev, (int64_t)1,
+                     (uint32_t)max_evals);
+  launch_select(pts, m, I, n_points, min_w, s);
+}
+
+void launch_incr_set_budget(const IncrDev &I, int32_t b, hipStream_t s) {
+  hipLaunchKernelGGL(k_incr_fill, dim3(1), dim3(kT), 0, s, (uint32_t *)I.frame_budget, (int64_t)1,
+                     (uint32_t)b);
+  hipLaunchKernelGGL(k_incr_fill, dim3(1), dim3(kT), 0, s, (uint32_t *)I.budget_dev, (int64_t)1,
+                     (uint32_t)b);
+}
+
+void launch_incr_c2f(PointsDev pts, ToolDev t, GridDev g, const IncrDev &I, int64_t n_points,
+                     int64_t grid_bricks, int32_t n_c, hipStream_t s) {
+  if (!I.c2f_on) return;
+  hipLaunchKernelGGL(k_incr_fill, dim3(1), dim3(kT), 0, s, (uint32_t *)I.n_resolved, (int64_t)1,
+                     0u);
+  if (grid_bricks > 0) {
+    hipLaunchKernelGGL(k_incr_fill, dim3(1024), dim3(kT), 0, s, I.resolved, grid_bricks * 16, 0u);
+    if (n_points > 0)
+      hipLaunchKernelGGL(k_c2f_mark, dim3(grid_of(n_points, kT)), dim3(kT), 0, s, pts, g, I,
+                         n_points, n_c);
+  }
+  hipLaunchKernelGGL(k_c2f_restrict, dim3(grid_of(I.budget, kT)), dim3(kT), 0, s, pts, t, g, I);
+}
+
+void launch_incr_budget(const IncrDev &I, const ToolDev &t, hipStream_t s) {
+  if (I.lookup_target > 0) hipLaunchKernelGGL(k_incr_budget, dim3(1), dim3(1), 0, s, I, t.counters);
+}
+
 void launch_incr_frame_front(PointsDev pts, MapDev m, const IncrDev &I, const int32_t *changed,
                              const FrameCounters *fc, int64_t n_points, int64_t seen, int32_t frame,
                              bool moved, int32_t min_w, hipStream_t s) {
   hipLaunchKernelGGL(k_incr_fill, dim3(1), dim3(kT), 0, s, (uint32_t *)I.ctr,
                      (int64_t)(sizeof(IncrCounters) / 4), 0u);
+  hipLaunchKernelGGL(k_incr_copy_int, dim3(1), dim3(1), 0, s, I.frame_budget, I.budget_dev);
   hipLaunchKernelGGL(k_incr_fill, dim3(256), dim3(kT), 0, s, I.hist, (int64_t)2 * 65536, 0u);
   if (n_points > 0)
     hipLaunchKernelGGL(k_incr_triggers, dim3(grid_of(n_points, kT)), dim3(kT), 0, s, pts, m, I,
@@ -473,16 +611,7 @@ void launch_incr_frame_front(PointsDev pts, MapDev m, const IncrDev &I, const in
   hipLaunchKernelGGL(k_incr_collect, wide, dim3(kT), 0, s, m, changed, fc, frame, I);
   hipLaunchKernelGGL(k_incr_sort, dim3(1), dim3(kSelT), 0, s, I);
   hipLaunchKernelGGL(k_incr_neigh, dim3(kSample), dim3(384), 0, s, pts, I, n_points);
-  if (n_points > 0) {
-    const int64_t nblk = (n_points + kSelT - 1) / kSelT;
-    hipLaunchKernelGGL(k_incr_sel_count, dim3((unsigned)nblk), dim3(kSelT), 0, s, pts, m, I,
-                       n_points, min_w);
-    hipLaunchKernelGGL(k_incr_sel_scan, dim3(1), dim3(kSelT), 0, s, I, nblk);
-    hipLaunchKernelGGL(k_incr_sel_write, dim3((unsigned)nblk), dim3(kSelT), 0, s, pts, m, I,
-                       n_points, min_w);
-  } else {
-    hipLaunchKernelGGL(k_incr_fill, dim3(1), dim3(kT), 0, s, (uint32_t *)I.n_sel, (int64_t)1, 0u);
-  }
+  launch_select(pts, m, I, n_points, min_w, s);
 }
 
 void launch_incr_frame_back(PointsDev pts, MapDev m, ToolDev t, GridDev g, const IncrDev &I,

@@ -295,8 +295,26 @@ struct IncrDev {
   int64_t *cand_k;
   int64_t *sampled;       // [256] sampled changed voxels (keys)
   IncrCounters *ctr;
+  int32_t *budget_dev;    // the cap the selection applies (this frame's, or a drain's)
+  int32_t *frame_budget;  // the frames' cap (fixed, or adapted after every frame)
   int64_t max_points;
-  int32_t budget;
+  int32_t budget;         // capacity of sel / score_new: the largest cap
+  // adaptive cap: after a frame that evaluated n > 0 points for L > 0
+  // canonical lookups, frame_budget = clamp(lookup_target * n / L, b_min,
+  // b_max); lookup_target 0 keeps the cap fixed
+  int64_t lookup_target;
+  int32_t b_min, b_max;
+  // coarse-to-fine direction search (Section 3.6), when c2f_on: the coarse
+  // pass [mw] and the fine window of every orientation [K][mw] as allowed-
+  // orientation masks; the neighbour offsets within the search radius
+  // (x + 512 | (y + 512) << 10 | (z + 512) << 20), sorted by
+  // (|d|^2, dz, dy, dx), zero excluded; a bit plane over the brick grid
+  // (16 words per brick) of the resolved points' voxels, and their count
+  int32_t c2f_on, c2f_mw, c2f_n_off;
+  uint64_t *c2f_coarse, *c2f_fine;
+  uint32_t *c2f_off;
+  uint32_t *resolved;
+  int32_t *n_resolved;
 };
 void launch_incr_init(const IncrDev &I, int32_t n_c, hipStream_t s);
 void launch_incr_frame_front(PointsDev pts, MapDev m, const IncrDev &I, const int32_t *changed,
@@ -304,6 +322,19 @@ void launch_incr_frame_front(PointsDev pts, MapDev m, const IncrDev &I, const in
                              bool moved, int32_t min_w, hipStream_t s);
 void launch_incr_frame_back(PointsDev pts, MapDev m, ToolDev t, GridDev g, const IncrDev &I,
                             int64_t n_points, int32_t n_c, hipStream_t s);
+// Selection only (no trigger): a drain's list of up to max_evals queued points.
+void launch_incr_drain_front(PointsDev pts, MapDev m, const IncrDev &I, int64_t n_points,
+                             int32_t max_evals, int32_t min_w, hipStream_t s);
+// Coarse-to-fine restriction of the listed points' candidate masks: mark the
+// resolved points in the plane (cleared first, grid_bricks bricks), then
+// AND each listed point's mask with the coarse pass and the fine window of
+// its nearest resolved neighbour's stored direction.
+void launch_incr_c2f(PointsDev pts, ToolDev t, GridDev g, const IncrDev &I, int64_t n_points,
+                     int64_t grid_bricks, int32_t n_c, hipStream_t s);
+// Set the frames' cap (and the selection's) to b.
+void launch_incr_set_budget(const IncrDev &I, int32_t b, hipStream_t s);
+// After a frame's evaluation: the next frame's cap from its cost.
+void launch_incr_budget(const IncrDev &I, const ToolDev &t, hipStream_t s);
 
 // Smoothed clearance score.  T9: apron bricks of 9^3 floats (a brick's 8^3
 // voxels and the first layer of its +1 neighbours; tau where unmapped);
@@ -392,6 +423,29 @@ void launch_score_multi(const Params &p, PointsDev pts, const ToolDev *tools_dev
                         unsigned *work, hipStream_t s, bool dev_n = false);
 void launch_score(const Params &p, PointsDev pts, ToolDev t, GridDev g, int64_t n_points,
                   int variant, unsigned *work, hipStream_t s, bool dev_n = false);
+// One job of a cross-map scoring launch: every point of one context's map
+// (its point count read on the device) against one of its tools.
+struct ScoreJob {
+  Params p;
+  PointsDev pts;
+  ToolDev t;
+  GridDev g;
+  int32_t base;        // offset of the tool's begin offsets in the launch's LDS
+  int32_t pad;
+  int64_t max_points;  // capacity of the map (sizes the launch)
+};
+constexpr int kMaxJobs = 64;
+// One persistent launch over n_jobs jobs (jobs_dev: their device copy);
+// -1 when a tool has more than kNearK orientations or the tables exceed LDS.
+int launch_score_jobs(const ScoreJob *jobs_dev, const ScoreJob *jobs_host, int32_t n_jobs,
+                      unsigned *work, hipStream_t s);
+// For the server: record a context's frame graph without its scoring launch
+// (integration, normals and masks of the tools), and describe its scoring
+// jobs (one per tool) for a cross-map launch.
+int ctx_graph_prepare_unscored(af_ctx *c, const float lo[3], const float hi[3],
+                               int64_t max_returns, const int32_t *tool_ids, int32_t n_tools,
+                               void *stream);
+int ctx_score_jobs(af_ctx *c, const int32_t *tool_ids, int32_t n_tools, ScoreJob *out);
 int score_variants();
 int score_variant_default();
 // whether the configuration (after its fallbacks for this tool) honours PointsDev::sel

@@ -1541,6 +1541,69 @@ k_score_near_multi(Params p, PointsDev pts, const ToolDev *tools, ToolSet set, G
   if (cur >= 0) near_flush<0>(t.counters->s[slot], a, lane);
 }
 
+// Several maps in one persistent launch (a server step's streams): job j
+// scores every point of one context's map for one of its tools, with that
+// context's constants, points, grid and table.  Work item w is point
+// w - start[j] of the job j whose range holds it (job-major); the jobs'
+// point counts are read on the device (their frames were just integrated).
+// Every job's begin offsets are staged in LDS at jobs[j].base.  Same results
+// as one k_score_near launch per job.
+template <int NT, int UN, int FB, int CO, int B1, int PF, int RE>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8)))
+k_score_near_jobs(const ScoreJob *jobs, int32_t n_jobs, unsigned *work) {
+  constexpr int NW = NT / 64;
+  extern __shared__ uint32_t s_begin[];   // sized for the jobs at launch
+  for (int j = 0; j < n_jobs; ++j) {
+    const uint32_t *bg = jobs[j].t.begin;
+    const int K = jobs[j].t.K, o = jobs[j].base;
+    for (int k = threadIdx.x; k <= K; k += NT) s_begin[o + k] = bg[k];
+  }
+  __syncthreads();
+  const int lane = lane_id();
+  const int slot = (blockIdx.x * NW + (threadIdx.x >> 6)) % kStatSlots;
+  // lane j < n_jobs: job j's first work item (exclusive prefix of the counts)
+  const int64_t cnt = lane < n_jobs ? (int64_t)*jobs[lane].pts.n_points : 0;
+  int64_t incl = cnt;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int64_t v = __shfl_up(incl, off);
+    if (lane >= off) incl += v;
+  }
+  const int64_t start = incl - cnt;
+  const int64_t total = __shfl(incl, 63);
+  NearAcc a = near_acc_zero();
+  int64_t w = 0, batch_end = 0;
+  int cur = -1;
+  const ScoreJob *jp = jobs;   // the current job (read in place: wave-uniform loads)
+  SwGrid q;
+  int32_t mw = 0;
+  int64_t j0 = 0;
+  for (;;) {
+    if (w >= batch_end) {
+      unsigned got = 0;
+      if (lane == 0) got = atomicAdd(work, (unsigned)FB);
+      w = (int64_t)__builtin_amdgcn_readfirstlane(__shfl(got, 0));
+      batch_end = w + FB;
+    }
+    if (w >= total) break;
+    // the job whose range holds w: the last job starting at or before it
+    // (jobs with no point share a start with the next one and are skipped)
+    const uint64_t le = __ballot(lane < n_jobs && cnt > 0 && start <= w);
+    const int ji = 63 - __clzll((long long)le);
+    if (ji != cur) {
+      if (cur >= 0) near_flush<0>(jp->t.counters->s[slot], a, lane);
+      cur = ji;
+      jp = jobs + __builtin_amdgcn_readfirstlane(ji);
+      q = sw_grid(jp->g);
+      mw = (jp->t.K + 63) / 64;
+      j0 = __shfl(start, ji);
+    }
+    near_point<UN, CO, B1, PF, RE>(jp->p, jp->pts, jp->t, jp->g, q, s_begin + jp->base, mw,
+                                   w - j0, lane, a);
+    ++w;
+  }
+  if (cur >= 0) near_flush<0>(jp->t.counters->s[slot], a, lane);
+}
+
 using ScoreKernel = void (*)(Params, PointsDev, ToolDev, GridDev, int64_t, int32_t, unsigned *);
 
 struct ScoreVariant {
@@ -1708,6 +1771,44 @@ void launch_score_multi(const Params &p, PointsDev pts, const ToolDev *tools_dev
   hipLaunchKernelGGL(k_zero, dim3(1), dim3(1), 0, s, work);
   hipLaunchKernelGGL(fn, dim3((unsigned)wg), dim3(256), lds, s, p, pts, tools_dev, set, g,
                      dev_n ? (int64_t)-1 : n, work);
+}
+
+int launch_score_jobs(const ScoreJob *jobs_dev, const ScoreJob *jobs_host, int32_t n_jobs,
+                      unsigned *work, hipStream_t s) {
+  if (n_jobs <= 0) return 0;
+  if (n_jobs > kMaxJobs) return -1;
+  bool rel = true;
+  int64_t words = 0, np = 0;
+  for (int j = 0; j < n_jobs; ++j) {
+    rel = rel && jobs_host[j].t.rent != nullptr;
+    words += jobs_host[j].t.K + 1;
+    if (jobs_host[j].t.K > kNearK) return -1;
+    np += jobs_host[j].max_points;
+  }
+  using JobKernel = void (*)(const ScoreJob *, int32_t, unsigned *);
+  const JobKernel fn = rel ? k_score_near_jobs<256, 1, 8, 2, 1, 1, 1>
+                           : k_score_near_jobs<256, 1, 8, 2, 1, 1, 0>;
+  if (g_num_cu == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    if (hipDeviceGetAttribute(&g_num_cu, hipDeviceAttributeMultiprocessorCount, dev) !=
+            hipSuccess ||
+        g_num_cu <= 0)
+      g_num_cu = 256;
+  }
+  const size_t lds = sizeof(uint32_t) * (size_t)words;
+  if (lds > 64 * 1024) return -1;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, lds) != hipSuccess ||
+      per_cu <= 0)
+    per_cu = 1;
+  int64_t wg = (int64_t)per_cu * g_num_cu;
+  const int64_t need = (np + 3) / 4;
+  if (wg > need) wg = need;
+  if (wg < 1) wg = 1;
+  hipLaunchKernelGGL(k_zero, dim3(1), dim3(1), 0, s, work);
+  hipLaunchKernelGGL(fn, dim3((unsigned)wg), dim3(256), lds, s, jobs_dev, n_jobs, work);
+  return 0;
 }
 
 static int effective_variant(int variant, const ToolDev &t) {

@@ -6,8 +6,12 @@
 // device memory between frames), a HIP stream, a recorded frame graph
 // (integration followed by scoring of the stream's tools) and a small queue
 // of pinned host slots that hold frames as they arrive.  One step takes the
-// oldest queued frame of every stream, launches all of them on their own HIP
-// streams (the GPU overlaps them), then waits for each and reports its status.
+// oldest queued frame of every stream and launches each stream's recorded
+// integration (with its normals and candidate masks) on its own HIP stream;
+// in batched mode (the default) one scoring launch then labels the points of
+// every stream that took a frame, each against its own map and tools, after
+// which every stream reads its counts back.  Without batching each stream's
+// graph also holds its own scoring launch and the GPU overlaps the streams.
 //
 // Admission reserves the stream's declared device budget (af_config.
 // hbm_budget) against the server's budget.  A context never allocates beyond
@@ -24,6 +28,7 @@
 #include <vector>
 
 #include "af.h"
+#include "af_internal.h"
 
 namespace {
 
@@ -41,6 +46,9 @@ struct Served {
   bool used = false;
   af_ctx *ctx = nullptr;
   hipStream_t hs = nullptr;
+  hipEvent_t done = nullptr;   // the stream's integration of this step (batched mode)
+  std::vector<int32_t> tools;  // tools its frames are scored for
+  bool batched = false;        // graph recorded without scoring
   int64_t reserved = 0;
   int64_t max_returns = 0;   // 0 until the frame graph is recorded
   int64_t last_id = -1;      // last frame id queued
@@ -56,6 +64,12 @@ struct af_server {
   int64_t reserved = 0;
   int32_t rr = 0;   // stream visited first by the next step (round robin)
   std::vector<Served> streams;
+  bool batch = true;             // one scoring launch per step across streams
+  hipStream_t bs = nullptr;      // the batched scoring launch's stream
+  hipEvent_t scored = nullptr;   // recorded after it
+  af::ScoreJob *jobs_host = nullptr;   // pinned, kMaxJobs
+  af::ScoreJob *jobs_dev = nullptr;
+  unsigned *work = nullptr;
   char err[256] = "no error";
 };
 
@@ -67,6 +81,19 @@ int sfail(af_server *s, int rc, const char *fmt, ...) {
   vsnprintf(s->err, sizeof(s->err), fmt, ap);
   va_end(ap);
   return rc;
+}
+
+// The batched launch's stream, event, job tables and work counter (made on
+// the first prepare in batched mode).
+int batch_resources(af_server *s) {
+  if (s->bs) return AF_OK;
+  if (hipStreamCreateWithFlags(&s->bs, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&s->scored, hipEventDisableTiming) != hipSuccess ||
+      hipHostMalloc((void **)&s->jobs_host, sizeof(af::ScoreJob) * af::kMaxJobs) != hipSuccess ||
+      hipMalloc((void **)&s->jobs_dev, sizeof(af::ScoreJob) * af::kMaxJobs) != hipSuccess ||
+      hipMalloc((void **)&s->work, 64) != hipSuccess)
+    return sfail(s, AF_EDEVICE, "batched scoring resources");
+  return AF_OK;
 }
 
 Served *get(af_server *s, int32_t id) {
@@ -96,12 +123,23 @@ int af_server_create(int64_t hbm_budget, int32_t max_streams, af_server **out) {
   return AF_OK;
 }
 
+int af_server_batch(af_server *s, int32_t on) {
+  if (!s) return AF_EINVAL;
+  for (const Served &t : s->streams)
+    if (t.used && t.max_returns)
+      return sfail(s, AF_EINVAL, "choose the mode before any stream is prepared");
+  s->batch = on != 0;
+  return AF_OK;
+}
+
 int af_server_release(af_server *s, int32_t id) {
   Served *t = get(s, id);
   if (!t) return s ? sfail(s, AF_EINVAL, "stream %d is not admitted", id) : AF_EINVAL;
   hipStreamSynchronize(t->hs);
+  if (s->bs) hipStreamSynchronize(s->bs);
   af_destroy(t->ctx);
   hipStreamDestroy(t->hs);
+  if (t->done) hipEventDestroy(t->done);
   free_slots(*t);
   s->reserved -= t->reserved;
   *t = Served();
@@ -112,6 +150,12 @@ int af_server_destroy(af_server *s) {
   if (!s) return AF_EINVAL;
   for (int32_t i = 0; i < (int32_t)s->streams.size(); ++i)
     if (s->streams[i].used) af_server_release(s, i);
+  if (s->bs) hipStreamSynchronize(s->bs);
+  if (s->jobs_dev) hipFree(s->jobs_dev);
+  if (s->work) hipFree(s->work);
+  if (s->jobs_host) hipHostFree(s->jobs_host);
+  if (s->scored) hipEventDestroy(s->scored);
+  if (s->bs) hipStreamDestroy(s->bs);
   delete s;
   return AF_OK;
 }
@@ -137,7 +181,9 @@ int af_server_admit(af_server *s, const af_config *cfg, int32_t *id) {
   Served t;
   int rc = af_create(cfg, &t.ctx);
   if (rc != AF_OK) return sfail(s, rc, "context creation failed (%d)", rc);
-  if (hipStreamCreateWithFlags(&t.hs, hipStreamNonBlocking) != hipSuccess) {
+  if (hipStreamCreateWithFlags(&t.hs, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&t.done, hipEventDisableTiming) != hipSuccess) {
+    if (t.hs) hipStreamDestroy(t.hs);
     af_destroy(t.ctx);
     return sfail(s, AF_EDEVICE, "stream creation failed");
   }
@@ -168,8 +214,16 @@ int af_server_prepare(af_server *s, int32_t id, const float lo[3], const float h
   hipStreamSynchronize(t->hs);
   free_slots(*t);
   t->max_returns = 0;
-  int rc = af_graph_prepare(t->ctx, lo, hi, max_returns, tool_ids, n_tools, t->hs);
+  if (s->batch) {
+    const int rc = batch_resources(s);
+    if (rc != AF_OK) return rc;
+  }
+  int rc = s->batch ? af::ctx_graph_prepare_unscored(t->ctx, lo, hi, max_returns, tool_ids,
+                                                     n_tools, t->hs)
+                    : af_graph_prepare(t->ctx, lo, hi, max_returns, tool_ids, n_tools, t->hs);
   if (rc != AF_OK) return sfail(s, rc, "stream %d: %s", id, af_last_error(t->ctx));
+  t->tools.assign(tool_ids, tool_ids + n_tools);
+  t->batched = s->batch;
   for (int i = 0; i < kQueueSlots; ++i) {
     float *p = nullptr;
     if (hipHostMalloc((void **)&p, sizeof(float) * 3 * max_returns) != hipSuccess) {
@@ -238,10 +292,42 @@ int af_server_step(af_server *s, int32_t *stream_ids, int64_t *frame_ids, int32_
     run.push_back({id, rc});
   }
   s->rr = (s->rr + 1) % ns;
+  // batched mode: one scoring launch over every stream that integrated a frame
+  int32_t n_jobs = 0;
+  for (const Launched &l : run) {
+    Served &t = s->streams[l.id];
+    if (l.rc != AF_OK || !t.batched) continue;
+    if (n_jobs + (int32_t)t.tools.size() > af::kMaxJobs) break;
+    af::ctx_score_jobs(t.ctx, t.tools.data(), (int32_t)t.tools.size(), s->jobs_host + n_jobs);
+    n_jobs += (int32_t)t.tools.size();
+    hipEventRecord(t.done, t.hs);
+    hipStreamWaitEvent(s->bs, t.done, 0);
+  }
+  int batch_rc = AF_OK;
+  if (n_jobs > 0) {
+    int32_t words = 0;
+    for (int32_t j = 0; j < n_jobs; ++j) {
+      s->jobs_host[j].base = words;
+      words += s->jobs_host[j].t.K + 1;
+    }
+    if (hipMemcpyAsync(s->jobs_dev, s->jobs_host, sizeof(af::ScoreJob) * n_jobs,
+                       hipMemcpyHostToDevice, s->bs) != hipSuccess ||
+        af::launch_score_jobs(s->jobs_dev, s->jobs_host, n_jobs, s->work, s->bs) != 0 ||
+        hipGetLastError() != hipSuccess)
+      batch_rc = AF_EDEVICE;
+    hipEventRecord(s->scored, s->bs);
+    for (const Launched &l : run)
+      if (l.rc == AF_OK && s->streams[l.id].batched)
+        hipStreamWaitEvent(s->streams[l.id].hs, s->scored, 0);
+  }
   int worst = AF_OK;
   for (Launched &l : run) {
     Served &t = s->streams[l.id];
     int rc = l.rc;
+    if (rc == AF_OK && t.batched && batch_rc != AF_OK) {
+      hipStreamSynchronize(t.hs);
+      rc = batch_rc;
+    }
     if (rc == AF_OK) rc = af_graph_sync(t.ctx);
     else hipStreamSynchronize(t.hs);   // the copy may still read the slot
     const Slot f = t.queue.front();

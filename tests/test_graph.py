@@ -4,7 +4,9 @@ one-launch scoring of four tools -- leaves the map, the points, the labels,
 first free orientations and statistics exactly as af_integrate_frame followed
 by af_score_tools does, frame by frame.  Replays take frames of varying size,
 with eager work, host reads and synchronisations between them, and one frame
-in the middle goes through the eager calls on the same context.  A frame that
+in the middle goes through the eager calls on the same context.  After frame 3
+and the last frame, every tool's labels, first free orientations and canonical
+counts of the recorded context also equal the oracle's.  A frame that
 maps a block beyond the recorded scene box is reported, and the context then
 continues eagerly to the same result.  Tiny scene (v = 2 cm), four tools of
 the batching workload."""
@@ -65,10 +67,35 @@ def _same_map(a, b):
         assert np.array_equal(pa[k], pb[k]), k
 
 
-def test_replays_equal_eager(synth_mod):
+def _same_as_oracle(ctx, orc, rots, where):
+    """Labels and first free orientations of every tool against the oracle
+    fed the same frames (and its canonical counts)."""
+    for i in IDS:
+        K = len(rots[i])
+        orc.score(i)
+        lab = ctx.read_labels(i)
+        r = orc.read_results(K)
+        assert np.array_equal(lab["key"], orc.read_points()["key"]), (where, i)
+        assert np.array_equal(lab["label"], r["label"]), (where, i)
+        assert np.array_equal(lab["first_free"].astype(np.int64), r["first_free"]), (where, i)
+        sg, so = ctx.score_stats(i), orc.score_stats()
+        for k in ("n_confident", "n_accessible", "n_blocked", "n_no_candidate",
+                  "canonical_tests", "canonical_lookups"):
+            assert sg[k] == so[k], (where, i, k)
+
+
+def test_replays_equal_eager(synth_mod, oracle_mod):
     import torch
     assert torch.cuda.is_available()
     w, frames, sizes, make = _setup(synth_mod)
+    tools = synth_mod.batch_tools()[:4]
+    rots = [synth_mod.orientations(synth_mod.fibonacci_directions(128), 4),
+            synth_mod.orientations(synth_mod.fibonacci_directions(64), 1),
+            synth_mod.orientations(synth_mod.yaw_directions(70), 1),
+            synth_mod.orientations(synth_mod.fibonacci_directions(32), 8)]
+    orc = oracle_mod.Oracle(voxel=w.voxel, trunc=w.trunc, r_c=w.r_c)
+    for i, (tl, r) in enumerate(zip(tools, rots)):
+        orc.set_tool(i, tl, r)
     eager, rec = make(), make()
     allx = np.concatenate([f.xyz for f in frames])
     lo, hi = allx.min(0) - 0.5, allx.max(0) + 0.5
@@ -93,6 +120,9 @@ def test_replays_equal_eager(synth_mod):
             for k in FRAME_KEYS:
                 assert fe[k] == fr[k], (j, k)
         _same_scores(eager, rec, j)
+        orc.integrate_frame(f.xyz[:n], f.origin, f.frame_id)
+        if j in (3, len(frames) - 1):
+            _same_as_oracle(rec, orc, rots, j)
     _same_map(eager, rec)
 
 

@@ -216,3 +216,186 @@ def test_trigger_i_on_a_moving_surface(oracle_mod, synth_mod):
         assert st["trig_i"] == n_i
         if fid == 2:
             assert n_i > 0
+
+
+def _run(oracle_mod, synth_mod, n_frames, **kw):
+    from oracle.incremental import IncrementalOracle
+    w = synth_mod.tiny()
+    frames = w.frames(n_frames)
+    orc = oracle_mod.Oracle(voxel=w.voxel, trunc=w.trunc, r_c=w.r_c)
+    orc.set_tool(0, w.tool, w.rot)
+    return w, frames, IncrementalOracle(orc, 0, len(w.rot), **kw)
+
+
+def test_drain_equals_a_larger_frame_budget(oracle_mod, synth_mod):
+    """A frame with a small cap followed by a drain of everything queued
+    leaves every point as a frame without a cap does (the drain evaluates the
+    same points on the same map, in the same order), frame after frame."""
+    w, frames, small = _run(oracle_mod, synth_mod, 6, budget=300)
+    _, _, full = _run(oracle_mod, synth_mod, 6, budget=10 ** 9)
+    for f in frames:
+        st = small.frame(f.xyz, f.origin, f.frame_id)
+        assert st["evaluated"] <= 300
+        d = small.drain(10 ** 9)
+        assert d["trig_i"] == 0
+        ft = full.frame(f.xyz, f.origin, f.frame_id)
+        # what stays queued is below the confidence gate, as after the full frame
+        assert d["backlog"] == ft["backlog"]
+        assert st["evaluated"] + d["evaluated"] == ft["evaluated"]
+        for x, y in zip(small.labels(), full.labels()):
+            assert np.array_equal(x, y)
+
+
+def test_partial_drains_in_point_order(oracle_mod, synth_mod):
+    """Drains of 150 take the queued points in point order: after a frame with
+    cap 200 and two drains of 150, the evaluated points are the first 500
+    queued ones, as with one frame of cap 500."""
+    w, frames, a = _run(oracle_mod, synth_mod, 1, budget=200)
+    _, _, b = _run(oracle_mod, synth_mod, 1, budget=500)
+    f = frames[0]
+    a.frame(f.xyz, f.origin, f.frame_id)
+    first = list(a.last_evaluated)
+    a.drain(150)
+    first += a.last_evaluated
+    a.drain(150)
+    first += a.last_evaluated
+    b.frame(f.xyz, f.origin, f.frame_id)
+    assert first == list(b.last_evaluated) and len(first) == 500
+    for x, y in zip(a.labels(), b.labels()):
+        assert np.array_equal(x, y)
+
+
+def test_adaptive_cap(oracle_mod, synth_mod):
+    """The adaptive cap stays within [b_min, b_max], follows the previous
+    frame's lookups per evaluation, and with a target no frame can reach it
+    stays at b_max, which then matches a fixed cap of b_max exactly."""
+    w, frames, ad = _run(oracle_mod, synth_mod, 8, budget=400, lookup_target=150000,
+                         b_min=50, b_max=3000)
+    caps = []
+    prev = None
+    for f in frames:
+        st = ad.frame(f.xyz, f.origin, f.frame_id)
+        assert 50 <= st["budget"] <= 3000
+        if prev is not None and prev["evaluated"] and prev["lookups"]:
+            want = 150000 * prev["evaluated"] // prev["lookups"]
+            assert st["budget"] == min(3000, max(50, want))
+        caps.append(st["budget"])
+        prev = st
+    assert caps[0] == 400 and len(set(caps)) > 2          # it adapts
+    _, _, hi = _run(oracle_mod, synth_mod, 8, budget=900, lookup_target=10 ** 12, b_min=1,
+                    b_max=900)
+    _, _, fx = _run(oracle_mod, synth_mod, 8, budget=900)
+    for j, f in enumerate(frames):
+        a = hi.frame(f.xyz, f.origin, f.frame_id)
+        b = fx.frame(f.xyz, f.origin, f.frame_id)
+        assert a["budget"] == 900 and a["evaluated"] == b["evaluated"]
+        for x, y in zip(hi.labels(), fx.labels()):
+            assert np.array_equal(x, y)
+
+
+def test_coarse_fine_sets_on_the_yaw_set(oracle_mod, synth_mod):
+    """The paper's D = 180 yaw directions (2 degree steps): the coarse pass is
+    every tenth direction (20 degrees apart, 18 of them) and the fine window
+    of direction k is k-12 .. k+12 (within 24 degrees), 25 directions."""
+    from oracle.incremental import coarse_fine_sets
+    c, f = coarse_fine_sets(synth_mod.orientations(synth_mod.yaw_directions(180), 1))
+    bits = lambda w: [k for k in range(180) if (int(w[k // 64]) >> (k % 64)) & 1]
+    assert bits(c) == list(range(0, 180, 10))
+    for k in (0, 7, 90, 179):
+        assert bits(f[k]) == sorted((k + d) % 180 for d in range(-12, 13))
+    # rolls share their direction's membership
+    c4, f4 = coarse_fine_sets(synth_mod.orientations(synth_mod.yaw_directions(180), 4))
+    assert bits(c4)[:8] == [0, 1, 2, 3, 40, 41, 42, 43]
+
+
+def test_allow_restriction_by_single_orientations(oracle_mod, synth_mod):
+    """Scoring with an allowed set gives, for each point, the first allowed
+    orientation that is a free candidate: checked against scoring each
+    allowed orientation on its own (one-orientation allow masks)."""
+    w = synth_mod.tiny()
+    rot = synth_mod.orientations(synth_mod.yaw_directions(180), 1)
+    o = oracle_mod.Oracle(voxel=w.voxel, trunc=w.trunc, r_c=w.r_c)
+    for f in w.frames(6):
+        o.integrate_frame(f.xyz, f.origin, f.frame_id)
+    o.set_tool(0, w.tool, rot)
+    keys = o.read_points()["key"]
+    rng = np.random.default_rng(3)
+    pick = keys[rng.choice(len(keys), 40, replace=False)]
+    allow = np.zeros((len(pick), 3), np.uint64)
+    for j in range(len(pick)):
+        for k in rng.choice(180, 40, replace=False):
+            allow[j, k // 64] |= np.uint64(1) << np.uint64(k % 64)
+    o.score(0, pick, allow=allow)
+    got = [o.point_result(int(k), 180) for k in pick]
+    seen = 0
+    for j, k in enumerate(pick):
+        if got[j]["label"] == 0:
+            continue
+        first = -1
+        for kk in range(180):
+            if not (int(allow[j, kk // 64]) >> (kk % 64)) & 1:
+                continue
+            one = np.zeros((1, 3), np.uint64)
+            one[0, kk // 64] = np.uint64(1) << np.uint64(kk % 64)
+            o.score(0, [k], allow=one)
+            if o.point_result(int(k), 180)["label"] == 1:
+                first = kk
+                break
+        assert got[j]["first_free"] == first, (j, got[j], first)
+        seen += first >= 0
+    assert seen > 5
+
+
+def test_nearest_resolved_neighbour_rule(oracle_mod, synth_mod):
+    """The neighbour rule on hand-placed states: equal distances resolve by
+    (dz, dy, dx); points farther than 0.3 m and unresolved points are not
+    neighbours; the point itself is not its own neighbour."""
+    from oracle.incremental import IncrementalOracle
+    w = synth_mod.tiny()
+    rot = synth_mod.orientations(synth_mod.yaw_directions(180), 1)
+    o = oracle_mod.Oracle(voxel=w.voxel, trunc=w.trunc, r_c=w.r_c)
+    o.set_tool(0, w.tool, rot)
+    inc = IncrementalOracle(o, 0, 180, budget=10)
+    inc.enable_c2f(rot)
+    key = oracle_mod.key
+    st = lambda best, d: dict(best=best, best_dir=d, a=1.0, S=0, W=10, pending=False, outcome=1)
+    inc.state = {key(0, 0, 0): st(2, 5), key(1, 0, 0): st(1, 30), key(0, 0, -1): st(0, 60),
+                 key(0, -1, 0): st(5, 90),                  # not resolved (best = n_c)
+                 key(20, 0, 0): st(0, 120)}                 # 0.4 m away at v = 2 cm
+    allow = inc._allow([key(0, 0, 0), key(19, 0, 0), key(0, 0, 40)])
+    assert inc.last_neighbour[key(0, 0, 0)] == (key(0, 0, -1), 60)   # dz = -1 first
+    assert inc.last_neighbour[key(19, 0, 0)] == (key(20, 0, 0), 120)
+    assert key(0, 0, 40) not in inc.last_neighbour                   # none within 0.3 m
+    from oracle.incremental import coarse_fine_sets
+    c, f = coarse_fine_sets(rot)
+    assert np.array_equal(allow[0], c | f[60]) and np.array_equal(allow[2], c)
+
+
+def test_c2f_searches_fewer_orientations(oracle_mod, synth_mod):
+    """On the tiny scene with the yaw set, the coarse-to-fine search tests
+    fewer candidates than the full search of the same evaluations, and every
+    point it labels accessible is accessible under the full search too (its
+    free orientation is one of the full set's)."""
+    from oracle.incremental import IncrementalOracle
+    w = synth_mod.tiny()
+    rot = synth_mod.orientations(synth_mod.yaw_directions(180), 1)
+    runs = []
+    for c2f in (False, True):
+        o = oracle_mod.Oracle(voxel=w.voxel, trunc=w.trunc, r_c=w.r_c)
+        o.set_tool(0, w.tool, rot)
+        inc = IncrementalOracle(o, 0, 180, budget=10 ** 9)
+        if c2f:
+            inc.enable_c2f(rot)
+        tests = 0
+        for f in w.frames(4):
+            inc.frame(f.xyz, f.origin, f.frame_id)
+            tests += o.score_stats()["candidate_tests"]
+        runs.append((inc, tests))
+    (full, t_full), (cf, t_cf) = runs
+    assert t_cf < t_full
+    kf, lf, _, _, _ = full.labels()
+    kc, lc, _, _, _ = cf.labels()
+    assert np.array_equal(kf, kc)
+    acc_c = np.isin(lc, (1, 4))
+    assert acc_c.sum() > 100
+    assert np.all(np.isin(lf[acc_c], (1, 4)))

@@ -210,3 +210,50 @@ def test_edge_cases(smooth_setup, synth_mod):
             ctx.smooth_eval(pt, qt, kw["samples"], C, kw["tau_s"], s=st)
     with pytest.raises(AFError):
         ctx.smooth_eval(pt, qt, sm, C, TS, s=st, dq=torch.empty(4, 4, device="cuda"))
+
+
+def test_tree_subset_against_fp64_oracle(synth_mod, oracle_mod):
+    """The differentiation workload's gradient check at its stated scale: a
+    10,000-point subset of the tree TSDF (40 frames; the points are the
+    10,000 surface voxels nearest a seeded one, jittered off the voxel
+    centres), one
+    start per point towards a Fibonacci direction, the saw box's 64 samples
+    (stations to 1.3 m).  The oracle integrates the same frames restricted to
+    a region reaching past every sample.  ds/dq and ds/dp within 1e-4
+    relative of the fp64 gradient, s within 1e-5."""
+    import torch
+    from paper_2608_06412_amd import Context, default_config
+    w = synth_mod.tree(n_frames=40)
+    frames = w.frames(40)
+    ctx = Context(default_config(w.voxel, w.trunc, r_c=w.r_c, max_blocks=1 << 16,
+                                 max_points=1 << 21))
+    for f in frames:
+        ctx.integrate_frame(torch.from_numpy(f.xyz).cuda(), f.origin, f.frame_id)
+    key = ctx.read_points()["key"]
+    from paper_2608_06412_amd.af import unpack_keys
+    ijk = unpack_keys(key)
+    rng = np.random.default_rng(31)
+    c = ijk[rng.integers(len(ijk))]
+    pick = ijk[np.argsort(((ijk - c) ** 2).sum(1), kind="stable")[:10000]]
+    smp = synth_mod.tool_samples(w.tool, 16)
+    reach = int(np.ceil(np.linalg.norm(smp, axis=1).max() / w.voxel)) + 4
+    lo, hi = pick.min(0) - reach, pick.max(0) + reach
+    orc = oracle_mod.Oracle(voxel=w.voxel, trunc=w.trunc, r_c=w.r_c)
+    orc.set_roi(lo, hi)
+    for f in frames:
+        orc.integrate_frame(f.xyz, f.origin, f.frame_id)
+    p = ((pick + 0.5 + rng.uniform(-0.3, 0.3, pick.shape)) * w.voxel).astype(np.float32)
+    q = synth_mod.quaternion_towards(synth_mod.fibonacci_directions(64))[
+        rng.integers(0, 64, len(p))].astype(np.float32)
+    s, dq, dp = _gpu_eval(ctx, p, q, smp)
+    so, dqo, dpo, face = orc.smooth(p, q, smp, C, TS)
+    assert np.all(np.abs(s - so) <= 1e-5 * np.abs(so) + 1e-4), np.abs(s - so).max()
+    ok = face > 1e-6
+    big = np.linalg.norm(dpo, axis=1) > 1e-3 * np.median(np.linalg.norm(dpo, axis=1))
+    sel = ok & big
+    eq, ep = _rel(dq[sel], dqo[sel]), _rel(dp[sel], dpo[sel])
+    print("tree pairs %d, compared %d, max rel dq %.2e dp %.2e" % (len(p), sel.sum(), eq.max(),
+                                                                  ep.max()), flush=True)
+    assert sel.sum() > 0.9 * len(p)
+    assert eq.max() < 1e-4
+    assert ep.max() < 1e-4

@@ -1,10 +1,13 @@
 """Serving two concurrent sensor streams (af_server): each stream's labels,
 first free orientations, statistics and TSDF after every frame equal those of
 its own eager context fed the same frames (af_integrate_frame +
-af_score_points), whatever the interleaving of submissions; admission
+af_score_points), whatever the interleaving of submissions, and after frames
+5, 12 and 20 of each stream its labels, first free orientations and
+canonical counts equal the oracle's fed the same frames; admission
 follows the device budget; a full frame queue is refused.  Stream 0: the tiny
 scene with a cylinder; stream 1: a seeded box cluster with a box tool and
-frames of 500-3,000 returns (v = 2 cm both)."""
+frames of 500-3,000 returns (v = 2 cm both).  Both modes: one scoring launch
+per step across the streams (batched), and one per stream."""
 import numpy as np
 import pytest
 
@@ -42,13 +45,27 @@ def _same(a, b, where):
         assert sa[k] == sb[k], (where, k)
 
 
-def test_two_streams_equal_their_eager_contexts(synth_mod):
+def _same_as_oracle(ctx, orc, K, where):
+    orc.score(0)
+    lab = ctx.read_labels(0)
+    r = orc.read_results(K)
+    assert np.array_equal(lab["key"], orc.read_points()["key"]), where
+    assert np.array_equal(lab["label"], r["label"]), where
+    assert np.array_equal(lab["first_free"].astype(np.int64), r["first_free"]), where
+    sg, so = ctx.score_stats(0), orc.score_stats()
+    for k in ("n_confident", "n_accessible", "n_blocked", "n_no_candidate", "canonical_tests",
+              "canonical_lookups"):
+        assert sg[k] == so[k], (where, k)
+
+
+@pytest.mark.parametrize("batch", [True, False])
+def test_two_streams_equal_their_eager_contexts(synth_mod, oracle_mod, batch):
     import torch
     from paper_2608_06412_amd import AFError, Context, Server
     from paper_2608_06412_amd.af import AF_EBUSY, AF_ENOMEM
     frames, tools, rots, cfg = _streams(synth_mod)
     GiB = 1 << 30
-    srv = Server(3 * GiB, max_streams=3)
+    srv = Server(3 * GiB, max_streams=3, batch=batch)
     sids = [srv.admit(cfg(GiB)), srv.admit(cfg(GiB))]
     with pytest.raises(AFError) as e:
         srv.admit(cfg(2 * GiB))
@@ -62,6 +79,12 @@ def test_two_streams_equal_their_eager_contexts(synth_mod):
         r = Context(cfg(0))
         r.set_tool_kernels(0, tools[s], rots[s])
         refs.append(r)
+    orcs = []
+    w0 = synth_mod.tiny()     # both streams use its voxel, truncation and r_c
+    for s in range(2):
+        o = oracle_mod.Oracle(voxel=w0.voxel, trunc=w0.trunc, r_c=w0.r_c)
+        o.set_tool(0, tools[s], rots[s])
+        orcs.append(o)
     nxt = [0, 0]     # next frame to submit, per stream
     done = [0, 0]    # frames processed, per stream
     it = 0
@@ -86,6 +109,9 @@ def test_two_streams_equal_their_eager_contexts(synth_mod):
             refs[s].integrate_frame(torch.from_numpy(f.xyz).cuda(), f.origin, f.frame_id)
             refs[s].score_points(0)
             _same(srv.context(sid), refs[s], (s, fid))
+            orcs[s].integrate_frame(f.xyz, f.origin, f.frame_id)
+            if done[s] in (4, 11, len(frames[s]) - 1):
+                _same_as_oracle(srv.context(sid), orcs[s], len(rots[s]), (s, fid))
             done[s] += 1
         it += 1
         assert it < 200
