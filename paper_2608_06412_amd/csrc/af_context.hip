@@ -509,10 +509,6 @@ static int tool_release(af_ctx *c, int32_t tool_id, hipStream_t s) {
   dev_free(c, t.c4begin, sizeof(uint32_t) * (t.K + 1));
   dev_free(c, t.c4flag, t.K);
   dev_free(c, t.c4entries, sizeof(uint32_t) * std::max<int64_t>(1, t.n_c4entries));
-  dev_free(c, t.b4start, sizeof(uint32_t) * t.K);
-  dev_free(c, t.b4begin, sizeof(uint32_t) * (t.K + 1));
-  dev_free(c, t.b4flag, t.K);
-  dev_free(c, t.b4entries, sizeof(uint32_t) * std::max<int64_t>(1, t.n_b4entries));
   memset(&t, 0, sizeof(t));
   return AF_OK;
 }
@@ -547,21 +543,6 @@ static int tool_finish(af_ctx *c, int32_t tool_id, ToolDev &nt, uint32_t *counts
                           nt.c4entries, nt.c4flag, 1, 2, s) != 0)
     return hip_check(c, "coarse4 fill");
   nt.n_c4entries = c4total;
-  // the same for the body tail (the body entries after the first kBodyHead)
-  ALLOC(c, nt.b4start, K);
-  ALLOC(c, nt.b4begin, K + 1);
-  ALLOC(c, nt.b4flag, K);
-  if (launch_table_coarse(K, nt.begin, counts, nt.entries, nt.b4start, ccounts, nt.b4begin,
-                          nullptr, nt.b4flag, 0, 2, s, 1) != 0)
-    return hip_check(c, "body tail count");
-  uint32_t b4total = 0;
-  HIP_TRY(c, hipMemcpyAsync(&b4total, nt.b4begin + K, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-  HIP_TRY(c, hipStreamSynchronize(s));
-  ALLOC(c, nt.b4entries, std::max<uint32_t>(1u, b4total));
-  if (launch_table_coarse(K, nt.begin, counts, nt.entries, nt.b4start, ccounts, nt.b4begin,
-                          nt.b4entries, nt.b4flag, 1, 2, s, 1) != 0)
-    return hip_check(c, "body tail fill");
-  nt.n_b4entries = b4total;
   HIP_TRY(c, hipStreamSynchronize(s));
   dev_free(c, ccounts, sizeof(uint32_t) * K);
   {

@@ -187,13 +187,6 @@ struct ToolDev {
   uint32_t *c4entries;
   uint8_t *c4flag;      // [K] 1: list valid
   int64_t n_c4entries;
-  // the same lists for the body tail: the body entries after the first
-  // kBodyHead, which start at b4start[k] (= far_begin[k] when there are none)
-  uint32_t *b4start;    // [K]
-  uint32_t *b4begin;    // [K + 1]
-  uint32_t *b4entries;
-  uint8_t *b4flag;      // [K]
-  int64_t n_b4entries;
   // grid-relative form of the table for the current brick grid: per entry
   // {brick delta (ox>>3) + gx (oy>>3) + gx gy (oz>>3), in-brick offsets
   // (ox&7) | (oy&7) << 4 | (oz&7) << 8 | class << 30}.  Rebuilt whenever the
@@ -205,10 +198,6 @@ struct ToolDev {
   int64_t n_entries;
   int32_t reach;        // largest |offset| component over the table, voxels
 };
-
-// Body entries a scoring kernel takes in its first fine step; the body tail
-// after them has 4^3-cell lists for a coarse skip.
-constexpr uint32_t kBodyHead = 64;
 
 // Table entry packing: 10-bit two's complement offsets, class in bits 30-31.
 __host__ __device__ inline uint32_t pack_entry(int ox, int oy, int oz, int cls) {
@@ -406,13 +395,10 @@ int launch_table_build(const ToolGeom &tg, int32_t K, const double *rot_dev,
                        uint32_t *entries_dev, int pass, hipStream_t s);
 
 int launch_table_grid(const ToolDev &t, const GridDev &g, hipStream_t s);
-// body_tail: the lists of the body tail (entries after the first kBodyHead
-// body entries) instead of the corridor; far_begin then receives the tail's
-// first entry.
 int launch_table_coarse(int32_t K, const uint32_t *begin, const uint32_t *counts,
                         const uint32_t *entries, uint32_t *far_begin, uint32_t *ccounts,
                         uint32_t *cbegin, uint32_t *centries, uint8_t *cflag, int pass, int sh,
-                        hipStream_t s, int body_tail = 0);
+                        hipStream_t s);
 
 // dev_n: the kernels take the point count from the device counter; n_points
 // is then only an upper bound that sizes the launch

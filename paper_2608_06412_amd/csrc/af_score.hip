@@ -1013,14 +1013,13 @@ __device__ inline bool scan_fine_sw(const Params &p, const ToolDev &t, const SwG
 // relative to the grid; a cell's bit lives in its brick's octant byte.  The
 // list holds every cell offset floor((r + o) / 4) over corridor entries o and
 // positions r in [0, 4)^3 of the point inside its cell.
-__device__ inline bool cells_clear4_sw(const uint32_t *lbegin, const uint32_t *lentries,
-                                       const SwGrid &q, const uint32_t c4[3],
-                                       const uint8_t *occ4, int k) {
-  const uint32_t cb = lbegin[k], ce = lbegin[k + 1];
+__device__ inline bool corridor_clear4_sw(const ToolDev &t, const SwGrid &q, const uint32_t c4[3],
+                                          const uint8_t *occ4, int k) {
+  const uint32_t cb = t.c4begin[k], ce = t.c4begin[k + 1];
   const uint32_t lane = (uint32_t)lane_id();
   for (uint32_t base = cb; base < ce; base += 64) {
     const uint32_t idx = base + lane;
-    const uint32_t d = lentries[idx < ce ? idx : ce - 1];
+    const uint32_t d = t.c4entries[idx < ce ? idx : ce - 1];
     const uint32_t X = c4[0] + (uint32_t)entry_x(d), Y = c4[1] + (uint32_t)entry_y(d),
                    Z = c4[2] + (uint32_t)entry_z(d);
     const uint32_t brick = (X >> 1) + q.gx * (Y >> 1) + q.gxy * (Z >> 1);
@@ -1031,17 +1030,10 @@ __device__ inline bool cells_clear4_sw(const uint32_t *lbegin, const uint32_t *l
   }
   return true;
 }
-__device__ inline bool corridor_clear4_sw(const ToolDev &t, const SwGrid &q, const uint32_t c4[3],
-                                          const uint8_t *occ4, int k) {
-  return cells_clear4_sw(t.c4begin, t.c4entries, q, c4, occ4, k);
-}
 
 // Entries [b, e) of orientation k after its first E: body entries finely,
 // then the corridor -- skipped when its 4^3 cells are clear (CO), finely
-// otherwise.  With CO the body is split as well: its first kBodyHead entries
-// are scanned finely, and the tail after them is skipped when its 4^3 cells
-// are clear (it then adds no body hit).  Canonical lookups stay the
-// table-order count.
+// otherwise.  Canonical lookups stay the table-order count.
 template <int UN, int CO, int B1, int RE = 0, int LZ = 0>
 __device__ inline bool scan_rest_sw(const Params &p, const ToolDev &t, const SwGrid &q,
                                     const SwFrame &f, int k, uint32_t b, uint32_t e, int body,
@@ -1052,24 +1044,8 @@ __device__ inline bool scan_rest_sw(const Params &p, const ToolDev &t, const SwG
   if (!CO) return scan_fine_sw<UN, B1, RE, 0, LZ>(p, t, q, f, b, e, body, lookups, sbody, first);
   const uint32_t fb = t.far_begin[k];
   const uint32_t mid = fb > b ? fb : b;
-  const uint32_t tb = t.b4start[k];
-  const uint32_t head = tb > b && tb < mid ? tb : mid;   // end of the finely scanned body part
-  if (!scan_fine_sw<UN, B1, RE, B1 ? 1 : 0, LZ>(p, t, q, f, b, head, body, lookups, sbody, first))
+  if (!scan_fine_sw<UN, B1, RE, B1 ? 1 : 0, LZ>(p, t, q, f, b, mid, body, lookups, sbody, first))
     return false;
-  if (head < mid) {
-    bool clear = false;
-    if (t.b4flag[k] != 0) {
-      ++cchecks;
-      clear = cells_clear4_sw(t.b4begin, t.b4entries, q, c4, occ4, k);
-      if (clear) {
-        ++cclear;
-        lookups += mid - head;
-      }
-    }
-    if (!clear &&
-        !scan_fine_sw<UN, B1, RE, B1 ? 1 : 0, LZ>(p, t, q, f, head, mid, body, lookups, sbody))
-      return false;
-  }
   if (mid >= e) return true;
   if (t.c4flag[k] != 0) {
     ++cchecks;

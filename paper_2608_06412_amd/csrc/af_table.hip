@@ -144,18 +144,14 @@ __global__ void k_table_scan(int32_t K, const uint32_t *counts, uint32_t *begin)
   begin[K] = acc;
 }
 
-// Coarse list of a range of orientation k's entries for cells of C = 2^SH
-// voxels per axis: every cell offset floor((r + o)/C) (r in [0, C)^3 the
-// point's position inside its cell, o an entry of the range), as a bitmap over
-// the bounding box of those offsets, compacted in linear order.  A bounding
-// box above kCoarseBits cells leaves the orientation without a list
-// (cflag = 0).  MODE 0: the corridor [far_begin, end), whose start it also
-// records; MODE 1: the body tail, the body entries after the first
-// kBodyHead (which the scoring kernels take in one fine step), whose start
-// it records in far_begin's place.
+// Coarse corridor list of orientation k for cells of C = 2^SH voxels per
+// axis: every cell offset floor((r + o)/C) (r in [0, C)^3 the point's
+// position inside its cell, o a corridor entry), as a bitmap over the
+// bounding box of those offsets, compacted in linear order.  A bounding box
+// above kCoarseBits cells leaves the orientation without a list (cflag = 0).
 constexpr int kCoarseBits = 1 << 18;
 
-template <int SH, int MODE>
+template <int SH>
 __global__ void __launch_bounds__(256)
 k_table_coarse(int32_t K, const uint32_t *begin, const uint32_t *counts, const uint32_t *entries,
                uint32_t *far_begin, uint32_t *ccounts, const uint32_t *cbegin,
@@ -166,9 +162,7 @@ k_table_coarse(int32_t K, const uint32_t *begin, const uint32_t *counts, const u
   __shared__ uint32_t part[256];
   const int k = blockIdx.x;
   if (k >= K) return;
-  const uint32_t body_end = begin[k] + 3 + counts[2 * k];
-  const uint32_t tail = begin[k] + 3 + kBodyHead < body_end ? begin[k] + 3 + kBodyHead : body_end;
-  const uint32_t fb = MODE == 0 ? body_end : tail, e = MODE == 0 ? begin[k + 1] : body_end;
+  const uint32_t fb = begin[k] + 3 + counts[2 * k], e = begin[k + 1];
   if (threadIdx.x < 3) {
     lo[threadIdx.x] = 1 << 20;
     hi[threadIdx.x] = -(1 << 20);
@@ -274,14 +268,10 @@ int launch_table_grid(const ToolDev &t, const GridDev &g, hipStream_t s) {
 int launch_table_coarse(int32_t K, const uint32_t *begin, const uint32_t *counts,
                         const uint32_t *entries, uint32_t *far_begin, uint32_t *ccounts,
                         uint32_t *cbegin, uint32_t *centries, uint8_t *cflag, int pass, int sh,
-                        hipStream_t s, int body_tail) {
+                        hipStream_t s) {
   if (sh != 2) return -1;
-  if (body_tail)
-    hipLaunchKernelGGL((k_table_coarse<2, 1>), dim3((unsigned)K), dim3(256), 0, s, K, begin,
-                       counts, entries, far_begin, ccounts, cbegin, centries, cflag, pass);
-  else
-    hipLaunchKernelGGL((k_table_coarse<2, 0>), dim3((unsigned)K), dim3(256), 0, s, K, begin,
-                       counts, entries, far_begin, ccounts, cbegin, centries, cflag, pass);
+  hipLaunchKernelGGL(k_table_coarse<2>, dim3((unsigned)K), dim3(256), 0, s, K, begin, counts,
+                     entries, far_begin, ccounts, cbegin, centries, cflag, pass);
   if (pass == 0) hipLaunchKernelGGL(k_coarse_scan, dim3(1), dim3(1), 0, s, K, ccounts, cbegin);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
