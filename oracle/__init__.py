@@ -122,6 +122,10 @@ def _load():
     L.orc_key.argtypes = [i64, i64, i64]
     L.orc_unkey.argtypes = [i64, vp]
     L.orc_params.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.orc_set_window.restype = ctypes.c_int
+    L.orc_set_window.argtypes = [vp, vp]
+    L.orc_window.restype = ctypes.c_int
+    L.orc_window.argtypes = [vp, vp, vp, vp]
     L.orc_changed_voxels.restype = i64
     L.orc_changed_voxels.argtypes = [vp, vp, i64]
     L.orc_body_hits.restype = ctypes.c_int
@@ -231,6 +235,19 @@ class Oracle:
                           ctypes.byref(dm), ctypes.byref(sc))
         return dict(tau_u=t.value, R=r.value, rc_u=rc.value, dmin_u=dm.value,
                     scale=sc.value)
+
+    def set_window(self, blocks):
+        L = np.ascontiguousarray(blocks, dtype=np.int64).reshape(3)
+        if self.L.orc_set_window(self.h, _p(L)) != 0:
+            raise ValueError("oracle rejected the window")
+
+    def window(self):
+        """(lo, hi, shifts) of the window in blocks, or None before it is set."""
+        lo = np.zeros(3, np.int64)
+        hi = np.zeros(3, np.int64)
+        sh = ctypes.c_int64()
+        on = self.L.orc_window(self.h, _p(lo), _p(hi), ctypes.byref(sh))
+        return (lo, hi, sh.value) if on else None
 
     def set_roi(self, lo, hi):
         lo = np.ascontiguousarray(lo, dtype=np.int64)

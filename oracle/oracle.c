@@ -145,6 +145,10 @@ struct orc {
   int64_t tau_u, R, rc_u, dmin_u;
   int roi;
   int64_t roi_lo[3], roi_hi[3];
+  /* sliding window (Section 3.3): L blocks per axis, centred (in voxels) on
+   * the sensor of the frame that last shifted it; blocks [lo, hi] */
+  int win_on, win_set;
+  int64_t win_L[3], win_c[3], win_lo[3], win_hi[3], win_shifts;
   int64_t last_frame_id;
   /* voxels */
   hmap vmap;
@@ -176,6 +180,24 @@ static int in_roi(const orc_t *o, int64_t x, int64_t y, int64_t z) {
   if (!o->roi) return 1;
   return x >= o->roi_lo[0] && x <= o->roi_hi[0] && y >= o->roi_lo[1] &&
          y <= o->roi_hi[1] && z >= o->roi_lo[2] && z <= o->roi_hi[2];
+}
+
+/* Whether voxel x lies in the sliding window (always, without a window or
+ * before its first frame). */
+static int in_window(const orc_t *o, int64_t x, int64_t y, int64_t z) {
+  if (!o->win_on || !o->win_set) return 1;
+  const int64_t v[3] = {x, y, z};
+  for (int i = 0; i < 3; ++i) {
+    int64_t b = orc_floor_div(v[i], 8);
+    if (b < o->win_lo[i] || b > o->win_hi[i]) return 0;
+  }
+  return 1;
+}
+
+/* A voxel the integration may write: inside the region of interest and the
+ * window. */
+static int in_map(const orc_t *o, int64_t x, int64_t y, int64_t z) {
+  return in_roi(o, x, y, z) && in_window(o, x, y, z);
 }
 
 orc_t *orc_create(const orc_config *cfg) {
@@ -229,6 +251,59 @@ void orc_set_roi(orc_t *o, const int64_t lo[3], const int64_t hi[3]) {
   }
 }
 
+/* Section 3.3 "Sliding-Window TSDF": a box of L[i] blocks (8 voxels) per
+ * axis.  At each frame, before integration: on the first frame, and whenever
+ * the sensor's voxel is more than 30 % of the window's size (8 L voxels)
+ * from the window's centre along some axis, the window is re-centred on the
+ * sensor's voxel c and covers blocks [floor(c/8) - floor(L/2), + L - 1];
+ * every voxel outside it is discarded (it reads unknown again).  The frame
+ * then writes only voxels inside the window and creates points only there.
+ * Points outside keep their records and results and are not scored; the
+ * normal's neighbours are the points inside the window.  Set before the
+ * first frame (returns -1 otherwise, or for L < 2). */
+int orc_set_window(orc_t *o, const int64_t L[3]) {
+  if (o->last_frame_id >= 0) return -1;
+  for (int i = 0; i < 3; ++i)
+    if (L[i] < 2) return -1;
+  o->win_on = 1;
+  o->win_set = 0;
+  o->win_shifts = 0;
+  for (int i = 0; i < 3; ++i) o->win_L[i] = L[i];
+  return 0;
+}
+
+/* Window box (blocks) and the number of shifts so far; returns 0 before the
+ * first frame. */
+int orc_window(const orc_t *o, int64_t lo[3], int64_t hi[3], int64_t *shifts) {
+  for (int i = 0; i < 3; ++i) {
+    lo[i] = o->win_lo[i];
+    hi[i] = o->win_hi[i];
+  }
+  *shifts = o->win_shifts;
+  return o->win_on && o->win_set;
+}
+
+/* Discard every voxel outside the window (arrays compacted, map rebuilt). */
+static void evict_outside(orc_t *o) {
+  int64_t m = 0;
+  for (int64_t i = 0; i < o->nv; ++i) {
+    int64_t v[3];
+    orc_unkey(o->vkey[i], v);
+    if (!in_window(o, v[0], v[1], v[2])) continue;
+    o->vkey[m] = o->vkey[i];
+    o->S[m] = o->S[i];
+    o->dS[m] = o->dS[i];
+    o->W[m] = o->W[i];
+    o->dW[m] = o->dW[i];
+    o->clr[m] = o->clr[i];
+    ++m;
+  }
+  o->nv = m;
+  hm_free(&o->vmap);
+  hm_init(&o->vmap, 1 << 16);
+  for (int64_t i = 0; i < m; ++i) hm_put(&o->vmap, o->vkey[i], i);
+}
+
 int orc_params(const orc_t *o, int64_t *tau_u, int64_t *R, int64_t *rc_u,
                int64_t *dmin_u, double *scale) {
   *tau_u = o->tau_u;
@@ -257,7 +332,11 @@ static int64_t voxel_slot(orc_t *o, int64_t key) {
   c = o->vcap;
   o->clr = (uint8_t *)grow_array(o->clr, sizeof(uint8_t), &c, i + 1);
   o->vcap = c;
+  /* a slot freed by the window's eviction holds an old record */
   o->vkey[i] = key;
+  o->S[i] = o->dS[i] = 0;
+  o->W[i] = o->dW[i] = 0;
+  o->clr[i] = 0;
   o->nv += 1;
   hm_put(&o->vmap, key, i);
   return i;
@@ -321,7 +400,7 @@ static void accumulate_cube(orc_t *o, const int64_t P[3], const int64_t Q[3]) {
     for (int64_t dy = -o->R; dy <= o->R; ++dy)
       for (int64_t dx = -o->R; dx <= o->R; ++dx) {
         int64_t x[3] = {ip[0] + dx, ip[1] + dy, ip[2] + dz};
-        if (!in_roi(o, x[0], x[1], x[2])) continue;
+        if (!in_map(o, x[0], x[1], x[2])) continue;
         int64_t c[3], a[3], cq[3];
         for (int i = 0; i < 3; ++i) {
           c[i] = 256 * x[i] + 128;
@@ -373,7 +452,7 @@ static void mark_band(orc_t *o, const int64_t P[3], const int64_t Q[3]) {
     int64_t x[3];
     for (int i = 0; i < 3; ++i)
       x[i] = orc_floor_div(P[i] + round_div(lam * g[i], L), 256);
-    if (!in_roi(o, x[0], x[1], x[2])) continue;
+    if (!in_map(o, x[0], x[1], x[2])) continue;
     int64_t s = voxel_slot(o, orc_key(x[0], x[1], x[2]));
     o->clr[s] = 1;
     o->fst.band_marks += 1;
@@ -386,6 +465,27 @@ int orc_integrate_frame(orc_t *o, const float *xyz, int64_t n,
   int64_t Q[3];
   for (int i = 0; i < 3; ++i)
     if (!quantize((double)origin[i], o->scale, &Q[i])) return -1;
+  if (o->win_on) {
+    int64_t qv[3];
+    int shift = !o->win_set;
+    for (int i = 0; i < 3; ++i) {
+      qv[i] = orc_floor_div(Q[i], 256);
+      int64_t d = qv[i] - o->win_c[i];
+      if (o->win_set && 10 * (d < 0 ? -d : d) > 3 * 8 * o->win_L[i]) shift = 1;
+    }
+    if (shift) {
+      for (int i = 0; i < 3; ++i) {
+        o->win_c[i] = qv[i];
+        o->win_lo[i] = orc_floor_div(qv[i], 8) - o->win_L[i] / 2;
+        o->win_hi[i] = o->win_lo[i] + o->win_L[i] - 1;
+      }
+      if (o->win_set) {
+        evict_outside(o);
+        o->win_shifts += 1;
+      }
+      o->win_set = 1;
+    }
+  }
   memset(&o->fst, 0, sizeof(o->fst));
   o->fst.n_in = n;
   int64_t *P = (int64_t *)malloc(sizeof(int64_t) * 3 * (n > 0 ? n : 1));
@@ -414,7 +514,7 @@ int orc_integrate_frame(orc_t *o, const float *xyz, int64_t n,
     /* Section 3.1: the voxel holding a return becomes a surface point. */
     int64_t ip[3];
     for (int i = 0; i < 3; ++i) ip[i] = orc_floor_div(P[3 * r + i], 256);
-    if (!in_roi(o, ip[0], ip[1], ip[2])) continue;
+    if (!in_map(o, ip[0], ip[1], ip[2])) continue;
     int64_t k = orc_key(ip[0], ip[1], ip[2]);
     if (hm_get(&o->pmap, k) < 0 && hm_get(&seen, k) < 0) {
       hm_put(&seen, k, 1);
@@ -466,7 +566,7 @@ int orc_integrate_frame(orc_t *o, const float *xyz, int64_t n,
     if (!ok[r]) continue;
     int64_t ip[3];
     for (int i = 0; i < 3; ++i) ip[i] = orc_floor_div(P[3 * r + i], 256);
-    if (!in_roi(o, ip[0], ip[1], ip[2])) continue;
+    if (!in_map(o, ip[0], ip[1], ip[2])) continue;
     int64_t p = hm_get(&o->pmap, orc_key(ip[0], ip[1], ip[2]));
     if (o->last_frame[p] == (int32_t)frame_id) continue;
     o->last_frame[p] = (int32_t)frame_id;
@@ -900,6 +1000,7 @@ static int point_normal(const orc_t *o, int64_t p, const int32_t *nbo, int nnb,
   for (int j = 0; j < nnb && cnt < o->cfg.knn_k; ++j) {
     const int32_t *d = nbo + 3 * j;
     if (hm_get(&o->pmap, orc_key(s[0] + d[0], s[1] + d[1], s[2] + d[2])) < 0) continue;
+    if (!in_window(o, s[0] + d[0], s[1] + d[1], s[2] + d[2])) continue;
     cnt++;
     for (int a = 0; a < 3; ++a) sx[a] += d[a];
     sxx[0] += (int64_t)d[0] * d[0];
@@ -997,21 +1098,34 @@ static int score_impl(orc_t *o, int tool_id, const int64_t *keys, int64_t n_keys
   if (tt->K <= 0) return -4;
   int32_t K = tt->K;
   int32_t mw = (K + 63) / 64;
-  if (o->rcap < o->np || o->mask_words != mw) {
+  if (o->mask_words != mw) {
     free(o->label); free(o->first_free); free(o->has_normal); free(o->normal);
     free(o->mask);
-    o->rcap = o->np > 0 ? o->np : 1;
-    o->label = (uint8_t *)calloc(o->rcap, 1);
-    o->first_free = (int32_t *)calloc(o->rcap, sizeof(int32_t));
-    o->has_normal = (int32_t *)calloc(o->rcap, sizeof(int32_t));
-    o->normal = (int64_t *)calloc(o->rcap * 3, sizeof(int64_t));
-    o->mask = (uint64_t *)calloc(o->rcap * mw, sizeof(uint64_t));
+    o->label = NULL; o->first_free = NULL; o->has_normal = NULL; o->normal = NULL;
+    o->mask = NULL;
+    o->rcap = 0;
     o->mask_words = mw;
   }
-  for (int64_t p = 0; p < o->np; ++p) {
-    o->label[p] = 255; /* not evaluated */
-    o->first_free[p] = -1;
+  if (o->rcap < o->np) {
+    /* grow, keeping earlier results (a window keeps those of points outside) */
+    int64_t c0 = o->rcap, c;
+    int64_t need = o->np > 0 ? o->np : 1;
+    c = c0; o->label = (uint8_t *)grow_array(o->label, 1, &c, need);
+    c = c0; o->first_free = (int32_t *)grow_array(o->first_free, sizeof(int32_t), &c, need);
+    c = c0; o->has_normal = (int32_t *)grow_array(o->has_normal, sizeof(int32_t), &c, need);
+    c = c0; o->normal = (int64_t *)grow_array(o->normal, 3 * sizeof(int64_t), &c, need);
+    c = c0; o->mask = (uint64_t *)grow_array(o->mask, (int64_t)mw * sizeof(uint64_t), &c, need);
+    for (int64_t p = c0; p < c; ++p) {
+      o->label[p] = 255; /* not evaluated */
+      o->first_free[p] = -1;
+    }
+    o->rcap = c;
   }
+  if (!o->win_on)
+    for (int64_t p = 0; p < o->np; ++p) {
+      o->label[p] = 255; /* not evaluated */
+      o->first_free[p] = -1;
+    }
   memset(&o->sst, 0, sizeof(o->sst));
   o->sst.n_points = o->np;
   /* neighbour offsets, nearest first */
@@ -1033,6 +1147,9 @@ static int score_impl(orc_t *o, int tool_id, const int64_t *keys, int64_t n_keys
     if (p < 0) continue;
     int64_t s[3];
     orc_unkey(o->pkey[p], s);
+    /* with a window, every-point scoring skips the points outside it (their
+     * results stay as they were) */
+    if (!keys && !in_window(o, s[0], s[1], s[2])) continue;
     vrec self = lookup(o, s[0], s[1], s[2]);
     o->first_free[p] = -1;
     o->has_normal[p] = 0;

@@ -140,6 +140,9 @@ int64_t orc_isqrt(int64_t n);
 int64_t orc_floor_div(int64_t a, int64_t b);
 int64_t orc_key(int64_t x, int64_t y, int64_t z);
 void orc_unkey(int64_t key, int64_t out[3]);
+/* Sliding window of L[3] blocks (see oracle.c); before the first frame. */
+int orc_set_window(orc_t *o, const int64_t L[3]);
+int orc_window(const orc_t *o, int64_t lo[3], int64_t hi[3], int64_t *shifts);
 int orc_params(const orc_t *o, int64_t *tau_u, int64_t *R, int64_t *rc_u,
                int64_t *dmin_u, double *scale);
 

@@ -424,6 +424,19 @@ def tree(n_frames: int = 600, n_hits=20000, sigma: float = 0.02, seed: int = 5,
                     orientations(fibonacci_directions(64), 4), n_frames)
 
 
+def window_walk(n_frames: int = 48, n_hits: int = 3000, sigma: float = 0.01, seed: int = 17,
+                scene_seed: int = 11) -> Workload:
+    """Sliding-window workload: a 6 x 6 m box cluster on a ground slab, the
+    sensor on a 2 m circle at 1.2 m looking down (elevation -52..+7 deg), one
+    lap in `n_frames` frames (26 cm per frame at 48), v = 2 cm, tau = 6 cm.
+    With a 3.2 m window (20 blocks) the window shifts every few frames and
+    regions leave it and come back within the lap."""
+    return Workload("window_walk", 0.02, 0.06, 0.01, box_cluster_scene(scene_seed),
+                    circle_poses(n_frames, radius=2.0, centre=(0.0, 0.0), z=1.2), n_hits,
+                    sigma, seed, -52.0, 7.0, cylinder_tool(),
+                    orientations(fibonacci_directions(64), 1), n_frames)
+
+
 def uneven_counts(n: int, lo: int = 5000, hi: int = 40000, seed: int = 9):
     return np.random.default_rng(seed).integers(lo, hi + 1, size=n)
 
