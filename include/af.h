@@ -54,8 +54,10 @@ enum {
   AF_ACCESSIBLE = 1,   /* some candidate orientation is free */
   AF_BLOCKED = 2,      /* every candidate orientation collides */
   AF_NO_CANDIDATE = 3, /* no orientation passes the normal/observation filters */
-  AF_TENTATIVE = 4     /* incremental mode: a free direction is stored, but the
+  AF_TENTATIVE = 4,    /* incremental mode: a free direction is stored, but the
                           combined confidence c * a is not above 0.7 yet */
+  AF_NOT_EVALUATED = 255 /* sliding window: never scored (outside the window at
+                            every scoring call since the point was created) */
 };
 
 /* table entry classes */
@@ -215,6 +217,29 @@ int af_integrate_frame(af_ctx *ctx, const float *xyz, int64_t n,
 int af_integrate_frame_host(af_ctx *ctx, const float *xyz, int64_t n,
                             const float origin[3], int64_t frame_id, void *stream);
 
+/* Section 3.3 "Sliding-Window TSDF": bound the map to a box of blocks[a]
+ * voxel blocks (8 voxels each) per axis that follows the sensor.  At the
+ * first frame, and at every frame whose sensor voxel lies more than 30 % of
+ * the window's size (8 blocks[a] voxels) from the window's centre along some
+ * axis, the window is re-centred on the sensor's voxel c: it then covers
+ * blocks floor(c/8) - floor(blocks/2) .. + blocks - 1 on each axis, and
+ * every block outside it is discarded before the frame (its voxels read
+ * unknown again, W = 0; its memory is reused).  Frames write only voxels
+ * inside the window and create surface points only there.  Points outside
+ * keep their records and their last labels and are not scored; the normal's
+ * neighbours are the points inside the window.  Memory then stays bounded
+ * by the window (max_blocks of about blocks[0] blocks[1] blocks[2] suffice).
+ * Call once, before the first frame; 2 <= blocks[a] <= 4096.  Allocates
+ * 4 bytes per block and per point of capacity.  Not combinable with frame
+ * graphs, multi-tool scoring, the incremental mode, the smoothed score or
+ * variant tuning (those calls return AF_EINVAL).  AF_EINVAL after a frame. */
+int af_set_window(af_ctx *ctx, const int32_t blocks[3]);
+/* The window's current block box [lo, hi] (HOST arrays, either may be NULL)
+ * and the number of shifts so far (the first placement is not a shift).
+ * Returns 1 once placed, 0 before the first frame, AF_EINVAL without a
+ * window. */
+int af_window_state(af_ctx *ctx, int32_t lo[3], int32_t hi[3], int64_t *shifts);
+
 /* Sections 3.4-3.5: label every surface point for tool `tool_id`: W < W_min
  * -> AF_UNSCORED; else candidates = orientations whose approach direction is
  * within the normal half-cone and seen from that side by a stored viewpoint;
@@ -226,7 +251,11 @@ int af_integrate_frame_host(af_ctx *ctx, const float *xyz, int64_t n,
  * recomputed only for points within 3 voxels of points added since; the
  * first call allocates that cache (32 bytes per point of capacity, 64 per
  * brick of the grid), AF_ENOMEM if the device budget cannot hold it.
- * Asynchronous on `stream`.  AF_ENOTOOL if the tool was never set. */
+ * Asynchronous on `stream`.  AF_ENOTOOL if the tool was never set.  With a
+ * sliding window (af_set_window) only the points inside it are scored, with
+ * normals computed afresh; the others keep their labels (AF_NOT_EVALUATED
+ * if never scored); tools with K above 1024 or a reach above 255 voxels are
+ * then refused (AF_EINVAL). */
 int af_score_points(af_ctx *ctx, int32_t tool_id, void *stream);
 
 /* Copy labels of points [first, first + count) in canonical order (by first

@@ -6,5 +6,5 @@ kernels), ``score_points`` (label every confident surface point) and
 ``read_labels``.  The work runs in libaf.so; this package only marshals
 arguments.
 """
-from .af import (ACCESSIBLE, BLOCKED, NO_CANDIDATE, UNSCORED, AFError, Context,  # noqa: F401
-                 Server, default_config, lib, load_library)
+from .af import (ACCESSIBLE, BLOCKED, NO_CANDIDATE, NOT_EVALUATED, UNSCORED,  # noqa: F401
+                 AFError, Context, Server, default_config, lib, load_library, window_blocks)

@@ -9,6 +9,7 @@ or fails to load, importing this module raises.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 
 import numpy as np
@@ -18,6 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libaf.so")
 
 AF_OK, AF_EINVAL, AF_ENOMEM, AF_EDEVICE, AF_ENOTOOL, AF_EOVERFLOW, AF_EBUSY = 0, -1, -2, -3, -4, -5, -6
 UNSCORED, ACCESSIBLE, BLOCKED, NO_CANDIDATE, TENTATIVE = 0, 1, 2, 3, 4
+NOT_EVALUATED = 255   # sliding window: never scored
 CLS_BODY, CLS_NEAR, CLS_FAR = 0, 1, 2
 TOOL_CYLINDER, TOOL_BOX = 0, 1
 
@@ -108,6 +110,8 @@ SIGNATURES = {
     "af_set_tool_kernels": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(Tool), _i32, _vp, _vp]),
     "af_integrate_frame": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _vp]),
     "af_integrate_frame_host": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _vp]),
+    "af_set_window": (ctypes.c_int, [_vp, _vp]),
+    "af_window_state": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "af_score_points": (ctypes.c_int, [_vp, _i32, _vp]),
     "af_read_labels": (ctypes.c_int, [_vp, _i32, _i64, _i64, _vp, _vp, _vp, _vp, _vp]),
     "af_num_points": (_i64, [_vp]),
@@ -250,6 +254,13 @@ def _check_f32(t, shape, name):
         raise TypeError("%s must be a contiguous CUDA float32 tensor of shape %s" % (name, shape))
 
 
+def window_blocks(size_m, voxel: float):
+    """Blocks per axis of a window of size_m[a] metres: ceil(size / 8 v), at
+    least 2."""
+    return np.array([max(2, int(math.ceil(float(L) / (8.0 * voxel) - 1e-9))) for L in size_m],
+                    np.int32)
+
+
 def pca_axes(moments) -> tuple:
     """af_pca_axes: (axes [n][3] int64, has [n] int32) for neighbourhood
     moments [n][10] (count, sum d [3], sum dd^T [6])."""
@@ -344,6 +355,24 @@ class Context:
         self._check(self._lib.af_integrate_frame(self.h, ctypes.c_void_p(xyz.data_ptr()),
                                                  int(xyz.shape[0]), _p(o), int(frame_id),
                                                  _stream_handle(stream)))
+
+    def set_window(self, blocks):
+        """Sliding window of blocks[a] voxel blocks per axis (af_set_window);
+        before the first frame.  `blocks` may also be derived from a size in
+        metres with window_blocks()."""
+        b = np.ascontiguousarray(blocks, dtype=np.int32).reshape(3)
+        self._check(self._lib.af_set_window(self.h, _p(b)))
+
+    def window_state(self):
+        """(lo, hi, shifts) of the window in blocks, or None before its first
+        placement."""
+        lo = np.zeros(3, np.int32)
+        hi = np.zeros(3, np.int32)
+        sh = ctypes.c_int64()
+        rc = self._lib.af_window_state(self.h, _p(lo), _p(hi), ctypes.byref(sh))
+        if rc < 0:
+            self._check(rc)
+        return (lo, hi, sh.value) if rc == 1 else None
 
     def score_points(self, tool_id: int, stream=None):
         self._check(self._lib.af_score_points(self.h, int(tool_id), _stream_handle(stream)))

@@ -72,6 +72,13 @@ struct af_ctx {
   int64_t n_points, n_blocks;   // host mirrors after the last frame
   int32_t bbox_lo[3], bbox_hi[3];
   bool have_bbox;
+  // sliding window (af_set_window): L blocks per axis, centred (in voxels)
+  // on the sensor of the frame that last shifted it; blocks [lo, hi]
+  bool win_on, win_set;
+  int32_t win_L[3], win_c[3], win_lo[3], win_hi[3];
+  int64_t win_shifts;
+  int32_t *win_sel, *win_nsel;  // device: points inside the window (scoring list)
+  std::vector<int64_t> label_init;  // per tool: points whose label slot has been initialised
   hipStream_t last_stream;
   af_frame_stats fstats;
   std::string err;
@@ -206,9 +213,9 @@ static bool grid_covers(const af_ctx *c) {
   return inside;
 }
 
-int ensure_grid(af_ctx *c, hipStream_t s, bool &rebuilt) {
+int ensure_grid(af_ctx *c, hipStream_t s, bool &rebuilt, bool force = false) {
   rebuilt = false;
-  if (grid_covers(c)) return AF_OK;
+  if (!force && grid_covers(c)) return AF_OK;
   const int32_t need = grid_margin_need(c);
   GridDev &g = c->grid;
   GridDev ng;
@@ -229,6 +236,20 @@ int ensure_grid(af_ctx *c, hipStream_t s, bool &rebuilt) {
   if ((int64_t)ng.gd[0] * ng.gd[1] >= (int64_t(1) << 24))
     return fail(c, AF_ENOMEM, "brick grid of %d x %d bricks per layer", ng.gd[0], ng.gd[1]);
   c->graph_stale = true;
+  if (c->grid_bricks == nb && g.gd[0] == ng.gd[0] && g.gd[1] == ng.gd[1] && g.gd[2] == ng.gd[2]) {
+    // same extent at a new origin (a window shift): keep the buffers
+    ng.pred = g.pred;
+    ng.surf = g.surf;
+    ng.occ_any = g.occ_any;
+    ng.occ4 = g.occ4;
+    ng.occ1 = g.occ1;
+    c->grid = ng;
+    launch_grid_fill(c->grid, s);
+    for (const ToolDev &t : c->tools)
+      if (t.entries && launch_table_grid(t, c->grid, s) != 0) return hip_check(c, "table grid");
+    rebuilt = true;
+    return hip_check(c, "grid fill");
+  }
   if (c->grid_bricks > 0) {
     HIP_TRY(c, hipStreamSynchronize(s));
     dev_free(c, g.pred, sizeof(uint32_t) * 32 * c->grid_bricks);
@@ -449,6 +470,7 @@ int af_create(const af_config *cfg, af_ctx **out) {
   c->own_mask.assign(cfg->max_tools, 0);
   c->tools.assign(cfg->max_tools, ToolDev());
   c->tool_bytes.assign(cfg->max_tools, 0);
+  c->label_init.assign(cfg->max_tools, 0);
   for (auto &t : c->tools) memset(&t, 0, sizeof(t));
   if (hipHostMalloc((void **)&c->counters_host, sizeof(FrameCounters)) != hipSuccess)
     return bail(AF_ENOMEM);
@@ -570,6 +592,7 @@ static int tool_finish(af_ctx *c, int32_t tool_id, ToolDev &nt, uint32_t *counts
   ToolDev &t = c->tools[tool_id];
   t = nt;
   c->tool_bytes[tool_id] = sizeof(uint32_t) * (int64_t)total;
+  c->label_init[tool_id] = 0;
   c->last_stream = s;
   if (c->grid_bricks > 0 && launch_table_grid(t, c->grid, s) != 0) return hip_check(c, "table grid");
   HIP_TRY(c, hipMemcpy(&c->tools_dev[tool_id], &t, sizeof(ToolDev), hipMemcpyHostToDevice));
@@ -774,6 +797,40 @@ int af_set_tool_table(af_ctx *c, int32_t tool_id, const af_kernel_table *tab, vo
   return rc;
 }
 
+int af_set_window(af_ctx *c, const int32_t blocks[3]) {
+  if (!c) return AF_EINVAL;
+  if (!blocks) return fail(c, AF_EINVAL, "no window size");
+  if (c->last_frame >= 0 || c->n_points > 0 || c->win_on)
+    return fail(c, AF_EINVAL, "the window is set once, before the first frame");
+  if (c->incr_on || c->gexec)
+    return fail(c, AF_EINVAL, "no window with the incremental mode or a frame graph");
+  for (int a = 0; a < 3; ++a)
+    if (blocks[a] < 2 || blocks[a] > 4096)
+      return fail(c, AF_EINVAL, "window of %d blocks on axis %d (2..4096)", blocks[a], a);
+  ALLOC(c, c->map.free_ids, c->cfg.max_blocks);
+  ALLOC(c, c->map.n_free, 1);
+  ALLOC(c, c->win_sel, c->cfg.max_points);
+  ALLOC(c, c->win_nsel, 1);
+  HIP_TRY(c, hipMemset(c->map.n_free, 0, sizeof(int32_t)));
+  HIP_TRY(c, hipDeviceSynchronize());
+  for (int a = 0; a < 3; ++a) c->win_L[a] = blocks[a];
+  c->win_on = true;
+  c->win_set = false;
+  c->win_shifts = 0;
+  return AF_OK;
+}
+
+int af_window_state(af_ctx *c, int32_t lo[3], int32_t hi[3], int64_t *shifts) {
+  if (!c) return AF_EINVAL;
+  if (!c->win_on) return fail(c, AF_EINVAL, "no window");
+  for (int a = 0; a < 3; ++a) {
+    if (lo) lo[a] = c->win_lo[a];
+    if (hi) hi[a] = c->win_hi[a];
+  }
+  if (shifts) *shifts = c->win_shifts;
+  return c->win_set ? 1 : 0;
+}
+
 int af_integrate_frame_host(af_ctx *c, const float *xyz, int64_t n, const float origin[3],
                             int64_t frame_id, void *stream) {
   if (!c) return AF_EINVAL;
@@ -815,22 +872,56 @@ int af_integrate_frame(af_ctx *c, const float *xyz, int64_t n, const float origi
   }
   hipStream_t s = (hipStream_t)stream;
   int rc;
-  if (n > c->fs.cap) {
+  // Section 3.3: the window follows the sensor (see af_set_window)
+  bool shift = false, thaw = false;
+  int3 wlo = make_int3(-(1 << 30), -(1 << 30), -(1 << 30));
+  int3 whi = make_int3(1 << 30, 1 << 30, 1 << 30);
+  if (c->win_on) {
+    const int32_t qv[3] = {Q.x >> 8, Q.y >> 8, Q.z >> 8};
+    shift = !c->win_set;
+    for (int a = 0; a < 3; ++a)
+      if (c->win_set && 10 * (int64_t)std::abs(qv[a] - c->win_c[a]) > 3 * 8 * (int64_t)c->win_L[a])
+        shift = true;
+    if (shift) {
+      for (int a = 0; a < 3; ++a) {
+        c->win_c[a] = qv[a];
+        c->win_lo[a] = (qv[a] >> 3) - c->win_L[a] / 2;
+        c->win_hi[a] = c->win_lo[a] + c->win_L[a] - 1;
+        c->bbox_lo[a] = c->win_lo[a];
+        c->bbox_hi[a] = c->win_hi[a];
+      }
+      c->have_bbox = true;
+      thaw = c->win_set;
+      c->win_set = true;
+    }
+    wlo = make_int3(c->win_lo[0], c->win_lo[1], c->win_lo[2]);
+    whi = make_int3(c->win_hi[0], c->win_hi[1], c->win_hi[2]);
+  }
+  // a shift may re-create one block per point besides the frame's own
+  constexpr int64_t kPerReturn = kMaxSpan + kMaxBand;
+  const int64_t need = n + (thaw ? (c->n_points + kPerReturn - 1) / kPerReturn : 0);
+  if (need > c->fs.cap) {
     HIP_TRY(c, hipStreamSynchronize(s));
-    if ((rc = alloc_scratch(c, std::max<int64_t>(n, 2 * c->fs.cap))) != AF_OK) return rc;
+    if ((rc = alloc_scratch(c, std::max<int64_t>(need, 2 * c->fs.cap))) != AF_OK) return rc;
   }
   const int32_t frame = (int32_t)frame_id;
   hipEvent_t t0 = timing_mark(c, s);
-  launch_set_frame_args(c->fargs, n, Q, frame, s);
+  if (thaw) {
+    launch_window_evict(c->map, c->pts, c->n_blocks, c->n_points, wlo, whi, s);
+    c->win_shifts += 1;
+  }
+  launch_set_frame_args(c->fargs, n, Q, frame, wlo, whi, s);
   launch_frame_prep(xyz, c->fargs, n, c->p, c->map, c->pts, c->fs, c->counters, s);
+  if (thaw) launch_window_thaw(c->map, c->pts, c->fs, c->counters, c->n_points, wlo, whi, s);
   launch_assign_blocks(c->map, c->fs, c->counters, c->fargs, s);
   launch_commit_blocks(c->map, c->counters, s);
+  if (thaw) launch_window_link(c->map, c->pts, c->n_points, wlo, whi, s);
   HIP_TRY(c, hipMemcpyAsync(c->counters_host, c->counters, offsetof(FrameCounters, fold),
                             hipMemcpyDeviceToHost, s));
   HIP_TRY(c, hipStreamSynchronize(s));
   if ((rc = hip_check(c, "frame prep")) != AF_OK) return rc;
   FrameCounters h = *c->counters_host;
-  if (h.n_new_blocks > 0) {
+  if (h.n_new_blocks > 0 && !c->win_on) {   // (with a window the box is the window)
     for (int a = 0; a < 3; ++a) {
       if (!c->have_bbox || h.bmin[a] < c->bbox_lo[a]) c->bbox_lo[a] = h.bmin[a];
       if (!c->have_bbox || h.bmax[a] > c->bbox_hi[a]) c->bbox_hi[a] = h.bmax[a];
@@ -838,12 +929,15 @@ int af_integrate_frame(af_ctx *c, const float *xyz, int64_t n, const float origi
     c->have_bbox = true;
   }
   bool rebuilt = false;
-  if ((rc = ensure_grid(c, s, rebuilt)) != AF_OK) return rc;
+  if ((rc = ensure_grid(c, s, rebuilt, shift)) != AF_OK) return rc;
   launch_touch_band(c->fargs, n, c->p, c->map, c->fs, c->counters, s);
   launch_points_append(h.n_new_points, c->map, c->pts, c->fs, c->counters, c->fargs, s);
   launch_commit_points(c->pts, c->counters, s);
   launch_points_view(c->fargs, n, c->p, c->pts, c->fs, s);
-  int64_t nb_after = std::min<int64_t>((int64_t)h.blocks_before + h.n_new_blocks, c->cfg.max_blocks);
+  // new blocks take evicted ids first
+  int64_t nb_after = std::min<int64_t>(
+      (int64_t)h.blocks_before + std::max<int64_t>(0, (int64_t)h.n_new_blocks - h.free_before),
+      c->cfg.max_blocks);
   hipEvent_t t1 = timing_mark(c, s);
   launch_integrate(c->fargs, n, c->p, c->map, c->fs, c->counters, c->grid,
                    std::max<int64_t>(1, std::min<int64_t>(nb_after, n * (kMaxSpan + kMaxBand))), s);
@@ -871,6 +965,47 @@ int af_integrate_frame(af_ctx *c, const float *xyz, int64_t n, const float origi
 
 static int cached_normals(af_ctx *c, hipStream_t s);
 
+// With a sliding window only the points inside it are scored (fresh normals
+// over the window's point list); the others keep their last labels, and a
+// point never scored reads 255.
+static int score_window(af_ctx *c, int32_t tool_id, hipStream_t s) {
+  ToolDev &t = c->tools[tool_id];
+  if (!score_variant_takes_list(score_variant_default(), t))
+    return fail(c, AF_EINVAL, "tool %d: K above 1024 or reach above 255 voxels (not with a "
+                              "sliding window)", tool_id);
+  const int variant =
+      score_variant_takes_list(c->score_variant, t) ? c->score_variant : score_variant_default();
+  const int3 lo = make_int3(c->win_lo[0], c->win_lo[1], c->win_lo[2]);
+  const int3 hi = make_int3(c->win_hi[0], c->win_hi[1], c->win_hi[2]);
+  int64_t &init = c->label_init[tool_id];
+  if (init < c->n_points) {
+    launch_label_fill(t.label, t.first_free, init, c->n_points, s);
+    init = c->n_points;
+  }
+  hipEvent_t t0 = timing_mark(c, s);
+  HIP_TRY(c, hipMemsetAsync(t.counters, 0, sizeof(ScoreCounters), s));
+  launch_window_list(c->pts, c->n_points, lo, hi, c->win_sel, c->win_nsel, s);
+  PointsDev ps = c->pts;
+  ps.sel = c->win_sel;
+  ps.n_sel = c->win_nsel;
+  hipEvent_t t1 = timing_mark(c, s);
+  launch_normals(c->p, c->map, ps, c->grid, c->n_points, s, true);
+  hipEvent_t t2 = timing_mark(c, s);
+  launch_mask(c->p, ps, t, c->grid, c->n_points, s, true);
+  hipEvent_t t3 = timing_mark(c, s);
+  launch_score(c->p, ps, t, c->grid, c->n_points, variant, c->work, s, true);
+  hipEvent_t t4 = timing_mark(c, s);
+  if (c->timing) {
+    timing_pair(c, ST_SCORE, t0, t4);
+    timing_pair(c, ST_K_NORMALS, t1, t2);
+    timing_pair(c, ST_K_MASK, t2, t3);
+    timing_pair(c, ST_K_SCORE, t3, t4);
+    c->score_calls += 1;
+  }
+  c->last_stream = s;
+  return hip_check(c, "score (window)");
+}
+
 int af_score_points(af_ctx *c, int32_t tool_id, void *stream) {
   if (!c) return AF_EINVAL;
   if (c->graph_dirty) {
@@ -883,6 +1018,7 @@ int af_score_points(af_ctx *c, int32_t tool_id, void *stream) {
   hipStream_t s = (hipStream_t)stream;
   int rc = regrid(c, s);
   if (rc != AF_OK) return rc;
+  if (c->win_on) return score_window(c, tool_id, s);
   hipEvent_t t0 = timing_mark(c, s);
   HIP_TRY(c, hipMemsetAsync(t.counters, 0, sizeof(ScoreCounters), s));
   hipEvent_t t1 = timing_mark(c, s);
@@ -974,6 +1110,7 @@ static int cached_normals(af_ctx *c, hipStream_t s) {
 
 int af_score_tools(af_ctx *c, const int32_t *tool_ids, int32_t n_tools, void *stream) {
   if (!c) return AF_EINVAL;
+  if (c->win_on) return fail(c, AF_EINVAL, "multi-tool scoring is not available with a window");
   int rc;
   if (c->graph_dirty && (rc = graph_settle(c)) != AF_OK) return rc;
   ToolSet set;
@@ -1050,6 +1187,7 @@ static int graph_prepare(af_ctx *c, const float lo[3], const float hi[3], int64_
 
 int af_graph_prepare(af_ctx *c, const float lo[3], const float hi[3], int64_t max_returns,
                      const int32_t *tool_ids, int32_t n_tools, void *stream) {
+  if (c && c->win_on) return fail(c, AF_EINVAL, "frame graphs are not available with a window");
   return graph_prepare(c, lo, hi, max_returns, tool_ids, n_tools, stream, true);
 }
 
@@ -1169,7 +1307,9 @@ int af_graph_frame(af_ctx *c, const float *xyz, int64_t n, const float origin[3]
   hipStream_t s = (hipStream_t)stream;
   if (n > 0 && xyz != c->slot_xyz)
     HIP_TRY(c, hipMemcpyAsync(c->slot_xyz, xyz, sizeof(float) * 3 * n, hipMemcpyDefault, s));
-  launch_set_frame_args(c->fargs, n, Q, (int32_t)frame_id, s);
+  launch_set_frame_args(c->fargs, n, Q, (int32_t)frame_id,
+                        make_int3(-(1 << 30), -(1 << 30), -(1 << 30)),
+                        make_int3(1 << 30, 1 << 30, 1 << 30), s);
   HIP_TRY(c, hipGraphLaunch(c->gexec, s));
   c->last_frame = frame_id;
   c->last_stream = s;
@@ -1201,6 +1341,7 @@ static void smooth_build(af_ctx *c, const SmoothBuffers &b, hipStream_t s, Smoot
 // TSDF values and the brick table for the smoothed score, rebuilt from the
 // current map (a few tens of microseconds; the map may change between calls).
 static int smooth_prepare(af_ctx *c, hipStream_t s, SmoothField &f) {
+  if (c->win_on) return fail(c, AF_EINVAL, "the smoothed score is not available with a window");
   int rc;
   if (c->graph_dirty && (rc = graph_settle(c)) != AF_OK) return rc;
   if ((rc = regrid(c, s)) != AF_OK) return rc;
@@ -1334,6 +1475,7 @@ int af_smooth_eval_static(af_ctx *c, const float *p, const float *q, int64_t n,
       (!dq) != (!dp) || (n > 0 && !s_out && !dq))
     return fail(c, AF_EINVAL, "bad smoothed-score arguments");
   hipStream_t s = (hipStream_t)stream;
+  if (c->win_on) return fail(c, AF_EINVAL, "the smoothed score is not available with a window");
   uint8_t *base = nullptr;
   int rc = static_scratch(c, &base);
   if (rc != AF_OK) return rc;
@@ -1385,6 +1527,7 @@ int af_incremental_enable(af_ctx *c, int32_t tool_id, int32_t budget) {
   const ToolDev &t = c->tools[tool_id];
   if (!t.entries) return fail(c, AF_ENOTOOL, "tool %d has no kernels", tool_id);
   if (budget < 1) return fail(c, AF_EINVAL, "budget must be positive");
+  if (c->win_on) return fail(c, AF_EINVAL, "the incremental mode is not available with a window");
   if (c->p.n_c > 255) return fail(c, AF_EINVAL, "n_c above 255");
   if (c->last_frame >= 0 || c->n_points > 0)
     return fail(c, AF_EINVAL, "the incremental mode starts before the first frame");
@@ -1695,6 +1838,7 @@ int af_tune_score(af_ctx *c, int32_t tool_id, int32_t reps, void *stream, int32_
     if (rc != AF_OK) return rc;
   }
   if (tool_id < 0 || tool_id >= c->cfg.max_tools) return fail(c, AF_EINVAL, "bad tool id");
+  if (c->win_on) return fail(c, AF_EINVAL, "variant tuning is not available with a window");
   ToolDev &t = c->tools[tool_id];
   if (!t.entries) return fail(c, AF_ENOTOOL, "tool %d has no kernels", tool_id);
   if (reps < 1) reps = 1;
@@ -1936,6 +2080,11 @@ int af_frame_stats_get(af_ctx *c, af_frame_stats *st) {
   st->n_points = c->n_points;
   st->voxels_folded = (int64_t)h.voxels_folded;
   st->n_blocks = c->n_blocks;
+  if (c->map.n_free) {   // sliding window: blocks held, not ids ever handed out
+    int32_t nf = 0;
+    HIP_TRY(c, hipMemcpy(&nf, c->map.n_free, sizeof(int32_t), hipMemcpyDeviceToHost));
+    st->n_blocks -= nf;
+  }
   st->new_blocks = h.n_new_blocks;
   return AF_OK;
 }

@@ -85,6 +85,10 @@ __device__ inline Span cube_span(int4 P, int R) {
   return s;
 }
 
+__device__ inline bool in_box(int32_t bx, int32_t by, int32_t bz, int3 lo, int3 hi) {
+  return bx >= lo.x && bx <= hi.x && by >= lo.y && by <= hi.y && bz >= lo.z && bz <= hi.z;
+}
+
 // --------------------------------------------------------------- prep
 // Quantise each return, insert the blocks of its cube and of its band
 // samples, and insert its voxel into the point set.
@@ -93,6 +97,7 @@ k_frame_prep(const float *__restrict__ xyz, const FrameArgs *fa, Params p, MapDe
              PointsDev pts, FrameScratch fs, FrameCounters *c) {
   const int64_t n = fa->n;
   const int3 Q = fa->Q;
+  const int3 wlo = fa->wlo, whi = fa->whi;
   int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   bool in = r < n;
   bool ok = in;
@@ -126,6 +131,10 @@ k_frame_prep(const float *__restrict__ xyz, const FrameArgs *fa, Params p, MapDe
   for (int bz = 0; bz < sp.n[2]; ++bz)
     for (int by = 0; by < sp.n[1]; ++by)
       for (int bx = 0; bx < sp.n[0]; ++bx) {
+        if (!in_box(sp.lo[0] + bx, sp.lo[1] + by, sp.lo[2] + bz, wlo, whi)) {
+          fs.span[r * kMaxSpan + idx++] = -1;   // outside the window: not written
+          continue;
+        }
         bool fresh;
         int32_t s = hash_insert(m.h, pack_key(sp.lo[0] + bx, sp.lo[1] + by, sp.lo[2] + bz), fresh);
         if (s < 0) full = true;
@@ -140,6 +149,10 @@ k_frame_prep(const float *__restrict__ xyz, const FrameArgs *fa, Params p, MapDe
     int64_t vx = (P[0] + div_round(lam * g[0], L)) >> 8;
     int64_t vy = (P[1] + div_round(lam * g[1], L)) >> 8;
     int64_t vz = (P[2] + div_round(lam * g[2], L)) >> 8;
+    if (!in_box((int32_t)(vx >> 3), (int32_t)(vy >> 3), (int32_t)(vz >> 3), wlo, whi)) {
+      fs.band[2 * (r * kMaxBand + j)] = -3;   // outside the window: neither marked nor counted
+      continue;
+    }
     bool fresh;
     int32_t s = hash_insert(m.h, pack_key(vx >> 3, vy >> 3, vz >> 3), fresh);
     if (s < 0) full = true;
@@ -148,7 +161,12 @@ k_frame_prep(const float *__restrict__ xyz, const FrameArgs *fa, Params p, MapDe
     fs.band[2 * (r * kMaxBand + j) + 1] = (int)((vx & 7) | ((vy & 7) << 3) | ((vz & 7) << 6));
   }
   if (j < kMaxBand) fs.band[2 * (r * kMaxBand + j)] = -2;  // end marker
-  // the return's voxel is a surface point
+  // the return's voxel is a surface point (inside the window)
+  if (!in_box(P[0] >> 11, P[1] >> 11, P[2] >> 11, wlo, whi)) {
+    fs.pslot[r] = -1;
+    if (full) atomicOr(&c->status, kStatusHashFull);
+    return;
+  }
   bool fresh;
   int32_t ps = hash_insert(pts.h, pack_key(P[0] >> 8, P[1] >> 8, P[2] >> 8), fresh);
   if (ps < 0) full = true;
@@ -173,6 +191,7 @@ __global__ void k_reset_counters(FrameCounters *c, MapDev m, PointsDev pts) {
   }
   c->blocks_before = *m.n_blocks;
   c->points_before = *pts.n_points;
+  c->free_before = m.n_free ? *m.n_free : 0;
 }
 
 // One workgroup per new block: assign its id and clear its voxels.
@@ -181,9 +200,10 @@ k_assign_blocks(MapDev m, FrameScratch fs, FrameCounters *c, const FrameArgs *fa
   const int32_t frame = fa->frame;
   int n_new = c->n_new_blocks;
   int64_t base = *m.n_blocks;
+  const int nfree = c->free_before;   // evicted ids first (sliding window)
   for (int i = blockIdx.x; i < n_new; i += gridDim.x) {
     int32_t slot = fs.new_blocks[i];
-    int64_t id = base + i;
+    int64_t id = i < nfree ? (int64_t)m.free_ids[nfree - 1 - i] : base + (i - nfree);
     if (id >= m.max_blocks) {
       if (threadIdx.x == 0) {
         m.h.vals[slot] = -1;
@@ -217,6 +237,9 @@ k_assign_blocks(MapDev m, FrameScratch fs, FrameCounters *c, const FrameArgs *fa
 __global__ void k_commit_blocks(MapDev m, FrameCounters *c) {
   int64_t base = *m.n_blocks;
   int64_t add = c->n_new_blocks;
+  const int64_t nfree = c->free_before;
+  if (m.n_free) *m.n_free = (int32_t)(add < nfree ? nfree - add : 0);
+  add = add > nfree ? add - nfree : 0;
   if (base + add > m.max_blocks) add = m.max_blocks - base;
   *m.n_blocks = (int32_t)(base + add);
 }
@@ -246,6 +269,7 @@ k_touch_band(const FrameArgs *fa, Params p, MapDev m, FrameScratch fs, FrameCoun
       for (int j = 0; j < kMaxBand; ++j) {
         int32_t s = fs.band[2 * (r * kMaxBand + j)];
         if (s == -2) break;
+        if (s == -3) continue;
         ++marks;
         int32_t id = s >= 0 ? m.h.vals[s] : -1;
         if (id < 0) continue;
@@ -664,6 +688,7 @@ __global__ void __launch_bounds__(kBlockVox)
 k_grid_rebuild(Params p, MapDev m, GridDev g, int64_t n_blocks) {
   __shared__ uint8_t code[kBlockVox];
   for (int64_t id = blockIdx.x; id < n_blocks; id += gridDim.x) {
+    if (m.bkey[id] == kEmpty) continue;   // an evicted block's free id
     const int t = threadIdx.x;
     const int64_t v = id * kBlockVox + t;
     write_brick(p, m, g, id, m.S[v], m.W[v], code, m.clr[id * 16 + (t >> 5)],
@@ -696,10 +721,133 @@ __global__ void k_zero_words(uint32_t *p, int64_t n) {
     p[i] = 0u;
 }
 
-__global__ void k_set_frame_args(FrameArgs *fa, int64_t n, int3 Q, int32_t frame) {
+__global__ void k_set_frame_args(FrameArgs *fa, int64_t n, int3 Q, int32_t frame, int3 wlo,
+                                 int3 whi) {
   fa->n = n;
   fa->Q = Q;
   fa->frame = frame;
+  fa->wlo = wlo;
+  fa->whi = whi;
+}
+
+// ------------------------------------------------------- sliding window
+// One workgroup per block id: a live block outside [lo, hi] is cleared (its
+// voxels read unknown again), its key removed and its id pushed on the free
+// list.
+__global__ void __launch_bounds__(kThreads)
+k_window_evict(MapDev m, int64_t n_blocks, int3 lo, int3 hi) {
+  for (int64_t id = blockIdx.x; id < n_blocks; id += gridDim.x) {
+    const int64_t key = m.bkey[id];
+    if (key == kEmpty) continue;
+    int32_t b[3];
+    unpack_key(key, b[0], b[1], b[2]);
+    if (in_box(b[0], b[1], b[2], lo, hi)) continue;
+    for (int t = threadIdx.x; t < kBlockVox; t += kThreads) {
+      m.S[id * kBlockVox + t] = 0;
+      m.W[id * kBlockVox + t] = 0;
+    }
+    if (threadIdx.x < 16) {
+      m.clr[id * 16 + threadIdx.x] = 0;
+      m.surf[id * 16 + threadIdx.x] = 0;
+    }
+    __syncthreads();   // every thread has read bkey[id] before it changes
+    if (threadIdx.x == 0) {
+      m.bkey[id] = kEmpty;
+      m.touched[id] = -1;
+      m.free_ids[atomicAdd(m.n_free, 1)] = (int32_t)id;
+    }
+  }
+}
+
+__global__ void k_hash_clear(HashTable h) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= (int64_t)h.mask;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    h.keys[i] = kEmpty;
+    h.vals[i] = -1;
+  }
+}
+
+// Live blocks back into the cleared hash.
+__global__ void __launch_bounds__(kThreads) k_window_rehash(MapDev m, int64_t n_blocks) {
+  const int64_t id = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (id >= n_blocks) return;
+  const int64_t key = m.bkey[id];
+  if (key == kEmpty) return;
+  bool fresh;
+  const int32_t s = hash_insert(m.h, key, fresh);
+  if (s >= 0) m.h.vals[s] = (int32_t)id;   // the hash holds 2 max_blocks slots: never full
+}
+
+__device__ inline void point_block(const PointsDev &pts, int64_t i, int32_t v[3]) {
+  unpack_key(pts.key[i], v[0], v[1], v[2]);
+}
+
+// Points outside [lo, hi] lose their voxel address (their block is gone).
+__global__ void __launch_bounds__(kThreads)
+k_window_points(PointsDev pts, int64_t n_points, int3 lo, int3 hi) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n_points) return;
+  int32_t v[3];
+  point_block(pts, i, v);
+  if (!in_box(v[0] >> 3, v[1] >> 3, v[2] >> 3, lo, hi)) pts.addr[i] = -1;
+}
+
+// Points inside [lo, hi] without a block: their block joins the frame's new
+// blocks (assigned and cleared with them).
+__global__ void __launch_bounds__(kThreads)
+k_window_thaw(MapDev m, PointsDev pts, FrameScratch fs, FrameCounters *c, int64_t n_points,
+              int3 lo, int3 hi) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n_points || pts.addr[i] >= 0) return;
+  int32_t v[3];
+  point_block(pts, i, v);
+  if (!in_box(v[0] >> 3, v[1] >> 3, v[2] >> 3, lo, hi)) return;
+  bool fresh;
+  const int32_t s = hash_insert(m.h, pack_key(v[0] >> 3, v[1] >> 3, v[2] >> 3), fresh);
+  if (s < 0) atomicOr(&c->status, kStatusHashFull);
+  if (fresh) fs.new_blocks[atomicAdd(&c->n_new_blocks, 1)] = s;
+}
+
+// After assignment: those points get their voxel address and surface bit.
+__global__ void __launch_bounds__(kThreads)
+k_window_link(MapDev m, PointsDev pts, int64_t n_points, int3 lo, int3 hi) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n_points || pts.addr[i] >= 0) return;
+  int32_t v[3];
+  point_block(pts, i, v);
+  if (!in_box(v[0] >> 3, v[1] >> 3, v[2] >> 3, lo, hi)) return;
+  const int32_t bs = hash_find(m.h, pack_key(v[0] >> 3, v[1] >> 3, v[2] >> 3));
+  const int32_t bid = bs >= 0 ? m.h.vals[bs] : -1;
+  if (bid < 0) return;   // block capacity exhausted (the frame reports it)
+  const int vi = (v[0] & 7) | ((v[1] & 7) << 3) | ((v[2] & 7) << 6);
+  pts.addr[i] = bid * kBlockVox + vi;
+  atomicOr(&m.surf[(int64_t)bid * 16 + (vi >> 5)], 1u << (vi & 31));
+}
+
+// Points inside [lo, hi] listed (one atomic per wave).
+__global__ void __launch_bounds__(kThreads)
+k_window_list(PointsDev pts, int64_t n_points, int3 lo, int3 hi, int32_t *sel, int32_t *n_sel) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  bool take = false;
+  if (i < n_points) {
+    int32_t v[3];
+    point_block(pts, i, v);
+    take = in_box(v[0] >> 3, v[1] >> 3, v[2] >> 3, lo, hi);
+  }
+  const unsigned long long bal = __ballot(take);
+  const int lane = lane_id();
+  int base = 0;
+  if (lane == 0 && bal) base = atomicAdd(n_sel, __popcll(bal));
+  base = __shfl(base, 0);
+  if (take) sel[base + __popcll(bal & ((1ull << lane) - 1ull))] = (int32_t)i;
+}
+
+__global__ void k_label_fill(uint8_t *label, int16_t *ff, int64_t from, int64_t to) {
+  for (int64_t i = from + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < to;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    label[i] = 255;
+    ff[i] = -1;
+  }
 }
 
 inline unsigned grid_for(int64_t threads) {
@@ -719,8 +867,55 @@ void launch_stick_status(FrameCounters *c, hipStream_t s) {
   hipLaunchKernelGGL(k_stick_status, dim3(1), dim3(1), 0, s, c);
 }
 
-void launch_set_frame_args(FrameArgs *fa, int64_t n, int3 Q, int32_t frame, hipStream_t s) {
-  hipLaunchKernelGGL(k_set_frame_args, dim3(1), dim3(1), 0, s, fa, n, Q, frame);
+void launch_set_frame_args(FrameArgs *fa, int64_t n, int3 Q, int32_t frame, int3 wlo, int3 whi,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_set_frame_args, dim3(1), dim3(1), 0, s, fa, n, Q, frame, wlo, whi);
+}
+
+void launch_window_evict(MapDev m, PointsDev pts, int64_t n_blocks, int64_t n_points, int3 lo,
+                         int3 hi, hipStream_t s) {
+  if (n_blocks > 0)
+    hipLaunchKernelGGL(k_window_evict, dim3((unsigned)std::min<int64_t>(n_blocks, 8192)),
+                       dim3(kThreads), 0, s, m, n_blocks, lo, hi);
+  const int64_t slots = (int64_t)m.h.mask + 1;
+  hipLaunchKernelGGL(k_hash_clear, dim3((unsigned)std::min<int64_t>(4096, (slots + 255) / 256)),
+                     dim3(256), 0, s, m.h);
+  if (n_blocks > 0)
+    hipLaunchKernelGGL(k_window_rehash, dim3(grid_for(n_blocks)), dim3(kThreads), 0, s, m,
+                       n_blocks);
+  if (n_points > 0)
+    hipLaunchKernelGGL(k_window_points, dim3(grid_for(n_points)), dim3(kThreads), 0, s, pts,
+                       n_points, lo, hi);
+}
+
+void launch_window_thaw(MapDev m, PointsDev pts, FrameScratch fs, FrameCounters *c,
+                        int64_t n_points, int3 lo, int3 hi, hipStream_t s) {
+  if (n_points > 0)
+    hipLaunchKernelGGL(k_window_thaw, dim3(grid_for(n_points)), dim3(kThreads), 0, s, m, pts, fs,
+                       c, n_points, lo, hi);
+}
+
+void launch_window_link(MapDev m, PointsDev pts, int64_t n_points, int3 lo, int3 hi,
+                        hipStream_t s) {
+  if (n_points > 0)
+    hipLaunchKernelGGL(k_window_link, dim3(grid_for(n_points)), dim3(kThreads), 0, s, m, pts,
+                       n_points, lo, hi);
+}
+
+void launch_window_list(PointsDev pts, int64_t n_points, int3 lo, int3 hi, int32_t *sel,
+                        int32_t *n_sel, hipStream_t s) {
+  launch_zero_words(n_sel, sizeof(int32_t), s);
+  if (n_points > 0)
+    hipLaunchKernelGGL(k_window_list, dim3(grid_for(n_points)), dim3(kThreads), 0, s, pts,
+                       n_points, lo, hi, sel, n_sel);
+}
+
+void launch_label_fill(uint8_t *label, int16_t *first_free, int64_t from, int64_t to,
+                       hipStream_t s) {
+  if (to > from)
+    hipLaunchKernelGGL(k_label_fill,
+                       dim3((unsigned)std::min<int64_t>(1024, (to - from + 255) / 256)),
+                       dim3(256), 0, s, label, first_free, from, to);
 }
 
 void launch_frame_prep(const float *xyz, const FrameArgs *fa, int64_t nb, const Params &p,

@@ -69,6 +69,7 @@ struct FrameCounters {
   int32_t n_changed;   // voxels that received a contribution (listed when fs.changed is set)
   int32_t bmin[3], bmax[3];
   int32_t blocks_before, points_before;
+  int32_t free_before;   // evicted ids available when the frame started
   int32_t sticky;   // status bits of recorded frames since the host last looked (not reset per frame)
   int32_t sbmin[3], sbmax[3];   // block box of those frames (empty when sbmin > sbmax)
   // per-slot fold statistics: [slot][0] applied pairs, [1] cone-excluded
@@ -108,8 +109,12 @@ struct MapDev {
   uint32_t *surf;                // [max_blocks * 16]
   int32_t *touched;              // [max_blocks] last frame that touched the block
   int32_t *tpos;                 // [max_blocks] position in that frame's touched list
-  int32_t *n_blocks;             // device counter
+  int32_t *n_blocks;             // device counter (ids ever handed out)
   int64_t max_blocks;
+  // sliding window only (null otherwise): ids of evicted blocks, reused
+  // last-in first-out before n_blocks grows
+  int32_t *free_ids;             // [max_blocks]
+  int32_t *n_free;               // device counter
 };
 
 struct PointsDev {
@@ -253,8 +258,10 @@ struct FrameArgs {
   int64_t n;      // returns in the frame
   int3 Q;         // quantised sensor origin
   int32_t frame;  // frame id
+  int3 wlo, whi;  // block box the frame may write (the sliding window; else unbounded)
 };
-void launch_set_frame_args(FrameArgs *fa, int64_t n, int3 Q, int32_t frame, hipStream_t s);
+void launch_set_frame_args(FrameArgs *fa, int64_t n, int3 Q, int32_t frame, int3 wlo, int3 whi,
+                           hipStream_t s);
 
 // Cached normal axes (state: -2 pending, 0 none, 1 axis valid).
 struct NormalCache {
@@ -386,6 +393,24 @@ void launch_points_append(int64_t n_new, MapDev m, PointsDev pts, FrameScratch f
 void launch_commit_points(PointsDev pts, FrameCounters *c, hipStream_t s);
 void launch_points_view(const FrameArgs *fa, int64_t nb, const Params &p, PointsDev pts,
                         FrameScratch fs, hipStream_t s);
+// Sliding window (Section 3.3).  On a shift, before the frame: blocks
+// outside the new box [lo, hi] are cleared and their ids freed, the block
+// hash is rebuilt from the live blocks, and points outside the box lose their
+// voxel address.  In the shifting frame, between prep and block assignment,
+// the blocks of points back inside the box are inserted (thaw); after
+// assignment those points get their address and surface bit again (link).
+void launch_window_evict(MapDev m, PointsDev pts, int64_t n_blocks, int64_t n_points, int3 lo,
+                         int3 hi, hipStream_t s);
+void launch_window_thaw(MapDev m, PointsDev pts, FrameScratch fs, FrameCounters *c,
+                        int64_t n_points, int3 lo, int3 hi, hipStream_t s);
+void launch_window_link(MapDev m, PointsDev pts, int64_t n_points, int3 lo, int3 hi,
+                        hipStream_t s);
+// Points of [0, n_points) inside the box, listed into sel (count in *n_sel).
+void launch_window_list(PointsDev pts, int64_t n_points, int3 lo, int3 hi, int32_t *sel,
+                        int32_t *n_sel, hipStream_t s);
+// label[i] = 255 (never evaluated), first_free[i] = -1 for i in [from, to).
+void launch_label_fill(uint8_t *label, int16_t *first_free, int64_t from, int64_t to,
+                       hipStream_t s);
 void launch_grid_fill(GridDev g, hipStream_t s);
 void launch_grid_rebuild(const Params &p, MapDev m, GridDev g, int64_t n_blocks,
                          hipStream_t s);

@@ -1,0 +1,113 @@
+"""Sliding window (Section 3.3) on the GPU against the oracle, bit for bit:
+the 48-frame walk around a box cluster with a 20-block window (it shifts
+about every four frames and regions leave and come back).  After every
+frame: the window box and shift count, the frame statistics; every third
+frame: labels and first free orientations of every point (those outside the
+window keep theirs), the TSDF and the point records.  The block capacity is
+the window's own block count, so the map must reuse evicted blocks."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+BLOCKS = 20
+FRAME_KEYS = ("n_in", "n_valid", "n_dropped", "pairs_applied", "pairs_excluded",
+              "band_marks", "new_points", "n_points", "voxels_folded")
+SCORE_KEYS = ("n_points", "n_confident", "n_accessible", "n_blocked", "n_no_candidate",
+              "candidate_tests", "canonical_tests", "canonical_lookups")
+
+
+def _cmp_tsdf(ctx, orc):
+    g = ctx.read_tsdf()
+    o = orc.read_tsdf()
+    assert len(g[0]) == len(o[0])
+    for a, b, name in zip(g, o, ("key", "S", "W", "cleared")):
+        assert np.array_equal(np.asarray(a, np.int64), np.asarray(b, np.int64)), name
+
+
+def _cmp_points(ctx, orc):
+    g, o = ctx.read_points(), orc.read_points()
+    for k in ("key", "first_frame", "n_vp", "vp", "sumq", "nq"):
+        assert np.array_equal(np.asarray(g[k], np.int64), np.asarray(o[k], np.int64)), k
+
+
+def test_window_walk(synth_mod, oracle_mod):
+    import torch
+    from paper_2608_06412_amd import Context, default_config
+    assert torch.cuda.is_available()
+    w = synth_mod.window_walk()
+    frames = w.frames()
+    cfg = default_config(w.voxel, w.trunc, r_c=w.r_c, max_blocks=BLOCKS ** 3,
+                         max_points=1 << 17, max_orientations=64, max_tools=1)
+    ctx = Context(cfg)
+    ctx.set_window([BLOCKS] * 3)
+    assert ctx.window_state() is None
+    orc = oracle_mod.Oracle(voxel=w.voxel, trunc=w.trunc, r_c=w.r_c)
+    orc.set_window([BLOCKS] * 3)
+    ctx.set_tool_kernels(0, w.tool, w.rot)
+    orc.set_tool(0, w.tool, w.rot)
+    K = len(w.rot)
+    max_held = 0
+    for f in frames:
+        print("window frame", f.frame_id, flush=True)
+        x = torch.from_numpy(f.xyz).cuda()
+        ctx.integrate_frame(x, f.origin, f.frame_id)
+        orc.integrate_frame(f.xyz, f.origin, f.frame_id)
+        glo, ghi, gsh = ctx.window_state()
+        olo, ohi, osh = orc.window()
+        assert glo.tolist() == olo.tolist() and ghi.tolist() == ohi.tolist() and gsh == osh
+        gs, os_ = ctx.frame_stats(), orc.frame_stats()
+        assert {k: gs[k] for k in FRAME_KEYS} == {k: os_[k] for k in FRAME_KEYS}
+        max_held = max(max_held, gs["n_blocks"])
+        if f.frame_id % 3 == 2 or f.frame_id == len(frames) - 1:
+            ctx.score_points(0)
+            orc.score(0)
+            lab = ctx.read_labels(0)
+            r = orc.read_results(K)
+            assert np.array_equal(lab["label"], r["label"])
+            assert np.array_equal(lab["first_free"].astype(np.int64), r["first_free"])
+            gst, ost = ctx.score_stats(0), orc.score_stats()
+            assert {k: gst[k] for k in SCORE_KEYS} == {k: ost[k] for k in SCORE_KEYS}
+            _cmp_tsdf(ctx, orc)
+            _cmp_points(ctx, orc)
+    assert orc.window()[2] >= 5
+    assert max_held <= BLOCKS ** 3
+    lab = ctx.read_labels(0)
+    assert np.any(lab["label"] == 255) and np.any(lab["label"] == 1)
+
+
+def test_window_argument_rules(synth_mod):
+    import torch
+    from paper_2608_06412_amd import AFError, Context, default_config
+    w = synth_mod.tiny()
+    cfg = default_config(w.voxel, w.trunc, r_c=w.r_c, max_blocks=1 << 12, max_points=1 << 14,
+                         max_orientations=64, max_tools=1)
+    ctx = Context(cfg)
+    with pytest.raises(AFError):
+        ctx.set_window([1, 8, 8])
+    with pytest.raises(AFError):
+        ctx.set_window([8, 8, 5000])
+    ctx.set_window([8, 8, 8])
+    with pytest.raises(AFError):
+        ctx.set_window([8, 8, 8])            # once
+    ctx.set_tool_kernels(0, w.tool, w.rot)
+    for call in (lambda: ctx.incremental_enable(0, 100),
+                 lambda: ctx.graph_prepare([-1, -1, -1], [1, 1, 1], 1000, [0]),
+                 lambda: ctx.score_tools([0]),
+                 lambda: ctx.tune_score(0)):
+        with pytest.raises(AFError):
+            call()
+    f = w.frames(1)[0]
+    ctx.integrate_frame(torch.from_numpy(f.xyz).cuda(), f.origin, 0)
+    p = torch.zeros((1, 3), dtype=torch.float32, device="cuda")
+    q = torch.tensor([[1.0, 0.0, 0.0, 0.0]], dtype=torch.float32, device="cuda")
+    smp = torch.zeros((4, 3), dtype=torch.float32, device="cuda")
+    out = torch.zeros(1, dtype=torch.float32, device="cuda")
+    with pytest.raises(AFError):
+        ctx.smooth_eval(p, q, smp, s=out)
+    plain = Context(cfg)
+    plain.integrate_frame(torch.from_numpy(f.xyz).cuda(), f.origin, 0)
+    with pytest.raises(AFError):
+        plain.set_window([8, 8, 8])          # after the first frame
+    with pytest.raises(AFError):
+        plain.window_state()                 # no window
