@@ -49,6 +49,14 @@ stored; the last evaluation found every candidate blocked / no candidate).
 Trigger (iii) re-queues the points labelled BLOCKED or NO_CANDIDATE after the
 previous frame.
 
+With a sliding window (Section 3.3, set on the C oracle before the first
+frame): trigger (iii) re-queues only the inaccessible points inside the
+window (the paper's wording), and the nearest resolved neighbour of the
+coarse-to-fine search is taken among points inside the window.  Nothing else
+changes: points outside have no voxel (W = 0), so they are never selected,
+trigger (i) needs W > 0 before and after, and their label follows from
+c = 0.
+
 Coarse-to-fine direction search (Section 3.6, optional): an evaluation tests
 only the orientations of a coarse pass and of a fine window around the best
 direction of the nearest resolved neighbour.  Readings, for any orientation
@@ -182,6 +190,9 @@ class IncrementalOracle:
         the fine window of its nearest resolved neighbour's stored direction."""
         c = self.c2f
         res = [(k, st["best_dir"]) for k, st in self.state.items() if st["best"] < self.n_c]
+        if res:   # only points inside the sliding window
+            ins = self._inside([k for k, _ in res])
+            res = [r for r, i in zip(res, ins) if i]
         allow = np.tile(c["coarse"], (len(chosen), 1))
         self.last_neighbour = {}
         if not res or not chosen:
@@ -204,6 +215,16 @@ class IncrementalOracle:
     def _label(self, st, W):
         return label_of(st, W, self.n_c, self.k_c, self.accept)
 
+    def _inside(self, keys):
+        """Whether each point key lies in the sliding window (all of them
+        without one)."""
+        keys = np.asarray(keys, np.int64)
+        win = self.orc.window()
+        if win is None or len(keys) == 0:
+            return np.ones(len(keys), bool)
+        blk = np.floor_divide(unpack_keys(keys), 8)
+        return np.all((blk >= win[0]) & (blk <= win[1]), axis=1)
+
     def frame(self, xyz, origin, frame_id: int):
         orc = self.orc
         orc.integrate_frame(xyz, origin, frame_id)
@@ -218,7 +239,8 @@ class IncrementalOracle:
             moved = True
             self.q_last = Q
         n_new = n_i = n_ii = n_iii = 0
-        for k in keys:
+        inside = self._inside(keys)
+        for j, k in enumerate(keys):
             k = int(k)
             S, W = vox[k]
             st = self.state.get(k)
@@ -231,7 +253,8 @@ class IncrementalOracle:
             if st["W"] > 0 and W > 0 and abs(S * st["W"] - st["S"] * W) > 512 * W * st["W"]:
                 st["pending"] = True
                 n_i += 1
-            if moved and self._label(st, st["W"]) in (LABEL_BLOCKED, LABEL_NO_CANDIDATE):
+            if moved and inside[j] and self._label(st, st["W"]) in (LABEL_BLOCKED,
+                                                                    LABEL_NO_CANDIDATE):
                 st["pending"] = True
                 n_iii += 1
             st["S"], st["W"] = S, W

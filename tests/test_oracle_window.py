@@ -233,3 +233,48 @@ def test_labels_persist_outside_the_window(windowed, oracle_mod):
     kept = [k for k in keys[outside].tolist() if k in last and last[k][0] != 0]
     never = [k for k in keys.tolist() if k not in last]
     assert len(kept) > 100 and len(never) > 0
+
+
+def _incr_run(w, frames, oracle_mod, blocks, c2f=True, origins=None):
+    from oracle.incremental import IncrementalOracle
+    o = oracle_mod.Oracle(voxel=w.voxel, trunc=w.trunc, r_c=w.r_c)
+    if blocks is not None:
+        o.set_window([blocks] * 3)
+    o.set_tool(0, w.tool, w.rot)
+    inc = IncrementalOracle(o, 0, len(w.rot), budget=900)
+    if c2f:
+        inc.enable_c2f(w.rot)
+    per = []
+    for j, f in enumerate(frames):
+        before = inc.labels() if j else None
+        st = inc.frame(f.xyz, f.origin if origins is None else origins[j], f.frame_id)
+        per.append((before, dict(st), o.window(), inc.labels()))
+    return per
+
+
+def test_incremental_with_a_wide_window_is_without(synth_mod, oracle_mod):
+    w = synth_mod.tiny()
+    frames = w.frames(8)
+    origins = [np.asarray(f.origin, np.float32) for f in frames]
+    origins[5] = (np.asarray(frames[4].origin, np.float64) + [0.15, 0, 0]).astype(np.float32)
+    a = _incr_run(w, frames, oracle_mod, None, origins=origins)
+    b = _incr_run(w, frames, oracle_mod, 4096, origins=origins)
+    for (_, sa, _, la), (_, sb, _, lb) in zip(a, b):
+        assert sa == sb
+        for x, y in zip(la, lb):
+            assert np.array_equal(x, y)
+
+
+def test_incremental_trigger_iii_only_inside_the_window(walk, oracle_mod):
+    w, frames = walk
+    per = _incr_run(w, frames[:20], oracle_mod, BLOCKS)
+    cut = 0
+    for j in range(1, len(per)):
+        before, st, (lo, hi, _), _ = per[j]
+        keys, lab = before[0], before[1]
+        inacc = (lab == 2) | (lab == 3)
+        ins = _inside(_blocks_of(keys, oracle_mod), lo, hi)
+        # the walk moves 26 cm per frame: trigger (iii) fires every frame
+        assert st["trig_iii"] == int(np.sum(inacc & ins)), j
+        cut += int(np.sum(inacc & ~ins))
+    assert cut > 0          # the window left some inaccessible points out
