@@ -855,6 +855,67 @@ def run_incremental(args):
     print(json.dumps(out), flush=True)
 
 
+def run_window(args):
+    """Sliding-window workload: the tree sequence (600 frames, integrate and
+    score every frame) with a window of --window-m metres per axis.  Reports
+    the frame time (mean, p50, p99, and on the frames that shifted the
+    window), the blocks the map holds at most beside the unbounded map's at
+    the end, the shifts, and the points scored per frame."""
+    import torch
+    import synth
+    from paper_2608_06412_amd import Context, default_config, window_blocks
+
+    n = max(args.steps, 1) if args.steps != 400 else 600
+    w = synth.tree(n_frames=max(600, n))
+    frames = w.frames(n)
+    torch.cuda.set_device(0)
+    blocks = window_blocks([args.window_m] * 3, w.voxel)
+    cfg = default_config(w.voxel, w.trunc, r_c=w.r_c, max_blocks=1 << 17, max_points=1 << 22,
+                         max_orientations=len(w.rot), max_tools=1)
+    ctx = Context(cfg)
+    ctx.set_window(blocks)
+    ctx.set_tool_kernels(0, w.tool, w.rot)
+    resident = [torch.from_numpy(f.xyz).cuda() for f in frames]
+    torch.cuda.synchronize()
+    ms, shifted, held, scored = [], [], [], []
+    last = 0
+    for i, f in enumerate(frames):
+        t0 = time.perf_counter()
+        ctx.integrate_frame(resident[i], f.origin, f.frame_id)
+        ctx.score_points(0)
+        st = ctx.score_stats(0)            # synchronises
+        ms.append((time.perf_counter() - t0) * 1e3)
+        sh = ctx.window_state()[2]
+        shifted.append(sh != last)
+        last = sh
+        held.append(ctx.frame_stats()["n_blocks"])
+        scored.append(st["n_confident"])
+    ms = np.array(ms)
+    shifted = np.array(shifted)
+    out = {
+        "metric": "sliding-window tree workload: frame time (integrate + in-window scoring)",
+        "value": float(ms.mean()),
+        "unit": "ms per frame",
+        "n_gpus": 1, "steps": len(frames), "warmup": 0,
+        "ms_per_step": float(ms.mean()),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int64", "data": "synthetic",
+        "config": {"workload": "window: tree workload (20,000 returns per frame, K = 256, saw "
+                               "box), %.1f m window (%d blocks per axis)"
+                               % (args.window_m, int(blocks[0])),
+                   "frames": len(frames)},
+        "ms_per_frame": {"p50": float(np.percentile(ms, 50)), "p99": float(np.percentile(ms, 99)),
+                         "shift_frames_mean": float(ms[shifted].mean()) if shifted.any() else None,
+                         "other_frames_mean": float(ms[~shifted].mean())},
+        "shifts": int(last),
+        "blocks_held_max": int(max(held)),
+        "points_end": int(ctx.num_points()),
+        "confident_scored_per_frame_mean": float(np.mean(scored)),
+        "device_bytes": int(ctx.device_bytes()),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -870,7 +931,10 @@ def main():
     ap.add_argument("--score-variant", default=None,
                     help="scoring configuration (index or name) when not tuning; default: "
                          "the library's default configuration")
-    ap.add_argument("--workload", default="tree", choices=["tree", "batch", "serve", "smooth", "incremental"],
+    ap.add_argument("--window-m", type=float, default=10.0,
+                    help="window size per axis (metres) of the window workload")
+    ap.add_argument("--workload", default="tree",
+                    choices=["tree", "batch", "serve", "smooth", "incremental", "window"],
                     help="tree: the default single-tool workload; batch: 8 tools x 512 "
                          "orientations scored in one launch, frames of 5k-40k returns")
     ap.add_argument("--incr-budget", type=int, default=1 << 20,
@@ -930,6 +994,8 @@ def main():
         return run_smooth(args)
     if args.workload == "incremental":
         return run_incremental(args)
+    if args.workload == "window":
+        return run_window(args)
     if args.workload == "batch":
         run_batch(args)
         return
