@@ -230,9 +230,13 @@ int af_integrate_frame_host(af_ctx *ctx, const float *xyz, int64_t n,
  * neighbours are the points inside the window.  Memory then stays bounded
  * by the window (max_blocks of about blocks[0] blocks[1] blocks[2] suffice).
  * Call once, before the first frame; 2 <= blocks[a] <= 4096.  Allocates
- * 4 bytes per block and per point of capacity.  Not combinable with frame
- * graphs, multi-tool scoring, the incremental mode, the smoothed score or
- * variant tuning (those calls return AF_EINVAL).  AF_EINVAL after a frame. */
+ * 4 bytes per block and per point of capacity.  With the incremental mode
+ * (Section 3.5), trigger (iii) re-queues only the inaccessible points inside
+ * the window and the coarse-to-fine search takes its resolved neighbours
+ * inside it; points outside have no voxel (W = 0: never selected, c = 0).
+ * Not combinable with frame graphs, multi-tool scoring, the smoothed score
+ * or variant tuning (those calls return AF_EINVAL).  AF_EINVAL after a
+ * frame. */
 int af_set_window(af_ctx *ctx, const int32_t blocks[3]);
 /* The window's current block box [lo, hi] (HOST arrays, either may be NULL)
  * and the number of shifts so far (the first placement is not a shift).

@@ -802,8 +802,7 @@ int af_set_window(af_ctx *c, const int32_t blocks[3]) {
   if (!blocks) return fail(c, AF_EINVAL, "no window size");
   if (c->last_frame >= 0 || c->n_points > 0 || c->win_on)
     return fail(c, AF_EINVAL, "the window is set once, before the first frame");
-  if (c->incr_on || c->gexec)
-    return fail(c, AF_EINVAL, "no window with the incremental mode or a frame graph");
+  if (c->gexec) return fail(c, AF_EINVAL, "no window with a frame graph");
   for (int a = 0; a < 3; ++a)
     if (blocks[a] < 2 || blocks[a] > 4096)
       return fail(c, AF_EINVAL, "window of %d blocks on axis %d (2..4096)", blocks[a], a);
@@ -1527,7 +1526,6 @@ int af_incremental_enable(af_ctx *c, int32_t tool_id, int32_t budget) {
   const ToolDev &t = c->tools[tool_id];
   if (!t.entries) return fail(c, AF_ENOTOOL, "tool %d has no kernels", tool_id);
   if (budget < 1) return fail(c, AF_EINVAL, "budget must be positive");
-  if (c->win_on) return fail(c, AF_EINVAL, "the incremental mode is not available with a window");
   if (c->p.n_c > 255) return fail(c, AF_EINVAL, "n_c above 255");
   if (c->last_frame >= 0 || c->n_points > 0)
     return fail(c, AF_EINVAL, "the incremental mode starts before the first frame");
@@ -1698,6 +1696,19 @@ int af_incremental_budget(af_ctx *c, int64_t lookup_target, int32_t b_min, int32
   return hip_check(c, "incremental budget");
 }
 
+// The sliding window's block box for the incremental kernels (unbounded
+// without a window).
+static void incr_window(af_ctx *c) {
+  IncrDev &I = c->incr;
+  if (c->win_on && c->win_set) {
+    I.wlo = make_int3(c->win_lo[0], c->win_lo[1], c->win_lo[2]);
+    I.whi = make_int3(c->win_hi[0], c->win_hi[1], c->win_hi[2]);
+  } else {
+    I.wlo = make_int3(-(1 << 30), -(1 << 30), -(1 << 30));
+    I.whi = make_int3(1 << 30, 1 << 30, 1 << 30);
+  }
+}
+
 int af_incremental_frame(af_ctx *c, const float *xyz, int64_t n, const float origin[3],
                          int64_t frame_id, void *stream) {
   if (!c) return AF_EINVAL;
@@ -1724,6 +1735,7 @@ int af_incremental_frame(af_ctx *c, const float *xyz, int64_t n, const float ori
     }
   }
   IncrDev &I = c->incr;
+  incr_window(c);
   if ((rc = c2f_plane(c)) != AF_OK) return rc;
   launch_incr_frame_front(c->pts, c->map, I, c->incr_changed, c->counters, c->n_points,
                           c->incr_seen, (int32_t)frame_id, moved, c->p.conf_min_w, s);
@@ -1754,6 +1766,7 @@ int af_incremental_drain(af_ctx *c, int32_t max_evals, void *stream) {
     if (rc != AF_OK) return rc;
   }
   hipStream_t s = (hipStream_t)stream;
+  incr_window(c);
   PointsDev ps = c->pts;
   ps.sel = I.sel;
   ps.n_sel = I.n_sel;

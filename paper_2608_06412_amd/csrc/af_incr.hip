@@ -42,6 +42,12 @@ __device__ inline unsigned long long mix64(unsigned long long z) {
   return z ^ (z >> 31);
 }
 
+// Whether voxel (x, y, z) lies in the sliding window's block box.
+__device__ inline bool in_window(const IncrDev &I, int32_t x, int32_t y, int32_t z) {
+  return (x >> 3) >= I.wlo.x && (x >> 3) <= I.whi.x && (y >> 3) >= I.wlo.y &&
+         (y >> 3) <= I.whi.y && (z >> 3) >= I.wlo.z && (z >> 3) <= I.whi.z;
+}
+
 __device__ inline int64_t voxel_key(const MapDev &m, int32_t addr) {
   int32_t b[3];
   unpack_key(m.bkey[addr >> 9], b[0], b[1], b[2]);
@@ -135,7 +141,11 @@ k_incr_triggers(PointsDev pts, MapDev m, IncrDev I, int64_t n, int64_t seen, int
         if (d > 512 * W * Wp) c_i = 1;   // |S/W - S'/W'| > 2v (2v = 512 units)
       }
       const uint8_t lb = I.label[i];
-      if (moved && (lb == AF_BLOCKED || lb == AF_NO_CANDIDATE)) c_iii = 1;
+      if (moved && (lb == AF_BLOCKED || lb == AF_NO_CANDIDATE)) {
+        int32_t x, y, z;   // (iii) takes the points inside the sliding window
+        unpack_key(pts.key[i], x, y, z);
+        c_iii = in_window(I, x, y, z);
+      }
       if (c_i || c_iii) I.pending[i] = 1u;
     }
     I.S_prev[i] = (int32_t)S;
@@ -474,7 +484,7 @@ __global__ void __launch_bounds__(kT) k_c2f_mark(PointsDev pts, GridDev g, IncrD
     unpack_key(pts.key[i], x, y, z);
     const int bx = (x >> 3) - g.g0[0], by = (y >> 3) - g.g0[1], bz = (z >> 3) - g.g0[2];
     if ((unsigned)bx < (unsigned)g.gd[0] && (unsigned)by < (unsigned)g.gd[1] &&
-        (unsigned)bz < (unsigned)g.gd[2]) {
+        (unsigned)bz < (unsigned)g.gd[2] && in_window(I, x, y, z)) {
       const int64_t b = ((int64_t)bz * g.gd[1] + by) * g.gd[0] + bx;
       const int lin = (x & 7) | ((y & 7) << 3) | ((z & 7) << 6);
       atomicOr(&I.resolved[b * 16 + (lin >> 5)], 1u << (lin & 31));

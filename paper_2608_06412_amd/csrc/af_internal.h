@@ -322,6 +322,9 @@ struct IncrDev {
   uint32_t *c2f_off;
   uint32_t *resolved;
   int32_t *n_resolved;
+  // the sliding window's block box (unbounded without one): trigger (iii)
+  // and the resolved neighbours only take points inside it
+  int3 wlo, whi;
 };
 void launch_incr_init(const IncrDev &I, int32_t n_c, hipStream_t s);
 void launch_incr_frame_front(PointsDev pts, MapDev m, const IncrDev &I, const int32_t *changed,

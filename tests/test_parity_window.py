@@ -91,8 +91,7 @@ def test_window_argument_rules(synth_mod):
     with pytest.raises(AFError):
         ctx.set_window([8, 8, 8])            # once
     ctx.set_tool_kernels(0, w.tool, w.rot)
-    for call in (lambda: ctx.incremental_enable(0, 100),
-                 lambda: ctx.graph_prepare([-1, -1, -1], [1, 1, 1], 1000, [0]),
+    for call in (lambda: ctx.graph_prepare([-1, -1, -1], [1, 1, 1], 1000, [0]),
                  lambda: ctx.score_tools([0]),
                  lambda: ctx.tune_score(0)):
         with pytest.raises(AFError):
@@ -111,3 +110,48 @@ def test_window_argument_rules(synth_mod):
         plain.set_window([8, 8, 8])          # after the first frame
     with pytest.raises(AFError):
         plain.window_state()                 # no window
+
+
+STAT_KEYS = ("new_points", "trig_i", "trig_ii", "trig_iii", "sampled", "evaluated", "backlog")
+ORC_KEYS = ("new", "trig_i", "trig_ii", "trig_iii", "sampled", "evaluated", "backlog")
+
+
+@pytest.mark.parametrize("c2f", [False, True])
+def test_incremental_with_window(synth_mod, oracle_mod, c2f):
+    """The incremental mode on the walk with the window: after every frame
+    every point's label, stored score and direction, a, and every trigger
+    and backlog count equal the oracle's state machine (trigger (iii) and the
+    coarse-to-fine neighbours restricted to the window)."""
+    import torch
+    from oracle.incremental import IncrementalOracle
+    from paper_2608_06412_amd import Context, default_config
+    w = synth_mod.window_walk()
+    frames = w.frames(30)
+    cfg = default_config(w.voxel, w.trunc, r_c=w.r_c, max_blocks=BLOCKS ** 3,
+                         max_points=1 << 17, max_orientations=64, max_tools=1)
+    ctx = Context(cfg)
+    ctx.set_window([BLOCKS] * 3)
+    ctx.set_tool_kernels(0, w.tool, w.rot)
+    ctx.incremental_enable(0, 900)
+    orc = oracle_mod.Oracle(voxel=w.voxel, trunc=w.trunc, r_c=w.r_c)
+    orc.set_window([BLOCKS] * 3)
+    orc.set_tool(0, w.tool, w.rot)
+    inc = IncrementalOracle(orc, 0, len(w.rot), budget=900)
+    if c2f:
+        ctx.incremental_c2f()
+        inc.enable_c2f(w.rot)
+    for j, f in enumerate(frames):
+        print("incremental window frame", j, "c2f", c2f, flush=True)
+        ctx.incremental_frame(torch.from_numpy(f.xyz).cuda(), f.origin, f.frame_id)
+        ost = inc.frame(f.xyz, f.origin, f.frame_id)
+        gst = ctx.incremental_stats()
+        for gk, ok in zip(STAT_KEYS, ORC_KEYS):
+            assert gst[gk] == ost[ok], (j, gk, gst, ost)
+        g = ctx.read_incremental()
+        keys, lab, best, bdir, a = inc.labels()
+        assert np.array_equal(g["key"], keys), j
+        assert np.array_equal(g["label"], lab), (j, np.flatnonzero(g["label"] != lab)[:10])
+        assert np.array_equal(g["best"].astype(np.int32), best), j
+        assert np.array_equal(g["best_dir"].astype(np.int32), bdir), j
+        assert np.array_equal(g["a"], a), j
+    assert orc.window()[2] >= 3 and ost["backlog"] > 0
