@@ -417,11 +417,12 @@ def run_serve(args):
     stream; a fifth stream is refused).  Frames 0..W-1 warm up; W..W+K-1 are
     run back to back, one frame of every stream per server step, against the
     plain sequential path (per frame: integrate, score, wait) on four other
-    contexts and against a server that scores each stream in its own launch;
-    W+K..W+K+L-1 (default 150 per stream, 600 frames) arrive at 10 Hz from
-    each stream's phase, and the latency of each frame runs from its arrival
-    to its labels on the host.  The server is in batched mode: every step
-    scores all streams that took a frame in one launch."""
+    contexts, and against servers that batch every step's scoring into one
+    launch and that never do; W+K..W+K+L-1 (default 150 per stream, 600
+    frames) arrive at 10 Hz from each stream's phase, and the latency of each
+    frame runs from its arrival to its labels on the host.  The main server
+    keeps the library's batching rule (one scoring launch per step of 5 or
+    more streams)."""
     import torch
     import synth
     from paper_2608_06412_amd import AFError, Context, Server, default_config
@@ -430,24 +431,31 @@ def run_serve(args):
     K = args.steps if args.steps != 400 else 40
     L = args.latency_frames if args.latency_frames != 600 else 150
     n = W + K + L
-    specs = synth.serving(n_streams=4, n_frames=n)
+    NS = args.serve_streams
+    specs = synth.serving(n_streams=NS, n_frames=n)
     t = time.perf_counter()
     frames = [sp.workload.frames(n) for sp in specs]
-    log("generated 4 x %d frames in %.1f s" % (n, time.perf_counter() - t))
+    log("generated %d x %d frames in %.1f s" % (NS, n, time.perf_counter() - t))
     torch.cuda.set_device(0)
     GiB = 1 << 30
 
+    # four streams: 2e8 voxels and 4 M points each in 6 GiB; more streams
+    # share the same 24 GiB with proportionally smaller maps
+    per = 4.0 / NS
+
     def cfg(budget):
         w = specs[0].workload
-        c = default_config(w.voxel, w.trunc, r_c=w.r_c, max_blocks=390625, max_points=1 << 22,
-                           max_orientations=256, max_tools=1)
+        c = default_config(w.voxel, w.trunc, r_c=w.r_c, max_blocks=int(390625 * per),
+                           max_points=int((1 << 22) * per), max_orientations=256, max_tools=1)
         c.hbm_budget = int(budget)
         return c
+    stream_budget = int(6 * GiB * per)
+
     def make_server(batch):
-        srv = Server(24 * GiB, max_streams=5, batch=batch)
-        sids = [srv.admit(cfg(6 * GiB)) for _ in specs]
+        srv = Server(24 * GiB, max_streams=NS + 1, batch=batch)
+        sids = [srv.admit(cfg(stream_budget)) for _ in specs]
         try:
-            srv.admit(cfg(6 * GiB))
+            srv.admit(cfg(stream_budget))
             refused = False
         except AFError:
             refused = True
@@ -459,10 +467,12 @@ def run_serve(args):
                         max(len(f.xyz) for f in frames[s]), [0])
         return srv, sids, refused
 
-    # batched server (one scoring launch per step across the streams), the
-    # unbatched server (one scoring launch per stream, overlapped), and the
-    # plain sequential path
-    srv, sids, refused = make_server(True)
+    # the server with the library's batching rule (one scoring launch for
+    # steps of 5 or more streams, else one per stream), the server that
+    # batches every step, the one that never does, and the plain sequential
+    # path
+    srv, sids, refused = make_server(None)
+    srv_b, sids_b, _ = make_server(True)
     srv_o, sids_o, _ = make_server(False)
     seq = []
     for s, sp in enumerate(specs):
@@ -494,6 +504,7 @@ def run_serve(args):
                 tests += c.score_stats(0)["canonical_tests"]
         return tests
     serve_frames(0, W)
+    serve_frames(0, W, srv_b, sids_b)
     serve_frames(0, W, srv_o, sids_o)
     seq_frames(0, W)
     log("warm-up done; points per stream %s" % [srv.context(i).num_points() for i in sids])
@@ -501,6 +512,9 @@ def run_serve(args):
     t0 = time.perf_counter()
     tests_srv = serve_frames(W, W + K)
     wall_srv = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    tests_b = serve_frames(W, W + K, srv_b, sids_b)
+    wall_b = time.perf_counter() - t0
     t0 = time.perf_counter()
     tests_o = serve_frames(W, W + K, srv_o, sids_o)
     wall_o = time.perf_counter() - t0
@@ -515,15 +529,17 @@ def run_serve(args):
                    np.array_equal(server.context(sid).read_labels(0)["first_free"],
                                   seq[s].read_labels(0)["first_free"])
                    for s, sid in enumerate(ids))
-    same = same_as_seq(srv, sids) and same_as_seq(srv_o, sids_o)
+    same = same_as_seq(srv, sids) and same_as_seq(srv_b, sids_b) and same_as_seq(srv_o, sids_o)
+    srv_b.close()
     srv_o.close()
-    returns = sum(len(frames[s][k].xyz) for s in range(4) for k in range(W, W + K))
-    log("throughput: batched server %.1f ms per 4 frames, unbatched %.1f, sequential %.1f" %
-        (wall_srv / K * 1e3, wall_o / K * 1e3, wall_seq / K * 1e3))
+    returns = sum(len(frames[s][k].xyz) for s in range(NS) for k in range(W, W + K))
+    log("throughput: server %.1f ms per step, always batched %.1f, never batched %.1f, "
+        "sequential %.1f" % (wall_srv / K * 1e3, wall_b / K * 1e3, wall_o / K * 1e3,
+                             wall_seq / K * 1e3))
 
     # paced: every stream at 10 Hz from its phase
     def paced(run_one_step):
-        arr = sorted((specs[s].phase + 0.1 * j, s, W + K + j) for s in range(4) for j in range(L))
+        arr = sorted((specs[s].phase + 0.1 * j, s, W + K + j) for s in range(NS) for j in range(L))
         lat = []
         i = 0
         t0 = time.perf_counter() + 0.05
@@ -565,7 +581,7 @@ def run_serve(args):
     lat_srv = paced(srv_step)
     waiting = []
     pinned = {(s, k): torch.from_numpy(frames[s][k].xyz).pin_memory()
-              for s in range(4) for k in range(W + K, n)}
+              for s in range(NS) for k in range(W + K, n)}
 
     def seq_step(item, peek=False):
         if peek:
@@ -587,33 +603,39 @@ def run_serve(args):
                                   seq[s].read_labels(0)["label"]) for s, sid in enumerate(sids))
     pct = lambda v, q: float(np.percentile(v, q))
     out = {
-        "metric": "frame latency p50/p99 and throughput, 4 concurrent streams at 10 Hz",
+        "metric": "frame latency p50/p99 and throughput, %d concurrent streams at 10 Hz" % NS,
         "value": pct(lat_srv, 99),
         "unit": "ms (p99 frame latency, arrival to labels on the host)",
         "n_gpus": 1, "steps": K, "warmup": W,
         "ms_per_step": wall_srv / K * 1e3,
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "int64", "data": "synthetic",
-        "config": {"workload": "serve: 4 streams (2 procedural trees, 2 box clusters), own tool "
-                               "each at 256 orientations, frames of 5,000-40,000 returns at 10 Hz, "
-                               "TSDF capacity 2e8 voxels per stream",
+        "config": {"workload": "serve: %d streams (trees and box clusters alternating), own "
+                               "tool each at 256 orientations, frames of 5,000-40,000 returns at "
+                               "10 Hz, TSDF capacity %.2g voxels per stream"
+                               % (NS, 390625 * per * 512),
                    "frames_per_stream": {"warmup": W, "throughput": K, "paced": L},
                    "map_points_end": [int(srv.context(i).num_points()) for i in sids]},
-        "admission": {"budget_bytes": 24 * GiB, "per_stream_bytes": 6 * GiB, "admitted": len(sids),
-                      "fifth_refused": refused,
+        "admission": {"budget_bytes": 24 * GiB, "per_stream_bytes": stream_budget,
+                      "admitted": len(sids),
+                      "one_more_refused": refused,
                       "device_bytes": [int(srv.context(i).device_bytes()) for i in sids]},
         "latency_ms": {"p50": pct(lat_srv, 50), "p99": pct(lat_srv, 99), "max": float(lat_srv.max()),
                        "frames": int(len(lat_srv))},
         "sequential_latency_ms": {"p50": pct(lat_seq, 50), "p99": pct(lat_seq, 99),
                                   "max": float(lat_seq.max())},
-        "throughput": {"frames_per_s": 4 * K / wall_srv, "returns_per_s": returns / wall_srv,
+        "throughput": {"frames_per_s": NS * K / wall_srv, "returns_per_s": returns / wall_srv,
                        "tests_per_s": tests_srv / wall_srv,
-                       "mode": "batched: one scoring launch per server step across the streams",
-                       "unbatched_frames_per_s": 4 * K / wall_o,
-                       "sequential_frames_per_s": 4 * K / wall_seq,
+                       "mode": "one scoring launch per step when %d or more streams took a "
+                               "frame (here: %s), else one per stream" % (
+                                   5, "every step" if NS >= 5 else "never"),
+                       "always_batched_frames_per_s": NS * K / wall_b,
+                       "never_batched_frames_per_s": NS * K / wall_o,
+                       "sequential_frames_per_s": NS * K / wall_seq,
                        "sequential_tests_per_s": tests_seq / wall_seq,
-                       "speedup": wall_seq / wall_srv, "speedup_over_unbatched": wall_o / wall_srv,
-                       "same_tests": bool(tests_srv == tests_seq == tests_o),
+                       "speedup": wall_seq / wall_srv,
+                       "always_batched_over_never": wall_o / wall_b,
+                       "same_tests": bool(tests_srv == tests_seq == tests_o == tests_b),
                        "labels_identical": bool(same), "labels_identical_after_paced": bool(same_end)},
     }
     print(json.dumps(out), flush=True)
@@ -931,6 +953,8 @@ def main():
     ap.add_argument("--score-variant", default=None,
                     help="scoring configuration (index or name) when not tuning; default: "
                          "the library's default configuration")
+    ap.add_argument("--serve-streams", type=int, default=4,
+                    help="streams of the serve workload (the 24 GiB budget is shared)")
     ap.add_argument("--window-m", type=float, default=10.0,
                     help="window size per axis (metres) of the window workload")
     ap.add_argument("--workload", default="tree",

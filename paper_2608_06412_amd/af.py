@@ -674,7 +674,10 @@ class Server:
     budget, one context, HIP stream, recorded frame graph and frame queue per
     stream, and a step that runs the oldest queued frame of every stream."""
 
-    def __init__(self, hbm_budget: int, max_streams: int = 4, batch: bool = True):
+    def __init__(self, hbm_budget: int, max_streams: int = 4, batch=None):
+        """batch: None keeps the library's rule (one scoring launch for steps
+        of 5 or more streams), True batches every step of 2 or more, False
+        never, an int sets the minimum number of streams (af_server_batch)."""
         self._lib = lib()
         h = ctypes.c_void_p()
         rc = self._lib.af_server_create(int(hbm_budget), int(max_streams), ctypes.byref(h))
@@ -683,7 +686,9 @@ class Server:
         self.h = h
         self.max_streams = int(max_streams)
         self._ctx = {}
-        self._check(self._lib.af_server_batch(self.h, 1 if batch else 0))
+        if batch is not None:
+            m = (2 if batch else 0) if isinstance(batch, bool) else int(batch)
+            self._check(self._lib.af_server_batch(self.h, m))
 
     def close(self):
         if getattr(self, "h", None):

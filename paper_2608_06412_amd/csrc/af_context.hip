@@ -1214,6 +1214,19 @@ int ctx_score_jobs(af_ctx *c, const int32_t *tool_ids, int32_t n_tools, ScoreJob
   }
   return AF_OK;
 }
+
+// A recorded (unscored) frame scored on its own stream: the launch a scored
+// graph ends with (a server step that batches fewer than two streams).
+int ctx_score_stream(af_ctx *c, const int32_t *tool_ids, int32_t n_tools, void *stream) {
+  if (!c) return AF_EINVAL;
+  ToolSet set;
+  ToolDev host[kMultiTools];
+  const int rc = make_toolset(c, tool_ids, n_tools, set, host);
+  if (rc != AF_OK) return rc;
+  launch_score_multi(c->p, c->pts, c->tools_dev, host, set, c->grid, c->cfg.max_points, c->work,
+                     (hipStream_t)stream, true);
+  return hip_check(c, "score on the stream");
+}
 }  // namespace af
 
 extern "C" {

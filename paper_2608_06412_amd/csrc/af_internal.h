@@ -474,6 +474,8 @@ int ctx_graph_prepare_unscored(af_ctx *c, const float lo[3], const float hi[3],
                                int64_t max_returns, const int32_t *tool_ids, int32_t n_tools,
                                void *stream);
 int ctx_score_jobs(af_ctx *c, const int32_t *tool_ids, int32_t n_tools, ScoreJob *out);
+// Score such a frame on its own stream instead (what the scored graph does).
+int ctx_score_stream(af_ctx *c, const int32_t *tool_ids, int32_t n_tools, void *stream);
 int score_variants();
 int score_variant_default();
 // whether the configuration (after its fallbacks for this tool) honours PointsDev::sel

@@ -1558,25 +1558,28 @@ k_score_near_jobs(const ScoreJob *jobs, int32_t n_jobs, unsigned *work) {
     const int K = jobs[j].t.K, o = jobs[j].base;
     for (int k = threadIdx.x; k <= K; k += NT) s_begin[o + k] = bg[k];
   }
+  // s_start[j]: job j's first work item (prefix of the point counts, which
+  // the device holds: the frames were just integrated)
+  __shared__ int64_t s_start[kMaxJobs + 1];
+  if (threadIdx.x == 0) {
+    int64_t run = 0;
+    for (int j = 0; j < n_jobs; ++j) {
+      s_start[j] = run;
+      run += *jobs[j].pts.n_points;
+    }
+    s_start[n_jobs] = run;
+  }
   __syncthreads();
   const int lane = lane_id();
   const int slot = (blockIdx.x * NW + (threadIdx.x >> 6)) % kStatSlots;
-  // lane j < n_jobs: job j's first work item (exclusive prefix of the counts)
-  const int64_t cnt = lane < n_jobs ? (int64_t)*jobs[lane].pts.n_points : 0;
-  int64_t incl = cnt;
-  for (int off = 1; off < 64; off <<= 1) {
-    const int64_t v = __shfl_up(incl, off);
-    if (lane >= off) incl += v;
-  }
-  const int64_t start = incl - cnt;
-  const int64_t total = __shfl(incl, 63);
+  const int64_t total = s_start[n_jobs];
   NearAcc a = near_acc_zero();
   int64_t w = 0, batch_end = 0;
   int cur = -1;
   const ScoreJob *jp = jobs;   // the current job (read in place: wave-uniform loads)
   SwGrid q;
   int32_t mw = 0;
-  int64_t j0 = 0;
+  int64_t j0 = 0, j1 = 0;      // the current job's work items [j0, j1)
   for (;;) {
     if (w >= batch_end) {
       unsigned got = 0;
@@ -1585,17 +1588,18 @@ k_score_near_jobs(const ScoreJob *jobs, int32_t n_jobs, unsigned *work) {
       batch_end = w + FB;
     }
     if (w >= total) break;
-    // the job whose range holds w: the last job starting at or before it
-    // (jobs with no point share a start with the next one and are skipped)
-    const uint64_t le = __ballot(lane < n_jobs && cnt > 0 && start <= w);
-    const int ji = 63 - __clzll((long long)le);
-    if (ji != cur) {
+    if (w < j0 || w >= j1) {
+      // the job whose range holds w (a scan of the LDS starts; jobs without
+      // points have an empty range and are passed over)
+      int ji = 0;
+      while (s_start[ji + 1] <= w) ++ji;
       if (cur >= 0) near_flush<0>(jp->t.counters->s[slot], a, lane);
       cur = ji;
-      jp = jobs + __builtin_amdgcn_readfirstlane(ji);
+      jp = jobs + ji;
       q = sw_grid(jp->g);
       mw = (jp->t.K + 63) / 64;
-      j0 = __shfl(start, ji);
+      j0 = s_start[ji];
+      j1 = s_start[ji + 1];
     }
     near_point<UN, CO, B1, PF, RE>(jp->p, jp->pts, jp->t, jp->g, q, s_begin + jp->base, mw,
                                    w - j0, lane, a);

@@ -8,10 +8,12 @@
 // of pinned host slots that hold frames as they arrive.  One step takes the
 // oldest queued frame of every stream and launches each stream's recorded
 // integration (with its normals and candidate masks) on its own HIP stream;
-// in batched mode (the default) one scoring launch then labels the points of
-// every stream that took a frame, each against its own map and tools, after
-// which every stream reads its counts back.  Without batching each stream's
-// graph also holds its own scoring launch and the GPU overlaps the streams.
+// when enough streams took a frame (more than the runtime's hardware queues,
+// by default), one scoring launch then labels the points of all of them,
+// each against its own map and tools, after which every stream reads its
+// counts back; fewer streams are scored each on its own stream, where the
+// GPU overlaps them.  Without batching each stream's graph also holds its
+// own scoring launch.
 //
 // Admission reserves the stream's declared device budget (af_config.
 // hbm_budget) against the server's budget.  A context never allocates beyond
@@ -64,7 +66,7 @@ struct af_server {
   int64_t reserved = 0;
   int32_t rr = 0;   // stream visited first by the next step (round robin)
   std::vector<Served> streams;
-  bool batch = true;             // one scoring launch per step across streams
+  int32_t batch_min = 5;         // streams in a step that get one scoring launch (0: never)
   hipStream_t bs = nullptr;      // the batched scoring launch's stream
   hipEvent_t scored = nullptr;   // recorded after it
   af::ScoreJob *jobs_host = nullptr;   // pinned, kMaxJobs
@@ -123,12 +125,13 @@ int af_server_create(int64_t hbm_budget, int32_t max_streams, af_server **out) {
   return AF_OK;
 }
 
-int af_server_batch(af_server *s, int32_t on) {
+int af_server_batch(af_server *s, int32_t min_streams) {
   if (!s) return AF_EINVAL;
+  if (min_streams < 0) return sfail(s, AF_EINVAL, "min_streams %d < 0", min_streams);
   for (const Served &t : s->streams)
     if (t.used && t.max_returns)
       return sfail(s, AF_EINVAL, "choose the mode before any stream is prepared");
-  s->batch = on != 0;
+  s->batch_min = min_streams == 1 ? 2 : min_streams;
   return AF_OK;
 }
 
@@ -214,16 +217,17 @@ int af_server_prepare(af_server *s, int32_t id, const float lo[3], const float h
   hipStreamSynchronize(t->hs);
   free_slots(*t);
   t->max_returns = 0;
-  if (s->batch) {
+  const bool batched = s->batch_min > 0;
+  if (batched) {
     const int rc = batch_resources(s);
     if (rc != AF_OK) return rc;
   }
-  int rc = s->batch ? af::ctx_graph_prepare_unscored(t->ctx, lo, hi, max_returns, tool_ids,
+  int rc = batched ? af::ctx_graph_prepare_unscored(t->ctx, lo, hi, max_returns, tool_ids,
                                                      n_tools, t->hs)
                     : af_graph_prepare(t->ctx, lo, hi, max_returns, tool_ids, n_tools, t->hs);
   if (rc != AF_OK) return sfail(s, rc, "stream %d: %s", id, af_last_error(t->ctx));
   t->tools.assign(tool_ids, tool_ids + n_tools);
-  t->batched = s->batch;
+  t->batched = batched;
   for (int i = 0; i < kQueueSlots; ++i) {
     float *p = nullptr;
     if (hipHostMalloc((void **)&p, sizeof(float) * 3 * max_returns) != hipSuccess) {
@@ -292,17 +296,30 @@ int af_server_step(af_server *s, int32_t *stream_ids, int64_t *frame_ids, int32_
     run.push_back({id, rc});
   }
   s->rr = (s->rr + 1) % ns;
-  // batched mode: one scoring launch over every stream that integrated a frame
+  // batched mode: one scoring launch over the streams that integrated a
+  // frame when there are at least batch_min of them; otherwise (and past the
+  // launch's job capacity) a stream is scored on its own stream, with no
+  // cross-stream wait
+  std::vector<int32_t> batch;
+  for (Launched &l : run)
+    if (l.rc == AF_OK && s->streams[l.id].batched) batch.push_back(l.id);
   int32_t n_jobs = 0;
-  for (const Launched &l : run) {
-    Served &t = s->streams[l.id];
-    if (l.rc != AF_OK || !t.batched) continue;
-    if (n_jobs + (int32_t)t.tools.size() > af::kMaxJobs) break;
-    af::ctx_score_jobs(t.ctx, t.tools.data(), (int32_t)t.tools.size(), s->jobs_host + n_jobs);
-    n_jobs += (int32_t)t.tools.size();
-    hipEventRecord(t.done, t.hs);
-    hipStreamWaitEvent(s->bs, t.done, 0);
-  }
+  std::vector<char> in_launch(ns, 0);
+  if (s->batch_min > 0 && (int32_t)batch.size() >= s->batch_min)
+    for (int32_t id : batch) {
+      Served &t = s->streams[id];
+      if (n_jobs + (int32_t)t.tools.size() > af::kMaxJobs) continue;
+      af::ctx_score_jobs(t.ctx, t.tools.data(), (int32_t)t.tools.size(), s->jobs_host + n_jobs);
+      n_jobs += (int32_t)t.tools.size();
+      in_launch[id] = 1;
+      hipEventRecord(t.done, t.hs);
+      hipStreamWaitEvent(s->bs, t.done, 0);
+    }
+  for (Launched &l : run)
+    if (l.rc == AF_OK && s->streams[l.id].batched && !in_launch[l.id]) {
+      Served &t = s->streams[l.id];
+      l.rc = af::ctx_score_stream(t.ctx, t.tools.data(), (int32_t)t.tools.size(), t.hs);
+    }
   int batch_rc = AF_OK;
   if (n_jobs > 0) {
     int32_t words = 0;
@@ -317,14 +334,13 @@ int af_server_step(af_server *s, int32_t *stream_ids, int64_t *frame_ids, int32_
       batch_rc = AF_EDEVICE;
     hipEventRecord(s->scored, s->bs);
     for (const Launched &l : run)
-      if (l.rc == AF_OK && s->streams[l.id].batched)
-        hipStreamWaitEvent(s->streams[l.id].hs, s->scored, 0);
+      if (in_launch[l.id]) hipStreamWaitEvent(s->streams[l.id].hs, s->scored, 0);
   }
   int worst = AF_OK;
   for (Launched &l : run) {
     Served &t = s->streams[l.id];
     int rc = l.rc;
-    if (rc == AF_OK && t.batched && batch_rc != AF_OK) {
+    if (rc == AF_OK && in_launch[l.id] && batch_rc != AF_OK) {
       hipStreamSynchronize(t.hs);
       rc = batch_rc;
     }

@@ -41,3 +41,11 @@ def test_bad_server_arguments_and_unknown_streams():
             call()
     assert srv.pending(0) == -1
     srv.close()
+
+
+def test_batch_threshold_arguments():
+    from paper_2608_06412_amd import AFError, Server
+    with pytest.raises(AFError):
+        Server(1 << 30, max_streams=2, batch=-1)
+    for b in (None, True, False, 1, 2, 8):
+        Server(1 << 30, max_streams=2, batch=b).close()
