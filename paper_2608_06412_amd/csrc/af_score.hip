@@ -1034,7 +1034,7 @@ __device__ inline bool corridor_clear4_sw(const ToolDev &t, const SwGrid &q, con
 // Entries [b, e) of orientation k after its first E: body entries finely,
 // then the corridor -- skipped when its 4^3 cells are clear (CO), finely
 // otherwise.  Canonical lookups stay the table-order count.
-template <int UN, int CO, int B1, int RE = 0, int LZ = 0>
+template <int UN, int CO, int B1, int RE = 0, int LZ = 0, int UC = 0, int UB = 0>
 __device__ inline bool scan_rest_sw(const Params &p, const ToolDev &t, const SwGrid &q,
                                     const SwFrame &f, int k, uint32_t b, uint32_t e, int body,
                                     uint32_t &lookups, uint32_t &cchecks, uint32_t &cclear,
@@ -1044,8 +1044,18 @@ __device__ inline bool scan_rest_sw(const Params &p, const ToolDev &t, const SwG
   if (!CO) return scan_fine_sw<UN, B1, RE, 0, LZ>(p, t, q, f, b, e, body, lookups, sbody, first);
   const uint32_t fb = t.far_begin[k];
   const uint32_t mid = fb > b ? fb : b;
-  if (!scan_fine_sw<UN, B1, RE, B1 ? 1 : 0, LZ>(p, t, q, f, b, mid, body, lookups, sbody, first))
-    return false;
+  if constexpr (UB > 0) {
+    // the body's first chunk alone (most blocked candidates end there), the
+    // rest UB chunks per step
+    const uint32_t c1 = b + 64u < mid ? b + 64u : mid;
+    if (!scan_fine_sw<UN, B1, RE, B1 ? 1 : 0, LZ>(p, t, q, f, b, c1, body, lookups, sbody, first))
+      return false;
+    if (!scan_fine_sw<UB, B1, RE, B1 ? 1 : 0, LZ>(p, t, q, f, c1, mid, body, lookups, sbody))
+      return false;
+  } else {
+    if (!scan_fine_sw<UN, B1, RE, B1 ? 1 : 0, LZ>(p, t, q, f, b, mid, body, lookups, sbody, first))
+      return false;
+  }
   if (mid >= e) return true;
   if (t.c4flag[k] != 0) {
     ++cchecks;
@@ -1055,7 +1065,11 @@ __device__ inline bool scan_rest_sw(const Params &p, const ToolDev &t, const SwG
       return true;
     }
   }
-  return scan_fine_sw<UN, B1, RE, B1 ? 2 : 0, LZ>(p, t, q, f, mid, e, body, lookups, sfar);
+  // the corridor: UC chunks per step (0: UN); a candidate that gets this far
+  // is mostly free and reads its whole corridor, so two chunks in flight
+  // hide one gather latency at little waste
+  return scan_fine_sw<UC ? UC : UN, B1, RE, B1 ? 2 : 0, LZ>(p, t, q, f, mid, e, body, lookups,
+                                                          sfar);
 }
 
 // Candidate-parallel scoring with grid-relative lookups (the configurations
@@ -1292,7 +1306,7 @@ __device__ inline void near_flush(ScoreCounterBlock &sc, NearAcc &a, int lane) {
 
 // One point of the "near" scoring (see k_score_near): label and first free
 // orientation of point i for tool t, whose begin offsets are s_begin.
-template <int UN, int CO, int B1, int PF, int RE, int LZ = 0>
+template <int UN, int CO, int B1, int PF, int RE, int LZ = 0, int UC = 0, int UB = 0>
 __device__ inline void near_point(const Params &p, const PointsDev &pts, const ToolDev &t,
                                   const GridDev &g, const SwGrid &q, const uint32_t *s_begin,
                                   int32_t mw, int64_t i, int lane, NearAcc &acc) {
@@ -1398,7 +1412,7 @@ __device__ inline void near_point(const Params &p, const PointsDev &pts, const T
             body = __popcll(bm1);
             start = b + nin;
           }
-          if (scan_rest_sw<UN, CO, B1, RE, LZ>(p, t, q, f, kj, start, e, body, acc.lookups, acc.cchecks,
+          if (scan_rest_sw<UN, CO, B1, RE, LZ, UC, UB>(p, t, q, f, kj, start, e, body, acc.lookups, acc.cchecks,
                                            acc.cclear, acc.sbody, acc.sfar, c4, g.occ4,
                                            PF == 1 && UN == 1 ? &cur : nullptr)) {
             ff = (int16_t)kj;
@@ -1433,7 +1447,8 @@ __device__ inline void near_point(const Params &p, const PointsDev &pts, const T
 // only the undecided ones continue lane-parallel.  Requires K <= kNearK.
 // Same labels, first free orientations and canonical counts as the plain
 // scan.
-template <int NT, int UN, int FB, int CO, int B1, int DIAG, int PF = 1, int RE = 0>
+template <int NT, int UN, int FB, int CO, int B1, int DIAG, int PF = 1, int RE = 0, int UC = 0,
+          int UB = 0>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8)))
 k_score_near(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t mw,
              unsigned *work) {
@@ -1473,7 +1488,7 @@ k_score_near(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t m
         !pts.sel ? i
         : FB > 0 ? (int64_t)__builtin_amdgcn_readlane(selv, (int)(FB - (batch_end - i)))
                  : (int64_t)__builtin_amdgcn_readfirstlane(pts.sel[i]);
-    near_point<UN, CO, B1, PF, RE, 1>(p, pts, t, g, q, s_begin, mw, pi, lane, a);
+    near_point<UN, CO, B1, PF, RE, 1, UC, UB>(p, pts, t, g, q, s_begin, mw, pi, lane, a);
     if (a.lookups > (1u << 30)) near_flush<DIAG>(sc, a, lane);
     if (FB > 0) {
       if (++i >= batch_end) {
@@ -1632,6 +1647,9 @@ const ScoreVariant kVariants[] = {
     {k_score_near<256, 2, 8, 2, 1, 0, 1, 1>, 256, "near wg256 unroll2 dyn8 coarse4 bit rel", kNearK, 1},
     {k_score_near<512, 1, 8, 2, 1, 0, 1, 1>, 512, "near wg512 unroll1 dyn8 coarse4 bit rel", kNearK, 1},
     {k_score_near<256, 1, 8, 2, 1, 0, 2, 1>, 256, "near wg256 unroll1 dyn8 coarse4 bit prefix2 rel", kNearK, 1},
+    {k_score_near<256, 1, 8, 2, 1, 0, 1, 1, 2>, 256, "near wg256 unroll1 dyn8 coarse4 bit rel corr2", kNearK, 1},
+    {k_score_near<256, 1, 8, 2, 1, 1, 1, 1, 2>, 256, "near wg256 unroll1 dyn8 coarse4 bit rel corr2 diag", kNearK, 1},
+    {k_score_near<256, 1, 8, 2, 1, 0, 1, 1, 0, 2>, 256, "near wg256 unroll1 dyn8 coarse4 bit rel body2", kNearK, 1},
 };
 constexpr int kNumVariants = (int)(sizeof(kVariants) / sizeof(kVariants[0]));
 int g_resident[kNumVariants];   // workgroups per CU, from the occupancy query
@@ -1730,7 +1748,7 @@ int score_variants() { return kNumVariants; }
 
 // The configuration a new context uses (the fastest on the tree workload).
 int score_variant_default() {
-  static const char kDefault[] = "near wg256 unroll1 dyn8 coarse4 bit rel";
+  static const char kDefault[] = "near wg256 unroll1 dyn8 coarse4 bit rel corr2";
   for (int v = 0; v < kNumVariants; ++v)
     if (strcmp(kVariants[v].name, kDefault) == 0) return v;
   return 0;
