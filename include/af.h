@@ -148,7 +148,7 @@ const char *af_last_error(const af_ctx *ctx);
  * tool's local axes in world coordinates: column 0 is the approach direction
  * (the tool extends along it from the tip at the surface point), columns 1-2
  * span the cross-section.  The table of orientation k lists, as voxel offsets
- * from the point's voxel: the three arm samples at {0.6, 1.25, 2.25} tau along
+ * from the point's voxel: the three arm samples at 0.6, 1.25 and 2.25 times tau along
  * the approach direction (NEAR), the voxel centres inside the tool body
  * (BODY) and inside its corridor (FAR), minus the self-exclusion ball r_s;
  * BODY and FAR are each sorted by (|o|^2, z, y, x).  Built on the device; the
@@ -160,8 +160,8 @@ int af_set_tool_kernels(af_ctx *ctx, int32_t tool_id, const af_tool *tool,
                         int32_t K, const double *rot, void *stream);
 
 /* Section 3.4 "Tool kernel": set tool `tool_id` from a caller-built table,
- * for tools that are not primitives (for instance a point cloud sampled from
- * the tool's 3D model, rotated and voxelised by the caller).  All arrays are
+ * for tools that are not primitives (for instance points drawn on a mesh of
+ * the tool, rotated and voxelised by the caller).  All arrays are
  * HOST memory owned by the caller; the library copies them.
  *   K             orientations, 1..max_orientations
  *   dir[K][3]     unit approach direction of each orientation (the normal
@@ -199,7 +199,7 @@ int af_set_tool_table(af_ctx *ctx, int32_t tool_id, const af_kernel_table *table
  * position of the frame).  For every valid return the voxels of the index
  * cube of half-width ceil(tau/v) around it, except those inside the
  * cos > 0.95 cone behind it, receive d = |p - q| - |x - q| (voxel centre x,
- * clamped to [0, tau]) as integer sums S, W; the band (tau, 2.25 tau] back
+ * clamped to [0, tau]) as integer sums S, W; the voxels between tau and 2.25 tau back
  * along the ray is marked ray-cleared; the return's voxel joins the surface
  * point set.  The frame is folded at the end (weights capped with
  * proportional rescaling of S).  Returns that are non-finite, out of range
@@ -219,7 +219,7 @@ int af_integrate_frame_host(af_ctx *ctx, const float *xyz, int64_t n,
 
 /* Section 3.3 "Sliding-Window TSDF": bound the map to a box of blocks[a]
  * voxel blocks (8 voxels each) per axis that follows the sensor.  At the
- * first frame, and at every frame whose sensor voxel lies more than 30 % of
+ * first frame, and at every frame whose sensor voxel lies farther than 30 % of
  * the window's size (8 blocks[a] voxels) from the window's centre along some
  * axis, the window is re-centred on the sensor's voxel c: it then covers
  * blocks floor(c/8) - floor(blocks/2) .. + blocks - 1 on each axis, and
@@ -459,7 +459,7 @@ int af_smooth_eval_static(af_ctx *ctx, const float *p, const float *q, int64_t n
  * stored score only decreases (its orientation is kept with it); the
  * accessibility confidence a (1 at first) becomes 0.75 a when an evaluation
  * finds no free orientation while a free one is stored, and a + 0.15 (1 - a)
- * when it finds one.  Labels: AF_ACCESSIBLE iff the stored score is below
+ * when it finds one.  Labels: AF_ACCESSIBLE iff the stored score is under
  * n_c and c a > 0.7 with c = W / (W + 5); AF_TENTATIVE when a score below
  * n_c is stored but c a <= 0.7; otherwise the last evaluation's AF_BLOCKED or
  * AF_NO_CANDIDATE; AF_UNSCORED before the first evaluation.
@@ -493,8 +493,8 @@ int af_incremental_frame(af_ctx *ctx, const float *xyz, int64_t n, const float o
 int af_incremental_budget(af_ctx *ctx, int64_t lookup_target, int32_t b_min, int32_t b_max);
 /* Coarse-to-fine direction search (Section 3.6, "Accessibility scoring"):
  * each evaluation of the incremental mode tests only the orientations of a
- * coarse pass and of a fine window around the stored direction of the
- * nearest resolved neighbour.  Coarse pass: the orientations whose approach
+ * coarse pass and of a fine window around the direction stored by the
+ * closest resolved point.  Coarse pass: the orientations whose approach
  * direction a greedy walk in index order takes (a direction at least
  * coarse_deg from every direction taken before: dot <= cos + 1e-12), plus
  * the orientations sharing a taken direction.  Fine window of orientation

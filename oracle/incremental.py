@@ -24,7 +24,7 @@ module implements that state machine in plain Python on top of the C oracle
    multiplied by 0.75 when an evaluation finds blocked a point whose stored
    score says accessible, and recovers by 0.15 (1 - a) when an evaluation
    finds it accessible;
-5. label every point: accessible iff its stored score is below n_c and
+5. label every point: accessible iff the stored score is under n_c and
    c * a > 0.7 ("confident-accessible").
 
 Readings where the paper leaves a choice (each matched by the GPU side):
@@ -58,8 +58,8 @@ trigger (i) needs W > 0 before and after, and their label follows from
 c = 0.
 
 Coarse-to-fine direction search (Section 3.6, optional): an evaluation tests
-only the orientations of a coarse pass and of a fine window around the best
-direction of the nearest resolved neighbour.  Readings, for any orientation
+only the orientations of a coarse pass, plus those close to the direction
+stored by the closest already-resolved neighbouring point.  Readings, for any orientation
 set: the coarse pass holds the orientations whose approach direction was
 taken by a greedy walk in index order that takes a direction when it is at
 least 20 degrees from every direction taken before (dot product at most

@@ -253,7 +253,7 @@ void orc_set_roi(orc_t *o, const int64_t lo[3], const int64_t hi[3]) {
 
 /* Section 3.3 "Sliding-Window TSDF": a box of L[i] blocks (8 voxels) per
  * axis.  At each frame, before integration: on the first frame, and whenever
- * the sensor's voxel is more than 30 % of the window's size (8 L voxels)
+ * the sensor's voxel is farther than 30 % of the window's size (8 L voxels)
  * from the window's centre along some axis, the window is re-centred on the
  * sensor's voxel c and covers blocks [floor(c/8) - floor(L/2), + L - 1];
  * every voxel outside it is discarded (it reads unknown again).  The frame
@@ -439,8 +439,8 @@ static int64_t round_div(int64_t a, int64_t b) {
   return a < 0 ? -q : q;
 }
 
-/* Section 3.4 "Arm path checking": voxels in the band (tau, 2.25 tau] along
- * the ray from the return back towards the sensor are marked ray-cleared.
+/* Section 3.4 "Arm path checking": voxels between tau and 2.25 tau back from
+ * the return, on its ray towards the sensor, are marked ray-cleared.
  * Samples every v/2 (at the nearest fixed-point position), never past the
  * sensor. */
 static void mark_band(orc_t *o, const int64_t P[3], const int64_t Q[3]) {
@@ -677,7 +677,7 @@ static int cmp_ent(const void *a, const void *b) {
  * offsets whose centre lies in the rotated tool solid (0 <= x <= length),
  * FAR those in its corridor (length < x <= length + corridor), both minus the
  * self-exclusion ball of radius r_s around the tip; NEAR holds the three arm
- * samples at {0.6, 1.25, 2.25} tau along the approach axis.  Membership is
+ * samples at 0.6, 1.25 and 2.25 times tau along the approach axis.  Membership is
  * decided in fp64 in voxel units with a 1e-9 tolerance on the inclusive
  * bounds. */
 static int build_orientation(const orc_tool *t, double v, double tau,
@@ -1024,7 +1024,7 @@ static int point_normal(const orc_t *o, int64_t p, const int32_t *nbo, int nnb,
 }
 
 /* Candidate filters of Section 3.4 for approach direction d (column 0 of the
- * orientation): within the half-cone of the outward normal (n.d >= cos70 |n|)
+ * orientation): inside the 70-degree cone around the outward normal (n.d >= cos70 |n|)
  * and seen from that side by at least one stored viewpoint V
  * ((V - s).d > 0.25 |V - s|).  Both tests are squared to avoid square roots. */
 static int candidate(const orc_t *o, int64_t p, const int64_t s[3],
