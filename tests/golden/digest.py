@@ -45,3 +45,14 @@ def masks_digest(label, mask):
     label = np.asarray(label)
     m = np.where((np.asarray(label) == 0)[:, None], np.uint64(0), np.asarray(mask, np.uint64))
     return _sha(m)
+
+
+def inside_window(keys, lo, hi):
+    """Whether each point key's voxel lies in the block box [lo, hi] (key
+    unpacking only: 21 bits per axis, biased by 2^20)."""
+    k = np.asarray(keys, np.int64)
+    m = (1 << 21) - 1
+    v = np.stack([(k & m) - (1 << 20), ((k >> 21) & m) - (1 << 20),
+                  ((k >> 42) & m) - (1 << 20)], axis=1)
+    b = np.floor_divide(v, 8)
+    return np.all((b >= np.asarray(lo)) & (b <= np.asarray(hi)), axis=1)
