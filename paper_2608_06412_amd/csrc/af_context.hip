@@ -223,7 +223,9 @@ int ensure_grid(af_ctx *c, hipStream_t s, bool &rebuilt, bool force = false) {
   int64_t nb = 1;
   for (int a = 0; a < 3; ++a) {
     int32_t ext = c->bbox_hi[a] - c->bbox_lo[a] + 1;
-    int32_t margin = std::max<int32_t>(need, ext / 4);
+    // a growing map gets a quarter of its extent as slack; a window's box
+    // never grows, so its grid holds the tools' margin only
+    int32_t margin = c->win_on ? need : std::max<int32_t>(need, ext / 4);
     ng.g0[a] = c->bbox_lo[a] - margin;
     ng.gd[a] = ext + 2 * margin;
     nb *= ng.gd[a];

@@ -824,10 +824,14 @@ k_window_link(MapDev m, PointsDev pts, int64_t n_points, int3 lo, int3 hi) {
   atomicOr(&m.surf[(int64_t)bid * 16 + (vi >> 5)], 1u << (vi & 31));
 }
 
-// Points inside [lo, hi] listed (one atomic per wave).
-__global__ void __launch_bounds__(kThreads)
+// Points inside [lo, hi] listed: the waves' counts are combined in LDS, so
+// a workgroup of 1024 points takes one atomic on the list's counter (one per
+// wave serialised some 30,000 atomics on that address per call).
+constexpr int kListThreads = 1024;
+__global__ void __launch_bounds__(kListThreads)
 k_window_list(PointsDev pts, int64_t n_points, int3 lo, int3 hi, int32_t *sel, int32_t *n_sel) {
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  __shared__ int part[kListThreads / 64 + 1];
+  const int64_t i = (int64_t)blockIdx.x * kListThreads + threadIdx.x;
   bool take = false;
   if (i < n_points) {
     int32_t v[3];
@@ -835,11 +839,22 @@ k_window_list(PointsDev pts, int64_t n_points, int3 lo, int3 hi, int32_t *sel, i
     take = in_box(v[0] >> 3, v[1] >> 3, v[2] >> 3, lo, hi);
   }
   const unsigned long long bal = __ballot(take);
-  const int lane = lane_id();
-  int base = 0;
-  if (lane == 0 && bal) base = atomicAdd(n_sel, __popcll(bal));
-  base = __shfl(base, 0);
-  if (take) sel[base + __popcll(bal & ((1ull << lane) - 1ull))] = (int32_t)i;
+  const int lane = lane_id(), wave = (int)(threadIdx.x >> 6);
+  if (lane == 0) part[wave] = __popcll(bal);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int k = 0; k < kListThreads / 64; ++k) {
+      const int c = part[k];
+      part[k] = tot;
+      tot += c;
+    }
+    part[kListThreads / 64] = tot ? atomicAdd(n_sel, tot) : 0;
+  }
+  __syncthreads();
+  if (take)
+    sel[part[kListThreads / 64] + part[wave] + __popcll(bal & ((1ull << lane) - 1ull))] =
+        (int32_t)i;
 }
 
 __global__ void k_label_fill(uint8_t *label, int16_t *ff, int64_t from, int64_t to) {
@@ -906,8 +921,8 @@ void launch_window_list(PointsDev pts, int64_t n_points, int3 lo, int3 hi, int32
                         int32_t *n_sel, hipStream_t s) {
   launch_zero_words(n_sel, sizeof(int32_t), s);
   if (n_points > 0)
-    hipLaunchKernelGGL(k_window_list, dim3(grid_for(n_points)), dim3(kThreads), 0, s, pts,
-                       n_points, lo, hi, sel, n_sel);
+    hipLaunchKernelGGL(k_window_list, dim3((unsigned)((n_points + kListThreads - 1) / kListThreads)),
+                       dim3(kListThreads), 0, s, pts, n_points, lo, hi, sel, n_sel);
 }
 
 void launch_label_fill(uint8_t *label, int16_t *first_free, int64_t from, int64_t to,

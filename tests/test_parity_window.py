@@ -31,19 +31,24 @@ def _cmp_points(ctx, orc):
         assert np.array_equal(np.asarray(g[k], np.int64), np.asarray(o[k], np.int64)), k
 
 
-def test_window_walk(synth_mod, oracle_mod):
+# 20 blocks (3.2 m) per axis: a shift every four frames or so; 10 x 10 x 20
+# blocks: a shift every other frame, with the block capacity at 2,000, so
+# evicted ids are reused all the time
+@pytest.mark.parametrize("blocks", [(BLOCKS,) * 3, (10, 10, 20)])
+def test_window_walk(synth_mod, oracle_mod, blocks):
     import torch
     from paper_2608_06412_amd import Context, default_config
     assert torch.cuda.is_available()
     w = synth_mod.window_walk()
     frames = w.frames()
-    cfg = default_config(w.voxel, w.trunc, r_c=w.r_c, max_blocks=BLOCKS ** 3,
+    cap = blocks[0] * blocks[1] * blocks[2]
+    cfg = default_config(w.voxel, w.trunc, r_c=w.r_c, max_blocks=cap,
                          max_points=1 << 17, max_orientations=64, max_tools=1)
     ctx = Context(cfg)
-    ctx.set_window([BLOCKS] * 3)
+    ctx.set_window(list(blocks))
     assert ctx.window_state() is None
     orc = oracle_mod.Oracle(voxel=w.voxel, trunc=w.trunc, r_c=w.r_c)
-    orc.set_window([BLOCKS] * 3)
+    orc.set_window(list(blocks))
     ctx.set_tool_kernels(0, w.tool, w.rot)
     orc.set_tool(0, w.tool, w.rot)
     K = len(w.rot)
@@ -70,8 +75,8 @@ def test_window_walk(synth_mod, oracle_mod):
             assert {k: gst[k] for k in SCORE_KEYS} == {k: ost[k] for k in SCORE_KEYS}
             _cmp_tsdf(ctx, orc)
             _cmp_points(ctx, orc)
-    assert orc.window()[2] >= 5
-    assert max_held <= BLOCKS ** 3
+    assert orc.window()[2] >= (5 if blocks[0] == BLOCKS else 15)
+    assert max_held <= cap
     lab = ctx.read_labels(0)
     assert np.any(lab["label"] == 255) and np.any(lab["label"] == 1)
 

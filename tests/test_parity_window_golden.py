@@ -1,0 +1,112 @@
+"""GPU parity of the sliding window at the tree workload's full size (600
+frames of 20,000 returns, 1 cm voxels, saw box with a 1 m corridor, K = 256,
+a window of 125 blocks = 10 m per axis), against the oracle's results stored
+in tests/golden/window_full.json (written by tests/golden/make_window_golden.py,
+which calls only the oracle).
+
+Every frame is integrated; the points are scored after frames 100, 300 and
+600 only, so points outside the window at a checkpoint keep the labels of an
+earlier one (or read 255).  At each checkpoint: the window box and its shift
+count, the whole TSDF, every point record, every point's label and first free
+orientation, the normals and candidate masks of the confident points inside
+the window, the label counts and the canonical statistics, compared through
+SHA-256 digests of the full arrays, plus 400 seeded points element by
+element."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLDEN = os.path.join(HERE, "golden", "window_full.json")
+sys.path.insert(0, os.path.join(HERE, "golden"))
+
+
+@pytest.fixture(scope="module")
+def golden():
+    if not os.path.exists(GOLDEN):
+        pytest.skip("tests/golden/window_full.json not written yet")
+    g = json.load(open(GOLDEN))
+    if len(g["checkpoints"]) < 3:
+        pytest.skip("tests/golden/window_full.json is incomplete")
+    return g
+
+
+@pytest.fixture(scope="module")
+def gpu_states(synth_mod, golden):
+    import torch
+    from digest import (inside_window, labels_digest, masks_digest, normals_digest,
+                        points_digest, tsdf_digest)
+    from paper_2608_06412_amd import Context, default_config
+    assert torch.cuda.is_available()
+    w = synth_mod.tree()
+    frames = w.frames(600)
+    cfg = default_config(w.voxel, w.trunc, r_c=w.r_c, max_blocks=1 << 17, max_points=1 << 22,
+                         max_orientations=len(w.rot), max_tools=1)
+    ctx = Context(cfg)
+    ctx.set_window([golden["blocks"]] * 3)
+    ctx.set_tool_kernels(0, w.tool, w.rot)
+    want = {cp["frames"]: cp for cp in golden["checkpoints"]}
+    out = {}
+    for i, f in enumerate(frames):
+        ctx.integrate_frame(torch.from_numpy(f.xyz).cuda(), f.origin, f.frame_id)
+        if i + 1 not in want:
+            continue
+        ctx.score_points(0)
+        print("checkpoint %d: %d points" % (i + 1, ctx.num_points()), flush=True)
+        key, S, W, clr = ctx.read_tsdf()
+        pts = ctx.read_points()
+        lab = ctx.read_labels(0)
+        dbg = ctx.read_point_debug(0)
+        st = ctx.score_stats(0)
+        lo, hi, shifts = ctx.window_state()
+        ins = inside_window(pts["key"], lo, hi)
+        out[i + 1] = {
+            "window": [[int(x) for x in lo], [int(x) for x in hi], int(shifts)],
+            "n_voxels": int(len(key)), "n_points": int(len(pts["key"])),
+            "n_inside": int(ins.sum()),
+            "tsdf_sha": tsdf_digest(key, S, W, clr),
+            "points_sha": points_digest(pts),
+            "labels_sha": labels_digest(lab["key"], lab["label"], lab["first_free"]),
+            "normals_sha": normals_digest(lab["label"][ins], dbg["has_normal"][ins],
+                                          dbg["normal"][ins]),
+            "masks_sha": masks_digest(lab["label"][ins], dbg["mask"][ins]),
+            "label_counts": {str(k): int((lab["label"] == k).sum()) for k in (0, 1, 2, 3, 255)},
+            "score_stats": st,
+            "lab": lab,
+        }
+    return want, out
+
+
+CHECKS = ["window", "n_voxels", "n_points", "n_inside", "tsdf_sha", "points_sha",
+          "label_counts", "labels_sha", "normals_sha", "masks_sha"]
+
+
+@pytest.mark.parametrize("frames", [100, 300, 600])
+def test_sample_points(gpu_states, frames):
+    want, got = gpu_states
+    lab = got[frames]["lab"]
+    for s in want[frames]["sample"]:
+        j = s["i"]
+        assert int(lab["key"][j]) == s["key"], s
+        assert (int(lab["label"][j]), int(lab["first_free"][j])) == (s["label"],
+                                                                   s["first_free"]), s
+
+
+@pytest.mark.parametrize("frames", [100, 300, 600])
+@pytest.mark.parametrize("what", CHECKS)
+def test_whole_map(gpu_states, frames, what):
+    want, got = gpu_states
+    assert got[frames][what] == want[frames][what]
+
+
+@pytest.mark.parametrize("frames", [100, 300, 600])
+def test_statistics(gpu_states, frames):
+    want, got = gpu_states
+    for k in ("n_confident", "n_accessible", "n_blocked", "n_no_candidate",
+              "candidate_tests", "canonical_tests", "canonical_lookups"):
+        assert got[frames]["score_stats"][k] == want[frames]["score_stats"][k], k
