@@ -1188,7 +1188,6 @@ static int graph_prepare(af_ctx *c, const float lo[3], const float hi[3], int64_
 
 int af_graph_prepare(af_ctx *c, const float lo[3], const float hi[3], int64_t max_returns,
                      const int32_t *tool_ids, int32_t n_tools, void *stream) {
-  if (c && c->win_on) return fail(c, AF_EINVAL, "frame graphs are not available with a window");
   return graph_prepare(c, lo, hi, max_returns, tool_ids, n_tools, stream, true);
 }
 
@@ -1239,6 +1238,7 @@ static int graph_prepare(af_ctx *c, const float lo[3], const float hi[3], int64_
   if (!lo || !hi || max_returns < 1) return fail(c, AF_EINVAL, "bad graph arguments");
   if (c->incr_on)
     return fail(c, AF_EINVAL, "a context in incremental mode runs its frames eagerly");
+  if (c->win_on) return fail(c, AF_EINVAL, "frame graphs are not available with a window");
   int rc;
   if (c->graph_dirty && (rc = graph_settle(c)) != AF_OK) return rc;
   ToolSet set;

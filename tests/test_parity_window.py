@@ -115,6 +115,14 @@ def test_window_argument_rules(synth_mod):
         plain.set_window([8, 8, 8])          # after the first frame
     with pytest.raises(AFError):
         plain.window_state()                 # no window
+    # a block capacity below what the window holds is reported, not overrun
+    from paper_2608_06412_amd.af import AF_EOVERFLOW
+    small = Context(default_config(w.voxel, w.trunc, r_c=w.r_c, max_blocks=50,
+                                   max_points=1 << 14, max_orientations=64, max_tools=1))
+    small.set_window([20, 20, 20])
+    with pytest.raises(AFError) as e:
+        small.integrate_frame(torch.from_numpy(f.xyz).cuda(), f.origin, 0)
+    assert e.value.code == AF_EOVERFLOW
 
 
 STAT_KEYS = ("new_points", "trig_i", "trig_ii", "trig_iii", "sampled", "evaluated", "backlog")
