@@ -119,7 +119,7 @@ def test_window_argument_rules(synth_mod):
     from paper_2608_06412_amd.af import AF_EOVERFLOW
     small = Context(default_config(w.voxel, w.trunc, r_c=w.r_c, max_blocks=50,
                                    max_points=1 << 14, max_orientations=64, max_tools=1))
-    small.set_window([20, 20, 20])
+    small.set_window([40, 40, 40])           # 6.4 m: the whole tiny scene
     with pytest.raises(AFError) as e:
         small.integrate_frame(torch.from_numpy(f.xyz).cuda(), f.origin, 0)
     assert e.value.code == AF_EOVERFLOW
