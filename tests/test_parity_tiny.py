@@ -135,6 +135,9 @@ def test_all_score_variants(tiny_run):
     o = orc.score_stats()
     names = ctx.score_variants()
     assert len(names) >= 8
+    K = len(w.rot)
+    r = orc.read_results(K)
+    conf = r["label"] != 0
     for v in range(len(names)):
         ctx.set_score_variant(v)
         ctx.score_points(0)
@@ -143,6 +146,9 @@ def test_all_score_variants(tiny_run):
         assert np.array_equal(lab["first_free"].astype(np.int32), ff), names[v]
         g = ctx.score_stats(0)
         assert {k: g[k] for k in SCORE_KEYS} == {k: o[k] for k in SCORE_KEYS}, names[v]
+        # and the candidate masks the scoring read
+        dbg = ctx.read_point_debug(0)
+        assert np.array_equal(dbg["mask"][conf], r["mask"][conf]), names[v]
     best, ms = ctx.tune_score(0, reps=2)
     assert 0 <= best < len(names) and ctx.score_variant() == best
     assert all(m > 0 for m in ms)
