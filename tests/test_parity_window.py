@@ -55,9 +55,12 @@ def test_window_walk(synth_mod, oracle_mod, blocks):
     max_held = 0
     for f in frames:
         print("window frame", f.frame_id, flush=True)
-        x = torch.from_numpy(f.xyz).cuda()
+        # frames 10 and 11 arrive empty (the sensor still moves: a shift with
+        # no return to integrate)
+        xyz = f.xyz[:0] if f.frame_id in (10, 11) else f.xyz
+        x = torch.from_numpy(np.ascontiguousarray(xyz)).cuda()
         ctx.integrate_frame(x, f.origin, f.frame_id)
-        orc.integrate_frame(f.xyz, f.origin, f.frame_id)
+        orc.integrate_frame(xyz, f.origin, f.frame_id)
         glo, ghi, gsh = ctx.window_state()
         olo, ohi, osh = orc.window()
         assert glo.tolist() == olo.tolist() and ghi.tolist() == ohi.tolist() and gsh == osh
