@@ -898,13 +898,20 @@ def run_window(args):
     ctx.set_window(blocks)
     ctx.set_tool_kernels(0, w.tool, w.rot)
     resident = [torch.from_numpy(f.xyz).cuda() for f in frames]
+    if args.window_graph:
+        # recorded frames: a shift runs eagerly and records again
+        ctx.graph_prepare([-1.0] * 3, [1.0] * 3, max(len(f.xyz) for f in frames), [0])
     torch.cuda.synchronize()
     ms, shifted, held, scored = [], [], [], []
     last = 0
     for i, f in enumerate(frames):
         t0 = time.perf_counter()
-        ctx.integrate_frame(resident[i], f.origin, f.frame_id)
-        ctx.score_points(0)
+        if args.window_graph:
+            ctx.graph_frame(resident[i], f.origin, f.frame_id)
+            ctx.graph_sync()
+        else:
+            ctx.integrate_frame(resident[i], f.origin, f.frame_id)
+            ctx.score_points(0)
         st = ctx.score_stats(0)            # synchronises
         ms.append((time.perf_counter() - t0) * 1e3)
         sh = ctx.window_state()[2]
@@ -915,7 +922,8 @@ def run_window(args):
     ms = np.array(ms)
     shifted = np.array(shifted)
     out = {
-        "metric": "sliding-window tree workload: frame time (integrate + in-window scoring)",
+        "metric": "sliding-window tree workload: frame time (integrate + in-window scoring)"
+                  + (", recorded frames" if args.window_graph else ""),
         "value": float(ms.mean()),
         "unit": "ms per frame",
         "n_gpus": 1, "steps": len(frames), "warmup": 0,
@@ -925,7 +933,7 @@ def run_window(args):
         "config": {"workload": "window: tree workload (20,000 returns per frame, K = 256, saw "
                                "box), %.1f m window (%d blocks per axis)"
                                % (args.window_m, int(blocks[0])),
-                   "frames": len(frames)},
+                   "frames": len(frames), "recorded_frames": bool(args.window_graph)},
         "ms_per_frame": {"p50": float(np.percentile(ms, 50)), "p99": float(np.percentile(ms, 99)),
                          "shift_frames_mean": float(ms[shifted].mean()) if shifted.any() else None,
                          "other_frames_mean": float(ms[~shifted].mean())},
@@ -957,6 +965,8 @@ def main():
                     help="streams of the serve workload (the 24 GiB budget is shared)")
     ap.add_argument("--window-m", type=float, default=10.0,
                     help="window size per axis (metres) of the window workload")
+    ap.add_argument("--window-graph", action="store_true",
+                    help="window workload through recorded frames (af_graph_frame)")
     ap.add_argument("--workload", default="tree",
                     choices=["tree", "batch", "serve", "smooth", "incremental", "window"],
                     help="tree: the default single-tool workload; batch: 8 tools x 512 "

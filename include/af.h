@@ -234,9 +234,11 @@ int af_integrate_frame_host(af_ctx *ctx, const float *xyz, int64_t n,
  * (Section 3.5), trigger (iii) re-queues only the inaccessible points inside
  * the window and the coarse-to-fine search takes its resolved neighbours
  * inside it; points outside have no voxel (W = 0: never selected, c = 0).
- * Not combinable with frame graphs, multi-tool scoring, the smoothed score
- * or variant tuning (those calls return AF_EINVAL).  AF_EINVAL after a
- * frame. */
+ * Frame graphs record the windowed frame (see af_graph_prepare);
+ * af_score_tools lists the points and computes their normals once, then
+ * scores the tools one after the other (their masks share one buffer).  Not
+ * combinable with the smoothed score or variant tuning (those calls return
+ * AF_EINVAL).  AF_EINVAL after a frame or once a frame graph is prepared. */
 int af_set_window(af_ctx *ctx, const int32_t blocks[3]);
 /* The window's current block box [lo, hi] (HOST arrays, either may be NULL)
  * and the number of shifts so far (the first placement is not a shift).
@@ -382,7 +384,19 @@ int af_tune_score(af_ctx *ctx, int32_t tool_id, int32_t reps, void *stream, int3
  * capacity, grid growth, af_set_tool_kernels) makes af_graph_frame return
  * AF_EINVAL until af_graph_prepare is called again.  Labels, first free
  * orientations, statistics and the map after each replay equal those of
- * af_integrate_frame followed by af_score_tools. */
+ * af_integrate_frame followed by af_score_tools.
+ *
+ * With a sliding window (af_set_window, called first) the grid is the
+ * window's and lo/hi are checked but not used; the recorded frame lists the
+ * points inside the window and scores them tool by tool (as af_score_points
+ * does with a window); tools must suit af_score_points with a window.  A
+ * frame that places or moves the window (a host-side test on its origin)
+ * runs eagerly instead -- af_integrate_frame, then af_score_points for each
+ * tool -- and records the graph again for the new window (it synchronises
+ * `stream`); so does a frame after a reallocation, instead of AF_EINVAL.
+ * Labels, first free orientations, statistics and the map then equal those
+ * of af_integrate_frame followed by af_score_points for each tool.  Before
+ * the first frame the graph is recorded by that frame. */
 int af_graph_prepare(af_ctx *ctx, const float lo[3], const float hi[3], int64_t max_returns,
                      const int32_t *tool_ids, int32_t n_tools, void *stream);
 int af_graph_frame(af_ctx *ctx, const float *xyz, int64_t n, const float origin[3],
@@ -538,7 +552,9 @@ int af_read_incremental(af_ctx *ctx, int64_t first, int64_t count, int64_t *key,
  * float) into a free slot and queues it: AF_EBUSY when four frames already
  * wait, AF_EINVAL for a stream without a recorded graph, n above max_returns
  * or a frame id that does not increase.  af_server_pending gives the queue
- * length (-1 for a bad id).
+ * length (-1 for a bad id).  A stream whose context has a sliding window
+ * (af_set_window on af_server_context, before af_server_prepare) records its
+ * scoring in its own graph and is never batched; lo/hi are then unused.
  *
  * af_server_step takes the oldest queued frame of every stream (streams
  * visited round robin), launches each (host-to-device copy, then the recorded

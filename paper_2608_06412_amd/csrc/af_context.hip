@@ -45,6 +45,12 @@ struct af_ctx {
   int64_t slot_cap;
   bool graph_dirty;             // recorded frames ran since the host mirrors were refreshed
   bool graph_stale;             // a buffer the graph holds was reallocated
+  bool sticky_reset;            // the host has read the sticky status: the next frame clears it
+  // what the graph was prepared with (a windowed context records it again
+  // after every shift of the window)
+  int32_t g_ids[kMultiTools];
+  int32_t g_n;                  // tools of the prepared graph (0: none)
+  bool g_score;
   // incremental mode
   bool incr_on;
   int32_t incr_tool;
@@ -804,7 +810,7 @@ int af_set_window(af_ctx *c, const int32_t blocks[3]) {
   if (!blocks) return fail(c, AF_EINVAL, "no window size");
   if (c->last_frame >= 0 || c->n_points > 0 || c->win_on)
     return fail(c, AF_EINVAL, "the window is set once, before the first frame");
-  if (c->gexec) return fail(c, AF_EINVAL, "no window with a frame graph");
+  if (c->g_n) return fail(c, AF_EINVAL, "the window is set before the frame graph is prepared");
   for (int a = 0; a < 3; ++a)
     if (blocks[a] < 2 || blocks[a] > 4096)
       return fail(c, AF_EINVAL, "window of %d blocks on axis %d (2..4096)", blocks[a], a);
@@ -853,6 +859,17 @@ int af_integrate_frame_host(af_ctx *c, const float *xyz, int64_t n, const float 
   return af_integrate_frame(c, c->host_xyz, n, origin, frame_id, stream);
 }
 
+// Section 3.3: the window is placed at the first frame and moves (re-centred
+// on the sensor voxel) once the sensor is more than 30 % of its size from
+// the centre on any axis.  Q: the sensor origin in 1/256 voxel units.
+static bool window_shift_due(const af_ctx *c, int3 Q) {
+  if (!c->win_set) return true;
+  const int32_t qv[3] = {Q.x >> 8, Q.y >> 8, Q.z >> 8};
+  for (int a = 0; a < 3; ++a)
+    if (10 * (int64_t)std::abs(qv[a] - c->win_c[a]) > 3 * 8 * (int64_t)c->win_L[a]) return true;
+  return false;
+}
+
 int af_integrate_frame(af_ctx *c, const float *xyz, int64_t n, const float origin[3],
                        int64_t frame_id, void *stream) {
   if (!c) return AF_EINVAL;
@@ -879,10 +896,7 @@ int af_integrate_frame(af_ctx *c, const float *xyz, int64_t n, const float origi
   int3 whi = make_int3(1 << 30, 1 << 30, 1 << 30);
   if (c->win_on) {
     const int32_t qv[3] = {Q.x >> 8, Q.y >> 8, Q.z >> 8};
-    shift = !c->win_set;
-    for (int a = 0; a < 3; ++a)
-      if (c->win_set && 10 * (int64_t)std::abs(qv[a] - c->win_c[a]) > 3 * 8 * (int64_t)c->win_L[a])
-        shift = true;
+    shift = window_shift_due(c, Q);
     if (shift) {
       for (int a = 0; a < 3; ++a) {
         c->win_c[a] = qv[a];
@@ -966,25 +980,40 @@ int af_integrate_frame(af_ctx *c, const float *xyz, int64_t n, const float origi
 
 static int cached_normals(af_ctx *c, hipStream_t s);
 
+// Tools a windowed graph scores take the point list (reach of 255 voxels at most).
+static int window_tools_ok(af_ctx *c, const int32_t *ids, int32_t n) {
+  for (int32_t i = 0; i < n; ++i)
+    if (!score_variant_takes_list(score_variant_default(), c->tools[ids[i]]))
+      return fail(c, AF_EINVAL, "tool %d: reach above 255 voxels (not with a sliding window)",
+                  ids[i]);
+  return AF_OK;
+}
+
+// The score variant a listed (windowed) scoring of tool t runs.
+static int window_variant(const af_ctx *c, const ToolDev &t) {
+  return score_variant_takes_list(c->score_variant, t) ? c->score_variant
+                                                         : score_variant_default();
+}
+
 // With a sliding window only the points inside it are scored (fresh normals
-// over the window's point list); the others keep their last labels, and a
-// point never scored reads 255.
-static int score_window(af_ctx *c, int32_t tool_id, hipStream_t s) {
-  ToolDev &t = c->tools[tool_id];
-  if (!score_variant_takes_list(score_variant_default(), t))
-    return fail(c, AF_EINVAL, "tool %d: K above 1024 or reach above 255 voxels (not with a "
-                              "sliding window)", tool_id);
-  const int variant =
-      score_variant_takes_list(c->score_variant, t) ? c->score_variant : score_variant_default();
+// over the window's point list, listed once for all the tools); the others
+// keep their last labels, and a point never scored reads 255.
+static int score_window(af_ctx *c, const int32_t *ids, int32_t n_tools, hipStream_t s) {
+  int rc = window_tools_ok(c, ids, n_tools);
+  if (rc != AF_OK) return rc;
   const int3 lo = make_int3(c->win_lo[0], c->win_lo[1], c->win_lo[2]);
   const int3 hi = make_int3(c->win_hi[0], c->win_hi[1], c->win_hi[2]);
-  int64_t &init = c->label_init[tool_id];
-  if (init < c->n_points) {
-    launch_label_fill(t.label, t.first_free, init, c->n_points, s);
-    init = c->n_points;
+  for (int32_t i = 0; i < n_tools; ++i) {
+    ToolDev &t = c->tools[ids[i]];
+    int64_t &init = c->label_init[ids[i]];
+    if (init < c->n_points) {
+      launch_label_fill(t.label, t.first_free, init, c->n_points, s);
+      init = c->n_points;
+    }
   }
   hipEvent_t t0 = timing_mark(c, s);
-  HIP_TRY(c, hipMemsetAsync(t.counters, 0, sizeof(ScoreCounters), s));
+  for (int32_t i = 0; i < n_tools; ++i)
+    HIP_TRY(c, hipMemsetAsync(c->tools[ids[i]].counters, 0, sizeof(ScoreCounters), s));
   launch_window_list(c->pts, c->n_points, lo, hi, c->win_sel, c->win_nsel, s);
   PointsDev ps = c->pts;
   ps.sel = c->win_sel;
@@ -992,11 +1021,15 @@ static int score_window(af_ctx *c, int32_t tool_id, hipStream_t s) {
   hipEvent_t t1 = timing_mark(c, s);
   launch_normals(c->p, c->map, ps, c->grid, c->n_points, s, true);
   hipEvent_t t2 = timing_mark(c, s);
-  launch_mask(c->p, ps, t, c->grid, c->n_points, s, true);
-  hipEvent_t t3 = timing_mark(c, s);
-  launch_score(c->p, ps, t, c->grid, c->n_points, variant, c->work, s, true);
+  hipEvent_t t3 = t2;
+  for (int32_t i = 0; i < n_tools; ++i) {
+    const ToolDev &t = c->tools[ids[i]];
+    launch_mask(c->p, ps, t, c->grid, c->n_points, s, true);
+    if (i == 0) t3 = timing_mark(c, s);
+    launch_score(c->p, ps, t, c->grid, c->n_points, window_variant(c, t), c->work, s, true);
+  }
   hipEvent_t t4 = timing_mark(c, s);
-  if (c->timing) {
+  if (c->timing) {   // (the mask stage: the first tool's)
     timing_pair(c, ST_SCORE, t0, t4);
     timing_pair(c, ST_K_NORMALS, t1, t2);
     timing_pair(c, ST_K_MASK, t2, t3);
@@ -1019,7 +1052,7 @@ int af_score_points(af_ctx *c, int32_t tool_id, void *stream) {
   hipStream_t s = (hipStream_t)stream;
   int rc = regrid(c, s);
   if (rc != AF_OK) return rc;
-  if (c->win_on) return score_window(c, tool_id, s);
+  if (c->win_on) return score_window(c, &tool_id, 1, s);
   hipEvent_t t0 = timing_mark(c, s);
   HIP_TRY(c, hipMemsetAsync(t.counters, 0, sizeof(ScoreCounters), s));
   hipEvent_t t1 = timing_mark(c, s);
@@ -1043,7 +1076,7 @@ int af_score_points(af_ctx *c, int32_t tool_id, void *stream) {
 // The tool set of one multi-tool launch: ids checked, LDS offsets, and each
 // tool given its own mask buffers (masks of every tool must coexist).
 static int make_toolset(af_ctx *c, const int32_t *tool_ids, int32_t n_tools, ToolSet &set,
-                        ToolDev *host) {
+                        ToolDev *host, bool own_buffers = true) {
   if (!tool_ids || n_tools < 1 || n_tools > kMultiTools)
     return fail(c, AF_EINVAL, "n_tools must be 1..%d", kMultiTools);
   memset(&set, 0, sizeof(set));
@@ -1065,7 +1098,7 @@ static int make_toolset(af_ctx *c, const int32_t *tool_ids, int32_t n_tools, Too
   for (int32_t i = 0; i < n_tools; ++i) {
     const int32_t id = set.id[i];
     ToolDev &t = c->tools[id];
-    if (!c->own_mask[id]) {
+    if (own_buffers && !c->own_mask[id]) {
       const int64_t mw = (t.K + 63) / 64;
       uint64_t *mk = nullptr, *np = nullptr;
       ALLOC(c, mk, c->cfg.max_points * mw);
@@ -1111,14 +1144,14 @@ static int cached_normals(af_ctx *c, hipStream_t s) {
 
 int af_score_tools(af_ctx *c, const int32_t *tool_ids, int32_t n_tools, void *stream) {
   if (!c) return AF_EINVAL;
-  if (c->win_on) return fail(c, AF_EINVAL, "multi-tool scoring is not available with a window");
   int rc;
   if (c->graph_dirty && (rc = graph_settle(c)) != AF_OK) return rc;
   ToolSet set;
   ToolDev host[kMultiTools];
-  if ((rc = make_toolset(c, tool_ids, n_tools, set, host)) != AF_OK) return rc;
+  if ((rc = make_toolset(c, tool_ids, n_tools, set, host, !c->win_on)) != AF_OK) return rc;
   hipStream_t s = (hipStream_t)stream;
   if ((rc = regrid(c, s)) != AF_OK) return rc;
+  if (c->win_on) return score_window(c, tool_ids, n_tools, s);
   hipEvent_t t0 = timing_mark(c, s);
   for (int32_t i = 0; i < n_tools; ++i)
     HIP_TRY(c, hipMemsetAsync(host[i].counters, 0, sizeof(ScoreCounters), s));
@@ -1152,25 +1185,28 @@ static hipError_t clear_sticky(af_ctx *c) {
 
 // Wait for recorded frames, refresh the host's point and block counts and
 // report any status they raised (sticky across frames).
+// One copy and one wait: the last frame left the counts in the counters'
+// snapshot, and the sticky fields are reset by the next recorded frame.
 static int graph_settle(af_ctx *c) {
   c->graph_dirty = false;
+  HIP_TRY(c, hipMemcpyAsync(c->counters_host, c->counters, offsetof(FrameCounters, fold),
+                            hipMemcpyDeviceToHost, c->last_stream));
   HIP_TRY(c, hipStreamSynchronize(c->last_stream));
-  FrameCounters h;
-  HIP_TRY(c, hipMemcpy(&h, c->counters, offsetof(FrameCounters, fold), hipMemcpyDeviceToHost));
-  int32_t nb = 0, np = 0;
-  HIP_TRY(c, hipMemcpy(&nb, c->map.n_blocks, sizeof(int32_t), hipMemcpyDeviceToHost));
-  HIP_TRY(c, hipMemcpy(&np, c->pts.n_points, sizeof(int32_t), hipMemcpyDeviceToHost));
-  c->n_blocks = std::min<int64_t>(nb, c->cfg.max_blocks);
-  c->n_points = std::min<int64_t>(np, c->cfg.max_points);
-  if (h.sbmin[0] <= h.sbmax[0]) {
+  const FrameCounters h = *c->counters_host;
+  c->n_blocks = std::min<int64_t>(h.snap_blocks, c->cfg.max_blocks);
+  c->n_points = std::min<int64_t>(h.snap_points, c->cfg.max_points);
+  if (h.sbmin[0] <= h.sbmax[0] && !c->win_on) {   // (with a window the box is the window)
     for (int a = 0; a < 3; ++a) {
       c->bbox_lo[a] = c->have_bbox ? std::min(c->bbox_lo[a], h.sbmin[a]) : h.sbmin[a];
       c->bbox_hi[a] = c->have_bbox ? std::max(c->bbox_hi[a], h.sbmax[a]) : h.sbmax[a];
     }
     c->have_bbox = true;
   }
-  HIP_TRY(c, clear_sticky(c));
+  c->sticky_reset = true;
   c->status = h.sticky;
+  // a windowed graph scores every point its frames create
+  if (c->win_on && c->g_score)
+    for (int32_t i = 0; i < c->g_n; ++i) c->label_init[c->g_ids[i]] = c->n_points;
   // a block beyond the recorded box: the grid must grow, so the graph is done
   if (h.sticky & kStatusOutsideGrid) c->graph_stale = true;
   if (h.sticky & kStatusHashFull) return fail(c, AF_EOVERFLOW, "hash table full");
@@ -1216,6 +1252,8 @@ int ctx_score_jobs(af_ctx *c, const int32_t *tool_ids, int32_t n_tools, ScoreJob
   return AF_OK;
 }
 
+bool ctx_windowed(const af_ctx *c) { return c && c->win_on; }
+
 // A recorded (unscored) frame scored on its own stream: the launch a scored
 // graph ends with (a server step that batches fewer than two streams).
 int ctx_score_stream(af_ctx *c, const int32_t *tool_ids, int32_t n_tools, void *stream) {
@@ -1232,46 +1270,39 @@ int ctx_score_stream(af_ctx *c, const int32_t *tool_ids, int32_t n_tools, void *
 
 extern "C" {
 
-static int graph_prepare(af_ctx *c, const float lo[3], const float hi[3], int64_t max_returns,
-                         const int32_t *tool_ids, int32_t n_tools, void *stream, bool score) {
-  if (!c) return AF_EINVAL;
-  if (!lo || !hi || max_returns < 1) return fail(c, AF_EINVAL, "bad graph arguments");
-  if (c->incr_on)
-    return fail(c, AF_EINVAL, "a context in incremental mode runs its frames eagerly");
-  if (c->win_on) return fail(c, AF_EINVAL, "frame graphs are not available with a window");
-  int rc;
-  if (c->graph_dirty && (rc = graph_settle(c)) != AF_OK) return rc;
+// Capture of one frame on the context's capture stream: integration of up to
+// slot_cap returns (the frame's size, origin and id, and the window box, read
+// from the device argument block), then normals, masks and scoring of the
+// prepared tools.  Without a window the grid covers the scene box and every
+// point is scored in one multi-tool launch; with one, the grid is the window's
+// and the points inside it are listed and scored tool by tool, so a shift
+// (which moves the grid) records the frame again.
+static int graph_record(af_ctx *c, hipStream_t s) {
   ToolSet set;
   ToolDev host[kMultiTools];
-  if ((rc = make_toolset(c, tool_ids, n_tools, set, host)) != AF_OK) return rc;
-  hipStream_t s = (hipStream_t)stream;
+  // (a windowed frame scores its tools one after the other: they share the
+  // mask buffers)
+  int rc = make_toolset(c, c->g_ids, c->g_n, set, host, !c->win_on);
+  if (rc != AF_OK) return rc;
+  if (c->win_on && (rc = window_tools_ok(c, c->g_ids, c->g_n)) != AF_OK) return rc;
+  if (c->win_on)   // labels of points no graph scored yet read "never evaluated"
+    for (int32_t i = 0; i < c->g_n; ++i) {
+      int64_t &init = c->label_init[c->g_ids[i]];
+      if (init < c->n_points) {
+        launch_label_fill(c->tools[c->g_ids[i]].label, c->tools[c->g_ids[i]].first_free, init,
+                          c->n_points, s);
+        init = c->n_points;
+      }
+    }
   HIP_TRY(c, hipStreamSynchronize(s));
-  // the grid covers the scene box (and every block so far) and never grows
-  const double bs = 8.0 * c->cfg.voxel;
-  for (int a = 0; a < 3; ++a) {
-    if (!(lo[a] < hi[a]) || !(fabs((double)lo[a]) < 1e4) || !(fabs((double)hi[a]) < 1e4))
-      return fail(c, AF_EINVAL, "bad scene box");
-    const int32_t l = (int32_t)floor((double)lo[a] / bs), h = (int32_t)floor((double)hi[a] / bs);
-    c->bbox_lo[a] = c->have_bbox ? std::min(c->bbox_lo[a], l) : l;
-    c->bbox_hi[a] = c->have_bbox ? std::max(c->bbox_hi[a], h) : h;
-  }
-  c->have_bbox = true;
-  if ((rc = regrid(c, s)) != AF_OK) return rc;
-  if (max_returns > c->fs.cap && (rc = alloc_scratch(c, max_returns)) != AF_OK) return rc;
-  if (c->slot_xyz) dev_free(c, c->slot_xyz, sizeof(float) * 3 * c->slot_cap);
-  c->slot_xyz = nullptr;
-  ALLOC(c, c->slot_xyz, 3 * max_returns);
-  c->slot_cap = max_returns;
-  launch_normals(c->p, c->map, c->pts, c->grid, 0, s);   // uploads its constant table
-  HIP_TRY(c, hipStreamSynchronize(s));
-  HIP_TRY(c, clear_sticky(c));
   if (c->gexec) hipGraphExecDestroy(c->gexec);
   if (c->graph) hipGraphDestroy(c->graph);
   c->gexec = nullptr;
   c->graph = nullptr;
   if (!c->cap_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
   hipStream_t cs = c->cap_stream;
-  const int64_t cap = max_returns, NP = c->cfg.max_points;
+  const int64_t cap = c->slot_cap, NP = c->cfg.max_points;
+  const int32_t n_tools = c->g_n;
   HIP_TRY(c, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
   launch_frame_prep(c->slot_xyz, c->fargs, cap, c->p, c->map, c->pts, c->fs, c->counters, cs);
   launch_assign_blocks(c->map, c->fs, c->counters, c->fargs, cs);
@@ -1282,13 +1313,28 @@ static int graph_prepare(af_ctx *c, const float lo[3], const float hi[3], int64_
   launch_points_view(c->fargs, cap, c->p, c->pts, c->fs, cs);
   launch_integrate(c->fargs, cap, c->p, c->map, c->fs, c->counters, c->grid,
                    std::min<int64_t>(c->cfg.max_blocks, cap * (kMaxSpan + kMaxBand)), cs);
-  launch_stick_status(c->counters, cs);
+  launch_stick_status(c->counters, c->map.n_blocks, c->pts.n_points, cs);
   for (int32_t i = 0; i < n_tools; ++i)
     launch_zero_words(host[i].counters, sizeof(ScoreCounters), cs);
-  launch_normals(c->p, c->map, c->pts, c->grid, NP, cs, true);
-  for (int32_t i = 0; i < n_tools; ++i) launch_mask(c->p, c->pts, host[i], c->grid, NP, cs, true);
-  if (score)
-    launch_score_multi(c->p, c->pts, c->tools_dev, host, set, c->grid, NP, c->work, cs, true);
+  if (!c->win_on) {
+    launch_normals(c->p, c->map, c->pts, c->grid, NP, cs, true);
+    for (int32_t i = 0; i < n_tools; ++i)
+      launch_mask(c->p, c->pts, host[i], c->grid, NP, cs, true);
+    if (c->g_score)
+      launch_score_multi(c->p, c->pts, c->tools_dev, host, set, c->grid, NP, c->work, cs, true);
+  } else {
+    const int3 lo = make_int3(c->win_lo[0], c->win_lo[1], c->win_lo[2]);
+    const int3 hi = make_int3(c->win_hi[0], c->win_hi[1], c->win_hi[2]);
+    launch_window_list(c->pts, NP, lo, hi, c->win_sel, c->win_nsel, cs, true);
+    PointsDev ps = c->pts;
+    ps.sel = c->win_sel;
+    ps.n_sel = c->win_nsel;
+    launch_normals(c->p, c->map, ps, c->grid, NP, cs, true);
+    for (int32_t i = 0; i < n_tools; ++i) {
+      launch_mask(c->p, ps, host[i], c->grid, NP, cs, true);
+      launch_score(c->p, ps, host[i], c->grid, NP, window_variant(c, host[i]), c->work, cs, true);
+    }
+  }
   hipGraph_t g = nullptr;
   const hipError_t e1 = hipStreamEndCapture(cs, &g);
   if (e1 != hipSuccess || !g)
@@ -1297,14 +1343,73 @@ static int graph_prepare(af_ctx *c, const float lo[3], const float hi[3], int64_
   HIP_TRY(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
   c->graph_stale = false;
   c->last_stream = s;
-  return hip_check(c, "graph prepare");
+  return hip_check(c, "graph record");
+}
+
+static int graph_prepare(af_ctx *c, const float lo[3], const float hi[3], int64_t max_returns,
+                         const int32_t *tool_ids, int32_t n_tools, void *stream, bool score) {
+  if (!c) return AF_EINVAL;
+  if (!lo || !hi || max_returns < 1) return fail(c, AF_EINVAL, "bad graph arguments");
+  if (c->incr_on)
+    return fail(c, AF_EINVAL, "a context in incremental mode runs its frames eagerly");
+  if (c->win_on && !score)
+    return fail(c, AF_EINVAL, "a windowed context scores inside its recorded frame");
+  int rc;
+  if (c->graph_dirty && (rc = graph_settle(c)) != AF_OK) return rc;
+  ToolSet set;
+  ToolDev host[kMultiTools];
+  if ((rc = make_toolset(c, tool_ids, n_tools, set, host, !c->win_on)) != AF_OK) return rc;
+  if (c->win_on && (rc = window_tools_ok(c, tool_ids, n_tools)) != AF_OK) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(c, hipStreamSynchronize(s));
+  const double bs = 8.0 * c->cfg.voxel;
+  int32_t blo[3], bhi[3];
+  for (int a = 0; a < 3; ++a) {
+    if (!(lo[a] < hi[a]) || !(fabs((double)lo[a]) < 1e4) || !(fabs((double)hi[a]) < 1e4))
+      return fail(c, AF_EINVAL, "bad scene box");
+    blo[a] = (int32_t)floor((double)lo[a] / bs);
+    bhi[a] = (int32_t)floor((double)hi[a] / bs);
+  }
+  // the grid covers the scene box (and every block so far) and never grows;
+  // with a window the box is the window's, wherever it is
+  if (!c->win_on) {
+    for (int a = 0; a < 3; ++a) {
+      c->bbox_lo[a] = c->have_bbox ? std::min(c->bbox_lo[a], blo[a]) : blo[a];
+      c->bbox_hi[a] = c->have_bbox ? std::max(c->bbox_hi[a], bhi[a]) : bhi[a];
+    }
+    c->have_bbox = true;
+    if ((rc = regrid(c, s)) != AF_OK) return rc;
+  }
+  if (max_returns > c->fs.cap && (rc = alloc_scratch(c, max_returns)) != AF_OK) return rc;
+  if (c->slot_xyz) dev_free(c, c->slot_xyz, sizeof(float) * 3 * c->slot_cap);
+  c->slot_xyz = nullptr;
+  ALLOC(c, c->slot_xyz, 3 * max_returns);
+  c->slot_cap = max_returns;
+  launch_normals(c->p, c->map, c->pts, c->grid, 0, s);   // uploads its constant table
+  HIP_TRY(c, hipStreamSynchronize(s));
+  HIP_TRY(c, clear_sticky(c));
+  c->sticky_reset = false;
+  for (int32_t i = 0; i < n_tools; ++i) c->g_ids[i] = tool_ids[i];
+  c->g_n = n_tools;
+  c->g_score = score;
+  if (c->win_on && !c->win_set) {
+    // the window (and so the grid) is placed by the first frame, which runs
+    // eagerly and records the graph
+    if (c->gexec) hipGraphExecDestroy(c->gexec);
+    if (c->graph) hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+    c->graph_stale = false;
+    return AF_OK;
+  }
+  return graph_record(c, s);
 }
 
 int af_graph_frame(af_ctx *c, const float *xyz, int64_t n, const float origin[3],
                    int64_t frame_id, void *stream) {
   if (!c) return AF_EINVAL;
-  if (!c->gexec) return fail(c, AF_EINVAL, "no recorded frame graph");
-  if (c->graph_stale)
+  if (!c->g_n) return fail(c, AF_EINVAL, "no recorded frame graph");
+  if (c->graph_stale && !c->win_on)
     return fail(c, AF_EINVAL, "buffers of the recorded frame graph were reallocated: prepare again");
   if (n < 0 || n > c->slot_cap || (n > 0 && !xyz) || !origin)
     return fail(c, AF_EINVAL, "bad frame arguments (n = %lld, slot %lld)", (long long)n,
@@ -1321,9 +1426,31 @@ int af_graph_frame(af_ctx *c, const float *xyz, int64_t n, const float origin[3]
   hipStream_t s = (hipStream_t)stream;
   if (n > 0 && xyz != c->slot_xyz)
     HIP_TRY(c, hipMemcpyAsync(c->slot_xyz, xyz, sizeof(float) * 3 * n, hipMemcpyDefault, s));
-  launch_set_frame_args(c->fargs, n, Q, (int32_t)frame_id,
-                        make_int3(-(1 << 30), -(1 << 30), -(1 << 30)),
-                        make_int3(1 << 30, 1 << 30, 1 << 30), s);
+  int3 wlo = make_int3(-(1 << 30), -(1 << 30), -(1 << 30));
+  int3 whi = make_int3(1 << 30, 1 << 30, 1 << 30);
+  if (c->win_on) {
+    if (!c->gexec || window_shift_due(c, Q)) {
+      // the frame that places or moves the window: evictions, block
+      // re-creation and the grid's move run eagerly (as af_integrate_frame
+      // and af_score_points would), then the frame is recorded again
+      int rc;
+      if (c->graph_dirty && (rc = graph_settle(c)) != AF_OK) return rc;
+      if ((rc = af_integrate_frame(c, c->slot_xyz, n, origin, frame_id, stream)) != AF_OK)
+        return rc;
+      if ((rc = score_window(c, c->g_ids, c->g_n, s)) != AF_OK) return rc;
+      return graph_record(c, s);
+    }
+    if (c->graph_stale) {   // (a windowed context records the frame again)
+      int rc;
+      if (c->graph_dirty && (rc = graph_settle(c)) != AF_OK) return rc;
+      if ((rc = graph_record(c, s)) != AF_OK) return rc;
+    }
+    wlo = make_int3(c->win_lo[0], c->win_lo[1], c->win_lo[2]);
+    whi = make_int3(c->win_hi[0], c->win_hi[1], c->win_hi[2]);
+  }
+  launch_set_frame_args(c->fargs, n, Q, (int32_t)frame_id, wlo, whi, s,
+                        c->sticky_reset ? c->counters : nullptr);
+  c->sticky_reset = false;
   HIP_TRY(c, hipGraphLaunch(c->gexec, s));
   c->last_frame = frame_id;
   c->last_stream = s;

@@ -706,13 +706,16 @@ __global__ void k_grid_fill(GridDev g, int64_t nbricks) {
   for (int64_t j = i; j < nbricks * 16; j += stride) g.occ1[j] = 0u;
 }
 
-__global__ void k_stick_status(FrameCounters *c) {
+__global__ void k_stick_status(FrameCounters *c, const int32_t *n_blocks,
+                               const int32_t *n_points) {
   c->sticky |= c->status;
   if (c->n_new_blocks > 0)
     for (int a = 0; a < 3; ++a) {
       c->sbmin[a] = c->bmin[a] < c->sbmin[a] ? c->bmin[a] : c->sbmin[a];
       c->sbmax[a] = c->bmax[a] > c->sbmax[a] ? c->bmax[a] : c->sbmax[a];
     }
+  c->snap_blocks = *n_blocks;
+  c->snap_points = *n_points;
 }
 
 __global__ void k_zero_words(uint32_t *p, int64_t n) {
@@ -722,12 +725,19 @@ __global__ void k_zero_words(uint32_t *p, int64_t n) {
 }
 
 __global__ void k_set_frame_args(FrameArgs *fa, int64_t n, int3 Q, int32_t frame, int3 wlo,
-                                 int3 whi) {
+                                 int3 whi, FrameCounters *clear) {
   fa->n = n;
   fa->Q = Q;
   fa->frame = frame;
   fa->wlo = wlo;
   fa->whi = whi;
+  if (clear) {
+    clear->sticky = 0;
+    for (int a = 0; a < 3; ++a) {
+      clear->sbmin[a] = 0x7fffffff;
+      clear->sbmax[a] = -0x7fffffff - 1;
+    }
+  }
 }
 
 // ------------------------------------------------------- sliding window
@@ -826,14 +836,16 @@ k_window_link(MapDev m, PointsDev pts, int64_t n_points, int3 lo, int3 hi) {
 
 // Points inside [lo, hi] listed: the waves' counts are combined in LDS, so
 // a workgroup of 1024 points takes one atomic on the list's counter (one per
-// wave serialised some 30,000 atomics on that address per call).
+// wave serialised some 30,000 atomics on that address per call).  A negative
+// n_points reads the count on the device (a recorded frame).
 constexpr int kListThreads = 1024;
 __global__ void __launch_bounds__(kListThreads)
 k_window_list(PointsDev pts, int64_t n_points, int3 lo, int3 hi, int32_t *sel, int32_t *n_sel) {
   __shared__ int part[kListThreads / 64 + 1];
   const int64_t i = (int64_t)blockIdx.x * kListThreads + threadIdx.x;
+  const int64_t n = n_points < 0 ? (int64_t)*pts.n_points : n_points;
   bool take = false;
-  if (i < n_points) {
+  if (i < n) {
     int32_t v[3];
     point_block(pts, i, v);
     take = in_box(v[0] >> 3, v[1] >> 3, v[2] >> 3, lo, hi);
@@ -878,13 +890,14 @@ void launch_zero_words(void *p, int64_t bytes, hipStream_t s) {
                      dim3(256), 0, s, (uint32_t *)p, n);
 }
 
-void launch_stick_status(FrameCounters *c, hipStream_t s) {
-  hipLaunchKernelGGL(k_stick_status, dim3(1), dim3(1), 0, s, c);
+void launch_stick_status(FrameCounters *c, const int32_t *n_blocks, const int32_t *n_points,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_stick_status, dim3(1), dim3(1), 0, s, c, n_blocks, n_points);
 }
 
 void launch_set_frame_args(FrameArgs *fa, int64_t n, int3 Q, int32_t frame, int3 wlo, int3 whi,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(k_set_frame_args, dim3(1), dim3(1), 0, s, fa, n, Q, frame, wlo, whi);
+                           hipStream_t s, FrameCounters *clear) {
+  hipLaunchKernelGGL(k_set_frame_args, dim3(1), dim3(1), 0, s, fa, n, Q, frame, wlo, whi, clear);
 }
 
 void launch_window_evict(MapDev m, PointsDev pts, int64_t n_blocks, int64_t n_points, int3 lo,
@@ -918,11 +931,12 @@ void launch_window_link(MapDev m, PointsDev pts, int64_t n_points, int3 lo, int3
 }
 
 void launch_window_list(PointsDev pts, int64_t n_points, int3 lo, int3 hi, int32_t *sel,
-                        int32_t *n_sel, hipStream_t s) {
+                        int32_t *n_sel, hipStream_t s, bool dev_n) {
   launch_zero_words(n_sel, sizeof(int32_t), s);
   if (n_points > 0)
     hipLaunchKernelGGL(k_window_list, dim3((unsigned)((n_points + kListThreads - 1) / kListThreads)),
-                       dim3(kListThreads), 0, s, pts, n_points, lo, hi, sel, n_sel);
+                       dim3(kListThreads), 0, s, pts, dev_n ? (int64_t)-1 : n_points, lo, hi, sel,
+                       n_sel);
 }
 
 void launch_label_fill(uint8_t *label, int16_t *first_free, int64_t from, int64_t to,

@@ -72,6 +72,7 @@ struct FrameCounters {
   int32_t free_before;   // evicted ids available when the frame started
   int32_t sticky;   // status bits of recorded frames since the host last looked (not reset per frame)
   int32_t sbmin[3], sbmax[3];   // block box of those frames (empty when sbmin > sbmax)
+  int32_t snap_blocks, snap_points;   // block ids and points after the last recorded frame
   // per-slot fold statistics: [slot][0] applied pairs, [1] cone-excluded
   // pairs, [2] folded voxels (summed on the host; not part of the mid-frame
   // read of the fields above)
@@ -260,8 +261,10 @@ struct FrameArgs {
   int32_t frame;  // frame id
   int3 wlo, whi;  // block box the frame may write (the sliding window; else unbounded)
 };
+// clear: when set, also resets the sticky status and block box of c (the
+// first recorded frame after the host read them)
 void launch_set_frame_args(FrameArgs *fa, int64_t n, int3 Q, int32_t frame, int3 wlo, int3 whi,
-                           hipStream_t s);
+                           hipStream_t s, FrameCounters *clear = nullptr);
 
 // Cached normal axes (state: -2 pending, 0 none, 1 axis valid).
 struct NormalCache {
@@ -377,7 +380,10 @@ void launch_smooth_refine(const SmoothField &f, double v, const float *p, int64_
                           const float *q0, int32_t n_starts, const float *samples, int32_t M,
                           float c, float tau_s, int32_t steps, float eta, float max_step,
                           float *q_out, float *s_out, unsigned long long *work, hipStream_t s);
-void launch_stick_status(FrameCounters *c, hipStream_t s);
+// a recorded frame's end: status and block box into the sticky fields, and
+// the block and point counts into the snapshot the host reads
+void launch_stick_status(FrameCounters *c, const int32_t *n_blocks, const int32_t *n_points,
+                         hipStream_t s);
 void launch_zero_words(void *p, int64_t bytes, hipStream_t s);   // a fill kernel (graph-safe)
 // nb: an upper bound of the frame's returns (sizes the launches)
 void launch_frame_prep(const float *xyz, const FrameArgs *fa, int64_t nb, const Params &p,
@@ -409,8 +415,9 @@ void launch_window_thaw(MapDev m, PointsDev pts, FrameScratch fs, FrameCounters 
 void launch_window_link(MapDev m, PointsDev pts, int64_t n_points, int3 lo, int3 hi,
                         hipStream_t s);
 // Points of [0, n_points) inside the box, listed into sel (count in *n_sel).
+// dev_n: n_points bounds the launch and the count is read on the device
 void launch_window_list(PointsDev pts, int64_t n_points, int3 lo, int3 hi, int32_t *sel,
-                        int32_t *n_sel, hipStream_t s);
+                        int32_t *n_sel, hipStream_t s, bool dev_n = false);
 // label[i] = 255 (never evaluated), first_free[i] = -1 for i in [from, to).
 void launch_label_fill(uint8_t *label, int16_t *first_free, int64_t from, int64_t to,
                        hipStream_t s);
@@ -476,6 +483,9 @@ int ctx_graph_prepare_unscored(af_ctx *c, const float lo[3], const float hi[3],
 int ctx_score_jobs(af_ctx *c, const int32_t *tool_ids, int32_t n_tools, ScoreJob *out);
 // Score such a frame on its own stream instead (what the scored graph does).
 int ctx_score_stream(af_ctx *c, const int32_t *tool_ids, int32_t n_tools, void *stream);
+// A context with a sliding window (its frames are scored inside its own graph,
+// over the window's point list, so the server does not batch it).
+bool ctx_windowed(const af_ctx *c);
 int score_variants();
 int score_variant_default();
 // whether the configuration (after its fallbacks for this tool) honours PointsDev::sel

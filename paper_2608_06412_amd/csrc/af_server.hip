@@ -217,7 +217,7 @@ int af_server_prepare(af_server *s, int32_t id, const float lo[3], const float h
   hipStreamSynchronize(t->hs);
   free_slots(*t);
   t->max_returns = 0;
-  const bool batched = s->batch_min > 0;
+  const bool batched = s->batch_min > 0 && !af::ctx_windowed(t->ctx);
   if (batched) {
     const int rc = batch_resources(s);
     if (rc != AF_OK) return rc;
