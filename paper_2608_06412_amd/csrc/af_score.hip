@@ -734,6 +734,7 @@ __device__ inline int nth_bit(uint64_t m, int r) {
 
 constexpr int kLdsK = 256;    // orientations whose table heads the "swar" kernels stage in LDS
 constexpr int kNearK = 1024;  // orientations whose table offsets the "near" kernels stage in LDS
+constexpr int kLfK = 256;     // orientations whose first entries the "lds1" configurations stage
 
 // Hit test of one table entry at point s: arm samples (NEAR) hit on TSDF < r_c
 // or unknown-and-not-cleared; body and corridor entries hit on TSDF < r_c
@@ -1306,10 +1307,14 @@ __device__ inline void near_flush(ScoreCounterBlock &sc, NearAcc &a, int lane) {
 
 // One point of the "near" scoring (see k_score_near): label and first free
 // orientation of point i for tool t, whose begin offsets are s_begin.
-template <int UN, int CO, int B1, int PF, int RE, int LZ = 0, int UC = 0, int UB = 0>
+// LF: s_first holds, for every orientation k, its 64 entries after the arm
+// samples (lane l: entry min(begin[k] + 3 + l, begin[k + 1] - 1)), 4-byte
+// form, so a candidate's first step reads its entries from LDS.
+template <int UN, int CO, int B1, int PF, int RE, int LZ = 0, int UC = 0, int UB = 0, int LF = 0>
 __device__ inline void near_point(const Params &p, const PointsDev &pts, const ToolDev &t,
                                   const GridDev &g, const SwGrid &q, const uint32_t *s_begin,
-                                  int32_t mw, int64_t i, int lane, NearAcc &acc) {
+                                  int32_t mw, int64_t i, int lane, NearAcc &acc,
+                                  const uint32_t *s_first = nullptr) {
   constexpr uint32_t E = 3;   // the arm samples
   constexpr int F = 64 / PF;  // prefix entries per candidate when PF > 1
   static_assert(PF == 1 || PF == 2 || PF == 4 || PF == 8, "PF divides the wave");
@@ -1347,9 +1352,14 @@ __device__ inline void near_point(const Params &p, const PointsDev &pts, const T
       Ent pre{};
       auto first_step = [&](uint64_t o) {
         const int kn = 64 * w + (__ffsll((long long)o) - 1);
-        const uint32_t bn = s_begin[kn] + E, en = s_begin[kn + 1];
-        const uint32_t idx = bn + (uint32_t)lane;
-        return load_entry<RE>(t, idx < en ? idx : en - 1);
+        if constexpr (LF != 0) {
+          static_assert(RE == 1 && PF == 1 && UN == 1, "4-byte entries, one step");
+          return (Ent)s_first[kn * 64 + lane];
+        } else {
+          const uint32_t bn = s_begin[kn] + E, en = s_begin[kn + 1];
+          const uint32_t idx = bn + (uint32_t)lane;
+          return load_entry<RE>(t, idx < en ? idx : en - 1);
+        }
       };
       if (PF == 1 && open) pre = first_step(open);
       while (open && ff < 0) {
@@ -1412,9 +1422,9 @@ __device__ inline void near_point(const Params &p, const PointsDev &pts, const T
             body = __popcll(bm1);
             start = b + nin;
           }
-          if (scan_rest_sw<UN, CO, B1, RE, LZ, UC, UB>(p, t, q, f, kj, start, e, body, acc.lookups, acc.cchecks,
-                                           acc.cclear, acc.sbody, acc.sfar, c4, g.occ4,
-                                           PF == 1 && UN == 1 ? &cur : nullptr)) {
+          if (scan_rest_sw<UN, CO, B1, RE, LZ, UC, UB>(
+                  p, t, q, f, kj, start, e, body, acc.lookups, acc.cchecks, acc.cclear, acc.sbody,
+                  acc.sfar, c4, g.occ4, PF == 1 && UN == 1 ? &cur : nullptr)) {
             ff = (int16_t)kj;
             break;
           }
@@ -1448,7 +1458,7 @@ __device__ inline void near_point(const Params &p, const PointsDev &pts, const T
 // Same labels, first free orientations and canonical counts as the plain
 // scan.
 template <int NT, int UN, int FB, int CO, int B1, int DIAG, int PF = 1, int RE = 0, int UC = 0,
-          int UB = 0>
+          int UB = 0, int LF = 0>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8)))
 k_score_near(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t mw,
              unsigned *work) {
@@ -1456,8 +1466,19 @@ k_score_near(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t m
   if (n < 0) n = pts.sel ? (int64_t)*pts.n_sel : (int64_t)*pts.n_points;
   constexpr int NW = NT / 64;
   __shared__ uint32_t s_begin[kNearK + 1];
+  // LF: the first 64 entries after the arm samples of every orientation
+  // (K <= kLfK, 64 KiB), read from LDS instead of the table
+  __shared__ uint32_t s_first[LF ? kLfK * 64 : 1];
   const int K = t.K;
   for (int j = threadIdx.x; j <= K; j += NT) s_begin[j] = t.begin[j];
+  if constexpr (LF != 0) {
+    static_assert(NT == 1024, "two workgroups of 68 KiB LDS fill a CU's 160 KiB at 8 waves/SIMD");
+    for (int j = threadIdx.x; j < K * 64; j += NT) {
+      const uint32_t b = t.begin[j >> 6] + 3u, e = t.begin[(j >> 6) + 1];
+      const uint32_t idx = b + (uint32_t)(j & 63);
+      s_first[j] = load_entry<1>(t, idx < e ? idx : e - 1);
+    }
+  }
   __syncthreads();
   const SwGrid q = sw_grid(g);
   const int lane = lane_id();
@@ -1488,7 +1509,8 @@ k_score_near(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t m
         !pts.sel ? i
         : FB > 0 ? (int64_t)__builtin_amdgcn_readlane(selv, (int)(FB - (batch_end - i)))
                  : (int64_t)__builtin_amdgcn_readfirstlane(pts.sel[i]);
-    near_point<UN, CO, B1, PF, RE, 1, UC, UB>(p, pts, t, g, q, s_begin, mw, pi, lane, a);
+    near_point<UN, CO, B1, PF, RE, 1, UC, UB, LF>(p, pts, t, g, q, s_begin, mw, pi, lane, a,
+                                                  s_first);
     if (a.lookups > (1u << 30)) near_flush<DIAG>(sc, a, lane);
     if (FB > 0) {
       if (++i >= batch_end) {
@@ -1631,6 +1653,7 @@ struct ScoreVariant {
   const char *name;
   int max_k;         // largest K the configuration handles (0: any)
   int needs_rel;     // 1: only with the 4-byte entry form (offsets within +-255)
+  const char *above_k;   // the configuration that runs above max_k (null: the plain one)
 };
 
 // The tunable score configurations (identical results; speed only).
@@ -1650,8 +1673,17 @@ const ScoreVariant kVariants[] = {
     {k_score_near<256, 1, 8, 2, 1, 0, 1, 1, 2>, 256, "near wg256 unroll1 dyn8 coarse4 bit rel corr2", kNearK, 1},
     {k_score_near<256, 1, 8, 2, 1, 1, 1, 1, 2>, 256, "near wg256 unroll1 dyn8 coarse4 bit rel corr2 diag", kNearK, 1},
     {k_score_near<256, 1, 8, 2, 1, 0, 1, 1, 0, 2>, 256, "near wg256 unroll1 dyn8 coarse4 bit rel body2", kNearK, 1},
+    {k_score_near<1024, 1, 8, 2, 1, 0, 1, 1, 2, 0, 1>, 1024,
+     "near wg1024 unroll1 dyn8 coarse4 bit rel corr2 lds1", kLfK, 1,
+     "near wg256 unroll1 dyn8 coarse4 bit rel corr2"},
 };
 constexpr int kNumVariants = (int)(sizeof(kVariants) / sizeof(kVariants[0]));
+
+static int variant_index(const char *name) {
+  for (int v = 0; v < kNumVariants; ++v)
+    if (strcmp(kVariants[v].name, name) == 0) return v;
+  return 0;
+}
 int g_resident[kNumVariants];   // workgroups per CU, from the occupancy query
 int g_num_cu = 0;
 
@@ -1748,10 +1780,7 @@ int score_variants() { return kNumVariants; }
 
 // The configuration a new context uses (the fastest on the tree workload).
 int score_variant_default() {
-  static const char kDefault[] = "near wg256 unroll1 dyn8 coarse4 bit rel corr2";
-  for (int v = 0; v < kNumVariants; ++v)
-    if (strcmp(kVariants[v].name, kDefault) == 0) return v;
-  return 0;
+  return variant_index("near wg1024 unroll1 dyn8 coarse4 bit rel corr2 lds1");
 }
 
 const char *score_variant_name(int v) {
@@ -1846,6 +1875,8 @@ int launch_score_jobs(const ScoreJob *jobs_dev, const ScoreJob *jobs_host, int32
 
 static int effective_variant(int variant, const ToolDev &t) {
   if (variant < 0 || variant >= kNumVariants) variant = 0;
+  if (kVariants[variant].max_k && t.K > kVariants[variant].max_k)
+    variant = kVariants[variant].above_k ? variant_index(kVariants[variant].above_k) : 0;
   if (kVariants[variant].max_k && t.K > kVariants[variant].max_k) variant = 0;
   if (kVariants[variant].needs_rel && !t.rent) variant = 0;
   return variant;
