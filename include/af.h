@@ -369,7 +369,8 @@ int af_tune_score(af_ctx *ctx, int32_t tool_id, int32_t reps, void *stream, int3
  * (metres, merged with every block already mapped) and is not regrown while
  * the graph is in use, so no frame needs a host round trip.  Synchronises
  * `stream`.  AF_EINVAL for bad arguments or tools (as af_score_tools),
- * AF_ENOMEM, AF_EDEVICE if the capture fails.
+ * AF_ENOMEM, AF_EDEVICE if the capture fails; a failed call leaves no
+ * recorded graph (af_graph_frame then returns AF_EINVAL).
  *
  * af_graph_frame replays the graph for one frame: `xyz` (device, n x 3 float,
  * n <= max_returns; may be af_graph_slot(), which skips a copy), sensor origin

@@ -1349,13 +1349,14 @@ static int graph_record(af_ctx *c, hipStream_t s) {
 static int graph_prepare(af_ctx *c, const float lo[3], const float hi[3], int64_t max_returns,
                          const int32_t *tool_ids, int32_t n_tools, void *stream, bool score) {
   if (!c) return AF_EINVAL;
+  int rc;
+  if (c->graph_dirty && (rc = graph_settle(c)) != AF_OK) return rc;
+  c->g_n = 0;   // a prepare that fails leaves no graph to replay
   if (!lo || !hi || max_returns < 1) return fail(c, AF_EINVAL, "bad graph arguments");
   if (c->incr_on)
     return fail(c, AF_EINVAL, "a context in incremental mode runs its frames eagerly");
   if (c->win_on && !score)
     return fail(c, AF_EINVAL, "a windowed context scores inside its recorded frame");
-  int rc;
-  if (c->graph_dirty && (rc = graph_settle(c)) != AF_OK) return rc;
   ToolSet set;
   ToolDev host[kMultiTools];
   if ((rc = make_toolset(c, tool_ids, n_tools, set, host, !c->win_on)) != AF_OK) return rc;
@@ -1390,7 +1391,6 @@ static int graph_prepare(af_ctx *c, const float lo[3], const float hi[3], int64_
   HIP_TRY(c, clear_sticky(c));
   c->sticky_reset = false;
   for (int32_t i = 0; i < n_tools; ++i) c->g_ids[i] = tool_ids[i];
-  c->g_n = n_tools;
   c->g_score = score;
   if (c->win_on && !c->win_set) {
     // the window (and so the grid) is placed by the first frame, which runs
@@ -1400,15 +1400,18 @@ static int graph_prepare(af_ctx *c, const float lo[3], const float hi[3], int64_
     c->gexec = nullptr;
     c->graph = nullptr;
     c->graph_stale = false;
+    c->g_n = n_tools;
     return AF_OK;
   }
-  return graph_record(c, s);
+  c->g_n = n_tools;
+  if ((rc = graph_record(c, s)) != AF_OK) c->g_n = 0;
+  return rc;
 }
 
 int af_graph_frame(af_ctx *c, const float *xyz, int64_t n, const float origin[3],
                    int64_t frame_id, void *stream) {
   if (!c) return AF_EINVAL;
-  if (!c->g_n) return fail(c, AF_EINVAL, "no recorded frame graph");
+  if (!c->g_n || (!c->gexec && !c->win_on)) return fail(c, AF_EINVAL, "no recorded frame graph");
   if (c->graph_stale && !c->win_on)
     return fail(c, AF_EINVAL, "buffers of the recorded frame graph were reallocated: prepare again");
   if (n < 0 || n > c->slot_cap || (n > 0 && !xyz) || !origin)

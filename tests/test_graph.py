@@ -172,3 +172,7 @@ def test_graph_argument_errors(synth_mod):
     with pytest.raises(AFError):
         ctx.graph_frame(x[:100].contiguous(), f.origin, f.frame_id)   # id not increasing
     ctx.graph_sync()
+    with pytest.raises(AFError):
+        ctx.graph_prepare([0, 0, 0], [1, 1, 1], 100, [0, 0])      # a failed prepare ...
+    with pytest.raises(AFError):
+        ctx.graph_frame(x[:100].contiguous(), f.origin, f.frame_id + 1)   # ... leaves no graph
