@@ -422,7 +422,9 @@ def run_serve(args):
     frames) arrive at 10 Hz from each stream's phase, and the latency of each
     frame runs from its arrival to its labels on the host.  The main server
     keeps the library's batching rule (one scoring launch per step of 5 or
-    more streams)."""
+    more streams).  With --serve-incremental B every context (served and
+    sequential) runs the incremental mode with a budget of B evaluations per
+    frame, and labels are the incremental mode's."""
     import torch
     import synth
     from paper_2608_06412_amd import AFError, Context, Server, default_config
@@ -432,6 +434,17 @@ def run_serve(args):
     L = args.latency_frames if args.latency_frames != 600 else 150
     n = W + K + L
     NS = args.serve_streams
+    INC = args.serve_incremental
+
+    def frame_on(c, x, f):
+        if INC:
+            c.incremental_frame(x, f.origin, f.frame_id)
+        else:
+            c.integrate_frame(x, f.origin, f.frame_id)
+            c.score_points(0)
+
+    def read_out(c):
+        return c.read_incremental(labels_only=True) if INC else c.read_labels(0)
     specs = synth.serving(n_streams=NS, n_frames=n)
     t = time.perf_counter()
     frames = [sp.workload.frames(n) for sp in specs]
@@ -463,6 +476,8 @@ def run_serve(args):
             w = sp.workload
             allx = np.concatenate([f.xyz for f in frames[s]])
             srv.context(sids[s]).set_tool_kernels(0, w.tool, w.rot)
+            if INC:
+                srv.context(sids[s]).incremental_enable(0, INC)
             srv.prepare(sids[s], allx.min(0) - 1.0, allx.max(0) + 1.0,
                         max(len(f.xyz) for f in frames[s]), [0])
         return srv, sids, refused
@@ -479,6 +494,8 @@ def run_serve(args):
         w = sp.workload
         c = Context(cfg(0))
         c.set_tool_kernels(0, w.tool, w.rot)
+        if INC:
+            c.incremental_enable(0, INC)
         seq.append(c)
     resident = [[torch.from_numpy(f.xyz).cuda() for f in fr[:W + K]] for fr in frames]
 
@@ -499,8 +516,7 @@ def run_serve(args):
         for k in range(lo, hi):
             for s, c in enumerate(seq):
                 f = frames[s][k]
-                c.integrate_frame(resident[s][k], f.origin, f.frame_id)
-                c.score_points(0)
+                frame_on(c, resident[s][k], f)
                 tests += c.score_stats(0)["canonical_tests"]
         return tests
     serve_frames(0, W)
@@ -524,6 +540,10 @@ def run_serve(args):
     wall_seq = time.perf_counter() - t0
 
     def same_as_seq(server, ids):
+        if INC:
+            return all(np.array_equal(server.context(sid).read_incremental()[k],
+                                      seq[s].read_incremental()[k])
+                       for s, sid in enumerate(ids) for k in ("label", "best", "best_dir", "a"))
         return all(np.array_equal(server.context(sid).read_labels(0)["label"],
                                   seq[s].read_labels(0)["label"]) and
                    np.array_equal(server.context(sid).read_labels(0)["first_free"],
@@ -574,7 +594,7 @@ def run_serve(args):
             if st != 0:
                 raise RuntimeError("stream %d frame %d: %s" % (sid, fid, srv.last_error()))
             s = sids.index(sid)
-            srv.context(sid).read_labels(0)
+            read_out(srv.context(sid))
             j = next(j for j, q in enumerate(queue) if q[0] == s and q[1] == fid)
             done.append(queue.pop(j)[2])
         return done
@@ -594,16 +614,15 @@ def run_serve(args):
         a, s, k = waiting.pop(0)
         f = frames[s][k]
         x = pinned[(s, k)].cuda(non_blocking=True)
-        seq[s].integrate_frame(x, f.origin, f.frame_id)
-        seq[s].score_points(0)
-        seq[s].read_labels(0)
+        frame_on(seq[s], x, f)
+        read_out(seq[s])
         return [a]
     lat_seq = paced(seq_step)
-    same_end = all(np.array_equal(srv.context(sid).read_labels(0)["label"],
-                                  seq[s].read_labels(0)["label"]) for s, sid in enumerate(sids))
+    same_end = same_as_seq(srv, sids)
     pct = lambda v, q: float(np.percentile(v, q))
     out = {
-        "metric": "frame latency p50/p99 and throughput, %d concurrent streams at 10 Hz" % NS,
+        "metric": "frame latency p50/p99 and throughput, %d concurrent streams at 10 Hz" % NS
+                  + (", incremental mode" if INC else ""),
         "value": pct(lat_srv, 99),
         "unit": "ms (p99 frame latency, arrival to labels on the host)",
         "n_gpus": 1, "steps": K, "warmup": W,
@@ -615,6 +634,7 @@ def run_serve(args):
                                "10 Hz, TSDF capacity %.2g voxels per stream"
                                % (NS, 390625 * per * 512),
                    "frames_per_stream": {"warmup": W, "throughput": K, "paced": L},
+                   "incremental_budget": INC,
                    "map_points_end": [int(srv.context(i).num_points()) for i in sids]},
         "admission": {"budget_bytes": 24 * GiB, "per_stream_bytes": stream_budget,
                       "admitted": len(sids),
@@ -626,9 +646,10 @@ def run_serve(args):
                                   "max": float(lat_seq.max())},
         "throughput": {"frames_per_s": NS * K / wall_srv, "returns_per_s": returns / wall_srv,
                        "tests_per_s": tests_srv / wall_srv,
-                       "mode": "one scoring launch per step when %d or more streams took a "
-                               "frame (here: %s), else one per stream" % (
-                                   5, "every step" if NS >= 5 else "never"),
+                       "mode": ("incremental frames, each on its own stream" if INC else
+                                "one scoring launch per step when %d or more streams took a "
+                                "frame (here: %s), else one per stream" % (
+                                    5, "every step" if NS >= 5 else "never")),
                        "always_batched_frames_per_s": NS * K / wall_b,
                        "never_batched_frames_per_s": NS * K / wall_o,
                        "sequential_frames_per_s": NS * K / wall_seq,
@@ -963,6 +984,8 @@ def main():
                          "the library's default configuration")
     ap.add_argument("--serve-streams", type=int, default=4,
                     help="streams of the serve workload (the 24 GiB budget is shared)")
+    ap.add_argument("--serve-incremental", type=int, default=0,
+                    help="serve workload in the incremental mode with this budget (0: stateless)")
     ap.add_argument("--window-m", type=float, default=10.0,
                     help="window size per axis (metres) of the window workload")
     ap.add_argument("--window-graph", action="store_true",

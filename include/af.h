@@ -480,7 +480,8 @@ int af_smooth_eval_static(af_ctx *ctx, const float *p, const float *q, int64_t n
  * AF_NO_CANDIDATE; AF_UNSCORED before the first evaluation.
  *
  * af_incremental_enable: tool `tool_id` (K <= 1024, reach <= 255 voxels),
- * budget >= 1; before the context's first frame (AF_EINVAL otherwise).
+ * budget >= 1; before the context's first frame and before any frame graph
+ * is prepared (AF_EINVAL otherwise).
  * Allocates the state (23 B per point of capacity) and a changed-voxel list
  * (4 B per voxel of block capacity).  af_incremental_frame integrates one
  * frame as af_integrate_frame does, then runs the steps above; it
@@ -555,7 +556,13 @@ int af_read_incremental(af_ctx *ctx, int64_t first, int64_t count, int64_t *key,
  * or a frame id that does not increase.  af_server_pending gives the queue
  * length (-1 for a bad id).  A stream whose context has a sliding window
  * (af_set_window on af_server_context, before af_server_prepare) records its
- * scoring in its own graph and is never batched; lo/hi are then unused.
+ * scoring in its own graph and is never batched; lo/hi are then unused.  A
+ * stream whose context is in the incremental mode (af_incremental_enable,
+ * before af_server_prepare) records no graph: af_server_prepare allocates a
+ * device slot of max_returns returns (lo, hi and tool_ids unused), and each
+ * step runs af_incremental_frame on the stream's HIP stream (it synchronises
+ * that stream once, after block allocation, so such frames overlap the other
+ * streams' work but not each other's first half).
  *
  * af_server_step takes the oldest queued frame of every stream (streams
  * visited round robin), launches each (host-to-device copy, then the recorded

@@ -1254,6 +1254,20 @@ int ctx_score_jobs(af_ctx *c, const int32_t *tool_ids, int32_t n_tools, ScoreJob
 
 bool ctx_windowed(const af_ctx *c) { return c && c->win_on; }
 
+bool ctx_incremental(const af_ctx *c) { return c && c->incr_on; }
+
+int ctx_frame_slot(af_ctx *c, int64_t max_returns) {
+  if (!c || max_returns < 1) return AF_EINVAL;
+  if (c->slot_xyz && c->slot_cap >= max_returns) return AF_OK;
+  HIP_TRY(c, hipDeviceSynchronize());
+  if (c->slot_xyz) dev_free(c, c->slot_xyz, sizeof(float) * 3 * c->slot_cap);
+  c->slot_xyz = nullptr;
+  c->slot_cap = 0;
+  ALLOC(c, c->slot_xyz, 3 * max_returns);
+  c->slot_cap = max_returns;
+  return AF_OK;
+}
+
 // A recorded (unscored) frame scored on its own stream: the launch a scored
 // graph ends with (a server step that batches fewer than two streams).
 int ctx_score_stream(af_ctx *c, const int32_t *tool_ids, int32_t n_tools, void *stream) {
@@ -1674,6 +1688,7 @@ int af_incremental_enable(af_ctx *c, int32_t tool_id, int32_t budget) {
   if (c->p.n_c > 255) return fail(c, AF_EINVAL, "n_c above 255");
   if (c->last_frame >= 0 || c->n_points > 0)
     return fail(c, AF_EINVAL, "the incremental mode starts before the first frame");
+  if (c->g_n) return fail(c, AF_EINVAL, "a context with a recorded frame graph runs stateless frames");
   if (!score_variant_takes_list(score_variant_default(), t))
     return fail(c, AF_EINVAL, "tool %d: K above 1024 or reach above 255 voxels", tool_id);
   budget = (int32_t)std::min<int64_t>(budget, c->cfg.max_points);

@@ -486,6 +486,11 @@ int ctx_score_stream(af_ctx *c, const int32_t *tool_ids, int32_t n_tools, void *
 // A context with a sliding window (its frames are scored inside its own graph,
 // over the window's point list, so the server does not batch it).
 bool ctx_windowed(const af_ctx *c);
+// A context in the incremental mode (its frames run af_incremental_frame,
+// eagerly, from a device slot of max_returns returns that ctx_frame_slot
+// allocates; af_graph_slot returns it).
+bool ctx_incremental(const af_ctx *c);
+int ctx_frame_slot(af_ctx *c, int64_t max_returns);
 int score_variants();
 int score_variant_default();
 // whether the configuration (after its fallbacks for this tool) honours PointsDev::sel

@@ -15,6 +15,11 @@
 // GPU overlaps them.  Without batching each stream's graph also holds its
 // own scoring launch.
 //
+// A stream whose context is in the incremental mode (Section 3.5) records
+// no graph: its frames run af_incremental_frame on its own HIP stream, and a
+// stream with a sliding window records its scoring inside its own graph;
+// neither takes part in the batched scoring launch.
+//
 // Admission reserves the stream's declared device budget (af_config.
 // hbm_budget) against the server's budget.  A context never allocates beyond
 // its own budget, so the streams together never exceed the server's.
@@ -51,6 +56,7 @@ struct Served {
   hipEvent_t done = nullptr;   // the stream's integration of this step (batched mode)
   std::vector<int32_t> tools;  // tools its frames are scored for
   bool batched = false;        // graph recorded without scoring
+  bool incremental = false;    // frames run af_incremental_frame (no graph)
   int64_t reserved = 0;
   int64_t max_returns = 0;   // 0 until the frame graph is recorded
   int64_t last_id = -1;      // last frame id queued
@@ -217,17 +223,21 @@ int af_server_prepare(af_server *s, int32_t id, const float lo[3], const float h
   hipStreamSynchronize(t->hs);
   free_slots(*t);
   t->max_returns = 0;
-  const bool batched = s->batch_min > 0 && !af::ctx_windowed(t->ctx);
+  const bool incremental = af::ctx_incremental(t->ctx);
+  const bool batched = s->batch_min > 0 && !af::ctx_windowed(t->ctx) && !incremental;
   if (batched) {
     const int rc = batch_resources(s);
     if (rc != AF_OK) return rc;
   }
-  int rc = batched ? af::ctx_graph_prepare_unscored(t->ctx, lo, hi, max_returns, tool_ids,
-                                                     n_tools, t->hs)
-                    : af_graph_prepare(t->ctx, lo, hi, max_returns, tool_ids, n_tools, t->hs);
+  int rc = incremental ? af::ctx_frame_slot(t->ctx, max_returns)
+           : batched   ? af::ctx_graph_prepare_unscored(t->ctx, lo, hi, max_returns, tool_ids,
+                                                        n_tools, t->hs)
+                       : af_graph_prepare(t->ctx, lo, hi, max_returns, tool_ids, n_tools, t->hs);
   if (rc != AF_OK) return sfail(s, rc, "stream %d: %s", id, af_last_error(t->ctx));
-  t->tools.assign(tool_ids, tool_ids + n_tools);
+  if (incremental) t->tools.clear();
+  else t->tools.assign(tool_ids, tool_ids + n_tools);
   t->batched = batched;
+  t->incremental = incremental;
   for (int i = 0; i < kQueueSlots; ++i) {
     float *p = nullptr;
     if (hipHostMalloc((void **)&p, sizeof(float) * 3 * max_returns) != hipSuccess) {
@@ -292,7 +302,9 @@ int af_server_step(af_server *s, int32_t *stream_ids, int64_t *frame_ids, int32_
     if (f.n > 0 && hipMemcpyAsync(dev, f.host, sizeof(float) * 3 * f.n, hipMemcpyHostToDevice,
                                   t.hs) != hipSuccess)
       rc = AF_EDEVICE;
-    if (rc == AF_OK) rc = af_graph_frame(t.ctx, dev, f.n, f.origin, f.frame_id, t.hs);
+    if (rc == AF_OK)
+      rc = t.incremental ? af_incremental_frame(t.ctx, dev, f.n, f.origin, f.frame_id, t.hs)
+                         : af_graph_frame(t.ctx, dev, f.n, f.origin, f.frame_id, t.hs);
     run.push_back({id, rc});
   }
   s->rr = (s->rr + 1) % ns;
