@@ -504,7 +504,9 @@ class Context:
     def graph_prepare(self, lo, hi, max_returns: int, tool_ids, stream=None):
         """Record one frame (integration of up to max_returns returns, then
         scoring of tool_ids in one launch) as a HIP graph; the brick grid
-        covers the scene box [lo, hi] (metres)."""
+        covers the scene box [lo, hi] (metres).  With a sliding window the
+        grid is the window's (lo and hi are checked but not used) and a frame
+        that moves the window runs eagerly and records the graph again."""
         lo = np.ascontiguousarray(lo, dtype=np.float32).reshape(3)
         hi = np.ascontiguousarray(hi, dtype=np.float32).reshape(3)
         ids = (ctypes.c_int32 * len(tool_ids))(*[int(x) for x in tool_ids])
@@ -731,6 +733,9 @@ class Server:
         return int(self._lib.af_server_hip_stream(self.h, int(sid)) or 0)
 
     def prepare(self, sid: int, lo, hi, max_returns: int, tool_ids):
+        """Record the stream's frame graph (see Context.graph_prepare); a
+        context in the incremental mode records none and takes a device slot
+        of max_returns returns instead."""
         lo = np.ascontiguousarray(lo, dtype=np.float32).reshape(3)
         hi = np.ascontiguousarray(hi, dtype=np.float32).reshape(3)
         ids = (ctypes.c_int32 * len(tool_ids))(*[int(x) for x in tool_ids])
