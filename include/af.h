@@ -392,9 +392,10 @@ int af_tune_score(af_ctx *ctx, int32_t tool_id, int32_t reps, void *stream, int3
  * points inside the window and scores them tool by tool (as af_score_points
  * does with a window); tools must suit af_score_points with a window.  A
  * frame that places or moves the window (a host-side test on its origin)
- * runs eagerly instead -- af_integrate_frame, then af_score_points for each
- * tool -- and records the graph again for the new window (it synchronises
- * `stream`); so does a frame after a reallocation, instead of AF_EINVAL.
+ * runs eagerly instead -- af_integrate_frame, then af_score_tools over the
+ * prepared tools -- and records the graph again for the new window (it
+ * synchronises `stream`); a frame after a reallocation records the graph
+ * again and replays it, instead of AF_EINVAL.
  * Labels, first free orientations, statistics and the map then equal those
  * of af_integrate_frame followed by af_score_points for each tool.  Before
  * the first frame the graph is recorded by that frame. */
