@@ -163,10 +163,12 @@ def test_window_graph_arguments(synth_mod):
 
 
 @pytest.mark.parametrize("batch", [True, False])
-def test_served_windowed_streams(synth_mod, batch):
+def test_served_windowed_streams(synth_mod, oracle_mod, batch):
     """Two windowed walk streams (windows of 20^3 and 10 x 10 x 20 blocks) and
     the tiny scene without a window served together: every stream equals its
-    eager context after every step."""
+    eager context after every step, and after the last step the first stream's
+    labels of the points inside its window equal the oracle's (fed the same
+    frames with the same window)."""
     import torch
     from paper_2608_06412_amd import Context, Server, default_config
     w = synth_mod.window_walk()
@@ -227,3 +229,10 @@ def test_served_windowed_streams(synth_mod, batch):
                 assert ctx.window_state()[2] == refs[s].window_state()[2], (step, s)
     for s in (0, 1):
         assert srv.context(sids[s]).window_state()[2] >= 2
+    orc = oracle_mod.Oracle(voxel=w.voxel, trunc=w.trunc, r_c=w.r_c)
+    orc.set_window(list(specs[0]))
+    for i, (tl, r) in enumerate(zip(tools, rots)):
+        orc.set_tool(i, tl, r)
+    for f in walk:
+        orc.integrate_frame(f.xyz, f.origin, f.frame_id)
+    _inside_equal_oracle(srv.context(sids[0]), orc, rots, "served")
