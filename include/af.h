@@ -380,7 +380,8 @@ int af_tune_score(af_ctx *ctx, int32_t tool_id, int32_t reps, void *stream, int3
  * since the last settlement overflowed the hash table, block or point
  * capacity, or mapped a block outside the recorded scene box (those frames'
  * results are then incomplete).  Every other call of this interface settles
- * first, so eager calls and replays may be mixed on one stream.  A call that
+ * first, so eager calls and replays may be mixed on one stream (a replay on
+ * another stream than the previous one settles that one first).  A call that
  * reallocates a buffer the graph holds (a frame larger than the scratch
  * capacity, grid growth, af_set_tool_kernels) makes af_graph_frame return
  * AF_EINVAL until af_graph_prepare is called again.  Labels, first free

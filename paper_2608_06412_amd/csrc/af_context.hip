@@ -1441,6 +1441,11 @@ int af_graph_frame(af_ctx *c, const float *xyz, int64_t n, const float origin[3]
     *qq[a] = (int)llrint(t);
   }
   hipStream_t s = (hipStream_t)stream;
+  // a replay still running on another stream reads the slot: let it finish
+  if (c->graph_dirty && s != c->last_stream) {
+    const int rc = graph_settle(c);
+    if (rc != AF_OK) return rc;
+  }
   if (n > 0 && xyz != c->slot_xyz)
     HIP_TRY(c, hipMemcpyAsync(c->slot_xyz, xyz, sizeof(float) * 3 * n, hipMemcpyDefault, s));
   int3 wlo = make_int3(-(1 << 30), -(1 << 30), -(1 << 30));
