@@ -6,7 +6,8 @@ by af_score_tools does, frame by frame.  Replays take frames of varying size,
 with eager work, host reads and synchronisations between them, and one frame
 in the middle goes through the eager calls on the same context.  After frame 3
 and the last frame, every tool's labels, first free orientations and canonical
-counts of the recorded context also equal the oracle's.  A frame that
+counts of the recorded context also equal the oracle's.  Replays alternating
+between two streams end with the same results.  A frame that
 maps a block beyond the recorded scene box is reported, and the context then
 continues eagerly to the same result.  Tiny scene (v = 2 cm), four tools of
 the batching workload."""
@@ -123,6 +124,30 @@ def test_replays_equal_eager(synth_mod, oracle_mod):
         orc.integrate_frame(f.xyz[:n], f.origin, f.frame_id)
         if j in (3, len(frames) - 1):
             _same_as_oracle(rec, orc, rots, j)
+    _same_map(eager, rec)
+
+
+def test_replays_on_alternating_streams(synth_mod):
+    """Replays issued on two streams in turn, with no synchronisation between
+    frames (each replay first copies its returns into the context's one frame
+    slot): the map, points, labels and statistics at the end equal the eager
+    calls'."""
+    import torch
+    w, frames, sizes, make = _setup(synth_mod)
+    eager, rec = make(), make()
+    allx = np.concatenate([f.xyz for f in frames])
+    rec.graph_prepare(allx.min(0) - 0.5, allx.max(0) + 0.5, max(sizes), IDS)
+    xs = [torch.from_numpy(np.ascontiguousarray(f.xyz[:n])).cuda() for f, n in zip(frames, sizes)]
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    for j, (f, x) in enumerate(zip(frames, xs)):
+        print("alternating-stream frame", j, flush=True)
+        rec.graph_frame(x, f.origin, f.frame_id, stream=streams[j % 2])
+    rec.graph_sync()
+    for f, x in zip(frames, xs):
+        eager.integrate_frame(x, f.origin, f.frame_id)
+    eager.score_tools(IDS)
+    _same_scores(eager, rec, "alternating streams")
     _same_map(eager, rec)
 
 
