@@ -421,8 +421,8 @@ def run_serve(args):
     launch and that never do; W+K..W+K+L-1 (default 150 per stream, 600
     frames) arrive at 10 Hz from each stream's phase, and the latency of each
     frame runs from its arrival to its labels on the host.  The main server
-    keeps the library's batching rule (one scoring launch per step of 5 or
-    more streams).  With --serve-incremental B every context (served and
+    keeps the library's default (each stream scored on its own stream, no
+    cross-stream launch).  With --serve-incremental B every context (served and
     sequential) runs the incremental mode with a budget of B evaluations per
     frame, and labels are the incremental mode's."""
     import torch
@@ -482,10 +482,9 @@ def run_serve(args):
                         max(len(f.xyz) for f in frames[s]), [0])
         return srv, sids, refused
 
-    # the server with the library's batching rule (one scoring launch for
-    # steps of 5 or more streams, else one per stream), the server that
-    # batches every step, the one that never does, and the plain sequential
-    # path
+    # the server with the library's default (each stream scored on its own
+    # stream), the server that batches every step, the one that never does
+    # (explicitly), and the plain sequential path
     srv, sids, refused = make_server(None)
     srv_b, sids_b, _ = make_server(True)
     srv_o, sids_o, _ = make_server(False)
@@ -647,9 +646,7 @@ def run_serve(args):
         "throughput": {"frames_per_s": NS * K / wall_srv, "returns_per_s": returns / wall_srv,
                        "tests_per_s": tests_srv / wall_srv,
                        "mode": ("incremental frames, each on its own stream" if INC else
-                                "one scoring launch per step when %d or more streams took a "
-                                "frame (here: %s), else one per stream" % (
-                                    5, "every step" if NS >= 5 else "never")),
+                                "the library default: each stream scored on its own stream"),
                        "always_batched_frames_per_s": NS * K / wall_b,
                        "never_batched_frames_per_s": NS * K / wall_o,
                        "sequential_frames_per_s": NS * K / wall_seq,

@@ -578,20 +578,21 @@ int af_read_incremental(af_ctx *ctx, int64_t first, int64_t count, int64_t *key,
  * server. */
 typedef struct af_server af_server;
 int af_server_create(int64_t hbm_budget, int32_t max_streams, af_server **out);
-/* Batching of the serving workload's "frames from all streams batched into
- * one integrate+score step": with min_streams >= 2, each stream's recorded
- * graph holds its integration, normals and candidate masks, and a step in
- * which at least min_streams streams took a frame scores the points of all
- * of them in ONE persistent launch (each point against its own map and
- * tools; at most 64 stream-tool pairs per launch, further streams are
- * scored on their own streams; more than 64 KiB of table offsets fails the
- * frames with AF_EDEVICE); a step with fewer streams scores each on its own
- * stream.  min_streams = 0: never batch (each graph holds its own scoring
- * launch); 1 means 2.  Default 5, one more than the HIP runtime's default of
- * 4 hardware queues per process: up to 4 streams already run side by side
- * on their own queues, and one launch for them only adds a wait for the
- * slowest stream's masks.  Labels and counts are the same in every mode.
- * Set before any stream is prepared (AF_EINVAL otherwise, or for
+/* Scoring the frames of all streams of a step in one launch: with
+ * min_streams >= 2, each stream's recorded graph holds its integration,
+ * normals and candidate masks, and a step in which at least min_streams
+ * streams took a frame scores the points of all of them in ONE persistent
+ * launch (each point against its own map and tools; at most 64 stream-tool
+ * pairs per launch, further streams are scored on their own streams; more
+ * than 64 KiB of table offsets fails the frames with AF_EDEVICE); a step
+ * with fewer streams scores each on its own stream.  min_streams = 0: never
+ * batch (each graph holds its own scoring launch, with the single-tool
+ * kernel when the stream has one tool); 1 means 2.  Default 0: per-stream
+ * launches run side by side on the runtime's hardware queues, and a stream
+ * with one tool then scores with the single-tool kernel, which the
+ * cross-stream launch cannot match; one launch also waits for the slowest
+ * stream's masks.  Labels and counts are the same in every mode.  Set
+ * before any stream is prepared (AF_EINVAL otherwise, or for
  * min_streams < 0). */
 int af_server_batch(af_server *srv, int32_t min_streams);
 int af_server_destroy(af_server *srv);

@@ -677,9 +677,9 @@ class Server:
     stream, and a step that runs the oldest queued frame of every stream."""
 
     def __init__(self, hbm_budget: int, max_streams: int = 4, batch=None):
-        """batch: None keeps the library's rule (one scoring launch for steps
-        of 5 or more streams), True batches every step of 2 or more, False
-        never, an int sets the minimum number of streams (af_server_batch)."""
+        """batch: None keeps the library's default (no cross-stream scoring
+        launch), True batches every step of 2 or more streams, False never,
+        an int sets the minimum number of streams (af_server_batch)."""
         self._lib = lib()
         h = ctypes.c_void_p()
         rc = self._lib.af_server_create(int(hbm_budget), int(max_streams), ctypes.byref(h))

@@ -1161,7 +1161,10 @@ int af_score_tools(af_ctx *c, const int32_t *tool_ids, int32_t n_tools, void *st
   for (int32_t i = 0; i < n_tools; ++i)
     launch_mask(c->p, c->pts, host[i], c->grid, c->n_points, s);
   hipEvent_t t3 = timing_mark(c, s);
-  launch_score_multi(c->p, c->pts, c->tools_dev, host, set, c->grid, c->n_points, c->work, s);
+  if (n_tools == 1)   // one tool: the single-tool kernel (same results)
+    launch_score(c->p, c->pts, host[0], c->grid, c->n_points, c->score_variant, c->work, s);
+  else
+    launch_score_multi(c->p, c->pts, c->tools_dev, host, set, c->grid, c->n_points, c->work, s);
   hipEvent_t t4 = timing_mark(c, s);
   if (c->timing) {
     timing_pair(c, ST_SCORE, t0, t4);
@@ -1276,8 +1279,12 @@ int ctx_score_stream(af_ctx *c, const int32_t *tool_ids, int32_t n_tools, void *
   ToolDev host[kMultiTools];
   const int rc = make_toolset(c, tool_ids, n_tools, set, host);
   if (rc != AF_OK) return rc;
-  launch_score_multi(c->p, c->pts, c->tools_dev, host, set, c->grid, c->cfg.max_points, c->work,
-                     (hipStream_t)stream, true);
+  if (n_tools == 1)   // one tool: the single-tool kernel (same results)
+    launch_score(c->p, c->pts, host[0], c->grid, c->cfg.max_points, c->score_variant, c->work,
+                 (hipStream_t)stream, true);
+  else
+    launch_score_multi(c->p, c->pts, c->tools_dev, host, set, c->grid, c->cfg.max_points,
+                       c->work, (hipStream_t)stream, true);
   return hip_check(c, "score on the stream");
 }
 }  // namespace af
@@ -1334,8 +1341,12 @@ static int graph_record(af_ctx *c, hipStream_t s) {
     launch_normals(c->p, c->map, c->pts, c->grid, NP, cs, true);
     for (int32_t i = 0; i < n_tools; ++i)
       launch_mask(c->p, c->pts, host[i], c->grid, NP, cs, true);
-    if (c->g_score)
-      launch_score_multi(c->p, c->pts, c->tools_dev, host, set, c->grid, NP, c->work, cs, true);
+    if (c->g_score) {
+      if (n_tools == 1)   // one tool: the single-tool kernel (same results)
+        launch_score(c->p, c->pts, host[0], c->grid, NP, c->score_variant, c->work, cs, true);
+      else
+        launch_score_multi(c->p, c->pts, c->tools_dev, host, set, c->grid, NP, c->work, cs, true);
+    }
   } else {
     const int3 lo = make_int3(c->win_lo[0], c->win_lo[1], c->win_lo[2]);
     const int3 hi = make_int3(c->win_hi[0], c->win_hi[1], c->win_hi[2]);

@@ -7,13 +7,13 @@
 // (integration followed by scoring of the stream's tools) and a small queue
 // of pinned host slots that hold frames as they arrive.  One step takes the
 // oldest queued frame of every stream and launches each stream's recorded
-// integration (with its normals and candidate masks) on its own HIP stream;
-// when enough streams took a frame (more than the runtime's hardware queues,
-// by default), one scoring launch then labels the points of all of them,
-// each against its own map and tools, after which every stream reads its
-// counts back; fewer streams are scored each on its own stream, where the
-// GPU overlaps them.  Without batching each stream's graph also holds its
-// own scoring launch.
+// frame on its own HIP stream, where the GPU overlaps them.  In batched mode
+// (af_server_batch) the graphs stop after the candidate masks, and when
+// enough streams took a frame one scoring launch labels the points of all
+// of them, each against its own map and tools, after which every stream
+// reads its counts back; fewer streams are scored each on its own stream.
+// Otherwise (the default) each stream's graph also holds its own scoring
+// launch.
 //
 // A stream whose context is in the incremental mode (Section 3.5) records
 // no graph: its frames run af_incremental_frame on its own HIP stream, and a
@@ -72,7 +72,7 @@ struct af_server {
   int64_t reserved = 0;
   int32_t rr = 0;   // stream visited first by the next step (round robin)
   std::vector<Served> streams;
-  int32_t batch_min = 5;         // streams in a step that get one scoring launch (0: never)
+  int32_t batch_min = 0;         // streams in a step that get one scoring launch (0: never)
   hipStream_t bs = nullptr;      // the batched scoring launch's stream
   hipEvent_t scored = nullptr;   // recorded after it
   af::ScoreJob *jobs_host = nullptr;   // pinned, kMaxJobs

@@ -58,10 +58,11 @@ def _same_as_oracle(ctx, orc, K, where):
         assert sg[k] == so[k], (where, k)
 
 
-# True: one scoring launch for every step of two streams; None: the default
-# rule (two streams are below it, so each is scored on its own stream after
-# its unscored graph); False: each graph holds its own scoring launch
-@pytest.mark.parametrize("batch", [True, None, False])
+# True: one scoring launch for every step of two streams; 3: batched graphs
+# with a threshold above two streams, so each is scored on its own stream
+# after its unscored graph; None (the default) and False: each graph holds
+# its own scoring launch
+@pytest.mark.parametrize("batch", [True, 3, None, False])
 def test_two_streams_equal_their_eager_contexts(synth_mod, oracle_mod, batch):
     import torch
     from paper_2608_06412_amd import AFError, Context, Server
