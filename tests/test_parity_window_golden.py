@@ -11,7 +11,12 @@ count, the whole TSDF, every point record, every point's label and first free
 orientation, the normals and candidate masks of the confident points inside
 the window, the label counts and the canonical statistics, compared through
 SHA-256 digests of the full arrays, plus 400 seeded points element by
-element."""
+element.
+
+The same 600 frames through recorded frames (af_graph_frame, scoring every
+frame) must give the same window, TSDF, point records, in-window normals,
+masks and statistics at each checkpoint (labels outside the window then come
+from later scorings, so the whole-map label digests are not compared)."""
 import json
 import os
 import sys
@@ -107,6 +112,66 @@ def test_whole_map(gpu_states, frames, what):
 @pytest.mark.parametrize("frames", [100, 300, 600])
 def test_statistics(gpu_states, frames):
     want, got = gpu_states
+    for k in ("n_confident", "n_accessible", "n_blocked", "n_no_candidate",
+              "candidate_tests", "canonical_tests", "canonical_lookups"):
+        assert got[frames]["score_stats"][k] == want[frames]["score_stats"][k], k
+
+
+@pytest.fixture(scope="module")
+def gpu_states_recorded(synth_mod, golden):
+    import torch
+    from digest import inside_window, masks_digest, normals_digest, points_digest, tsdf_digest
+    from paper_2608_06412_amd import Context, default_config
+    w = synth_mod.tree()
+    frames = w.frames(600)
+    cfg = default_config(w.voxel, w.trunc, r_c=w.r_c, max_blocks=1 << 17, max_points=1 << 22,
+                         max_orientations=len(w.rot), max_tools=1)
+    ctx = Context(cfg)
+    ctx.set_window([golden["blocks"]] * 3)
+    ctx.set_tool_kernels(0, w.tool, w.rot)
+    ctx.graph_prepare([-1.0] * 3, [1.0] * 3, max(len(f.xyz) for f in frames), [0])
+    want = {cp["frames"]: cp for cp in golden["checkpoints"]}
+    out = {}
+    for i, f in enumerate(frames):
+        ctx.graph_frame(torch.from_numpy(f.xyz).cuda(), f.origin, f.frame_id)
+        if i + 1 not in want:
+            continue
+        ctx.graph_sync()
+        print("recorded checkpoint %d: %d points" % (i + 1, ctx.num_points()), flush=True)
+        key, S, W, clr = ctx.read_tsdf()
+        pts = ctx.read_points()
+        lab = ctx.read_labels(0)
+        dbg = ctx.read_point_debug(0)
+        lo, hi, shifts = ctx.window_state()
+        ins = inside_window(pts["key"], lo, hi)
+        out[i + 1] = {
+            "window": [[int(x) for x in lo], [int(x) for x in hi], int(shifts)],
+            "n_voxels": int(len(key)), "n_points": int(len(pts["key"])),
+            "n_inside": int(ins.sum()),
+            "tsdf_sha": tsdf_digest(key, S, W, clr),
+            "points_sha": points_digest(pts),
+            "normals_sha": normals_digest(lab["label"][ins], dbg["has_normal"][ins],
+                                          dbg["normal"][ins]),
+            "masks_sha": masks_digest(lab["label"][ins], dbg["mask"][ins]),
+            "score_stats": ctx.score_stats(0),
+        }
+    return want, out
+
+
+RECORDED_CHECKS = ["window", "n_voxels", "n_points", "n_inside", "tsdf_sha", "points_sha",
+                   "normals_sha", "masks_sha"]
+
+
+@pytest.mark.parametrize("frames", [100, 300, 600])
+@pytest.mark.parametrize("what", RECORDED_CHECKS)
+def test_recorded_whole_map(gpu_states_recorded, frames, what):
+    want, got = gpu_states_recorded
+    assert got[frames][what] == want[frames][what]
+
+
+@pytest.mark.parametrize("frames", [100, 300, 600])
+def test_recorded_statistics(gpu_states_recorded, frames):
+    want, got = gpu_states_recorded
     for k in ("n_confident", "n_accessible", "n_blocked", "n_no_candidate",
               "candidate_tests", "canonical_tests", "canonical_lookups"):
         assert got[frames]["score_stats"][k] == want[frames]["score_stats"][k], k
