@@ -725,6 +725,225 @@ k_mask(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t mw, int
               cand);
 }
 
+// The same candidate masks and arm-sample planes for K <= 64 MW orientations,
+// with the heads walked per lane: each lane first tests the normal cone of
+// every head (wave-uniform directions), then visits only its own heads inside
+// the cone, in any word, so the observation test and the arm samples run on
+// as many heads as the wave's busiest lane has in its cone (consecutive heads
+// of a direction set often share a band of the sphere, so one word can hold
+// all of one lane's cone and none of its neighbour's).  The heads' directions,
+// arm entries and runs are staged in LDS once per workgroup; each lane's
+// words collect there, and the carries across words (orientations before a
+// word's first head) are applied afterwards, in word order.
+template <int MW>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
+k_mask_walk(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n) {
+  // n < 0: the point count on the device (recorded graphs, point lists)
+  if (n < 0) n = pts.sel ? (int64_t)*pts.n_sel : (int64_t)*pts.n_points;
+  if ((int64_t)blockIdx.x * kThreads >= n) return;   // whole workgroup past the end
+  __shared__ double s_dir[3][64 * MW];
+  __shared__ uint2 s_arm[3][64 * MW];
+  __shared__ uint64_t s_run[64 * MW];
+  __shared__ uint64_t s_word[3][MW][kThreads];   // candidate word, plane 0, plane 1
+  for (int k = threadIdx.x; k < 64 * MW; k += kThreads) {
+    const int w = k >> 6, j = k & 63;
+    const int kend = t.K - 64 * w < 64 ? t.K - 64 * w : 64;
+    uint64_t run = 0ull;
+    if (j < kend) {
+      const uint64_t valid = kend == 64 ? ~0ull : ((1ull << kend) - 1ull);
+      const uint64_t heads = ~t.same[w] & valid;
+      const double *R = t.rot + 9 * (int64_t)k;
+      s_dir[0][k] = R[0];
+      s_dir[1][k] = R[3];
+      s_dir[2][k] = R[6];
+      const uint32_t b = t.begin[k];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) s_arm[a][k] = t.xent[b + a];
+      if ((heads >> j) & 1ull) {
+        const uint64_t above = j == 63 ? 0ull : heads & ~((2ull << j) - 1ull);
+        run = (above ? (above & (~above + 1ull)) - 1ull : valid) & ~((1ull << j) - 1ull);
+      }
+    }
+    s_run[k] = run;
+  }
+#pragma unroll
+  for (int w = 0; w < MW; ++w)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) s_word[c][w][threadIdx.x] = 0ull;
+  const int64_t jj = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const bool act = jj < n;
+  const int64_t i = pts.sel ? (act ? (int64_t)pts.sel[jj] : 0) : jj;
+  const int hn = act ? pts.has_normal[i] : -1;
+  double n0 = 0, n1 = 0, n2 = 0, nn = 0;
+  double wx[kMaxVp], wy[kMaxVp], wz[kMaxVp], ww[kMaxVp];
+  int nv = 0;
+  SwFrame f;
+  f.Bp = f.rp = 0u;
+  const SwGrid q = sw_grid(g);
+  if (hn >= 0) {
+    if (hn > 0) {
+      const int32_t *nvp = pts.normal + 3 * i;
+      n0 = (double)nvp[0];
+      n1 = (double)nvp[1];
+      n2 = (double)nvp[2];
+      nn = (double)((int64_t)nvp[0] * nvp[0] + (int64_t)nvp[1] * nvp[1] +
+                    (int64_t)nvp[2] * nvp[2]);
+    }
+    int32_t s[3];
+    unpack_key(pts.key[i], s[0], s[1], s[2]);
+    nv = pts.nvp[i];
+#pragma unroll
+    for (int j = 0; j < kMaxVp; ++j) {
+      if (j < nv) {
+        const int32_t *V = pts.vp + (i * kMaxVp + j) * 3;
+        int64_t a0 = (int64_t)V[0] - (256 * (int64_t)s[0] + 128);
+        int64_t a1 = (int64_t)V[1] - (256 * (int64_t)s[1] + 128);
+        int64_t a2 = (int64_t)V[2] - (256 * (int64_t)s[2] + 128);
+        wx[j] = (double)a0;
+        wy[j] = (double)a1;
+        wz[j] = (double)a2;
+        ww[j] = (double)(a0 * a0 + a1 * a1 + a2 * a2);
+      } else {
+        wx[j] = wy[j] = wz[j] = ww[j] = 0.0;
+      }
+    }
+    f = sw_frame(g, q, s);
+  } else {
+#pragma unroll
+    for (int j = 0; j < kMaxVp; ++j) wx[j] = wy[j] = wz[j] = ww[j] = 0.0;
+  }
+  // normal cone of every head
+  uint64_t cone[MW];
+#pragma unroll
+  for (int w = 0; w < MW; ++w) {
+    const int kend = t.K - 64 * w < 64 ? t.K - 64 * w : 64;
+    const uint64_t valid = kend == 64 ? ~0ull : ((1ull << kend) - 1ull);
+    const uint64_t heads = ~t.same[w] & valid;
+    cone[w] = hn == 0 ? heads : 0ull;
+    if (hn > 0) {
+      for (uint64_t rem = heads; rem; rem &= rem - 1ull) {
+        const int j = __ffsll((unsigned long long)rem) - 1;
+        const double *R = t.rot + 9 * (int64_t)(64 * w + j);
+        const double d0 = R[0], d1 = R[3], d2 = R[6];
+        const double dot = (n0 * d0 + n1 * d1) + n2 * d2;
+        if (dot >= 0.0 && dot * dot >= p.cos2 * nn) cone[w] |= 1ull << j;
+      }
+    }
+  }
+  __syncthreads();
+  // A head's arm-sample words are requested in its iteration and decoded in
+  // the next one, so their latency overlaps the next head's tests.
+  uint32_t pw[3] = {0u, 0u, 0u}, pb[3] = {0u, 0u, 0u};
+  uint64_t prun = 0ull;   // run of the head whose words are in flight (0: none)
+  int pword = 0;          // its word
+  auto settle = [&]() {
+    if (!prun) return;
+    const uint32_t r = ((pw[0] >> pb[0]) & 3u) ? 1u
+                       : ((pw[1] >> pb[1]) & 3u) ? 2u
+                       : ((pw[2] >> pb[2]) & 3u) ? 3u
+                                                 : 0u;
+    if (r & 1u) s_word[1][pword][threadIdx.x] |= prun;
+    if (r >> 1) s_word[2][pword][threadIdx.x] |= prun;
+  };
+  int cw = 0;
+  uint64_t rem = cone[0];
+  for (;;) {
+    // the lane's next head inside the cone, in word order
+    while (!rem && cw < MW - 1) {
+      ++cw;
+#pragma unroll
+      for (int u = 1; u < MW; ++u)
+        if (u == cw) rem = cone[u];
+    }
+    if (!__any(rem != 0ull)) break;
+    uint32_t cw3[3] = {0u, 0u, 0u}, cb[3] = {0u, 0u, 0u};
+    uint64_t run = 0ull;
+    if (rem) {
+      const int k = 64 * cw + __ffsll((unsigned long long)rem) - 1;
+      rem &= rem - 1ull;
+      const double d0 = s_dir[0][k], d1 = s_dir[1][k], d2 = s_dir[2][k];
+      bool seen = false;
+#pragma unroll
+      for (int v = 0; v < kMaxVp; ++v) {
+        if (v < nv && !seen) {
+          double wd = (wx[v] * d0 + wy[v] * d1) + wz[v] * d2;
+          seen = wd > 0.0 && wd * wd > p.obs2 * ww[v];
+        }
+      }
+      if (seen) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+          cw3[a] = __builtin_amdgcn_raw_buffer_load_b32(q.pred, code_sw_at(q, f, s_arm[a][k], cb[a]),
+                                                        0, 0);
+        run = s_run[k];
+        s_word[0][cw][threadIdx.x] |= run;
+      }
+    }
+    settle();   // the previous head's words, requested an iteration ago
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      pw[a] = cw3[a];
+      pb[a] = cb[a];
+    }
+    prun = run;
+    pword = cw;
+  }
+  settle();
+  // carries across words: orientations before a word's first head take the
+  // candidate bit and arm-sample result of the last head before them
+  unsigned long long cand = 0;
+  bool ok = false;
+  uint32_t nb = 0u;
+#pragma unroll
+  for (int w = 0; w < MW; ++w) {
+    const int kend = t.K - 64 * w < 64 ? t.K - 64 * w : 64;
+    const uint64_t valid = kend == 64 ? ~0ull : ((1ull << kend) - 1ull);
+    const uint64_t heads = ~t.same[w] & valid;
+    const uint64_t carry = heads ? ((heads & (~heads + 1ull)) - 1ull) : valid;
+    uint64_t word = s_word[0][w][threadIdx.x] | (ok ? carry : 0ull);
+    uint64_t pl0 = s_word[1][w][threadIdx.x] | ((nb & 1u) ? carry : 0ull);
+    uint64_t pl1 = s_word[2][w][threadIdx.x] | ((nb >> 1) ? carry : 0ull);
+    if (heads) {
+      const int jl = 63 - __clzll((long long)heads);   // the word's last head
+      ok = (word >> jl) & 1ull;
+      nb = (uint32_t)((pl0 >> jl) & 1ull) | ((uint32_t)((pl1 >> jl) & 1ull) << 1);
+    }
+    if (pts.sel) {
+      if (act) {
+        t.mask[i * MW + w] = word;
+        t.nearp[i * 2 * MW + w] = pl0;
+        t.nearp[i * 2 * MW + MW + w] = pl1;
+      }
+    } else {
+      s_word[0][w][threadIdx.x] = word;
+      s_word[1][w][threadIdx.x] = pl0;
+      s_word[2][w][threadIdx.x] = pl1;
+    }
+    cand += (unsigned long long)__popcll(word);
+  }
+  if (!pts.sel) {
+    // rows of consecutive points are contiguous: written out together
+    __syncthreads();
+    const int64_t i0 = (int64_t)blockIdx.x * kThreads;
+    const int np = n - i0 < kThreads ? (int)(n - i0) : kThreads;
+    for (int k = threadIdx.x; k < np * MW; k += kThreads)
+      t.mask[i0 * MW + k] = s_word[0][k % MW][k / MW];
+    for (int k = threadIdx.x; k < np * 2 * MW; k += kThreads) {
+      const int r = k / (2 * MW), c = k % (2 * MW);
+      t.nearp[i0 * 2 * MW + k] = c < MW ? s_word[1][c][r] : s_word[2][c - MW][r];
+    }
+  }
+  for (int off = 32; off >= 1; off >>= 1) {
+    unsigned lo = __shfl_xor((unsigned)(cand & 0xffffffffu), off);
+    unsigned hi = __shfl_xor((unsigned)(cand >> 32), off);
+    cand += ((unsigned long long)hi << 32) | lo;
+  }
+  if (lane_id() == 0 && cand)
+    atomicAdd(&t.counters->s[(blockIdx.x * kWaves + (threadIdx.x >> 6)) % kStatSlots]
+                   .candidate_tests,
+              cand);
+}
+
 // Position of the r-th (1-based) set bit of m, or 64.
 __device__ inline int nth_bit(uint64_t m, int r) {
   if (__popcll(m) < r) return 64;
@@ -1769,6 +1988,15 @@ void launch_mask(const Params &p, PointsDev pts, ToolDev t, GridDev g, int64_t n
                  hipStream_t s, bool dev_n) {
   int32_t mw = (t.K + 63) / 64;
   if (n <= 0) return;
+  const dim3 grid((unsigned)((n + kThreads - 1) / kThreads));
+  const int64_t nn = dev_n ? (int64_t)-1 : n;
+  switch (mw) {   // up to 256 orientations: heads walked per lane
+    case 1: hipLaunchKernelGGL(k_mask_walk<1>, grid, dim3(kThreads), 0, s, p, pts, t, g, nn); return;
+    case 2: hipLaunchKernelGGL(k_mask_walk<2>, grid, dim3(kThreads), 0, s, p, pts, t, g, nn); return;
+    case 3: hipLaunchKernelGGL(k_mask_walk<3>, grid, dim3(kThreads), 0, s, p, pts, t, g, nn); return;
+    case 4: hipLaunchKernelGGL(k_mask_walk<4>, grid, dim3(kThreads), 0, s, p, pts, t, g, nn); return;
+    default: break;
+  }
   const int stage = mw <= kMaskStageMw && !pts.sel ? 1 : 0;   // a point list scatters rows
   const size_t lds = stage ? sizeof(uint64_t) * kThreads * 3 * mw : 0;
   hipLaunchKernelGGL(k_mask, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads),
