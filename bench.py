@@ -197,7 +197,10 @@ def trace_summary(csv_path, warmup, steps):
             m = re.search(r"\b(k_[A-Za-z0-9_]+)\s*[<(]", name)
             if not m:
                 continue
-            base = "k_score" if m.group(1).startswith("k_score") else m.group(1)
+            base = m.group(1)
+            for fam in ("k_score", "k_mask"):   # kernel variants reported under one name
+                if base.startswith(fam):
+                    base = fam
             if base not in TRACE_KERNELS:
                 continue
             per.setdefault(base, []).append(
