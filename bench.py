@@ -974,7 +974,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--latency-frames", type=int, default=600,
                     help="frames of the tree sequence replayed at 10 Hz on a fresh map")
-    ap.add_argument("--cpu-frames", type=int, default=12)
+    ap.add_argument("--cpu-frames", type=int, default=6)
     ap.add_argument("--cpu-points", type=int, default=100000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tune", action="store_true",
