@@ -304,3 +304,38 @@ def test_normal_cache_budget_refusal(synth_mod, oracle_mod):
     lab = probe.read_labels(0)
     keys, lbl, ff = orc.labels(len(w.rot), lab["key"])
     assert np.array_equal(lab["label"], lbl)
+
+
+@pytest.mark.parametrize("n_dir,n_roll", [(80, 3), (30, 5), (100, 3)])
+def test_rolls_across_mask_words(tiny_run, synth_mod, n_dir, n_roll):
+    """Orientations that share an approach direction form runs; with 3 or 5
+    rolls per direction (K = 240, 150 and 300) some runs start in one 64-bit
+    mask word and end in the next, so those orientations take the candidate
+    bit and arm-sample result of a head in the previous word (K = 300 goes
+    through the mask kernel for more than 256 orientations, on a context fed
+    the same frames).  Labels, first free orientations, candidate masks and
+    canonical counts equal the oracle's, which tests every orientation on its
+    own."""
+    w, ctx, orc, _ = tiny_run
+    rot = synth_mod.orientations(synth_mod.fibonacci_directions(n_dir), n_roll)
+    K = len(rot)
+    assert any((k // 64) != ((k // n_roll) * n_roll) // 64 for k in range(K))   # a run crosses
+    if K > 256:
+        torch = _torch()
+        ctx = _ctx(w, max_orientations=512)
+        for f in w.frames():
+            ctx.integrate_frame(torch.from_numpy(f.xyz).cuda(), f.origin, f.frame_id)
+    ctx.set_tool_kernels(1, w.tool, rot)
+    orc.set_tool(1, w.tool, rot)
+    ctx.score_points(1)
+    orc.score(1)
+    lab = ctx.read_labels(1)
+    r = orc.read_results(K)
+    assert np.array_equal(lab["key"], orc.read_points()["key"])
+    assert np.array_equal(lab["label"], r["label"])
+    assert np.array_equal(lab["first_free"].astype(np.int64), r["first_free"])
+    conf = r["label"] != 0
+    assert np.array_equal(ctx.read_point_debug(1)["mask"][conf], r["mask"][conf])
+    g, o = ctx.score_stats(1), orc.score_stats()
+    assert {k: g[k] for k in SCORE_KEYS} == {k: o[k] for k in SCORE_KEYS}
+    assert set(np.unique(r["label"])) >= {1, 2}
