@@ -555,189 +555,35 @@ __device__ inline uint32_t ent_code(const SwGrid &q, const SwFrame &f, uint32_t 
   return B1 ? occ_rel(q, f, e) : code_rel(q, f, e);
 }
 
-// One lane per point: the point's normal and viewpoint vectors stay in
-// registers (fp64, exact conversions of integers) while every lane walks the
-// same orientation list, so each direction is a wave-uniform load.
+// Candidate masks (Section 3.4 "Approach directions"): one lane per point,
+// its normal and viewpoint vectors in registers (fp64, exact conversions of
+// integers).  For every candidate direction the lane also reads the
+// direction's three arm samples (Section 3.4 "Arm path checking"; they depend
+// on the approach direction only, so orientations that share it share the
+// result) and records which one hits first, as two bit planes per mask word.
+// An orientation that shares its predecessor's approach direction takes its
+// candidate bit and arm-sample result, so only heads (orientations with a
+// direction of their own) are evaluated, each head's result covering its run.
 //
-// For every candidate direction the lane also reads the direction's three
-// arm samples (Section 3.4 "Arm path checking"; they depend on the approach
-// direction only, so orientations that share it share the result) and
-// records which one hits first, as two bit planes per mask word.  With
-// dynamic LDS (mw <= kMaskStageMw) the workgroup's words are staged there and
-// written out contiguously (a lane's own words are 8 bytes at a 96-byte
-// stride, which the memory system would write back as partial lines).
-constexpr int kMaskStageMw = 8;
-
-__global__ void __launch_bounds__(kThreads)
-k_mask(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int32_t mw, int stage) {
-  // n < 0: the point count on the device (recorded graphs, point lists)
-  if (n < 0) n = pts.sel ? (int64_t)*pts.n_sel : (int64_t)*pts.n_points;
-  if ((int64_t)blockIdx.x * kThreads >= n) return;   // whole workgroup past the end
-  extern __shared__ uint64_t s_out[];   // [kThreads * mw] mask, then [kThreads * 2 mw] planes
-  const int64_t jj = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  const bool act = jj < n;
-  const int lane = lane_id();
-  // a point list scatters the rows: it is launched without staging
-  const int64_t i = pts.sel ? (act ? (int64_t)pts.sel[jj] : 0) : jj;
-  const int hn = act ? pts.has_normal[i] : -1;
-  double n0 = 0, n1 = 0, n2 = 0, nn = 0;
-  double wx[kMaxVp], wy[kMaxVp], wz[kMaxVp], ww[kMaxVp];
-  int nv = 0;
-  if (hn >= 0) {
-    if (hn > 0) {
-      const int32_t *nvp = pts.normal + 3 * i;
-      n0 = (double)nvp[0];
-      n1 = (double)nvp[1];
-      n2 = (double)nvp[2];
-      nn = (double)((int64_t)nvp[0] * nvp[0] + (int64_t)nvp[1] * nvp[1] +
-                    (int64_t)nvp[2] * nvp[2]);
-    }
-    int32_t s[3];
-    unpack_key(pts.key[i], s[0], s[1], s[2]);
-    nv = pts.nvp[i];
-#pragma unroll
-    for (int j = 0; j < kMaxVp; ++j) {
-      if (j < nv) {
-        const int32_t *V = pts.vp + (i * kMaxVp + j) * 3;
-        int64_t a0 = (int64_t)V[0] - (256 * (int64_t)s[0] + 128);
-        int64_t a1 = (int64_t)V[1] - (256 * (int64_t)s[1] + 128);
-        int64_t a2 = (int64_t)V[2] - (256 * (int64_t)s[2] + 128);
-        wx[j] = (double)a0;
-        wy[j] = (double)a1;
-        wz[j] = (double)a2;
-        ww[j] = (double)(a0 * a0 + a1 * a1 + a2 * a2);
-      } else {
-        wx[j] = wy[j] = wz[j] = ww[j] = 0.0;
-      }
-    }
-  }
-  const SwGrid q = sw_grid(g);
-  SwFrame f;
-  f.Bp = f.rp = 0u;
-  if (hn >= 0) {
-    int32_t s[3];
-    unpack_key(pts.key[i], s[0], s[1], s[2]);
-    f = sw_frame(g, q, s);
-  }
-  unsigned long long cand = 0;
-  bool ok = false;     // candidate bit of the previous orientation
-  uint32_t nb = 0u;    // its arm-sample result
-  for (int w = 0; w < mw; ++w) {
-    const int kend = t.K - 64 * w < 64 ? t.K - 64 * w : 64;
-    const uint64_t valid = kend == 64 ? ~0ull : ((1ull << kend) - 1ull);
-    const uint64_t heads = ~t.same[w] & valid;   // orientations with their own direction
-    // An orientation that shares its predecessor's approach direction takes
-    // its candidate bit and arm-sample result, so only heads are evaluated
-    // and each head's result covers its run of orientations (bits below the
-    // first head continue the previous word's last run).
-    // lane j holds the three arm entries of orientation 64 w + j (read
-    // once per word, their latency hidden behind the first heads' tests)
-    uint2 ae[3] = {{0u, 0u}, {0u, 0u}, {0u, 0u}};
-    if (lane < kend) {
-      const uint32_t b = t.begin[64 * w + lane];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) ae[a] = t.xent[b + a];
-    }
-    const uint64_t carry = heads ? ((heads & (~heads + 1ull)) - 1ull) : valid;
-    uint64_t word = ok ? carry : 0ull;
-    uint64_t pl0 = (nb & 1u) ? carry : 0ull, pl1 = (nb >> 1) ? carry : 0ull;
-    // A head's arm-sample words are requested in its iteration and decoded in
-    // the next one, so their latency overlaps the next head's tests.
-    uint32_t pw[3] = {0u, 0u, 0u}, pb[3] = {0u, 0u, 0u};
-    uint64_t prun = 0ull;   // run of the head whose words are in flight (0: none)
-    auto settle = [&]() {
-      if (!prun) return;
-      nb = ((pw[0] >> pb[0]) & 3u) ? 1u
-           : ((pw[1] >> pb[1]) & 3u) ? 2u
-           : ((pw[2] >> pb[2]) & 3u) ? 3u
-                                     : 0u;
-      pl0 |= (nb & 1u) ? prun : 0ull;
-      pl1 |= (nb >> 1) ? prun : 0ull;
-    };
-    for (uint64_t rem = heads; rem; rem &= rem - 1ull) {
-      const int j = __ffsll((unsigned long long)rem) - 1;
-      const uint64_t above = j == 63 ? 0ull : heads & ~((2ull << j) - 1ull);
-      const uint64_t run = (above ? (above & (~above + 1ull)) - 1ull : valid) & ~((1ull << j) - 1ull);
-      const double *R = t.rot + 9 * (int64_t)(64 * w + j);
-      const double d0 = R[0], d1 = R[3], d2 = R[6];
-      ok = hn >= 0;
-      if (hn > 0) {
-        double dot = (n0 * d0 + n1 * d1) + n2 * d2;
-        ok = dot >= 0.0 && dot * dot >= p.cos2 * nn;
-      }
-      if (ok) {
-        bool seen = false;
-#pragma unroll
-        for (int v = 0; v < kMaxVp; ++v) {
-          if (v < nv && !seen) {
-            double wd = (wx[v] * d0 + wy[v] * d1) + wz[v] * d2;
-            seen = wd > 0.0 && wd * wd > p.obs2 * ww[v];
-          }
-        }
-        ok = seen;
-      }
-      settle();   // the previous head's words, requested an iteration ago
-      uint32_t cw[3] = {0u, 0u, 0u}, cb[3] = {0u, 0u, 0u};
-      if (ok) {
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          const uint2 e = {(uint32_t)__builtin_amdgcn_readlane((int)ae[a].x, j),
-                           (uint32_t)__builtin_amdgcn_readlane((int)ae[a].y, j)};
-          cw[a] = __builtin_amdgcn_raw_buffer_load_b32(q.pred, code_sw_at(q, f, e, cb[a]), 0, 0);
-        }
-      }
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        pw[a] = cw[a];
-        pb[a] = cb[a];
-      }
-      prun = run;
-      word |= ok ? run : 0ull;
-    }
-    settle();
-    if (stage) {
-      s_out[threadIdx.x * mw + w] = word;
-      s_out[kThreads * mw + threadIdx.x * 2 * mw + w] = pl0;
-      s_out[kThreads * mw + threadIdx.x * 2 * mw + mw + w] = pl1;
-    } else if (act) {
-      t.mask[i * mw + w] = word;
-      t.nearp[i * 2 * mw + w] = pl0;
-      t.nearp[i * 2 * mw + mw + w] = pl1;
-    }
-    cand += (unsigned long long)__popcll(word);
-  }
-  if (stage) {
-    __syncthreads();
-    const int64_t i0 = (int64_t)blockIdx.x * kThreads;
-    const int64_t np = n - i0 < kThreads ? n - i0 : kThreads;
-    for (int64_t k = threadIdx.x; k < np * mw; k += kThreads) t.mask[i0 * mw + k] = s_out[k];
-    for (int64_t k = threadIdx.x; k < np * 2 * mw; k += kThreads)
-      t.nearp[i0 * 2 * mw + k] = s_out[kThreads * mw + k];
-  }
-  for (int off = 32; off >= 1; off >>= 1) {
-    unsigned lo = __shfl_xor((unsigned)(cand & 0xffffffffu), off);
-    unsigned hi = __shfl_xor((unsigned)(cand >> 32), off);
-    cand += ((unsigned long long)hi << 32) | lo;
-  }
-  if (lane_id() == 0 && cand)
-    atomicAdd(&t.counters->s[(blockIdx.x * kWaves + (threadIdx.x >> 6)) % kStatSlots]
-                   .candidate_tests,
-              cand);
-}
-
-// The same candidate masks and arm-sample planes for K <= 64 MW orientations,
-// with the heads walked per lane: each lane first tests the normal cone of
-// every head (wave-uniform directions), then visits only its own heads inside
-// the cone, in any word, so the observation test and the arm samples run on
-// as many heads as the wave's busiest lane has in its cone (consecutive heads
-// of a direction set often share a band of the sphere, so one word can hold
-// all of one lane's cone and none of its neighbour's).  The heads' directions,
-// arm entries and runs are staged in LDS once per workgroup; each lane's
-// words collect there, and the carries across words (orientations before a
-// word's first head) are applied afterwards, in word order.
+// MW mask words (from word w0 of mw) per launch, with the heads walked per
+// lane: each lane first tests the normal cone of every head (wave-uniform
+// directions), then visits only its own heads inside the cone, in any word,
+// so the observation test and the arm samples run on as many heads as the
+// wave's busiest lane has in its cone (consecutive heads of a direction set
+// often share a band of the sphere, so one word can hold all of one lane's
+// cone and none of its neighbour's).  The heads' directions, arm entries and
+// runs are staged in LDS once per workgroup; each lane's words collect there,
+// and the carries across words (orientations before a word's first head) are
+// applied afterwards, in word order.  The rows of a workgroup's points are
+// then written out together (a lane's own words are 8 bytes at a 96-byte
+// stride, which the memory system would write back as partial lines).  A
+// launch after the first takes its carry-in from the last orientation of word
+// w0 - 1 as the previous launch wrote it: that orientation belongs to the run
+// of the last head before word w0, so it holds that head's candidate bit and
+// arm-sample result (every word but the last is full).
 template <int MW>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
-k_mask_walk(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n) {
+k_mask_walk(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n, int w0, int mw) {
   // n < 0: the point count on the device (recorded graphs, point lists)
   if (n < 0) n = pts.sel ? (int64_t)*pts.n_sel : (int64_t)*pts.n_points;
   if ((int64_t)blockIdx.x * kThreads >= n) return;   // whole workgroup past the end
@@ -746,17 +592,17 @@ k_mask_walk(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n) {
   __shared__ uint64_t s_run[64 * MW];
   __shared__ uint64_t s_word[3][MW][kThreads];   // candidate word, plane 0, plane 1
   for (int k = threadIdx.x; k < 64 * MW; k += kThreads) {
-    const int w = k >> 6, j = k & 63;
+    const int w = w0 + (k >> 6), j = k & 63;
     const int kend = t.K - 64 * w < 64 ? t.K - 64 * w : 64;
     uint64_t run = 0ull;
     if (j < kend) {
       const uint64_t valid = kend == 64 ? ~0ull : ((1ull << kend) - 1ull);
       const uint64_t heads = ~t.same[w] & valid;
-      const double *R = t.rot + 9 * (int64_t)k;
+      const double *R = t.rot + 9 * (int64_t)(64 * w + j);
       s_dir[0][k] = R[0];
       s_dir[1][k] = R[3];
       s_dir[2][k] = R[6];
-      const uint32_t b = t.begin[k];
+      const uint32_t b = t.begin[64 * w + j];
 #pragma unroll
       for (int a = 0; a < 3; ++a) s_arm[a][k] = t.xent[b + a];
       if ((heads >> j) & 1ull) {
@@ -816,14 +662,14 @@ k_mask_walk(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n) {
   uint64_t cone[MW];
 #pragma unroll
   for (int w = 0; w < MW; ++w) {
-    const int kend = t.K - 64 * w < 64 ? t.K - 64 * w : 64;
+    const int kend = t.K - 64 * (w0 + w) < 64 ? t.K - 64 * (w0 + w) : 64;
     const uint64_t valid = kend == 64 ? ~0ull : ((1ull << kend) - 1ull);
-    const uint64_t heads = ~t.same[w] & valid;
+    const uint64_t heads = ~t.same[w0 + w] & valid;
     cone[w] = hn == 0 ? heads : 0ull;
     if (hn > 0) {
       for (uint64_t rem = heads; rem; rem &= rem - 1ull) {
         const int j = __ffsll((unsigned long long)rem) - 1;
-        const double *R = t.rot + 9 * (int64_t)(64 * w + j);
+        const double *R = t.rot + 9 * (int64_t)(64 * (w0 + w) + j);
         const double d0 = R[0], d1 = R[3], d2 = R[6];
         const double dot = (n0 * d0 + n1 * d1) + n2 * d2;
         if (dot >= 0.0 && dot * dot >= p.cos2 * nn) cone[w] |= 1ull << j;
@@ -894,11 +740,16 @@ k_mask_walk(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n) {
   unsigned long long cand = 0;
   bool ok = false;
   uint32_t nb = 0u;
+  if (w0 > 0 && act) {
+    ok = (t.mask[i * mw + w0 - 1] >> 63) != 0ull;
+    nb = (uint32_t)(t.nearp[i * 2 * mw + w0 - 1] >> 63) |
+         ((uint32_t)(t.nearp[i * 2 * mw + mw + w0 - 1] >> 63) << 1);
+  }
 #pragma unroll
   for (int w = 0; w < MW; ++w) {
-    const int kend = t.K - 64 * w < 64 ? t.K - 64 * w : 64;
+    const int kend = t.K - 64 * (w0 + w) < 64 ? t.K - 64 * (w0 + w) : 64;
     const uint64_t valid = kend == 64 ? ~0ull : ((1ull << kend) - 1ull);
-    const uint64_t heads = ~t.same[w] & valid;
+    const uint64_t heads = ~t.same[w0 + w] & valid;
     const uint64_t carry = heads ? ((heads & (~heads + 1ull)) - 1ull) : valid;
     uint64_t word = s_word[0][w][threadIdx.x] | (ok ? carry : 0ull);
     uint64_t pl0 = s_word[1][w][threadIdx.x] | ((nb & 1u) ? carry : 0ull);
@@ -910,9 +761,9 @@ k_mask_walk(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n) {
     }
     if (pts.sel) {
       if (act) {
-        t.mask[i * MW + w] = word;
-        t.nearp[i * 2 * MW + w] = pl0;
-        t.nearp[i * 2 * MW + MW + w] = pl1;
+        t.mask[i * mw + w0 + w] = word;
+        t.nearp[i * 2 * mw + w0 + w] = pl0;
+        t.nearp[i * 2 * mw + mw + w0 + w] = pl1;
       }
     } else {
       s_word[0][w][threadIdx.x] = word;
@@ -926,11 +777,20 @@ k_mask_walk(Params p, PointsDev pts, ToolDev t, GridDev g, int64_t n) {
     __syncthreads();
     const int64_t i0 = (int64_t)blockIdx.x * kThreads;
     const int np = n - i0 < kThreads ? (int)(n - i0) : kThreads;
-    for (int k = threadIdx.x; k < np * MW; k += kThreads)
-      t.mask[i0 * MW + k] = s_word[0][k % MW][k / MW];
-    for (int k = threadIdx.x; k < np * 2 * MW; k += kThreads) {
-      const int r = k / (2 * MW), c = k % (2 * MW);
-      t.nearp[i0 * 2 * MW + k] = c < MW ? s_word[1][c][r] : s_word[2][c - MW][r];
+    if (MW == mw) {
+      for (int k = threadIdx.x; k < np * MW; k += kThreads)
+        t.mask[i0 * MW + k] = s_word[0][k % MW][k / MW];
+      for (int k = threadIdx.x; k < np * 2 * MW; k += kThreads) {
+        const int r = k / (2 * MW), c = k % (2 * MW);
+        t.nearp[i0 * 2 * MW + k] = c < MW ? s_word[1][c][r] : s_word[2][c - MW][r];
+      }
+    } else {   // this launch's words of each row
+      for (int k = threadIdx.x; k < np * MW; k += kThreads) {
+        const int r = k / MW, c = k % MW;
+        t.mask[(i0 + r) * mw + w0 + c] = s_word[0][c][r];
+        t.nearp[(i0 + r) * 2 * mw + w0 + c] = s_word[1][c][r];
+        t.nearp[(i0 + r) * 2 * mw + mw + w0 + c] = s_word[2][c][r];
+      }
     }
   }
   for (int off = 32; off >= 1; off >>= 1) {
@@ -1990,17 +1850,16 @@ void launch_mask(const Params &p, PointsDev pts, ToolDev t, GridDev g, int64_t n
   if (n <= 0) return;
   const dim3 grid((unsigned)((n + kThreads - 1) / kThreads));
   const int64_t nn = dev_n ? (int64_t)-1 : n;
-  switch (mw) {   // up to 256 orientations: heads walked per lane
-    case 1: hipLaunchKernelGGL(k_mask_walk<1>, grid, dim3(kThreads), 0, s, p, pts, t, g, nn); return;
-    case 2: hipLaunchKernelGGL(k_mask_walk<2>, grid, dim3(kThreads), 0, s, p, pts, t, g, nn); return;
-    case 3: hipLaunchKernelGGL(k_mask_walk<3>, grid, dim3(kThreads), 0, s, p, pts, t, g, nn); return;
-    case 4: hipLaunchKernelGGL(k_mask_walk<4>, grid, dim3(kThreads), 0, s, p, pts, t, g, nn); return;
-    default: break;
+  // heads walked per lane, four mask words per launch (each launch after the
+  // first reads the words the previous one wrote)
+  for (int w0 = 0; w0 < mw; w0 += 4) {
+    switch (mw - w0 < 4 ? mw - w0 : 4) {
+      case 1: hipLaunchKernelGGL(k_mask_walk<1>, grid, dim3(kThreads), 0, s, p, pts, t, g, nn, w0, mw); break;
+      case 2: hipLaunchKernelGGL(k_mask_walk<2>, grid, dim3(kThreads), 0, s, p, pts, t, g, nn, w0, mw); break;
+      case 3: hipLaunchKernelGGL(k_mask_walk<3>, grid, dim3(kThreads), 0, s, p, pts, t, g, nn, w0, mw); break;
+      default: hipLaunchKernelGGL(k_mask_walk<4>, grid, dim3(kThreads), 0, s, p, pts, t, g, nn, w0, mw); break;
+    }
   }
-  const int stage = mw <= kMaskStageMw && !pts.sel ? 1 : 0;   // a point list scatters rows
-  const size_t lds = stage ? sizeof(uint64_t) * kThreads * 3 * mw : 0;
-  hipLaunchKernelGGL(k_mask, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads),
-                     lds, s, p, pts, t, g, dev_n ? (int64_t)-1 : n, mw, stage);
 }
 
 int score_variants() { return kNumVariants; }

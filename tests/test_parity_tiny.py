@@ -311,9 +311,9 @@ def test_rolls_across_mask_words(tiny_run, synth_mod, n_dir, n_roll):
     """Orientations that share an approach direction form runs; with 3 or 5
     rolls per direction (K = 240, 150 and 300) some runs start in one 64-bit
     mask word and end in the next, so those orientations take the candidate
-    bit and arm-sample result of a head in the previous word (K = 300 goes
-    through the mask kernel for more than 256 orientations, on a context fed
-    the same frames).  Labels, first free orientations, candidate masks and
+    bit and arm-sample result of a head in the previous word (K = 300 takes
+    two mask launches, the second carrying in from the first's last word; it
+    runs on a context fed the same frames).  Labels, first free orientations, candidate masks and
     canonical counts equal the oracle's, which tests every orientation on its
     own."""
     w, ctx, orc, _ = tiny_run
