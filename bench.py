@@ -1206,7 +1206,7 @@ def main():
                 "bytes_model": "8 B per canonical lookup not answered by the mask kernel + "
                                "per confident point 8 B key + 3K/8 B mask and arm planes + "
                                "4 B weight + 3 B outputs",
-                "score_path": {"kernels": "k_mask + k_score",
+                "score_path": {"kernels": "k_mask_walk + k_score",
                                "algorithmic_bytes_per_step": byts / max(K, 1),
                                "achieved": path_achieved, "frac": path_achieved / HBM_PEAK_GBS},
                 "avg_launch_ms": tm["k_score_ms"] / max(tm["score_calls"], 1),
